@@ -1,0 +1,247 @@
+/*
+ * trx.h - C ABI of the MI355X transmission forward-model library.
+ *
+ * The library evaluates the transit-depth forward model of TauREx 3
+ * (Al-Refaie et al., arXiv:1912.07759) on one AMD Instinct MI355X (gfx950):
+ *
+ *   a1  pressure grid, free chemistry with H2/He fill, mean molecular weight
+ *       (Pressure Profiles and Chemistry subsections);
+ *   a2  hydrostatic altitude recursion (Forward Models section, altitude
+ *       equation), FP64 on the GPU;
+ *   a3  chord path-length triangle and annulus weights (transit-depth
+ *       integrals of the Forward Models section), FP64 on the GPU;
+ *   a4  per-layer absorption coefficient: bilinear (T, log10 P) interpolation
+ *       of cross-section tables, Rayleigh and CIA, weighted by mixing ratio
+ *       and number density and summed before the path integral
+ *       (equations opt_dpth, cia_opt_dpth, contrib; Opacities section);
+ *   a5  optical depth tau[ray, wn] = sum_k dl[ray, k] kappa[k, wn];
+ *   a6  depth D = (Rp^2 + sum_j A_j (1 - exp(-tau_j))) / Rs^2;
+ *   a7  binning to channels with overlap weights (Binning subsection);
+ *   a8  chi^2 against an observation and its gradient with respect to the
+ *       per-layer temperatures, log10 mixing ratios and Rp;
+ *   a9  a batched form over a ragged live-point set run as one persistent,
+ *       graph-captured launch (the plan API).
+ *
+ * Conventions
+ *  - Units are SI (Forward Models section) except: wavenumbers in cm^-1,
+ *    cross-sections in cm^2/molecule, CIA in cm^5/molecule^2, masses in amu.
+ *  - All profile arrays are bottom first (layer 0 at the highest pressure,
+ *    where the planet radius is defined).
+ *  - Host pointers are read during the call only.  Device pointers are
+ *    borrowed until the work enqueued on the context's stream has finished;
+ *    the caller owns every input and output buffer.
+ *  - Errors: a call that returns a status other than TRX_OK has enqueued no
+ *    work; trx_last_error() then returns a message.  Out-of-range T or P is
+ *    not an error (the tables clamp, Opacities section).  An invalid model
+ *    inside a batch never fails the call: its model_status entry is set
+ *    (bit mask below) and its outputs are NaN, so a sampler can assign it
+ *    the minimum likelihood (Model Rejection subsection).
+ */
+#ifndef TRX_H
+#define TRX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct trx_ctx trx_ctx;
+typedef struct trx_tables trx_tables;
+typedef struct trx_bins trx_bins;
+typedef struct trx_plan trx_plan;
+
+typedef enum {
+  TRX_OK = 0,
+  TRX_E_INVALID_ARG = 1,   /* bad pointer, size, grid or handle */
+  TRX_E_OUT_OF_MEMORY = 2, /* device allocation failed */
+  TRX_E_DEVICE = 3,        /* a HIP runtime call failed */
+  TRX_E_UNSUPPORTED = 4    /* valid request outside what is built */
+} trx_status;
+
+/* Arithmetic of the opacity and optical-depth steps.  Geometry, altitude and
+ * the final depth assembly are FP64 in every mode.
+ *  TRX_FP64         FP64 tables, FP64 opacity, FP64 contraction (reference).
+ *  TRX_FP32         FP32 tables and opacity, FP32 matrix-core contraction with
+ *                   the path lengths split into FP32 hi + lo parts.
+ *  TRX_BF16_SPLIT2  FP32 opacity; path lengths and opacity each split into
+ *                   two bf16 parts, three bf16 matrix-core products
+ *                   (hi*hi + hi*lo + lo*hi) with FP32 accumulation.
+ *  TRX_BF16_SPLIT3  three bf16 parts each, six products (~FP32 accuracy). */
+typedef enum {
+  TRX_FP64 = 0,
+  TRX_FP32 = 1,
+  TRX_BF16_SPLIT2 = 2,
+  TRX_BF16_SPLIT3 = 3
+} trx_precision;
+
+/* model_status bits */
+enum {
+  TRX_MODEL_OK = 0,
+  TRX_MODEL_BAD_CHEMISTRY = 1, /* sum of absorber mixing ratios >= 1, or non-finite */
+  TRX_MODEL_BAD_PROFILE = 2,   /* n_layers out of range, T <= 0, Rp/Rs/GM <= 0,
+                                  p_bot <= p_top, non-finite input */
+  TRX_MODEL_BAD_WINDOW = 4,    /* window empty or outside the grid */
+  TRX_MODEL_NONFINITE = 8      /* a non-finite value appeared in the outputs */
+};
+
+/* Limits of this build. */
+#define TRX_MAX_LAYERS_FP64 1024 /* TRX_FP64 */
+#define TRX_MAX_LAYERS_MFMA 224  /* the matrix-core modes */
+#define TRX_MAX_ABSORBERS 32
+#define TRX_MAX_CIA 8
+#define TRX_MAX_TGRID 128
+#define TRX_MAX_PGRID 128
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; work is enqueued on the default
+ * stream until trx_set_stream is called. */
+trx_status trx_create(int device, trx_ctx** out);
+trx_status trx_destroy(trx_ctx* ctx);
+/* Message of the last failing call on this context ("" if none).  The
+ * string is owned by the context and valid until its next call. */
+const char* trx_last_error(const trx_ctx* ctx);
+/* Enqueue subsequent work on `hip_stream` (a hipStream_t; NULL = default). */
+trx_status trx_set_stream(trx_ctx* ctx, void* hip_stream);
+/* Block until all work enqueued by this context has finished. */
+trx_status trx_synchronize(trx_ctx* ctx);
+
+/* ---- opacity tables (Opacities section) ------------------------------- */
+
+/* All pointers are HOST pointers, read during the call.  Every table lives
+ * on one shared wavenumber grid (the paper's "native" grid, resampling
+ * done by the caller).  Species ids: 0..n_abs-1 absorbers, n_abs = H2,
+ * n_abs+1 = He. */
+typedef struct {
+  int32_t n_wn;                 /* >= 2 */
+  const double* wn_cm1;         /* [n_wn] strictly increasing */
+  int32_t n_T;                  /* 2..TRX_MAX_TGRID */
+  const double* T_K;            /* [n_T] strictly increasing */
+  int32_t n_P;                  /* 2..TRX_MAX_PGRID */
+  const double* log10P_Pa;      /* [n_P] strictly increasing */
+  int32_t n_abs;                /* 0..TRX_MAX_ABSORBERS */
+  const double* xsec_cm2;       /* [n_abs][n_T][n_P][n_wn] */
+  const double* abs_mass_amu;   /* [n_abs] */
+  double h2_mass_amu;
+  double he_mass_amu;
+  int32_t n_cia;                /* 0..TRX_MAX_CIA */
+  int32_t n_Tcia;               /* 2..TRX_MAX_TGRID if n_cia > 0 */
+  const double* Tcia_K;         /* [n_Tcia] strictly increasing */
+  const double* cia_cm5;        /* [n_cia][n_Tcia][n_wn] */
+  const int32_t* cia_pair;      /* [n_cia][2] species ids */
+  const double* rayleigh_cm2;   /* [n_abs + 2][n_wn], or NULL for none */
+} trx_tables_desc;
+
+/* Copy the tables to the device (FP64 and FP32 copies, wavenumber
+ * contiguous).  The handle owns the device memory. */
+trx_status trx_tables_create(trx_ctx* ctx, const trx_tables_desc* desc, trx_tables** out);
+trx_status trx_tables_destroy(trx_tables* t);
+
+/* ---- channels (Binning subsection) ------------------------------------ */
+
+/* n_ch channels [lo_c, hi_c) in cm^-1 (HOST pointers).  Native bin edges
+ * are the midpoints of the table grid, end bins mirrored; the weight of
+ * native point i in channel c is the overlap of the two bins divided by
+ * the native bin width; a channel's value is the weighted mean over the
+ * native points of a model's window (NaN if it has none). */
+trx_status trx_bins_create(trx_ctx* ctx, const trx_tables* t, int32_t n_ch,
+                           const double* lo_cm1, const double* hi_cm1, trx_bins** out);
+trx_status trx_bins_destroy(trx_bins* b);
+
+/* ---- a batch of models ------------------------------------------------ */
+
+/* B models with their own layer counts and wavenumber windows.  Array
+ * pointers are DEVICE pointers; scalars are host values. */
+typedef struct {
+  int32_t B;                    /* >= 1 */
+  int32_t max_layers;           /* host upper bound on n_layers[b] */
+  const int32_t* n_layers;      /* [B] >= 2 */
+  const int64_t* layer_off;     /* [B+1] offsets into T_K, layer_off[0] = 0 */
+  const double* T_K;            /* [layer_off[B]] per-layer temperature */
+  const double* p_bot_Pa;       /* [B] boundary pressure at the bottom */
+  const double* p_top_Pa;       /* [B] boundary pressure at the top */
+  const double* log10_vmr;      /* [B][n_abs] constant absorber profiles */
+  const double* Rp_m;           /* [B] planet radius at z = 0 */
+  const double* Rs_m;           /* [B] stellar radius */
+  const double* GM_m3s2;        /* [B] planet G*M */
+  const int32_t* wn_lo;         /* [B] window start index (inclusive) */
+  const int32_t* wn_hi;         /* [B] window end index (exclusive) */
+  double he_h2_ratio;           /* He/H2 volume ratio of the fill */
+  double k_B;                   /* Boltzmann constant, J/K */
+  double amu_kg;                /* atomic mass unit, kg */
+  int32_t gravity;              /* 0: g = GM/(Rp+z)^2, 1: g = GM/Rp^2 */
+} trx_batch;
+
+/* Forward model for every model of the batch.
+ *  depth_native  DEVICE [B][n_wn] or NULL: native depth; only the entries
+ *                inside each model's window are written.
+ *  depth_binned  DEVICE [B][n_ch] or NULL (requires bins).
+ *  model_status  DEVICE [B], required.
+ * Returns TRX_E_UNSUPPORTED if max_layers exceeds the mode's limit. */
+trx_status trx_forward(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch,
+                       const trx_bins* bins, trx_precision precision,
+                       double* depth_native, double* depth_binned, int32_t* model_status);
+
+/* chi^2 = sum_c ((D_c - obs_c)/sigma_c)^2 and its gradient, per model.
+ *  obs        DEVICE [B][n_ch]; sigma DEVICE [n_ch] (> 0).
+ *  chi2       DEVICE [B]
+ *  dT         DEVICE [layer_off[B]]   d chi2 / d T_l
+ *  dlog10vmr  DEVICE [B][n_abs]       d chi2 / d log10 chi_i (fill gases
+ *                                     follow the sum constraint)
+ *  dRp        DEVICE [B]              d chi2 / d Rp
+ *  depth_binned DEVICE [B][n_ch] or NULL
+ *  recompute  1: the opacity and optical depth are recomputed in the
+ *             backward pass instead of stored (the only mode built).
+ * Derivatives at table nodes and under clamps are one-sided (the lower
+ * bracket's slope; zero under a clamp).  The binned spectrum must cover
+ * every channel in each model's window, else that model's chi2 is NaN. */
+trx_status trx_chi2_grad(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch,
+                         const trx_bins* bins, trx_precision precision,
+                         const double* obs, const double* sigma, int32_t recompute,
+                         double* chi2, double* dT, double* dlog10vmr, double* dRp,
+                         double* depth_binned, int32_t* model_status);
+
+/* ---- plans: fixed-capacity batched launches --------------------------- */
+
+/* flags */
+enum {
+  TRX_PLAN_GRAPH = 1,       /* capture the launch sequence in a HIP graph */
+  TRX_PLAN_PERSISTENT = 2,  /* persistent kernel with work queues */
+  TRX_PLAN_GRAD = 4         /* plan computes chi^2 and its gradient */
+};
+
+/* A plan owns device buffers for up to B_max models of at most N_max
+ * layers (total layers <= B_max * N_max) and the workspace of one launch.
+ * Its input buffers are exposed through trx_plan_batch; a launch reads them
+ * on the context's stream. */
+trx_status trx_plan_create(trx_ctx* ctx, const trx_tables* t, const trx_bins* bins,
+                           int32_t B_max, int32_t N_max, trx_precision precision,
+                           int32_t flags, trx_plan** out);
+trx_status trx_plan_destroy(trx_plan* p);
+/* Fill `out` with the plan's own DEVICE input buffers (B = B_max); the
+ * caller writes its models there and sets out->B before each launch. */
+trx_status trx_plan_batch(trx_plan* p, trx_batch* out);
+/* Run the forward model (and the gradient for TRX_PLAN_GRAD plans) for the
+ * first `B` models of the plan's input buffers.  Output pointers as in
+ * trx_forward / trx_chi2_grad; obs/sigma only for gradient plans.  The
+ * output pointers must be the same on every launch of a graph plan. */
+trx_status trx_plan_launch(trx_plan* p, int32_t B, double* depth_native,
+                           double* depth_binned, int32_t* model_status,
+                           const double* obs, const double* sigma, double* chi2,
+                           double* dT, double* dlog10vmr, double* dRp);
+
+/* ---- tuning ------------------------------------------------------------ */
+
+/* Time the kernel variants of `precision` on the plan's current inputs
+ * (first B models) and keep the fastest for this plan; if cache_json is not
+ * NULL, the choice is also recorded there under a key of the device name
+ * and shape bucket, and read back by later plans of the same bucket. */
+trx_status trx_autotune(trx_plan* p, int32_t B, const char* cache_json);
+/* Current variant of a plan as a short printable string. */
+const char* trx_plan_describe(const trx_plan* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRX_H */

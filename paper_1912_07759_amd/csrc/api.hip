@@ -1,0 +1,423 @@
+// Host side of the C ABI declared in include/trx.h: argument validation,
+// device copies of the tables and channel weights, workspace management and
+// the launch sequence (geometry -> opacity/optical depth/depth -> binning).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "trx_internal.h"
+#include "trx_host.h"
+
+using namespace trx;
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+trx_status trx::set_err(trx_ctx* c, trx_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+trx_status trx::hip_err(trx_ctx* c, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return set_err(c, TRX_E_OUT_OF_MEMORY, "%s: out of device memory", what);
+  return set_err(c, TRX_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+trx_status trx::ensure_buffer(trx_ctx* c, DevBuf& buf, size_t bytes, const char* what) {
+  if (buf.bytes >= bytes && buf.ptr) return TRX_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_err(c, e, what);
+  if (buf.ptr) hipFree(buf.ptr);
+  buf.ptr = nullptr;
+  buf.bytes = 0;
+  size_t want = std::max(bytes, (size_t)256);
+  e = hipMalloc(&buf.ptr, want);
+  if (e != hipSuccess) { buf.ptr = nullptr; return hip_err(c, e, what); }
+  buf.bytes = want;
+  return TRX_OK;
+}
+
+static bool strictly_increasing(const double* x, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  for (int i = 1; i < n; ++i)
+    if (!(x[i] > x[i - 1])) return false;
+  return true;
+}
+
+namespace {
+
+__global__ void k_to_f32(const double* __restrict__ s, float* __restrict__ d, int64_t n, double scale) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += st) d[i] = (float)(s[i] * scale);
+}
+
+__global__ void k_copy_status(const uint8_t* ws, int64_t slab, const int32_t* B_dev, int B,
+                              int32_t* out) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  int nb = B_dev ? *B_dev : B;
+  if (b < nb) out[b] = reinterpret_cast<const ModelHdr*>(ws + (int64_t)b * slab)->status;
+}
+
+}  // namespace
+
+trx_status trx::upload(trx_ctx* c, const double* host, int64_t n, double** d64, float** d32,
+                       std::vector<void*>& owned, double scale32) {
+  *d64 = nullptr;
+  *d32 = nullptr;
+  if (n == 0) return TRX_OK;
+  hipError_t e = hipMalloc(d64, n * sizeof(double));
+  if (e != hipSuccess) return hip_err(c, e, "trx_tables_create");
+  owned.push_back(*d64);
+  e = hipMalloc(d32, n * sizeof(float));
+  if (e != hipSuccess) return hip_err(c, e, "trx_tables_create");
+  owned.push_back(*d32);
+  e = hipMemcpy(*d64, host, n * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_err(c, e, "trx_tables_create");
+  hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, (hipStream_t)0, *d64, *d32, n, scale32);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "trx_tables_create");
+  return TRX_OK;
+}
+
+void trx::launch_copy_status(const uint8_t* ws, int64_t slab, const int32_t* B_dev, int B,
+                             int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_status, dim3((B + 255) / 256), dim3(256), 0, s, ws, slab, B_dev, B,
+                     out);
+}
+
+// --------------------------------------------------------------------------
+// context
+// --------------------------------------------------------------------------
+extern "C" trx_status trx_create(int device, trx_ctx** out) {
+  if (!out) return TRX_E_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TRX_E_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return TRX_E_DEVICE;
+  trx_ctx* c = new trx_ctx();
+  c->device = device;
+  c->stream = nullptr;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->n_cu = prop.multiProcessorCount;
+    snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+  }
+  *out = c;
+  return TRX_OK;
+}
+
+extern "C" trx_status trx_destroy(trx_ctx* c) {
+  if (!c) return TRX_E_INVALID_ARG;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->ws, &c->aws, &c->grad})
+    if (b->ptr) hipFree(b->ptr);
+  delete c;
+  return TRX_OK;
+}
+
+extern "C" const char* trx_last_error(const trx_ctx* c) { return c ? c->err.c_str() : ""; }
+
+extern "C" trx_status trx_set_stream(trx_ctx* c, void* s) {
+  if (!c) return TRX_E_INVALID_ARG;
+  c->stream = (hipStream_t)s;
+  return TRX_OK;
+}
+
+extern "C" trx_status trx_synchronize(trx_ctx* c) {
+  if (!c) return TRX_E_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  return e == hipSuccess ? TRX_OK : hip_err(c, e, "trx_synchronize");
+}
+
+// --------------------------------------------------------------------------
+// tables
+// --------------------------------------------------------------------------
+extern "C" trx_status trx_tables_create(trx_ctx* c, const trx_tables_desc* d, trx_tables** out) {
+  if (!c) return TRX_E_INVALID_ARG;
+  c->err.clear();
+  if (!d || !out) return set_err(c, TRX_E_INVALID_ARG, "trx_tables_create: null argument");
+  *out = nullptr;
+  if (d->n_wn < 2 || !d->wn_cm1 || !strictly_increasing(d->wn_cm1, d->n_wn))
+    return set_err(c, TRX_E_INVALID_ARG, "wavenumber grid must have >= 2 strictly increasing finite points");
+  if (d->n_T < 2 || d->n_T > TRX_MAX_TGRID || !d->T_K || !strictly_increasing(d->T_K, d->n_T) ||
+      d->T_K[0] <= 0)
+    return set_err(c, TRX_E_INVALID_ARG, "temperature grid must have 2..%d strictly increasing positive points",
+                   TRX_MAX_TGRID);
+  if (d->n_P < 2 || d->n_P > TRX_MAX_PGRID || !d->log10P_Pa || !strictly_increasing(d->log10P_Pa, d->n_P))
+    return set_err(c, TRX_E_INVALID_ARG, "log10 pressure grid must have 2..%d strictly increasing points",
+                   TRX_MAX_PGRID);
+  if (d->n_abs < 0 || d->n_abs > TRX_MAX_ABSORBERS)
+    return set_err(c, TRX_E_INVALID_ARG, "n_abs must be in 0..%d", TRX_MAX_ABSORBERS);
+  if (d->n_abs > 0 && (!d->xsec_cm2 || !d->abs_mass_amu))
+    return set_err(c, TRX_E_INVALID_ARG, "xsec_cm2 and abs_mass_amu are required when n_abs > 0");
+  for (int i = 0; i < d->n_abs; ++i)
+    if (!(std::isfinite(d->abs_mass_amu[i]) && d->abs_mass_amu[i] > 0))
+      return set_err(c, TRX_E_INVALID_ARG, "absorber mass %d must be positive", i);
+  if (!(d->h2_mass_amu > 0) || !(d->he_mass_amu > 0))
+    return set_err(c, TRX_E_INVALID_ARG, "H2 and He masses must be positive");
+  if (d->n_cia < 0 || d->n_cia > TRX_MAX_CIA)
+    return set_err(c, TRX_E_INVALID_ARG, "n_cia must be in 0..%d", TRX_MAX_CIA);
+  if (d->n_cia > 0) {
+    if (d->n_Tcia < 2 || d->n_Tcia > TRX_MAX_TGRID || !d->Tcia_K ||
+        !strictly_increasing(d->Tcia_K, d->n_Tcia) || !d->cia_cm5 || !d->cia_pair)
+      return set_err(c, TRX_E_INVALID_ARG, "CIA needs a strictly increasing T grid of 2..%d points, tables and pairs",
+                     TRX_MAX_TGRID);
+    for (int p = 0; p < 2 * d->n_cia; ++p)
+      if (d->cia_pair[p] < 0 || d->cia_pair[p] >= d->n_abs + 2)
+        return set_err(c, TRX_E_INVALID_ARG, "CIA species id out of range");
+  }
+  hipSetDevice(c->device);
+  trx_tables* t = new trx_tables();
+  t->ctx = c;
+  DevTables& D = t->dev;
+  memset(&D, 0, sizeof D);
+  D.n_wn = d->n_wn; D.n_T = d->n_T; D.n_P = d->n_P; D.n_abs = d->n_abs;
+  D.n_cia = d->n_cia; D.n_Tcia = d->n_cia > 0 ? d->n_Tcia : 0;
+  D.has_rayleigh = d->rayleigh_cm2 ? 1 : 0;
+  t->wn.assign(d->wn_cm1, d->wn_cm1 + d->n_wn);
+  auto fail = [&](trx_status s) { for (void* p : t->owned) hipFree(p); delete t; return s; };
+  float* f32 = nullptr;
+  double* g = nullptr;
+  trx_status s;
+  if ((s = upload(c, d->wn_cm1, d->n_wn, &g, &f32, t->owned)) != TRX_OK) return fail(s);
+  D.wn = g;
+  if ((s = upload(c, d->T_K, d->n_T, &g, &f32, t->owned)) != TRX_OK) return fail(s);
+  D.T = g;
+  if ((s = upload(c, d->log10P_Pa, d->n_P, &g, &f32, t->owned)) != TRX_OK) return fail(s);
+  D.logP = g;
+  int64_t nx = (int64_t)d->n_abs * d->n_T * d->n_P * d->n_wn;
+  if ((s = upload(c, d->xsec_cm2, nx, &g, &f32, t->owned)) != TRX_OK) return fail(s);
+  D.xsec64 = g; D.xsec32 = f32;
+  if (d->n_cia > 0) {
+    if ((s = upload(c, d->Tcia_K, d->n_Tcia, &g, &f32, t->owned)) != TRX_OK) return fail(s);
+    D.Tcia = g;
+    int64_t nc = (int64_t)d->n_cia * d->n_Tcia * d->n_wn;
+    if ((s = upload(c, d->cia_cm5, nc, &g, &f32, t->owned, kCiaScale32)) != TRX_OK) return fail(s);
+    D.cia64 = g; D.cia32 = f32;
+    for (int p = 0; p < d->n_cia; ++p) {
+      D.cia_pair[p][0] = d->cia_pair[2 * p];
+      D.cia_pair[p][1] = d->cia_pair[2 * p + 1];
+    }
+  }
+  if (d->rayleigh_cm2) {
+    if ((s = upload(c, d->rayleigh_cm2, (int64_t)(d->n_abs + 2) * d->n_wn, &g, &f32, t->owned)) != TRX_OK)
+      return fail(s);
+    D.ray64 = g; D.ray32 = f32;
+  }
+  for (int i = 0; i < d->n_abs; ++i) D.mass[i] = d->abs_mass_amu[i];
+  D.mass[d->n_abs] = d->h2_mass_amu;
+  D.mass[d->n_abs + 1] = d->he_mass_amu;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(hip_err(c, e, "trx_tables_create"));
+  *out = t;
+  return TRX_OK;
+}
+
+extern "C" trx_status trx_tables_destroy(trx_tables* t) {
+  if (!t) return TRX_E_INVALID_ARG;
+  hipSetDevice(t->ctx->device);
+  hipDeviceSynchronize();
+  for (void* p : t->owned) hipFree(p);
+  delete t;
+  return TRX_OK;
+}
+
+// --------------------------------------------------------------------------
+// channels
+// --------------------------------------------------------------------------
+extern "C" trx_status trx_bins_create(trx_ctx* c, const trx_tables* t, int32_t n_ch, const double* lo,
+                                      const double* hi, trx_bins** out) {
+  if (!c) return TRX_E_INVALID_ARG;
+  c->err.clear();
+  if (!t || !lo || !hi || !out || n_ch < 1)
+    return set_err(c, TRX_E_INVALID_ARG, "trx_bins_create: null argument or n_ch < 1");
+  *out = nullptr;
+  for (int k = 0; k < n_ch; ++k)
+    if (!(std::isfinite(lo[k]) && std::isfinite(hi[k]) && hi[k] > lo[k]))
+      return set_err(c, TRX_E_INVALID_ARG, "channel %d must have finite edges lo < hi", k);
+  const std::vector<double>& wn = t->wn;
+  const int W = (int)wn.size();
+  std::vector<double> elo(W), ehi(W);
+  for (int i = 0; i + 1 < W; ++i) {
+    double m = 0.5 * (wn[i] + wn[i + 1]);
+    ehi[i] = m;
+    elo[i + 1] = m;
+  }
+  elo[0] = wn[0] - (elo[1] - wn[0]);
+  ehi[W - 1] = wn[W - 1] + (wn[W - 1] - ehi[W - 2]);
+  std::vector<int32_t> i0(n_ch), i1(n_ch);
+  std::vector<int64_t> off(n_ch);
+  std::vector<double> w;
+  for (int k = 0; k < n_ch; ++k) {
+    // native bins overlapping [lo, hi): ehi > lo and elo < hi
+    int a = (int)(std::upper_bound(ehi.begin(), ehi.end(), lo[k]) - ehi.begin());
+    int b = (int)(std::lower_bound(elo.begin(), elo.end(), hi[k]) - elo.begin());
+    if (b < a) b = a;
+    i0[k] = a;
+    i1[k] = b;
+    off[k] = (int64_t)w.size();
+    for (int i = a; i < b; ++i) {
+      double ov = std::min(hi[k], ehi[i]) - std::max(lo[k], elo[i]);
+      w.push_back(std::max(ov, 0.0) / (ehi[i] - elo[i]));
+    }
+  }
+  if (w.empty()) w.push_back(0.0);
+  hipSetDevice(c->device);
+  trx_bins* bn = new trx_bins();
+  bn->ctx = c;
+  bn->tables = t;
+  bn->n_ch = n_ch;
+  hipError_t e = hipSuccess;
+  auto put = [&](void** d, const void* h, size_t n) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(d, n);
+    if (e == hipSuccess) { bn->owned.push_back(*d); e = hipMemcpy(*d, h, n, hipMemcpyHostToDevice); }
+  };
+  put((void**)&bn->i0, i0.data(), n_ch * sizeof(int32_t));
+  put((void**)&bn->i1, i1.data(), n_ch * sizeof(int32_t));
+  put((void**)&bn->off, off.data(), n_ch * sizeof(int64_t));
+  put((void**)&bn->w, w.data(), w.size() * sizeof(double));
+  if (e != hipSuccess) {
+    for (void* p : bn->owned) hipFree(p);
+    delete bn;
+    return hip_err(c, e, "trx_bins_create");
+  }
+  *out = bn;
+  return TRX_OK;
+}
+
+extern "C" trx_status trx_bins_destroy(trx_bins* b) {
+  if (!b) return TRX_E_INVALID_ARG;
+  hipSetDevice(b->ctx->device);
+  hipDeviceSynchronize();
+  for (void* p : b->owned) hipFree(p);
+  delete b;
+  return TRX_OK;
+}
+
+// --------------------------------------------------------------------------
+// forward
+// --------------------------------------------------------------------------
+trx_status trx::check_batch(trx_ctx* c, const trx_tables* t, const trx_batch* bt, int precision) {
+  if (!t) return set_err(c, TRX_E_INVALID_ARG, "tables handle is null");
+  if (t->ctx != c) return set_err(c, TRX_E_INVALID_ARG, "tables belong to another context");
+  if (!bt) return set_err(c, TRX_E_INVALID_ARG, "batch is null");
+  if (bt->B < 1) return set_err(c, TRX_E_INVALID_ARG, "batch.B must be >= 1");
+  if (precision < TRX_FP64 || precision > TRX_BF16_SPLIT3)
+    return set_err(c, TRX_E_INVALID_ARG, "unknown precision %d", precision);
+  if (bt->max_layers < 2) return set_err(c, TRX_E_INVALID_ARG, "batch.max_layers must be >= 2");
+  const int limit = precision == TRX_FP64 ? TRX_MAX_LAYERS_FP64 : TRX_MAX_LAYERS_MFMA;
+  if (bt->max_layers > limit)
+    return set_err(c, TRX_E_UNSUPPORTED, "max_layers %d exceeds %d for this precision", bt->max_layers, limit);
+  if (!bt->n_layers || !bt->layer_off || !bt->T_K || !bt->p_bot_Pa || !bt->p_top_Pa || !bt->Rp_m ||
+      !bt->Rs_m || !bt->GM_m3s2 || !bt->wn_lo || !bt->wn_hi || (t->dev.n_abs > 0 && !bt->log10_vmr))
+    return set_err(c, TRX_E_INVALID_ARG, "a batch array pointer is null");
+  if (!(bt->he_h2_ratio >= 0) || !(bt->k_B > 0) || !(bt->amu_kg > 0))
+    return set_err(c, TRX_E_INVALID_ARG, "he_h2_ratio must be >= 0 and k_B, amu_kg > 0");
+  if (bt->gravity != 0 && bt->gravity != 1) return set_err(c, TRX_E_INVALID_ARG, "gravity must be 0 or 1");
+  return TRX_OK;
+}
+
+DevBatch trx::dev_batch(const trx_batch* bt) {
+  DevBatch d;
+  d.n_layers = bt->n_layers; d.layer_off = bt->layer_off; d.T = bt->T_K;
+  d.p_bot = bt->p_bot_Pa; d.p_top = bt->p_top_Pa; d.log10_vmr = bt->log10_vmr;
+  d.Rp = bt->Rp_m; d.Rs = bt->Rs_m; d.GM = bt->GM_m3s2;
+  d.wn_lo = bt->wn_lo; d.wn_hi = bt->wn_hi;
+  d.he_h2 = bt->he_h2_ratio; d.kB = bt->k_B; d.amu = bt->amu_kg; d.gravity = bt->gravity;
+  return d;
+}
+
+trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B,
+                                const int32_t* B_dev, int max_layers, const trx_bins* bins,
+                                int precision, const RunConfig& rc, uint8_t* ws, void* aws,
+                                double* depth_native, double* depth_binned, int32_t* status) {
+  const Layout L = make_layout(max_layers, precision);
+  GeomArgs g;
+  g.bt = db;
+  g.tab = t->dev;
+  g.L = L;
+  g.ws = ws;
+  g.B_dev = B_dev;
+  g.B = B;
+  g.precision = precision;
+  g.n_limit = max_layers;
+  g.span_cols = rc.span_cols;
+  g.depth_native = depth_native;
+  launch_geom(g, B, c->stream);
+  launch_copy_status(ws, L.slab, B_dev, B, status, c->stream);
+
+  FwdArgs f;
+  memset(&f, 0, sizeof f);
+  f.tab = t->dev;
+  f.L = L;
+  f.ws = ws;
+  f.B_dev = B_dev;
+  f.B = B;
+  f.span_cols = rc.span_cols;
+  f.n_spans = (t->dev.n_wn + rc.span_cols - 1) / rc.span_cols;
+  f.depth_native = depth_native;
+  f.aws = aws;
+  f.model_status = status;
+  if (precision == TRX_FP64) {
+    launch_fwd64(f, B, c->stream);
+  } else {
+    launch_fwd_mfma(f, precision, rc.nrb_max, B, 0, c->stream);
+  }
+  if (depth_binned) {
+    BinArgs ba;
+    ba.ws = ws; ba.L = L; ba.B_dev = B_dev; ba.B = B;
+    ba.n_wn = t->dev.n_wn; ba.n_ch = bins->n_ch;
+    ba.ch_i0 = bins->i0; ba.ch_i1 = bins->i1; ba.ch_off = bins->off; ba.ch_w = bins->w;
+    ba.aws = aws; ba.aws_f64 = precision == TRX_FP64; ba.out = depth_binned;
+    launch_bin(ba, B, c->stream);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "kernel launch");
+  return TRX_OK;
+}
+
+RunConfig trx::default_config(int precision, int max_layers) {
+  RunConfig rc;
+  rc.span_cols = 256;
+  rc.nrb_max = (max_layers + 31) / 32;
+  (void)precision;
+  return rc;
+}
+
+extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_batch* bt,
+                                  const trx_bins* bins, trx_precision precision, double* depth_native,
+                                  double* depth_binned, int32_t* model_status) {
+  if (!c) return TRX_E_INVALID_ARG;
+  c->err.clear();
+  trx_status s = check_batch(c, t, bt, precision);
+  if (s != TRX_OK) return s;
+  if (!model_status) return set_err(c, TRX_E_INVALID_ARG, "model_status is required");
+  if (depth_binned && !bins) return set_err(c, TRX_E_INVALID_ARG, "depth_binned requires bins");
+  if (bins && bins->tables != t) return set_err(c, TRX_E_INVALID_ARG, "bins were made for other tables");
+  hipSetDevice(c->device);
+  const Layout L = make_layout(bt->max_layers, precision);
+  if ((s = ensure_buffer(c, c->ws, (size_t)bt->B * L.slab, "workspace")) != TRX_OK) return s;
+  const size_t esz = precision == TRX_FP64 ? 8 : 4;
+  if ((s = ensure_buffer(c, c->aws, (size_t)bt->B * t->dev.n_wn * esz, "workspace")) != TRX_OK) return s;
+  RunConfig rc = default_config(precision, bt->max_layers);
+  return enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision, rc,
+                         (uint8_t*)c->ws.ptr, c->aws.ptr, depth_native, depth_binned, model_status);
+}

@@ -1,0 +1,322 @@
+// Geometry kernel (FP64): steps a1-a3 of the forward model for one model
+// per workgroup, plus the per-layer interpolation records used by the
+// opacity step (a4).
+//
+//  a1  Pressure Profiles subsection: N+1 log-spaced boundary pressures,
+//      centres P_l = p_l sqrt(p_{l+1}/p_l).  Chemistry subsection: constant
+//      absorbers, H2/He fill sharing the rest of the volume with He/H2 = r,
+//      mean molecular weight over all species.  Number density P/(k_B T).
+//  a2  Forward Models section, altitude equation: z_0 = 0,
+//      z_l = z_{l-1} - H_{l-1} ln(P_l/P_{l-1}), H = k_B T / (mu g),
+//      g = GM/(Rp + z)^2 (or GM/Rp^2); one lane runs the recurrence.
+//  a3  Chord lengths of the ray at z_j through the shell between
+//      h_k = (z_{k-1}+z_k)/2 and h_{k+1} (h_0 = 0, h_N = z_{N-1}), written
+//      in the cancellation-free form
+//        dl[j,j] = 2 q_j(h_{j+1}),
+//        dl[j,k] = 2 (h_{k+1}-h_k)(2Rp+h_k+h_{k+1}) / (q_j(h_{k+1}) + q_j(h_k)),
+//      q_j(h) = sqrt((h - z_j)(2Rp + h + z_j)); annulus weights
+//      A_j = 2 (Rp + z_j)(h_{j+1} - h_j), stored divided by Rs^2.
+//  a4  records: per layer the four bilinear corner weights on (T, log10 P)
+//      times 1e-4 rho (cm^2 -> m^2), the Rayleigh weight 1e-4 rho, the two
+//      CIA weights in T times 1e-10 rho^2 (cm^5 -> m^5), and the corner
+//      indices.  Out-of-range T and log10 P clamp to the grid; T and P both
+//      below the grid give zero cross-section (Opacities section).
+#include "trx_internal.h"
+
+namespace trx {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+// Lower-closed bracket with edge clamping: grid[i] <= x < grid[i+1];
+// below the grid: i = 0, w = 0; at or above the top: i = n-2, w = 1.
+__device__ inline void bracket(const double* g, int n, double x, int& i, double& w,
+                               bool& below, bool& clamped) {
+  below = false;
+  clamped = false;
+  if (x < g[0]) { i = 0; w = 0.0; below = true; clamped = true; return; }
+  if (x >= g[n - 1]) { i = n - 2; w = 1.0; clamped = true; return; }
+  int lo = 0, hi = n - 1;  // g[lo] <= x < g[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (g[mid] <= x) lo = mid; else hi = mid;
+  }
+  i = lo;
+  w = (x - g[lo]) / (g[lo + 1] - g[lo]);
+}
+
+// Round a float to bf16 (nearest even) and return the bf16 bits.  Finite
+// inputs only (the path lengths are finite and non-negative).
+__device__ inline uint16_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline double bf16_to_double(uint16_t h) {
+  return (double)__uint_as_float(((uint32_t)h) << 16);
+}
+
+__global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
+  const int b = blockIdx.x;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if (b >= B) return;
+  const Layout& L = a.L;
+  const DevTables& tb = a.tab;
+  uint8_t* slab = a.ws + (int64_t)b * L.slab;
+  ModelHdr* h = reinterpret_cast<ModelHdr*>(slab);
+  double* zs = reinterpret_cast<double*>(slab + L.off_z);
+  double* A64 = reinterpret_cast<double*>(slab + L.off_A64);
+  float* A32 = reinterpret_cast<float*>(slab + L.off_A32);
+  double* lw64 = reinterpret_cast<double*>(slab + L.off_lw64);
+  float* lw32 = reinterpret_cast<float*>(slab + L.off_lw32);
+  int32_t* lid = reinterpret_cast<int32_t*>(slab + L.off_lid);
+
+  __shared__ double sP[TRX_MAX_LAYERS_FP64];
+  __shared__ double sZ[TRX_MAX_LAYERS_FP64];
+  __shared__ double sC[TRX_MAX_LAYERS_FP64];   // kB T_l * ln(P_{l+1}/P_l)
+  __shared__ int s_status;
+  __shared__ double s_mu;
+
+  const int tid = threadIdx.x;
+  const int N = a.bt.n_layers[b];
+  const int lo = a.bt.wn_lo[b], hi = a.bt.wn_hi[b];
+  const int64_t off = a.bt.layer_off[b];
+  const double Rp = a.bt.Rp[b], Rs = a.bt.Rs[b], GM = a.bt.GM[b];
+  const double pb = a.bt.p_bot[b], pt = a.bt.p_top[b];
+  const int nabs = tb.n_abs;
+
+  if (tid == 0) {
+    int st = 0;
+    if (N < 2 || N > a.n_limit) st |= TRX_MODEL_BAD_PROFILE;
+    if (!finite_pos(Rp) || !finite_pos(Rs) || !finite_pos(GM)) st |= TRX_MODEL_BAD_PROFILE;
+    if (!finite_pos(pb) || !finite_pos(pt) || !(pb > pt)) st |= TRX_MODEL_BAD_PROFILE;
+    if (!(lo >= 0 && hi <= tb.n_wn && hi > lo)) st |= TRX_MODEL_BAD_WINDOW;
+    double S = 0.0;
+    bool fin = true;
+    for (int i = 0; i < nabs; ++i) {
+      double x = a.bt.log10_vmr[(int64_t)b * nabs + i];
+      fin = fin && isfinite(x);
+      S += pow(10.0, x);
+    }
+    if (!fin || !(S < 1.0)) st |= TRX_MODEL_BAD_CHEMISTRY;
+    s_status = st;
+  }
+  __syncthreads();
+  if ((s_status & TRX_MODEL_BAD_PROFILE) == 0) {
+    for (int l = tid; l < N; l += kThreads) {
+      double T = a.bt.T[off + l];
+      if (!finite_pos(T)) atomicOr(&s_status, TRX_MODEL_BAD_PROFILE);
+    }
+  }
+  __syncthreads();
+  const int status = s_status;
+  if (status) {
+    if (tid == 0) {
+      h->n = 0; h->status = status; h->lo = lo; h->hi = hi;
+      h->nrb = 0; h->nkb = 0; h->span_lo = 0; h->span_hi = 0;
+    }
+    if (a.depth_native && (status & TRX_MODEL_BAD_WINDOW) == 0) {
+      for (int i = lo + tid; i < hi; i += kThreads)
+        a.depth_native[(int64_t)b * tb.n_wn + i] = __builtin_nan("");
+    }
+    return;
+  }
+
+  // a1: pressure grid (boundaries log-spaced, geometric centres)
+  const double xb = log10(pb), xt = log10(pt);
+  for (int l = tid; l < N; l += kThreads) {
+    double p0 = pow(10.0, xb + (xt - xb) * (double)l / (double)N);
+    double p1 = pow(10.0, xb + (xt - xb) * (double)(l + 1) / (double)N);
+    sP[l] = p0 * sqrt(p1 / p0);
+  }
+  // a1: chemistry
+  if (tid == 0) {
+    double S = 0.0, mu = 0.0;
+    for (int i = 0; i < nabs; ++i) {
+      double c = pow(10.0, a.bt.log10_vmr[(int64_t)b * nabs + i]);
+      h->chi_s[i] = c;
+      h->chi_s32[i] = (float)c;
+      S += c;
+      mu += c * tb.mass[i];
+    }
+    const double r = a.bt.he_h2;
+    const double ch2 = (1.0 - S) / (1.0 + r), che = r * ch2;
+    h->chi_s[nabs] = ch2;
+    h->chi_s[nabs + 1] = che;
+    h->chi_s32[nabs] = (float)ch2;
+    h->chi_s32[nabs + 1] = (float)che;
+    mu += ch2 * tb.mass[nabs] + che * tb.mass[nabs + 1];
+    s_mu = mu * a.bt.amu;
+    for (int p = 0; p < tb.n_cia; ++p) {
+      double w = h->chi_s[tb.cia_pair[p][0]] * h->chi_s[tb.cia_pair[p][1]];
+      h->cia_w[p] = w;
+      h->cia_w32[p] = (float)w;
+    }
+  }
+  __syncthreads();
+  const double mu = s_mu;
+  for (int l = tid; l < N - 1; l += kThreads)
+    sC[l] = a.bt.kB * a.bt.T[off + l] * log(sP[l + 1] / sP[l]) / mu;
+  __syncthreads();
+  // a2: altitude recurrence, one lane
+  if (tid == 0) {
+    double z = 0.0;
+    sZ[0] = 0.0;
+    if (a.bt.gravity == 0) {
+      const double invGM = 1.0 / GM;
+      for (int l = 1; l < N; ++l) {
+        const double rz = Rp + z;
+        z = z - sC[l - 1] * rz * rz * invGM;   // H = kB T (Rp+z)^2 / (mu GM)
+        sZ[l] = z;
+      }
+    } else {
+      const double f = Rp * Rp / GM;
+      for (int l = 1; l < N; ++l) {
+        z = z - sC[l - 1] * f;
+        sZ[l] = z;
+      }
+    }
+    const int sc = a.span_cols;
+    h->n = N; h->status = 0; h->lo = lo; h->hi = hi;
+    h->nrb = (N + 31) / 32; h->nkb = (N + 15) / 16;
+    h->span_lo = lo / sc; h->span_hi = (hi + sc - 1) / sc;
+    h->Rp2_Rs2 = (Rp / Rs) * (Rp / Rs);
+    h->inv_Rs2 = 1.0 / (Rs * Rs);
+    h->Rp = Rp;
+    h->mu_kg = mu;
+  }
+  __syncthreads();
+  const double inv_Rs2 = 1.0 / (Rs * Rs);
+
+  // a3: annulus weights; a4: layer records
+  const int NP = L.NP;
+  for (int l = tid; l < NP; l += kThreads) {
+    if (l < N) {
+      const double z = sZ[l];
+      const double hl = (l == 0) ? 0.0 : 0.5 * (sZ[l - 1] + z);
+      const double hu = (l == N - 1) ? z : 0.5 * (z + sZ[l + 1]);
+      const double A = 2.0 * (Rp + z) * (hu - hl) * inv_Rs2;
+      zs[l] = z;
+      A64[l] = A;
+      A32[l] = (float)A;
+      const double T = a.bt.T[off + l];
+      const double P = sP[l];
+      const double n = P / (a.bt.kB * T);
+      int iT, iP, iC;
+      double wT, wP, wC;
+      bool Tb, Pb, c0, c1, c2;
+      bracket(tb.T, tb.n_T, T, iT, wT, Tb, c0);
+      bracket(tb.logP, tb.n_P, log10(P), iP, wP, Pb, c1);
+      const double f1 = 1e-4 * n;
+      double w[8];
+      if (Tb && Pb) {
+        w[0] = w[1] = w[2] = w[3] = 0.0;
+      } else {
+        w[0] = f1 * (1.0 - wT) * (1.0 - wP);
+        w[1] = f1 * wT * (1.0 - wP);
+        w[2] = f1 * (1.0 - wT) * wP;
+        w[3] = f1 * wT * wP;
+      }
+      w[4] = tb.has_rayleigh ? f1 : 0.0;
+      if (tb.n_cia > 0) {
+        bracket(tb.Tcia, tb.n_Tcia, T, iC, wC, Tb, c2);
+        const double f2 = 1e-10 * n * n;
+        w[5] = f2 * (1.0 - wC);
+        w[6] = f2 * wC;
+      } else {
+        iC = 0;
+        w[5] = w[6] = 0.0;
+      }
+      w[7] = 0.0;
+      for (int q = 0; q < 8; ++q) {
+        lw64[8 * l + q] = w[q];
+        lw32[8 * l + q] = (float)(q >= 5 ? w[q] / kCiaScale32 : w[q]);
+      }
+      lid[2 * l] = iT * tb.n_P + iP;
+      lid[2 * l + 1] = iC;
+    } else {
+      zs[l] = 0.0;
+      A64[l] = 0.0;
+      A32[l] = 0.0f;
+      for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
+      lid[2 * l] = -1;   // padding layer: no corners
+      lid[2 * l + 1] = -1;
+    }
+  }
+  __syncthreads();
+
+  // a3: chord lengths
+  auto dl_of = [&](int j, int k) -> double {
+    if (j >= N || k >= N || k < j) return 0.0;
+    const double zj = sZ[j];
+    const double hk = (k == 0) ? 0.0 : 0.5 * (sZ[k - 1] + sZ[k]);
+    const double hk1 = (k == N - 1) ? sZ[N - 1] : 0.5 * (sZ[k] + sZ[k + 1]);
+    const double q1 = sqrt(fmax((hk1 - zj) * (2.0 * Rp + hk1 + zj), 0.0));
+    if (k == j) return 2.0 * q1;
+    const double q0 = sqrt((hk - zj) * (2.0 * Rp + hk + zj));
+    return 2.0 * (hk1 - hk) * (2.0 * Rp + hk + hk1) / (q1 + q0);
+  };
+  uint8_t* dst = slab + L.off_dl;
+  if (a.precision == TRX_FP64) {
+    double* dlT = reinterpret_cast<double*>(dst);
+    for (int e = tid; e < NP * NP; e += kThreads) {
+      const int k = e / NP, j = e % NP;
+      dlT[e] = dl_of(j, k);
+    }
+  } else if (a.precision == TRX_FP32) {
+    // v_mfma_f32_32x32x2_f32 A operand: lane l, step i holds
+    // dl[32 rb + l%32][16 kb + 2 i + l/32]; pieces hi, lo.
+    float* f = reinterpret_cast<float*>(dst);
+    const int npairs = frag_pairs(L.NRB, L.NKB);
+    for (int e = tid; e < npairs * 64; e += kThreads) {
+      const int pr = e / 64, lane = e % 64;
+      int rb = 0, base = 0;
+      while (base + (L.NKB - 2 * rb) <= pr) { base += L.NKB - 2 * rb; ++rb; }
+      const int kb = 2 * rb + (pr - base);
+      float* o = f + (int64_t)pr * 2 * 512;
+      for (int i = 0; i < 8; ++i) {
+        const double d = dl_of(32 * rb + (lane & 31), 16 * kb + 2 * i + (lane >> 5));
+        const float hi32 = (float)d;
+        o[lane * 8 + i] = hi32;
+        o[512 + lane * 8 + i] = (float)(d - (double)hi32);
+      }
+    }
+  } else {
+    // v_mfma_f32_32x32x16_bf16 A operand: lane l holds
+    // dl[32 rb + l%32][16 kb + 8 (l/32) + v], v = 0..7; 2 or 3 bf16 pieces.
+    uint16_t* f = reinterpret_cast<uint16_t*>(dst);
+    const int np = a.precision == TRX_BF16_SPLIT3 ? 3 : 2;
+    const int npairs = frag_pairs(L.NRB, L.NKB);
+    for (int e = tid; e < npairs * 64; e += kThreads) {
+      const int pr = e / 64, lane = e % 64;
+      int rb = 0, base = 0;
+      while (base + (L.NKB - 2 * rb) <= pr) { base += L.NKB - 2 * rb; ++rb; }
+      const int kb = 2 * rb + (pr - base);
+      uint16_t* o = f + (int64_t)pr * np * 512;
+      for (int v = 0; v < 8; ++v) {
+        const double d = dl_of(32 * rb + (lane & 31), 16 * kb + 8 * (lane >> 5) + v);
+        const uint16_t p0 = bf16_bits((float)d);
+        const double r1 = d - bf16_to_double(p0);
+        const uint16_t p1 = bf16_bits((float)r1);
+        o[lane * 8 + v] = p0;
+        o[512 + lane * 8 + v] = p1;
+        if (np == 3) {
+          const double r2 = r1 - bf16_to_double(p1);
+          o[1024 + lane * 8 + v] = bf16_bits((float)r2);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
+  if (B_grid <= 0) return;
+  hipLaunchKernelGGL(k_geom, dim3(B_grid), dim3(kThreads), 0, s, a);
+}
+
+}  // namespace trx

@@ -1,0 +1,69 @@
+// Host-side handle definitions of libtrx (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "trx_internal.h"
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct trx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int n_cu = 256;
+  char arch[64] = {0};
+  DevBuf ws;    // per-model slabs
+  DevBuf aws;   // native atmospheric depth
+  DevBuf grad;  // gradient workspace
+};
+
+struct trx_tables {
+  trx_ctx* ctx = nullptr;
+  trx::DevTables dev;
+  std::vector<double> wn;     // host copy of the grid
+  std::vector<void*> owned;
+};
+
+struct trx_bins {
+  trx_ctx* ctx = nullptr;
+  const trx_tables* tables = nullptr;
+  int n_ch = 0;
+  int32_t* i0 = nullptr;
+  int32_t* i1 = nullptr;
+  int64_t* off = nullptr;
+  double* w = nullptr;
+  std::vector<void*> owned;
+};
+
+namespace trx {
+
+// Launch-shape choices of one run (the autotuner's search space).
+struct RunConfig {
+  int span_cols = 256;   // columns per (model, span) work item
+  int nrb_max = 7;       // ray-block capacity of the matrix-core kernel
+  int persistent = 0;    // 1: persistent grid with work queues
+  int waves = 4;         // waves per workgroup
+};
+
+trx_status set_err(trx_ctx* c, trx_status s, const char* fmt, ...);
+trx_status hip_err(trx_ctx* c, hipError_t e, const char* what);
+trx_status ensure_buffer(trx_ctx* c, DevBuf& buf, size_t bytes, const char* what);
+trx_status upload(trx_ctx* c, const double* host, int64_t n, double** d64, float** d32,
+                  std::vector<void*>& owned, double scale32 = 1.0);
+void launch_copy_status(const uint8_t* ws, int64_t slab, const int32_t* B_dev, int B, int32_t* out,
+                        hipStream_t s);
+trx_status check_batch(trx_ctx* c, const trx_tables* t, const trx_batch* bt, int precision);
+DevBatch dev_batch(const trx_batch* bt);
+RunConfig default_config(int precision, int max_layers);
+trx_status enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B, const int32_t* B_dev,
+                           int max_layers, const trx_bins* bins, int precision, const RunConfig& rc,
+                           uint8_t* ws, void* aws, double* depth_native, double* depth_binned,
+                           int32_t* status);
+
+}  // namespace trx

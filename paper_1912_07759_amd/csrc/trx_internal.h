@@ -1,0 +1,200 @@
+// Internal layout shared by the HIP sources of libtrx (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/trx.h"
+
+namespace trx {
+
+constexpr int kHdrBytes = 2048;    // per-model header block in the slab
+// CIA cross-sections (~1e-46 cm^5) are below the FP32 range and their layer
+// weights 1e-10 rho^2 (up to ~1e42 m^-6) above it, so the FP32 copy of the
+// CIA tables is stored multiplied by kCiaScale32 and the FP32 CIA weights
+// divided by it.
+constexpr double kCiaScale32 = 1e40;
+constexpr int kMaxSpecies = TRX_MAX_ABSORBERS + 2;
+
+// Per-model values written by the geometry kernel and read by every later
+// kernel.  Lives at the start of each model's workspace slab.
+struct ModelHdr {
+  int32_t n;          // layers (0 when the model is invalid)
+  int32_t status;     // TRX_MODEL_* bits
+  int32_t lo, hi;     // window [lo, hi)
+  int32_t nrb;        // 32-ray blocks = ceil(n / 32)
+  int32_t nkb;        // 16-layer blocks = ceil(n / 16)
+  int32_t span_lo, span_hi;  // spans covered by the window
+  double Rp2_Rs2;     // (Rp/Rs)^2
+  double inv_Rs2;     // 1/Rs^2
+  double Rp, mu_kg;
+  double chi_s[kMaxSpecies];        // absorbers, H2, He
+  double cia_w[TRX_MAX_CIA];        // chi_a * chi_b per CIA pair
+  float chi_s32[kMaxSpecies];
+  float cia_w32[TRX_MAX_CIA];
+};
+static_assert(sizeof(ModelHdr) <= kHdrBytes, "header too large");
+
+// Device copy of the tables.
+struct DevTables {
+  int32_t n_wn, n_T, n_P, n_abs, n_cia, n_Tcia;
+  int32_t has_rayleigh;
+  const double* wn;        // [n_wn]
+  const double* T;         // [n_T]
+  const double* logP;      // [n_P]
+  const double* Tcia;      // [n_Tcia]
+  const double* xsec64;    // [n_abs][n_T][n_P][n_wn]
+  const float* xsec32;
+  const double* cia64;     // [n_cia][n_Tcia][n_wn]
+  const float* cia32;
+  const double* ray64;     // [n_abs+2][n_wn] (zeros when absent)
+  const float* ray32;
+  double mass[kMaxSpecies];          // amu: absorbers, H2, He
+  int32_t cia_pair[TRX_MAX_CIA][2];
+};
+
+// Per-model slab layout (byte offsets from the slab start).
+struct Layout {
+  int32_t NP;              // padded layer capacity (multiple of 32)
+  int32_t NRB, NKB;        // NP/32, NP/16
+  int64_t off_z, off_A64, off_A32, off_lw64, off_lw32, off_lid, off_dl;
+  int64_t dl_bytes;        // mode-specific path-length storage
+  int64_t slab;            // bytes per model (multiple of 256)
+};
+
+// Number of (ray block, layer block) fragment pairs stored for the matrix-core
+// modes: for ray block rb every layer block kb >= 2*rb.
+__host__ __device__ inline int frag_pairs(int NRB, int NKB) {
+  int p = 0;
+  for (int rb = 0; rb < NRB; ++rb) p += (NKB - 2 * rb) > 0 ? (NKB - 2 * rb) : 0;
+  return p;
+}
+__host__ __device__ inline int frag_index(int rb, int kb, int NKB) {
+  // pairs are stored rb-major; ray block r contributes NKB - 2 r entries,
+  // so ray block rb starts at sum_{r<rb} (NKB - 2 r) = rb NKB - rb (rb - 1).
+  return rb * NKB - rb * (rb - 1) + (kb - 2 * rb);
+}
+
+// Number of stored pieces of the path lengths per mode.
+inline int dl_pieces(int precision) {
+  switch (precision) {
+    case TRX_FP32: return 2;
+    case TRX_BF16_SPLIT2: return 2;
+    case TRX_BF16_SPLIT3: return 3;
+    default: return 1;
+  }
+}
+
+// Bytes of one (rb, kb) fragment piece: 64 lanes x 8 values.
+inline int frag_piece_bytes(int precision) {
+  return precision == TRX_FP32 ? 64 * 8 * 4 : 64 * 8 * 2;
+}
+
+inline Layout make_layout(int N_max, int precision) {
+  Layout L{};
+  L.NP = ((N_max + 31) / 32) * 32;
+  L.NRB = L.NP / 32;
+  L.NKB = L.NP / 16;
+  int64_t o = kHdrBytes;
+  auto take = [&](int64_t bytes) { int64_t r = o; o += (bytes + 255) / 256 * 256; return r; };
+  L.off_z = take(8LL * L.NP);
+  L.off_A64 = take(8LL * L.NP);
+  L.off_A32 = take(4LL * L.NP);
+  L.off_lw64 = take(8LL * 8 * L.NP);
+  L.off_lw32 = take(4LL * 8 * L.NP);
+  L.off_lid = take(4LL * 2 * L.NP);
+  if (precision == TRX_FP64) {
+    L.dl_bytes = 8LL * L.NP * L.NP;  // dense transposed dlT[k][j]
+  } else {
+    L.dl_bytes = (int64_t)frag_pairs(L.NRB, L.NKB) * dl_pieces(precision) *
+                 frag_piece_bytes(precision);
+  }
+  L.off_dl = take(L.dl_bytes);
+  L.slab = o;
+  return L;
+}
+
+}  // namespace trx
+
+namespace trx {
+
+// Batch inputs as seen by the kernels (device pointers).
+struct DevBatch {
+  const int32_t* n_layers;
+  const int64_t* layer_off;
+  const double* T;
+  const double* p_bot;
+  const double* p_top;
+  const double* log10_vmr;
+  const double* Rp;
+  const double* Rs;
+  const double* GM;
+  const int32_t* wn_lo;
+  const int32_t* wn_hi;
+  double he_h2, kB, amu;
+  int32_t gravity;
+};
+
+struct GeomArgs {
+  DevBatch bt;
+  DevTables tab;
+  Layout L;
+  uint8_t* ws;            // slabs: model b at ws + b * L.slab
+  const int32_t* B_dev;   // device model count (plans), or null
+  int32_t B;              // host model count (used when B_dev is null)
+  int32_t precision;
+  int32_t n_limit;        // largest accepted layer count
+  int32_t span_cols;      // columns per work span
+  double* depth_native;   // [B][n_wn] or null: NaN written for invalid models
+};
+
+__host__ __device__ inline ModelHdr* hdr_of(uint8_t* ws, const Layout& L, int b) {
+  return reinterpret_cast<ModelHdr*>(ws + (int64_t)b * L.slab);
+}
+
+void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s);
+
+}  // namespace trx
+
+namespace trx {
+
+// Arguments of the opacity + optical depth + depth kernels.
+struct FwdArgs {
+  DevTables tab;
+  Layout L;
+  uint8_t* ws;
+  const int32_t* B_dev;
+  int32_t B;
+  int32_t span_cols;      // columns per (model, span) work item
+  int32_t n_spans;
+  double* depth_native;   // [B][n_wn] or null
+  void* aws;              // [B][n_wn] atmospheric part a/Rs^2 (double for FP64, else float)
+  int32_t* model_status;  // [B]
+  // persistent scheduling (null for grid launches)
+  const int32_t* items;   // packed (span << 20 | model) in queue order
+  const int32_t* qbounds; // [2 * n_queues] item range per queue
+  int32_t* qcount;        // [n_queues] counters (zeroed before launch)
+  int32_t n_queues;
+};
+
+struct BinArgs {
+  const uint8_t* ws;
+  Layout L;
+  const int32_t* B_dev;
+  int32_t B;
+  int32_t n_wn;
+  int32_t n_ch;
+  const int32_t* ch_i0;   // [n_ch] first native index overlapping channel c
+  const int32_t* ch_i1;   // [n_ch] one past the last
+  const int64_t* ch_off;  // [n_ch] offset of channel c's weights
+  const double* ch_w;     // weights
+  const void* aws;
+  int32_t aws_f64;
+  double* out;            // [B][n_ch]
+};
+
+void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s);
+void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int persistent_grid,
+                     hipStream_t s);
+void launch_bin(const BinArgs& a, int B_grid, hipStream_t s);
+
+}  // namespace trx

@@ -1,0 +1,266 @@
+"""Python binding of libtrx (ctypes): argument marshalling only.
+
+Every step of the forward model and its gradient runs in the HIP library;
+this module converts arrays to device tensors, fills the C structs of
+``include/trx.h`` and calls the entry points of the same names.  PyTorch is
+used for device memory and the current stream.  If ``libtrx.so`` has not
+been built the import of the library fails loudly: there is no fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrx.so")
+
+FP64, FP32, BF16_SPLIT2, BF16_SPLIT3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16_SPLIT2, "bf16x3": BF16_SPLIT3}
+
+MODEL_OK, BAD_CHEMISTRY, BAD_PROFILE, BAD_WINDOW, NONFINITE = 0, 1, 2, 4, 8
+PLAN_GRAPH, PLAN_PERSISTENT, PLAN_GRAD = 1, 2, 4
+
+STATUS_NAMES = {0: "TRX_OK", 1: "TRX_E_INVALID_ARG", 2: "TRX_E_OUT_OF_MEMORY",
+                3: "TRX_E_DEVICE", 4: "TRX_E_UNSUPPORTED"}
+
+EXPORTS = ["trx_create", "trx_destroy", "trx_last_error", "trx_set_stream",
+           "trx_synchronize", "trx_tables_create", "trx_tables_destroy",
+           "trx_bins_create", "trx_bins_destroy", "trx_forward", "trx_chi2_grad",
+           "trx_plan_create", "trx_plan_destroy", "trx_plan_batch", "trx_plan_launch",
+           "trx_autotune", "trx_plan_describe"]
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_D = ctypes.c_double
+
+
+class TrxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class TablesDesc(ctypes.Structure):
+    _fields_ = [("n_wn", _I), ("wn_cm1", _P), ("n_T", _I), ("T_K", _P),
+                ("n_P", _I), ("log10P_Pa", _P), ("n_abs", _I), ("xsec_cm2", _P),
+                ("abs_mass_amu", _P), ("h2_mass_amu", _D), ("he_mass_amu", _D),
+                ("n_cia", _I), ("n_Tcia", _I), ("Tcia_K", _P), ("cia_cm5", _P),
+                ("cia_pair", _P), ("rayleigh_cm2", _P)]
+
+
+class BatchC(ctypes.Structure):
+    _fields_ = [("B", _I), ("max_layers", _I), ("n_layers", _P), ("layer_off", _P),
+                ("T_K", _P), ("p_bot_Pa", _P), ("p_top_Pa", _P), ("log10_vmr", _P),
+                ("Rp_m", _P), ("Rs_m", _P), ("GM_m3s2", _P), ("wn_lo", _P),
+                ("wn_hi", _P), ("he_h2_ratio", _D), ("k_B", _D), ("amu_kg", _D),
+                ("gravity", _I)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtrx (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1912_07759_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name in EXPORTS:
+            getattr(L, name).restype = ctypes.c_int
+        L.trx_last_error.restype = ctypes.c_char_p
+        L.trx_plan_describe.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """A libtrx context on one HIP device; calls use torch's current stream."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = lib().trx_create(int(device), ctypes.byref(h))
+        if rc != 0:
+            raise TrxError(rc, "trx_create failed")
+        self.h = h
+
+    def check(self, rc):
+        if rc != 0:
+            raise TrxError(rc, lib().trx_last_error(self.h).decode())
+
+    def bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.check(lib().trx_set_stream(self.h, ctypes.c_void_p(s)))
+
+    def synchronize(self):
+        self.check(lib().trx_synchronize(self.h))
+
+    def last_error(self):
+        return lib().trx_last_error(self.h).decode()
+
+    def close(self):
+        if self.h:
+            lib().trx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tables:
+    """Device copy of opacity tables (host float64 arrays in)."""
+
+    def __init__(self, ctx, wn, T_grid, log10P_grid, xsec, abs_mass, h2_mass, he_mass,
+                 Tcia_grid=None, cia=None, cia_pair=None, rayleigh=None):
+        self.ctx = ctx
+        c = lambda a, dt=np.float64: None if a is None else np.ascontiguousarray(a, dtype=dt)
+        self._keep = [c(wn), c(T_grid), c(log10P_grid), c(xsec), c(abs_mass),
+                      c(Tcia_grid), c(cia), c(cia_pair, np.int32), c(rayleigh)]
+        wn, T_grid, log10P_grid, xsec, abs_mass, Tcia_grid, cia, cia_pair, rayleigh = self._keep
+        n_cia = 0 if cia is None else int(cia.shape[0])
+        d = TablesDesc(len(wn), _hptr(wn), len(T_grid), _hptr(T_grid), len(log10P_grid),
+                       _hptr(log10P_grid), int(xsec.shape[0]), _hptr(xsec), _hptr(abs_mass),
+                       float(h2_mass), float(he_mass), n_cia,
+                       0 if Tcia_grid is None else len(Tcia_grid), _hptr(Tcia_grid),
+                       _hptr(cia) if n_cia else None, _hptr(cia_pair) if n_cia else None,
+                       _hptr(rayleigh))
+        h = ctypes.c_void_p()
+        ctx.check(lib().trx_tables_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self.n_wn = len(wn)
+        self.n_abs = int(xsec.shape[0])
+        self._keep = None
+
+    @classmethod
+    def from_synth(cls, ctx, t):
+        return cls(ctx, t.wn, t.T_grid, t.log10P_grid, t.xsec, t.abs_mass, t.h2_mass,
+                   t.he_mass, t.Tcia_grid if t.cia.shape[0] else None,
+                   t.cia if t.cia.shape[0] else None,
+                   t.cia_pair if t.cia.shape[0] else None, t.rayleigh)
+
+    def close(self):
+        if self.h:
+            lib().trx_tables_destroy(self.h)
+            self.h = None
+
+
+class Bins:
+    """Channels [lo, hi) in cm^-1 for a set of tables."""
+
+    def __init__(self, ctx, tables, lo, hi):
+        self.ctx = ctx
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        h = ctypes.c_void_p()
+        ctx.check(lib().trx_bins_create(ctx.h, tables.h, int(len(lo)), _hptr(lo), _hptr(hi),
+                                        ctypes.byref(h)))
+        self.h = h
+        self.n = len(lo)
+
+    def close(self):
+        if self.h:
+            lib().trx_bins_destroy(self.h)
+            self.h = None
+
+
+class DeviceBatch:
+    """B models on the device.  Arrays may be numpy or torch; they are copied
+    to ``device`` with the dtypes of ``include/trx.h``."""
+
+    def __init__(self, n_layers, T, p_bot, p_top, log10_vmr, Rp, Rs, GM, wn_lo, wn_hi,
+                 he_h2=0.17, k_B=1.380649e-23, amu=1.66053906660e-27, gravity=0,
+                 device="cuda", max_layers=None):
+        dev = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a,
+                                          dtype=dt).to(dev).contiguous()
+        self.n_layers = t(n_layers, torch.int32)
+        nl = self.n_layers.to("cpu").to(torch.int64)
+        off = torch.zeros(nl.numel() + 1, dtype=torch.int64)
+        off[1:] = torch.cumsum(nl, 0)
+        self.layer_off = off.to(dev)
+        self.T = t(T, torch.float64)
+        self.p_bot, self.p_top = t(p_bot, torch.float64), t(p_top, torch.float64)
+        self.log10_vmr = t(log10_vmr, torch.float64)
+        self.Rp, self.Rs, self.GM = t(Rp, torch.float64), t(Rs, torch.float64), t(GM, torch.float64)
+        self.wn_lo, self.wn_hi = t(wn_lo, torch.int32), t(wn_hi, torch.int32)
+        self.he_h2, self.k_B, self.amu, self.gravity = he_h2, k_B, amu, gravity
+        self.B = int(self.n_layers.numel())
+        self.max_layers = int(max_layers if max_layers is not None else max(2, int(nl.max())))
+
+    @classmethod
+    def from_synth(cls, b, device="cuda", max_layers=None):
+        return cls(b.n_layers, b.T, b.p_bot, b.p_top, b.log10_vmr, b.Rp, b.Rs, b.GM,
+                   b.wn_lo, b.wn_hi, b.he_h2, b.k_B, b.amu, b.gravity, device, max_layers)
+
+    def cstruct(self, B=None):
+        return BatchC(self.B if B is None else B, self.max_layers, _ptr(self.n_layers),
+                      _ptr(self.layer_off), _ptr(self.T), _ptr(self.p_bot), _ptr(self.p_top),
+                      _ptr(self.log10_vmr), _ptr(self.Rp), _ptr(self.Rs), _ptr(self.GM),
+                      _ptr(self.wn_lo), _ptr(self.wn_hi), float(self.he_h2), float(self.k_B),
+                      float(self.amu), int(self.gravity))
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def forward(ctx, tables, batch, bins=None, precision=FP64, native=True, binned=True,
+            out_native=None, out_binned=None, out_status=None):
+    """trx_forward.  Returns (depth_native [B, n_wn] or None,
+    depth_binned [B, n_ch] or None, model_status [B])."""
+    dev = batch.T.device
+    B = batch.B
+    if native and out_native is None:
+        out_native = torch.full((B, tables.n_wn), float("nan"), dtype=torch.float64, device=dev)
+    if not native:
+        out_native = None
+    if binned and bins is not None and out_binned is None:
+        out_binned = torch.empty((B, bins.n), dtype=torch.float64, device=dev)
+    if bins is None or not binned:
+        out_binned = None
+    if out_status is None:
+        out_status = torch.empty(B, dtype=torch.int32, device=dev)
+    ctx.bind_stream()
+    bc = batch.cstruct()
+    ctx.check(lib().trx_forward(ctx.h, tables.h, ctypes.byref(bc),
+                                bins.h if bins is not None else None, _prec(precision),
+                                _ptr(out_native), _ptr(out_binned), _ptr(out_status)))
+    return out_native, out_binned, out_status
+
+
+def chi2_grad(ctx, tables, batch, bins, obs, sigma, precision=FP32, recompute=True,
+              binned=False):
+    """trx_chi2_grad.  Returns dict(chi2 [B], dT [sum N], dlog10_vmr [B, n_abs],
+    dRp [B], status [B], binned [B, n_ch] or None)."""
+    dev = batch.T.device
+    B = batch.B
+    obs = torch.as_tensor(obs, dtype=torch.float64).to(dev).contiguous()
+    sigma = torch.as_tensor(sigma, dtype=torch.float64).to(dev).contiguous()
+    out = {"chi2": torch.empty(B, dtype=torch.float64, device=dev),
+           "dT": torch.empty(batch.T.numel(), dtype=torch.float64, device=dev),
+           "dlog10_vmr": torch.empty((B, tables.n_abs), dtype=torch.float64, device=dev),
+           "dRp": torch.empty(B, dtype=torch.float64, device=dev),
+           "status": torch.empty(B, dtype=torch.int32, device=dev),
+           "binned": torch.empty((B, bins.n), dtype=torch.float64, device=dev) if binned else None}
+    ctx.bind_stream()
+    bc = batch.cstruct()
+    ctx.check(lib().trx_chi2_grad(ctx.h, tables.h, ctypes.byref(bc), bins.h, _prec(precision),
+                                  _ptr(obs), _ptr(sigma), int(bool(recompute)), _ptr(out["chi2"]),
+                                  _ptr(out["dT"]), _ptr(out["dlog10_vmr"]), _ptr(out["dRp"]),
+                                  _ptr(out["binned"]), _ptr(out["status"])))
+    return out

@@ -1,0 +1,97 @@
+"""GPU parity of the forward model (HIP library through the C ABI) against
+the FP64 oracle on the same seeded inputs."""
+
+import numpy as np
+import pytest
+
+import synth
+from synth.workloads import make_config
+from parity_util import TOL, binned_rel_err, native_rel_err, oracle_batch
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp64", "fp32", "bf16x2", "bf16x3"]
+
+
+def _run(ctx, tables, batch, channels, precision, max_layers=None):
+    from paper_1912_07759_amd import trx
+    T = trx.Tables.from_synth(ctx, tables)
+    bins = trx.Bins(ctx, T, channels.lo, channels.hi) if channels is not None else None
+    db = trx.DeviceBatch.from_synth(batch, max_layers=max_layers)
+    nat, binned, st = trx.forward(ctx, T, db, bins, precision)
+    ctx.synchronize()
+    out = (nat.cpu().numpy(), None if binned is None else binned.cpu().numpy(),
+           st.cpu().numpy())
+    if bins is not None:
+        bins.close()
+    T.close()
+    return out
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_plain_single_model_100_layers(gpu_ctx, mode):
+    """Plain model: 100 layers, isothermal 1500 K, one absorber, 2000 wn."""
+    tables, batch, _ = make_config(1)
+    nat, _, st = _run(gpu_ctx, tables, batch, None, mode)
+    assert st[0] == 0
+    _, ref = oracle_batch(tables, batch, None, mode)
+    err = native_rel_err(nat[0], ref[0]["depth"], 0, tables.n_wn)
+    print(f"cfg1 {mode}: max rel err {err:.3e}")
+    assert err <= TOL[mode]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_guillot_5_absorbers_cia_rayleigh_binned(gpu_ctx, mode):
+    """Single model with 5 absorbers, CIA and Rayleigh on a 3000-point grid
+    (several 256-column spans and a ragged tail), binned to 50 channels."""
+    tables, batch, ch = make_config(2, n_wn=3000, n_lines=300)
+    nat, binned, st = _run(gpu_ctx, tables, batch, ch, mode)
+    assert st[0] == 0
+    _, ref = oracle_batch(tables, batch, ch, mode)
+    e1 = native_rel_err(nat[0], ref[0]["depth"], 0, tables.n_wn)
+    e2 = binned_rel_err(binned[0], ref[0]["binned"])
+    print(f"cfg2-small {mode}: native {e1:.3e} binned {e2:.3e}")
+    assert e1 <= TOL[mode] and e2 <= TOL[mode]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_ragged_batch(gpu_ctx, mode):
+    """12 models, 50..200 layers, ragged windows on a 3000-point grid."""
+    tables, batch, ch = make_config(3, n_wn=3000, n_lines=300, B=12)
+    nat, binned, st = _run(gpu_ctx, tables, batch, ch, mode, max_layers=200)
+    assert np.all(st == 0)
+    idx, ref = oracle_batch(tables, batch, ch, mode)
+    worst = 0.0
+    for b, r in zip(idx, ref):
+        lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+        e1 = native_rel_err(nat[b], r["depth"], lo, hi)
+        e2 = binned_rel_err(binned[b], r["binned"])
+        # outside the window nothing is written
+        assert np.all(np.isnan(nat[b][:lo])) and np.all(np.isnan(nat[b][hi:]))
+        worst = max(worst, e1, e2)
+    print(f"cfg3-small {mode}: worst rel err {worst:.3e}")
+    assert worst <= TOL[mode]
+
+
+def test_invalid_models_flagged(gpu_ctx):
+    """Invalid models get a status bit and NaN outputs; valid neighbours are
+    unaffected (Model Rejection subsection)."""
+    from paper_1912_07759_amd import trx
+    tables, batch, ch = make_config(3, n_wn=1000, n_lines=100, B=6)
+    batch.log10_vmr[1, :] = -0.1          # sum chi >= 1
+    batch.T[batch.layer_off[2]] = -5.0    # negative temperature
+    batch.wn_hi[3] = batch.wn_lo[3]       # empty window
+    batch.Rp[4] = 0.0
+    nat, binned, st = _run(gpu_ctx, tables, batch, ch, "fp64", max_layers=200)
+    assert st[0] == 0 and st[5] == 0
+    assert st[1] & trx.BAD_CHEMISTRY
+    assert st[2] & trx.BAD_PROFILE
+    assert st[3] & trx.BAD_WINDOW
+    assert st[4] & trx.BAD_PROFILE
+    for b in (1, 2, 4):
+        assert np.all(np.isnan(binned[b]))
+        lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+        assert np.all(np.isnan(nat[b][lo:hi]))
+    idx, ref = oracle_batch(tables, batch, ch, "fp64", models=[0, 5])
+    for b, r in zip(idx, ref):
+        assert binned_rel_err(binned[b], r["binned"]) <= TOL["fp64"]
