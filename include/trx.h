@@ -231,6 +231,27 @@ trx_status trx_plan_launch(trx_plan* p, int32_t B, double* depth_native,
                            const double* obs, const double* sigma, double* chi2,
                            double* dT, double* dlog10vmr, double* dRp);
 
+/* ---- measurement --------------------------------------------------------- */
+
+/* Kernel classes timed by trx_profile. */
+enum {
+  TRX_KERNEL_GEOMETRY = 0,  /* a1-a3: profiles, altitude, path lengths */
+  TRX_KERNEL_FORWARD = 1,   /* a4-a6: opacity, optical depth, depth */
+  TRX_KERNEL_BINNING = 2,   /* a7 */
+  TRX_KERNEL_ADJOINT = 3,   /* a8: opacity/optical-depth adjoint */
+  TRX_KERNEL_GEOM_ADJ = 4,  /* a8: geometry and altitude adjoint */
+  TRX_KERNEL_SCHEDULE = 5,  /* a9: work ordering of the batched launch */
+  TRX_KERNEL_CLASSES = 6
+};
+
+/* enable = 1: reset the totals and record a HIP event pair around every
+ * later kernel launch of this context that is not part of a graph;
+ * enable = 0: stop recording. */
+trx_status trx_profile(trx_ctx* ctx, int32_t enable);
+/* Wait for the recorded launches and return, for one kernel class, the
+ * summed GPU time between its event pairs (ms) and the number of launches. */
+trx_status trx_profile_read(trx_ctx* ctx, int32_t kernel, double* total_ms, int32_t* launches);
+
 /* ---- tuning ------------------------------------------------------------ */
 
 /* Time the kernel variants of `precision` on the plan's current inputs

@@ -19,8 +19,11 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtrx.so")
 ARCH = "gfx950"
 
+# -amdgpu-mfma-vgpr-form: matrix instructions read and write their
+# accumulators in VGPRs (no copies to and from AGPRs around each one).
 CFLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form=1",
           "-Wno-unused-command-line-argument"]
 
 

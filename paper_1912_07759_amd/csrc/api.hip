@@ -126,8 +126,10 @@ extern "C" trx_status trx_destroy(trx_ctx* c) {
   if (!c) return TRX_E_INVALID_ARG;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->ws, &c->aws, &c->grad})
+  for (DevBuf* b : {&c->ws, &c->aws, &c->grad, &c->sched})
     if (b->ptr) hipFree(b->ptr);
+  for (auto& r : c->pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+  for (hipEvent_t e : c->pool) hipEventDestroy(e);
   delete c;
   return TRX_OK;
 }
@@ -202,13 +204,13 @@ extern "C" trx_status trx_tables_create(trx_ctx* c, const trx_tables_desc* d, tr
   D.T = g;
   if ((s = upload(c, d->log10P_Pa, d->n_P, &g, &f32, t->owned)) != TRX_OK) return fail(s);
   D.logP = g;
-  int64_t nx = (int64_t)d->n_abs * d->n_T * d->n_P * d->n_wn;
+  const int64_t nx = (int64_t)d->n_abs * d->n_T * d->n_P * d->n_wn;
   if ((s = upload(c, d->xsec_cm2, nx, &g, &f32, t->owned)) != TRX_OK) return fail(s);
   D.xsec64 = g; D.xsec32 = f32;
   if (d->n_cia > 0) {
     if ((s = upload(c, d->Tcia_K, d->n_Tcia, &g, &f32, t->owned)) != TRX_OK) return fail(s);
     D.Tcia = g;
-    int64_t nc = (int64_t)d->n_cia * d->n_Tcia * d->n_wn;
+    const int64_t nc = (int64_t)d->n_cia * d->n_Tcia * d->n_wn;
     if ((s = upload(c, d->cia_cm5, nc, &g, &f32, t->owned, kCiaScale32)) != TRX_OK) return fail(s);
     D.cia64 = g; D.cia32 = f32;
     for (int p = 0; p < d->n_cia; ++p) {
@@ -348,7 +350,8 @@ DevBatch trx::dev_batch(const trx_batch* bt) {
 trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B,
                                 const int32_t* B_dev, int max_layers, const trx_bins* bins,
                                 int precision, const RunConfig& rc, uint8_t* ws, void* aws,
-                                double* depth_native, double* depth_binned, int32_t* status) {
+                                const SchedBufs& sb, double* depth_native, double* depth_binned,
+                                int32_t* status) {
   const Layout L = make_layout(max_layers, precision);
   GeomArgs g;
   g.bt = db;
@@ -361,8 +364,18 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   g.n_limit = max_layers;
   g.span_cols = rc.span_cols;
   g.depth_native = depth_native;
-  launch_geom(g, B, c->stream);
+  g.mlay = sb.mlay;
+  g.mspan = sb.mspan;
+  {
+    ProfScope ps(c, TRX_KERNEL_GEOMETRY);
+    launch_geom(g, B, c->stream);
+  }
   launch_copy_status(ws, L.slab, B_dev, B, status, c->stream);
+  const bool persistent = rc.persistent && precision != TRX_FP64;
+  if (persistent) {
+    ProfScope ps(c, TRX_KERNEL_SCHEDULE);
+    launch_schedule(sb.mlay, B_dev, B, sb.order, sb.qcount, c->stream);
+  }
 
   FwdArgs f;
   memset(&f, 0, sizeof f);
@@ -376,10 +389,17 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   f.depth_native = depth_native;
   f.aws = aws;
   f.model_status = status;
-  if (precision == TRX_FP64) {
-    launch_fwd64(f, B, c->stream);
-  } else {
-    launch_fwd_mfma(f, precision, rc.nrb_max, B, 0, c->stream);
+  f.order = sb.order;
+  f.mspan = sb.mspan;
+  f.qcount = sb.qcount;
+  f.persistent = persistent ? 1 : 0;
+  {
+    ProfScope ps(c, TRX_KERNEL_FORWARD);
+    if (precision == TRX_FP64) {
+      launch_fwd64(f, B, c->stream);
+    } else {
+      launch_fwd_mfma(f, precision, rc.nrb_max, B, c->n_cu, c->stream);
+    }
   }
   if (depth_binned) {
     BinArgs ba;
@@ -387,6 +407,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
     ba.n_wn = t->dev.n_wn; ba.n_ch = bins->n_ch;
     ba.ch_i0 = bins->i0; ba.ch_i1 = bins->i1; ba.ch_off = bins->off; ba.ch_w = bins->w;
     ba.aws = aws; ba.aws_f64 = precision == TRX_FP64; ba.out = depth_binned;
+    ProfScope ps(c, TRX_KERNEL_BINNING);
     launch_bin(ba, B, c->stream);
   }
   hipError_t e = hipGetLastError();
@@ -396,9 +417,8 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
 
 RunConfig trx::default_config(int precision, int max_layers) {
   RunConfig rc;
-  rc.span_cols = 256;
   rc.nrb_max = (max_layers + 31) / 32;
-  (void)precision;
+  rc.persistent = precision != TRX_FP64;
   return rc;
 }
 
@@ -417,7 +437,69 @@ extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_bat
   if ((s = ensure_buffer(c, c->ws, (size_t)bt->B * L.slab, "workspace")) != TRX_OK) return s;
   const size_t esz = precision == TRX_FP64 ? 8 : 4;
   if ((s = ensure_buffer(c, c->aws, (size_t)bt->B * t->dev.n_wn * esz, "workspace")) != TRX_OK) return s;
+  if ((s = ensure_buffer(c, c->sched, SchedBufs::bytes(bt->B), "workspace")) != TRX_OK) return s;
   RunConfig rc = default_config(precision, bt->max_layers);
   return enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision, rc,
-                         (uint8_t*)c->ws.ptr, c->aws.ptr, depth_native, depth_binned, model_status);
+                         (uint8_t*)c->ws.ptr, c->aws.ptr, SchedBufs::carve(c->sched.ptr, bt->B),
+                         depth_native, depth_binned, model_status);
+}
+
+// --------------------------------------------------------------------------
+// measurement
+// --------------------------------------------------------------------------
+static hipEvent_t take_event(trx_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+trx::ProfScope::ProfScope(trx_ctx* ctx, int k) : c(ctx), kind(k) {
+  if (!c->profile || c->capturing) return;
+  a = take_event(c);
+  b = take_event(c);
+  hipEventRecord(a, c->stream);
+}
+
+trx::ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEventRecord(b, c->stream);
+  c->pending.push_back({kind, a, b});
+}
+
+static void drain(trx_ctx* c) {
+  for (auto& r : c->pending) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->total_ms[r.kind] += ms;
+      c->launches[r.kind] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
+extern "C" trx_status trx_profile(trx_ctx* c, int32_t enable) {
+  if (!c) return TRX_E_INVALID_ARG;
+  drain(c);
+  c->profile = enable != 0;
+  if (enable)
+    for (int k = 0; k < TRX_KERNEL_CLASSES; ++k) { c->total_ms[k] = 0; c->launches[k] = 0; }
+  return TRX_OK;
+}
+
+extern "C" trx_status trx_profile_read(trx_ctx* c, int32_t kernel, double* total_ms, int32_t* launches) {
+  if (!c) return TRX_E_INVALID_ARG;
+  if (kernel < 0 || kernel >= TRX_KERNEL_CLASSES || !total_ms || !launches)
+    return set_err(c, TRX_E_INVALID_ARG, "trx_profile_read: bad kernel class or null output");
+  drain(c);
+  *total_ms = c->total_ms[kernel];
+  *launches = c->launches[kernel];
+  return TRX_OK;
 }

@@ -23,15 +23,17 @@ namespace trx {
 
 namespace {
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 1;
 constexpr int kSpan = 64 * kWaves;
 
+// Mixing-ratio-weighted table values of one column in FP64:
+// M(c) = sum_i chi_i sigma_i[c] and C(t) = sum_p (chi chi')_p sigma_p[t].
 struct Mixer64 {
   const double* xs;   // xsec64 + col
   const double* ci;   // cia64 + col
   int64_t abs_stride; // n_T * n_P * n_wn
   int64_t cia_stride; // n_Tcia * n_wn
-  int W, nP, nabs, ncia;
+  int W, nabs, ncia;
   const double* chi;  // header chi_s
   const double* ciaw; // header cia_w
 
@@ -49,43 +51,39 @@ struct Mixer64 {
   }
 };
 
-// Corner values of the current layer's bracket, reused when consecutive
-// layers share corners (the bracket index is uniform across the wave).
-struct Corners64 {
-  int base = -1 << 30, cbase = -1 << 30;
-  double c00 = 0, c10 = 0, c01 = 0, c11 = 0, C0 = 0, C1 = 0;
+constexpr int kRowsAbs = 80;
+constexpr int kRowsCia = 32;
+static_assert(kRowsAbs >= kMaxU && kRowsCia >= kMaxV, "block staging must fit");
 
-  __device__ void update(const Mixer64& m, int nb, int ncb) {
-    const int nP = m.nP;
-    if (nb != base) {
-      if (nb == base - 1) {            // one pressure node down (moving up)
-        c01 = c00; c11 = c10;
-        c00 = m.corner(nb); c10 = m.corner(nb + nP);
-      } else if (nb == base + 1) {
-        c00 = c01; c10 = c11;
-        c01 = m.corner(nb + 1); c11 = m.corner(nb + nP + 1);
-      } else if (nb == base + nP) {    // one temperature node up
-        c00 = c10; c01 = c11;
-        c10 = m.corner(nb + nP); c11 = m.corner(nb + nP + 1);
-      } else if (nb == base - nP) {
-        c10 = c00; c11 = c01;
-        c00 = m.corner(nb); c01 = m.corner(nb + 1);
-      } else {
-        c00 = m.corner(nb); c10 = m.corner(nb + nP);
-        c01 = m.corner(nb + 1); c11 = m.corner(nb + nP + 1);
+__device__ inline void stage64(const Mixer64& m, const int32_t* ids, int nU, const int32_t* tids,
+                               int nV, double* rows, double* crows, int lane) {
+  for (int u0 = 0; u0 < nU; u0 += 16) {
+    double s[16];
+#pragma unroll
+    for (int g = 0; g < 16; ++g) s[g] = 0.0;
+    for (int i = 0; i < m.nabs; ++i) {
+      const double x = m.chi[i];
+      double v[16];
+#pragma unroll
+      for (int g = 0; g < 16; ++g) {
+        const int u = u0 + g < nU ? u0 + g : nU - 1;
+        v[g] = m.xs[(int64_t)ids[u] * m.W + i * m.abs_stride];
       }
-      base = nb;
+#pragma unroll
+      for (int g = 0; g < 16; ++g) s[g] = fma(x, v[g], s[g]);
     }
-    if (m.ncia > 0 && ncb != cbase) {
-      if (ncb == cbase + 1) { C0 = C1; C1 = m.cia(ncb + 1); }
-      else if (ncb == cbase - 1) { C1 = C0; C0 = m.cia(ncb); }
-      else { C0 = m.cia(ncb); C1 = m.cia(ncb + 1); }
-      cbase = ncb;
-    }
+#pragma unroll
+    for (int g = 0; g < 16; ++g)
+      if (u0 + g < nU) rows[(u0 + g) * 64 + lane] = s[g];
   }
-};
+  for (int v = 0; v < nV; ++v) crows[v * 64 + lane] = m.cia(tids[v]);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ __launch_bounds__(64 * kWaves) void k_fwd64(FwdArgs a) {
+  __shared__ double s_rows[kWaves][kRowsAbs + kRowsCia][64];
   const int b = blockIdx.x;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if (b >= B) return;
@@ -109,9 +107,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd64(FwdArgs a) {
   m.ci = tb.cia64 + cc;
   m.abs_stride = (int64_t)tb.n_T * tb.n_P * W;
   m.cia_stride = (int64_t)tb.n_Tcia * W;
-  m.W = W; m.nP = tb.n_P; m.nabs = tb.n_abs; m.ncia = tb.n_cia;
+  m.W = W; m.nabs = tb.n_abs; m.ncia = tb.n_cia;
   m.chi = h->chi_s;
   m.ciaw = h->cia_w;
+  const bool has_cia = tb.n_cia > 0;
 
   double R = 0.0;
   if (tb.has_rayleigh)
@@ -119,30 +118,59 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd64(FwdArgs a) {
 
   const double* lw = reinterpret_cast<const double*>(slab + L.off_lw64);
   const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
+  const KBlk* kblk = reinterpret_cast<const KBlk*>(slab + L.off_kblk);
+  const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const double* A = reinterpret_cast<const double*>(slab + L.off_A64);
   const double* dlT = reinterpret_cast<const double*>(slab + L.off_dl);
   const int NP = L.NP;
+  double* rows = &s_rows[wave][0][0];
+  double* crows = rows + kRowsAbs * 64;
+
+  // whole-model staging when the distinct corners fit, else per layer block
+  const bool mstage = ml->nU <= kRowsAbs && ml->nV <= kRowsCia;
+  const int slot_off = mstage ? 2 : 4;
+  if (mstage) stage64(m, ml->ids, ml->nU, ml->tids, has_cia ? ml->nV : 0, rows, crows, lane);
 
   double atm = 0.0;
-  const int nrb = (N + 31) / 32;
+  const int nrb = (N + 31) / 32, nkb = (N + 15) / 16;
   for (int rb = 0; rb < nrb; ++rb) {
     double tau[32];
 #pragma unroll
     for (int j = 0; j < 32; ++j) tau[j] = 0.0;
-    Corners64 cs;
-    for (int k = 32 * rb; k < N; ++k) {
-      cs.update(m, lid[2 * k], lid[2 * k + 1]);
-      const double* w = lw + 8 * k;
-      double kap = w[0] * cs.c00;
-      kap = fma(w[1], cs.c10, kap);
-      kap = fma(w[2], cs.c01, kap);
-      kap = fma(w[3], cs.c11, kap);
-      kap = fma(w[4], R, kap);
-      kap = fma(w[5], cs.C0, kap);
-      kap = fma(w[6], cs.C1, kap);
-      const double* d = dlT + (int64_t)k * NP + 32 * rb;
+    for (int kb = 2 * rb; kb < nkb; ++kb) {
+      if (!mstage) {
+        const KBlk* kd = kblk + kb;
+        __builtin_amdgcn_wave_barrier();
+        stage64(m, kd->ids, kd->nU, kd->tids, has_cia ? kd->nV : 0, rows, crows, lane);
+      }
+      double kap[16];
 #pragma unroll
-      for (int j = 0; j < 32; ++j) tau[j] = fma(d[j], kap, tau[j]);
+      for (int j = 0; j < 16; ++j) {
+        const int l = 16 * kb + j;
+        double k = 0.0;
+        if (l < N) {
+          const uint32_t sl = (uint32_t)lid[8 * l + slot_off];
+          const double* w = lw + 8 * l;
+          k = w[0] * rows[(sl & 0xff) * 64 + lane];
+          k = fma(w[1], rows[((sl >> 8) & 0xff) * 64 + lane], k);
+          k = fma(w[2], rows[((sl >> 16) & 0xff) * 64 + lane], k);
+          k = fma(w[3], rows[(sl >> 24) * 64 + lane], k);
+          k = fma(w[4], R, k);
+          if (has_cia) {
+            const uint32_t cl = (uint32_t)lid[8 * l + slot_off + 1];
+            k = fma(w[5], crows[(cl & 0xff) * 64 + lane], k);
+            k = fma(w[6], crows[((cl >> 8) & 0xff) * 64 + lane], k);
+          }
+        }
+        kap[j] = k;
+      }
+      // tau_j += dl[j, l] kappa_l for the 32 rays of this block (dl = 0 for l < j)
+#pragma unroll
+      for (int jl = 0; jl < 16; ++jl) {
+        const double* d = dlT + (int64_t)(16 * kb + jl) * NP + 32 * rb;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) tau[j] = fma(d[j], kap[jl], tau[j]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 32; ++j) atm = fma(A[32 * rb + j], -expm1(-tau[j]), atm);
@@ -158,8 +186,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd64(FwdArgs a) {
 }  // namespace
 
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s) {
-  if (B_grid <= 0 || a.n_spans <= 0) return;
-  hipLaunchKernelGGL(k_fwd64, dim3(B_grid, a.n_spans), dim3(64 * kWaves), 0, s, a);
+  if (B_grid <= 0) return;
+  const int spans = (a.tab.n_wn + kSpan - 1) / kSpan;
+  hipLaunchKernelGGL(k_fwd64, dim3(B_grid, spans), dim3(64 * kWaves), 0, s, a);
 }
 
 }  // namespace trx

@@ -1,31 +1,41 @@
 // Matrix-core forward kernel for the FP32 and split-bf16 modes: opacity
-// (a4), optical depth (a5) and depth (a6) of one (model, 256-column span)
-// per workgroup, one 64-column slice per wave.
+// (a4), optical depth (a5) and depth (a6) of one (model, 64-column span) per
+// workgroup of four waves.
 //
-// Opacity.  Each lane owns one wavenumber column and computes the absorption
-// coefficient of the 16 layers of a layer block in FP32 from the
-// mixing-ratio-weighted corner values of the layer's (T, log10 P) bracket
-// (equations opt_dpth, cia_opt_dpth, contrib; Opacities section), exactly as
-// in the FP64 kernel but in FP32 from the FP32 tables.
+// Staging.  At the start of a work item the workgroup stages in LDS, for its
+// 64 columns, the mixed value M_q = sum_i chi_i sigma_i[q] of every distinct
+// table corner q of the model (the tables share one (T, log10 P) grid, so the
+// bilinear weights are common to all absorbers and the absorber sum is taken
+// once per corner) and the CIA sums C_t = sum_pairs chi_a chi_b sigma_pair[t]
+// at its temperature nodes.  Waves split the corners (corner ids are uniform
+// scalar loads) and keep 16 table loads per lane in flight.  A model with
+// more distinct corners than the staging capacity stages those of each
+// 16-layer block instead.
 //
-// Optical depth.  tau[ray, col] = sum_k dl[ray, k] kappa[k, col] is the
-// matrix product dl (rays x layers, upper triangular) x kappa (layers x
-// columns), done on the matrix cores with 32x32 output tiles: a wave holds
-// the accumulators of every 32-ray block for its two 32-column blocks and
-// walks the layer blocks once; a ray block only takes layer blocks at or
-// above its first ray (the triangle).  The opacity block computed by a lane
-// (one column, 16 layers) is turned into the B operand layout with one
-// v_permlane32_swap per register pair (lanes l and l+32 exchange halves).
-//   FP32 mode: v_mfma_f32_32x32x2_f32 with kappa in FP32 and the path
-//     lengths in two FP32 pieces (hi + lo), two products.
+// Per 16-layer block the workgroup then
+//  1. computes the absorption coefficient of the block's layers, wave w taking
+//     layers 4w..4w+3 with one column per lane:
+//       kappa_l = sum_q w_lq M_q + w_R R + w_c0 C_0 + w_c1 C_1
+//     (equations opt_dpth, cia_opt_dpth, contrib; Opacities section), the
+//     weights (bilinear factors x 1e-4 rho, CIA factors x 1e-10 rho^2) and
+//     corner slots being per-layer records of the geometry kernel read with
+//     scalar loads, and writes kappa to LDS already in the B-operand layout
+//     of the matrix instruction (split into bf16 pieces in the bf16 modes);
+//  2. accumulates tau[ray, col] += dl[ray, layers of the block] x kappa on the
+//     matrix cores: wave w owns the ray blocks w, w+4 (both 32-column blocks,
+//     so each path-length fragment is read once), and a ray block only takes
+//     the layer blocks at or above its first ray (the triangle).
+//   FP32 mode: v_mfma_f32_32x32x2_f32, kappa in FP32, path lengths as two
+//     FP32 pieces (hi + lo).
 //   bf16 modes: v_mfma_f32_32x32x16_bf16 with both operands split into bf16
-//     pieces, x = x0 + x1 (+ x2); the products x0*y0 + x0*y1 + x1*y0 (two
-//     pieces) or all products with piece-index sum <= 2 (three pieces) are
-//     accumulated in FP32, recovering ~16 or ~24 bits of the operands.
+//     pieces x = x0 + x1 (+ x2); the products with piece-index sum < 2 (two
+//     pieces: x0 y0 + x0 y1 + x1 y0) or < 3 (three pieces, six products) are
+//     accumulated in FP32.
 //
-// Depth.  Each accumulator element is a (ray, column) optical depth; the
-// lane adds (A_j/Rs^2)(1 - exp(-tau)) over its 16 rows per ray block and the
-// two lanes sharing a column combine with one cross-lane exchange.
+// Depth.  Each accumulator element is a (ray, column) optical depth; a wave
+// adds (A_j/Rs^2)(1 - exp(-tau)) over the 32 rays of a block per column (two
+// lanes per column, one cross-lane exchange) into a per-ray-block partial in
+// LDS, and the partials are summed in ray-block order (same bits every run).
 #include "trx_internal.h"
 
 namespace trx {
@@ -33,166 +43,222 @@ namespace trx {
 namespace {
 
 constexpr int kWaves = 4;
-constexpr int kSpan = 64 * kWaves;
+constexpr int kCols = 64;               // columns per workgroup
+constexpr int kRowsAbs = 112;           // staged cross-section corners
+constexpr int kRowsCia = 32;            // staged CIA nodes
+static_assert(kRowsAbs >= kMaxU && kRowsCia >= kMaxV, "block staging must fit");
+constexpr int kInFlight = 16;           // table loads per lane issued together
+constexpr int kChunk = 8;               // items popped per atomic (persistent launch)
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-struct Mixer32 {
-  const float* xs;
-  const float* ci;
-  int64_t abs_stride, cia_stride;
-  int W, nP, nabs, ncia;
-  const float* chi;
-  const float* ciaw;
-
-  __device__ float corner(int c) const {
-    float s = 0.f;
-    const float* p = xs + (int64_t)c * W;
-    for (int i = 0; i < nabs; ++i) s = fmaf(chi[i], p[i * abs_stride], s);
-    return s;
-  }
-  __device__ float cia(int t) const {
-    float s = 0.f;
-    const float* p = ci + (int64_t)t * W;
-    for (int q = 0; q < ncia; ++q) s = fmaf(ciaw[q], p[q * cia_stride], s);
-    return s;
-  }
+template <int MODE>
+struct Cfg {
+  // bf16 pieces of each operand (FP32 mode: 1 kappa piece, 2 path pieces)
+  static constexpr int npc = MODE == TRX_BF16_SPLIT3 ? 3 : (MODE == TRX_BF16_SPLIT2 ? 2 : 1);
+  // dwords of the B-operand buffer: [piece][column block][lane][4] (bf16) or
+  // [column block][step 0..7][lane] (FP32)
+  static constexpr int frag_dw = MODE == TRX_FP32 ? 2 * 8 * 64 : npc * 2 * 64 * 4;
 };
 
-struct Corners32 {
-  int base = -1 << 30, cbase = -1 << 30;
-  float c00 = 0, c10 = 0, c01 = 0, c11 = 0, C0 = 0, C1 = 0;
+template <int MODE, int RBW>
+struct Smem {
+  float rows[kRowsAbs + kRowsCia][kCols];
+  __attribute__((aligned(16))) uint32_t frag[Cfg<MODE>::frag_dw];
+  float part[kWaves * RBW][kCols];
+  // per-item copies of the model's records (read with uniform LDS addresses)
+  __attribute__((aligned(16))) float lw[TRX_MAX_LAYERS_MFMA][8];   // layer weights
+  int2 sl[TRX_MAX_LAYERS_MFMA];                                     // corner slots
+  int32_t ids[kRowsAbs];                                            // staged corner ids
+  int32_t tids[kRowsCia];                                           // staged CIA nodes
+  float chi[TRX_MAX_ABSORBERS];
+  float ciaw[TRX_MAX_CIA];
+  int32_t items[kChunk];
+  int32_t base;
+};
 
-  __device__ void update(const Mixer32& m, int nb, int ncb) {
-    const int nP = m.nP;
-    if (nb != base) {
-      if (nb == base - 1) {
-        c01 = c00; c11 = c10;
-        c00 = m.corner(nb); c10 = m.corner(nb + nP);
-      } else if (nb == base + 1) {
-        c00 = c01; c10 = c11;
-        c01 = m.corner(nb + 1); c11 = m.corner(nb + nP + 1);
-      } else if (nb == base + nP) {
-        c00 = c10; c01 = c11;
-        c10 = m.corner(nb + nP); c11 = m.corner(nb + nP + 1);
-      } else if (nb == base - nP) {
-        c10 = c00; c11 = c01;
-        c00 = m.corner(nb); c01 = m.corner(nb + 1);
-      } else {
-        c00 = m.corner(nb); c10 = m.corner(nb + nP);
-        c01 = m.corner(nb + 1); c11 = m.corner(nb + nP + 1);
+// rows[u][lane] = sum_i chi[i] * tab[i][ids[u]][col] for the corners
+// u = wave, wave + 4, ... < nU (tab_col = table + col; absorber stride
+// abs_stride, corner stride W).  The (corner, absorber) pairs are walked with
+// uniform counters, kInFlight loads at a time; partial sums are added to the
+// row when the corner changes.
+__device__ inline void stage_rows(const float* tab_col, int64_t abs_stride, int W, const int32_t* ids, int nU,
+                                  const float* chi, int nabs, float* rows, int wave, int lane) {
+  for (int u = wave; u < nU; u += kWaves) rows[u * kCols + lane] = 0.f;
+  if (nabs == 0) return;
+  int u = wave, i = 0;
+  while (u < nU) {
+    float v[kInFlight], cw[kInFlight];
+    int uu[kInFlight];
+#pragma unroll
+    for (int k = 0; k < kInFlight; ++k) {
+      const bool ok = u < nU;
+      uu[k] = ok ? u : -1;
+      cw[k] = ok ? chi[i] : 0.f;
+      v[k] = tab_col[(int64_t)i * abs_stride + (int64_t)ids[ok ? u : wave] * W];
+      if (++i == nabs) { i = 0; u += kWaves; }
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kInFlight; ++k) {
+      acc = fmaf(cw[k], v[k], acc);
+      if (k == kInFlight - 1 || uu[k + 1 < kInFlight ? k + 1 : k] != uu[k]) {
+        if (uu[k] >= 0) rows[uu[k] * kCols + lane] += acc;
+        acc = 0.f;
       }
-      base = nb;
-    }
-    if (m.ncia > 0 && ncb != cbase) {
-      if (ncb == cbase + 1) { C0 = C1; C1 = m.cia(ncb + 1); }
-      else if (ncb == cbase - 1) { C1 = C0; C0 = m.cia(ncb); }
-      else { C0 = m.cia(ncb); C1 = m.cia(ncb + 1); }
-      cbase = ncb;
     }
   }
-};
-
-__device__ inline uint32_t swap_lo(uint32_t x, uint32_t y, uint32_t& hi_out) {
-  // v_permlane32_swap: the upper 32 lanes of x trade places with the lower
-  // 32 lanes of y.  Returns the new x; the new y goes to hi_out.
-  auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
-  hi_out = r[1];
-  return r[0];
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// (a, b) rounded to bf16 (nearest even) and packed, a in the low half
 __device__ inline uint32_t bf16_pair(float a, float b) {
-  __bf16 ha = (__bf16)a, hb = (__bf16)b;
-  return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
 }
 __device__ inline float bf16_lo_f(uint32_t p) { return __uint_as_float(p << 16); }
 __device__ inline float bf16_hi_f(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
 
-template <int MODE>
-struct Pieces {
-  static constexpr int n = MODE == TRX_BF16_SPLIT3 ? 3 : 2;
-};
-
-template <int MODE, int NRB>
-__global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
-  const int b = blockIdx.x;
-  const int B = a.B_dev ? *a.B_dev : a.B;
-  if (b >= B) return;
+// One work item: model b, columns [64 span, 64 span + 64).  Called by all
+// threads of the workgroup (every early return is uniform).
+// RBW: ray blocks per wave (ray blocks / 4, rounded up).
+template <int MODE, int RBW>
+__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in, Smem<MODE, RBW>& sm) {
+  using C = Cfg<MODE>;
+  // the item is the same for the whole workgroup: keep it, and every address
+  // derived from it, in scalar registers (scalar loads of the layer records)
+  const int b = __builtin_amdgcn_readfirstlane(b_in);
+  const int span = __builtin_amdgcn_readfirstlane(span_in);
   const Layout& L = a.L;
   const uint8_t* slab = a.ws + (int64_t)b * L.slab;
-  const ModelHdr* h = reinterpret_cast<const ModelHdr*>(slab);
-  const int N = h->n;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
+  const int N = hd->n;
   if (N == 0) return;
-  const int lo = h->lo, hi = h->hi;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col0 = blockIdx.y * kSpan + wave * 64;
-  if (col0 >= hi || col0 + 64 <= lo) return;
+  const int lo = hd->lo, hi = hd->hi;
+  const int col0 = span * kCols;
+  if (col0 >= hi || col0 + kCols <= lo) return;
+  // the wave index is uniform across the wave: keep it (and what derives
+  // from it) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int col = col0 + lane;
   const bool valid = col >= lo && col < hi;
   const int cc = valid ? col : lo;
   const DevTables& tb = a.tab;
   const int W = tb.n_wn;
-
-  Mixer32 m;
-  m.xs = tb.xsec32 + cc;
-  m.ci = tb.cia32 + cc;
-  m.abs_stride = (int64_t)tb.n_T * tb.n_P * W;
-  m.cia_stride = (int64_t)tb.n_Tcia * W;
-  m.W = W; m.nP = tb.n_P; m.nabs = tb.n_abs; m.ncia = tb.n_cia;
-  m.chi = h->chi_s32;
-  m.ciaw = h->cia_w32;
+  const bool has_cia = tb.n_cia > 0;
 
   float R = 0.f;
   if (tb.has_rayleigh)
-    for (int s = 0; s < tb.n_abs + 2; ++s) R = fmaf(h->chi_s32[s], tb.ray32[(int64_t)s * W + cc], R);
+    for (int s = 0; s < tb.n_abs + 2; ++s) R = fmaf(hd->chi_s32[s], tb.ray32[(int64_t)s * W + cc], R);
 
   const float* lw = reinterpret_cast<const float*>(slab + L.off_lw32);
   const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
+  const KBlk* kblk = reinterpret_cast<const KBlk*>(slab + L.off_kblk);
+  const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const float* Aw = reinterpret_cast<const float*>(slab + L.off_A32);
   const uint8_t* frag = slab + L.off_dl;
-  const int nkb = h->nkb, nrb = h->nrb;
+  const int nkb = hd->nkb, nrb = hd->nrb;
   const int NKB = L.NKB;
 
-  f32x16 acc[NRB][2];
+  const float* xs = tb.xsec32 + cc;
+  const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
+  const float* ci = tb.cia32 + cc;
+  const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
+  float* rows = &sm.rows[0][0];
+  float* crows = &sm.rows[kRowsAbs][0];
+  const int tid = threadIdx.x;
+  // copy the corner ids of the model (or of layer block kb) into LDS, then
+  // stage the mixed rows
+  auto stage = [&](const int32_t* ids, int nU, const int32_t* tids, int nV) {
+    for (int e = tid; e < nU; e += 64 * kWaves) sm.ids[e] = ids[e];
+    for (int e = tid; e < nV; e += 64 * kWaves) sm.tids[e] = tids[e];
+    __syncthreads();
+    stage_rows(xs, abs_stride, W, sm.ids, nU, sm.chi, tb.n_abs, rows, wave, lane);
+    if (has_cia) stage_rows(ci, cia_stride, W, sm.tids, nV, sm.ciaw, tb.n_cia, crows, wave, lane);
+  };
+  // whole-model staging when the distinct corners fit, else per layer block
+  const bool mstage = ml->nU <= kRowsAbs && ml->nV <= kRowsCia;
+  const int slot_off = mstage ? 2 : 4;
+  for (int e = tid; e < N * 8; e += 64 * kWaves) (&sm.lw[0][0])[e] = lw[e];
+  for (int e = tid; e < N; e += 64 * kWaves) sm.sl[e] = *reinterpret_cast<const int2*>(lid + 8 * e + slot_off);
+  if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
+  if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w32[tid];
+  __syncthreads();
+  if (mstage) stage(ml->ids, ml->nU, ml->tids, ml->nV);
+
+  f32x16 acc[RBW][2];
 #pragma unroll
-  for (int r = 0; r < NRB; ++r) {
+  for (int r = 0; r < RBW; ++r) {
     acc[r][0] = f32x16{};
     acc[r][1] = f32x16{};
   }
-  Corners32 cs;
-  const int hl = lane >> 5;
 
   for (int kb = 0; kb < nkb; ++kb) {
-    float kap[16];
+    if (!mstage) {
+      const KBlk* kd = kblk + kb;
+      stage(kd->ids, kd->nU, kd->tids, kd->nV);
+    }
+    __syncthreads();
+
+    // 1. opacity of layers 16 kb + 4 wave + jj, one column per lane
+    float kap[4];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int l = 16 * kb + j;
+    for (int jj = 0; jj < 4; ++jj) {
+      const int l = 16 * kb + 4 * wave + jj;
+      float k = 0.f;
       if (l < N) {
-        cs.update(m, lid[2 * l], lid[2 * l + 1]);
-        const float* w = lw + 8 * l;
-        float k = w[0] * cs.c00;
-        k = fmaf(w[1], cs.c10, k);
-        k = fmaf(w[2], cs.c01, k);
-        k = fmaf(w[3], cs.c11, k);
+        const float* w = sm.lw[l];
+        const int2 sl2 = sm.sl[l];
+        const uint32_t sl = (uint32_t)sl2.x;
+        k = w[0] * rows[(sl & 0xff) * kCols + lane];
+        k = fmaf(w[1], rows[((sl >> 8) & 0xff) * kCols + lane], k);
+        k = fmaf(w[2], rows[((sl >> 16) & 0xff) * kCols + lane], k);
+        k = fmaf(w[3], rows[(sl >> 24) * kCols + lane], k);
         k = fmaf(w[4], R, k);
-        k = fmaf(w[5], cs.C0, k);
-        k = fmaf(w[6], cs.C1, k);
-        kap[j] = k;
-      } else {
-        kap[j] = 0.f;
+        if (has_cia) {
+          const uint32_t cl = (uint32_t)sl2.y;
+          k = fmaf(w[5], crows[(cl & 0xff) * kCols + lane], k);
+          k = fmaf(w[6], crows[((cl >> 8) & 0xff) * kCols + lane], k);
+        }
+      }
+      kap[jj] = k;
+    }
+    const int cb = lane >> 5, lc = lane & 31;
+    if constexpr (MODE == TRX_FP32) {
+      // 32x32x2 step i holds layers 2i, 2i+1: lane 32 (k%2) + col%32
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int k = 4 * wave + jj;
+        sm.frag[(cb * 8 + (k >> 1)) * 64 + 32 * (k & 1) + lc] = __float_as_uint(kap[jj]);
+      }
+    } else {
+      // 32x32x16: lane 32 (k/8) + col%32 holds layers 8 (k/8) .. +7 packed
+      // by pairs; this wave's layers are k = 4 wave .. 4 wave + 3
+      const int fl = 32 * (wave >> 1) + lc;
+      const int d0 = 2 * (wave & 1);
+      float x0 = kap[0], x1 = kap[1], x2 = kap[2], x3 = kap[3];
+#pragma unroll
+      for (int p = 0; p < C::npc; ++p) {
+        const uint32_t q0 = bf16_pair(x0, x1), q1 = bf16_pair(x2, x3);
+        uint32_t* dst = sm.frag + ((p * 2 + cb) * 64 + fl) * 4 + d0;
+        *reinterpret_cast<uint2*>(dst) = make_uint2(q0, q1);
+        x0 -= bf16_lo_f(q0);
+        x1 -= bf16_hi_f(q0);
+        x2 -= bf16_lo_f(q1);
+        x3 -= bf16_hi_f(q1);
       }
     }
-    if constexpr (MODE == TRX_FP32) {
-      // B operand of 32x32x2, step i: lane l holds kappa[2i + l/32][col l%32].
-      uint32_t b0[8], b1[8];
+    __syncthreads();
+
+    // 2. matrix products for this wave's ray blocks rb = wave + 4 r
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        b0[i] = swap_lo(__float_as_uint(kap[2 * i]), __float_as_uint(kap[2 * i + 1]), b1[i]);
-#pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) {
-        if (rb < nrb && kb >= 2 * rb) {
+    for (int r = 0; r < RBW; ++r) {
+      const int rb = wave + kWaves * r;
+      if (rb < nrb && kb >= 2 * rb) {
+        if constexpr (MODE == TRX_FP32) {
           const float* fp = reinterpret_cast<const float*>(frag) +
                             (int64_t)frag_index(rb, kb, NKB) * 2 * 512 + lane * 8;
           const float4 h0 = *reinterpret_cast<const float4*>(fp);
@@ -202,110 +268,165 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
           const float ah[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
           const float al[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const float x0 = __uint_as_float(b0[i]), x1 = __uint_as_float(b1[i]);
-            acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[i], x0, acc[rb][0], 0, 0, 0);
-            acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(al[i], x0, acc[rb][0], 0, 0, 0);
-            acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[i], x1, acc[rb][1], 0, 0, 0);
-            acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(al[i], x1, acc[rb][1], 0, 0, 0);
+          for (int tcb = 0; tcb < 2; ++tcb) {
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+              const float bk = __uint_as_float(sm.frag[(tcb * 8 + st) * 64 + lane]);
+              acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[st], bk, acc[r][tcb], 0, 0, 0);
+              acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x2f32(al[st], bk, acc[r][tcb], 0, 0, 0);
+            }
           }
-        }
-      }
-    } else {
-      constexpr int NPC = Pieces<MODE>::n;
-      // split kappa into bf16 pieces, packed by layer pairs (2d, 2d+1)
-      uint32_t pk[NPC][8];
+        } else {
+          const u32x4* fp = reinterpret_cast<const u32x4*>(
+              frag + ((int64_t)frag_index(rb, kb, NKB) * C::npc * 512 + lane * 8) * 2);
+          u32x4 Ap[C::npc];
 #pragma unroll
-      for (int d = 0; d < 8; ++d) {
-        float x0 = kap[2 * d], x1 = kap[2 * d + 1];
+          for (int p = 0; p < C::npc; ++p) Ap[p] = fp[p * 64];
 #pragma unroll
-        for (int p = 0; p < NPC; ++p) {
-          const uint32_t q = bf16_pair(x0, x1);
-          pk[p][d] = q;
-          x0 -= bf16_lo_f(q);
-          x1 -= bf16_hi_f(q);
-        }
-      }
-      // B operand of 32x32x16: lane l holds kappa[8 (l/32) + v][col l%32];
-      // column block 0 = columns 0..31 of the wave, block 1 = 32..63.
-      u32x4 B0[NPC], B1[NPC];
+          for (int tcb = 0; tcb < 2; ++tcb) {
+            u32x4 Bp[C::npc];
 #pragma unroll
-      for (int p = 0; p < NPC; ++p) {
+            for (int p = 0; p < C::npc; ++p)
+              Bp[p] = *reinterpret_cast<const u32x4*>(sm.frag + ((p * 2 + tcb) * 64 + lane) * 4);
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          uint32_t y;
-          B0[p][d] = swap_lo(pk[p][d], pk[p][d + 4], y);
-          B1[p][d] = y;
-        }
-      }
+            for (int pa = 0; pa < C::npc; ++pa) {
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) {
-        if (rb < nrb && kb >= 2 * rb) {
-          const u32x4* fp = reinterpret_cast<const u32x4*>(frag + ((int64_t)frag_index(rb, kb, NKB) * NPC * 512 +
-                                                                  lane * 8) * 2);
-          u32x4 Ap[NPC];
-#pragma unroll
-          for (int p = 0; p < NPC; ++p) Ap[p] = fp[p * 64];
-#pragma unroll
-          for (int pa = 0; pa < NPC; ++pa) {
-#pragma unroll
-            for (int pb = 0; pb + pa < NPC; ++pb) {
-              const bf16x8 av = __builtin_bit_cast(bf16x8, Ap[pa]);
-              acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  av, __builtin_bit_cast(bf16x8, B0[pb]), acc[rb][0], 0, 0, 0);
-              acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  av, __builtin_bit_cast(bf16x8, B1[pb]), acc[rb][1], 0, 0, 0);
+              for (int pb = 0; pb + pa < C::npc; ++pb)
+                acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Ap[pa]),
+                                                                      __builtin_bit_cast(bf16x8, Bp[pb]),
+                                                                      acc[r][tcb], 0, 0, 0);
             }
           }
         }
       }
     }
+    __syncthreads();   // fragments (and block-staged rows) are rewritten next
   }
+  (void)kblk;
 
-  // depth: rows of accumulator register r are 8 (r/4) + 4 (l/32) + r%4
-  float s0 = 0.f, s1 = 0.f;
+  // depth: accumulator register q holds ray 8 (q/4) + 4 (lane/32) + q%4
   const float nl2e = -1.4426950408889634f;
+  const int hl = lane >> 5;
 #pragma unroll
-  for (int rb = 0; rb < NRB; ++rb) {
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wave + kWaves * r;
     if (rb < nrb) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = 32 * rb + 8 * (r >> 2) + 4 * hl + (r & 3);
-        const float A = Aw[row];
-        s0 = fmaf(A, 1.f - exp2f(nl2e * acc[rb][0][r]), s0);
-        s1 = fmaf(A, 1.f - exp2f(nl2e * acc[rb][1][r]), s1);
+      for (int tcb = 0; tcb < 2; ++tcb) {
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const float A = Aw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)];
+          s = fmaf(A, 1.f - __builtin_amdgcn_exp2f(nl2e * acc[r][tcb][q]), s);
+        }
+        s += __shfl_xor(s, 32, 64);
+        if (hl == 0) sm.part[rb][32 * tcb + (lane & 31)] = s;
       }
     }
   }
-  s0 += __shfl_xor(s0, 32, 64);
-  s1 += __shfl_xor(s1, 32, 64);
-  if (valid) {
-    const float atm = hl ? s1 : s0;
+  __syncthreads();
+  if (wave == 0 && valid) {
+    float atm = 0.f;
+    for (int rb = 0; rb < nrb; ++rb) atm += sm.part[rb][lane];
     const int64_t o = (int64_t)b * W + col;
     reinterpret_cast<float*>(a.aws)[o] = atm;
-    if (a.depth_native) a.depth_native[o] = h->Rp2_Rs2 + (double)atm;
+    if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + (double)atm;
     if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
+  }
+  __syncthreads();
+}
+
+// One workgroup per (model, span).
+template <int MODE, int RBW>
+__global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
+  __shared__ Smem<MODE, RBW> sm;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if ((int)blockIdx.x >= B) return;
+  process<MODE, RBW>(a, blockIdx.x, blockIdx.y, sm);
+}
+
+// Persistent: a fixed grid pops chunks of (span, model) items from kQueues
+// queues, queue q holding the spans s = q (mod kQueues) in increasing order
+// and, per span, the models longest first; a workgroup starts on the queue of
+// its XCD (workgroups are dealt to the XCDs round-robin) so that the waves of
+// one XCD share the table rows of few spans in its L2, and moves on to the
+// other queues when its own is drained.  Every workgroup leaves once all
+// queues are drained.
+template <int MODE, int RBW>
+__global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma_persist(FwdArgs a) {
+  __shared__ Smem<MODE, RBW> sm;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  const int nspans = (a.tab.n_wn + kCols - 1) / kCols;
+  const int q0 = blockIdx.x % kQueues;
+  for (int k = 0; k < kQueues; ++k) {
+    const int q = (q0 + k) % kQueues;
+    const int nsq = q < nspans ? (nspans - q + kQueues - 1) / kQueues : 0;
+    const int total = nsq * B;
+    while (true) {
+      if (threadIdx.x == 0) sm.base = total > 0 ? atomicAdd(&a.qcount[q], kChunk) : 0;
+      __syncthreads();
+      const int base = sm.base;
+      if (threadIdx.x < kChunk) {
+        const int i = base + threadIdx.x;
+        int code = -1;
+        if (i < total) {
+          const int ls = i / B, slot = i - ls * B;
+          const int sp = ls * kQueues + q;
+          const int bm = a.order[slot];
+          const int2 r = a.mspan[bm];
+          if (sp >= r.x && sp < r.y) code = bm;
+        }
+        sm.items[threadIdx.x] = code;
+      }
+      __syncthreads();
+      if (base >= total) break;
+      for (int c = 0; c < kChunk; ++c) {
+        const int bm = sm.items[c];
+        if (bm >= 0) process<MODE, RBW>(a, bm, ((base + c) / B) * kQueues + q, sm);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int MODE, int RBW>
+int occupancy() {
+  static int blocks = 0;
+  if (!blocks) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW>, 64 * kWaves, 0) !=
+            hipSuccess || nb < 1)
+      nb = 1;
+    blocks = nb;
+  }
+  return blocks;
+}
+
+template <int MODE, int RBW>
+void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
+  if (a.persistent) {
+    const int grid = n_cu * occupancy<MODE, RBW>();
+    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW>), dim3(grid), dim3(64 * kWaves), 0, s, a);
+  } else {
+    dim3 grid(B_grid, (a.tab.n_wn + kCols - 1) / kCols);
+    hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW>), grid, dim3(64 * kWaves), 0, s, a);
   }
 }
 
 template <int MODE>
-void launch_mode(const FwdArgs& a, int nrb, int B_grid, hipStream_t s) {
-  dim3 grid(B_grid, a.n_spans), blk(64 * kWaves);
-  if (nrb <= 2) hipLaunchKernelGGL((k_fwd_mfma<MODE, 2>), grid, blk, 0, s, a);
-  else if (nrb <= 4) hipLaunchKernelGGL((k_fwd_mfma<MODE, 4>), grid, blk, 0, s, a);
-  else hipLaunchKernelGGL((k_fwd_mfma<MODE, 7>), grid, blk, 0, s, a);
+void launch_mode(const FwdArgs& a, int nrb, int B_grid, int n_cu, hipStream_t s) {
+  if (nrb <= 4) launch_rbw<MODE, 1>(a, B_grid, n_cu, s);
+  else launch_rbw<MODE, 2>(a, B_grid, n_cu, s);
 }
 
 }  // namespace
 
-void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int persistent_grid,
-                     hipStream_t s) {
-  (void)persistent_grid;
-  if (B_grid <= 0 || a.n_spans <= 0) return;
+void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int n_cu, hipStream_t s) {
+  if (B_grid <= 0) return;
   switch (precision) {
-    case TRX_FP32: launch_mode<TRX_FP32>(a, nrb_max, B_grid, s); break;
-    case TRX_BF16_SPLIT2: launch_mode<TRX_BF16_SPLIT2>(a, nrb_max, B_grid, s); break;
-    default: launch_mode<TRX_BF16_SPLIT3>(a, nrb_max, B_grid, s); break;
+    case TRX_FP32: launch_mode<TRX_FP32>(a, nrb_max, B_grid, n_cu, s); break;
+    case TRX_BF16_SPLIT2: launch_mode<TRX_BF16_SPLIT2>(a, nrb_max, B_grid, n_cu, s); break;
+    default: launch_mode<TRX_BF16_SPLIT3>(a, nrb_max, B_grid, n_cu, s); break;
   }
 }
 

@@ -117,6 +117,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     if (tid == 0) {
       h->n = 0; h->status = status; h->lo = lo; h->hi = hi;
       h->nrb = 0; h->nkb = 0; h->span_lo = 0; h->span_hi = 0;
+      if (a.mlay) a.mlay[b] = 0;
+      if (a.mspan) a.mspan[b] = make_int2(0, 0);
     }
     if (a.depth_native && (status & TRX_MODEL_BAD_WINDOW) == 0) {
       for (int i = lo + tid; i < hi; i += kThreads)
@@ -135,10 +137,12 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   // a1: chemistry
   if (tid == 0) {
     double S = 0.0, mu = 0.0;
+    for (int i = 0; i < TRX_MAX_ABSORBERS; ++i) h->chi_abs32[i] = 0.0f;
     for (int i = 0; i < nabs; ++i) {
       double c = pow(10.0, a.bt.log10_vmr[(int64_t)b * nabs + i]);
       h->chi_s[i] = c;
       h->chi_s32[i] = (float)c;
+      h->chi_abs32[i] = (float)c;
       S += c;
       mu += c * tb.mass[i];
     }
@@ -150,8 +154,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     h->chi_s32[nabs + 1] = (float)che;
     mu += ch2 * tb.mass[nabs] + che * tb.mass[nabs + 1];
     s_mu = mu * a.bt.amu;
-    for (int p = 0; p < tb.n_cia; ++p) {
-      double w = h->chi_s[tb.cia_pair[p][0]] * h->chi_s[tb.cia_pair[p][1]];
+    for (int p = 0; p < TRX_MAX_CIA; ++p) {
+      double w = p < tb.n_cia ? h->chi_s[tb.cia_pair[p][0]] * h->chi_s[tb.cia_pair[p][1]] : 0.0;
       h->cia_w[p] = w;
       h->cia_w32[p] = (float)w;
     }
@@ -183,6 +187,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     h->n = N; h->status = 0; h->lo = lo; h->hi = hi;
     h->nrb = (N + 31) / 32; h->nkb = (N + 15) / 16;
     h->span_lo = lo / sc; h->span_hi = (hi + sc - 1) / sc;
+    if (a.mlay) a.mlay[b] = N;
+    if (a.mspan) a.mspan[b] = make_int2(lo / kSpanCols, (hi + kSpanCols - 1) / kSpanCols);
     h->Rp2_Rs2 = (Rp / Rs) * (Rp / Rs);
     h->inv_Rs2 = 1.0 / (Rs * Rs);
     h->Rp = Rp;
@@ -235,18 +241,141 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         lw64[8 * l + q] = w[q];
         lw32[8 * l + q] = (float)(q >= 5 ? w[q] / kCiaScale32 : w[q]);
       }
-      lid[2 * l] = iT * tb.n_P + iP;
-      lid[2 * l + 1] = iC;
+      lid[8 * l] = iT * tb.n_P + iP;
+      lid[8 * l + 1] = iC;
     } else {
       zs[l] = 0.0;
       A64[l] = 0.0;
       A32[l] = 0.0f;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
-      lid[2 * l] = -1;   // padding layer: no corners
-      lid[2 * l + 1] = -1;
+      for (int q = 0; q < 8; ++q) lid[8 * l + q] = 0;   // padding layer: zero weights
     }
   }
   __syncthreads();
+
+  // distinct corners of the whole model (bitmaps over the corner ids, slots
+  // = rank of the id among the set bits) and each layer's slots in them
+  {
+    __shared__ uint32_t s_bm[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
+    __shared__ uint32_t s_pre[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
+    __shared__ uint32_t s_cbm[TRX_MAX_TGRID / 32];
+    __shared__ uint32_t s_cpre[TRX_MAX_TGRID / 32];
+    const int nwords = (tb.n_T * tb.n_P + 31) / 32;
+    const int ncwords = (tb.n_Tcia + 31) / 32;
+    for (int w = tid; w < nwords; w += kThreads) s_bm[w] = 0u;
+    for (int w = tid; w < ncwords; w += kThreads) s_cbm[w] = 0u;
+    __syncthreads();
+    for (int l = tid; l < N; l += kThreads) {
+      const int base = lid[8 * l];
+      const int cs[4] = {base, base + tb.n_P, base + 1, base + tb.n_P + 1};
+      for (int q = 0; q < 4; ++q) atomicOr(&s_bm[cs[q] >> 5], 1u << (cs[q] & 31));
+      if (tb.n_cia > 0) {
+        const int t0 = lid[8 * l + 1];
+        atomicOr(&s_cbm[t0 >> 5], 1u << (t0 & 31));
+        atomicOr(&s_cbm[(t0 + 1) >> 5], 1u << ((t0 + 1) & 31));
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t acc = 0;
+      for (int w = 0; w < nwords; ++w) { s_pre[w] = acc; acc += __popc(s_bm[w]); }
+      uint32_t cacc = 0;
+      for (int w = 0; w < ncwords; ++w) { s_cpre[w] = cacc; cacc += __popc(s_cbm[w]); }
+      MList* ml = reinterpret_cast<MList*>(slab + L.off_mlist);
+      ml->nU = (int)acc;
+      ml->nV = tb.n_cia > 0 ? (int)cacc : 0;
+    }
+    __syncthreads();
+    MList* ml = reinterpret_cast<MList*>(slab + L.off_mlist);
+    for (int w = tid; w < nwords; w += kThreads) {
+      uint32_t bits = s_bm[w];
+      int slot = (int)s_pre[w];
+      while (bits) {
+        const int bpos = __ffs(bits) - 1;
+        if (slot < kMListU) ml->ids[slot] = 32 * w + bpos;
+        ++slot;
+        bits &= bits - 1;
+      }
+    }
+    if (tb.n_cia > 0) {
+      for (int w = tid; w < ncwords; w += kThreads) {
+        uint32_t bits = s_cbm[w];
+        int slot = (int)s_cpre[w];
+        while (bits) {
+          const int bpos = __ffs(bits) - 1;
+          if (slot < kMListV) ml->tids[slot] = 32 * w + bpos;
+          ++slot;
+          bits &= bits - 1;
+        }
+      }
+    }
+    auto rank = [&](const uint32_t* bm, const uint32_t* pre, int c) -> uint32_t {
+      const uint32_t below = bm[c >> 5] & ((1u << (c & 31)) - 1u);
+      const uint32_t r = pre[c >> 5] + __popc(below);
+      return r > 255u ? 255u : r;
+    };
+    for (int l = tid; l < N; l += kThreads) {
+      const int base = lid[8 * l];
+      const int cs[4] = {base, base + tb.n_P, base + 1, base + tb.n_P + 1};
+      uint32_t slots = 0;
+      for (int q = 0; q < 4; ++q) slots |= rank(s_bm, s_pre, cs[q]) << (8 * q);
+      lid[8 * l + 2] = (int32_t)slots;
+      uint32_t cslots = 0;
+      if (tb.n_cia > 0) {
+        const int t0 = lid[8 * l + 1];
+        cslots = rank(s_cbm, s_cpre, t0) | (rank(s_cbm, s_cpre, t0 + 1) << 8);
+      }
+      lid[8 * l + 3] = (int32_t)cslots;
+    }
+  }
+  __syncthreads();
+
+  // distinct corners of each 16-layer block and each layer's slots in them
+  KBlk* kblk = reinterpret_cast<KBlk*>(slab + L.off_kblk);
+  const int nkb = (N + 15) / 16;
+  for (int kb = tid; kb < L.NKB; kb += kThreads) {
+    KBlk d;
+    d.nU = 0;
+    d.nV = 0;
+    bool over = false;
+    for (int j = 0; j < 16 && kb < nkb; ++j) {
+      const int l = 16 * kb + j;
+      if (l >= N) break;
+      const int base = lid[8 * l];
+      const int cs[4] = {base, base + tb.n_P, base + 1, base + tb.n_P + 1};
+      uint32_t slots = 0;
+      for (int q = 0; q < 4; ++q) {
+        int u = 0;
+        while (u < d.nU && d.ids[u] != cs[q]) ++u;
+        if (u == d.nU) {
+          if (d.nU == kMaxU) { over = true; u = 0; }
+          else d.ids[d.nU++] = cs[q];
+        }
+        slots |= (uint32_t)u << (8 * q);
+      }
+      lid[8 * l + 4] = (int32_t)slots;
+      uint32_t cslots = 0;
+      if (tb.n_cia > 0) {
+        const int t0 = lid[8 * l + 1];
+        const int ts[2] = {t0, t0 + 1};
+        for (int q = 0; q < 2; ++q) {
+          int v = 0;
+          while (v < d.nV && d.tids[v] != ts[q]) ++v;
+          if (v == d.nV) {
+            if (d.nV == kMaxV) { over = true; v = 0; }
+            else d.tids[d.nV++] = ts[q];
+          }
+          cslots |= (uint32_t)v << (8 * q);
+        }
+      }
+      lid[8 * l + 5] = (int32_t)cslots;
+    }
+    if (over) d.nU = -1;
+    for (int u = d.nU < 0 ? 0 : d.nU; u < kMaxU; ++u) d.ids[u] = 0;
+    for (int v = d.nV; v < kMaxV; ++v) d.tids[v] = 0;
+    d.pad[0] = d.pad[1] = 0;
+    kblk[kb] = d;
+  }
 
   // a3: chord lengths
   auto dl_of = [&](int j, int k) -> double {
@@ -312,7 +441,41 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   }
 }
 
+// Work order of the persistent launch: model indices sorted by layer count,
+// longest first (counting sort), and the queue counters zeroed.
+__global__ __launch_bounds__(1024) void k_schedule(const int32_t* mlay, const int32_t* B_dev, int B,
+                                                   int32_t* order, int32_t* qcount) {
+  __shared__ int32_t hist[TRX_MAX_LAYERS_FP64 + 1];
+  const int nb = B_dev ? *B_dev : B;
+  for (int i = threadIdx.x; i <= TRX_MAX_LAYERS_FP64; i += blockDim.x) hist[i] = 0;
+  if (threadIdx.x < kQueues) qcount[threadIdx.x] = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int n = min(max(mlay[b], 0), TRX_MAX_LAYERS_FP64);
+    atomicAdd(&hist[n], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int n = TRX_MAX_LAYERS_FP64; n >= 0; --n) {
+      const int c = hist[n];
+      hist[n] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int n = min(max(mlay[b], 0), TRX_MAX_LAYERS_FP64);
+    order[atomicAdd(&hist[n], 1)] = b;
+  }
+}
+
 }  // namespace
+
+void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* order, int32_t* qcount,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(1024), 0, s, mlay, B_dev, B, order, qcount);
+}
 
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;

@@ -21,6 +21,15 @@ struct trx_ctx {
   DevBuf ws;    // per-model slabs
   DevBuf aws;   // native atmospheric depth
   DevBuf grad;  // gradient workspace
+  DevBuf sched; // work order of the persistent launch
+  // profiling (trx_profile)
+  bool profile = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[TRX_KERNEL_CLASSES] = {0};
+  int launches[TRX_KERNEL_CLASSES] = {0};
+  bool capturing = false;
 };
 
 struct trx_tables {
@@ -45,13 +54,39 @@ namespace trx {
 
 // Launch-shape choices of one run (the autotuner's search space).
 struct RunConfig {
-  int span_cols = 256;   // columns per (model, span) work item
-  int nrb_max = 7;       // ray-block capacity of the matrix-core kernel
-  int persistent = 0;    // 1: persistent grid with work queues
-  int waves = 4;         // waves per workgroup
+  int span_cols = kSpanCols;  // columns per (model, span) work item
+  int nrb_max = 7;            // ray-block capacity of the matrix-core kernel
+  int persistent = 1;         // 1: persistent grid with work queues
+};
+
+// Scheduling buffers of one launch (device memory).
+struct SchedBufs {
+  int32_t* mlay = nullptr;   // [B]
+  int2* mspan = nullptr;     // [B]
+  int32_t* order = nullptr;  // [B]
+  int32_t* qcount = nullptr; // [kQueues]
+  static size_t bytes(int B) { return (size_t)B * 16 + 256; }
+  static SchedBufs carve(void* base, int B) {
+    SchedBufs s;
+    uint8_t* p = (uint8_t*)base;
+    s.mspan = (int2*)p;
+    s.mlay = (int32_t*)(p + (size_t)B * 8);
+    s.order = (int32_t*)(p + (size_t)B * 12);
+    s.qcount = (int32_t*)(p + (size_t)B * 16);
+    return s;
+  }
 };
 
 trx_status set_err(trx_ctx* c, trx_status s, const char* fmt, ...);
+
+// Brackets a kernel launch with profiling events when profiling is on.
+struct ProfScope {
+  trx_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(trx_ctx* ctx, int k);
+  ~ProfScope();
+};
 trx_status hip_err(trx_ctx* c, hipError_t e, const char* what);
 trx_status ensure_buffer(trx_ctx* c, DevBuf& buf, size_t bytes, const char* what);
 trx_status upload(trx_ctx* c, const double* host, int64_t n, double** d64, float** d32,
@@ -63,7 +98,7 @@ DevBatch dev_batch(const trx_batch* bt);
 RunConfig default_config(int precision, int max_layers);
 trx_status enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B, const int32_t* B_dev,
                            int max_layers, const trx_bins* bins, int precision, const RunConfig& rc,
-                           uint8_t* ws, void* aws, double* depth_native, double* depth_binned,
-                           int32_t* status);
+                           uint8_t* ws, void* aws, const SchedBufs& sb, double* depth_native,
+                           double* depth_binned, int32_t* status);
 
 }  // namespace trx

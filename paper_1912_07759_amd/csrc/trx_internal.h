@@ -13,6 +13,30 @@ constexpr int kHdrBytes = 2048;    // per-model header block in the slab
 // CIA tables is stored multiplied by kCiaScale32 and the FP32 CIA weights
 // divided by it.
 constexpr double kCiaScale32 = 1e40;
+
+// Per 16-layer block, the distinct table corners its layers interpolate
+// between: at most 4 (T, P) corners of the cross-section grid and 2
+// temperature nodes of the CIA grid per layer.
+constexpr int kMaxU = 64;
+constexpr int kMaxV = 32;
+// Per model, the distinct corners of all its layers (ids sorted): kernels
+// stage them once per work item when they fit their capacity.
+constexpr int kMListU = 160;
+constexpr int kMListV = 32;
+struct alignas(16) MList {
+  int32_t nU;            // distinct cross-section corners (may exceed kMListU)
+  int32_t nV;            // distinct CIA nodes (may exceed kMListV)
+  int32_t pad[2];
+  int32_t ids[kMListU];
+  int32_t tids[kMListV];
+};
+struct alignas(16) KBlk {
+  int32_t nU;
+  int32_t nV;
+  int32_t ids[kMaxU];    // corner id iT * n_P + iP
+  int32_t tids[kMaxV];   // CIA temperature node
+  int32_t pad[2];
+};
 constexpr int kMaxSpecies = TRX_MAX_ABSORBERS + 2;
 
 // Per-model values written by the geometry kernel and read by every later
@@ -28,6 +52,7 @@ struct ModelHdr {
   double inv_Rs2;     // 1/Rs^2
   double Rp, mu_kg;
   double chi_s[kMaxSpecies];        // absorbers, H2, He
+  float chi_abs32[TRX_MAX_ABSORBERS];  // absorbers only, zero padded
   double cia_w[TRX_MAX_CIA];        // chi_a * chi_b per CIA pair
   float chi_s32[kMaxSpecies];
   float cia_w32[TRX_MAX_CIA];
@@ -43,9 +68,9 @@ struct DevTables {
   const double* logP;      // [n_P]
   const double* Tcia;      // [n_Tcia]
   const double* xsec64;    // [n_abs][n_T][n_P][n_wn]
-  const float* xsec32;
+  const float* xsec32;     // same layout in FP32
   const double* cia64;     // [n_cia][n_Tcia][n_wn]
-  const float* cia32;
+  const float* cia32;      // same layout in FP32, times kCiaScale32
   const double* ray64;     // [n_abs+2][n_wn] (zeros when absent)
   const float* ray32;
   double mass[kMaxSpecies];          // amu: absorbers, H2, He
@@ -56,7 +81,7 @@ struct DevTables {
 struct Layout {
   int32_t NP;              // padded layer capacity (multiple of 32)
   int32_t NRB, NKB;        // NP/32, NP/16
-  int64_t off_z, off_A64, off_A32, off_lw64, off_lw32, off_lid, off_dl;
+  int64_t off_z, off_A64, off_A32, off_lw64, off_lw32, off_lid, off_kblk, off_mlist, off_dl;
   int64_t dl_bytes;        // mode-specific path-length storage
   int64_t slab;            // bytes per model (multiple of 256)
 };
@@ -101,7 +126,11 @@ inline Layout make_layout(int N_max, int precision) {
   L.off_A32 = take(4LL * L.NP);
   L.off_lw64 = take(8LL * 8 * L.NP);
   L.off_lw32 = take(4LL * 8 * L.NP);
-  L.off_lid = take(4LL * 2 * L.NP);
+  // per layer: abs corner, CIA node, model-list slots (abs, CIA), block-list
+  // slots (abs, CIA), 2 spare
+  L.off_lid = take(4LL * 8 * L.NP);
+  L.off_kblk = take((int64_t)sizeof(KBlk) * L.NKB);
+  L.off_mlist = take((int64_t)sizeof(MList));
   if (precision == TRX_FP64) {
     L.dl_bytes = 8LL * L.NP * L.NP;  // dense transposed dlT[k][j]
   } else {
@@ -145,7 +174,14 @@ struct GeomArgs {
   int32_t n_limit;        // largest accepted layer count
   int32_t span_cols;      // columns per work span
   double* depth_native;   // [B][n_wn] or null: NaN written for invalid models
+  int32_t* mlay;          // [B] layer count (0 for an invalid model)
+  int2* mspan;            // [B] spans [lo, hi) of kSpanCols columns its window covers
 };
+
+// Columns of one work item of the forward kernels.
+constexpr int kSpanCols = 64;
+// Work queues of the persistent launch (one per XCD of the MI355X).
+constexpr int kQueues = 8;
 
 __host__ __device__ inline ModelHdr* hdr_of(uint8_t* ws, const Layout& L, int b) {
   return reinterpret_cast<ModelHdr*>(ws + (int64_t)b * L.slab);
@@ -169,12 +205,17 @@ struct FwdArgs {
   double* depth_native;   // [B][n_wn] or null
   void* aws;              // [B][n_wn] atmospheric part a/Rs^2 (double for FP64, else float)
   int32_t* model_status;  // [B]
-  // persistent scheduling (null for grid launches)
-  const int32_t* items;   // packed (span << 20 | model) in queue order
-  const int32_t* qbounds; // [2 * n_queues] item range per queue
-  int32_t* qcount;        // [n_queues] counters (zeroed before launch)
-  int32_t n_queues;
+  // persistent scheduling: items (span, model) of queue q are the spans
+  // s = q (mod kQueues) in increasing order, each with the models in order[]
+  // (layer count descending); workgroups pop chunks of items with atomics.
+  const int32_t* order;   // [B] model indices, longest first
+  const int2* mspan;      // [B] span range per model
+  int32_t* qcount;        // [kQueues] item counters, zeroed by the schedule kernel
+  int32_t persistent;     // 1: persistent grid, 0: one workgroup per (model, span)
 };
+
+void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* order, int32_t* qcount,
+                     hipStream_t s);
 
 struct BinArgs {
   const uint8_t* ws;
@@ -193,8 +234,7 @@ struct BinArgs {
 };
 
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s);
-void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int persistent_grid,
-                     hipStream_t s);
+void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int n_cu, hipStream_t s);
 void launch_bin(const BinArgs& a, int B_grid, hipStream_t s);
 
 }  // namespace trx

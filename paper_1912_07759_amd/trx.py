@@ -29,7 +29,10 @@ EXPORTS = ["trx_create", "trx_destroy", "trx_last_error", "trx_set_stream",
            "trx_synchronize", "trx_tables_create", "trx_tables_destroy",
            "trx_bins_create", "trx_bins_destroy", "trx_forward", "trx_chi2_grad",
            "trx_plan_create", "trx_plan_destroy", "trx_plan_batch", "trx_plan_launch",
-           "trx_autotune", "trx_plan_describe"]
+           "trx_autotune", "trx_plan_describe", "trx_profile", "trx_profile_read"]
+
+KERNEL_GEOMETRY, KERNEL_FORWARD, KERNEL_BINNING, KERNEL_ADJOINT, KERNEL_GEOM_ADJ, \
+    KERNEL_SCHEDULE = range(6)
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
@@ -106,6 +109,16 @@ class Context:
 
     def synchronize(self):
         self.check(lib().trx_synchronize(self.h))
+
+    def profile(self, enable=True):
+        self.check(lib().trx_profile(self.h, int(bool(enable))))
+
+    def profile_read(self, kernel):
+        """(total GPU ms, launches) of one kernel class since profile(True)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int32()
+        self.check(lib().trx_profile_read(self.h, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def last_error(self):
         return lib().trx_last_error(self.h).decode()
