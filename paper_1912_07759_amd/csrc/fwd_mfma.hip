@@ -44,9 +44,9 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kCols = 64;               // columns per workgroup
-constexpr int kRowsAbs = 112;           // staged cross-section corners
-constexpr int kRowsCia = 32;            // staged CIA nodes
-static_assert(kRowsAbs >= kMaxU && kRowsCia >= kMaxV, "block staging must fit");
+// staged rows: the cross-section corners, then the CIA nodes
+constexpr int kRows = 96;
+static_assert(kRows >= kMaxU + kMaxV, "block staging must fit");
 constexpr int kInFlight = 16;           // table loads per lane issued together
 constexpr int kChunk = 8;               // items popped per atomic (persistent launch)
 
@@ -65,14 +65,14 @@ struct Cfg {
 
 template <int MODE, int RBW>
 struct Smem {
-  float rows[kRowsAbs + kRowsCia][kCols];
+  float rows[kRows][kCols];
   __attribute__((aligned(16))) uint32_t frag[Cfg<MODE>::frag_dw];
   float part[kWaves * RBW][kCols];
   // per-item copies of the model's records (read with uniform LDS addresses)
   __attribute__((aligned(16))) float lw[TRX_MAX_LAYERS_MFMA][8];   // layer weights
   int2 sl[TRX_MAX_LAYERS_MFMA];                                     // corner slots
-  int32_t ids[kRowsAbs];                                            // staged corner ids
-  int32_t tids[kRowsCia];                                           // staged CIA nodes
+  int32_t ids[kRows];                                               // staged corner ids
+  int32_t tids[kRows];                                              // staged CIA nodes
   float chi[TRX_MAX_ABSORBERS];
   float ciaw[TRX_MAX_CIA];
   int32_t items[kChunk];
@@ -80,35 +80,52 @@ struct Smem {
 };
 
 // rows[u][lane] = sum_i chi[i] * tab[i][ids[u]][col] for the corners
-// u = wave, wave + 4, ... < nU (tab_col = table + col; absorber stride
-// abs_stride, corner stride W).  The (corner, absorber) pairs are walked with
-// uniform counters, kInFlight loads at a time; partial sums are added to the
-// row when the corner changes.
-__device__ inline void stage_rows(const float* tab_col, int64_t abs_stride, int W, const int32_t* ids, int nU,
-                                  const float* chi, int nabs, float* rows, int wave, int lane) {
-  for (int u = wave; u < nU; u += kWaves) rows[u * kCols + lane] = 0.f;
-  if (nabs == 0) return;
-  int u = wave, i = 0;
-  while (u < nU) {
-    float v[kInFlight], cw[kInFlight];
-    int uu[kInFlight];
+// u = wave, wave + 4, ... < nU of a table laid out [i][corner][W].  Loads
+// are buffer loads: one resource per absorber i (its range bounds every
+// access), the column as the per-lane offset and the corner row as a uniform
+// offset.  A batch of kSG corners x up to kSA absorbers is issued before the
+// first use and reduced per corner.
+constexpr int kSG = 8;
+constexpr int kSA = 4;
+constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit buffer, gfx9 family
+__device__ inline void stage_rows(const float* tab, int64_t abs_stride, int W, int col, const int32_t* ids,
+                                  int nU, const float* chi, int nabs, float* rows, int wave, int lane) {
+  const int voff = col * 4;
+  const int rec = (int)(abs_stride * 4 < 0x7fffffff ? abs_stride * 4 : 0x7fffffff);
+  for (int u0 = wave; u0 < nU; u0 += kWaves * kSG) {
+    int soff[kSG];
 #pragma unroll
-    for (int k = 0; k < kInFlight; ++k) {
-      const bool ok = u < nU;
-      uu[k] = ok ? u : -1;
-      cw[k] = ok ? chi[i] : 0.f;
-      v[k] = tab_col[(int64_t)i * abs_stride + (int64_t)ids[ok ? u : wave] * W];
-      if (++i == nabs) { i = 0; u += kWaves; }
+    for (int g = 0; g < kSG; ++g) {
+      const int u = u0 + kWaves * g < nU ? u0 + kWaves * g : u0;
+      soff[g] = __builtin_amdgcn_readfirstlane(ids[u]) * W * 4;
     }
-    float acc = 0.f;
+    float s[kSG];
 #pragma unroll
-    for (int k = 0; k < kInFlight; ++k) {
-      acc = fmaf(cw[k], v[k], acc);
-      if (k == kInFlight - 1 || uu[k + 1 < kInFlight ? k + 1 : k] != uu[k]) {
-        if (uu[k] >= 0) rows[uu[k] * kCols + lane] += acc;
-        acc = 0.f;
+    for (int g = 0; g < kSG; ++g) s[g] = 0.f;
+    for (int i0 = 0; i0 < nabs; i0 += kSA) {
+      float v[kSA][kSG];
+#pragma unroll
+      for (int ii = 0; ii < kSA; ++ii) {
+        if (i0 + ii < nabs) {
+          const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+              (void*)(tab + (int64_t)(i0 + ii) * abs_stride), (short)0, rec, kRsrcWord3);
+#pragma unroll
+          for (int g = 0; g < kSG; ++g)
+            v[ii][g] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff[g], 0));
+        }
+      }
+#pragma unroll
+      for (int ii = 0; ii < kSA; ++ii) {
+        if (i0 + ii < nabs) {
+          const float c = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(chi[i0 + ii])));
+#pragma unroll
+          for (int g = 0; g < kSG; ++g) s[g] = fmaf(c, v[ii][g], s[g]);
+        }
       }
     }
+#pragma unroll
+    for (int g = 0; g < kSG; ++g)
+      if (u0 + kWaves * g < nU) rows[(u0 + kWaves * g) * kCols + lane] = s[g];
   }
 }
 
@@ -163,12 +180,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
   const int nkb = hd->nkb, nrb = hd->nrb;
   const int NKB = L.NKB;
 
-  const float* xs = tb.xsec32 + cc;
   const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
-  const float* ci = tb.cia32 + cc;
   const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
   float* rows = &sm.rows[0][0];
-  float* crows = &sm.rows[kRowsAbs][0];
+  float* crows = rows;   // CIA rows follow the staged corners
   const int tid = threadIdx.x;
   // copy the corner ids of the model (or of layer block kb) into LDS, then
   // stage the mixed rows
@@ -176,11 +191,12 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
     for (int e = tid; e < nU; e += 64 * kWaves) sm.ids[e] = ids[e];
     for (int e = tid; e < nV; e += 64 * kWaves) sm.tids[e] = tids[e];
     __syncthreads();
-    stage_rows(xs, abs_stride, W, sm.ids, nU, sm.chi, tb.n_abs, rows, wave, lane);
-    if (has_cia) stage_rows(ci, cia_stride, W, sm.tids, nV, sm.ciaw, tb.n_cia, crows, wave, lane);
+    stage_rows(tb.xsec32, abs_stride, W, cc, sm.ids, nU, sm.chi, tb.n_abs, rows, wave, lane);
+    crows = rows + nU * kCols;
+    if (has_cia) stage_rows(tb.cia32, cia_stride, W, cc, sm.tids, nV, sm.ciaw, tb.n_cia, crows, wave, lane);
   };
   // whole-model staging when the distinct corners fit, else per layer block
-  const bool mstage = ml->nU <= kRowsAbs && ml->nV <= kRowsCia;
+  const bool mstage = ml->nU + ml->nV <= kRows;
   const int slot_off = mstage ? 2 : 4;
   for (int e = tid; e < N * 8; e += 64 * kWaves) (&sm.lw[0][0])[e] = lw[e];
   for (int e = tid; e < N; e += 64 * kWaves) sm.sl[e] = *reinterpret_cast<const int2*>(lid + 8 * e + slot_off);
@@ -203,28 +219,45 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
     }
     __syncthreads();
 
-    // 1. opacity of layers 16 kb + 4 wave + jj, one column per lane
+    // 1. opacity of layers 16 kb + 4 wave + jj, one column per lane; the
+    // corner slots are uniform, and values are reused while consecutive
+    // layers share their bracket
     float kap[4];
+    {
+      uint32_t psl = 0xffffffffu, pcl = 0xffffffffu;
+      float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, c0 = 0.f, c1 = 0.f;
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int l = 16 * kb + 4 * wave + jj;
-      float k = 0.f;
-      if (l < N) {
-        const float* w = sm.lw[l];
-        const int2 sl2 = sm.sl[l];
-        const uint32_t sl = (uint32_t)sl2.x;
-        k = w[0] * rows[(sl & 0xff) * kCols + lane];
-        k = fmaf(w[1], rows[((sl >> 8) & 0xff) * kCols + lane], k);
-        k = fmaf(w[2], rows[((sl >> 16) & 0xff) * kCols + lane], k);
-        k = fmaf(w[3], rows[(sl >> 24) * kCols + lane], k);
-        k = fmaf(w[4], R, k);
-        if (has_cia) {
-          const uint32_t cl = (uint32_t)sl2.y;
-          k = fmaf(w[5], crows[(cl & 0xff) * kCols + lane], k);
-          k = fmaf(w[6], crows[((cl >> 8) & 0xff) * kCols + lane], k);
+      for (int jj = 0; jj < 4; ++jj) {
+        const int l = 16 * kb + 4 * wave + jj;
+        float k = 0.f;
+        if (l < N) {
+          const float* w = sm.lw[l];
+          const uint32_t sl = __builtin_amdgcn_readfirstlane((uint32_t)sm.sl[l].x);
+          if (sl != psl) {
+            m0 = rows[(sl & 0xff) * kCols + lane];
+            m1 = rows[((sl >> 8) & 0xff) * kCols + lane];
+            m2 = rows[((sl >> 16) & 0xff) * kCols + lane];
+            m3 = rows[(sl >> 24) * kCols + lane];
+            psl = sl;
+          }
+          k = w[0] * m0;
+          k = fmaf(w[1], m1, k);
+          k = fmaf(w[2], m2, k);
+          k = fmaf(w[3], m3, k);
+          k = fmaf(w[4], R, k);
+          if (has_cia) {
+            const uint32_t cl = __builtin_amdgcn_readfirstlane((uint32_t)sm.sl[l].y);
+            if (cl != pcl) {
+              c0 = crows[(cl & 0xff) * kCols + lane];
+              c1 = crows[((cl >> 8) & 0xff) * kCols + lane];
+              pcl = cl;
+            }
+            k = fmaf(w[5], c0, k);
+            k = fmaf(w[6], c1, k);
+          }
         }
+        kap[jj] = k;
       }
-      kap[jj] = k;
     }
     const int cb = lane >> 5, lc = lane & 31;
     if constexpr (MODE == TRX_FP32) {
@@ -353,7 +386,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
 // other queues when its own is drained.  Every workgroup leaves once all
 // queues are drained.
 template <int MODE, int RBW>
-__global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma_persist(FwdArgs a) {
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_fwd_mfma_persist(FwdArgs a) {
   __shared__ Smem<MODE, RBW> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int nspans = (a.tab.n_wn + kCols - 1) / kCols;
