@@ -39,11 +39,44 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--variant", default=None,
+                   help="force a plan variant (e.g. 'persistent=1 group=32') instead of "
+                        "the autotuner's choice")
+    p.add_argument("--fp64-looped", type=int, default=256, metavar="M",
+                   help="time the plain FP64 path one model per launch on M models "
+                        "(0: skip); the rate is scaled to the batch")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="also run one plain device copy of this many MiB (reference "
+                        "for the HBM byte counters of a profiler run)")
     return p.parse_args()
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_of(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed profiler summary,
+    if it was taken on the current source of the kernel, else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_bytes_{kernel}_{precision}_batched4096.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in fields.get("sources", "").split():
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if not fields.get("sources") or h.hexdigest() != fields.get("sources_sha256"):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def time_steps(fn, steps, warmup):
@@ -79,26 +112,35 @@ def main():
     bins = trx.Bins(ctx, T, ch.lo, ch.hi)
     db = trx.DeviceBatch.from_synth(batch, max_layers=200)
     B = batch.B
-    native = torch.empty((B, tables.n_wn), dtype=torch.float64, device="cuda")
-    binned = torch.empty((B, bins.n), dtype=torch.float64, device="cuda")
-    status = torch.empty(B, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
 
-    def step(prec):
-        return lambda: trx.forward(ctx, T, db, bins, prec, native=False, out_binned=binned,
-                                   out_status=status)
+    # the batched launch: one graph-captured plan, variant autotuned on this batch
+    plan = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision=args.precision, graph=True)
+    t1 = time.time()
+    if args.variant:
+        plan.set_variant(args.variant)
+    else:
+        plan.autotune(db)
+    variant = plan.describe()
+    log(f"variant {variant} ({time.time() - t1:.1f} s)")
 
-    ms = time_steps(step(args.precision), args.steps, args.warmup)
+    def step():
+        plan.launch(db)
+
+    ms = time_steps(step, args.steps, args.warmup)
     log(f"{args.precision}: {ms:.3f} ms/step")
+    _, binned, status = plan.launch(db)
+    torch.cuda.synchronize()
     assert int((status != 0).sum()) == 0
 
-    # dominant kernel, timed live with HIP events around each launch
+    # dominant kernel, timed live with HIP events around each launch on the
+    # library's stream (the plan launches its kernels one by one meanwhile)
     ctx.profile(True)
     for _ in range(args.steps):
-        step(args.precision)()
+        step()
     kms = {}
-    for k, name in ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_FORWARD, "forward"),
-                    (trx.KERNEL_BINNING, "binning")):
+    for k, name in ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_SCHEDULE, "schedule"),
+                    (trx.KERNEL_FORWARD, "forward"), (trx.KERNEL_BINNING, "binning")):
         tot, n = ctx.profile_read(k)
         kms[name] = tot / max(n, 1)
     ctx.profile(False)
@@ -107,20 +149,57 @@ def main():
     flops = float(np.sum(n_l * (n_l + 1.0) * w_l))        # triangular dl.kappa, 2 flop/MAC
     achieved = flops / (kms["forward"] * 1e-3) / 1e12
     peak = PEAKS_TFLOPS[args.precision]
-    roofline = {"bound": "mfma" if args.precision != "fp64" else "alu",
-                "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "k_fwd_mfma" if args.precision != "fp64" else "k_fwd64",
-                "kernel_ms": round(kms["forward"], 4),
+    kname = {"fp64": "k_fwd64"}.get(args.precision,
+                                    "k_fwd_mfma_persist" if "persistent=1" in variant
+                                    else "k_fwd_mfma")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": traffic_of(kname, args.precision),
+                "kernel": kname, "kernel_ms": round(kms["forward"], 4),
                 "algorithmic_tflop_per_launch": round(flops / 1e12, 4)}
 
-    # plain FP64 GPU path on the same batch (the speed-up reference)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # plain FP64 GPU path on the same batch: batched (one graph) and looped
+    # (one model per launch), separating the batching gain from precision
     fp64 = None
     if not args.no_fp64 and args.precision != "fp64":
-        ms64 = time_steps(step("fp64"), max(2, args.steps // 3), 1)
-        fp64 = {"ms_per_step": round(ms64, 3), "spectra_per_s": round(B / (ms64 * 1e-3), 1),
-                "speedup": round(ms64 / ms, 2)}
-        log(f"fp64: {ms64:.3f} ms/step")
+        p64 = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision="fp64", graph=True)
+        ms64 = time_steps(lambda: p64.launch(db), max(2, args.steps // 3), 1)
+        p64.close()
+        fp64 = {"batched_ms_per_step": round(ms64, 3),
+                "batched_spectra_per_s": round(B / (ms64 * 1e-3), 1),
+                "speedup_vs_batched": round(ms64 / ms, 2)}
+        log(f"fp64 batched: {ms64:.3f} ms/step")
+        if args.fp64_looped > 0:
+            M = min(args.fp64_looped, B)
+            pick = np.random.default_rng(1).permutation(B)[:M]
+            one = trx.Plan(ctx, T, bins, B_max=1, N_max=200, precision="fp64", graph=False,
+                           persistent=False)
+            views = [db.view(int(b)) for b in pick]
+            for v in views[:4]:
+                one.launch(v)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for v in views:
+                one.launch(v)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t1
+            one.close()
+            work = float(np.sum(n_l[pick] * w_l[pick]))
+            rate = M / sec * (work / M) / float(np.mean(n_l * w_l))
+            fp64.update({"looped_spectra_per_s": round(rate, 1),
+                         "looped_sample": f"{M} random models, one launch each, rate scaled to "
+                                          f"the batch's mean layers x window",
+                         "speedup_vs_looped": round(B / (ms * 1e-3) / rate, 2)})
+            log(f"fp64 looped: {rate:.1f} spectra/s")
 
     # oracle leg: CPU baseline rate and the error stamp of sampled models
     cpu = None
@@ -128,8 +207,6 @@ def main():
     if not args.no_cpu:
         import oracle
         from threadpoolctl import threadpool_limits
-        step(args.precision)()
-        torch.cuda.synchronize()
         gb = binned.cpu().numpy()
         order = np.argsort(batch.n_layers * (batch.wn_hi - batch.wn_lo))
         pick = [int(order[-1]), int(order[0])] + [int(i) for i in
@@ -165,7 +242,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": CONFIG_NAMES[3], "models": B, "layers": "50-200",
                       "wavenumbers": tables.n_wn, "window": "5000-40000", "absorbers": 5,
-                      "channels": bins.n, "precision": args.precision},
+                      "channels": bins.n, "precision": args.precision,
+                      "launch": "hip graph of one plan", "variant": variant},
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
            "kernel_ms": {k: round(v, 4) for k, v in kms.items()}}
     print(json.dumps(out), flush=True)

@@ -202,31 +202,41 @@ trx_status trx_chi2_grad(trx_ctx* ctx, const trx_tables* t, const trx_batch* bat
                          double* chi2, double* dT, double* dlog10vmr, double* dRp,
                          double* depth_binned, int32_t* model_status);
 
-/* ---- plans: fixed-capacity batched launches --------------------------- */
+/* ---- plans: fixed-capacity batched launches (a9) ------------------------ */
 
-/* flags */
+/* Plan flags. */
 enum {
-  TRX_PLAN_GRAPH = 1,       /* capture the launch sequence in a HIP graph */
-  TRX_PLAN_PERSISTENT = 2,  /* persistent kernel with work queues */
+  TRX_PLAN_GRAPH = 1,       /* replay the launch sequence from a HIP graph */
+  TRX_PLAN_PERSISTENT = 2,  /* allow the persistent work-queue kernel */
   TRX_PLAN_GRAD = 4         /* plan computes chi^2 and its gradient */
 };
 
-/* A plan owns device buffers for up to B_max models of at most N_max
- * layers (total layers <= B_max * N_max) and the workspace of one launch.
- * Its input buffers are exposed through trx_plan_batch; a launch reads them
- * on the context's stream. */
+/* A plan owns the workspace for up to B_max models of at most N_max layers
+ * and, for TRX_PLAN_GRAPH, the captured HIP graph of one launch: geometry,
+ * work ordering, opacity/optical depth/depth and binning (and the gradient
+ * kernels for TRX_PLAN_GRAD).  It replaces the sampler-level parallelism
+ * over live points (Parallel/MPI discussion of the Benchmarks section) by
+ * one launch over the whole live-point set.  bins may be NULL (then no
+ * binned output).  Creating a plan allocates; launching one does not. */
 trx_status trx_plan_create(trx_ctx* ctx, const trx_tables* t, const trx_bins* bins,
                            int32_t B_max, int32_t N_max, trx_precision precision,
                            int32_t flags, trx_plan** out);
 trx_status trx_plan_destroy(trx_plan* p);
-/* Fill `out` with the plan's own DEVICE input buffers (B = B_max); the
- * caller writes its models there and sets out->B before each launch. */
+/* Fill `out` with device input buffers owned by the plan (B = B_max,
+ * max_layers = N_max, layer_off sized for B_max * N_max layers; default
+ * constants He/H2 0.17, CODATA k_B and atomic mass unit, gravity 0).  Their
+ * use is optional: any batch with B <= B_max and max_layers <= N_max can be
+ * launched. */
 trx_status trx_plan_batch(trx_plan* p, trx_batch* out);
-/* Run the forward model (and the gradient for TRX_PLAN_GRAD plans) for the
- * first `B` models of the plan's input buffers.  Output pointers as in
- * trx_forward / trx_chi2_grad; obs/sigma only for gradient plans.  The
- * output pointers must be the same on every launch of a graph plan. */
-trx_status trx_plan_launch(trx_plan* p, int32_t B, double* depth_native,
+/* Run the plan on `batch` (batch->B models).  Outputs as in trx_forward and
+ * trx_chi2_grad; obs, sigma and the gradient outputs only for TRX_PLAN_GRAD
+ * plans (NULL otherwise).  A graph plan captures its graph on the first
+ * launch and again whenever an array pointer, output pointer or constant of
+ * the call differs from the captured one; batch->B travels through device
+ * memory, so a new B alone replays the same graph.  While trx_profile is
+ * enabled the same kernels are launched one by one instead, so that each
+ * is timed. */
+trx_status trx_plan_launch(trx_plan* p, const trx_batch* batch, double* depth_native,
                            double* depth_binned, int32_t* model_status,
                            const double* obs, const double* sigma, double* chi2,
                            double* dT, double* dlog10vmr, double* dRp);
@@ -254,12 +264,20 @@ trx_status trx_profile_read(trx_ctx* ctx, int32_t kernel, double* total_ms, int3
 
 /* ---- tuning ------------------------------------------------------------ */
 
-/* Time the kernel variants of `precision` on the plan's current inputs
- * (first B models) and keep the fastest for this plan; if cache_json is not
- * NULL, the choice is also recorded there under a key of the device name
- * and shape bucket, and read back by later plans of the same bucket. */
-trx_status trx_autotune(trx_plan* p, int32_t B, const char* cache_json);
-/* Current variant of a plan as a short printable string. */
+/* Choose the plan's kernel variant (persistent or one workgroup per item;
+ * the model-group size of the persistent work order) for batches like
+ * `batch`.  If cache_json names a file holding a choice for this device,
+ * precision and shape bucket (B_max, N_max, grid size, absorbers), that
+ * choice is taken without timing; otherwise every variant is run on `batch`
+ * (outside any graph, outputs discarded), the fastest mean of three timed
+ * runs is kept and, if cache_json is not NULL, written to the file (a flat
+ * JSON object of strings).  Synchronises the context's stream. */
+trx_status trx_autotune(trx_plan* p, const trx_batch* batch, const char* cache_json);
+/* Set the variant directly from a string as returned by trx_plan_describe
+ * ("persistent=1 group=32"; unknown keys are an error). */
+trx_status trx_plan_set_variant(trx_plan* p, const char* variant);
+/* Current variant of a plan as a short printable string (owned by the
+ * plan, valid until the next call on it). */
 const char* trx_plan_describe(const trx_plan* p);
 
 #ifdef __cplusplus

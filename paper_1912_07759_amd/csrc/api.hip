@@ -393,6 +393,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   f.mspan = sb.mspan;
   f.qcount = sb.qcount;
   f.persistent = persistent ? 1 : 0;
+  f.group = rc.group;
   {
     ProfScope ps(c, TRX_KERNEL_FORWARD);
     if (precision == TRX_FP64) {

@@ -76,6 +76,7 @@ struct Smem {
   float chi[TRX_MAX_ABSORBERS];
   float ciaw[TRX_MAX_CIA];
   int32_t items[kChunk];
+  int32_t spans[kChunk];
   int32_t base;
 };
 
@@ -395,27 +396,36 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
     const int q = (q0 + k) % kQueues;
     const int nsq = q < nspans ? (nspans - q + kQueues - 1) / kQueues : 0;
     const int total = nsq * B;
+    // items of queue q: model groups of G (in the order of order[]), within a
+    // group the queue's spans in increasing order, within a span the group's
+    // models; G = B gives plain span-major order
+    const int G = a.group > 0 && a.group < B ? a.group : B;
     while (true) {
       if (threadIdx.x == 0) sm.base = total > 0 ? atomicAdd(&a.qcount[q], kChunk) : 0;
       __syncthreads();
       const int base = sm.base;
       if (threadIdx.x < kChunk) {
         const int i = base + threadIdx.x;
-        int code = -1;
+        int code = -1, sp = 0;
         if (i < total) {
-          const int ls = i / B, slot = i - ls * B;
-          const int sp = ls * kQueues + q;
+          const int g = i / (nsq * G);
+          const int rem = i - g * nsq * G;
+          const int gm = min(G, B - g * G);
+          const int ls = rem / gm;
+          const int slot = g * G + (rem - ls * gm);
+          sp = ls * kQueues + q;
           const int bm = a.order[slot];
           const int2 r = a.mspan[bm];
           if (sp >= r.x && sp < r.y) code = bm;
         }
         sm.items[threadIdx.x] = code;
+        sm.spans[threadIdx.x] = sp;
       }
       __syncthreads();
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW>(a, bm, ((base + c) / B) * kQueues + q, sm);
+        if (bm >= 0) process<MODE, RBW>(a, bm, sm.spans[c], sm);
       }
       __syncthreads();
     }

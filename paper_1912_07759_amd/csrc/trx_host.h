@@ -57,6 +57,7 @@ struct RunConfig {
   int span_cols = kSpanCols;  // columns per (model, span) work item
   int nrb_max = 7;            // ray-block capacity of the matrix-core kernel
   int persistent = 1;         // 1: persistent grid with work queues
+  int group = 0;              // models per item group of the persistent order (0: all)
 };
 
 // Scheduling buffers of one launch (device memory).

@@ -205,13 +205,15 @@ struct FwdArgs {
   double* depth_native;   // [B][n_wn] or null
   void* aws;              // [B][n_wn] atmospheric part a/Rs^2 (double for FP64, else float)
   int32_t* model_status;  // [B]
-  // persistent scheduling: items (span, model) of queue q are the spans
-  // s = q (mod kQueues) in increasing order, each with the models in order[]
-  // (layer count descending); workgroups pop chunks of items with atomics.
+  // persistent scheduling: queue q holds the items (model, span) of the
+  // spans s = q (mod kQueues); the models in order[] (layer count
+  // descending) are taken in groups of `group`, each group over the queue's
+  // spans in increasing order; workgroups pop chunks of items with atomics.
   const int32_t* order;   // [B] model indices, longest first
   const int2* mspan;      // [B] span range per model
   int32_t* qcount;        // [kQueues] item counters, zeroed by the schedule kernel
   int32_t persistent;     // 1: persistent grid, 0: one workgroup per (model, span)
+  int32_t group;          // models per item group of the persistent order (0: all)
 };
 
 void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* order, int32_t* qcount,

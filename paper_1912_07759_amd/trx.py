@@ -29,7 +29,8 @@ EXPORTS = ["trx_create", "trx_destroy", "trx_last_error", "trx_set_stream",
            "trx_synchronize", "trx_tables_create", "trx_tables_destroy",
            "trx_bins_create", "trx_bins_destroy", "trx_forward", "trx_chi2_grad",
            "trx_plan_create", "trx_plan_destroy", "trx_plan_batch", "trx_plan_launch",
-           "trx_autotune", "trx_plan_describe", "trx_profile", "trx_profile_read"]
+           "trx_autotune", "trx_plan_set_variant", "trx_plan_describe", "trx_profile",
+           "trx_profile_read"]
 
 KERNEL_GEOMETRY, KERNEL_FORWARD, KERNEL_BINNING, KERNEL_ADJOINT, KERNEL_GEOM_ADJ, \
     KERNEL_SCHEDULE = range(6)
@@ -220,12 +221,36 @@ class DeviceBatch:
         return cls(b.n_layers, b.T, b.p_bot, b.p_top, b.log10_vmr, b.Rp, b.Rs, b.GM,
                    b.wn_lo, b.wn_hi, b.he_h2, b.k_B, b.amu, b.gravity, device, max_layers)
 
+    @property
+    def n_abs(self):
+        return int(self.log10_vmr.shape[1]) if self.log10_vmr.dim() == 2 else 0
+
+    def view(self, b):
+        """Model b alone, sharing this batch's device arrays."""
+        return _ModelView(self, b)
+
     def cstruct(self, B=None):
         return BatchC(self.B if B is None else B, self.max_layers, _ptr(self.n_layers),
                       _ptr(self.layer_off), _ptr(self.T), _ptr(self.p_bot), _ptr(self.p_top),
                       _ptr(self.log10_vmr), _ptr(self.Rp), _ptr(self.Rs), _ptr(self.GM),
                       _ptr(self.wn_lo), _ptr(self.wn_hi), float(self.he_h2), float(self.k_B),
                       float(self.amu), int(self.gravity))
+
+
+class _ModelView:
+    """Model b of a DeviceBatch as a batch of one (pointer offsets into the
+    parent's device arrays; layer offsets stay absolute)."""
+
+    def __init__(self, db, b):
+        self.db, self.b, self.B = db, int(b), 1
+
+    def cstruct(self):
+        d, b = self.db, self.b
+        at = lambda t, k: ctypes.c_void_p(t.data_ptr() + k * t.element_size())
+        return BatchC(1, d.max_layers, at(d.n_layers, b), at(d.layer_off, b), _ptr(d.T),
+                      at(d.p_bot, b), at(d.p_top, b), at(d.log10_vmr, b * d.n_abs),
+                      at(d.Rp, b), at(d.Rs, b), at(d.GM, b), at(d.wn_lo, b), at(d.wn_hi, b),
+                      float(d.he_h2), float(d.k_B), float(d.amu), int(d.gravity))
 
 
 def _prec(p):
@@ -277,3 +302,79 @@ def chi2_grad(ctx, tables, batch, bins, obs, sigma, precision=FP32, recompute=Tr
                                   _ptr(out["dT"]), _ptr(out["dlog10_vmr"]), _ptr(out["dRp"]),
                                   _ptr(out["binned"]), _ptr(out["status"])))
     return out
+
+
+class Plan:
+    """trx_plan_*: a batched launch for up to B_max models of at most N_max
+    layers, replayed from a HIP graph when ``graph`` is set.
+
+    Outputs default to plan-owned tensors of B_max rows (the first B rows are
+    returned), so that repeated launches keep the output pointers a graph
+    was captured with."""
+
+    def __init__(self, ctx, tables, bins, B_max, N_max, precision=FP32, graph=True,
+                 persistent=True, grad=False):
+        self.ctx, self.tables, self.bins = ctx, tables, bins
+        self.B_max, self.N_max = int(B_max), int(N_max)
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_PERSISTENT if persistent else 0) | \
+            (PLAN_GRAD if grad else 0)
+        h = ctypes.c_void_p()
+        ctx.check(lib().trx_plan_create(ctx.h, tables.h, bins.h if bins is not None else None,
+                                        self.B_max, self.N_max, _prec(precision), flags,
+                                        ctypes.byref(h)))
+        self.h = h
+        dev = torch.device("cuda", ctx.device)
+        self.out_status = torch.empty(self.B_max, dtype=torch.int32, device=dev)
+        self.out_binned = None if bins is None else torch.empty(
+            (self.B_max, bins.n), dtype=torch.float64, device=dev)
+        self.out_native = None
+
+    def launch(self, batch, native=False, binned=True, out_native=None, out_binned=None,
+               out_status=None):
+        """trx_plan_launch on ``batch`` (a DeviceBatch).  Returns (depth_native
+        or None, depth_binned or None, model_status), each with B rows."""
+        B = batch.B
+        if native and out_native is None:
+            if self.out_native is None:
+                self.out_native = torch.full((self.B_max, self.tables.n_wn), float("nan"),
+                                             dtype=torch.float64, device=self.out_status.device)
+            out_native = self.out_native
+        if not native:
+            out_native = None
+        if binned and out_binned is None:
+            out_binned = self.out_binned
+        if not binned:
+            out_binned = None
+        if out_status is None:
+            out_status = self.out_status
+        self.ctx.bind_stream()
+        bc = batch.cstruct()
+        self.ctx.check(lib().trx_plan_launch(self.h, ctypes.byref(bc), _ptr(out_native),
+                                             _ptr(out_binned), _ptr(out_status), None, None,
+                                             None, None, None, None))
+        cut = lambda t: None if t is None else t[:B]
+        return cut(out_native), cut(out_binned), out_status[:B]
+
+    def autotune(self, batch, cache_json=None):
+        self.ctx.bind_stream()
+        bc = batch.cstruct()
+        path = None if cache_json is None else os.fsencode(cache_json)
+        self.ctx.check(lib().trx_autotune(self.h, ctypes.byref(bc), path))
+        return self.describe()
+
+    def set_variant(self, variant):
+        self.ctx.check(lib().trx_plan_set_variant(self.h, variant.encode()))
+
+    def describe(self):
+        return lib().trx_plan_describe(self.h).decode()
+
+    def close(self):
+        if self.h:
+            lib().trx_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
