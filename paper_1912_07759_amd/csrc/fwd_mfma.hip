@@ -47,6 +47,8 @@ constexpr int kCols = 64;               // columns per workgroup
 // staged rows: the cross-section corners, then the CIA nodes
 constexpr int kRows = 96;
 static_assert(kRows >= kMaxU + kMaxV, "block staging must fit");
+static_assert(TRX_MAX_LAYERS_MFMA % 32 == 0 && TRX_MAX_LAYERS_MFMA <= 64 * kWaves,
+              "a thread copies at most two record halves and one slot pair");
 constexpr int kInFlight = 16;           // table loads per lane issued together
 constexpr int kChunk = 8;               // items popped per atomic (persistent launch)
 
@@ -66,10 +68,14 @@ struct Cfg {
 template <int MODE, int RBW>
 struct Smem {
   float rows[kRows][kCols];
-  __attribute__((aligned(16))) uint32_t frag[Cfg<MODE>::frag_dw];
-  float part[kWaves * RBW][kCols];
+  // B-operand fragments of the current layer block; after the last block
+  // the same space holds the per-ray-block depth partials
+  union {
+    __attribute__((aligned(16))) uint32_t frag[2][Cfg<MODE>::frag_dw];   // by layer-block parity
+    float part[kWaves * RBW][kCols];
+  };
   // per-item copies of the model's records (read with uniform LDS addresses)
-  __attribute__((aligned(16))) float lw[TRX_MAX_LAYERS_MFMA][8];   // layer weights
+  __attribute__((aligned(16))) float lw[TRX_MAX_LAYERS_MFMA][8];   // layer weights, [7] = A_l/Rs^2
   int2 sl[TRX_MAX_LAYERS_MFMA];                                     // corner slots
   int32_t ids[kRows];                                               // staged corner ids
   int32_t tids[kRows];                                              // staged CIA nodes
@@ -139,6 +145,14 @@ __device__ inline uint32_t bf16_pair(float a, float b) {
 __device__ inline float bf16_lo_f(uint32_t p) { return __uint_as_float(p << 16); }
 __device__ inline float bf16_hi_f(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
 
+// Ray block r (0..RBW-1) of a wave: w, then 7 - w, so that the long
+// triangle rows (low ray blocks) and the short ones are dealt evenly.
+template <int RBW>
+__device__ __forceinline__ int own_rb(int wave, int r) {
+  return r == 0 ? wave : 2 * kWaves - 1 - wave;
+}
+static_assert(TRX_MAX_LAYERS_MFMA <= 32 * 2 * kWaves, "two ray blocks per wave cover every ray");
+
 // One work item: model b, columns [64 span, 64 span + 64).  Called by all
 // threads of the workgroup (every early return is uniform).
 // RBW: ray blocks per wave (ray blocks / 4, rounded up).
@@ -168,15 +182,28 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
   const int W = tb.n_wn;
   const bool has_cia = tb.n_cia > 0;
 
+  // Rayleigh sum over all species, eight loads in flight (species indexes
+  // past the last are clamped and their terms skipped)
   float R = 0.f;
-  if (tb.has_rayleigh)
-    for (int s = 0; s < tb.n_abs + 2; ++s) R = fmaf(hd->chi_s32[s], tb.ray32[(int64_t)s * W + cc], R);
+  if (tb.has_rayleigh) {
+    const int ns = tb.n_abs + 2;
+    const __amdgpu_buffer_rsrc_t rr =
+        __builtin_amdgcn_make_buffer_rsrc((void*)tb.ray32, (short)0, ns * W * 4, kRsrcWord3);
+    for (int s0 = 0; s0 < ns; s0 += 8) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rr, cc * 4, min(s0 + k, ns - 1) * W * 4, 0));
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (s0 + k < ns) R = fmaf(hd->chi_s32[s0 + k], v[k], R);
+    }
+  }
 
   const float* lw = reinterpret_cast<const float*>(slab + L.off_lw32);
   const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
   const KBlk* kblk = reinterpret_cast<const KBlk*>(slab + L.off_kblk);
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
-  const float* Aw = reinterpret_cast<const float*>(slab + L.off_A32);
   const uint8_t* frag = slab + L.off_dl;
   const int nkb = hd->nkb, nrb = hd->nrb;
   const int NKB = L.NKB;
@@ -199,12 +226,40 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
   // whole-model staging when the distinct corners fit, else per layer block
   const bool mstage = ml->nU + ml->nV <= kRows;
   const int slot_off = mstage ? 2 : 4;
-  for (int e = tid; e < N * 8; e += 64 * kWaves) (&sm.lw[0][0])[e] = lw[e];
-  for (int e = tid; e < N; e += 64 * kWaves) sm.sl[e] = *reinterpret_cast<const int2*>(lid + 8 * e + slot_off);
-  if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
-  if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w32[tid];
+  // the model's records (and its corner lists) into LDS: all loads of a
+  // thread are issued before its stores.  The 32 nrb >= N records copied
+  // include the zero records of the padding layers, so every layer and ray
+  // of the last blocks reads defined values.
+  {
+    const int nrec = 32 * nrb;
+    const float4* src = reinterpret_cast<const float4*>(lw);
+    float4* dst = reinterpret_cast<float4*>(&sm.lw[0][0]);
+    const int n4 = 2 * nrec;
+    const int e0 = tid, e1 = tid + 64 * kWaves;
+    const float4 r0 = e0 < n4 ? src[e0] : float4{};
+    const float4 r1 = e1 < n4 ? src[e1] : float4{};
+    const int2 s0 = tid < nrec ? *reinterpret_cast<const int2*>(lid + 8 * tid + slot_off) : int2{};
+    int u0 = 0, u1 = 0;
+    if (mstage) {
+      if (tid < ml->nU) u0 = ml->ids[tid];
+      if (tid < ml->nV) u1 = ml->tids[tid];
+    }
+    if (e0 < n4) dst[e0] = r0;
+    if (e1 < n4) dst[e1] = r1;
+    if (tid < nrec) sm.sl[tid] = s0;
+    if (mstage) {
+      if (tid < ml->nU) sm.ids[tid] = u0;
+      if (tid < ml->nV) sm.tids[tid] = u1;
+    }
+    if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
+    if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w32[tid];
+  }
   __syncthreads();
-  if (mstage) stage(ml->ids, ml->nU, ml->tids, ml->nV);
+  if (mstage) {
+    stage_rows(tb.xsec32, abs_stride, W, cc, sm.ids, ml->nU, sm.chi, tb.n_abs, rows, wave, lane);
+    crows = rows + ml->nU * kCols;
+    if (has_cia) stage_rows(tb.cia32, cia_stride, W, cc, sm.tids, ml->nV, sm.ciaw, tb.n_cia, crows, wave, lane);
+  }
 
   f32x16 acc[RBW][2];
 #pragma unroll
@@ -213,51 +268,86 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
     acc[r][1] = f32x16{};
   }
 
+  // path-length (A operand) fragments of this wave's ray blocks: those of
+  // block kb + 1 are loaded right after the products of block kb, so their
+  // latency overlaps the opacity of kb + 1
+  constexpr int kAW = MODE == TRX_FP32 ? 4 : C::npc;   // 16-byte words per lane
+  u32x4 Anx[RBW][kAW];
+  auto load_A = [&](int kb) {
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+      const int rb = own_rb<RBW>(wave, r);
+      if (rb < nrb && kb >= 2 * rb) {
+        if constexpr (MODE == TRX_FP32) {
+          const u32x4* fp = reinterpret_cast<const u32x4*>(frag + ((int64_t)frag_index(rb, kb, NKB) * 2 * 512 +
+                                                                   lane * 8) * 4);
+          Anx[r][0] = fp[0];
+          Anx[r][1] = fp[1];
+          Anx[r][2] = fp[128];
+          Anx[r][3] = fp[129];
+        } else {
+          const u32x4* fp = reinterpret_cast<const u32x4*>(
+              frag + ((int64_t)frag_index(rb, kb, NKB) * C::npc * 512 + lane * 8) * 2);
+#pragma unroll
+          for (int p = 0; p < C::npc; ++p) Anx[r][p] = fp[p * 64];
+        }
+      }
+    }
+  };
+  load_A(0);
+  if (mstage) __syncthreads();   // staged rows visible
+
   for (int kb = 0; kb < nkb; ++kb) {
     if (!mstage) {
+      // all waves are past the opacity of block kb - 1 (barrier below)
       const KBlk* kd = kblk + kb;
       stage(kd->ids, kd->nU, kd->tids, kd->nV);
+      __syncthreads();
     }
-    __syncthreads();
+    uint32_t* fr = sm.frag[kb & 1];
 
-    // 1. opacity of layers 16 kb + 4 wave + jj, one column per lane; the
-    // corner slots are uniform, and values are reused while consecutive
-    // layers share their bracket
+    // 1. opacity of layers 16 kb + 4 wave + jj, one column per lane: the
+    // slot words and weights of the wave's 4 layers first, then all their
+    // row reads, then the arithmetic (two LDS round trips)
     float kap[4];
     {
-      uint32_t psl = 0xffffffffu, pcl = 0xffffffffu;
-      float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, c0 = 0.f, c1 = 0.f;
+      const int l0 = 16 * kb + 4 * wave;
+      uint32_t sl[4], cl[4];
+      float4 wa[4];
+      float3 wb[4];
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const int l = 16 * kb + 4 * wave + jj;
-        float k = 0.f;
-        if (l < N) {
-          const float* w = sm.lw[l];
-          const uint32_t sl = __builtin_amdgcn_readfirstlane((uint32_t)sm.sl[l].x);
-          if (sl != psl) {
-            m0 = rows[(sl & 0xff) * kCols + lane];
-            m1 = rows[((sl >> 8) & 0xff) * kCols + lane];
-            m2 = rows[((sl >> 16) & 0xff) * kCols + lane];
-            m3 = rows[(sl >> 24) * kCols + lane];
-            psl = sl;
-          }
-          k = w[0] * m0;
-          k = fmaf(w[1], m1, k);
-          k = fmaf(w[2], m2, k);
-          k = fmaf(w[3], m3, k);
-          k = fmaf(w[4], R, k);
-          if (has_cia) {
-            const uint32_t cl = __builtin_amdgcn_readfirstlane((uint32_t)sm.sl[l].y);
-            if (cl != pcl) {
-              c0 = crows[(cl & 0xff) * kCols + lane];
-              c1 = crows[((cl >> 8) & 0xff) * kCols + lane];
-              pcl = cl;
-            }
-            k = fmaf(w[5], c0, k);
-            k = fmaf(w[6], c1, k);
-          }
+        const int2 t = sm.sl[l0 + jj];
+        sl[jj] = __builtin_amdgcn_readfirstlane((uint32_t)t.x);
+        cl[jj] = __builtin_amdgcn_readfirstlane((uint32_t)t.y);
+        wa[jj] = *reinterpret_cast<const float4*>(&sm.lw[l0 + jj][0]);
+        wb[jj] = *reinterpret_cast<const float3*>(&sm.lw[l0 + jj][4]);
+      }
+      float m[4][4], c[4][2];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        m[jj][0] = rows[(sl[jj] & 0xff) * kCols + lane];
+        m[jj][1] = rows[((sl[jj] >> 8) & 0xff) * kCols + lane];
+        m[jj][2] = rows[((sl[jj] >> 16) & 0xff) * kCols + lane];
+        m[jj][3] = rows[(sl[jj] >> 24) * kCols + lane];
+        if (has_cia) {
+          c[jj][0] = crows[(cl[jj] & 0xff) * kCols + lane];
+          c[jj][1] = crows[((cl[jj] >> 8) & 0xff) * kCols + lane];
         }
-        kap[jj] = k;
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        float k = wa[jj].x * m[jj][0];
+        k = fmaf(wa[jj].y, m[jj][1], k);
+        k = fmaf(wa[jj].z, m[jj][2], k);
+        k = fmaf(wa[jj].w, m[jj][3], k);
+        k = fmaf(wb[jj].x, R, k);
+        if (has_cia) {
+          k = fmaf(wb[jj].y, c[jj][0], k);
+          k = fmaf(wb[jj].z, c[jj][1], k);
+        }
+        // layers past N have zero weights and slots (LDS rows are finite)
+        kap[jj] = l0 + jj < N ? k : 0.f;
       }
     }
     const int cb = lane >> 5, lc = lane & 31;
@@ -266,7 +356,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         const int k = 4 * wave + jj;
-        sm.frag[(cb * 8 + (k >> 1)) * 64 + 32 * (k & 1) + lc] = __float_as_uint(kap[jj]);
+        fr[(cb * 8 + (k >> 1)) * 64 + 32 * (k & 1) + lc] = __float_as_uint(kap[jj]);
       }
     } else {
       // 32x32x16: lane 32 (k/8) + col%32 holds layers 8 (k/8) .. +7 packed
@@ -277,7 +367,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
 #pragma unroll
       for (int p = 0; p < C::npc; ++p) {
         const uint32_t q0 = bf16_pair(x0, x1), q1 = bf16_pair(x2, x3);
-        uint32_t* dst = sm.frag + ((p * 2 + cb) * 64 + fl) * 4 + d0;
+        uint32_t* dst = fr + ((p * 2 + cb) * 64 + fl) * 4 + d0;
         *reinterpret_cast<uint2*>(dst) = make_uint2(q0, q1);
         x0 -= bf16_lo_f(q0);
         x1 -= bf16_hi_f(q0);
@@ -285,72 +375,86 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
         x3 -= bf16_hi_f(q1);
       }
     }
+    // one barrier per layer block: the fragments are double-buffered, and a
+    // wave that rewrites this buffer (block kb + 2) has passed the barrier of
+    // block kb + 1, which every wave reaches only after its products of kb
     __syncthreads();
 
-    // 2. matrix products for this wave's ray blocks rb = wave + 4 r
+    // 2. matrix products for this wave's ray blocks (B fragments read once
+    // for both)
+    bool any = false;
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
-      const int rb = wave + kWaves * r;
-      if (rb < nrb && kb >= 2 * rb) {
-        if constexpr (MODE == TRX_FP32) {
-          const float* fp = reinterpret_cast<const float*>(frag) +
-                            (int64_t)frag_index(rb, kb, NKB) * 2 * 512 + lane * 8;
-          const float4 h0 = *reinterpret_cast<const float4*>(fp);
-          const float4 h1 = *reinterpret_cast<const float4*>(fp + 4);
-          const float4 l0 = *reinterpret_cast<const float4*>(fp + 512);
-          const float4 l1 = *reinterpret_cast<const float4*>(fp + 516);
-          const float ah[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
-          const float al[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+      const int rb = own_rb<RBW>(wave, r);
+      any |= rb < nrb && kb >= 2 * rb;
+    }
+    if (any) {
+      if constexpr (MODE == TRX_FP32) {
+        float bk[2][8];
 #pragma unroll
-          for (int tcb = 0; tcb < 2; ++tcb) {
+        for (int tcb = 0; tcb < 2; ++tcb)
 #pragma unroll
-            for (int st = 0; st < 8; ++st) {
-              const float bk = __uint_as_float(sm.frag[(tcb * 8 + st) * 64 + lane]);
-              acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[st], bk, acc[r][tcb], 0, 0, 0);
-              acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x2f32(al[st], bk, acc[r][tcb], 0, 0, 0);
+          for (int st = 0; st < 8; ++st) bk[tcb][st] = __uint_as_float(fr[(tcb * 8 + st) * 64 + lane]);
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+          const int rb = own_rb<RBW>(wave, r);
+          if (rb < nrb && kb >= 2 * rb) {
+#pragma unroll
+            for (int tcb = 0; tcb < 2; ++tcb) {
+#pragma unroll
+              for (int st = 0; st < 8; ++st) {
+                const float ah = __uint_as_float(Anx[r][st >> 2][st & 3]);
+                const float al = __uint_as_float(Anx[r][2 + (st >> 2)][st & 3]);
+                acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah, bk[tcb][st], acc[r][tcb], 0, 0, 0);
+                acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x2f32(al, bk[tcb][st], acc[r][tcb], 0, 0, 0);
+              }
             }
           }
-        } else {
-          const u32x4* fp = reinterpret_cast<const u32x4*>(
-              frag + ((int64_t)frag_index(rb, kb, NKB) * C::npc * 512 + lane * 8) * 2);
-          u32x4 Ap[C::npc];
+        }
+      } else {
+        u32x4 Bp[2][C::npc];
 #pragma unroll
-          for (int p = 0; p < C::npc; ++p) Ap[p] = fp[p * 64];
+        for (int tcb = 0; tcb < 2; ++tcb)
 #pragma unroll
-          for (int tcb = 0; tcb < 2; ++tcb) {
-            u32x4 Bp[C::npc];
+          for (int p = 0; p < C::npc; ++p)
+            Bp[tcb][p] = *reinterpret_cast<const u32x4*>(fr + ((p * 2 + tcb) * 64 + lane) * 4);
 #pragma unroll
-            for (int p = 0; p < C::npc; ++p)
-              Bp[p] = *reinterpret_cast<const u32x4*>(sm.frag + ((p * 2 + tcb) * 64 + lane) * 4);
+        for (int r = 0; r < RBW; ++r) {
+          const int rb = own_rb<RBW>(wave, r);
+          if (rb < nrb && kb >= 2 * rb) {
 #pragma unroll
-            for (int pa = 0; pa < C::npc; ++pa) {
+            for (int tcb = 0; tcb < 2; ++tcb) {
 #pragma unroll
-              for (int pb = 0; pb + pa < C::npc; ++pb)
-                acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Ap[pa]),
-                                                                      __builtin_bit_cast(bf16x8, Bp[pb]),
-                                                                      acc[r][tcb], 0, 0, 0);
+              for (int pa = 0; pa < C::npc; ++pa) {
+#pragma unroll
+                for (int pb = 0; pb + pa < C::npc; ++pb)
+                  acc[r][tcb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                      __builtin_bit_cast(bf16x8, Anx[r][pa]), __builtin_bit_cast(bf16x8, Bp[tcb][pb]),
+                      acc[r][tcb], 0, 0, 0);
+              }
             }
           }
         }
       }
     }
-    __syncthreads();   // fragments (and block-staged rows) are rewritten next
+    if (kb + 1 < nkb) load_A(kb + 1);
   }
   (void)kblk;
+  __syncthreads();   // the partials below reuse the fragment space
 
   // depth: accumulator register q holds ray 8 (q/4) + 4 (lane/32) + q%4
   const float nl2e = -1.4426950408889634f;
   const int hl = lane >> 5;
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
-    const int rb = wave + kWaves * r;
+    const int rb = own_rb<RBW>(wave, r);
     if (rb < nrb) {
 #pragma unroll
       for (int tcb = 0; tcb < 2; ++tcb) {
         float s = 0.f;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-          const float A = Aw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)];
+          const float A = sm.lw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)][7];
           s = fmaf(A, 1.f - __builtin_amdgcn_exp2f(nl2e * acc[r][tcb][q]), s);
         }
         s += __shfl_xor(s, 32, 64);
@@ -387,7 +491,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
 // other queues when its own is drained.  Every workgroup leaves once all
 // queues are drained.
 template <int MODE, int RBW>
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_fwd_mfma_persist(FwdArgs a) {
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_mfma_persist(FwdArgs a) {
   __shared__ Smem<MODE, RBW> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int nspans = (a.tab.n_wn + kCols - 1) / kCols;

@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         lw64[8 * l + q] = w[q];
         lw32[8 * l + q] = (float)(q >= 5 ? w[q] / kCiaScale32 : w[q]);
       }
+      lw32[8 * l + 7] = (float)A;   // FP32 records carry the ray's annulus weight
       lid[8 * l] = iT * tb.n_P + iP;
       lid[8 * l + 1] = iC;
     } else {
