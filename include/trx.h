@@ -82,7 +82,11 @@ enum {
   TRX_MODEL_BAD_PROFILE = 2,   /* n_layers out of range, T <= 0, Rp/Rs/GM <= 0,
                                   p_bot <= p_top, non-finite input */
   TRX_MODEL_BAD_WINDOW = 4,    /* window empty or outside the grid */
-  TRX_MODEL_NONFINITE = 8      /* a non-finite value appeared in the outputs */
+  TRX_MODEL_NONFINITE = 8,     /* a non-finite value appeared in the outputs */
+  TRX_MODEL_GRAD_UNSUPPORTED = 16 /* trx_chi2_grad: the model has more distinct
+                                     table corners and CIA nodes than the
+                                     gradient kernel stages (96); its gradient
+                                     outputs are NaN */
 };
 
 /* Limits of this build. */

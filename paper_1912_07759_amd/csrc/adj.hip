@@ -1,0 +1,475 @@
+// Adjoint of chi^2 = sum_c ((D_c - O_c)/sigma_c)^2 (a8) with respect to the
+// per-layer temperatures, the log10 mixing ratios and Rp, in recompute mode:
+// the opacity and optical depth of the forward pass are not stored but
+// recomputed per (model, 64-column span) work item.
+//
+// Reverse of the forward steps, per model b and native point i:
+//   Dbar_c = 2 (D_c - O_c)/sigma_c^2, Dbar_i = sum_c Dbar_c w_ci / sum_i' w_ci'
+//   (binning, Binning subsection);
+//   D_i = Rp^2/Rs^2 + sum_j A_j (1 - e^{-tau_ij}), A_j = 2 (Rp + z_j)(h_{j+1} -
+//   h_j)/Rs^2 (transit-depth equations): Abar_j = sum_i Dbar_i (1 - e^{-tau}),
+//   taubar_ij = Dbar_i A_j e^{-tau_ij};
+//   tau = dl kappa (eq. tot_opt_dpth): kappabar = dl^T taubar, and the
+//   path-length cotangent dlbar = taubar kappa^T is never formed: its
+//   contractions with the chord derivatives are taken per column,
+//     zbar_j  += sum_i taubar_ij (Fz kappa)_ji,   Fz = d dl / d z_j,
+//     Rpbar   += sum_i sum_j taubar_ij (FR kappa)_ji,   FR = d dl / d Rp,
+//     hbar_{k+1} += sum_i (kappa_ki - kappa_{k+1,i}) (Gh^T taubar)_ki,
+//   with Gh_{j,k+1} = d(2 q_j(h_{k+1}))/dh_{k+1} (the shell boundary h_m
+//   enters dl[j, m-1] with + and dl[j, m] with -);
+//   kappa (equations opt_dpth, cia_opt_dpth, contrib; Opacities section):
+//     Tbar_k += sum_i kappabar_ki dkappa_ki/dT_k (bracket slopes and
+//     d rho/dT from the derivative records), and the mixing-ratio adjoints
+//     through the mixed corner rows, the Rayleigh sum and the CIA sums.
+// A last per-model kernel walks the annulus weights, the shell boundaries,
+// the altitude recursion (Forward Models section) and the chemistry (fill
+// gases follow the sum constraint; log10 parameters) in reverse, in FP64.
+//
+// The item kernel works in FP32 (FP32 tables, derivative matrices rounded
+// from FP64) and accumulates per-model sums in FP64 atomics; the result is
+// held to 1e-4 of the FP64 reference gradient.
+#include "trx_internal.h"
+#include "stage.h"
+
+namespace trx {
+
+namespace {
+
+using stage::kRsrcWord3;
+using stage::stage_rows;
+constexpr int kWaves = 4;
+constexpr int kCols = 64;
+constexpr int kRows = 96;
+constexpr int kRayRegs = TRX_MAX_LAYERS_MFMA / kWaves;   // rays per wave
+static_assert(stage::kWaves == kWaves && stage::kCols == kCols, "staging shape");
+static_assert(kRows >= kMaxU + kMaxV, "staging capacity");
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---- chi^2 and the per-point cotangent Dbar_i ---------------------------
+__global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
+  const int b = blockIdx.x;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if (b >= B) return;
+  const uint8_t* slab = a.ws + (int64_t)b * a.L.slab;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
+  double* acc = a.acc + (int64_t)b * a.G.n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < a.G.n; e += 256) acc[e] = 0.0;
+  const int N = hd->n;
+  if (N == 0) {
+    if (tid == 0) a.chi2[b] = __builtin_nan("");
+    return;
+  }
+  const int lo = hd->lo, hi = hd->hi, W = a.tab.n_wn;
+  float* dbar = a.dbar + (int64_t)b * W;
+  for (int i = lo + tid; i < hi; i += 256) dbar[i] = 0.f;
+  __syncthreads();
+  __shared__ double s_part[2][kWaves];
+  double c2 = 0.0, sd = 0.0;
+  for (int c = wave; c < a.n_ch; c += kWaves) {
+    const int c0 = a.ch_i0[c];
+    const int i0 = max(c0, lo), i1 = min(a.ch_i1[c], hi);
+    const double* w = a.ch_w + a.ch_off[c] - c0;
+    double ws = 0.0;
+    for (int i = i0 + lane; i < i1; i += 64) ws += w[i];
+    ws = wave_sum_d(ws);
+    const double sg = a.sigma[c];
+    const double r = (a.binned[(int64_t)b * a.n_ch + c] - a.obs[(int64_t)b * a.n_ch + c]) / sg;
+    const double db = 2.0 * r / sg;
+    c2 += r * r;
+    sd += db;
+    const double coef = db / ws;
+    for (int i = i0 + lane; i < i1; i += 64) atomicAdd(&dbar[i], (float)(coef * w[i]));
+  }
+  if (lane == 0) {
+    s_part[0][wave] = c2;
+    s_part[1][wave] = sd;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t2 = 0.0, ts = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+      t2 += s_part[0][w];
+      ts += s_part[1][w];
+    }
+    a.chi2[b] = t2;
+    // D_i = (Rp/Rs)^2 + ...: sum_i Dbar_i = sum_c Dbar_c
+    acc[a.G.o_Rp] = ts * 2.0 * hd->Rp * hd->inv_Rs2;
+  }
+}
+
+// ---- per (model, span) recompute and backward ---------------------------
+struct ItemLds {
+  float* rows;   // [kRows][64] mixed corner rows, then CIA node rows
+  float* kt;     // [NP][64] kappa, later taubar
+  float* sh;     // [kRows][64] adjoints of the mixed rows
+  float* rh;     // [64] adjoint of the Rayleigh sum
+  float* lw;     // [NP][8] layer records
+  float* lwd;    // [NP][8] d(records)/dT
+  int2* sl;      // [NP] model-list slots
+  int32_t* ids;  // [kRows]
+  int32_t* tids; // [kRows]
+  float* chi;    // [TRX_MAX_ABSORBERS]
+  float* ciaw;   // [TRX_MAX_CIA]
+};
+
+__host__ __device__ inline size_t carve(const Layout& L, unsigned char* base, ItemLds* out) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base ? base + o : nullptr;
+    o += (bytes + 15) / 16 * 16;
+    return p;
+  };
+  const int NP = L.NP;
+  ItemLds s;
+  s.rows = (float*)take((size_t)kRows * kCols * 4);
+  s.kt = (float*)take((size_t)NP * kCols * 4);
+  s.sh = (float*)take((size_t)kRows * kCols * 4);
+  s.rh = (float*)take((size_t)kCols * 4);
+  s.lw = (float*)take((size_t)NP * 8 * 4);
+  s.lwd = (float*)take((size_t)NP * 8 * 4);
+  s.sl = (int2*)take((size_t)NP * 8);
+  s.ids = (int32_t*)take(kRows * 4);
+  s.tids = (int32_t*)take(kRows * 4);
+  s.chi = (float*)take(TRX_MAX_ABSORBERS * 4);
+  s.ciaw = (float*)take(TRX_MAX_CIA * 4);
+  if (out) *out = s;
+  return o;
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  const int b = __builtin_amdgcn_readfirstlane(blockIdx.x);
+  if (b >= B) return;
+  const int span = __builtin_amdgcn_readfirstlane(blockIdx.y);
+  const Layout& L = a.L;
+  const GradAcc& G = a.G;
+  const uint8_t* slab = a.ws + (int64_t)b * L.slab;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
+  const int N = hd->n;
+  if (N == 0) return;
+  const int lo = hd->lo, hi = hd->hi;
+  const int col0 = span * kCols;
+  if (col0 >= hi || col0 + kCols <= lo) return;
+  const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
+  const int nU = ml->nU, nV = ml->nV;
+  if (nU + nV > kRows || nV > kMListV) {
+    // more distinct corners than the staging capacity: not built here
+    if (threadIdx.x == 0) atomicOr(&a.model_status[b], TRX_MODEL_GRAD_UNSUPPORTED);
+    return;
+  }
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int col = col0 + lane;
+  const bool valid = col >= lo && col < hi;
+  const int cc = valid ? col : lo;
+  const DevTables& tb = a.tab;
+  const int W = tb.n_wn;
+  const bool has_cia = tb.n_cia > 0;
+  const int NP = L.NP;
+  ItemLds s;
+  carve(L, dyn, &s);
+
+  // records, derivative records, slots, corner lists
+  {
+    const float4* lw4 = reinterpret_cast<const float4*>(slab + L.off_lw32);
+    const float4* ld4 = reinterpret_cast<const float4*>(slab + L.off_lwd32);
+    const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
+    for (int e = tid; e < 2 * NP; e += 64 * kWaves) {
+      reinterpret_cast<float4*>(s.lw)[e] = lw4[e];
+      reinterpret_cast<float4*>(s.lwd)[e] = ld4[e];
+    }
+    for (int e = tid; e < NP; e += 64 * kWaves) s.sl[e] = *reinterpret_cast<const int2*>(lid + 8 * e + 2);
+    for (int e = tid; e < nU; e += 64 * kWaves) s.ids[e] = ml->ids[e];
+    for (int e = tid; e < nV; e += 64 * kWaves) s.tids[e] = ml->tids[e];
+    if (tid < TRX_MAX_ABSORBERS) s.chi[tid] = hd->chi_abs32[tid];
+    if (tid < TRX_MAX_CIA) s.ciaw[tid] = hd->cia_w32[tid];
+  }
+  __syncthreads();
+  const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
+  const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
+  float* rows = s.rows;
+  float* crows = rows + nU * kCols;
+  stage_rows(tb.xsec32, abs_stride, W, cc, s.ids, nU, s.chi, tb.n_abs, rows, wave, lane);
+  if (has_cia) stage_rows(tb.cia32, cia_stride, W, cc, s.tids, nV, s.ciaw, tb.n_cia, crows, wave, lane);
+  float R = 0.f;
+  if (tb.has_rayleigh)
+    for (int q = 0; q < tb.n_abs + 2; ++q) R = fmaf(hd->chi_s32[q], tb.ray32[(int64_t)q * W + cc], R);
+  for (int e = tid; e < (nU + nV) * kCols; e += 64 * kWaves) s.sh[e] = 0.f;
+  if (tid < kCols) s.rh[tid] = 0.f;
+  __syncthreads();
+
+  // kappa (or, with the derivative records, dkappa/dT) of layer k
+  auto comb = [&](int k, const float* w) -> float {
+    const uint32_t sa = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].x);
+    float v = w[0] * rows[(sa & 0xff) * kCols + lane];
+    v = fmaf(w[1], rows[((sa >> 8) & 0xff) * kCols + lane], v);
+    v = fmaf(w[2], rows[((sa >> 16) & 0xff) * kCols + lane], v);
+    v = fmaf(w[3], rows[(sa >> 24) * kCols + lane], v);
+    v = fmaf(w[4], R, v);
+    if (has_cia) {
+      const uint32_t sc = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].y);
+      v = fmaf(w[5], crows[(sc & 0xff) * kCols + lane], v);
+      v = fmaf(w[6], crows[((sc >> 8) & 0xff) * kCols + lane], v);
+    }
+    return v;
+  };
+
+  // A: kappa of every layer
+  for (int k = wave; k < N; k += kWaves) s.kt[k * kCols + lane] = comb(k, s.lw + 8 * k);
+  __syncthreads();
+
+  // B: per ray j (wave w: j = w, w + 4, ...) tau, (Fz kappa)_j, (FR kappa)_j
+  double* acc = a.acc + (int64_t)b * G.n;
+  const float Db = valid ? a.dbar[(int64_t)b * W + col] : 0.f;
+  const float4* __restrict__ m3 = reinterpret_cast<const float4*>(slab + L.off_m3);
+  float tbr[kRayRegs];
+  float rp = 0.f;
+#pragma unroll
+  for (int r = 0; r < kRayRegs; ++r) {
+    const int j = wave + kWaves * r;
+    float tv = 0.f;
+    if (j < N) {
+      float tau = 0.f, u = 0.f, v = 0.f;
+      const float4* __restrict__ row = m3 + (int64_t)j * NP;
+      for (int k = j; k < N; ++k) {
+        const float4 m = row[k];
+        const float x = s.kt[k * kCols + lane];
+        tau = fmaf(m.x, x, tau);
+        u = fmaf(m.y, x, u);
+        v = fmaf(m.z, x, v);
+      }
+      const float e = __expf(-tau);
+      tv = Db * s.lw[8 * j + 7] * e;
+      const float ab = wave_sum(-Db * expm1f(-tau));
+      const float zb = wave_sum(tv * u);
+      if (lane == 0) {
+        atomicAdd(acc + G.o_A + j, (double)ab);
+        atomicAdd(acc + G.o_z + j, (double)zb);
+      }
+      rp = fmaf(tv, v, rp);
+    }
+    tbr[r] = tv;
+  }
+  {
+    const float t = wave_sum(rp);
+    if (lane == 0) atomicAdd(acc + G.o_Rp, (double)t);
+  }
+  __syncthreads();   // kappa is no longer read: its space takes taubar
+#pragma unroll
+  for (int r = 0; r < kRayRegs; ++r) {
+    const int j = wave + kWaves * r;
+    if (j < N) s.kt[j * kCols + lane] = tbr[r];
+  }
+  __syncthreads();
+
+  // C: per layer k kappabar = (dl^T taubar)_k and (Gh^T taubar)_k
+  const float2* __restrict__ mt = reinterpret_cast<const float2*>(slab + L.off_mt);
+  for (int k = wave; k < N; k += kWaves) {
+    float kb = 0.f, g = 0.f;
+    const float2* __restrict__ row = mt + (int64_t)k * NP;
+    for (int j = 0; j <= k; ++j) {
+      const float2 m = row[j];
+      const float t = s.kt[j * kCols + lane];
+      kb = fmaf(m.x, t, kb);
+      g = fmaf(m.y, t, g);
+    }
+    const float* w = s.lw + 8 * k;
+    const float kap = comb(k, w);
+    const float kap1 = k + 1 < N ? comb(k + 1, s.lw + 8 * (k + 1)) : 0.f;
+    const float dk = comb(k, s.lwd + 8 * k);
+    const float hb = wave_sum(g * (kap - kap1));
+    const float Tb = wave_sum(kb * dk);
+    if (lane == 0) {
+      atomicAdd(acc + G.o_h + k + 1, (double)hb);
+      atomicAdd(acc + G.o_T + k, (double)Tb);
+    }
+    const uint32_t sa = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].x);
+    atomicAdd(&s.sh[(sa & 0xff) * kCols + lane], w[0] * kb);
+    atomicAdd(&s.sh[((sa >> 8) & 0xff) * kCols + lane], w[1] * kb);
+    atomicAdd(&s.sh[((sa >> 16) & 0xff) * kCols + lane], w[2] * kb);
+    atomicAdd(&s.sh[(sa >> 24) * kCols + lane], w[3] * kb);
+    atomicAdd(&s.rh[lane], w[4] * kb);
+    if (has_cia) {
+      const uint32_t sc = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].y);
+      atomicAdd(&s.sh[(nU + (sc & 0xff)) * kCols + lane], w[5] * kb);
+      atomicAdd(&s.sh[(nU + ((sc >> 8) & 0xff)) * kCols + lane], w[6] * kb);
+    }
+  }
+  __syncthreads();
+
+  // D: mixing-ratio adjoints: corner rows against each absorber's table,
+  // CIA node rows against each pair's table, the Rayleigh row per species
+  const int rec = (int)(abs_stride * 4 < 0x7fffffff ? abs_stride * 4 : 0x7fffffff);
+  for (int i = 0; i < tb.n_abs; ++i) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(tb.xsec32 + (int64_t)i * abs_stride), (short)0, rec, kRsrcWord3);
+    float acc_i = 0.f;
+    for (int u0 = wave; u0 < nU; u0 += kWaves * 8) {
+      float v[8];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        const int u = u0 + kWaves * g < nU ? u0 + kWaves * g : u0;
+        v[g] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+            rs, cc * 4, __builtin_amdgcn_readfirstlane(s.ids[u]) * W * 4, 0));
+      }
+#pragma unroll
+      for (int g = 0; g < 8; ++g)
+        if (u0 + kWaves * g < nU) acc_i = fmaf(s.sh[(u0 + kWaves * g) * kCols + lane], v[g], acc_i);
+    }
+    acc_i = wave_sum(acc_i);
+    if (lane == 0) atomicAdd(acc + G.o_chi + i, (double)acc_i);
+  }
+  if (has_cia) {
+    for (int p = 0; p < tb.n_cia; ++p) {
+      const float* tp = tb.cia32 + (int64_t)p * cia_stride;
+      float acc_p = 0.f;
+      for (int t = wave; t < nV; t += kWaves)
+        acc_p = fmaf(s.sh[(nU + t) * kCols + lane], tp[(int64_t)s.tids[t] * W + cc], acc_p);
+      acc_p = wave_sum(acc_p);
+      if (lane == 0) atomicAdd(acc + G.o_cw + p, (double)acc_p);
+    }
+  }
+  if (tb.has_rayleigh) {
+    const float rl = s.rh[lane];
+    for (int q = wave; q < tb.n_abs + 2; q += kWaves) {
+      const float t = wave_sum(rl * tb.ray32[(int64_t)q * W + cc]);
+      if (lane == 0) atomicAdd(acc + G.o_chi + q, (double)t);
+    }
+  }
+}
+
+// ---- per model: annulus weights, shell boundaries, altitude, chemistry ---
+__global__ __launch_bounds__(64) void k_adj_geom(AdjArgs a) {
+  const int b = blockIdx.x;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if (b >= B) return;
+  const Layout& L = a.L;
+  const GradAcc& G = a.G;
+  const uint8_t* slab = a.ws + (int64_t)b * L.slab;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
+  const int N = hd->n;
+  const int nabs = a.tab.n_abs;
+  const int64_t off = a.bt.layer_off[b];
+  const int nl = a.bt.n_layers[b];
+  const bool bad = N == 0 || (a.model_status[b] & (TRX_MODEL_NONFINITE | TRX_MODEL_GRAD_UNSUPPORTED)) ||
+                   !isfinite(a.chi2[b]);
+  if (bad) {
+    const double nan = __builtin_nan("");
+    for (int l = threadIdx.x; l < nl; l += 64) a.dT[off + l] = nan;
+    for (int i = threadIdx.x; i < nabs; i += 64) a.dvmr[(int64_t)b * nabs + i] = nan;
+    if (threadIdx.x == 0) a.dRp[b] = nan;
+    return;
+  }
+  if (threadIdx.x != 0) return;   // one sequential FP64 sweep per model (N <= 224)
+  double* acc = a.acc + (int64_t)b * G.n;
+  double* Ab = acc + G.o_A;
+  double* zb = acc + G.o_z;
+  double* hb = acc + G.o_h;
+  double* Tb = acc + G.o_T;
+  const double* z = reinterpret_cast<const double*>(slab + L.off_z);
+  const double Rp = hd->Rp, inv_Rs2 = hd->inv_Rs2, mu = hd->mu_kg;
+  const double GM = a.bt.GM[b], kB = a.bt.kB;
+  const double* T = a.bt.T + off;
+  double Rpb = acc[G.o_Rp];
+  auto hof = [&](int k) -> double { return k == 0 ? 0.0 : (k == N ? z[N - 1] : 0.5 * (z[k - 1] + z[k])); };
+  // annulus weights A_j = 2 (Rp + z_j)(h_{j+1} - h_j)/Rs^2
+  for (int j = 0; j < N; ++j) {
+    const double dh = hof(j + 1) - hof(j);
+    const double f = 2.0 * Ab[j] * inv_Rs2;
+    zb[j] += f * dh;
+    Rpb += f * dh;
+    hb[j + 1] += f * (Rp + z[j]);
+    hb[j] -= f * (Rp + z[j]);
+  }
+  // shell boundaries: h_k = (z_{k-1} + z_k)/2, h_N = z_{N-1} (h_0 = 0 fixed)
+  for (int k = 1; k < N; ++k) {
+    zb[k - 1] += 0.5 * hb[k];
+    zb[k] += 0.5 * hb[k];
+  }
+  zb[N - 1] += hb[N];
+  // altitude recursion z_l = z_{l-1} - sC_{l-1} f, sC = k_B T ln(P_l/P_{l-1})/mu,
+  // f = (Rp + z_{l-1})^2/GM (or Rp^2/GM), in reverse
+  const double xb = log10(a.bt.p_bot[b]), xt = log10(a.bt.p_top[b]);
+  auto Pof = [&](int l) -> double {
+    const double p0 = pow(10.0, xb + (xt - xb) * (double)l / (double)N);
+    const double p1 = pow(10.0, xb + (xt - xb) * (double)(l + 1) / (double)N);
+    return p0 * sqrt(p1 / p0);
+  };
+  double mub = 0.0;
+  double Pl = Pof(N - 1);
+  for (int l = N - 1; l >= 1; --l) {
+    const double Pm = Pof(l - 1);
+    const double sC = kB * T[l - 1] * log(Pl / Pm) / mu;
+    const double g = zb[l];
+    if (a.bt.gravity == 0) {
+      const double rz = Rp + z[l - 1];
+      const double f = rz * rz / GM;
+      zb[l - 1] += g * (1.0 - 2.0 * sC * rz / GM);
+      Rpb += g * (-2.0 * sC * rz / GM);
+      Tb[l - 1] += g * (-sC * f / T[l - 1]);
+      mub += g * (sC * f / mu);
+    } else {
+      const double f = Rp * Rp / GM;
+      zb[l - 1] += g;
+      Rpb += g * (-2.0 * sC * Rp / GM);
+      Tb[l - 1] += g * (-sC * f / T[l - 1]);
+      mub += g * (sC * f / mu);
+    }
+    Pl = Pm;
+  }
+  // chemistry: CIA weights chi_a chi_b, mu = amu sum chi_s m_s, fill gases
+  // chi_H2 = (1 - S)/(1 + r), chi_He = r chi_H2, log10 parameters
+  double cb[kMaxSpecies];
+  for (int q = 0; q < nabs + 2; ++q) cb[q] = acc[G.o_chi + q] + mub * a.bt.amu * a.tab.mass[q];
+  for (int p = 0; p < a.tab.n_cia; ++p) {
+    const int sa = a.tab.cia_pair[p][0], sb = a.tab.cia_pair[p][1];
+    const double w = acc[G.o_cw + p];
+    cb[sa] += w * hd->chi_s[sb];
+    cb[sb] += w * hd->chi_s[sa];
+  }
+  const double r = a.bt.he_h2;
+  const double fb = (cb[nabs] + r * cb[nabs + 1]) / (1.0 + r);
+  for (int i = 0; i < nabs; ++i)
+    a.dvmr[(int64_t)b * nabs + i] = (cb[i] - fb) * hd->chi_s[i] * 2.302585092994045684;
+  for (int l = 0; l < N; ++l) a.dT[off + l] = Tb[l];
+  a.dRp[b] = Rpb;
+}
+
+}  // namespace
+
+size_t adj_item_lds_bytes(const Layout& L) { return carve(L, nullptr, nullptr); }
+
+void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
+  if (B_grid <= 0) return;
+  hipLaunchKernelGGL(k_chi2_dbar, dim3(B_grid), dim3(256), 0, s, a);
+}
+
+hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
+  if (B_grid <= 0) return hipSuccess;
+  const size_t lds = adj_item_lds_bytes(a.L);
+  hipError_t e = hipFuncSetAttribute((const void*)k_adj_item, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int spans = (a.tab.n_wn + kCols - 1) / kCols;
+  hipLaunchKernelGGL(k_adj_item, dim3(B_grid, spans), dim3(64 * kWaves), lds, s, a);
+  return hipGetLastError();
+}
+
+void launch_adj_geom(const AdjArgs& a, int B_grid, hipStream_t s) {
+  if (B_grid <= 0) return;
+  hipLaunchKernelGGL(k_adj_geom, dim3(B_grid), dim3(64), 0, s, a);
+}
+
+}  // namespace trx

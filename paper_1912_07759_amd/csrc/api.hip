@@ -351,8 +351,8 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
                                 const int32_t* B_dev, int max_layers, const trx_bins* bins,
                                 int precision, const RunConfig& rc, uint8_t* ws, void* aws,
                                 const SchedBufs& sb, double* depth_native, double* depth_binned,
-                                int32_t* status) {
-  const Layout L = make_layout(max_layers, precision);
+                                int32_t* status, bool grad_layout) {
+  const Layout L = make_layout(max_layers, precision, grad_layout);
   GeomArgs g;
   g.bt = db;
   g.tab = t->dev;
@@ -413,6 +413,76 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
+  return TRX_OK;
+}
+
+size_t trx::grad_scratch_bytes(int B, int n_wn, int n_ch, int NP) {
+  const GradAcc G = make_grad_acc(NP);
+  return (size_t)B * G.n * 8 + (size_t)B * n_ch * 8 + (size_t)B * n_wn * 4 + 1024;
+}
+
+trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B,
+                                  const int32_t* B_dev, int max_layers, const trx_bins* bins, int precision,
+                                  const RunConfig& rc, DevBuf& ws, DevBuf& aws, DevBuf& sched, DevBuf& grad,
+                                  const double* obs, const double* sigma, double* chi2, double* dT,
+                                  double* dvmr, double* dRp, double* depth_binned, int32_t* status,
+                                  bool alloc) {
+  const Layout L = make_layout(max_layers, precision, true);
+  const GradAcc G = make_grad_acc(L.NP);
+  const int W = t->dev.n_wn;
+  const size_t esz = precision == TRX_FP64 ? 8 : 4;
+  if (alloc) {
+    trx_status s;
+    if ((s = ensure_buffer(c, ws, (size_t)B * L.slab, "workspace")) != TRX_OK) return s;
+    if ((s = ensure_buffer(c, aws, (size_t)B * W * esz, "workspace")) != TRX_OK) return s;
+    if ((s = ensure_buffer(c, sched, SchedBufs::bytes(B), "workspace")) != TRX_OK) return s;
+    if ((s = ensure_buffer(c, grad, grad_scratch_bytes(B, W, bins->n_ch, L.NP), "workspace")) != TRX_OK)
+      return s;
+  }
+  uint8_t* gp = (uint8_t*)grad.ptr;
+  double* acc = (double*)gp;
+  double* binned_tmp = (double*)(gp + (size_t)B * G.n * 8);
+  float* dbar = (float*)(gp + (size_t)B * G.n * 8 + (size_t)B * bins->n_ch * 8);
+  double* binned = depth_binned ? depth_binned : binned_tmp;
+  trx_status s = enqueue_forward(c, t, db, B, B_dev, max_layers, bins, precision, rc, (uint8_t*)ws.ptr,
+                                 aws.ptr, SchedBufs::carve(sched.ptr, B), nullptr, binned, status, true);
+  if (s != TRX_OK) return s;
+  AdjArgs a;
+  memset(&a, 0, sizeof a);
+  a.tab = t->dev;
+  a.L = L;
+  a.G = G;
+  a.ws = (uint8_t*)ws.ptr;
+  a.bt = db;
+  a.B_dev = B_dev;
+  a.B = B;
+  a.n_ch = bins->n_ch;
+  a.ch_i0 = bins->i0; a.ch_i1 = bins->i1; a.ch_off = bins->off; a.ch_w = bins->w;
+  a.binned = binned;
+  a.obs = obs;
+  a.sigma = sigma;
+  a.chi2 = chi2;
+  a.dbar = dbar;
+  a.acc = acc;
+  a.dT = dT;
+  a.dvmr = dvmr;
+  a.dRp = dRp;
+  a.model_status = status;
+  {
+    ProfScope ps(c, TRX_KERNEL_GEOM_ADJ);
+    launch_chi2_dbar(a, B, c->stream);
+  }
+  {
+    ProfScope ps(c, TRX_KERNEL_ADJOINT);
+    hipError_t e = launch_adj_item(a, B, c->stream);
+    if (e != hipSuccess) return hip_err(c, e, "adjoint launch");
+  }
+  {
+    ProfScope ps(c, TRX_KERNEL_GEOM_ADJ);
+    launch_adj_geom(a, B, c->stream);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "adjoint launch");
   return TRX_OK;
 }
 
@@ -503,4 +573,30 @@ extern "C" trx_status trx_profile_read(trx_ctx* c, int32_t kernel, double* total
   *total_ms = c->total_ms[kernel];
   *launches = c->launches[kernel];
   return TRX_OK;
+}
+
+// --------------------------------------------------------------------------
+// chi^2 and its gradient (recompute mode)
+// --------------------------------------------------------------------------
+extern "C" trx_status trx_chi2_grad(trx_ctx* c, const trx_tables* t, const trx_batch* bt,
+                                    const trx_bins* bins, trx_precision precision, const double* obs,
+                                    const double* sigma, int32_t recompute, double* chi2, double* dT,
+                                    double* dlog10vmr, double* dRp, double* depth_binned,
+                                    int32_t* model_status) {
+  if (!c) return TRX_E_INVALID_ARG;
+  c->err.clear();
+  trx_status s = check_batch(c, t, bt, precision);
+  if (s != TRX_OK) return s;
+  if (!bins) return set_err(c, TRX_E_INVALID_ARG, "trx_chi2_grad needs channels (bins)");
+  if (bins->tables != t) return set_err(c, TRX_E_INVALID_ARG, "bins were made for other tables");
+  if (!obs || !sigma || !chi2 || !dT || !dRp || !model_status || (t->dev.n_abs > 0 && !dlog10vmr))
+    return set_err(c, TRX_E_INVALID_ARG, "trx_chi2_grad: a required pointer is null");
+  if (!recompute)
+    return set_err(c, TRX_E_UNSUPPORTED, "only the recompute mode of the gradient is built");
+  if (bt->max_layers > TRX_MAX_LAYERS_MFMA)
+    return set_err(c, TRX_E_UNSUPPORTED, "the gradient supports at most %d layers", TRX_MAX_LAYERS_MFMA);
+  hipSetDevice(c->device);
+  return enqueue_chi2_grad(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision,
+                           default_config(precision, bt->max_layers), c->ws, c->aws, c->sched, c->grad,
+                           obs, sigma, chi2, dT, dlog10vmr, dRp, depth_binned, model_status);
 }

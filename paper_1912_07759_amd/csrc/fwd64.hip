@@ -118,7 +118,7 @@ __device__ void process64(const FwdArgs& a, int b_in, int span_in, Smem64& sm) {
     crows = rows + nU * kCols;
     if (has_cia) stage64(tb.cia64, cia_stride, W, cc, sm.tids, nV, hd->cia_w, tb.n_cia, crows, wave, lane);
   };
-  const bool mstage = ml->nU + ml->nV <= kRows;
+  const bool mstage = ml->nU + ml->nV <= kRows && ml->nV <= kMListV;
   const int slot_off = mstage ? 2 : 4;
   if (mstage) stage(ml->ids, ml->nU, ml->tids, ml->nV);
   if (tid < kCols) sm.atm[tid] = 0.0;

@@ -213,9 +213,10 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       const double n = P / (a.bt.kB * T);
       int iT, iP, iC;
       double wT, wP, wC;
-      bool Tb, Pb, c0, c1, c2;
+      bool Tb, Pb, c0, c1, c2 = false;
       bracket(tb.T, tb.n_T, T, iT, wT, Tb, c0);
       bracket(tb.logP, tb.n_P, log10(P), iP, wP, Pb, c1);
+      const bool Tb_abs = Tb;
       const double f1 = 1e-4 * n;
       double w[8];
       if (Tb && Pb) {
@@ -242,6 +243,33 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         lw32[8 * l + q] = (float)(q >= 5 ? w[q] / kCiaScale32 : w[q]);
       }
       lw32[8 * l + 7] = (float)A;   // FP32 records carry the ray's annulus weight
+      if (L.grad) {
+        // d(weight)/dT at fixed P: the bracket slope in T (zero where T is
+        // clamped: one-sided at nodes, Opacities section rules) and the
+        // number-density factor, d rho/dT = -rho/T (rho^2 for CIA)
+        float* lwd = reinterpret_cast<float*>(slab + L.off_lwd32) + 8 * l;
+        const double dwT = c0 ? 0.0 : 1.0 / (tb.T[iT + 1] - tb.T[iT]);
+        double d[8];
+        if (Tb_abs && Pb) {
+          d[0] = d[1] = d[2] = d[3] = 0.0;
+        } else {
+          d[0] = -f1 * dwT * (1.0 - wP) - w[0] / T;
+          d[1] = f1 * dwT * (1.0 - wP) - w[1] / T;
+          d[2] = -f1 * dwT * wP - w[2] / T;
+          d[3] = f1 * dwT * wP - w[3] / T;
+        }
+        d[4] = -w[4] / T;
+        if (tb.n_cia > 0) {
+          const double dwC = c2 ? 0.0 : 1.0 / (tb.Tcia[iC + 1] - tb.Tcia[iC]);
+          const double f2 = 1e-10 * n * n;
+          d[5] = -f2 * dwC - 2.0 * w[5] / T;
+          d[6] = f2 * dwC - 2.0 * w[6] / T;
+        } else {
+          d[5] = d[6] = 0.0;
+        }
+        d[7] = 0.0;
+        for (int q = 0; q < 8; ++q) lwd[q] = (float)(q >= 5 ? d[q] / kCiaScale32 : d[q]);
+      }
       lid[8 * l] = iT * tb.n_P + iP;
       lid[8 * l + 1] = iC;
     } else {
@@ -249,6 +277,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       A64[l] = 0.0;
       A32[l] = 0.0f;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
+      if (L.grad)
+        for (int q = 0; q < 8; ++q) reinterpret_cast<float*>(slab + L.off_lwd32)[8 * l + q] = 0.0f;
       for (int q = 0; q < 8; ++q) lid[8 * l + q] = 0;   // padding layer: zero weights
     }
   }
@@ -389,6 +419,45 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     const double q0 = sqrt((hk - zj) * (2.0 * Rp + hk + zj));
     return 2.0 * (hk1 - hk) * (2.0 * Rp + hk + hk1) / (q1 + q0);
   };
+  if (L.grad) {
+    // derivative matrices of the chords (gradient layouts): with
+    // q_j(h) = sqrt((h - z_j)(2Rp + h + z_j)), dl[j,k] = 2 (q_j(h_{k+1}) -
+    // [k > j] q_j(h_k)), dq/dz_j = -(Rp + z_j)/q, dq/dRp = (h - z_j)/q,
+    // dq/dh = (Rp + h)/q; the zero chord of the top ray has no derivative.
+    float4* m3 = reinterpret_cast<float4*>(slab + L.off_m3);
+    float2* mt = reinterpret_cast<float2*>(slab + L.off_mt);
+    auto hb = [&](int k) -> double {
+      return k == 0 ? 0.0 : (k == N ? sZ[N - 1] : 0.5 * (sZ[k - 1] + sZ[k]));
+    };
+    for (int e = tid; e < NP * NP; e += kThreads) {
+      const int j = e / NP, k = e % NP;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      float gh = 0.f;
+      if (j < N && k < N && k >= j) {
+        const double zj = sZ[j];
+        const double h1 = hb(k + 1);
+        const double q1 = sqrt(fmax((h1 - zj) * (2.0 * Rp + h1 + zj), 0.0));
+        const double d = dl_of(j, k);
+        double fz = 0.0, fr = 0.0;
+        if (q1 > 0.0) {
+          gh = (float)(2.0 * (Rp + h1) / q1);
+          if (k == j) {
+            fz = -2.0 * (Rp + zj) / q1;
+            fr = 2.0 * (h1 - zj) / q1;
+          } else {
+            const double h0 = hb(k);
+            const double q0 = sqrt((h0 - zj) * (2.0 * Rp + h0 + zj));
+            // -2 (Rp + z_j)(1/q1 - 1/q0) = (Rp + z_j) dl / (q0 q1)
+            fz = (Rp + zj) * d / (q0 * q1);
+            fr = 2.0 * ((h1 - zj) / q1 - (h0 - zj) / q0);
+          }
+        }
+        v = make_float4((float)d, (float)fz, (float)fr, 0.f);
+      }
+      m3[(int64_t)j * NP + k] = v;
+      mt[(int64_t)k * NP + j] = make_float2(v.x, gh);
+    }
+  }
   uint8_t* dst = slab + L.off_dl;
   if (a.precision == TRX_FP64) {
     double* dlT = reinterpret_cast<double*>(dst);

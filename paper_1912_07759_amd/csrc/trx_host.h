@@ -100,6 +100,15 @@ RunConfig default_config(int precision, int max_layers);
 trx_status enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B, const int32_t* B_dev,
                            int max_layers, const trx_bins* bins, int precision, const RunConfig& rc,
                            uint8_t* ws, void* aws, const SchedBufs& sb, double* depth_native,
-                           double* depth_binned, int32_t* status);
+                           double* depth_binned, int32_t* status, bool grad_layout = false);
+
+size_t grad_scratch_bytes(int B, int n_wn, int n_ch, int NP);
+// Forward pass on the gradient layout, chi^2, and the adjoint kernels.
+// alloc: grow the buffers as needed (false: they are already large enough).
+trx_status enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B, const int32_t* B_dev,
+                             int max_layers, const trx_bins* bins, int precision, const RunConfig& rc,
+                             DevBuf& ws, DevBuf& aws, DevBuf& sched, DevBuf& grad, const double* obs,
+                             const double* sigma, double* chi2, double* dT, double* dvmr, double* dRp,
+                             double* depth_binned, int32_t* status, bool alloc = true);
 
 }  // namespace trx

@@ -83,6 +83,11 @@ struct Layout {
   int32_t NRB, NKB;        // NP/32, NP/16
   int64_t off_z, off_A64, off_A32, off_lw64, off_lw32, off_lid, off_kblk, off_mlist, off_dl;
   int64_t dl_bytes;        // mode-specific path-length storage
+  // gradient layouts only (0 otherwise):
+  int64_t off_lwd32;       // [NP][8] FP32 d(record weight)/dT at fixed P
+  int64_t off_m3;          // [NP][NP] float4 (dl, d dl/dz_j, d dl/dRp, 0), row = ray j
+  int64_t off_mt;          // [NP][NP] float2 (dl_jk, d(2 q_j(h_{k+1}))/dh_{k+1}), row = layer k
+  int32_t grad;
   int64_t slab;            // bytes per model (multiple of 256)
 };
 
@@ -114,7 +119,7 @@ inline int frag_piece_bytes(int precision) {
   return precision == TRX_FP32 ? 64 * 8 * 4 : 64 * 8 * 2;
 }
 
-inline Layout make_layout(int N_max, int precision) {
+inline Layout make_layout(int N_max, int precision, bool grad = false) {
   Layout L{};
   L.NP = ((N_max + 31) / 32) * 32;
   L.NRB = L.NP / 32;
@@ -138,6 +143,12 @@ inline Layout make_layout(int N_max, int precision) {
                  frag_piece_bytes(precision);
   }
   L.off_dl = take(L.dl_bytes);
+  if (grad) {
+    L.grad = 1;
+    L.off_lwd32 = take(4LL * 8 * L.NP);
+    L.off_m3 = take(16LL * L.NP * L.NP);
+    L.off_mt = take(8LL * L.NP * L.NP);
+  }
   L.slab = o;
   return L;
 }
@@ -234,6 +245,56 @@ struct BinArgs {
   int32_t aws_f64;
   double* out;            // [B][n_ch]
 };
+
+// Per-model FP64 accumulators of the adjoint (offsets in doubles).
+struct GradAcc {
+  int32_t NP;
+  int32_t o_A, o_z, o_h, o_T, o_Rp, o_chi, o_cw, n;
+};
+inline GradAcc make_grad_acc(int NP) {
+  GradAcc g{};
+  g.NP = NP;
+  int o = 0;
+  g.o_A = o; o += NP;          // dchi2/dA_j (A_j including 1/Rs^2)
+  g.o_z = o; o += NP;          // dchi2/dz_j
+  g.o_h = o; o += NP + 1;      // dchi2/dh_k, shell boundaries 0..N
+  g.o_T = o; o += NP;          // dchi2/dT_l through the opacity
+  g.o_Rp = o; o += 1;          // dchi2/dRp (explicit terms)
+  g.o_chi = o; o += kMaxSpecies;  // dchi2/dchi_s through the opacity
+  g.o_cw = o; o += TRX_MAX_CIA;   // dchi2/d(chi_a chi_b) per CIA pair
+  g.n = (o + 31) / 32 * 32;
+  return g;
+}
+
+// Arguments of the adjoint kernels.
+struct AdjArgs {
+  DevTables tab;
+  Layout L;
+  GradAcc G;
+  uint8_t* ws;
+  DevBatch bt;
+  const int32_t* B_dev;
+  int32_t B;
+  int32_t n_ch;
+  const int32_t* ch_i0;
+  const int32_t* ch_i1;
+  const int64_t* ch_off;
+  const double* ch_w;
+  const double* binned;   // [B][n_ch] forward result
+  const double* obs;      // [B][n_ch]
+  const double* sigma;    // [n_ch]
+  double* chi2;           // [B]
+  float* dbar;            // [B][n_wn] dchi2/dD_i inside the window
+  double* acc;            // [B][G.n]
+  double* dT;             // [layer_off[B]]
+  double* dvmr;           // [B][n_abs]
+  double* dRp;            // [B]
+  int32_t* model_status;  // [B]
+};
+size_t adj_item_lds_bytes(const Layout& L);
+void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s);
+hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s);
+void launch_adj_geom(const AdjArgs& a, int B_grid, hipStream_t s);
 
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s);
 void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int n_cu, hipStream_t s);

@@ -304,6 +304,57 @@ def chi2_grad(ctx, tables, batch, bins, obs, sigma, precision=FP32, recompute=Tr
     return out
 
 
+class Chi2Problem:
+    """Everything of a chi^2 evaluation except the differentiated parameters:
+    the context, tables, channels, a DeviceBatch giving the layer counts,
+    pressures, radii, windows and constants, the observation and sigma."""
+
+    def __init__(self, ctx, tables, bins, batch, obs, sigma, precision=FP32):
+        self.ctx, self.tables, self.bins, self.batch = ctx, tables, bins, batch
+        dev = batch.T.device
+        self.obs = torch.as_tensor(obs, dtype=torch.float64).to(dev).contiguous()
+        self.sigma = torch.as_tensor(sigma, dtype=torch.float64).to(dev).contiguous()
+        self.precision = precision
+
+    def with_params(self, T, log10_vmr, Rp):
+        """A DeviceBatch sharing this problem's arrays but the given
+        parameter tensors (float64, on the device)."""
+        b = object.__new__(DeviceBatch)
+        b.__dict__.update(self.batch.__dict__)
+        b.T = T.detach().to(torch.float64).contiguous()
+        b.log10_vmr = log10_vmr.detach().to(torch.float64).contiguous()
+        b.Rp = Rp.detach().to(torch.float64).contiguous()
+        return b
+
+
+class TransitChi2(torch.autograd.Function):
+    """chi^2 per model as a differentiable function of the per-layer
+    temperatures T [sum N], the log10 mixing ratios [B, n_abs] and Rp [B].
+
+    The value and the gradient come from one trx_chi2_grad call (recompute
+    mode: no opacity or optical depth is kept); only the gradient vectors
+    are saved for backward."""
+
+    @staticmethod
+    def forward(ctx, T, log10_vmr, Rp, problem):
+        b = problem.with_params(T, log10_vmr, Rp)
+        out = chi2_grad(problem.ctx, problem.tables, b, problem.bins, problem.obs,
+                        problem.sigma, problem.precision)
+        bad = out["status"] != 0
+        if bool(bad.any()):
+            out["chi2"] = torch.where(bad, torch.full_like(out["chi2"], float("nan")), out["chi2"])
+        ctx.save_for_backward(out["dT"], out["dlog10_vmr"], out["dRp"], problem.batch.layer_off)
+        return out["chi2"]
+
+    @staticmethod
+    def backward(ctx, g):
+        dT, dv, dR, off = ctx.saved_tensors
+        g = g.to(torch.float64)
+        counts = (off[1:] - off[:-1]).to(torch.int64)
+        gT = dT * torch.repeat_interleave(g, counts)
+        return gT, dv * g[:, None], dR * g, None
+
+
 class Plan:
     """trx_plan_*: a batched launch for up to B_max models of at most N_max
     layers, replayed from a HIP graph when ``graph`` is set.

@@ -1,0 +1,128 @@
+"""GPU parity of chi^2 and its gradient (a8, through trx_chi2_grad) against
+the oracle's FP64 reference gradient and against central differences of the
+library's own FP64 forward model; the autograd Function."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth.workloads import make_config, observation_noise
+
+pytestmark = pytest.mark.gpu
+
+# Reading A17: gradient error norm-wise and per component above 1e-3 of
+# the largest component, against the FP64 reference.
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def problem():
+    """Gradient workload, reduced: 100-layer perturbed Guillot profiles,
+    7 absorbers, CIA and Rayleigh, 100 channels, 6 parameter points; the
+    observation is the truth (point 0) binned by the oracle plus seeded
+    50 ppm noise."""
+    tables, batch, ch = make_config(4, n_wn=2500, n_lines=250, B=6)
+    truth = oracle.forward_model(batch.model(0), tables, ch)["binned"]
+    noise, sigma = observation_noise(4, 1, len(ch.lo))
+    obs = np.tile(truth + noise[0], (batch.B, 1))
+    return tables, batch, ch, obs, sigma
+
+
+def _gpu(ctx, tables, batch, ch, obs, sigma, precision, T=None):
+    from paper_1912_07759_amd import trx
+    Tt = trx.Tables.from_synth(ctx, tables)
+    bins = trx.Bins(ctx, Tt, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=100)
+    out = trx.chi2_grad(ctx, Tt, db, bins, obs, sigma, precision)
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    bins.close()
+    Tt.close()
+    return res
+
+
+def _grad_err(g, ref):
+    v = np.concatenate([g["dT"], g["dlog10_vmr"], [g["dRp"]]])
+    r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
+    norm = np.linalg.norm(v - r) / np.linalg.norm(r)
+    big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
+    comp = np.max(np.abs(v[big] - r[big]) / np.abs(r[big]))
+    return norm, comp
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x2", "fp64"])
+def test_gradient_matches_oracle(gpu_ctx, problem, mode):
+    tables, batch, ch, obs, sigma = problem
+    g = _gpu(gpu_ctx, tables, batch, ch, obs, sigma, mode)
+    assert np.all(g["status"] == 0)
+    off = batch.layer_off
+    worst = 0.0
+    for b in range(batch.B):
+        ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
+        assert abs(g["chi2"][b] - ref["chi2"]) <= 1e-5 * ref["chi2"]
+        mine = {"dT": g["dT"][off[b]:off[b + 1]], "dlog10_vmr": g["dlog10_vmr"][b],
+                "dRp": g["dRp"][b]}
+        norm, comp = _grad_err(mine, ref)
+        print(f"{mode} model {b}: chi2 {g['chi2'][b]:.6e} grad norm err {norm:.2e} comp err {comp:.2e}")
+        worst = max(worst, norm, comp)
+    assert worst <= GRAD_TOL
+
+
+def test_gradient_central_differences(gpu_ctx, problem):
+    """Central differences of chi^2 from the library's FP64 forward path
+    (step 1e-4 K, 1e-6 dex, 1e-7 Rp) against the FP32 gradient."""
+    tables, batch, ch, obs, sigma = problem
+    base = _gpu(gpu_ctx, tables, batch, ch, obs, sigma, "fp32")
+    b = 1
+    off = int(batch.layer_off[b])
+
+    def chi2_at(mod):
+        bb = batch.subset([b])
+        mod(bb)
+        r = _gpu(gpu_ctx, tables, bb, ch, obs[b:b + 1], sigma, "fp64")
+        return float(r["chi2"][0])
+
+    checks = []
+    for l in (3, 40, 77):
+        h = 1e-4
+        def up(bb, l=l, s=+1):
+            bb.T[l] += s * h
+        fd = (chi2_at(lambda bb: up(bb, s=+1)) - chi2_at(lambda bb: up(bb, s=-1))) / (2 * h)
+        checks.append(("dT", l, fd, base["dT"][off + l]))
+    for i in (0, 3):
+        h = 1e-6
+        def vm(bb, i=i, s=+1):
+            bb.log10_vmr[0, i] += s * h
+        fd = (chi2_at(lambda bb: vm(bb, s=+1)) - chi2_at(lambda bb: vm(bb, s=-1))) / (2 * h)
+        checks.append(("dvmr", i, fd, base["dlog10_vmr"][b, i]))
+    h = 1e-7 * batch.Rp[b]
+    def rp(bb, s=+1):
+        bb.Rp[0] += s * h
+    fd = (chi2_at(lambda bb: rp(bb, s=+1)) - chi2_at(lambda bb: rp(bb, s=-1))) / (2 * h)
+    checks.append(("dRp", 0, fd, base["dRp"][b]))
+    for name, i, fd, g in checks:
+        print(f"{name}[{i}]: central difference {fd:.8e} gradient {g:.8e}")
+        assert abs(g - fd) <= 1e-4 * abs(fd) + 1e-9 * max(abs(c[2]) for c in checks)
+
+
+def test_autograd_function(gpu_ctx, problem):
+    from paper_1912_07759_amd import trx
+    tables, batch, ch, obs, sigma = problem
+    Tt = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, Tt, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=100)
+    prob = trx.Chi2Problem(gpu_ctx, Tt, bins, db, obs, sigma, "fp32")
+    T = db.T.clone().requires_grad_(True)
+    v = db.log10_vmr.clone().requires_grad_(True)
+    R = db.Rp.clone().requires_grad_(True)
+    c2 = trx.TransitChi2.apply(T, v, R, prob)
+    w = torch.arange(1, batch.B + 1, dtype=torch.float64, device=c2.device)
+    (c2 * w).sum().backward()
+    ref = trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, sigma, "fp32")
+    counts = torch.as_tensor(np.diff(batch.layer_off), device=c2.device)
+    assert torch.allclose(c2, ref["chi2"])
+    assert torch.allclose(T.grad, ref["dT"] * torch.repeat_interleave(w, counts))
+    assert torch.allclose(v.grad, ref["dlog10_vmr"] * w[:, None])
+    assert torch.allclose(R.grad, ref["dRp"] * w)
+    bins.close()
+    Tt.close()
