@@ -239,7 +239,8 @@ trx_status trx_plan_batch(trx_plan* p, trx_batch* out);
  * the call differs from the captured one; batch->B travels through device
  * memory, so a new B alone replays the same graph.  While trx_profile is
  * enabled the same kernels are launched one by one instead, so that each
- * is timed. */
+ * is timed.  A TRX_PLAN_GRAD plan needs obs, sigma, chi2, dT, dlog10vmr,
+ * dRp (as in trx_chi2_grad) and does not write depth_native (NULL). */
 trx_status trx_plan_launch(trx_plan* p, const trx_batch* batch, double* depth_native,
                            double* depth_binned, int32_t* model_status,
                            const double* obs, const double* sigma, double* chi2,

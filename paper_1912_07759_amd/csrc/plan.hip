@@ -33,7 +33,7 @@ struct trx_plan {
   std::vector<void*> owned;
   trx_batch own{};
   int32_t* B_dev = nullptr;
-  DevBuf ws, aws, sched, tune_binned, tune_status;
+  DevBuf ws, aws, sched, grad, tune_binned, tune_status;
   // graph state
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -42,6 +42,20 @@ struct trx_plan {
   double* cap_native = nullptr;
   double* cap_binned = nullptr;
   int32_t* cap_status = nullptr;
+  const void* cap_grad[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+// Outputs (and, for gradient plans, observation inputs) of one launch.
+struct PlanIO {
+  double* native;
+  double* binned;
+  int32_t* status;
+  const double* obs;
+  const double* sigma;
+  double* chi2;
+  double* dT;
+  double* dvmr;
+  double* dRp;
 };
 
 namespace {
@@ -77,6 +91,14 @@ trx_status enqueue(trx_plan* p, const trx_batch* bt, int B, const int32_t* B_dev
   return enqueue_forward(p->ctx, p->t, dev_batch(bt), B, B_dev, p->N_max, p->bins, p->precision, rc,
                          (uint8_t*)p->ws.ptr, p->aws.ptr, SchedBufs::carve(p->sched.ptr, p->B_max), native,
                          binned, status);
+}
+
+trx_status enqueue_io(trx_plan* p, const trx_batch* bt, int B, const int32_t* B_dev, const RunConfig& rc,
+                      const PlanIO& io) {
+  if (!(p->flags & TRX_PLAN_GRAD)) return enqueue(p, bt, B, B_dev, rc, io.native, io.binned, io.status);
+  return enqueue_chi2_grad(p->ctx, p->t, dev_batch(bt), B, B_dev, p->N_max, p->bins, p->precision, rc, p->ws,
+                           p->aws, p->sched, p->grad, io.obs, io.sigma, io.chi2, io.dT, io.dvmr, io.dRp,
+                           io.binned, io.status, false);
 }
 
 trx_status check_launch(trx_plan* p, const trx_batch* bt, double* binned, const int32_t* status,
@@ -180,7 +202,10 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   if (N_max > limit) return set_err(c, TRX_E_UNSUPPORTED, "N_max %d exceeds %d for this precision", N_max, limit);
   if (flags & ~(TRX_PLAN_GRAPH | TRX_PLAN_PERSISTENT | TRX_PLAN_GRAD))
     return set_err(c, TRX_E_INVALID_ARG, "unknown plan flags 0x%x", flags);
-  if (flags & TRX_PLAN_GRAD) return set_err(c, TRX_E_UNSUPPORTED, "gradient plans are not built");
+  const bool grad = (flags & TRX_PLAN_GRAD) != 0;
+  if (grad && !bins) return set_err(c, TRX_E_INVALID_ARG, "gradient plans need channels (bins)");
+  if (grad && N_max > TRX_MAX_LAYERS_MFMA)
+    return set_err(c, TRX_E_UNSUPPORTED, "the gradient supports at most %d layers", TRX_MAX_LAYERS_MFMA);
   hipSetDevice(c->device);
   trx_plan* p = new trx_plan();
   p->ctx = c; p->t = t; p->bins = bins;
@@ -189,9 +214,12 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   if (!(flags & TRX_PLAN_PERSISTENT)) p->rc.persistent = 0;
   describe(p);
   auto fail = [&](trx_status s) { trx_plan_destroy(p); return s; };
-  const Layout L = make_layout(N_max, precision);
+  const Layout L = make_layout(N_max, precision, grad);
   trx_status s;
   if ((s = ensure_buffer(c, p->ws, (size_t)B_max * L.slab, "plan workspace")) != TRX_OK) return fail(s);
+  if (grad && (s = ensure_buffer(c, p->grad, grad_scratch_bytes(B_max, t->dev.n_wn, bins->n_ch, L.NP),
+                                 "plan workspace")) != TRX_OK)
+    return fail(s);
   const size_t esz = precision == TRX_FP64 ? 8 : 4;
   if ((s = ensure_buffer(c, p->aws, (size_t)B_max * t->dev.n_wn * esz, "plan workspace")) != TRX_OK)
     return fail(s);
@@ -240,7 +268,7 @@ extern "C" trx_status trx_plan_destroy(trx_plan* p) {
   hipStreamSynchronize(c->stream);
   drop_graph(p);
   if (p->cap) hipStreamDestroy(p->cap);
-  for (DevBuf* b : {&p->ws, &p->aws, &p->sched, &p->tune_binned, &p->tune_status})
+  for (DevBuf* b : {&p->ws, &p->aws, &p->sched, &p->grad, &p->tune_binned, &p->tune_status})
     if (b->ptr) hipFree(b->ptr);
   for (void* d : p->owned) hipFree(d);
   delete p;
@@ -260,18 +288,26 @@ extern "C" trx_status trx_plan_launch(trx_plan* p, const trx_batch* bt, double* 
   if (!p) return TRX_E_INVALID_ARG;
   trx_ctx* c = p->ctx;
   c->err.clear();
-  if (obs || sigma || chi2 || dT || dlog10vmr || dRp)
+  const bool grad = (p->flags & TRX_PLAN_GRAD) != 0;
+  if (!grad && (obs || sigma || chi2 || dT || dlog10vmr || dRp))
     return set_err(c, TRX_E_INVALID_ARG, "gradient outputs need a TRX_PLAN_GRAD plan");
+  if (grad && (!obs || !sigma || !chi2 || !dT || !dRp || (p->t->dev.n_abs > 0 && !dlog10vmr)))
+    return set_err(c, TRX_E_INVALID_ARG, "a gradient plan needs obs, sigma, chi2, dT, dlog10vmr and dRp");
+  if (grad && native)
+    return set_err(c, TRX_E_INVALID_ARG, "gradient plans do not write the native depth");
   trx_status s = check_launch(p, bt, binned, status, true);
   if (s != TRX_OK) return s;
   hipSetDevice(c->device);
+  const PlanIO io{native, binned, status, obs, sigma, chi2, dT, dlog10vmr, dRp};
   // eager launches for plans without a graph, and while profiling (the
   // per-kernel events cannot sit between the nodes of a replayed graph)
-  if (!(p->flags & TRX_PLAN_GRAPH) || c->profile)
-    return enqueue(p, bt, bt->B, nullptr, p->rc, native, binned, status);
+  if (!(p->flags & TRX_PLAN_GRAPH) || c->profile) return enqueue_io(p, bt, bt->B, nullptr, p->rc, io);
 
-  if (!p->exec || !same_batch(*bt, p->cap_batch) || native != p->cap_native || binned != p->cap_binned ||
-      status != p->cap_status) {
+  const void* gio[6] = {obs, sigma, chi2, dT, dlog10vmr, dRp};
+  bool same = p->exec && same_batch(*bt, p->cap_batch) && native == p->cap_native && binned == p->cap_binned &&
+              status == p->cap_status;
+  for (int k = 0; k < 6 && same; ++k) same = gio[k] == p->cap_grad[k];
+  if (!same) {
     drop_graph(p);
     hipStream_t user = c->stream;
     c->stream = p->cap;
@@ -282,7 +318,7 @@ extern "C" trx_status trx_plan_launch(trx_plan* p, const trx_batch* bt, double* 
       c->capturing = false;
       return hip_err(c, e, "graph capture");
     }
-    s = enqueue(p, bt, p->B_max, p->B_dev, p->rc, native, binned, status);
+    s = enqueue_io(p, bt, p->B_max, p->B_dev, p->rc, io);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(p->cap, &g);
     c->stream = user;
@@ -302,6 +338,7 @@ extern "C" trx_status trx_plan_launch(trx_plan* p, const trx_batch* bt, double* 
     p->cap_native = native;
     p->cap_binned = binned;
     p->cap_status = status;
+    for (int k = 0; k < 6; ++k) p->cap_grad[k] = gio[k];
   }
   hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->stream, p->B_dev, bt->B);
   hipError_t e = hipGetLastError();

@@ -379,6 +379,35 @@ class Plan:
         self.out_binned = None if bins is None else torch.empty(
             (self.B_max, bins.n), dtype=torch.float64, device=dev)
         self.out_native = None
+        self.grad = bool(grad)
+        if self.grad:
+            f64 = dict(dtype=torch.float64, device=dev)
+            self.obs = torch.zeros((self.B_max, bins.n), **f64)
+            self.sigma = torch.ones(bins.n, **f64)
+            self.out_chi2 = torch.empty(self.B_max, **f64)
+            self.out_dT = torch.empty(self.B_max * self.N_max, **f64)
+            self.out_dvmr = torch.empty((self.B_max, max(tables.n_abs, 1)), **f64)
+            self.out_dRp = torch.empty(self.B_max, **f64)
+
+    def launch_grad(self, batch, obs, sigma):
+        """trx_plan_launch of a gradient plan: chi^2 against obs [B, n_ch]
+        with sigma [n_ch] and its gradient.  obs and sigma are copied into
+        plan-owned tensors (stable pointers for the graph).  Returns dict
+        (chi2, dT [sum N], dlog10_vmr [B, n_abs], dRp, binned, status)."""
+        B = batch.B
+        self.obs[:B].copy_(torch.as_tensor(obs, dtype=torch.float64).reshape(B, -1))
+        self.sigma.copy_(torch.as_tensor(sigma, dtype=torch.float64))
+        self.ctx.bind_stream()
+        bc = batch.cstruct()
+        self.ctx.check(lib().trx_plan_launch(
+            self.h, ctypes.byref(bc), None, _ptr(self.out_binned), _ptr(self.out_status),
+            _ptr(self.obs), _ptr(self.sigma), _ptr(self.out_chi2), _ptr(self.out_dT),
+            _ptr(self.out_dvmr), _ptr(self.out_dRp)))
+        # dT is indexed by the batch's (absolute) layer offsets
+        nT = int(batch.T.numel()) if hasattr(batch, "T") else int(batch.db.layer_off[batch.b + 1])
+        return {"chi2": self.out_chi2[:B], "dT": self.out_dT[:nT],
+                "dlog10_vmr": self.out_dvmr[:B, :self.tables.n_abs], "dRp": self.out_dRp[:B],
+                "binned": self.out_binned[:B], "status": self.out_status[:B]}
 
     def launch(self, batch, native=False, binned=True, out_native=None, out_binned=None,
                out_status=None):

@@ -126,3 +126,38 @@ def test_autograd_function(gpu_ctx, problem):
     assert torch.allclose(R.grad, ref["dRp"] * w)
     bins.close()
     Tt.close()
+
+
+def test_gradient_plan_graph(gpu_ctx, problem):
+    """A graph-captured gradient plan reproduces trx_chi2_grad (up to the
+    summation order of the per-model atomics), over replays with unrelated
+    eager work in between and for a smaller B on the same graph."""
+    from paper_1912_07759_amd import trx
+    tables, batch, ch, obs, sigma = problem
+    Tt = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, Tt, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=100)
+    ref = {k: v.cpu().numpy() for k, v in
+           trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, sigma, "fp32").items() if v is not None}
+    plan = trx.Plan(gpu_ctx, Tt, bins, B_max=batch.B, N_max=100, precision="fp32", graph=True,
+                    grad=True)
+
+    def check(out, n):
+        for k in ("chi2", "dT", "dlog10_vmr", "dRp"):
+            got = out[k].cpu().numpy()
+            want = ref[k][:n] if k != "dT" else ref[k][:int(batch.layer_off[n])]
+            assert np.allclose(got, want, rtol=1e-5, atol=1e-9 * np.max(np.abs(want))), k
+    for r in range(3):
+        x = torch.randn(1 << 18, device="cuda").sum()
+        torch.cuda.synchronize()
+        out = plan.launch_grad(db, obs, sigma)
+        torch.cuda.synchronize()
+        assert float(x) == float(x)
+        check(out, batch.B)
+    sub = db.view(0)
+    out = plan.launch_grad(sub, obs[:1], sigma)
+    torch.cuda.synchronize()
+    check(out, 1)
+    plan.close()
+    bins.close()
+    Tt.close()
