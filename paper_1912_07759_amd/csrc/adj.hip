@@ -10,13 +10,14 @@
 //   h_j)/Rs^2 (transit-depth equations): Abar_j = sum_i Dbar_i (1 - e^{-tau}),
 //   taubar_ij = Dbar_i A_j e^{-tau_ij};
 //   tau = dl kappa (eq. tot_opt_dpth): kappabar = dl^T taubar, and the
-//   path-length cotangent dlbar = taubar kappa^T is never formed: its
-//   contractions with the chord derivatives are taken per column,
-//     zbar_j  += sum_i taubar_ij (Fz kappa)_ji,   Fz = d dl / d z_j,
-//     Rpbar   += sum_i sum_j taubar_ij (FR kappa)_ji,   FR = d dl / d Rp,
-//     hbar_{k+1} += sum_i (kappa_ki - kappa_{k+1,i}) (Gh^T taubar)_ki,
-//   with Gh_{j,k+1} = d(2 q_j(h_{k+1}))/dh_{k+1} (the shell boundary h_m
-//   enters dl[j, m-1] with + and dl[j, m] with -);
+//   path-length cotangent dlbar = taubar kappa^T is never formed.  With
+//   Q_m = q_j(h_m) the chord of ray j is written by parts,
+//   tau_j = 2 sum_{m>j} Q_m (kappa_{m-1} - kappa_m), and per column
+//     zbar_j  += taubar_ij sum_m Gz_jm (kappa_{m-1} - kappa_m),
+//     Rpbar   += sum_j taubar_ij sum_m GR_jm (kappa_{m-1} - kappa_m),
+//     hbar_m  += (kappa_{m-1} - kappa_m) sum_{j<m} Gh_jm taubar_ij,
+//   with Gz, GR, Gh = 2 dQ_m/d(z_j, Rp, h_m): every sum has terms of one
+//   sign where kappa falls with height (no cancellation in FP32);
 //   kappa (equations opt_dpth, cia_opt_dpth, contrib; Opacities section):
 //     Tbar_k += sum_i kappabar_ki dkappa_ki/dT_k (bracket slopes and
 //     d rho/dT from the derivative records), and the mixing-ratio adjoints
@@ -40,7 +41,7 @@ using stage::stage_rows;
 constexpr int kWaves = 4;
 constexpr int kCols = 64;
 constexpr int kRows = 96;
-constexpr int kRayRegs = TRX_MAX_LAYERS_MFMA / kWaves;   // rays per wave
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 static_assert(stage::kWaves == kWaves && stage::kCols == kCols, "staging shape");
 static_assert(kRows >= kMaxU + kMaxV, "staging capacity");
 
@@ -121,6 +122,8 @@ struct ItemLds {
   int32_t* tids; // [kRows]
   float* chi;    // [TRX_MAX_ABSORBERS]
   float* ciaw;   // [TRX_MAX_CIA]
+  float* rcol;   // [64] Rayleigh sum per column
+  float* pacc;   // [G.n] this item's partial sums (GradAcc offsets)
 };
 
 __host__ __device__ inline size_t carve(const Layout& L, unsigned char* base, ItemLds* out) {
@@ -143,6 +146,8 @@ __host__ __device__ inline size_t carve(const Layout& L, unsigned char* base, It
   s.tids = (int32_t*)take(kRows * 4);
   s.chi = (float*)take(TRX_MAX_ABSORBERS * 4);
   s.ciaw = (float*)take(TRX_MAX_CIA * 4);
+  s.rcol = (float*)take((size_t)kCols * 4);
+  s.pacc = (float*)take((size_t)make_grad_acc(NP).n * 4);
   if (out) *out = s;
   return o;
 }
@@ -208,104 +213,248 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   if (tb.has_rayleigh)
     for (int q = 0; q < tb.n_abs + 2; ++q) R = fmaf(hd->chi_s32[q], tb.ray32[(int64_t)q * W + cc], R);
   for (int e = tid; e < (nU + nV) * kCols; e += 64 * kWaves) s.sh[e] = 0.f;
-  if (tid < kCols) s.rh[tid] = 0.f;
+  for (int e = tid; e < G.n; e += 64 * kWaves) s.pacc[e] = 0.f;
+  if (tid < kCols) {
+    s.rh[tid] = 0.f;
+    s.rcol[tid] = R;
+  }
   __syncthreads();
 
-  // kappa (or, with the derivative records, dkappa/dT) of layer k
-  auto comb = [&](int k, const float* w) -> float {
-    const uint32_t sa = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].x);
-    float v = w[0] * rows[(sa & 0xff) * kCols + lane];
-    v = fmaf(w[1], rows[((sa >> 8) & 0xff) * kCols + lane], v);
-    v = fmaf(w[2], rows[((sa >> 16) & 0xff) * kCols + lane], v);
-    v = fmaf(w[3], rows[(sa >> 24) * kCols + lane], v);
-    v = fmaf(w[4], R, v);
+  // kappa (or, with the derivative records, dkappa/dT) of layer k at
+  // column c; the slot words are read per lane (k may differ across lanes)
+  auto comb = [&](int k, const float* w, int c) -> float {
+    const int2 sk = s.sl[k];
+    const uint32_t sa = (uint32_t)sk.x;
+    float v = w[0] * rows[(sa & 0xff) * kCols + c];
+    v = fmaf(w[1], rows[((sa >> 8) & 0xff) * kCols + c], v);
+    v = fmaf(w[2], rows[((sa >> 16) & 0xff) * kCols + c], v);
+    v = fmaf(w[3], rows[(sa >> 24) * kCols + c], v);
+    v = fmaf(w[4], s.rcol[c], v);
     if (has_cia) {
-      const uint32_t sc = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].y);
-      v = fmaf(w[5], crows[(sc & 0xff) * kCols + lane], v);
-      v = fmaf(w[6], crows[((sc >> 8) & 0xff) * kCols + lane], v);
+      const uint32_t sc = (uint32_t)sk.y;
+      v = fmaf(w[5], crows[(sc & 0xff) * kCols + c], v);
+      v = fmaf(w[6], crows[((sc >> 8) & 0xff) * kCols + c], v);
     }
     return v;
   };
 
-  // A: kappa of every layer
-  for (int k = wave; k < N; k += kWaves) s.kt[k * kCols + lane] = comb(k, s.lw + 8 * k);
+  // A: kappa of every layer of the padded ray blocks (zero past N)
+  const int nrb = hd->nrb;
+  const int NR = 32 * nrb;
+  for (int k = wave; k < NR; k += kWaves) s.kt[k * kCols + lane] = k < N ? comb(k, s.lw + 8 * k, lane) : 0.f;
   __syncthreads();
 
-  // B: per ray j (wave w: j = w, w + 4, ...) tau, (Fz kappa)_j, (FR kappa)_j
-  double* acc = a.acc + (int64_t)b * G.n;
-  const float Db = valid ? a.dbar[(int64_t)b * W + col] : 0.f;
-  const float4* __restrict__ m3 = reinterpret_cast<const float4*>(slab + L.off_m3);
-  float tbr[kRayRegs];
+  float* acc = s.pacc;   // per-item partial sums (LDS)
+  const int hl = lane >> 5, lc = lane & 31;
+  // column sums over the 32 lanes of a half-wave (one accumulator column each)
+  auto half_sum = [](float v) {
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
+
+  // B: per (32-ray, 32-column) tile, on v_mfma_f32_32x32x2f32 with K = two
+  // layers per step (A lane l: [ray l%32][layer l/32], B lane l:
+  // [layer l/32][column l%32], C register q: ray 8(q/4) + 4(l/32) + q%4,
+  // column l%32):
+  //   tau = dl kappa, U = Gz dkappa, V = GR dkappa, dkappa_k = kappa_k - kappa_{k+1};
+  // then taubar = Dbar A e^{-tau}, Abar_j, zbar_j, Rpbar column sums.
+  // Tiles t = wave, wave + 4, ... of nrb x 2; each wave keeps its taubar
+  // tiles in registers until every wave is done with kappa.
+  const float4* m3 = reinterpret_cast<const float4*>(slab + L.off_m3);
+  constexpr int kTilesMax = (TRX_MAX_LAYERS_MFMA / 32) * 2;
+  constexpr int kTW = (kTilesMax + kWaves - 1) / kWaves;
+  f32x16 tbt[kTW];
   float rp = 0.f;
 #pragma unroll
-  for (int r = 0; r < kRayRegs; ++r) {
-    const int j = wave + kWaves * r;
-    float tv = 0.f;
-    if (j < N) {
-      float tau = 0.f, u = 0.f, v = 0.f;
-      const float4* __restrict__ row = m3 + (int64_t)j * NP;
-      for (int k = j; k < N; ++k) {
-        const float4 m = row[k];
-        const float x = s.kt[k * kCols + lane];
-        tau = fmaf(m.x, x, tau);
-        u = fmaf(m.y, x, u);
-        v = fmaf(m.z, x, v);
+  for (int ti = 0; ti < kTW; ++ti) {
+    const int t = wave + kWaves * ti;
+    tbt[ti] = f32x16{};
+    if (t < 2 * nrb) {
+      const int rb = t >> 1, cb = t & 1;
+      const int c = 32 * cb + lc;
+      f32x16 tau = f32x16{}, U = f32x16{}, V = f32x16{};
+      const float4* arow = m3 + (int64_t)(32 * rb + lc) * NP;
+      // eight K-steps per round: their A loads are issued before the products
+      for (int k0 = 32 * rb; k0 < N; k0 += 16) {
+        float4 m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + 2 * u + hl;
+          m[u] = k < NR ? arow[k] : float4{};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (k0 + 2 * u < N) {
+            const int k = k0 + 2 * u + hl;
+            const float x = s.kt[k * kCols + c];
+            const float xn = k + 1 < NR ? s.kt[(k + 1) * kCols + c] : 0.f;   // kappa_N = 0
+            const float d = x - xn;
+            tau = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].x, x, tau, 0, 0, 0);
+            U = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].y, d, U, 0, 0, 0);
+            V = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].z, d, V, 0, 0, 0);
+          }
+        }
       }
-      const float e = __expf(-tau);
-      tv = Db * s.lw[8 * j + 7] * e;
-      const float ab = wave_sum(-Db * expm1f(-tau));
-      const float zb = wave_sum(tv * u);
-      if (lane == 0) {
-        atomicAdd(acc + G.o_A + j, (double)ab);
-        atomicAdd(acc + G.o_z + j, (double)zb);
+      const int cg = col0 + c;
+      const float Db = (cg >= lo && cg < hi) ? a.dbar[(int64_t)b * W + cg] : 0.f;
+      f32x16 tb, ab, zb;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
+        const float e = __expf(-tau[q]);
+        const float tv = Db * s.lw[8 * j + 7] * e;
+        tb[q] = tv;
+        ab[q] = -Db * expm1f(-tau[q]);
+        zb[q] = tv * U[q];
+        rp = fmaf(tv, V[q], rp);
       }
-      rp = fmaf(tv, v, rp);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        ab[q] = half_sum(ab[q]);
+        zb[q] = half_sum(zb[q]);
+      }
+      if (lc == 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
+          if (j < N) {
+            atomicAdd(acc + G.o_A + j, ab[q]);
+            atomicAdd(acc + G.o_z + j, zb[q]);
+          }
+        }
+      }
+      tbt[ti] = tb;
     }
-    tbr[r] = tv;
   }
   {
     const float t = wave_sum(rp);
-    if (lane == 0) atomicAdd(acc + G.o_Rp, (double)t);
+    if (lane == 0) atomicAdd(acc + G.o_Rp, t);
   }
   __syncthreads();   // kappa is no longer read: its space takes taubar
 #pragma unroll
-  for (int r = 0; r < kRayRegs; ++r) {
-    const int j = wave + kWaves * r;
-    if (j < N) s.kt[j * kCols + lane] = tbr[r];
+  for (int ti = 0; ti < kTW; ++ti) {
+    const int t = wave + kWaves * ti;
+    if (t < 2 * nrb) {
+      const int rb = t >> 1, cb = t & 1;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
+        s.kt[j * kCols + 32 * cb + lc] = tbt[ti][q];
+      }
+    }
   }
   __syncthreads();
 
-  // C: per layer k kappabar = (dl^T taubar)_k and (Gh^T taubar)_k
-  const float2* __restrict__ mt = reinterpret_cast<const float2*>(slab + L.off_mt);
-  for (int k = wave; k < N; k += kWaves) {
-    float kb = 0.f, g = 0.f;
-    const float2* __restrict__ row = mt + (int64_t)k * NP;
-    for (int j = 0; j <= k; ++j) {
-      const float2 m = row[j];
-      const float t = s.kt[j * kCols + lane];
-      kb = fmaf(m.x, t, kb);
-      g = fmaf(m.y, t, g);
+  // C: per (32-layer, 32-column) tile: kappabar = dl^T taubar and
+  // gbar = Gh^T taubar (K = two rays per step, rays j <= layer), then per
+  // (layer, column) the boundary, temperature and mixed-row adjoints
+  const float2* mt = reinterpret_cast<const float2*>(slab + L.off_mt);
+  for (int t = wave; t < 2 * nrb; t += kWaves) {
+    const int lb = t >> 1, cb = t & 1;
+    const int c = 32 * cb + lc;
+    f32x16 kb = f32x16{}, gb = f32x16{};
+    const float2* arow = mt + (int64_t)(32 * lb + lc) * NP;
+    const int jmax = min(N, 32 * lb + 32);
+    for (int j0 = 0; j0 < jmax; j0 += 16) {
+      float2 m[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + 2 * u + hl;
+        m[u] = j < NR ? arow[j] : float2{};
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (j0 + 2 * u < jmax) {
+          const int j = j0 + 2 * u + hl;
+          const float x = s.kt[j * kCols + c];
+          kb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].x, x, kb, 0, 0, 0);
+          gb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].y, x, gb, 0, 0, 0);
+        }
+      }
     }
-    const float* w = s.lw + 8 * k;
-    const float kap = comb(k, w);
-    const float kap1 = k + 1 < N ? comb(k + 1, s.lw + 8 * (k + 1)) : 0.f;
-    const float dk = comb(k, s.lwd + 8 * k);
-    const float hb = wave_sum(g * (kap - kap1));
-    const float Tb = wave_sum(kb * dk);
-    if (lane == 0) {
-      atomicAdd(acc + G.o_h + k + 1, (double)hb);
-      atomicAdd(acc + G.o_T + k, (double)Tb);
+    // per lane: layers k = 32 lb + 8 r + 4 (l/32) + i (runs r of four
+    // consecutive layers) at column c.  kappa of a run's five layers is
+    // computed once; the scatter into the mixed-row adjoints accumulates in
+    // registers while consecutive layers keep their corner slots and is
+    // flushed to LDS when they change; the column sums of all 16 layers are
+    // reduced together at the end.
+    float hs[16], ts[16];
+    float rsum = 0.f;
+    uint32_t psa = 0xffffffffu, psc = 0xffffffffu;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, c0 = 0.f, c1 = 0.f;
+    auto flush_abs = [&]() {
+      if (psa != 0xffffffffu) {
+        atomicAdd(&s.sh[(psa & 0xff) * kCols + c], a0);
+        atomicAdd(&s.sh[((psa >> 8) & 0xff) * kCols + c], a1);
+        atomicAdd(&s.sh[((psa >> 16) & 0xff) * kCols + c], a2);
+        atomicAdd(&s.sh[(psa >> 24) * kCols + c], a3);
+      }
+      a0 = a1 = a2 = a3 = 0.f;
+    };
+    auto flush_cia = [&]() {
+      if (psc != 0xffffffffu) {
+        atomicAdd(&s.sh[(nU + (psc & 0xff)) * kCols + c], c0);
+        atomicAdd(&s.sh[(nU + ((psc >> 8) & 0xff)) * kCols + c], c1);
+      }
+      c0 = c1 = 0.f;
+    };
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = 32 * lb + 8 * r + 4 * hl;
+      float kp[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) kp[i] = k0 + i < N ? comb(k0 + i, s.lw + 8 * (k0 + i), c) : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = 4 * r + i;
+        const int k = k0 + i;
+        hs[q] = 0.f;
+        ts[q] = 0.f;
+        if (k < N) {
+          const float* w = s.lw + 8 * k;
+          const float dk = comb(k, s.lwd + 8 * k, c);
+          hs[q] = gb[q] * (kp[i] - kp[i + 1]);
+          ts[q] = kb[q] * dk;
+          const float kv = kb[q];
+          const int2 sk = s.sl[k];
+          if ((uint32_t)sk.x != psa) {
+            flush_abs();
+            psa = (uint32_t)sk.x;
+          }
+          a0 = fmaf(w[0], kv, a0);
+          a1 = fmaf(w[1], kv, a1);
+          a2 = fmaf(w[2], kv, a2);
+          a3 = fmaf(w[3], kv, a3);
+          rsum = fmaf(w[4], kv, rsum);
+          if (has_cia) {
+            if ((uint32_t)sk.y != psc) {
+              flush_cia();
+              psc = (uint32_t)sk.y;
+            }
+            c0 = fmaf(w[5], kv, c0);
+            c1 = fmaf(w[6], kv, c1);
+          }
+        }
+      }
     }
-    const uint32_t sa = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].x);
-    atomicAdd(&s.sh[(sa & 0xff) * kCols + lane], w[0] * kb);
-    atomicAdd(&s.sh[((sa >> 8) & 0xff) * kCols + lane], w[1] * kb);
-    atomicAdd(&s.sh[((sa >> 16) & 0xff) * kCols + lane], w[2] * kb);
-    atomicAdd(&s.sh[(sa >> 24) * kCols + lane], w[3] * kb);
-    atomicAdd(&s.rh[lane], w[4] * kb);
-    if (has_cia) {
-      const uint32_t sc = __builtin_amdgcn_readfirstlane((uint32_t)s.sl[k].y);
-      atomicAdd(&s.sh[(nU + (sc & 0xff)) * kCols + lane], w[5] * kb);
-      atomicAdd(&s.sh[(nU + ((sc >> 8) & 0xff)) * kCols + lane], w[6] * kb);
+    flush_abs();
+    if (has_cia) flush_cia();
+    atomicAdd(&s.rh[c], rsum);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      hs[q] = half_sum(hs[q]);
+      ts[q] = half_sum(ts[q]);
+    }
+    if (lc == 0) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
+        if (k < N) {
+          atomicAdd(acc + G.o_h + k + 1, hs[q]);
+          atomicAdd(acc + G.o_T + k, ts[q]);
+        }
+      }
     }
   }
   __syncthreads();
@@ -313,24 +462,43 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   // D: mixing-ratio adjoints: corner rows against each absorber's table,
   // CIA node rows against each pair's table, the Rayleigh row per species
   const int rec = (int)(abs_stride * 4 < 0x7fffffff ? abs_stride * 4 : 0x7fffffff);
-  for (int i = 0; i < tb.n_abs; ++i) {
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)(tb.xsec32 + (int64_t)i * abs_stride), (short)0, rec, kRsrcWord3);
-    float acc_i = 0.f;
-    for (int u0 = wave; u0 < nU; u0 += kWaves * 8) {
-      float v[8];
+  constexpr int DG = 8, DA = 4;   // corners x absorbers in flight
+  for (int i0 = 0; i0 < tb.n_abs; i0 += DA) {
+    float acc_i[DA] = {0.f, 0.f, 0.f, 0.f};
+    for (int u0 = wave; u0 < nU; u0 += kWaves * DG) {
+      int soff[DG];
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
+      for (int g = 0; g < DG; ++g) {
         const int u = u0 + kWaves * g < nU ? u0 + kWaves * g : u0;
-        v[g] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-            rs, cc * 4, __builtin_amdgcn_readfirstlane(s.ids[u]) * W * 4, 0));
+        soff[g] = __builtin_amdgcn_readfirstlane(s.ids[u]) * W * 4;
+      }
+      float v[DA][DG];
+#pragma unroll
+      for (int ii = 0; ii < DA; ++ii) {
+        if (i0 + ii < tb.n_abs) {
+          const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+              (void*)(tb.xsec32 + (int64_t)(i0 + ii) * abs_stride), (short)0, rec, kRsrcWord3);
+#pragma unroll
+          for (int g = 0; g < DG; ++g)
+            v[ii][g] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, cc * 4, soff[g], 0));
+        }
       }
 #pragma unroll
-      for (int g = 0; g < 8; ++g)
-        if (u0 + kWaves * g < nU) acc_i = fmaf(s.sh[(u0 + kWaves * g) * kCols + lane], v[g], acc_i);
+      for (int ii = 0; ii < DA; ++ii) {
+        if (i0 + ii < tb.n_abs) {
+#pragma unroll
+          for (int g = 0; g < DG; ++g)
+            if (u0 + kWaves * g < nU) acc_i[ii] = fmaf(s.sh[(u0 + kWaves * g) * kCols + lane], v[ii][g], acc_i[ii]);
+        }
+      }
     }
-    acc_i = wave_sum(acc_i);
-    if (lane == 0) atomicAdd(acc + G.o_chi + i, (double)acc_i);
+#pragma unroll
+    for (int ii = 0; ii < DA; ++ii) {
+      if (i0 + ii < tb.n_abs) {
+        const float t = wave_sum(acc_i[ii]);
+        if (lane == 0) atomicAdd(acc + G.o_chi + i0 + ii, t);
+      }
+    }
   }
   if (has_cia) {
     for (int p = 0; p < tb.n_cia; ++p) {
@@ -339,15 +507,38 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
       for (int t = wave; t < nV; t += kWaves)
         acc_p = fmaf(s.sh[(nU + t) * kCols + lane], tp[(int64_t)s.tids[t] * W + cc], acc_p);
       acc_p = wave_sum(acc_p);
-      if (lane == 0) atomicAdd(acc + G.o_cw + p, (double)acc_p);
+      if (lane == 0) atomicAdd(acc + G.o_cw + p, acc_p);
     }
   }
   if (tb.has_rayleigh) {
     const float rl = s.rh[lane];
     for (int q = wave; q < tb.n_abs + 2; q += kWaves) {
       const float t = wave_sum(rl * tb.ray32[(int64_t)q * W + cc]);
-      if (lane == 0) atomicAdd(acc + G.o_chi + q, (double)t);
+      if (lane == 0) atomicAdd(acc + G.o_chi + q, t);
     }
+  }
+  // this item's partial sums, reduced per model in a fixed order later
+  __syncthreads();
+  float* dst = a.part + ((int64_t)b * a.n_spans + span) * G.n;
+  for (int e = tid; e < G.n; e += 64 * kWaves) dst[e] = s.pacc[e];
+}
+
+// ---- per model: sum of the item partials over its spans (FP64) -----------
+__global__ __launch_bounds__(256) void k_adj_reduce(AdjArgs a) {
+  const int b = blockIdx.x;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if (b >= B) return;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(a.ws + (int64_t)b * a.L.slab);
+  if (hd->n == 0) return;
+  const MList* ml = reinterpret_cast<const MList*>(a.ws + (int64_t)b * a.L.slab + a.L.off_mlist);
+  if (ml->nU + ml->nV > kRows || ml->nV > kMListV) return;   // flagged by the item kernel
+  const int n = a.G.n;
+  const float* src = a.part + (int64_t)b * a.n_spans * n;
+  double* acc = a.acc + (int64_t)b * n;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    double t = 0.0;
+    for (int sp = hd->span_lo; sp < hd->span_hi; ++sp) t += src[(int64_t)sp * n + e];
+    acc[e] += t;
   }
 }
 
@@ -465,6 +656,11 @@ hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   const int spans = (a.tab.n_wn + kCols - 1) / kCols;
   hipLaunchKernelGGL(k_adj_item, dim3(B_grid, spans), dim3(64 * kWaves), lds, s, a);
   return hipGetLastError();
+}
+
+void launch_adj_reduce(const AdjArgs& a, int B_grid, hipStream_t s) {
+  if (B_grid <= 0) return;
+  hipLaunchKernelGGL(k_adj_reduce, dim3(B_grid), dim3(256), 0, s, a);
 }
 
 void launch_adj_geom(const AdjArgs& a, int B_grid, hipStream_t s) {

@@ -418,7 +418,9 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
 
 size_t trx::grad_scratch_bytes(int B, int n_wn, int n_ch, int NP) {
   const GradAcc G = make_grad_acc(NP);
-  return (size_t)B * G.n * 8 + (size_t)B * n_ch * 8 + (size_t)B * n_wn * 4 + 1024;
+  const size_t spans = (size_t)(n_wn + kSpanCols - 1) / kSpanCols;
+  return (size_t)B * G.n * 8 + (size_t)B * n_ch * 8 + (size_t)B * n_wn * 4 + 256 +
+         (size_t)B * spans * G.n * 4 + 1024;
 }
 
 trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B,
@@ -443,6 +445,7 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   double* acc = (double*)gp;
   double* binned_tmp = (double*)(gp + (size_t)B * G.n * 8);
   float* dbar = (float*)(gp + (size_t)B * G.n * 8 + (size_t)B * bins->n_ch * 8);
+  float* part = (float*)(gp + ((size_t)B * G.n * 8 + (size_t)B * bins->n_ch * 8 + (size_t)B * W * 4 + 255) / 256 * 256);
   double* binned = depth_binned ? depth_binned : binned_tmp;
   trx_status s = enqueue_forward(c, t, db, B, B_dev, max_layers, bins, precision, rc, (uint8_t*)ws.ptr,
                                  aws.ptr, SchedBufs::carve(sched.ptr, B), nullptr, binned, status, true);
@@ -464,6 +467,8 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   a.chi2 = chi2;
   a.dbar = dbar;
   a.acc = acc;
+  a.part = part;
+  a.n_spans = (W + kSpanCols - 1) / kSpanCols;
   a.dT = dT;
   a.dvmr = dvmr;
   a.dRp = dRp;
@@ -479,6 +484,7 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   }
   {
     ProfScope ps(c, TRX_KERNEL_GEOM_ADJ);
+    launch_adj_reduce(a, B, c->stream);
     launch_adj_geom(a, B, c->stream);
   }
   hipError_t e = hipGetLastError();

@@ -420,10 +420,16 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     return 2.0 * (hk1 - hk) * (2.0 * Rp + hk + hk1) / (q1 + q0);
   };
   if (L.grad) {
-    // derivative matrices of the chords (gradient layouts): with
-    // q_j(h) = sqrt((h - z_j)(2Rp + h + z_j)), dl[j,k] = 2 (q_j(h_{k+1}) -
-    // [k > j] q_j(h_k)), dq/dz_j = -(Rp + z_j)/q, dq/dRp = (h - z_j)/q,
-    // dq/dh = (Rp + h)/q; the zero chord of the top ray has no derivative.
+    // derivative matrices of the chords (gradient layouts).  With
+    // q_j(h) = sqrt((h - z_j)(2Rp + h + z_j)) and Q_m = q_j(h_m) (Q_j = 0),
+    // dl[j,k] = 2 (Q_{k+1} - Q_k), so by parts
+    //   tau_j = sum_k dl[j,k] kappa_k = 2 sum_{m > j} Q_m (kappa_{m-1} - kappa_m)
+    // (kappa_N = 0): the derivatives in z_j and Rp are sums over the layer
+    // differences with weights 2 dQ_m/dz_j = -2 (Rp + z_j)/Q_m and
+    // 2 dQ_m/dRp = 2 (h_m - z_j)/Q_m, free of the cancellation between the
+    // diagonal chord and the others; the boundary h_m enters with
+    // 2 dQ_m/dh_m = 2 (Rp + h_m)/Q_m.  Stored at [j][k = m - 1]; the zero
+    // chord of the top ray (Q_N = 0 for j = N - 1) has no derivative.
     float4* m3 = reinterpret_cast<float4*>(slab + L.off_m3);
     float2* mt = reinterpret_cast<float2*>(slab + L.off_mt);
     auto hb = [&](int k) -> double {
@@ -441,16 +447,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         double fz = 0.0, fr = 0.0;
         if (q1 > 0.0) {
           gh = (float)(2.0 * (Rp + h1) / q1);
-          if (k == j) {
-            fz = -2.0 * (Rp + zj) / q1;
-            fr = 2.0 * (h1 - zj) / q1;
-          } else {
-            const double h0 = hb(k);
-            const double q0 = sqrt((h0 - zj) * (2.0 * Rp + h0 + zj));
-            // -2 (Rp + z_j)(1/q1 - 1/q0) = (Rp + z_j) dl / (q0 q1)
-            fz = (Rp + zj) * d / (q0 * q1);
-            fr = 2.0 * ((h1 - zj) / q1 - (h0 - zj) / q0);
-          }
+          fz = -2.0 * (Rp + zj) / q1;
+          fr = 2.0 * (h1 - zj) / q1;
         }
         v = make_float4((float)d, (float)fz, (float)fr, 0.f);
       }

@@ -85,7 +85,7 @@ struct Layout {
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise):
   int64_t off_lwd32;       // [NP][8] FP32 d(record weight)/dT at fixed P
-  int64_t off_m3;          // [NP][NP] float4 (dl, d dl/dz_j, d dl/dRp, 0), row = ray j
+  int64_t off_m3;          // [NP][NP] float4 (dl_jk, -2(Rp+z_j)/Q, 2(h_{k+1}-z_j)/Q, 0), Q = q_j(h_{k+1}), row = ray j
   int64_t off_mt;          // [NP][NP] float2 (dl_jk, d(2 q_j(h_{k+1}))/dh_{k+1}), row = layer k
   int32_t grad;
   int64_t slab;            // bytes per model (multiple of 256)
@@ -251,7 +251,7 @@ struct GradAcc {
   int32_t NP;
   int32_t o_A, o_z, o_h, o_T, o_Rp, o_chi, o_cw, n;
 };
-inline GradAcc make_grad_acc(int NP) {
+__host__ __device__ inline GradAcc make_grad_acc(int NP) {
   GradAcc g{};
   g.NP = NP;
   int o = 0;
@@ -286,6 +286,8 @@ struct AdjArgs {
   double* chi2;           // [B]
   float* dbar;            // [B][n_wn] dchi2/dD_i inside the window
   double* acc;            // [B][G.n]
+  float* part;            // [B][n_spans][G.n] per-item partial sums (same offsets)
+  int32_t n_spans;        // 64-column spans of the grid
   double* dT;             // [layer_off[B]]
   double* dvmr;           // [B][n_abs]
   double* dRp;            // [B]
@@ -294,6 +296,7 @@ struct AdjArgs {
 size_t adj_item_lds_bytes(const Layout& L);
 void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s);
 hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s);
+void launch_adj_reduce(const AdjArgs& a, int B_grid, hipStream_t s);
 void launch_adj_geom(const AdjArgs& a, int B_grid, hipStream_t s);
 
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s);
