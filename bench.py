@@ -45,6 +45,10 @@ def parse():
     p.add_argument("--fp64-looped", type=int, default=256, metavar="M",
                    help="time the plain FP64 path one model per launch on M models "
                         "(0: skip); the rate is scaled to the batch")
+    p.add_argument("--no-grad", action="store_true",
+                   help="skip the gradient leg (chi^2 gradients of the 256-point workload)")
+    p.add_argument("--grad-precision", default="fp64", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
+                   help="forward pass of the gradient leg (the residual needs its accuracy)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="also run one plain device copy of this many MiB (reference "
                         "for the HBM byte counters of a profiler run)")
@@ -77,6 +81,78 @@ def traffic_of(kernel, precision):
         return float(fields["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def gradient_leg(args, ctx, trx, torch):
+    """chi^2 gradients of 256 parameter points (100-layer perturbed Guillot
+    profiles, 7 absorbers, 50000-point tables, 100 channels, 50 ppm noise on
+    the truth's binned spectrum) from one graph-captured gradient plan."""
+    from synth.workloads import make_config, observation_noise
+    t0 = time.time()
+    tables, batch, ch = make_config(4)
+    log(f"gradient inputs generated in {time.time() - t0:.1f} s: B={batch.B}, W={tables.n_wn}")
+    T = trx.Tables.from_synth(ctx, tables)
+    bins = trx.Bins(ctx, T, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=100)
+    B = batch.B
+    # the observation: the truth (point 0) binned by the FP64 path, plus noise
+    _, truth, _ = trx.forward(ctx, T, trx.DeviceBatch.from_synth(batch.subset([0]), max_layers=100),
+                              bins, "fp64", native=False)
+    noise, sigma = observation_noise(4, 1, bins.n)
+    obs_row = truth[0].cpu().numpy() + noise[0]
+    obs = np.tile(obs_row, (B, 1))
+    plan = trx.Plan(ctx, T, bins, B_max=B, N_max=100, precision=args.grad_precision, graph=True,
+                    grad=True)
+    plan.autotune(db)
+    ms = time_steps(lambda: plan.launch_grad(db, obs, sigma), args.steps, args.warmup)
+    out = plan.launch_grad(db, obs, sigma)
+    torch.cuda.synchronize()
+    assert int((out["status"] != 0).sum()) == 0
+    ctx.profile(True)
+    for _ in range(max(2, args.steps // 3)):
+        plan.launch_grad(db, obs, sigma)
+    kms = {}
+    for k, name in ((trx.KERNEL_FORWARD, "forward"), (trx.KERNEL_ADJOINT, "adjoint_item"),
+                    (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")):
+        tot, n = ctx.profile_read(k)
+        kms[name] = round(tot / max(n, 1), 4)
+    ctx.profile(False)
+    res = {"metric": "gradient evals/s", "value": round(B / (ms * 1e-3), 1),
+           "unit": "gradient evals/s", "ms_per_step": round(ms, 3),
+           "precision": args.grad_precision, "kernel_ms": kms,
+           "config": {"workload": "gradient-256-100L-7abs-50kwn", "models": B, "layers": 100,
+                      "absorbers": tables.n_abs, "wavenumbers": tables.n_wn,
+                      "channels": bins.n, "noise_ppm": 50, "variant": plan.describe()}}
+    log(f"gradient: {ms:.3f} ms/step ({B / (ms * 1e-3):.1f} evals/s)")
+    if not args.no_cpu:
+        import oracle
+        from threadpoolctl import threadpool_limits
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        off = batch.layer_off
+        errs, done, t_cpu = [], 0, 0.0
+        with threadpool_limits(limits=1):
+            for b in range(B):
+                if done and t_cpu > args.cpu_seconds:
+                    break
+                t1 = time.perf_counter()
+                ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
+                t_cpu += time.perf_counter() - t1
+                done += 1
+                v = np.concatenate([g["dT"][off[b]:off[b + 1]], g["dlog10_vmr"][b], [g["dRp"][b]]])
+                r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
+                big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
+                errs.append(max(np.linalg.norm(v - r) / np.linalg.norm(r),
+                                float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big])))))
+        res["error"] = {"max_rel_err_gradient": max(errs), "models_checked": done}
+        res["cpu_baseline"] = {"value": round(done / t_cpu, 4), "unit": "gradient evals/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {done} of {B} points, {t_cpu:.1f} s "
+                                         f"single-threaded numpy FP64 reverse mode"}
+        log(f"gradient oracle: {done} points in {t_cpu:.1f} s; max err {max(errs):.2e}")
+    plan.close()
+    bins.close()
+    T.close()
+    return res
 
 
 def time_steps(fn, steps, warmup):
@@ -201,6 +277,10 @@ def main():
                          "speedup_vs_looped": round(B / (ms * 1e-3) / rate, 2)})
             log(f"fp64 looped: {rate:.1f} spectra/s")
 
+    grad = None
+    if not args.no_grad:
+        grad = gradient_leg(args, ctx, trx, torch)
+
     # oracle leg: CPU baseline rate and the error stamp of sampled models
     cpu = None
     err = None
@@ -245,7 +325,7 @@ def main():
                       "channels": bins.n, "precision": args.precision,
                       "launch": "hip graph of one plan", "variant": variant},
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
-           "kernel_ms": {k: round(v, 4) for k, v in kms.items()}}
+           "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad}
     print(json.dumps(out), flush=True)
 
 

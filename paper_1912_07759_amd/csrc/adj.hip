@@ -38,11 +38,11 @@ namespace {
 
 using stage::kRsrcWord3;
 using stage::stage_rows;
-constexpr int kWaves = 4;
+constexpr int kWaves = 8;   // two waves per SIMD: the item is latency-bound
 constexpr int kCols = 64;
 constexpr int kRows = 96;
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-static_assert(stage::kWaves == kWaves && stage::kCols == kCols, "staging shape");
+static_assert(stage::kCols == kCols, "staging shape");
 static_assert(kRows >= kMaxU + kMaxV, "staging capacity");
 
 __device__ inline float wave_sum(float v) {
@@ -58,6 +58,7 @@ __device__ inline double wave_sum_d(double v) {
 
 // ---- chi^2 and the per-point cotangent Dbar_i ---------------------------
 __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
+  constexpr int kW = 4;   // waves of this kernel
   const int b = blockIdx.x;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if (b >= B) return;
@@ -75,9 +76,9 @@ __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
   float* dbar = a.dbar + (int64_t)b * W;
   for (int i = lo + tid; i < hi; i += 256) dbar[i] = 0.f;
   __syncthreads();
-  __shared__ double s_part[2][kWaves];
+  __shared__ double s_part[2][kW];
   double c2 = 0.0, sd = 0.0;
-  for (int c = wave; c < a.n_ch; c += kWaves) {
+  for (int c = wave; c < a.n_ch; c += kW) {
     const int c0 = a.ch_i0[c];
     const int i0 = max(c0, lo), i1 = min(a.ch_i1[c], hi);
     const double* w = a.ch_w + a.ch_off[c] - c0;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
   __syncthreads();
   if (tid == 0) {
     double t2 = 0.0, ts = 0.0;
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < kW; ++w) {
       t2 += s_part[0][w];
       ts += s_part[1][w];
     }
@@ -207,8 +208,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
   float* rows = s.rows;
   float* crows = rows + nU * kCols;
-  stage_rows(tb.xsec32, abs_stride, W, cc, s.ids, nU, s.chi, tb.n_abs, rows, wave, lane);
-  if (has_cia) stage_rows(tb.cia32, cia_stride, W, cc, s.tids, nV, s.ciaw, tb.n_cia, crows, wave, lane);
+  stage_rows<kWaves>(tb.xsec32, abs_stride, W, cc, s.ids, nU, s.chi, tb.n_abs, rows, wave, lane);
+  if (has_cia) stage_rows<kWaves>(tb.cia32, cia_stride, W, cc, s.tids, nV, s.ciaw, tb.n_cia, crows, wave, lane);
   float R = 0.f;
   if (tb.has_rayleigh)
     for (int q = 0; q < tb.n_abs + 2; ++q) R = fmaf(hd->chi_s32[q], tb.ray32[(int64_t)q * W + cc], R);

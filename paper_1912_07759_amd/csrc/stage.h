@@ -10,7 +10,7 @@ constexpr int kWaves = 4;
 constexpr int kCols = 64;
 
 // rows[u][lane] = sum_i chi[i] * tab[i][ids[u]][col] for the corners
-// u = wave, wave + 4, ... < nU of a table laid out [i][corner][W].  Loads
+// u = wave, wave + NW, ... < nU of a table laid out [i][corner][W].  Loads
 // are buffer loads: one resource per absorber i (its range bounds every
 // access), the column as the per-lane offset and the corner row as a uniform
 // offset.  A batch of kSG corners x up to kSA absorbers is issued before the
@@ -18,15 +18,16 @@ constexpr int kCols = 64;
 constexpr int kSG = 8;
 constexpr int kSA = 4;
 constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit buffer, gfx9 family
+template <int NW = kWaves>
 __device__ inline void stage_rows(const float* tab, int64_t abs_stride, int W, int col, const int32_t* ids,
                                   int nU, const float* chi, int nabs, float* rows, int wave, int lane) {
   const int voff = col * 4;
   const int rec = (int)(abs_stride * 4 < 0x7fffffff ? abs_stride * 4 : 0x7fffffff);
-  for (int u0 = wave; u0 < nU; u0 += kWaves * kSG) {
+  for (int u0 = wave; u0 < nU; u0 += NW * kSG) {
     int soff[kSG];
 #pragma unroll
     for (int g = 0; g < kSG; ++g) {
-      const int u = u0 + kWaves * g < nU ? u0 + kWaves * g : u0;
+      const int u = u0 + NW * g < nU ? u0 + NW * g : u0;
       soff[g] = __builtin_amdgcn_readfirstlane(ids[u]) * W * 4;
     }
     float s[kSG];
@@ -55,7 +56,7 @@ __device__ inline void stage_rows(const float* tab, int64_t abs_stride, int W, i
     }
 #pragma unroll
     for (int g = 0; g < kSG; ++g)
-      if (u0 + kWaves * g < nU) rows[(u0 + kWaves * g) * kCols + lane] = s[g];
+      if (u0 + NW * g < nU) rows[(u0 + NW * g) * kCols + lane] = s[g];
   }
 }
 
