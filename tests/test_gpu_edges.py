@@ -1,0 +1,133 @@
+"""GPU edge cases of the forward model against the FP64 oracle: the fewest
+and the most layers each mode accepts, windows of one point and of the whole
+grid, temperatures and pressures outside the tables (each clamp rule),
+constant gravity and a model without any opacity.  The batches mix these
+cases in one launch (persistent in the matrix-core modes)."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth.atmosphere import guillot_T, log_midpoint_pressures, log_uniform_channels
+from synth.constants import GM_JUP, R_JUP, R_SUN
+from synth.workloads import Channels, batch_from_models, make_tables
+from parity_util import TOL, binned_rel_err, native_rel_err, oracle_batch
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp64", "fp32", "bf16x2", "bf16x3"]
+
+
+@pytest.fixture(scope="module")
+def tables():
+    return make_tables(2, n_wn=700, n_lines=120)
+
+
+def _channels(t):
+    lo, hi = log_uniform_channels(t.wn, 9)
+    return Channels(lo, hi)
+
+
+def _profile(N, T_irr=1200.0, shift=0.0):
+    return guillot_T(log_midpoint_pressures(1e6, 1e-4, N), GM_JUP / R_JUP ** 2, T_irr) + shift
+
+
+def _run(ctx, t, batch, ch, mode, max_layers):
+    from paper_1912_07759_amd import trx
+    T = trx.Tables.from_synth(ctx, t)
+    bins = trx.Bins(ctx, T, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=max_layers)
+    nat, binned, st = trx.forward(ctx, T, db, bins, mode)
+    ctx.synchronize()
+    out = nat.cpu().numpy(), binned.cpu().numpy(), st.cpu().numpy()
+    bins.close()
+    T.close()
+    return out
+
+
+def _check(t, batch, ch, mode, nat, binned, st):
+    assert np.all(st == 0), st
+    idx, ref = oracle_batch(t, batch, ch, mode)
+    worst = 0.0
+    for b, r in zip(idx, ref):
+        lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+        worst = max(worst, native_rel_err(nat[b], r["depth"], lo, hi),
+                    binned_rel_err(binned[b], r["binned"]))
+    return worst
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_layer_extremes_and_windows(gpu_ctx, tables, mode):
+    """N = 2, 3, 33 and the mode's maximum (224 for the matrix-core modes,
+    300 for FP64: two passes of its ray blocks); windows of one point at
+    either end of the grid, the whole grid, and a span-ragged middle."""
+    t = tables
+    W = t.n_wn
+    Nmax = 300 if mode == "fp64" else 224
+    Ns = [2, 3, 33, Nmax, Nmax, 64]
+    win = [(0, 1), (W - 1, W), (0, W), (5, W - 3), (63, 65), (130, 131)]
+    Ts = [_profile(N) for N in Ns]
+    vmr = np.tile(np.array([-4.0, -5.0, -6.0, -3.5, -7.0]), (len(Ns), 1))
+    batch = batch_from_models(Ts, 1e6, 1e-4, vmr, R_JUP, R_SUN, GM_JUP,
+                              [w[0] for w in win], [w[1] for w in win])
+    ch = _channels(t)
+    nat, binned, st = _run(gpu_ctx, t, batch, ch, mode, Nmax)
+    worst = _check(t, batch, ch, mode, nat, binned, st)
+    print(f"{mode}: layer/window extremes worst rel err {worst:.2e}")
+    assert worst <= TOL[mode]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_out_of_table_clamps(gpu_ctx, tables, mode):
+    """Temperatures below and above the table grid, and pressures below it
+    (the top layers at 1e-6 Pa): each clamp case, including T and P both
+    below the grid (zero cross-section)."""
+    t = tables
+    N = 60
+    T_hot = np.full(N, 5000.0)                     # above the T grid
+    T_cold = np.full(N, 120.0)                     # below the T grid
+    T_mix = np.where(np.arange(N) % 2 == 0, 150.0, 4200.0)
+    T_grad = np.linspace(4000.0, 100.0, N)         # crosses the grid
+    Ts = [T_hot, T_cold, T_mix, T_grad]
+    vmr = np.tile(np.array([-3.0, -4.0, -5.0, -6.0, -3.0]), (len(Ts), 1))
+    # 1e7 .. 1e-6 Pa extends past both ends of the log10 P grid (-4 .. 6)
+    batch = batch_from_models(Ts, 1e7, 1e-6, vmr, R_JUP, R_SUN, GM_JUP, 0, t.n_wn)
+    ch = _channels(t)
+    nat, binned, st = _run(gpu_ctx, t, batch, ch, mode, N)
+    worst = _check(t, batch, ch, mode, nat, binned, st)
+    print(f"{mode}: clamp cases worst rel err {worst:.2e}")
+    assert worst <= TOL[mode]
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x2"])
+def test_constant_gravity(gpu_ctx, tables, mode):
+    t = tables
+    Ts = [_profile(80), _profile(120, 1800.0)]
+    vmr = np.tile(np.array([-4.0, -5.0, -6.0, -3.5, -7.0]), (2, 1))
+    batch = batch_from_models(Ts, 1e6, 1e-4, vmr, R_JUP, R_SUN, GM_JUP, 0, t.n_wn, gravity=1)
+    ch = _channels(t)
+    nat, binned, st = _run(gpu_ctx, t, batch, ch, mode, 120)
+    worst = _check(t, batch, ch, mode, nat, binned, st)
+    print(f"{mode}: constant gravity worst rel err {worst:.2e}")
+    assert worst <= TOL[mode]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_no_opacity_gives_bare_disc(gpu_ctx, tables, mode):
+    """Zero cross-sections, no CIA, no Rayleigh: the depth is (Rp/Rs)^2 at
+    every point (transit-depth equations with a = 0)."""
+    t = dataclasses.replace(tables, xsec=np.zeros_like(tables.xsec),
+                            cia=np.zeros((0,) + tables.cia.shape[1:]),
+                            cia_pair=np.zeros((0, 2), np.int32), rayleigh=None)
+    Ts = [_profile(50), _profile(200)]
+    Rp = np.array([0.7, 1.9]) * R_JUP
+    vmr = np.full((2, t.n_abs), -3.0)
+    batch = batch_from_models(Ts, 1e6, 1e-4, vmr, Rp, R_SUN, GM_JUP, [0, 100], [t.n_wn, 400])
+    ch = _channels(t)
+    nat, binned, st = _run(gpu_ctx, t, batch, ch, mode, 200)
+    assert np.all(st == 0)
+    for b in range(2):
+        lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+        want = (Rp[b] / R_SUN) ** 2
+        assert np.all(nat[b, lo:hi] == want), (mode, b)
