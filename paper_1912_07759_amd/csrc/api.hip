@@ -394,6 +394,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   f.qcount = sb.qcount;
   f.persistent = persistent ? 1 : 0;
   f.group = rc.group;
+  f.span_group = rc.span_group > 0 ? rc.span_group : 1;
   {
     ProfScope ps(c, TRX_KERNEL_FORWARD);
     if (precision == TRX_FP64) {

@@ -85,6 +85,7 @@ struct Smem {
   int32_t ids[kRows];                                               // staged corner ids
   int32_t tids[kRows];                                              // staged CIA nodes
   float chi[TRX_MAX_ABSORBERS];
+  float chis[kMaxSpecies];   // all species (Rayleigh)
   float ciaw[TRX_MAX_CIA];
   int32_t items[kChunk];
   int32_t spans[kChunk];
@@ -112,48 +113,28 @@ static_assert(TRX_MAX_LAYERS_MFMA <= 32 * 2 * kWaves, "two ray blocks per wave c
 // threads of the workgroup (every early return is uniform).
 // RBW: ray blocks per wave (ray blocks / 4, rounded up).
 template <int MODE, int RBW>
-__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in, Smem<MODE, RBW>& sm) {
+__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end, Smem<MODE, RBW>& sm) {
   using C = Cfg<MODE>;
   // the item is the same for the whole workgroup: keep it, and every address
   // derived from it, in scalar registers (scalar loads of the layer records)
   const int b = __builtin_amdgcn_readfirstlane(b_in);
-  const int span = __builtin_amdgcn_readfirstlane(span_in);
   const Layout& L = a.L;
   const uint8_t* slab = a.ws + (int64_t)b * L.slab;
   const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
   const int N = hd->n;
   if (N == 0) return;
   const int lo = hd->lo, hi = hd->hi;
-  const int col0 = span * kCols;
-  if (col0 >= hi || col0 + kCols <= lo) return;
+  // the item's spans that meet the model's window
+  const int sp0 = __builtin_amdgcn_readfirstlane(max(s_first, lo / kCols));
+  const int sp1 = __builtin_amdgcn_readfirstlane(min(s_end, (hi + kCols - 1) / kCols));
+  if (sp0 >= sp1) return;
   // the wave index is uniform across the wave: keep it (and what derives
   // from it) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int col = col0 + lane;
-  const bool valid = col >= lo && col < hi;
-  const int cc = valid ? col : lo;
   const DevTables& tb = a.tab;
   const int W = tb.n_wn;
   const bool has_cia = tb.n_cia > 0;
-
-  // Rayleigh sum over all species, eight loads in flight (species indexes
-  // past the last are clamped and their terms skipped)
-  float R = 0.f;
-  if (tb.has_rayleigh) {
-    const int ns = tb.n_abs + 2;
-    const __amdgpu_buffer_rsrc_t rr =
-        __builtin_amdgcn_make_buffer_rsrc((void*)tb.ray32, (short)0, ns * W * 4, kRsrcWord3);
-    for (int s0 = 0; s0 < ns; s0 += 8) {
-      float v[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rr, cc * 4, min(s0 + k, ns - 1) * W * 4, 0));
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (s0 + k < ns) R = fmaf(hd->chi_s32[s0 + k], v[k], R);
-    }
-  }
 
   const float* lw = reinterpret_cast<const float*>(slab + L.off_lw32);
   const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
@@ -170,13 +151,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
   const int tid = threadIdx.x;
   // copy the corner ids of the model (or of layer block kb) into LDS, then
   // stage the mixed rows
-  auto stage = [&](const int32_t* ids, int nU, const int32_t* tids, int nV) {
+  auto stage = [&](const int32_t* ids, int nU, const int32_t* tids, int nV, int ccol) {
     for (int e = tid; e < nU; e += 64 * kWaves) sm.ids[e] = ids[e];
     for (int e = tid; e < nV; e += 64 * kWaves) sm.tids[e] = tids[e];
     __syncthreads();
-    stage_rows(tb.xsec32, abs_stride, W, cc, sm.ids, nU, sm.chi, tb.n_abs, rows, wave, lane);
+    stage_rows(tb.xsec32, abs_stride, W, ccol, sm.ids, nU, sm.chi, tb.n_abs, rows, wave, lane);
     crows = rows + nU * kCols;
-    if (has_cia) stage_rows(tb.cia32, cia_stride, W, cc, sm.tids, nV, sm.ciaw, tb.n_cia, crows, wave, lane);
+    if (has_cia) stage_rows(tb.cia32, cia_stride, W, ccol, sm.tids, nV, sm.ciaw, tb.n_cia, crows, wave, lane);
   };
   // whole-model staging when the distinct corners fit, else per layer block
   const bool mstage = ml->nU + ml->nV <= kRows && ml->nV <= kMListV;
@@ -207,9 +188,34 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
       if (tid < ml->nV) sm.tids[tid] = u1;
     }
     if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
+    if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s32[tid];
     if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w32[tid];
   }
   __syncthreads();
+
+  for (int span = sp0; span < sp1; ++span) {
+  const int col0 = span * kCols;
+  const int col = col0 + lane;
+  const bool valid = col >= lo && col < hi;
+  const int cc = valid ? col : lo;
+
+  // Rayleigh sum over all species, eight loads in flight (species indexes
+  // past the last are clamped and their terms skipped)
+  float R = 0.f;
+  if (tb.has_rayleigh) {
+    const int ns = tb.n_abs + 2;
+    const __amdgpu_buffer_rsrc_t rr =
+        __builtin_amdgcn_make_buffer_rsrc((void*)tb.ray32, (short)0, ns * W * 4, kRsrcWord3);
+    for (int s0 = 0; s0 < ns; s0 += 8) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rr, cc * 4, min(s0 + k, ns - 1) * W * 4, 0));
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (s0 + k < ns) R = fmaf(sm.chis[s0 + k], v[k], R);
+    }
+  }
   if (mstage) {
     stage_rows(tb.xsec32, abs_stride, W, cc, sm.ids, ml->nU, sm.chi, tb.n_abs, rows, wave, lane);
     crows = rows + ml->nU * kCols;
@@ -256,7 +262,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
     if (!mstage) {
       // all waves are past the opacity of block kb - 1 (barrier below)
       const KBlk* kd = kblk + kb;
-      stage(kd->ids, kd->nU, kd->tids, kd->nV);
+      stage(kd->ids, kd->nU, kd->tids, kd->nV, cc);
       __syncthreads();
     }
     uint32_t* fr = sm.frag[kb & 1];
@@ -426,7 +432,8 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int span_in,
     if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + (double)atm;
     if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
   }
-  __syncthreads();
+  __syncthreads();   // rows, fragments and partials are rewritten by the next span
+  }
 }
 
 // One workgroup per (model, span).
@@ -435,7 +442,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
   __shared__ Smem<MODE, RBW> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
-  process<MODE, RBW>(a, blockIdx.x, blockIdx.y, sm);
+  const int S = a.span_group;
+  process<MODE, RBW>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
 }
 
 // Persistent: a fixed grid pops chunks of (span, model) items from kQueues
@@ -449,15 +457,17 @@ template <int MODE, int RBW>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_mfma_persist(FwdArgs a) {
   __shared__ Smem<MODE, RBW> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
-  const int nspans = (a.tab.n_wn + kCols - 1) / kCols;
+  const int S = a.span_group;
+  const int ngroups = ((a.tab.n_wn + kCols - 1) / kCols + S - 1) / S;
   const int q0 = blockIdx.x % kQueues;
   for (int k = 0; k < kQueues; ++k) {
     const int q = (q0 + k) % kQueues;
-    const int nsq = q < nspans ? (nspans - q + kQueues - 1) / kQueues : 0;
+    const int nsq = q < ngroups ? (ngroups - q + kQueues - 1) / kQueues : 0;
     const int total = nsq * B;
     // items of queue q: model groups of G (in the order of order[]), within a
-    // group the queue's spans in increasing order, within a span the group's
-    // models; G = B gives plain span-major order
+    // group the queue's span groups (S consecutive spans) in increasing
+    // order, within a span group the group's models; G = B gives plain
+    // span-major order
     const int G = a.group > 0 && a.group < B ? a.group : B;
     while (true) {
       if (threadIdx.x == 0) sm.base = total > 0 ? atomicAdd(&a.qcount[q], kChunk) : 0;
@@ -475,7 +485,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
           sp = ls * kQueues + q;
           const int bm = a.order[slot];
           const int2 r = a.mspan[bm];
-          if (sp >= r.x && sp < r.y) code = bm;
+          if (r.x < (sp + 1) * S && r.y > sp * S) code = bm;
         }
         sm.items[threadIdx.x] = code;
         sm.spans[threadIdx.x] = sp;
@@ -484,7 +494,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW>(a, bm, sm.spans[c], sm);
+        if (bm >= 0) process<MODE, RBW>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
       }
       __syncthreads();
     }
@@ -510,7 +520,7 @@ void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
     const int grid = n_cu * occupancy<MODE, RBW>();
     hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW>), dim3(grid), dim3(64 * kWaves), 0, s, a);
   } else {
-    dim3 grid(B_grid, (a.tab.n_wn + kCols - 1) / kCols);
+    dim3 grid(B_grid, ((a.tab.n_wn + kCols - 1) / kCols + a.span_group - 1) / a.span_group);
     hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW>), grid, dim3(64 * kWaves), 0, s, a);
   }
 }

@@ -64,7 +64,8 @@ __global__ void k_set_count(int32_t* dst, int32_t v) { *dst = v; }
 
 void describe(trx_plan* p) {
   char buf[160];
-  snprintf(buf, sizeof buf, "persistent=%d group=%d", p->rc.persistent, p->rc.group);
+  snprintf(buf, sizeof buf, "persistent=%d group=%d spans=%d", p->rc.persistent, p->rc.group,
+           p->rc.span_group);
   p->desc = buf;
 }
 
@@ -178,6 +179,7 @@ bool parse_variant(const char* v, RunConfig& rc) {
     if (*end != '\0') return false;
     if (k == "persistent" && (x == 0 || x == 1)) r.persistent = (int)x;
     else if (k == "group" && x >= 0 && x <= (1 << 24)) r.group = (int)x;
+    else if (k == "spans" && x >= 1 && x <= 64) r.span_group = (int)x;
     else return false;
   }
   rc = r;
@@ -390,15 +392,17 @@ extern "C" trx_status trx_autotune(trx_plan* p, const trx_batch* bt, const char*
     base.persistent = 0;
     cand.push_back(base);
   } else {
-    RunConfig r = base;
-    r.persistent = 0;
-    cand.push_back(r);
-    if (p->flags & TRX_PLAN_PERSISTENT) {
-      for (int g : {0, 256, 128, 64, 32, 16, 8}) {
-        r = base;
-        r.persistent = 1;
-        r.group = g;
-        cand.push_back(r);
+    for (int sg : {1, 2, 4, 8}) {
+      RunConfig r = base;
+      r.span_group = sg;
+      r.persistent = 0;
+      cand.push_back(r);
+      if (p->flags & TRX_PLAN_PERSISTENT) {
+        for (int g : {0, 64, 16}) {
+          r.persistent = 1;
+          r.group = g;
+          cand.push_back(r);
+        }
       }
     }
   }

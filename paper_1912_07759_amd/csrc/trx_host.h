@@ -58,6 +58,7 @@ struct RunConfig {
   int nrb_max = 7;            // ray-block capacity of the matrix-core kernel
   int persistent = 1;         // 1: persistent grid with work queues
   int group = 0;              // models per item group of the persistent order (0: all)
+  int span_group = 4;         // consecutive 64-column spans per work item
 };
 
 // Scheduling buffers of one launch (device memory).

@@ -225,6 +225,7 @@ struct FwdArgs {
   int32_t* qcount;        // [kQueues] item counters, zeroed by the schedule kernel
   int32_t persistent;     // 1: persistent grid, 0: one workgroup per (model, span)
   int32_t group;          // models per item group of the persistent order (0: all)
+  int32_t span_group;     // consecutive spans per work item (matrix-core kernel)
 };
 
 void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* order, int32_t* qcount,

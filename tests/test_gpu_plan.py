@@ -153,7 +153,8 @@ def test_autotune_and_cache(gpu_ctx, ragged, tmp_path):
     assert list(data.values()) == [choice]
     _, got, _ = plan.launch(db)
     assert np.array_equal(_np(got), ref, equal_nan=True)
-    for v in ["persistent=0 group=0", "persistent=1 group=8", "persistent=1 group=0"]:
+    for v in ["persistent=0 group=0 spans=1", "persistent=1 group=8 spans=4",
+              "persistent=1 group=0 spans=2"]:
         plan.set_variant(v)
         assert plan.describe() == v
         _, got, _ = plan.launch(db)
