@@ -101,6 +101,80 @@ __device__ inline uint32_t bf16_pair(float a, float b) {
 __device__ inline float bf16_lo_f(uint32_t p) { return __uint_as_float(p << 16); }
 __device__ inline float bf16_hi_f(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
 
+// Model-level staging of one span: the mixed corner rows, the CIA node
+// rows and the Rayleigh sum of column `col`.  The loads of the CIA nodes
+// (up to two pairs) and of eight Rayleigh species are issued ahead of the
+// first corner batch, so their latency overlaps it.  Returns the Rayleigh sum.
+template <int MODE, int RBW>
+__device__ inline float stage_model(const DevTables& tb, const MList* ml, const Smem<MODE, RBW>& sm, float* rows,
+                                    float* crows, int col, int wave, int lane) {
+  const int W = tb.n_wn;
+  const int nU = ml->nU, nV = ml->nV;
+  const int voff = col * 4;
+  const bool has_cia = tb.n_cia > 0;
+  const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
+  const int crec = (int)(cia_stride * 4 < 0x7fffffff ? cia_stride * 4 : 0x7fffffff);
+  constexpr int CG = 8;   // CIA nodes per wave (nV <= kMListV = kWaves * CG)
+  static_assert(kMListV <= kWaves * CG, "one round covers the CIA nodes");
+  float cv[2][CG];
+  int npair = 0;
+  if (has_cia && nV > 0) {
+    npair = min(tb.n_cia, 2);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p < npair) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(tb.cia32 + (int64_t)p * cia_stride), (short)0, crec, kRsrcWord3);
+#pragma unroll
+        for (int g = 0; g < CG; ++g) {
+          const int t = wave + kWaves * g < nV ? wave + kWaves * g : 0;
+          cv[p][g] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+              r, voff, __builtin_amdgcn_readfirstlane(sm.tids[t]) * W * 4, 0));
+        }
+      }
+    }
+  }
+  const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
+  float rv[8];
+  if (ns > 0) {
+    const __amdgpu_buffer_rsrc_t rr =
+        __builtin_amdgcn_make_buffer_rsrc((void*)tb.ray32, (short)0, ns * W * 4, kRsrcWord3);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      rv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rr, voff, min(k, ns - 1) * W * 4, 0));
+  }
+  const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
+  stage_rows(tb.xsec32, abs_stride, W, col, sm.ids, nU, sm.chi, tb.n_abs, rows, wave, lane);
+  // CIA node rows: C_t = sum_p chi_a chi_b sigma_p[t]
+  if (npair > 0) {
+#pragma unroll
+    for (int g = 0; g < CG; ++g) {
+      const int t = wave + kWaves * g;
+      if (t < nV) {
+        float v = sm.ciaw[0] * cv[0][g];
+        if (npair > 1) v = fmaf(sm.ciaw[1], cv[1][g], v);
+        crows[t * kCols + lane] = v;
+      }
+    }
+    if (tb.n_cia > 2) {
+      // further pairs: added row by row
+      for (int p = 2; p < tb.n_cia; ++p) {
+        const float* tp = tb.cia32 + (int64_t)p * cia_stride;
+        for (int t = wave; t < nV; t += kWaves)
+          crows[t * kCols + lane] = fmaf(sm.ciaw[p], tp[(int64_t)sm.tids[t] * W + col], crows[t * kCols + lane]);
+      }
+    }
+  }
+  float R = 0.f;
+  if (ns > 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < ns) R = fmaf(sm.chis[k], rv[k], R);
+    for (int k = 8; k < ns; ++k) R = fmaf(sm.chis[k], tb.ray32[(int64_t)k * W + col], R);
+  }
+  return R;
+}
+
 // Ray block r (0..RBW-1) of a wave: w, then 7 - w, so that the long
 // triangle rows (low ray blocks) and the short ones are dealt evenly.
 template <int RBW>
@@ -199,10 +273,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   const bool valid = col >= lo && col < hi;
   const int cc = valid ? col : lo;
 
-  // Rayleigh sum over all species, eight loads in flight (species indexes
-  // past the last are clamped and their terms skipped)
   float R = 0.f;
-  if (tb.has_rayleigh) {
+  if (mstage) {
+    crows = rows + ml->nU * kCols;
+    R = stage_model(tb, ml, sm, rows, crows, cc, wave, lane);
+  } else if (tb.has_rayleigh) {
+    // Rayleigh sum over all species, eight loads in flight (species indexes
+    // past the last are clamped and their terms skipped)
     const int ns = tb.n_abs + 2;
     const __amdgpu_buffer_rsrc_t rr =
         __builtin_amdgcn_make_buffer_rsrc((void*)tb.ray32, (short)0, ns * W * 4, kRsrcWord3);
@@ -215,11 +292,6 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       for (int k = 0; k < 8; ++k)
         if (s0 + k < ns) R = fmaf(sm.chis[s0 + k], v[k], R);
     }
-  }
-  if (mstage) {
-    stage_rows(tb.xsec32, abs_stride, W, cc, sm.ids, ml->nU, sm.chi, tb.n_abs, rows, wave, lane);
-    crows = rows + ml->nU * kCols;
-    if (has_cia) stage_rows(tb.cia32, cia_stride, W, cc, sm.tids, ml->nV, sm.ciaw, tb.n_cia, crows, wave, lane);
   }
 
   f32x16 acc[RBW][2];
