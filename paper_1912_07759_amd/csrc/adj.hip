@@ -125,9 +125,10 @@ struct ItemLds {
   float* ciaw;   // [TRX_MAX_CIA]
   float* rcol;   // [64] Rayleigh sum per column
   float* pacc;   // [G.n] this item's partial sums (GradAcc offsets)
+  float* kap;    // [NP][64] kappa kept for the backward (models of <= 128 layers)
 };
 
-__host__ __device__ inline size_t carve(const Layout& L, unsigned char* base, ItemLds* out) {
+__host__ __device__ inline size_t carve(const Layout& L, unsigned char* base, ItemLds* out, bool keep) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
     unsigned char* p = base ? base + o : nullptr;
@@ -149,10 +150,16 @@ __host__ __device__ inline size_t carve(const Layout& L, unsigned char* base, It
   s.ciaw = (float*)take(TRX_MAX_CIA * 4);
   s.rcol = (float*)take((size_t)kCols * 4);
   s.pacc = (float*)take((size_t)make_grad_acc(NP).n * 4);
+  s.kap = keep ? (float*)take((size_t)NP * kCols * 4) : nullptr;
   if (out) *out = s;
   return o;
 }
 
+// KEEP (models of at most 128 layers, whose kappa fits in LDS beside the
+// rest): the boundary sums read the kept kappa in tile layout and the
+// temperature and mixed-row terms run per layer with one column per lane;
+// otherwise all three are taken per tile with kappa recomputed.
+template <bool KEEP>
 __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   const int B = a.B_dev ? *a.B_dev : a.B;
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   const bool has_cia = tb.n_cia > 0;
   const int NP = L.NP;
   ItemLds s;
-  carve(L, dyn, &s);
+  carve(L, dyn, &s, KEEP);
 
   // records, derivative records, slots, corner lists
   {
@@ -242,7 +249,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   // A: kappa of every layer of the padded ray blocks (zero past N)
   const int nrb = hd->nrb;
   const int NR = 32 * nrb;
-  for (int k = wave; k < NR; k += kWaves) s.kt[k * kCols + lane] = k < N ? comb(k, s.lw + 8 * k, lane) : 0.f;
+  for (int k = wave; k < NR; k += kWaves) {
+    const float v = k < N ? comb(k, s.lw + 8 * k, lane) : 0.f;
+    s.kt[k * kCols + lane] = v;
+    if constexpr (KEEP) s.kap[k * kCols + lane] = v;
+  }
   __syncthreads();
 
   float* acc = s.pacc;   // per-item partial sums (LDS)
@@ -351,6 +362,132 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   // gbar = Gh^T taubar (K = two rays per step, rays j <= layer), then per
   // (layer, column) the boundary, temperature and mixed-row adjoints
   const float2* mt = reinterpret_cast<const float2*>(slab + L.off_mt);
+  if constexpr (KEEP) {
+    // one tile per wave (2 nrb <= 8): products, then the boundary sums in
+    // tile layout from the kept kappa
+    static_assert(2 * 4 <= kWaves, "one tile per wave");
+    f32x16 kb = f32x16{};
+    const int t = wave;
+    const int lb = t >> 1, cb = t & 1;
+    const int c = 32 * cb + lc;
+    if (t < 2 * nrb) {
+      f32x16 gb = f32x16{};
+      const float2* arow = mt + (int64_t)(32 * lb + lc) * NP;
+      const int jmax = min(N, 32 * lb + 32);
+      for (int j0 = 0; j0 < jmax; j0 += 16) {
+        float2 m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = j0 + 2 * u + hl;
+          m[u] = j < NR ? arow[j] : float2{};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (j0 + 2 * u < jmax) {
+            const int j = j0 + 2 * u + hl;
+            const float x = s.kt[j * kCols + c];
+            kb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].x, x, kb, 0, 0, 0);
+            gb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].y, x, gb, 0, 0, 0);
+          }
+        }
+      }
+      float hs[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
+        const float d = s.kap[k * kCols + c] - (k + 1 < NR ? s.kap[(k + 1) * kCols + c] : 0.f);
+        hs[q] = k < N ? gb[q] * d : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) hs[q] = half_sum(hs[q]);
+      if (lc == 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
+          if (k < N) atomicAdd(acc + G.o_h + k + 1, hs[q]);
+        }
+      }
+    }
+    __syncthreads();   // taubar is no longer read: its space takes kappabar
+    if (t < 2 * nrb) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
+        s.kt[k * kCols + c] = kb[q];
+      }
+    }
+    __syncthreads();
+    // per layer, one column per lane (slots and weights uniform): the
+    // temperature term and the scatter into the mixed-row adjoints, which
+    // accumulates in registers while consecutive layers keep their slots
+    const int per = (N + kWaves - 1) / kWaves;
+    const int k0 = wave * per, k1 = min(N, k0 + per);
+    uint32_t psa = 0xffffffffu, psc = 0xffffffffu;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, q0 = 0.f, q1 = 0.f, rsum = 0.f;
+    for (int k = k0; k < k1; ++k) {
+      const int2 sk = s.sl[k];
+      const uint32_t sa = __builtin_amdgcn_readfirstlane((uint32_t)sk.x);
+      const uint32_t sc = __builtin_amdgcn_readfirstlane((uint32_t)sk.y);
+      const float4 wa = *reinterpret_cast<const float4*>(s.lw + 8 * k);
+      const float4 wb = *reinterpret_cast<const float4*>(s.lw + 8 * k + 4);
+      const float4 da = *reinterpret_cast<const float4*>(s.lwd + 8 * k);
+      const float4 db = *reinterpret_cast<const float4*>(s.lwd + 8 * k + 4);
+      const float m0 = rows[(sa & 0xff) * kCols + lane];
+      const float m1 = rows[((sa >> 8) & 0xff) * kCols + lane];
+      const float m2 = rows[((sa >> 16) & 0xff) * kCols + lane];
+      const float m3 = rows[(sa >> 24) * kCols + lane];
+      float dk = da.x * m0;
+      dk = fmaf(da.y, m1, dk);
+      dk = fmaf(da.z, m2, dk);
+      dk = fmaf(da.w, m3, dk);
+      dk = fmaf(db.x, R, dk);
+      if (has_cia) {
+        dk = fmaf(db.y, crows[(sc & 0xff) * kCols + lane], dk);
+        dk = fmaf(db.z, crows[((sc >> 8) & 0xff) * kCols + lane], dk);
+      }
+      const float kv = s.kt[k * kCols + lane];
+      const float ts = wave_sum(kv * dk);
+      if (lane == 0) atomicAdd(acc + G.o_T + k, ts);
+      if (sa != psa) {
+        if (psa != 0xffffffffu) {
+          atomicAdd(&s.sh[(psa & 0xff) * kCols + lane], a0);
+          atomicAdd(&s.sh[((psa >> 8) & 0xff) * kCols + lane], a1);
+          atomicAdd(&s.sh[((psa >> 16) & 0xff) * kCols + lane], a2);
+          atomicAdd(&s.sh[(psa >> 24) * kCols + lane], a3);
+        }
+        psa = sa;
+        a0 = a1 = a2 = a3 = 0.f;
+      }
+      a0 = fmaf(wa.x, kv, a0);
+      a1 = fmaf(wa.y, kv, a1);
+      a2 = fmaf(wa.z, kv, a2);
+      a3 = fmaf(wa.w, kv, a3);
+      rsum = fmaf(wb.x, kv, rsum);
+      if (has_cia) {
+        if (sc != psc) {
+          if (psc != 0xffffffffu) {
+            atomicAdd(&s.sh[(nU + (psc & 0xff)) * kCols + lane], q0);
+            atomicAdd(&s.sh[(nU + ((psc >> 8) & 0xff)) * kCols + lane], q1);
+          }
+          psc = sc;
+          q0 = q1 = 0.f;
+        }
+        q0 = fmaf(wb.y, kv, q0);
+        q1 = fmaf(wb.z, kv, q1);
+      }
+    }
+    if (psa != 0xffffffffu) {
+      atomicAdd(&s.sh[(psa & 0xff) * kCols + lane], a0);
+      atomicAdd(&s.sh[((psa >> 8) & 0xff) * kCols + lane], a1);
+      atomicAdd(&s.sh[((psa >> 16) & 0xff) * kCols + lane], a2);
+      atomicAdd(&s.sh[(psa >> 24) * kCols + lane], a3);
+    }
+    if (has_cia && psc != 0xffffffffu) {
+      atomicAdd(&s.sh[(nU + (psc & 0xff)) * kCols + lane], q0);
+      atomicAdd(&s.sh[(nU + ((psc >> 8) & 0xff)) * kCols + lane], q1);
+    }
+    if (k1 > k0) atomicAdd(&s.rh[lane], rsum);
+  } else
   for (int t = wave; t < 2 * nrb; t += kWaves) {
     const int lb = t >> 1, cb = t & 1;
     const int c = 32 * cb + lc;
@@ -642,7 +779,7 @@ __global__ __launch_bounds__(64) void k_adj_geom(AdjArgs a) {
 
 }  // namespace
 
-size_t adj_item_lds_bytes(const Layout& L) { return carve(L, nullptr, nullptr); }
+size_t adj_item_lds_bytes(const Layout& L) { return carve(L, nullptr, nullptr, L.NP <= 128); }
 
 void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
@@ -651,11 +788,16 @@ void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
 
 hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return hipSuccess;
+  const bool keep = a.L.NP <= 128;
   const size_t lds = adj_item_lds_bytes(a.L);
-  hipError_t e = hipFuncSetAttribute((const void*)k_adj_item, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* fn = keep ? (const void*)k_adj_item<true> : (const void*)k_adj_item<false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int spans = (a.tab.n_wn + kCols - 1) / kCols;
-  hipLaunchKernelGGL(k_adj_item, dim3(B_grid, spans), dim3(64 * kWaves), lds, s, a);
+  if (keep)
+    hipLaunchKernelGGL(k_adj_item<true>, dim3(B_grid, spans), dim3(64 * kWaves), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_item<false>, dim3(B_grid, spans), dim3(64 * kWaves), lds, s, a);
   return hipGetLastError();
 }
 
