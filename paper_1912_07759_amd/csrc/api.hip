@@ -352,7 +352,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
                                 int precision, const RunConfig& rc, uint8_t* ws, void* aws,
                                 const SchedBufs& sb, double* depth_native, double* depth_binned,
                                 int32_t* status, bool grad_layout) {
-  const Layout L = make_layout(max_layers, precision, grad_layout);
+  const Layout L = make_layout(max_layers, precision, grad_layout, t->dev);
   GeomArgs g;
   g.bt = db;
   g.tab = t->dev;
@@ -430,7 +430,7 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
                                   const double* obs, const double* sigma, double* chi2, double* dT,
                                   double* dvmr, double* dRp, double* depth_binned, int32_t* status,
                                   bool alloc) {
-  const Layout L = make_layout(max_layers, precision, true);
+  const Layout L = make_layout(max_layers, precision, true, t->dev);
   const GradAcc G = make_grad_acc(L.NP);
   const int W = t->dev.n_wn;
   const size_t esz = precision == TRX_FP64 ? 8 : 4;
@@ -511,7 +511,7 @@ extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_bat
   if (depth_binned && !bins) return set_err(c, TRX_E_INVALID_ARG, "depth_binned requires bins");
   if (bins && bins->tables != t) return set_err(c, TRX_E_INVALID_ARG, "bins were made for other tables");
   hipSetDevice(c->device);
-  const Layout L = make_layout(bt->max_layers, precision);
+  const Layout L = make_layout(bt->max_layers, precision, false, t->dev);
   if ((s = ensure_buffer(c, c->ws, (size_t)bt->B * L.slab, "workspace")) != TRX_OK) return s;
   const size_t esz = precision == TRX_FP64 ? 8 : 4;
   if ((s = ensure_buffer(c, c->aws, (size_t)bt->B * t->dev.n_wn * esz, "workspace")) != TRX_OK) return s;

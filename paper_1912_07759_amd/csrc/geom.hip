@@ -21,6 +21,11 @@
 //      CIA weights in T times 1e-10 rho^2 (cm^5 -> m^5), and the corner
 //      indices.  Out-of-range T and log10 P clamp to the grid; T and P both
 //      below the grid give zero cross-section (Opacities section).
+//      The model's opacity slots: its distinct corners (ordered by pressure
+//      node, then temperature node) and its distinct CIA temperature nodes.
+//
+// The matrix-core modes then take, per model, the products of the chord
+// lengths and the opacity weights (k_pmat below).
 #include "trx_internal.h"
 
 namespace trx {
@@ -284,9 +289,12 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   }
   __syncthreads();
 
-  // distinct corners of the whole model (bitmaps over the corner ids, slots
-  // = rank of the id among the set bits) and each layer's slots in them
+  // distinct corners of the whole model (bitmaps over the keys
+  // iP n_T + iT, slots = rank of the key among the set bits, so that the
+  // slots follow the pressure nodes and a run of slots is used by a run of
+  // layers) and each layer's slots in them
   {
+    __shared__ int s_nu;
     __shared__ uint32_t s_bm[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
     __shared__ uint32_t s_pre[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
     __shared__ uint32_t s_cbm[TRX_MAX_TGRID / 32];
@@ -296,9 +304,18 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     for (int w = tid; w < nwords; w += kThreads) s_bm[w] = 0u;
     for (int w = tid; w < ncwords; w += kThreads) s_cbm[w] = 0u;
     __syncthreads();
+    const int nT = tb.n_T, nP = tb.n_P;
+    // keys of the corners (iT, iP), (iT+1, iP), (iT, iP+1), (iT+1, iP+1)
+    auto corner_keys = [&](int base, int* ks) {
+      const int k0 = (base % nP) * nT + base / nP;
+      ks[0] = k0;
+      ks[1] = k0 + 1;
+      ks[2] = k0 + nT;
+      ks[3] = k0 + nT + 1;
+    };
     for (int l = tid; l < N; l += kThreads) {
-      const int base = lid[8 * l];
-      const int cs[4] = {base, base + tb.n_P, base + 1, base + tb.n_P + 1};
+      int cs[4];
+      corner_keys(lid[8 * l], cs);
       for (int q = 0; q < 4; ++q) atomicOr(&s_bm[cs[q] >> 5], 1u << (cs[q] & 31));
       if (tb.n_cia > 0) {
         const int t0 = lid[8 * l + 1];
@@ -315,15 +332,23 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       MList* ml = reinterpret_cast<MList*>(slab + L.off_mlist);
       ml->nU = (int)acc;
       ml->nV = tb.n_cia > 0 ? (int)cacc : 0;
+      s_nu = (int)acc;
     }
     __syncthreads();
     MList* ml = reinterpret_cast<MList*>(slab + L.off_mlist);
+    // the slot lists: the first kMListU / kMListV in the model list, all of
+    // them (table rows, corners then CIA nodes) in the slot table of the
+    // matrix-core modes
+    int32_t* sid = a.precision != TRX_FP64 ? reinterpret_cast<int32_t*>(slab + L.off_sid) : nullptr;
+    const int nu = s_nu;
     for (int w = tid; w < nwords; w += kThreads) {
       uint32_t bits = s_bm[w];
       int slot = (int)s_pre[w];
       while (bits) {
-        const int bpos = __ffs(bits) - 1;
-        if (slot < kMListU) ml->ids[slot] = 32 * w + bpos;
+        const int key = 32 * w + __ffs(bits) - 1;
+        const int id = (key % nT) * nP + key / nT;
+        if (slot < kMListU) ml->ids[slot] = id;
+        if (sid) sid[slot] = id;
         ++slot;
         bits &= bits - 1;
       }
@@ -333,24 +358,31 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         uint32_t bits = s_cbm[w];
         int slot = (int)s_cpre[w];
         while (bits) {
-          const int bpos = __ffs(bits) - 1;
-          if (slot < kMListV) ml->tids[slot] = 32 * w + bpos;
+          const int t = 32 * w + __ffs(bits) - 1;
+          if (slot < kMListV) ml->tids[slot] = t;
+          if (sid) sid[nu + slot] = t;
           ++slot;
           bits &= bits - 1;
         }
       }
     }
-    auto rank = [&](const uint32_t* bm, const uint32_t* pre, int c) -> uint32_t {
+    auto rank_full = [&](const uint32_t* bm, const uint32_t* pre, int c) -> uint32_t {
       const uint32_t below = bm[c >> 5] & ((1u << (c & 31)) - 1u);
-      const uint32_t r = pre[c >> 5] + __popc(below);
+      return pre[c >> 5] + __popc(below);
+    };
+    auto rank = [&](const uint32_t* bm, const uint32_t* pre, int c) -> uint32_t {
+      const uint32_t r = rank_full(bm, pre, c);
       return r > 255u ? 255u : r;
     };
     for (int l = tid; l < N; l += kThreads) {
-      const int base = lid[8 * l];
-      const int cs[4] = {base, base + tb.n_P, base + 1, base + tb.n_P + 1};
+      int cs[4];
+      corner_keys(lid[8 * l], cs);
       uint32_t slots = 0;
       for (int q = 0; q < 4; ++q) slots |= rank(s_bm, s_pre, cs[q]) << (8 * q);
       lid[8 * l + 2] = (int32_t)slots;
+      // unclamped 16-bit slots of the four corners
+      lid[8 * l + 6] = (int32_t)(rank_full(s_bm, s_pre, cs[0]) | (rank_full(s_bm, s_pre, cs[1]) << 16));
+      lid[8 * l + 7] = (int32_t)(rank_full(s_bm, s_pre, cs[2]) | (rank_full(s_bm, s_pre, cs[3]) << 16));
       uint32_t cslots = 0;
       if (tb.n_cia > 0) {
         const int t0 = lid[8 * l + 1];
@@ -463,49 +495,163 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       const int k = e / NP, j = e % NP;
       dlT[e] = dl_of(j, k);
     }
-  } else if (a.precision == TRX_FP32) {
-    // v_mfma_f32_32x32x2_f32 A operand: lane l, step i holds
-    // dl[32 rb + l%32][16 kb + 2 i + l/32]; pieces hi, lo.
-    float* f = reinterpret_cast<float*>(dst);
-    const int npairs = frag_pairs(L.NRB, L.NKB);
-    for (int e = tid; e < npairs * 64; e += kThreads) {
-      const int pr = e / 64, lane = e % 64;
-      int rb = 0, base = 0;
-      while (base + (L.NKB - 2 * rb) <= pr) { base += L.NKB - 2 * rb; ++rb; }
-      const int kb = 2 * rb + (pr - base);
-      float* o = f + (int64_t)pr * 2 * 512;
-      for (int i = 0; i < 8; ++i) {
-        const double d = dl_of(32 * rb + (lane & 31), 16 * kb + 2 * i + (lane >> 5));
-        const float hi32 = (float)d;
-        o[lane * 8 + i] = hi32;
-        o[512 + lane * 8 + i] = (float)(d - (double)hi32);
+  }
+}
+
+// Path-length x opacity-weight products of the matrix-core modes (steps a3
+// and a4 combined).  With the opacity slots q of a model and W[l][q] the
+// weight of slot q in the opacity of layer l (the bilinear corner weight
+// x 1e-4 rho, the CIA node weight x 1e-10 rho^2 / kCiaScale32, zero where
+// layer l does not use q), the optical depth of ray j at one wavenumber is
+//   tau_j = sum_l dl[j][l] kappa_l = sum_q P[j][q] M_q + PR_j R,
+//   P[j][q] = sum_{l >= j} dl[j][l] W[l][q],  PR_j = sum_{l >= j} dl[j][l] w_R,l,
+// where M_q is the mixed cross-section of slot q (sum_i chi_i sigma_i at a
+// corner, or the CIA sum at a node) and R the mixed Rayleigh cross-section:
+// the layer sums are taken here once per model in FP64, and the forward
+// kernel contracts over the slots.  One workgroup per model, one thread per
+// ray; P is accumulated in LDS 16 slots at a time, each block of slots over
+// the run of layers that use one of them, and stored as A-operand fragments
+// of the matrix instruction: FP32 mode hi + lo pieces in the
+// v_mfma_f32_32x32x2_f32 layout (lane l, step i: P[32 rb + l%32][16 kq + 2 i + l/32]),
+// bf16 modes 2 or 3 bf16 pieces in the v_mfma_f32_32x32x16_bf16 layout
+// (lane l: P[32 rb + l%32][16 kq + 8 (l/32) + v], v = 0..7).
+constexpr int kPT = 256;
+constexpr int kMaxKQ = (4 * TRX_MAX_LAYERS_MFMA + TRX_MAX_TGRID + 15) / 16;
+static_assert(TRX_MAX_LAYERS_MFMA <= kPT, "one thread per ray");
+
+__global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
+  const int b = blockIdx.x;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if (b >= B) return;
+  const Layout& L = a.L;
+  uint8_t* slab = a.ws + (int64_t)b * L.slab;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
+  const int N = hd->n;
+  if (N == 0) return;   // invalid model: the forward kernel skips it
+  const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
+  const int nU = ml->nU, nV = ml->nV;
+  const int nkq = (nU + nV + 15) / 16;
+  const double* zs = reinterpret_cast<const double*>(slab + L.off_z);
+  const double* A64 = reinterpret_cast<const double*>(slab + L.off_A64);
+  const double* lw64 = reinterpret_cast<const double*>(slab + L.off_lw64);
+  const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
+  float2* aw = reinterpret_cast<float2*>(slab + L.off_aw);
+  const double Rp = hd->Rp;
+  const int tid = threadIdx.x;
+  const int nrb = (N + 31) / 32;
+
+  __shared__ double sZ[TRX_MAX_LAYERS_MFMA];
+  __shared__ double sH[TRX_MAX_LAYERS_MFMA + 1];
+  __shared__ double sW[TRX_MAX_LAYERS_MFMA][7];   // 4 corners, 2 CIA nodes, Rayleigh
+  __shared__ int4 sS[TRX_MAX_LAYERS_MFMA];        // slots: corners 0,1 | 2,3 | CIA 0,1 (16 bits each)
+  __shared__ int sLo[kMaxKQ], sHi[kMaxKQ];
+  __shared__ double sAcc[16][kPT];
+
+  for (int l = tid; l < N; l += kPT) {
+    sZ[l] = zs[l];
+    for (int q = 0; q < 4; ++q) sW[l][q] = lw64[8 * l + q];
+    sW[l][4] = lw64[8 * l + 5] / kCiaScale32;
+    sW[l][5] = lw64[8 * l + 6] / kCiaScale32;
+    sW[l][6] = lw64[8 * l + 4];
+    const uint32_t cw = (uint32_t)lid[8 * l + 3];
+    const int cs = nV > 0 ? (int)((nU + (cw & 0xff)) | ((nU + ((cw >> 8) & 0xff)) << 16)) : -1;
+    sS[l] = make_int4(lid[8 * l + 6], lid[8 * l + 7], cs, 0);
+  }
+  for (int c = tid; c < nkq; c += kPT) {
+    sLo[c] = N;
+    sHi[c] = -1;
+  }
+  __syncthreads();
+  for (int m = tid; m <= N; m += kPT) sH[m] = m == 0 ? 0.0 : (m == N ? sZ[N - 1] : 0.5 * (sZ[m - 1] + sZ[m]));
+  // the run of layers of each slot block
+  for (int l = tid; l < N; l += kPT) {
+    const int4 ss = sS[l];
+    const uint32_t sl[6] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
+                            (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16};
+    for (int q = 0; q < (nV > 0 ? 6 : 4); ++q) {
+      atomicMin(&sLo[sl[q] >> 4], l);
+      atomicMax(&sHi[sl[q] >> 4], l);
+    }
+  }
+  __syncthreads();
+
+  // chord of ray j through layer l, carrying q_j(h_l) in q0 (Forward
+  // Models section; the same cancellation-free form as the FP64 chords)
+  const int j = tid;
+  const double zj = j < N ? sZ[j] : 0.0;
+  auto qj = [&](double h) { return sqrt(fmax((h - zj) * (2.0 * Rp + h + zj), 0.0)); };
+  auto chord = [&](int l, double& q0) -> double {
+    const double h0 = sH[l], h1 = sH[l + 1];
+    const double q1 = qj(h1);
+    const double d = l == j ? 2.0 * q1 : 2.0 * (h1 - h0) * (2.0 * Rp + h0 + h1) / (q1 + q0);
+    q0 = q1;
+    return d;
+  };
+
+  // annulus weight and Rayleigh path weight per ray (zero past N)
+  if (j < L.NP) {
+    float2 o = make_float2(0.f, 0.f);
+    if (j < N) {
+      double pr = 0.0;
+      if (a.tab.has_rayleigh) {
+        double q0 = 0.0;
+        for (int l = j; l < N; ++l) pr += chord(l, q0) * sW[l][6];
+      }
+      o = make_float2((float)A64[j], (float)pr);
+    }
+    aw[j] = o;
+  }
+
+  uint8_t* dst = slab + L.off_dl;
+  for (int c = 0; c < nkq; ++c) {
+    for (int v = 0; v < 16; ++v) sAcc[v][tid] = 0.0;
+    const int la = sLo[c], lb = sHi[c];
+    const int l0 = max(j, la);
+    if (j < N && l0 <= lb) {
+      double q0 = l0 == j ? 0.0 : qj(sH[l0]);
+      for (int l = l0; l <= lb; ++l) {
+        const double d = chord(l, q0);
+        const int4 ss = sS[l];
+        const uint32_t sl[6] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
+                                (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16};
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          if ((int)(sl[q] >> 4) == c && (q < 4 || nV > 0)) sAcc[sl[q] & 15][j] += d * sW[l][q];
       }
     }
-  } else {
-    // v_mfma_f32_32x32x16_bf16 A operand: lane l holds
-    // dl[32 rb + l%32][16 kb + 8 (l/32) + v], v = 0..7; 2 or 3 bf16 pieces.
-    uint16_t* f = reinterpret_cast<uint16_t*>(dst);
-    const int np = a.precision == TRX_BF16_SPLIT3 ? 3 : 2;
-    const int npairs = frag_pairs(L.NRB, L.NKB);
-    for (int e = tid; e < npairs * 64; e += kThreads) {
-      const int pr = e / 64, lane = e % 64;
-      int rb = 0, base = 0;
-      while (base + (L.NKB - 2 * rb) <= pr) { base += L.NKB - 2 * rb; ++rb; }
-      const int kb = 2 * rb + (pr - base);
-      uint16_t* o = f + (int64_t)pr * np * 512;
-      for (int v = 0; v < 8; ++v) {
-        const double d = dl_of(32 * rb + (lane & 31), 16 * kb + 8 * (lane >> 5) + v);
-        const uint16_t p0 = bf16_bits((float)d);
-        const double r1 = d - bf16_to_double(p0);
-        const uint16_t p1 = bf16_bits((float)r1);
-        o[lane * 8 + v] = p0;
-        o[512 + lane * 8 + v] = p1;
-        if (np == 3) {
-          const double r2 = r1 - bf16_to_double(p1);
-          o[1024 + lane * 8 + v] = bf16_bits((float)r2);
+    __syncthreads();
+    if (a.precision == TRX_FP32) {
+      float* f = reinterpret_cast<float*>(dst);
+      for (int e = tid; e < 64 * nrb; e += kPT) {
+        const int rb = e >> 6, lane = e & 63;
+        const int r = 32 * rb + (lane & 31);
+        float* o = f + (((int64_t)rb * L.NKQ + c) * 2 * 64 + lane) * 8;
+        for (int i = 0; i < 8; ++i) {
+          const double x = sAcc[2 * i + (lane >> 5)][r];
+          const float hi32 = (float)x;
+          o[i] = hi32;
+          o[64 * 8 + i] = (float)(x - (double)hi32);
+        }
+      }
+    } else {
+      uint16_t* f = reinterpret_cast<uint16_t*>(dst);
+      const int np = a.precision == TRX_BF16_SPLIT3 ? 3 : 2;
+      for (int e = tid; e < 64 * nrb; e += kPT) {
+        const int rb = e >> 6, lane = e & 63;
+        const int r = 32 * rb + (lane & 31);
+        uint16_t* o = f + (((int64_t)rb * L.NKQ + c) * np * 64 + lane) * 8;
+        for (int v = 0; v < 8; ++v) {
+          const double x = sAcc[8 * (lane >> 5) + v][r];
+          const uint16_t p0 = bf16_bits((float)x);
+          const double r1 = x - bf16_to_double(p0);
+          const uint16_t p1 = bf16_bits((float)r1);
+          o[v] = p0;
+          o[64 * 8 + v] = p1;
+          if (np == 3) o[2 * 64 * 8 + v] = bf16_bits((float)(r1 - bf16_to_double(p1)));
         }
       }
     }
+    __syncthreads();
   }
 }
 
@@ -548,6 +694,7 @@ void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* 
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   hipLaunchKernelGGL(k_geom, dim3(B_grid), dim3(kThreads), 0, s, a);
+  if (a.precision != TRX_FP64) hipLaunchKernelGGL(k_pmat, dim3(B_grid), dim3(kPT), 0, s, a);
 }
 
 }  // namespace trx

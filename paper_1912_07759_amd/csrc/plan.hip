@@ -216,7 +216,7 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   if (!(flags & TRX_PLAN_PERSISTENT)) p->rc.persistent = 0;
   describe(p);
   auto fail = [&](trx_status s) { trx_plan_destroy(p); return s; };
-  const Layout L = make_layout(N_max, precision, grad);
+  const Layout L = make_layout(N_max, precision, grad, t->dev);
   trx_status s;
   if ((s = ensure_buffer(c, p->ws, (size_t)B_max * L.slab, "plan workspace")) != TRX_OK) return fail(s);
   if (grad && (s = ensure_buffer(c, p->grad, grad_scratch_bytes(B_max, t->dev.n_wn, bins->n_ch, L.NP),

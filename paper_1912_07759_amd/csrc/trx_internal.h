@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/trx.h"
 
 namespace trx {
@@ -81,7 +83,10 @@ struct DevTables {
 struct Layout {
   int32_t NP;              // padded layer capacity (multiple of 32)
   int32_t NRB, NKB;        // NP/32, NP/16
+  int32_t NKQ;             // 16-slot blocks of the opacity slots (matrix-core modes)
   int64_t off_z, off_A64, off_A32, off_lw64, off_lw32, off_lid, off_kblk, off_mlist, off_dl;
+  int64_t off_sid;         // [16 NKQ] table row of each opacity slot (corners, then CIA nodes)
+  int64_t off_aw;          // [NP] float2 (A_j/Rs^2, Rayleigh path weight of ray j)
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise):
   int64_t off_lwd32;       // [NP][8] FP32 d(record weight)/dT at fixed P
@@ -91,20 +96,16 @@ struct Layout {
   int64_t slab;            // bytes per model (multiple of 256)
 };
 
-// Number of (ray block, layer block) fragment pairs stored for the matrix-core
-// modes: for ray block rb every layer block kb >= 2*rb.
-__host__ __device__ inline int frag_pairs(int NRB, int NKB) {
-  int p = 0;
-  for (int rb = 0; rb < NRB; ++rb) p += (NKB - 2 * rb) > 0 ? (NKB - 2 * rb) : 0;
-  return p;
-}
-__host__ __device__ inline int frag_index(int rb, int kb, int NKB) {
-  // pairs are stored rb-major; ray block r contributes NKB - 2 r entries,
-  // so ray block rb starts at sum_{r<rb} (NKB - 2 r) = rb NKB - rb (rb - 1).
-  return rb * NKB - rb * (rb - 1) + (kb - 2 * rb);
+// Opacity slots of a model in the matrix-core modes: its distinct
+// cross-section corners (at most 4 per layer, at most the grid's n_T n_P)
+// and its distinct CIA temperature nodes (at most 2 per layer).
+inline int slot_capacity(const DevTables& t, int NP) {
+  const int corners = std::min(4 * NP, t.n_T * t.n_P);
+  const int nodes = t.n_cia > 0 ? std::min(2 * NP, t.n_Tcia) : 0;
+  return corners + nodes;
 }
 
-// Number of stored pieces of the path lengths per mode.
+// Number of stored pieces of the path-length products per mode.
 inline int dl_pieces(int precision) {
   switch (precision) {
     case TRX_FP32: return 2;
@@ -114,16 +115,17 @@ inline int dl_pieces(int precision) {
   }
 }
 
-// Bytes of one (rb, kb) fragment piece: 64 lanes x 8 values.
+// Bytes of one (ray block, slot block) fragment piece: 64 lanes x 8 values.
 inline int frag_piece_bytes(int precision) {
   return precision == TRX_FP32 ? 64 * 8 * 4 : 64 * 8 * 2;
 }
 
-inline Layout make_layout(int N_max, int precision, bool grad = false) {
+inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& t) {
   Layout L{};
   L.NP = ((N_max + 31) / 32) * 32;
   L.NRB = L.NP / 32;
   L.NKB = L.NP / 16;
+  L.NKQ = (slot_capacity(t, L.NP) + 15) / 16;
   int64_t o = kHdrBytes;
   auto take = [&](int64_t bytes) { int64_t r = o; o += (bytes + 255) / 256 * 256; return r; };
   L.off_z = take(8LL * L.NP);
@@ -139,8 +141,10 @@ inline Layout make_layout(int N_max, int precision, bool grad = false) {
   if (precision == TRX_FP64) {
     L.dl_bytes = 8LL * L.NP * L.NP;  // dense transposed dlT[k][j]
   } else {
-    L.dl_bytes = (int64_t)frag_pairs(L.NRB, L.NKB) * dl_pieces(precision) *
-                 frag_piece_bytes(precision);
+    // P[j][q] = sum_l dl[j][l] W[l][q] in A-operand fragments [rb][kq][piece]
+    L.off_sid = take(4LL * 16 * L.NKQ);
+    L.off_aw = take(8LL * L.NP);
+    L.dl_bytes = (int64_t)L.NRB * L.NKQ * dl_pieces(precision) * frag_piece_bytes(precision);
   }
   L.off_dl = take(L.dl_bytes);
   if (grad) {
