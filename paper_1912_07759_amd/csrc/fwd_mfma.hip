@@ -37,6 +37,8 @@
 #include "trx_internal.h"
 #include "stage.h"
 
+#include <type_traits>
+
 namespace trx {
 
 namespace {
@@ -46,7 +48,6 @@ using stage::kRsrcWord3;
 constexpr int kWaves = 4;
 constexpr int kCols = 64;               // columns per workgroup
 constexpr int kKC = 128;                // slots per staging chunk
-constexpr int kSA = 4;                  // tables per load batch of a slot group
 constexpr int kChunk = 8;               // items popped per atomic (persistent launch)
 static_assert(TRX_MAX_LAYERS_MFMA % 32 == 0 && TRX_MAX_LAYERS_MFMA <= 64 * kWaves,
               "a thread copies the record of one ray");
@@ -110,8 +111,9 @@ static_assert(TRX_MAX_LAYERS_MFMA <= 32 * 2 * kWaves, "two ray blocks per wave c
 // s[i] += sum_t wt[t] tab_t[row_i][col] over the tables t < nt (table t at
 // tab + t stride) for the slots i in [i0, i1) of a group of 8; rows of the
 // slots outside are clamped into it (their loads are in range, their values
-// unused).  Loads: 8 slots x kSA tables per batch, buffer loads with the
+// unused).  Loads: 8 slots x SA tables per batch, buffer loads with the
 // column as the per-lane offset and the slot's row as the uniform offset.
+template <int SA>
 __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const float* wt, const int32_t* rows,
                                  int i0, int i1, int W, int voff, float* s) {
   const int rec = (int)(stride * 4 < 0x7fffffff ? stride * 4 : 0x7fffffff);
@@ -121,10 +123,10 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
     const int k = i < i0 ? i0 : (i >= i1 ? i1 - 1 : i);
     soff[i] = __builtin_amdgcn_readfirstlane(rows[k]) * W * 4;
   }
-  for (int t0 = 0; t0 < nt; t0 += kSA) {
-    float v[kSA][8];
+  for (int t0 = 0; t0 < nt; t0 += SA) {
+    float v[SA][8];
 #pragma unroll
-    for (int tt = 0; tt < kSA; ++tt) {
+    for (int tt = 0; tt < SA; ++tt) {
       if (t0 + tt < nt) {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
             (void*)(tab + (int64_t)(t0 + tt) * stride), (short)0, rec, kRsrcWord3);
@@ -133,7 +135,7 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
       }
     }
 #pragma unroll
-    for (int tt = 0; tt < kSA; ++tt) {
+    for (int tt = 0; tt < SA; ++tt) {
       if (t0 + tt < nt) {
         const float c = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(wt[t0 + tt])));
 #pragma unroll
@@ -173,6 +175,15 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   const int K = nU + nV;
   const int nrb = hd->nrb;
   const int NKQ = L.NKQ;
+  // slot blocks with a nonzero product, per ray block of this wave
+  uint64_t msk[RBW];
+  uint64_t any_msk = 0;
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = own_rb<RBW>(wave, r);
+    msk[r] = rb < nrb ? hd->kq_mask[rb] : 0ull;
+    any_msk |= msk[r];
+  }
   const int32_t* sid = reinterpret_cast<const int32_t*>(slab + L.off_sid);
   const float2* awg = reinterpret_cast<const float2*>(slab + L.off_aw);
   const u32x4* frag = reinterpret_cast<const u32x4*>(slab + L.off_dl);
@@ -200,7 +211,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       const int rb = own_rb<RBW>(wave, r);
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
-        if (rb < nrb && kq0 + kk < nq) {
+        if (kq0 + kk < nq && ((msk[r] >> (kqa + kq0 + kk)) & 1)) {
           const int64_t f = (int64_t)rb * NKQ + kqa + kq0 + kk;
           if constexpr (MODE == TRX_FP32) {
 #pragma unroll
@@ -237,13 +248,14 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       }
     }
 
+    // one staging chunk (slots c0 ..): stage, then contract; the first
+    // chunk zeroes the accumulators after its staging (they are not live
+    // during it)
     f32x16 acc[RBW][2];
-#pragma unroll
-    for (int r = 0; r < RBW; ++r) {
-      acc[r][0] = f32x16{};
-      acc[r][1] = f32x16{};
-    }
-    for (int c0 = 0; c0 < K; c0 += kKC) {
+    auto run_chunk = [&](const int c0, auto first_t) {
+      constexpr bool first = decltype(first_t)::value;
+      // tables per load batch: 8 when the accumulators are not live
+      constexpr int SA = first ? 8 : 4;
       const int nq = (min(kKC, K - c0) + 15) >> 4;
       const int kqa = c0 >> 4;
       if (K > kKC) {
@@ -263,9 +275,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.f;
         const int nc = min(max(nU - s0, 0), 8);
-        if (nc > 0) mix_group(tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g, 0, nc, W, voff, s);
+        if (nc > 0) mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g, 0, nc, W, voff, s);
         const int vb = min(max(K - s0, 0), 8);
-        if (vb > nc) mix_group(tb.cia32, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, voff, s);
+        if (vb > nc) mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, voff, s);
         const int kq = g >> 1, h = g & 1;
         const int tcb = lane >> 5, n = lane & 31;
         if constexpr (MODE == TRX_FP32) {
@@ -299,6 +311,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         sm.rpart[wave][lane] = rp;
       }
       __syncthreads();   // staged slots visible
+      if (first) {
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+          acc[r][0] = f32x16{};
+          acc[r][1] = f32x16{};
+        }
+      }
 
       // products: batches of KB slot blocks, the next batch's A fragments
       // loaded before the current batch's products (PF) or after them
@@ -309,7 +328,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
           const int kq = kb0 + kk;
-          if (kq < nq) {
+          if (kq < nq && ((any_msk >> (kqa + kq)) & 1)) {
             if constexpr (MODE == TRX_FP32) {
               float bk[2][8];
 #pragma unroll
@@ -322,7 +341,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
               }
 #pragma unroll
               for (int r = 0; r < RBW; ++r) {
-                if (own_rb<RBW>(wave, r) < nrb) {
+                if ((msk[r] >> (kqa + kq)) & 1) {
 #pragma unroll
                   for (int tcb = 0; tcb < 2; ++tcb) {
 #pragma unroll
@@ -344,7 +363,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
                   Bp[tcb][p] = *reinterpret_cast<const u32x4*>(sm.bfrag + (((kq * npc + p) * 2 + tcb) * 64 + lane) * 4);
 #pragma unroll
               for (int r = 0; r < RBW; ++r) {
-                if (own_rb<RBW>(wave, r) < nrb) {
+                if ((msk[r] >> (kqa + kq)) & 1) {
 #pragma unroll
                   for (int tcb = 0; tcb < 2; ++tcb) {
 #pragma unroll
@@ -374,7 +393,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
           }
         }
       }
-    }
+    };
+    run_chunk(0, std::true_type{});
+    for (int c0 = kKC; c0 < K; c0 += kKC) run_chunk(c0, std::false_type{});
     __syncthreads();   // the partials below reuse the slot buffer
 
     // depth: accumulator register q holds ray 8 (q/4) + 4 (lane/32) + q%4

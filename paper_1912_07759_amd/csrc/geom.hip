@@ -528,9 +528,11 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
   const int N = hd->n;
   if (N == 0) return;   // invalid model: the forward kernel skips it
+  ModelHdr* hw = reinterpret_cast<ModelHdr*>(slab);
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const int nU = ml->nU, nV = ml->nV;
   const int nkq = (nU + nV + 15) / 16;
+  static_assert(kMaxKQ <= 64, "slot-block masks are 64 bits");
   const double* zs = reinterpret_cast<const double*>(slab + L.off_z);
   const double* A64 = reinterpret_cast<const double*>(slab + L.off_A64);
   const double* lw64 = reinterpret_cast<const double*>(slab + L.off_lw64);
@@ -546,6 +548,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   __shared__ int4 sS[TRX_MAX_LAYERS_MFMA];        // slots: corners 0,1 | 2,3 | CIA 0,1 (16 bits each)
   __shared__ int sLo[kMaxKQ], sHi[kMaxKQ];
   __shared__ double sAcc[16][kPT];
+  __shared__ unsigned long long sMask[kPT / 32];
 
   for (int l = tid; l < N; l += kPT) {
     sZ[l] = zs[l];
@@ -561,6 +564,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     sLo[c] = N;
     sHi[c] = -1;
   }
+  if (tid < kPT / 32) sMask[tid] = 0ull;
   __syncthreads();
   for (int m = tid; m <= N; m += kPT) sH[m] = m == 0 ? 0.0 : (m == N ? sZ[N - 1] : 0.5 * (sZ[m - 1] + sZ[m]));
   // the run of layers of each slot block
@@ -619,6 +623,18 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
           if ((int)(sl[q] >> 4) == c && (q < 4 || nV > 0)) sAcc[sl[q] & 15][j] += d * sW[l][q];
       }
     }
+    {
+      // ray blocks with a nonzero product in this slot block (each thread
+      // checks its own ray; a wave holds two ray blocks)
+      bool nz = false;
+      for (int v = 0; v < 16; ++v) nz |= sAcc[v][j] != 0.0;
+      const unsigned long long bal = __ballot(nz);
+      if ((tid & 63) == 0) {
+        const int rb0 = 2 * (tid >> 6);
+        if (bal & 0xffffffffull) sMask[rb0] |= 1ull << c;
+        if (bal >> 32) sMask[rb0 + 1] |= 1ull << c;
+      }
+    }
     __syncthreads();
     if (a.precision == TRX_FP32) {
       float* f = reinterpret_cast<float*>(dst);
@@ -653,6 +669,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     }
     __syncthreads();
   }
+  if (tid < TRX_MAX_LAYERS_MFMA / 32) hw->kq_mask[tid] = tid < nrb ? sMask[tid] : 0ull;
 }
 
 // Work order of the persistent launch: model indices sorted by layer count,

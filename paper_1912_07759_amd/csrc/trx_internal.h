@@ -58,6 +58,10 @@ struct ModelHdr {
   double cia_w[TRX_MAX_CIA];        // chi_a * chi_b per CIA pair
   float chi_s32[kMaxSpecies];
   float cia_w32[TRX_MAX_CIA];
+  // matrix-core modes: bit kq of kq_mask[rb] is set when slot block kq of
+  // ray block rb has a nonzero path x weight product (rays above every layer
+  // of a slot block see none of it)
+  uint64_t kq_mask[TRX_MAX_LAYERS_MFMA / 32];
 };
 static_assert(sizeof(ModelHdr) <= kHdrBytes, "header too large");
 
