@@ -138,7 +138,11 @@ typedef struct {
 } trx_tables_desc;
 
 /* Copy the tables to the device (FP64 and FP32 copies, wavenumber
- * contiguous).  The handle owns the device memory. */
+ * contiguous).  The handle owns the device memory.  Returns
+ * TRX_E_INVALID_ARG for a malformed description and TRX_E_UNSUPPORTED when
+ * the FP32 table of one absorber (n_T n_P n_wn values), of one CIA pair
+ * (n_Tcia n_wn) or the Rayleigh table ((n_abs + 2) n_wn) reaches 2 GiB: the
+ * matrix-core kernels address a table row with a 32-bit byte offset. */
 trx_status trx_tables_create(trx_ctx* ctx, const trx_tables_desc* desc, trx_tables** out);
 trx_status trx_tables_destroy(trx_tables* t);
 

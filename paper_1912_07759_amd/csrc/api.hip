@@ -185,6 +185,12 @@ extern "C" trx_status trx_tables_create(trx_ctx* c, const trx_tables_desc* d, tr
       if (d->cia_pair[p] < 0 || d->cia_pair[p] >= d->n_abs + 2)
         return set_err(c, TRX_E_INVALID_ARG, "CIA species id out of range");
   }
+  {
+    const double lim = 2147483648.0;   // row offsets are 32-bit byte offsets
+    const double wb = 4.0 * d->n_wn;
+    if (wb * d->n_T * d->n_P >= lim || (d->n_cia > 0 && wb * d->n_Tcia >= lim) || wb * (d->n_abs + 2) >= lim)
+      return set_err(c, TRX_E_UNSUPPORTED, "an FP32 table of one absorber, CIA pair or the Rayleigh table reaches 2 GiB");
+  }
   hipSetDevice(c->device);
   trx_tables* t = new trx_tables();
   t->ctx = c;

@@ -75,12 +75,9 @@ struct Cfg {
 
 template <int MODE, int RBW>
 struct Smem {
-  // B operand of the staged slot chunk; after the products the same space
-  // holds the per-ray-block depth partials
-  union {
-    __attribute__((aligned(16))) uint32_t bfrag[Cfg<MODE, RBW>::bdw];
-    float part[kWaves * RBW][kCols];
-  };
+  // B operand of the staged slot chunk
+  __attribute__((aligned(16))) uint32_t bfrag[Cfg<MODE, RBW>::bdw];
+  float part[kWaves * RBW][kCols];  // per-ray-block depth partials
   float2 aw[TRX_MAX_LAYERS_MFMA];   // per ray: A_j/Rs^2, PR_j
   float rpart[kWaves][kCols];       // Rayleigh sums by wave
   int32_t sid[kKC];                 // table rows of the chunk's slots
@@ -396,7 +393,6 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     };
     run_chunk(0, std::true_type{});
     for (int c0 = kKC; c0 < K; c0 += kKC) run_chunk(c0, std::false_type{});
-    __syncthreads();   // the partials below reuse the slot buffer
 
     // depth: accumulator register q holds ray 8 (q/4) + 4 (lane/32) + q%4
     // of column 32 (column block) + lane%32
@@ -422,6 +418,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         }
       }
     }
+    // one barrier ends the span: past it every wave is done with the slot
+    // buffer, the ray weights and the Rayleigh sums of this span, so the
+    // next span's staging may start while wave 0 sums the partials (they
+    // are rewritten only after the next span's staging barrier)
     __syncthreads();
     if (wave == 0 && valid) {
       float atm = 0.f;
@@ -431,7 +431,6 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + (double)atm;
       if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
     }
-    __syncthreads();   // the slot buffer, partials and Rayleigh sums are rewritten by the next span
   }
 }
 

@@ -394,9 +394,10 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   __syncthreads();
 
   // distinct corners of each 16-layer block and each layer's slots in them
+  // (the FP64 kernel stages them when a model's lists overflow)
   KBlk* kblk = reinterpret_cast<KBlk*>(slab + L.off_kblk);
   const int nkb = (N + 15) / 16;
-  for (int kb = tid; kb < L.NKB; kb += kThreads) {
+  for (int kb = tid; kb < (a.precision == TRX_FP64 ? L.NKB : 0); kb += kThreads) {
     KBlk d;
     d.nU = 0;
     d.nV = 0;
@@ -579,10 +580,17 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   }
   __syncthreads();
 
+  // the rays of the padded ray blocks are replicated R times over the
+  // threads; replica rep takes the tasks rep, rep + R, ...: the slot blocks
+  // 0 .. nkq-1, then the Rayleigh path weights
+  const int NR32 = 32 * nrb;
+  const int R = kPT / NR32;
+  const int rep = tid / NR32;
+  const int j = tid - rep * NR32;
+  const bool act = rep < R && j < N;
+  const double zj = act ? sZ[j] : 0.0;
   // chord of ray j through layer l, carrying q_j(h_l) in q0 (Forward
   // Models section; the same cancellation-free form as the FP64 chords)
-  const int j = tid;
-  const double zj = j < N ? sZ[j] : 0.0;
   auto qj = [&](double h) { return sqrt(fmax((h - zj) * (2.0 * Rp + h + zj), 0.0)); };
   auto chord = [&](int l, double& q0) -> double {
     const double h0 = sH[l], h1 = sH[l + 1];
@@ -592,58 +600,58 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     return d;
   };
 
-  // annulus weight and Rayleigh path weight per ray (zero past N)
-  if (j < L.NP) {
-    float2 o = make_float2(0.f, 0.f);
-    if (j < N) {
-      double pr = 0.0;
-      if (a.tab.has_rayleigh) {
-        double q0 = 0.0;
-        for (int l = j; l < N; ++l) pr += chord(l, q0) * sW[l][6];
-      }
-      o = make_float2((float)A64[j], (float)pr);
-    }
-    aw[j] = o;
-  }
+  // annulus weights (zero past N); the Rayleigh task adds its path weights
+  if (tid < L.NP) aw[tid] = make_float2(tid < N ? (float)A64[tid] : 0.f, 0.f);
+  __syncthreads();   // ordered before the Rayleigh task's writes
 
   uint8_t* dst = slab + L.off_dl;
-  for (int c = 0; c < nkq; ++c) {
+  const int np = a.precision == TRX_BF16_SPLIT3 ? 3 : 2;
+  for (int r0 = 0; r0 <= nkq; r0 += R) {
+    const int c = r0 + rep;
     for (int v = 0; v < 16; ++v) sAcc[v][tid] = 0.0;
-    const int la = sLo[c], lb = sHi[c];
-    const int l0 = max(j, la);
-    if (j < N && l0 <= lb) {
-      double q0 = l0 == j ? 0.0 : qj(sH[l0]);
-      for (int l = l0; l <= lb; ++l) {
-        const double d = chord(l, q0);
-        const int4 ss = sS[l];
-        const uint32_t sl[6] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
-                                (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16};
+    if (act && c < nkq) {
+      const int la = sLo[c], lb = sHi[c];
+      const int l0 = max(j, la);
+      if (l0 <= lb) {
+        double q0 = l0 == j ? 0.0 : qj(sH[l0]);
+        for (int l = l0; l <= lb; ++l) {
+          const double d = chord(l, q0);
+          const int4 ss = sS[l];
+          const uint32_t sl[6] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
+                                  (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16};
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
-          if ((int)(sl[q] >> 4) == c && (q < 4 || nV > 0)) sAcc[sl[q] & 15][j] += d * sW[l][q];
+          for (int q = 0; q < 6; ++q)
+            if ((int)(sl[q] >> 4) == c && (q < 4 || nV > 0)) sAcc[sl[q] & 15][tid] += d * sW[l][q];
+        }
       }
+    } else if (act && c == nkq && a.tab.has_rayleigh) {
+      double pr = 0.0, q0 = 0.0;
+      for (int l = j; l < N; ++l) pr += chord(l, q0) * sW[l][6];
+      aw[j] = make_float2((float)A64[j], (float)pr);
     }
     {
       // ray blocks with a nonzero product in this slot block (each thread
-      // checks its own ray; a wave holds two ray blocks)
+      // checks its own ray; a half-wave holds one ray block of one replica)
       bool nz = false;
-      for (int v = 0; v < 16; ++v) nz |= sAcc[v][j] != 0.0;
+      for (int v = 0; v < 16; ++v) nz |= sAcc[v][tid] != 0.0;
       const unsigned long long bal = __ballot(nz);
-      if ((tid & 63) == 0) {
-        const int rb0 = 2 * (tid >> 6);
-        if (bal & 0xffffffffull) sMask[rb0] |= 1ull << c;
-        if (bal >> 32) sMask[rb0 + 1] |= 1ull << c;
+      if ((tid & 31) == 0 && rep < R && c < nkq) {
+        const unsigned long long half = (tid & 32) ? bal >> 32 : bal & 0xffffffffull;
+        if (half) atomicOr(&sMask[j >> 5], 1ull << c);
       }
     }
     __syncthreads();
+    // the fragments of the round's slot blocks
+    const int nc = min(R, nkq - r0);
     if (a.precision == TRX_FP32) {
       float* f = reinterpret_cast<float*>(dst);
-      for (int e = tid; e < 64 * nrb; e += kPT) {
-        const int rb = e >> 6, lane = e & 63;
-        const int r = 32 * rb + (lane & 31);
-        float* o = f + (((int64_t)rb * L.NKQ + c) * 2 * 64 + lane) * 8;
+      for (int e = tid; e < nc * 64 * nrb; e += kPT) {
+        const int cr = e / (64 * nrb), rem = e - cr * 64 * nrb;
+        const int rb = rem >> 6, lane = rem & 63;
+        const int col = cr * NR32 + 32 * rb + (lane & 31);
+        float* o = f + (((int64_t)rb * L.NKQ + r0 + cr) * 2 * 64 + lane) * 8;
         for (int i = 0; i < 8; ++i) {
-          const double x = sAcc[2 * i + (lane >> 5)][r];
+          const double x = sAcc[2 * i + (lane >> 5)][col];
           const float hi32 = (float)x;
           o[i] = hi32;
           o[64 * 8 + i] = (float)(x - (double)hi32);
@@ -651,13 +659,13 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
       }
     } else {
       uint16_t* f = reinterpret_cast<uint16_t*>(dst);
-      const int np = a.precision == TRX_BF16_SPLIT3 ? 3 : 2;
-      for (int e = tid; e < 64 * nrb; e += kPT) {
-        const int rb = e >> 6, lane = e & 63;
-        const int r = 32 * rb + (lane & 31);
-        uint16_t* o = f + (((int64_t)rb * L.NKQ + c) * np * 64 + lane) * 8;
+      for (int e = tid; e < nc * 64 * nrb; e += kPT) {
+        const int cr = e / (64 * nrb), rem = e - cr * 64 * nrb;
+        const int rb = rem >> 6, lane = rem & 63;
+        const int col = cr * NR32 + 32 * rb + (lane & 31);
+        uint16_t* o = f + (((int64_t)rb * L.NKQ + r0 + cr) * np * 64 + lane) * 8;
         for (int v = 0; v < 8; ++v) {
-          const double x = sAcc[8 * (lane >> 5) + v][r];
+          const double x = sAcc[8 * (lane >> 5) + v][col];
           const uint16_t p0 = bf16_bits((float)x);
           const double r1 = x - bf16_to_double(p0);
           const uint16_t p1 = bf16_bits((float)r1);

@@ -95,3 +95,25 @@ def test_invalid_models_flagged(gpu_ctx):
     idx, ref = oracle_batch(tables, batch, ch, "fp64", models=[0, 5])
     for b, r in zip(idx, ref):
         assert binned_rel_err(binned[b], r["binned"]) <= TOL["fp64"]
+
+
+def test_tables_beyond_32bit_row_offsets_rejected(gpu_ctx):
+    """An FP32 absorber table of 2 GiB or more is refused with
+    TRX_E_UNSUPPORTED before anything is read or copied (the row offsets of
+    the matrix-core kernels are 32-bit); the description is well formed, so
+    only the size is at fault."""
+    import ctypes
+    from paper_1912_07759_amd import trx
+    nT, nP, W = 128, 128, 1 << 15           # 4 * nT * nP * W = 2 GiB
+    wn = np.linspace(1000.0, 2000.0, W)
+    Tg = np.linspace(100.0, 4000.0, nT)
+    Pg = np.linspace(-4.0, 6.0, nP)
+    tiny = np.zeros(4)                       # never read: the size check comes first
+    mass = np.array([18.0])
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    d = trx.TablesDesc(W, ptr(wn), nT, ptr(Tg), nP, ptr(Pg), 1, ptr(tiny), ptr(mass),
+                       2.016, 4.0026, 0, 0, None, None, None, None)
+    h = ctypes.c_void_p()
+    rc = trx.lib().trx_tables_create(gpu_ctx.h, ctypes.byref(d), ctypes.byref(h))
+    assert rc == 4, trx.lib().trx_last_error(gpu_ctx.h)
+    assert not h.value
