@@ -143,6 +143,38 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
   }
 }
 
+// Full corner groups (8 slots, all corners) in batches of SA absorber
+// tables: issue_corners loads tables t0 .. t0 + SA - 1 of the 8 slot rows,
+// mix_corners adds chi_t times them; a wave keeps two batches in flight.
+template <int SA>
+__device__ inline void issue_corners(const float* tab, int64_t stride, int nt, const int32_t* rows, int t0, int W,
+                                     int voff, float (&v)[SA][8]) {
+  const int rec = (int)(stride * 4 < 0x7fffffff ? stride * 4 : 0x7fffffff);
+  int soff[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) soff[i] = __builtin_amdgcn_readfirstlane(rows[i]) * W * 4;
+#pragma unroll
+  for (int tt = 0; tt < SA; ++tt) {
+    if (t0 + tt < nt) {
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(tab + (int64_t)(t0 + tt) * stride), (short)0, rec, kRsrcWord3);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[tt][i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff[i], 0));
+    }
+  }
+}
+template <int SA>
+__device__ inline void mix_corners(const float* wt, int nt, int t0, const float (&v)[SA][8], float (&s)[8]) {
+#pragma unroll
+  for (int tt = 0; tt < SA; ++tt) {
+    if (t0 + tt < nt) {
+      const float c = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(wt[t0 + tt])));
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s[i] = fmaf(c, v[tt][i], s[i]);
+    }
+  }
+}
+
 // One work item: model b, columns [64 s_first, 64 s_end) cut to its window.
 // Called by all threads of the workgroup (every early return is uniform).
 template <int MODE, int RBW>
@@ -251,8 +283,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     f32x16 acc[RBW][2];
     auto run_chunk = [&](const int c0, auto first_t) {
       constexpr bool first = decltype(first_t)::value;
-      // tables per load batch: 8 when the accumulators are not live
-      constexpr int SA = first ? 8 : 4;
+      // tables per load batch (two batches in flight): 6 when the
+      // accumulators are not live, else 2
+      constexpr int SA = first ? 6 : 2;
       const int nq = (min(kKC, K - c0) + 15) >> 4;
       const int kqa = c0 >> 4;
       if (K > kKC) {
@@ -265,16 +298,12 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 
       // staging: 8-slot groups g = wave, wave + 4, ... of the chunk's nq
       // blocks; corner slots are mixed over the absorbers, node slots over
-      // the CIA pairs, slots past K are zero
-      for (int g = wave; g < 2 * nq; g += kWaves) {
-        const int s0 = c0 + 8 * g;
-        float s[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) s[i] = 0.f;
-        const int nc = min(max(nU - s0, 0), 8);
-        if (nc > 0) mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g, 0, nc, W, voff, s);
-        const int vb = min(max(K - s0, 0), 8);
-        if (vb > nc) mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, voff, s);
+      // the CIA pairs, slots past K are zero.  The full corner groups come
+      // first, their loads in batches of SA tables with the next batch
+      // issued before the current one is mixed (two register buffers); the
+      // remaining groups (corners and nodes, padding) follow one by one.
+      const int ng = 2 * nq;
+      auto write_group = [&](int g, float (&s)[8]) {
         const int kq = g >> 1, h = g & 1;
         const int tcb = lane >> 5, n = lane & 31;
         if constexpr (MODE == TRX_FP32) {
@@ -296,6 +325,48 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
             *reinterpret_cast<u32x4*>(sm.bfrag + (((kq * npc + p) * 2 + tcb) * 64 + 32 * h + n) * 4) = q;
           }
         }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = 0.f;
+      };
+      // full corner groups: g < gf
+      const int gf = min(ng, max(nU - c0, 0) / 8);
+      const int na = tb.n_abs;
+      const int nta = na > 0 ? na : 1;
+      {
+        float va[SA][8], vb2[SA][8], s[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = 0.f;
+        int g = wave, t0 = 0;
+        if (g < gf) issue_corners<SA>(tb.xsec32, abs_stride, na, sm.sid + 8 * g, t0, W, voff, va);
+        auto step = [&](float (&cur)[SA][8], float (&nxt)[SA][8]) {
+          int gn = g, tn = t0 + SA;
+          if (tn >= nta) {
+            gn = g + kWaves;
+            tn = 0;
+          }
+          if (gn < gf) issue_corners<SA>(tb.xsec32, abs_stride, na, sm.sid + 8 * gn, tn, W, voff, nxt);
+          mix_corners<SA>(sm.chi, na, t0, cur, s);
+          if (tn == 0) write_group(g, s);
+          g = gn;
+          t0 = tn;
+        };
+        while (g < gf) {
+          step(va, vb2);
+          if (g >= gf) break;
+          step(vb2, va);
+        }
+      }
+      // the other groups
+      for (int g = gf + ((wave - gf) % kWaves + kWaves) % kWaves; g < ng; g += kWaves) {
+        const int s0 = c0 + 8 * g;
+        float s[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = 0.f;
+        const int nc = min(max(nU - s0, 0), 8);
+        if (nc > 0) mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g, 0, nc, W, voff, s);
+        const int vb = min(max(K - s0, 0), 8);
+        if (vb > nc) mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, voff, s);
+        write_group(g, s);
       }
       if (c0 == 0) {
         float rp = 0.f;
