@@ -1,34 +1,39 @@
 // Adjoint of chi^2 = sum_c ((D_c - O_c)/sigma_c)^2 (a8) with respect to the
 // per-layer temperatures, the log10 mixing ratios and Rp, in recompute mode:
-// the opacity and optical depth of the forward pass are not stored but
-// recomputed per (model, 64-column span) work item.
+// the optical depth of the forward pass is not stored but recomputed per
+// work item.
 //
-// Reverse of the forward steps, per model b and native point i:
+// The forward model in the slot form of the matrix-core kernels: per model
+// and wavenumber column c,
+//   tau_j = sum_q P[j][q] M_q + PR_j R,  P = dl W,  PR = dl w_R,
+//   D = Rp^2/Rs^2 + sum_j A_j (1 - e^{-tau_j}),
+// with M_q the mixed cross-section of opacity slot q (a table corner,
+// sum_i chi_i sigma_i[q], or a CIA node, sum_p w_p sigma_p[t]), R the mixed
+// Rayleigh cross-section, W[l][q] the interpolation x density weights of
+// layer l and dl the chords (Forward Models section; equations opt_dpth,
+// cia_opt_dpth, contrib, tot_opt_dpth).  Reverse, per model:
 //   Dbar_c = 2 (D_c - O_c)/sigma_c^2, Dbar_i = sum_c Dbar_c w_ci / sum_i' w_ci'
 //   (binning, Binning subsection);
-//   D_i = Rp^2/Rs^2 + sum_j A_j (1 - e^{-tau_ij}), A_j = 2 (Rp + z_j)(h_{j+1} -
-//   h_j)/Rs^2 (transit-depth equations): Abar_j = sum_i Dbar_i (1 - e^{-tau}),
-//   taubar_ij = Dbar_i A_j e^{-tau_ij};
-//   tau = dl kappa (eq. tot_opt_dpth): kappabar = dl^T taubar, and the
-//   path-length cotangent dlbar = taubar kappa^T is never formed.  With
-//   Q_m = q_j(h_m) the chord of ray j is written by parts,
-//   tau_j = 2 sum_{m>j} Q_m (kappa_{m-1} - kappa_m), and per column
-//     zbar_j  += taubar_ij sum_m Gz_jm (kappa_{m-1} - kappa_m),
-//     Rpbar   += sum_j taubar_ij sum_m GR_jm (kappa_{m-1} - kappa_m),
-//     hbar_m  += (kappa_{m-1} - kappa_m) sum_{j<m} Gh_jm taubar_ij,
-//   with Gz, GR, Gh = 2 dQ_m/d(z_j, Rp, h_m): every sum has terms of one
-//   sign where kappa falls with height (no cancellation in FP32);
-//   kappa (equations opt_dpth, cia_opt_dpth, contrib; Opacities section):
-//     Tbar_k += sum_i kappabar_ki dkappa_ki/dT_k (bracket slopes and
-//     d rho/dT from the derivative records), and the mixing-ratio adjoints
-//     through the mixed corner rows, the Rayleigh sum and the CIA sums.
+//   taubar_j = Dbar A_j e^{-tau_j},  Abar_j = sum_i Dbar_i (1 - e^{-tau_j});
+//   Mbar = P^T taubar,  Rbar = PR^T taubar                (per column)
+//   Pbar = sum_c taubar M^T,  PRbar = sum_c taubar R      (over all columns)
+//   chibar_i = sum_c sum_q Mbar_q sigma_i[q], the CIA weights and the
+//   Rayleigh species likewise;
+// and once per model in FP64, from Pbar:
+//   Wbar = dl^T Pbar  ->  Tbar_l = sum_q Wbar[l][q] dW[l][q]/dT_l (bracket
+//   slopes and d rho/dT at fixed P),
+//   dlbar = Pbar W^T  ->  zbar_j, hbar_m, Rpbar through the chords
+//   dl[j][l] = 2 (Q_{j,l+1} - Q_{j,l}), Q_{j,m} = sqrt((h_m - z_j)(2 Rp + h_m + z_j)).
 // A last per-model kernel walks the annulus weights, the shell boundaries,
-// the altitude recursion (Forward Models section) and the chemistry (fill
-// gases follow the sum constraint; log10 parameters) in reverse, in FP64.
+// the altitude recursion and the chemistry (fill gases follow the sum
+// constraint; log10 parameters) in reverse, in FP64.
 //
-// The item kernel works in FP32 (FP32 tables, derivative matrices rounded
-// from FP64) and accumulates per-model sums in FP64 atomics; the result is
-// held to 1e-4 of the FP64 reference gradient.
+// The work item is one model over a group of consecutive 64-column spans;
+// its products run on v_mfma_f32_32x32x2_f32 (FP32 operands, P rounded from
+// FP64), Pbar is accumulated in registers over the item's spans and each
+// item writes its partial sums once; a per-model kernel adds them in a
+// fixed order in FP64.  The result is held to 1e-4 of the FP64 reference
+// gradient.
 #include "trx_internal.h"
 #include "stage.h"
 
@@ -37,13 +42,14 @@ namespace trx {
 namespace {
 
 using stage::kRsrcWord3;
-using stage::stage_rows;
-constexpr int kWaves = 8;   // two waves per SIMD: the item is latency-bound
+constexpr int kWaves = 8;
 constexpr int kCols = 64;
-constexpr int kRows = 96;
+constexpr int kLd = 65;   // LDS row stride of the [row][column] tiles: transposed reads hit distinct banks
+constexpr int kAS = 4;    // tables per load batch in the staging
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-static_assert(stage::kCols == kCols, "staging shape");
-static_assert(kRows >= kMaxU + kMaxV, "staging capacity");
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+static_assert(kKG % 32 == 0 && kKG <= 3 * 32, "slot blocks of the gradient");
+static_assert(TRX_MAX_LAYERS_MFMA <= 32 * kWaves, "one ray block per wave");
 
 __device__ inline float wave_sum(float v) {
 #pragma unroll
@@ -53,6 +59,12 @@ __device__ inline float wave_sum(float v) {
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// sum over the 32 lanes of a half-wave
+__device__ inline float half_sum(float v) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
@@ -110,62 +122,83 @@ __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
   }
 }
 
-// ---- per (model, span) recompute and backward ---------------------------
+// ---- per (model, span group): recompute and backward --------------------
 struct ItemLds {
-  float* rows;   // [kRows][64] mixed corner rows, then CIA node rows
-  float* kt;     // [NP][64] kappa, later taubar
-  float* sh;     // [kRows][64] adjoints of the mixed rows
-  float* rh;     // [64] adjoint of the Rayleigh sum
-  float* lw;     // [NP][8] layer records
-  float* lwd;    // [NP][8] d(records)/dT
-  int2* sl;      // [NP] model-list slots
-  int32_t* ids;  // [kRows]
-  int32_t* tids; // [kRows]
+  float* rows;   // [kKG][kLd] mixed slot rows M of the span, later their adjoints
+  float* tbar;   // [NP][kLd] taubar of the span
+  float2* aw;    // [NP] (A_j/Rs^2, PR_j)
+  float* rpart;  // [kWaves][64] Rayleigh sums by wave
+  float* rbar;   // [64] Rbar of the span
+  int32_t* sid;  // [kKG] table row of each slot
   float* chi;    // [TRX_MAX_ABSORBERS]
   float* ciaw;   // [TRX_MAX_CIA]
-  float* rcol;   // [64] Rayleigh sum per column
-  float* pacc;   // [G.n] this item's partial sums (GradAcc offsets)
-  float* kap;    // [NP][64] kappa kept for the backward (models of <= 128 layers)
+  float* chis;   // [kMaxSpecies]
+  float* pacc;   // [G.o_P] this item's partial sums below the Pbar block
 };
 
-__host__ __device__ inline size_t carve(const Layout& L, unsigned char* base, ItemLds* out, bool keep) {
+__host__ __device__ inline size_t carve(const Layout& L, const GradAcc& G, unsigned char* base, ItemLds* out) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
     unsigned char* p = base ? base + o : nullptr;
     o += (bytes + 15) / 16 * 16;
     return p;
   };
-  const int NP = L.NP;
   ItemLds s;
-  s.rows = (float*)take((size_t)kRows * kCols * 4);
-  s.kt = (float*)take((size_t)NP * kCols * 4);
-  s.sh = (float*)take((size_t)kRows * kCols * 4);
-  s.rh = (float*)take((size_t)kCols * 4);
-  s.lw = (float*)take((size_t)NP * 8 * 4);
-  s.lwd = (float*)take((size_t)NP * 8 * 4);
-  s.sl = (int2*)take((size_t)NP * 8);
-  s.ids = (int32_t*)take(kRows * 4);
-  s.tids = (int32_t*)take(kRows * 4);
+  s.rows = (float*)take((size_t)kKG * kLd * 4);
+  s.tbar = (float*)take((size_t)L.NP * kLd * 4);
+  s.aw = (float2*)take((size_t)L.NP * 8);
+  s.rpart = (float*)take((size_t)kWaves * kCols * 4);
+  s.rbar = (float*)take((size_t)kCols * 4);
+  s.sid = (int32_t*)take(kKG * 4);
   s.chi = (float*)take(TRX_MAX_ABSORBERS * 4);
   s.ciaw = (float*)take(TRX_MAX_CIA * 4);
-  s.rcol = (float*)take((size_t)kCols * 4);
-  s.pacc = (float*)take((size_t)make_grad_acc(NP).n * 4);
-  s.kap = keep ? (float*)take((size_t)NP * kCols * 4) : nullptr;
+  s.chis = (float*)take(kMaxSpecies * 4);
+  s.pacc = (float*)take((size_t)G.o_P * 4);
   if (out) *out = s;
   return o;
 }
 
-// KEEP (models of at most 128 layers, whose kappa fits in LDS beside the
-// rest): the boundary sums read the kept kappa in tile layout and the
-// temperature and mixed-row terms run per layer with one column per lane;
-// otherwise all three are taken per tile with kappa recomputed.
-template <bool KEEP>
+// s[i] += sum_t wt[t] tab_t[rows[i]][col] for the slots i in [i0, i1) of a
+// group of 8 (tables t < nt at tab + t stride); rows of the other slots are
+// clamped into the range (their loads are in bounds, their values unused).
+__device__ inline void mix_group(const float* tab, int64_t stride, int nt, const float* wt, const int32_t* rows,
+                                 int i0, int i1, int W, int voff, float (&s)[8]) {
+  const int rec = (int)(stride * 4 < 0x7fffffff ? stride * 4 : 0x7fffffff);
+  int soff[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = i < i0 ? i0 : (i >= i1 ? i1 - 1 : i);
+    soff[i] = __builtin_amdgcn_readfirstlane(rows[k]) * W * 4;
+  }
+  for (int t0 = 0; t0 < nt; t0 += kAS) {
+    float v[kAS][8];
+#pragma unroll
+    for (int tt = 0; tt < kAS; ++tt) {
+      if (t0 + tt < nt) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(tab + (int64_t)(t0 + tt) * stride), (short)0, rec, kRsrcWord3);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[tt][i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff[i], 0));
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < kAS; ++tt) {
+      if (t0 + tt < nt) {
+        const float c = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(wt[t0 + tt])));
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i >= i0 && i < i1) s[i] = fmaf(c, v[tt][i], s[i]);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int b = __builtin_amdgcn_readfirstlane(blockIdx.x);
   if (b >= B) return;
-  const int span = __builtin_amdgcn_readfirstlane(blockIdx.y);
+  const int item = __builtin_amdgcn_readfirstlane(blockIdx.y);
   const Layout& L = a.L;
   const GradAcc& G = a.G;
   const uint8_t* slab = a.ws + (int64_t)b * L.slab;
@@ -173,158 +206,123 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
   const int N = hd->n;
   if (N == 0) return;
   const int lo = hd->lo, hi = hd->hi;
-  const int col0 = span * kCols;
-  if (col0 >= hi || col0 + kCols <= lo) return;
+  const int S = a.span_group;
+  const int sp0 = max(item * S, lo / kCols), sp1 = min(item * S + S, (hi + kCols - 1) / kCols);
+  if (sp0 >= sp1) return;
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
-  const int nU = ml->nU, nV = ml->nV;
-  if (nU + nV > kRows || nV > kMListV) {
-    // more distinct corners than the staging capacity: not built here
+  const int nU = ml->nU, nV = ml->nV, K = nU + nV;
+  if (K > kKG) {
+    // more opacity slots than the gradient's capacity: not built here
     if (threadIdx.x == 0) atomicOr(&a.model_status[b], TRX_MODEL_GRAD_UNSUPPORTED);
     return;
   }
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
-  const int col = col0 + lane;
-  const bool valid = col >= lo && col < hi;
-  const int cc = valid ? col : lo;
+  const int hl = lane >> 5, lc = lane & 31;
   const DevTables& tb = a.tab;
   const int W = tb.n_wn;
-  const bool has_cia = tb.n_cia > 0;
-  const int NP = L.NP;
-  ItemLds s;
-  carve(L, dyn, &s, KEEP);
-
-  // records, derivative records, slots, corner lists
-  {
-    const float4* lw4 = reinterpret_cast<const float4*>(slab + L.off_lw32);
-    const float4* ld4 = reinterpret_cast<const float4*>(slab + L.off_lwd32);
-    const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
-    for (int e = tid; e < 2 * NP; e += 64 * kWaves) {
-      reinterpret_cast<float4*>(s.lw)[e] = lw4[e];
-      reinterpret_cast<float4*>(s.lwd)[e] = ld4[e];
-    }
-    for (int e = tid; e < NP; e += 64 * kWaves) s.sl[e] = *reinterpret_cast<const int2*>(lid + 8 * e + 2);
-    for (int e = tid; e < nU; e += 64 * kWaves) s.ids[e] = ml->ids[e];
-    for (int e = tid; e < nV; e += 64 * kWaves) s.tids[e] = ml->tids[e];
-    if (tid < TRX_MAX_ABSORBERS) s.chi[tid] = hd->chi_abs32[tid];
-    if (tid < TRX_MAX_CIA) s.ciaw[tid] = hd->cia_w32[tid];
-  }
-  __syncthreads();
+  const int nrb = hd->nrb, NR = 32 * nrb;
+  const int nqb = (K + 31) / 32, KP = 32 * nqb;   // 32-slot blocks
+  const int nkq = (K + 15) / 16;                  // 16-slot blocks
+  const int NJB = L.NP / 16;
   const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
   const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
-  float* rows = s.rows;
-  float* crows = rows + nU * kCols;
-  stage_rows<kWaves>(tb.xsec32, abs_stride, W, cc, s.ids, nU, s.chi, tb.n_abs, rows, wave, lane);
-  if (has_cia) stage_rows<kWaves>(tb.cia32, cia_stride, W, cc, s.tids, nV, s.ciaw, tb.n_cia, crows, wave, lane);
-  float R = 0.f;
-  if (tb.has_rayleigh)
-    for (int q = 0; q < tb.n_abs + 2; ++q) R = fmaf(hd->chi_s32[q], tb.ray32[(int64_t)q * W + cc], R);
-  for (int e = tid; e < (nU + nV) * kCols; e += 64 * kWaves) s.sh[e] = 0.f;
-  for (int e = tid; e < G.n; e += 64 * kWaves) s.pacc[e] = 0.f;
-  if (tid < kCols) {
-    s.rh[tid] = 0.f;
-    s.rcol[tid] = R;
+  const float* pa = reinterpret_cast<const float*>(slab + L.off_pa);
+  const float* pt = reinterpret_cast<const float*>(slab + L.off_pt);
+  ItemLds s;
+  carve(L, G, dyn, &s);
+
+  // records: ray weights (zero past N), slot rows, mixing ratios
+  {
+    const float2* awg = reinterpret_cast<const float2*>(slab + L.off_aw);
+    const int32_t* sid = reinterpret_cast<const int32_t*>(slab + L.off_sid);
+    if (tid < NR) s.aw[tid] = awg[tid];
+    if (tid < K) s.sid[tid] = sid[tid];
+    if (tid < TRX_MAX_ABSORBERS) s.chi[tid] = hd->chi_abs32[tid];
+    if (tid < TRX_MAX_CIA) s.ciaw[tid] = hd->cia_w32[tid];
+    if (tid < kMaxSpecies) s.chis[tid] = hd->chi_s32[tid];
+    for (int e = tid; e < G.o_P; e += 64 * kWaves) s.pacc[e] = 0.f;
   }
   __syncthreads();
+  float* acc = s.pacc;
 
-  // kappa (or, with the derivative records, dkappa/dT) of layer k at
-  // column c; the slot words are read per lane (k may differ across lanes)
-  auto comb = [&](int k, const float* w, int c) -> float {
-    const int2 sk = s.sl[k];
-    const uint32_t sa = (uint32_t)sk.x;
-    float v = w[0] * rows[(sa & 0xff) * kCols + c];
-    v = fmaf(w[1], rows[((sa >> 8) & 0xff) * kCols + c], v);
-    v = fmaf(w[2], rows[((sa >> 16) & 0xff) * kCols + c], v);
-    v = fmaf(w[3], rows[(sa >> 24) * kCols + c], v);
-    v = fmaf(w[4], s.rcol[c], v);
-    if (has_cia) {
-      const uint32_t sc = (uint32_t)sk.y;
-      v = fmaf(w[5], crows[(sc & 0xff) * kCols + c], v);
-      v = fmaf(w[6], crows[((sc >> 8) & 0xff) * kCols + c], v);
+  // Pbar tiles (32 rays x 32 slots) of this wave, t = wave + 8 u, kept in
+  // registers over the item's spans
+  constexpr int kPT = 3;
+  f32x16 pb[kPT];
+#pragma unroll
+  for (int u = 0; u < kPT; ++u) pb[u] = f32x16{};
+  const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
+
+  for (int span = sp0; span < sp1; ++span) {
+    const int col0 = span * kCols;
+    const int col = col0 + lane;
+    const bool valid = col >= lo && col < hi;
+    const int cc = valid ? col : lo;
+    const int voff = cc * 4;
+
+    // staging: M of the span's slots (zero past K) and the Rayleigh sums
+    {
+      float rp = 0.f;
+      for (int k = wave; k < ns; k += kWaves) rp = fmaf(s.chis[k], tb.ray32[(int64_t)k * W + cc], rp);
+      s.rpart[wave * kCols + lane] = rp;
     }
-    return v;
-  };
+    for (int g = wave; g < KP / 8; g += kWaves) {
+      const int s0 = 8 * g;
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.f;
+      const int nc = min(max(nU - s0, 0), 8);
+      if (nc > 0) mix_group(tb.xsec32, abs_stride, tb.n_abs, s.chi, s.sid + s0, 0, nc, W, voff, v);
+      const int vb = min(max(K - s0, 0), 8);
+      if (vb > nc) mix_group(tb.cia32, cia_stride, tb.n_cia, s.ciaw, s.sid + s0, nc, vb, W, voff, v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s.rows[(s0 + i) * kLd + lane] = v[i];
+    }
+    if (tid < kCols) s.rbar[tid] = 0.f;
+    __syncthreads();
 
-  // A: kappa of every layer of the padded ray blocks (zero past N)
-  const int nrb = hd->nrb;
-  const int NR = 32 * nrb;
-  for (int k = wave; k < NR; k += kWaves) {
-    const float v = k < N ? comb(k, s.lw + 8 * k, lane) : 0.f;
-    s.kt[k * kCols + lane] = v;
-    if constexpr (KEEP) s.kap[k * kCols + lane] = v;
-  }
-  __syncthreads();
-
-  float* acc = s.pacc;   // per-item partial sums (LDS)
-  const int hl = lane >> 5, lc = lane & 31;
-  // column sums over the 32 lanes of a half-wave (one accumulator column each)
-  auto half_sum = [](float v) {
+    // tau tiles (32 rays x 32 columns), t = wave, wave + 8: tau = P M + PR R
+    // over the nonzero 16-slot blocks; then taubar, Abar, PRbar and Rbar
+    for (int t = wave; t < 2 * nrb; t += kWaves) {
+      const int rb = t >> 1, tcb = t & 1;
+      const uint64_t m = hd->kq_mask[rb];
+      f32x16 tau = f32x16{};
+      for (int kq = 0; kq < nkq; ++kq) {
+        if (!((m >> kq) & 1)) continue;
+        const u32x4* fp = reinterpret_cast<const u32x4*>(pa + (((int64_t)rb * (kKG / 16) + kq) * 64 + lane) * 8);
+        const u32x4 a0 = fp[0], a1 = fp[1];
 #pragma unroll
-    for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
-  };
-
-  // B: per (32-ray, 32-column) tile, on v_mfma_f32_32x32x2f32 with K = two
-  // layers per step (A lane l: [ray l%32][layer l/32], B lane l:
-  // [layer l/32][column l%32], C register q: ray 8(q/4) + 4(l/32) + q%4,
-  // column l%32):
-  //   tau = dl kappa, U = Gz dkappa, V = GR dkappa, dkappa_k = kappa_k - kappa_{k+1};
-  // then taubar = Dbar A e^{-tau}, Abar_j, zbar_j, Rpbar column sums.
-  // Tiles t = wave, wave + 4, ... of nrb x 2; each wave keeps its taubar
-  // tiles in registers until every wave is done with kappa.
-  const float4* m3 = reinterpret_cast<const float4*>(slab + L.off_m3);
-  constexpr int kTilesMax = (TRX_MAX_LAYERS_MFMA / 32) * 2;
-  constexpr int kTW = (kTilesMax + kWaves - 1) / kWaves;
-  f32x16 tbt[kTW];
-  float rp = 0.f;
-#pragma unroll
-  for (int ti = 0; ti < kTW; ++ti) {
-    const int t = wave + kWaves * ti;
-    tbt[ti] = f32x16{};
-    if (t < 2 * nrb) {
-      const int rb = t >> 1, cb = t & 1;
-      const int c = 32 * cb + lc;
-      f32x16 tau = f32x16{}, U = f32x16{}, V = f32x16{};
-      const float4* arow = m3 + (int64_t)(32 * rb + lc) * NP;
-      // eight K-steps per round: their A loads are issued before the products
-      for (int k0 = 32 * rb; k0 < N; k0 += 16) {
-        float4 m[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int k = k0 + 2 * u + hl;
-          m[u] = k < NR ? arow[k] : float4{};
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (k0 + 2 * u < N) {
-            const int k = k0 + 2 * u + hl;
-            const float x = s.kt[k * kCols + c];
-            const float xn = k + 1 < NR ? s.kt[(k + 1) * kCols + c] : 0.f;   // kappa_N = 0
-            const float d = x - xn;
-            tau = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].x, x, tau, 0, 0, 0);
-            U = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].y, d, U, 0, 0, 0);
-            V = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].z, d, V, 0, 0, 0);
-          }
+        for (int i = 0; i < 8; ++i) {
+          const float av = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
+          const float bv = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
+          tau = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, tau, 0, 0, 0);
         }
       }
+      const int c = 32 * tcb + lc;
+      float Rc = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) Rc += s.rpart[w * kCols + c];
       const int cg = col0 + c;
       const float Db = (cg >= lo && cg < hi) ? a.dbar[(int64_t)b * W + cg] : 0.f;
-      f32x16 tb, ab, zb;
+      float ab[16], pr[16];
+      float rs = 0.f;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
-        const float e = __expf(-tau[q]);
-        const float tv = Db * s.lw[8 * j + 7] * e;
-        tb[q] = tv;
-        ab[q] = -Db * expm1f(-tau[q]);
-        zb[q] = tv * U[q];
-        rp = fmaf(tv, V[q], rp);
+        const float2 w = s.aw[j];
+        const float x = fmaf(w.y, Rc, tau[q]);
+        const float tv = Db * w.x * __expf(-x);
+        s.tbar[j * kLd + c] = tv;
+        ab[q] = -Db * expm1f(-x);
+        pr[q] = tv * Rc;
+        rs = fmaf(w.y, tv, rs);
       }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         ab[q] = half_sum(ab[q]);
-        zb[q] = half_sum(zb[q]);
+        pr[q] = half_sum(pr[q]);
       }
       if (lc == 0) {
 #pragma unroll
@@ -332,333 +330,130 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
           const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
           if (j < N) {
             atomicAdd(acc + G.o_A + j, ab[q]);
-            atomicAdd(acc + G.o_z + j, zb[q]);
+            atomicAdd(acc + G.o_PR + j, pr[q]);
           }
         }
       }
-      tbt[ti] = tb;
+      rs += __shfl_xor(rs, 32, 64);
+      if (hl == 0) atomicAdd(&s.rbar[c], rs);
     }
-  }
-  {
-    const float t = wave_sum(rp);
-    if (lane == 0) atomicAdd(acc + G.o_Rp, t);
-  }
-  __syncthreads();   // kappa is no longer read: its space takes taubar
+    __syncthreads();
+
+    // Pbar += taubar M^T over the span's 64 columns (tiles of nonzero P)
 #pragma unroll
-  for (int ti = 0; ti < kTW; ++ti) {
-    const int t = wave + kWaves * ti;
-    if (t < 2 * nrb) {
-      const int rb = t >> 1, cb = t & 1;
+    for (int u = 0; u < kPT; ++u) {
+      const int t = wave + kWaves * u;
+      if (t < nrb * nqb) {
+        const int rb = t / nqb, qb = t - rb * nqb;
+        if ((hd->kq_mask[rb] >> (2 * qb)) & 3) {
+          const float* ar = s.tbar + (32 * rb + lc) * kLd + hl;
+          const float* br = s.rows + (32 * qb + lc) * kLd + hl;
+#pragma unroll 8
+          for (int st = 0; st < 32; ++st)
+            pb[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[2 * st], br[2 * st], pb[u], 0, 0, 0);
+        }
+      }
+    }
+    // Mbar = P^T taubar: tile (32 slots x 32 columns) t = wave
+    f32x16 mb = f32x16{};
+    const bool has_mb = wave < 2 * nqb;
+    if (has_mb) {
+      const int qb = wave >> 1, tcb = wave & 1;
+      for (int jb = 0; jb < 2 * nrb; ++jb) {
+        if (!((hd->kq_mask[jb >> 1] >> (2 * qb)) & 3)) continue;
+        const u32x4* fp = reinterpret_cast<const u32x4*>(pt + (((int64_t)qb * NJB + jb) * 64 + lane) * 8);
+        const u32x4 a0 = fp[0], a1 = fp[1];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float av = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
+          const float bv = s.tbar[(16 * jb + 2 * i + hl) * kLd + 32 * tcb + lc];
+          mb = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, mb, 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();   // M is no longer read: its rows take Mbar
+    if (has_mb) {
+      const int qb = wave >> 1, tcb = wave & 1;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s.rows[(32 * qb + 8 * (q >> 2) + 4 * hl + (q & 3)) * kLd + 32 * tcb + lc] = mb[q];
+    }
+    __syncthreads();
+
+    // mixing-ratio adjoints: corner rows against each absorber's table,
+    // CIA node rows against each pair's table, Rbar against each species'
+    // Rayleigh row
+    {
+      const int rec = (int)(abs_stride * 4 < 0x7fffffff ? abs_stride * 4 : 0x7fffffff);
+      constexpr int DG = 8, DA = 4;   // corners x absorbers in flight
+      for (int i0 = 0; i0 < tb.n_abs; i0 += DA) {
+        float acc_i[DA] = {0.f, 0.f, 0.f, 0.f};
+        for (int u0 = wave; u0 < nU; u0 += kWaves * DG) {
+          int soff[DG];
+#pragma unroll
+          for (int g = 0; g < DG; ++g) {
+            const int u = u0 + kWaves * g < nU ? u0 + kWaves * g : u0;
+            soff[g] = __builtin_amdgcn_readfirstlane(s.sid[u]) * W * 4;
+          }
+          float v[DA][DG];
+#pragma unroll
+          for (int ii = 0; ii < DA; ++ii) {
+            if (i0 + ii < tb.n_abs) {
+              const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                  (void*)(tb.xsec32 + (int64_t)(i0 + ii) * abs_stride), (short)0, rec, kRsrcWord3);
+#pragma unroll
+              for (int g = 0; g < DG; ++g)
+                v[ii][g] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff[g], 0));
+            }
+          }
+#pragma unroll
+          for (int ii = 0; ii < DA; ++ii) {
+            if (i0 + ii < tb.n_abs) {
+#pragma unroll
+              for (int g = 0; g < DG; ++g)
+                if (u0 + kWaves * g < nU) acc_i[ii] = fmaf(s.rows[(u0 + kWaves * g) * kLd + lane], v[ii][g], acc_i[ii]);
+            }
+          }
+        }
+#pragma unroll
+        for (int ii = 0; ii < DA; ++ii) {
+          if (i0 + ii < tb.n_abs) {
+            const float t = wave_sum(acc_i[ii]);
+            if (lane == 0) atomicAdd(acc + G.o_chi + i0 + ii, t);
+          }
+        }
+      }
+      for (int p = 0; p < tb.n_cia; ++p) {
+        const float* tp = tb.cia32 + (int64_t)p * cia_stride;
+        float acc_p = 0.f;
+        for (int t = nU + wave; t < K; t += kWaves)
+          acc_p = fmaf(s.rows[t * kLd + lane], tp[(int64_t)s.sid[t] * W + cc], acc_p);
+        acc_p = wave_sum(acc_p);
+        if (lane == 0) atomicAdd(acc + G.o_cw + p, acc_p);
+      }
+      const float rl = s.rbar[lane];
+      for (int q = wave; q < ns; q += kWaves) {
+        const float t = wave_sum(rl * tb.ray32[(int64_t)q * W + cc]);
+        if (lane == 0) atomicAdd(acc + G.o_chi + q, t);
+      }
+    }
+    __syncthreads();   // rows, tbar and rbar are rewritten by the next span
+  }
+
+  // this item's partial sums, reduced per model in a fixed order later
+  float* dst = a.part + ((int64_t)b * a.n_items + item) * G.n;
+  for (int e = tid; e < G.o_P; e += 64 * kWaves) dst[e] = s.pacc[e];
+#pragma unroll
+  for (int u = 0; u < kPT; ++u) {
+    const int t = wave + kWaves * u;
+    if (t < nrb * nqb) {
+      const int rb = t / nqb, qb = t - rb * nqb;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
-        s.kt[j * kCols + 32 * cb + lc] = tbt[ti][q];
+        dst[G.o_P + j * kKG + 32 * qb + lc] = pb[u][q];
       }
     }
   }
-  __syncthreads();
-
-  // C: per (32-layer, 32-column) tile: kappabar = dl^T taubar and
-  // gbar = Gh^T taubar (K = two rays per step, rays j <= layer), then per
-  // (layer, column) the boundary, temperature and mixed-row adjoints
-  const float2* mt = reinterpret_cast<const float2*>(slab + L.off_mt);
-  if constexpr (KEEP) {
-    // one tile per wave (2 nrb <= 8): products, then the boundary sums in
-    // tile layout from the kept kappa
-    static_assert(2 * 4 <= kWaves, "one tile per wave");
-    f32x16 kb = f32x16{};
-    const int t = wave;
-    const int lb = t >> 1, cb = t & 1;
-    const int c = 32 * cb + lc;
-    if (t < 2 * nrb) {
-      f32x16 gb = f32x16{};
-      const float2* arow = mt + (int64_t)(32 * lb + lc) * NP;
-      const int jmax = min(N, 32 * lb + 32);
-      for (int j0 = 0; j0 < jmax; j0 += 16) {
-        float2 m[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = j0 + 2 * u + hl;
-          m[u] = j < NR ? arow[j] : float2{};
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (j0 + 2 * u < jmax) {
-            const int j = j0 + 2 * u + hl;
-            const float x = s.kt[j * kCols + c];
-            kb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].x, x, kb, 0, 0, 0);
-            gb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].y, x, gb, 0, 0, 0);
-          }
-        }
-      }
-      float hs[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
-        const float d = s.kap[k * kCols + c] - (k + 1 < NR ? s.kap[(k + 1) * kCols + c] : 0.f);
-        hs[q] = k < N ? gb[q] * d : 0.f;
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) hs[q] = half_sum(hs[q]);
-      if (lc == 0) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
-          if (k < N) atomicAdd(acc + G.o_h + k + 1, hs[q]);
-        }
-      }
-    }
-    __syncthreads();   // taubar is no longer read: its space takes kappabar
-    if (t < 2 * nrb) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
-        s.kt[k * kCols + c] = kb[q];
-      }
-    }
-    __syncthreads();
-    // per layer, one column per lane (slots and weights uniform): the
-    // temperature term and the scatter into the mixed-row adjoints, which
-    // accumulates in registers while consecutive layers keep their slots
-    const int per = (N + kWaves - 1) / kWaves;
-    const int k0 = wave * per, k1 = min(N, k0 + per);
-    uint32_t psa = 0xffffffffu, psc = 0xffffffffu;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, q0 = 0.f, q1 = 0.f, rsum = 0.f;
-    for (int k = k0; k < k1; ++k) {
-      const int2 sk = s.sl[k];
-      const uint32_t sa = __builtin_amdgcn_readfirstlane((uint32_t)sk.x);
-      const uint32_t sc = __builtin_amdgcn_readfirstlane((uint32_t)sk.y);
-      const float4 wa = *reinterpret_cast<const float4*>(s.lw + 8 * k);
-      const float4 wb = *reinterpret_cast<const float4*>(s.lw + 8 * k + 4);
-      const float4 da = *reinterpret_cast<const float4*>(s.lwd + 8 * k);
-      const float4 db = *reinterpret_cast<const float4*>(s.lwd + 8 * k + 4);
-      const float m0 = rows[(sa & 0xff) * kCols + lane];
-      const float m1 = rows[((sa >> 8) & 0xff) * kCols + lane];
-      const float m2 = rows[((sa >> 16) & 0xff) * kCols + lane];
-      const float m3 = rows[(sa >> 24) * kCols + lane];
-      float dk = da.x * m0;
-      dk = fmaf(da.y, m1, dk);
-      dk = fmaf(da.z, m2, dk);
-      dk = fmaf(da.w, m3, dk);
-      dk = fmaf(db.x, R, dk);
-      if (has_cia) {
-        dk = fmaf(db.y, crows[(sc & 0xff) * kCols + lane], dk);
-        dk = fmaf(db.z, crows[((sc >> 8) & 0xff) * kCols + lane], dk);
-      }
-      const float kv = s.kt[k * kCols + lane];
-      const float ts = wave_sum(kv * dk);
-      if (lane == 0) atomicAdd(acc + G.o_T + k, ts);
-      if (sa != psa) {
-        if (psa != 0xffffffffu) {
-          atomicAdd(&s.sh[(psa & 0xff) * kCols + lane], a0);
-          atomicAdd(&s.sh[((psa >> 8) & 0xff) * kCols + lane], a1);
-          atomicAdd(&s.sh[((psa >> 16) & 0xff) * kCols + lane], a2);
-          atomicAdd(&s.sh[(psa >> 24) * kCols + lane], a3);
-        }
-        psa = sa;
-        a0 = a1 = a2 = a3 = 0.f;
-      }
-      a0 = fmaf(wa.x, kv, a0);
-      a1 = fmaf(wa.y, kv, a1);
-      a2 = fmaf(wa.z, kv, a2);
-      a3 = fmaf(wa.w, kv, a3);
-      rsum = fmaf(wb.x, kv, rsum);
-      if (has_cia) {
-        if (sc != psc) {
-          if (psc != 0xffffffffu) {
-            atomicAdd(&s.sh[(nU + (psc & 0xff)) * kCols + lane], q0);
-            atomicAdd(&s.sh[(nU + ((psc >> 8) & 0xff)) * kCols + lane], q1);
-          }
-          psc = sc;
-          q0 = q1 = 0.f;
-        }
-        q0 = fmaf(wb.y, kv, q0);
-        q1 = fmaf(wb.z, kv, q1);
-      }
-    }
-    if (psa != 0xffffffffu) {
-      atomicAdd(&s.sh[(psa & 0xff) * kCols + lane], a0);
-      atomicAdd(&s.sh[((psa >> 8) & 0xff) * kCols + lane], a1);
-      atomicAdd(&s.sh[((psa >> 16) & 0xff) * kCols + lane], a2);
-      atomicAdd(&s.sh[(psa >> 24) * kCols + lane], a3);
-    }
-    if (has_cia && psc != 0xffffffffu) {
-      atomicAdd(&s.sh[(nU + (psc & 0xff)) * kCols + lane], q0);
-      atomicAdd(&s.sh[(nU + ((psc >> 8) & 0xff)) * kCols + lane], q1);
-    }
-    if (k1 > k0) atomicAdd(&s.rh[lane], rsum);
-  } else
-  for (int t = wave; t < 2 * nrb; t += kWaves) {
-    const int lb = t >> 1, cb = t & 1;
-    const int c = 32 * cb + lc;
-    f32x16 kb = f32x16{}, gb = f32x16{};
-    const float2* arow = mt + (int64_t)(32 * lb + lc) * NP;
-    const int jmax = min(N, 32 * lb + 32);
-    for (int j0 = 0; j0 < jmax; j0 += 16) {
-      float2 m[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = j0 + 2 * u + hl;
-        m[u] = j < NR ? arow[j] : float2{};
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (j0 + 2 * u < jmax) {
-          const int j = j0 + 2 * u + hl;
-          const float x = s.kt[j * kCols + c];
-          kb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].x, x, kb, 0, 0, 0);
-          gb = __builtin_amdgcn_mfma_f32_32x32x2f32(m[u].y, x, gb, 0, 0, 0);
-        }
-      }
-    }
-    // per lane: layers k = 32 lb + 8 r + 4 (l/32) + i (runs r of four
-    // consecutive layers) at column c.  kappa of a run's five layers is
-    // computed once; the scatter into the mixed-row adjoints accumulates in
-    // registers while consecutive layers keep their corner slots and is
-    // flushed to LDS when they change; the column sums of all 16 layers are
-    // reduced together at the end.
-    float hs[16], ts[16];
-    float rsum = 0.f;
-    uint32_t psa = 0xffffffffu, psc = 0xffffffffu;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, c0 = 0.f, c1 = 0.f;
-    auto flush_abs = [&]() {
-      if (psa != 0xffffffffu) {
-        atomicAdd(&s.sh[(psa & 0xff) * kCols + c], a0);
-        atomicAdd(&s.sh[((psa >> 8) & 0xff) * kCols + c], a1);
-        atomicAdd(&s.sh[((psa >> 16) & 0xff) * kCols + c], a2);
-        atomicAdd(&s.sh[(psa >> 24) * kCols + c], a3);
-      }
-      a0 = a1 = a2 = a3 = 0.f;
-    };
-    auto flush_cia = [&]() {
-      if (psc != 0xffffffffu) {
-        atomicAdd(&s.sh[(nU + (psc & 0xff)) * kCols + c], c0);
-        atomicAdd(&s.sh[(nU + ((psc >> 8) & 0xff)) * kCols + c], c1);
-      }
-      c0 = c1 = 0.f;
-    };
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k0 = 32 * lb + 8 * r + 4 * hl;
-      float kp[5];
-#pragma unroll
-      for (int i = 0; i < 5; ++i) kp[i] = k0 + i < N ? comb(k0 + i, s.lw + 8 * (k0 + i), c) : 0.f;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = 4 * r + i;
-        const int k = k0 + i;
-        hs[q] = 0.f;
-        ts[q] = 0.f;
-        if (k < N) {
-          const float* w = s.lw + 8 * k;
-          const float dk = comb(k, s.lwd + 8 * k, c);
-          hs[q] = gb[q] * (kp[i] - kp[i + 1]);
-          ts[q] = kb[q] * dk;
-          const float kv = kb[q];
-          const int2 sk = s.sl[k];
-          if ((uint32_t)sk.x != psa) {
-            flush_abs();
-            psa = (uint32_t)sk.x;
-          }
-          a0 = fmaf(w[0], kv, a0);
-          a1 = fmaf(w[1], kv, a1);
-          a2 = fmaf(w[2], kv, a2);
-          a3 = fmaf(w[3], kv, a3);
-          rsum = fmaf(w[4], kv, rsum);
-          if (has_cia) {
-            if ((uint32_t)sk.y != psc) {
-              flush_cia();
-              psc = (uint32_t)sk.y;
-            }
-            c0 = fmaf(w[5], kv, c0);
-            c1 = fmaf(w[6], kv, c1);
-          }
-        }
-      }
-    }
-    flush_abs();
-    if (has_cia) flush_cia();
-    atomicAdd(&s.rh[c], rsum);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      hs[q] = half_sum(hs[q]);
-      ts[q] = half_sum(ts[q]);
-    }
-    if (lc == 0) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int k = 32 * lb + 8 * (q >> 2) + 4 * hl + (q & 3);
-        if (k < N) {
-          atomicAdd(acc + G.o_h + k + 1, hs[q]);
-          atomicAdd(acc + G.o_T + k, ts[q]);
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // D: mixing-ratio adjoints: corner rows against each absorber's table,
-  // CIA node rows against each pair's table, the Rayleigh row per species
-  const int rec = (int)(abs_stride * 4 < 0x7fffffff ? abs_stride * 4 : 0x7fffffff);
-  constexpr int DG = 8, DA = 4;   // corners x absorbers in flight
-  for (int i0 = 0; i0 < tb.n_abs; i0 += DA) {
-    float acc_i[DA] = {0.f, 0.f, 0.f, 0.f};
-    for (int u0 = wave; u0 < nU; u0 += kWaves * DG) {
-      int soff[DG];
-#pragma unroll
-      for (int g = 0; g < DG; ++g) {
-        const int u = u0 + kWaves * g < nU ? u0 + kWaves * g : u0;
-        soff[g] = __builtin_amdgcn_readfirstlane(s.ids[u]) * W * 4;
-      }
-      float v[DA][DG];
-#pragma unroll
-      for (int ii = 0; ii < DA; ++ii) {
-        if (i0 + ii < tb.n_abs) {
-          const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-              (void*)(tb.xsec32 + (int64_t)(i0 + ii) * abs_stride), (short)0, rec, kRsrcWord3);
-#pragma unroll
-          for (int g = 0; g < DG; ++g)
-            v[ii][g] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, cc * 4, soff[g], 0));
-        }
-      }
-#pragma unroll
-      for (int ii = 0; ii < DA; ++ii) {
-        if (i0 + ii < tb.n_abs) {
-#pragma unroll
-          for (int g = 0; g < DG; ++g)
-            if (u0 + kWaves * g < nU) acc_i[ii] = fmaf(s.sh[(u0 + kWaves * g) * kCols + lane], v[ii][g], acc_i[ii]);
-        }
-      }
-    }
-#pragma unroll
-    for (int ii = 0; ii < DA; ++ii) {
-      if (i0 + ii < tb.n_abs) {
-        const float t = wave_sum(acc_i[ii]);
-        if (lane == 0) atomicAdd(acc + G.o_chi + i0 + ii, t);
-      }
-    }
-  }
-  if (has_cia) {
-    for (int p = 0; p < tb.n_cia; ++p) {
-      const float* tp = tb.cia32 + (int64_t)p * cia_stride;
-      float acc_p = 0.f;
-      for (int t = wave; t < nV; t += kWaves)
-        acc_p = fmaf(s.sh[(nU + t) * kCols + lane], tp[(int64_t)s.tids[t] * W + cc], acc_p);
-      acc_p = wave_sum(acc_p);
-      if (lane == 0) atomicAdd(acc + G.o_cw + p, acc_p);
-    }
-  }
-  if (tb.has_rayleigh) {
-    const float rl = s.rh[lane];
-    for (int q = wave; q < tb.n_abs + 2; q += kWaves) {
-      const float t = wave_sum(rl * tb.ray32[(int64_t)q * W + cc]);
-      if (lane == 0) atomicAdd(acc + G.o_chi + q, t);
-    }
-  }
-  // this item's partial sums, reduced per model in a fixed order later
-  __syncthreads();
-  float* dst = a.part + ((int64_t)b * a.n_spans + span) * G.n;
-  for (int e = tid; e < G.n; e += 64 * kWaves) dst[e] = s.pacc[e];
 }
 
 // ---- per model: sum of the item partials over its spans (FP64) -----------
@@ -666,17 +461,146 @@ __global__ __launch_bounds__(256) void k_adj_reduce(AdjArgs a) {
   const int b = blockIdx.x;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if (b >= B) return;
-  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(a.ws + (int64_t)b * a.L.slab);
+  const uint8_t* slab = a.ws + (int64_t)b * a.L.slab;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
   if (hd->n == 0) return;
-  const MList* ml = reinterpret_cast<const MList*>(a.ws + (int64_t)b * a.L.slab + a.L.off_mlist);
-  if (ml->nU + ml->nV > kRows || ml->nV > kMListV) return;   // flagged by the item kernel
-  const int n = a.G.n;
-  const float* src = a.part + (int64_t)b * a.n_spans * n;
-  double* acc = a.acc + (int64_t)b * n;
+  const MList* ml = reinterpret_cast<const MList*>(slab + a.L.off_mlist);
+  const int K = ml->nU + ml->nV;
+  if (K > kKG) return;   // flagged by the item kernel
+  const GradAcc& G = a.G;
+  const int S = a.span_group;
+  const int g0 = hd->span_lo / S, g1 = (hd->span_hi - 1) / S;   // items that meet the window
+  const float* src = a.part + (int64_t)b * a.n_items * G.n;
+  double* acc = a.acc + (int64_t)b * G.n;
+  const int NR = 32 * hd->nrb, KP = 32 * ((K + 31) / 32);
+  const int n = G.o_P + NR * kKG;
   for (int e = threadIdx.x; e < n; e += 256) {
+    if (e >= G.o_P && (e - G.o_P) % kKG >= KP) continue;
     double t = 0.0;
-    for (int sp = hd->span_lo; sp < hd->span_hi; ++sp) t += src[(int64_t)sp * n + e];
+    for (int g = g0; g <= g1; ++g) t += src[(int64_t)g * G.n + e];
     acc[e] += t;
+  }
+}
+
+// ---- per model: the path x weight products in reverse (FP64) -------------
+// Wbar[l][q] = sum_{j <= l} dl[j][l] Pbar[j][q] for the slots q of layer l
+// gives Tbar_l through dW/dT; dlbar[j][l] = sum_q Pbar[j][q] W[l][q] +
+// PRbar_j w_R,l gives the chord adjoints: with dl[j][l] = 2 (Q_{j,l+1} -
+// Q_{j,l}) (Q_{j,j} = 0), dQ/dh_m = (Rp + h_m)/Q, dQ/dz_j = -(Rp + z_j)/Q,
+// dQ/dRp = (h_m - z_j)/Q (a zero Q, the top ray at the top boundary, has no
+// derivative).
+constexpr int kPM = 256;
+__global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
+  const int b = blockIdx.x;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if (b >= B) return;
+  const Layout& L = a.L;
+  const GradAcc& G = a.G;
+  const uint8_t* slab = a.ws + (int64_t)b * L.slab;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
+  const int N = hd->n;
+  if (N == 0) return;
+  const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
+  const int nU = ml->nU, nV = ml->nV;
+  if (nU + nV > kKG) return;
+  const double* zs = reinterpret_cast<const double*>(slab + L.off_z);
+  const double* lw64 = reinterpret_cast<const double*>(slab + L.off_lw64);
+  const double* lwd = reinterpret_cast<const double*>(slab + L.off_lwd64);
+  const int32_t* lid = reinterpret_cast<const int32_t*>(slab + L.off_lid);
+  double* acc = a.acc + (int64_t)b * G.n;
+  const double* Pb = acc + G.o_P;
+  const double* PRb = acc + G.o_PR;
+  const double Rp = hd->Rp;
+  const int tid = threadIdx.x;
+
+  __shared__ double sZ[TRX_MAX_LAYERS_MFMA];
+  __shared__ double sH[TRX_MAX_LAYERS_MFMA + 1];
+  __shared__ double sW[TRX_MAX_LAYERS_MFMA][7];   // 4 corners, 2 CIA nodes, Rayleigh
+  __shared__ double sD[TRX_MAX_LAYERS_MFMA][7];   // their d/dT at fixed P
+  __shared__ int sS[TRX_MAX_LAYERS_MFMA][6];      // their slots
+  __shared__ double sHb[TRX_MAX_LAYERS_MFMA + 1];
+  __shared__ double sRp[kPM / 64];
+  const int nq = nV > 0 ? 6 : 4;
+  for (int l = tid; l < N; l += kPM) {
+    sZ[l] = zs[l];
+    const int perm[7] = {0, 1, 2, 3, 5, 6, 4};
+    for (int q = 0; q < 7; ++q) {
+      const double w = lw64[8 * l + perm[q]];
+      sW[l][q] = (q == 4 || q == 5) ? w / kCiaScale32 : w;
+      sD[l][q] = lwd[8 * l + perm[q]];
+    }
+    const uint32_t c01 = (uint32_t)lid[8 * l + 6], c23 = (uint32_t)lid[8 * l + 7];
+    const uint32_t cw = (uint32_t)lid[8 * l + 3];
+    sS[l][0] = c01 & 0xffff;
+    sS[l][1] = c01 >> 16;
+    sS[l][2] = c23 & 0xffff;
+    sS[l][3] = c23 >> 16;
+    sS[l][4] = nU + (cw & 0xff);
+    sS[l][5] = nU + ((cw >> 8) & 0xff);
+  }
+  for (int m = tid; m <= N; m += kPM) sHb[m] = 0.0;
+  __syncthreads();
+  for (int m = tid; m <= N; m += kPM) sH[m] = m == 0 ? 0.0 : (m == N ? sZ[N - 1] : 0.5 * (sZ[m - 1] + sZ[m]));
+  __syncthreads();
+  auto qv = [&](double h, double z) { return sqrt(fmax((h - z) * (2.0 * Rp + h + z), 0.0)); };
+  auto chord = [&](int j, int l) -> double {
+    const double zj = sZ[j];
+    const double h0 = sH[l], h1 = sH[l + 1];
+    const double q1 = qv(h1, zj);
+    if (l == j) return 2.0 * q1;
+    return 2.0 * (h1 - h0) * (2.0 * Rp + h0 + h1) / (q1 + qv(h0, zj));
+  };
+
+  // temperatures through the weights: thread per layer
+  for (int l = tid; l < N; l += kPM) {
+    double wb[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j <= l; ++j) {
+      const double d = chord(j, l);
+      const double* pr = Pb + (int64_t)j * kKG;
+      for (int q = 0; q < nq; ++q) wb[q] += d * pr[sS[l][q]];
+      wb[6] += d * PRb[j];
+    }
+    double t = 0.0;
+    for (int q = 0; q < nq; ++q) t += wb[q] * sD[l][q];
+    t += wb[6] * sD[l][6];
+    acc[G.o_T + l] += t;
+  }
+  // chords: thread per ray
+  double rpb = 0.0;
+  for (int j = tid; j < N; j += kPM) {
+    const double zj = sZ[j];
+    const double* pr = Pb + (int64_t)j * kKG;
+    double zb = 0.0;
+    double q0 = 0.0;
+    for (int l = j; l < N; ++l) {
+      double dlb = PRb[j] * sW[l][6];
+      for (int q = 0; q < nq; ++q) dlb += pr[sS[l][q]] * sW[l][q];
+      const double g = 2.0 * dlb;
+      const double h1 = sH[l + 1];
+      const double q1 = qv(h1, zj);
+      if (q1 > 0.0) {
+        zb -= g * (Rp + zj) / q1;
+        rpb += g * (h1 - zj) / q1;
+        atomicAdd(&sHb[l + 1], g * (Rp + h1) / q1);
+      }
+      if (l > j && q0 > 0.0) {
+        const double h0 = sH[l];
+        zb += g * (Rp + zj) / q0;
+        rpb -= g * (h0 - zj) / q0;
+        atomicAdd(&sHb[l], -g * (Rp + h0) / q0);
+      }
+      q0 = q1;
+    }
+    acc[G.o_z + j] += zb;
+  }
+  rpb = wave_sum_d(rpb);
+  if ((tid & 63) == 0) sRp[tid >> 6] = rpb;
+  __syncthreads();
+  for (int m = tid; m <= N; m += kPM) acc[G.o_h + m] += sHb[m];
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kPM / 64; ++w) t += sRp[w];
+    acc[G.o_Rp] += t;
   }
 }
 
@@ -779,7 +703,7 @@ __global__ __launch_bounds__(64) void k_adj_geom(AdjArgs a) {
 
 }  // namespace
 
-size_t adj_item_lds_bytes(const Layout& L) { return carve(L, nullptr, nullptr, L.NP <= 128); }
+size_t adj_item_lds_bytes(const Layout& L) { return carve(L, make_grad_acc(L.NP), nullptr, nullptr); }
 
 void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
@@ -788,22 +712,21 @@ void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
 
 hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return hipSuccess;
-  const bool keep = a.L.NP <= 128;
   const size_t lds = adj_item_lds_bytes(a.L);
-  const void* fn = keep ? (const void*)k_adj_item<true> : (const void*)k_adj_item<false>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_adj_item, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int spans = (a.tab.n_wn + kCols - 1) / kCols;
-  if (keep)
-    hipLaunchKernelGGL(k_adj_item<true>, dim3(B_grid, spans), dim3(64 * kWaves), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_adj_item<false>, dim3(B_grid, spans), dim3(64 * kWaves), lds, s, a);
+  hipLaunchKernelGGL(k_adj_item, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
   return hipGetLastError();
 }
 
 void launch_adj_reduce(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   hipLaunchKernelGGL(k_adj_reduce, dim3(B_grid), dim3(256), 0, s, a);
+}
+
+void launch_adj_pmat(const AdjArgs& a, int B_grid, hipStream_t s) {
+  if (B_grid <= 0) return;
+  hipLaunchKernelGGL(k_adj_pmat, dim3(B_grid), dim3(kPM), 0, s, a);
 }
 
 void launch_adj_geom(const AdjArgs& a, int B_grid, hipStream_t s) {

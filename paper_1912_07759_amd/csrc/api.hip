@@ -426,8 +426,9 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
 size_t trx::grad_scratch_bytes(int B, int n_wn, int n_ch, int NP) {
   const GradAcc G = make_grad_acc(NP);
   const size_t spans = (size_t)(n_wn + kSpanCols - 1) / kSpanCols;
+  const size_t items = (spans + kAdjSpanGroup - 1) / kAdjSpanGroup;
   return (size_t)B * G.n * 8 + (size_t)B * n_ch * 8 + (size_t)B * n_wn * 4 + 256 +
-         (size_t)B * spans * G.n * 4 + 1024;
+         (size_t)B * items * G.n * 4 + 1024;
 }
 
 trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B,
@@ -476,6 +477,8 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   a.acc = acc;
   a.part = part;
   a.n_spans = (W + kSpanCols - 1) / kSpanCols;
+  a.span_group = kAdjSpanGroup;
+  a.n_items = (a.n_spans + kAdjSpanGroup - 1) / kAdjSpanGroup;
   a.dT = dT;
   a.dvmr = dvmr;
   a.dRp = dRp;
@@ -492,6 +495,7 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   {
     ProfScope ps(c, TRX_KERNEL_GEOM_ADJ);
     launch_adj_reduce(a, B, c->stream);
+    launch_adj_pmat(a, B, c->stream);
     launch_adj_geom(a, B, c->stream);
   }
   hipError_t e = hipGetLastError();

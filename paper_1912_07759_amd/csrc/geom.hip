@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         // d(weight)/dT at fixed P: the bracket slope in T (zero where T is
         // clamped: one-sided at nodes, Opacities section rules) and the
         // number-density factor, d rho/dT = -rho/T (rho^2 for CIA)
-        float* lwd = reinterpret_cast<float*>(slab + L.off_lwd32) + 8 * l;
+        double* lwd = reinterpret_cast<double*>(slab + L.off_lwd64) + 8 * l;
         const double dwT = c0 ? 0.0 : 1.0 / (tb.T[iT + 1] - tb.T[iT]);
         double d[8];
         if (Tb_abs && Pb) {
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
           d[5] = d[6] = 0.0;
         }
         d[7] = 0.0;
-        for (int q = 0; q < 8; ++q) lwd[q] = (float)(q >= 5 ? d[q] / kCiaScale32 : d[q]);
+        for (int q = 0; q < 8; ++q) lwd[q] = q >= 5 ? d[q] / kCiaScale32 : d[q];
       }
       lid[8 * l] = iT * tb.n_P + iP;
       lid[8 * l + 1] = iC;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       A32[l] = 0.0f;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
       if (L.grad)
-        for (int q = 0; q < 8; ++q) reinterpret_cast<float*>(slab + L.off_lwd32)[8 * l + q] = 0.0f;
+        for (int q = 0; q < 8; ++q) reinterpret_cast<double*>(slab + L.off_lwd64)[8 * l + q] = 0.0;
       for (int q = 0; q < 8; ++q) lid[8 * l + q] = 0;   // padding layer: zero weights
     }
   }
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     // the slot lists: the first kMListU / kMListV in the model list, all of
     // them (table rows, corners then CIA nodes) in the slot table of the
     // matrix-core modes
-    int32_t* sid = a.precision != TRX_FP64 ? reinterpret_cast<int32_t*>(slab + L.off_sid) : nullptr;
+    int32_t* sid = L.off_sid ? reinterpret_cast<int32_t*>(slab + L.off_sid) : nullptr;
     const int nu = s_nu;
     for (int w = tid; w < nwords; w += kThreads) {
       uint32_t bits = s_bm[w];
@@ -452,43 +452,6 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     const double q0 = sqrt((hk - zj) * (2.0 * Rp + hk + zj));
     return 2.0 * (hk1 - hk) * (2.0 * Rp + hk + hk1) / (q1 + q0);
   };
-  if (L.grad) {
-    // derivative matrices of the chords (gradient layouts).  With
-    // q_j(h) = sqrt((h - z_j)(2Rp + h + z_j)) and Q_m = q_j(h_m) (Q_j = 0),
-    // dl[j,k] = 2 (Q_{k+1} - Q_k), so by parts
-    //   tau_j = sum_k dl[j,k] kappa_k = 2 sum_{m > j} Q_m (kappa_{m-1} - kappa_m)
-    // (kappa_N = 0): the derivatives in z_j and Rp are sums over the layer
-    // differences with weights 2 dQ_m/dz_j = -2 (Rp + z_j)/Q_m and
-    // 2 dQ_m/dRp = 2 (h_m - z_j)/Q_m, free of the cancellation between the
-    // diagonal chord and the others; the boundary h_m enters with
-    // 2 dQ_m/dh_m = 2 (Rp + h_m)/Q_m.  Stored at [j][k = m - 1]; the zero
-    // chord of the top ray (Q_N = 0 for j = N - 1) has no derivative.
-    float4* m3 = reinterpret_cast<float4*>(slab + L.off_m3);
-    float2* mt = reinterpret_cast<float2*>(slab + L.off_mt);
-    auto hb = [&](int k) -> double {
-      return k == 0 ? 0.0 : (k == N ? sZ[N - 1] : 0.5 * (sZ[k - 1] + sZ[k]));
-    };
-    for (int e = tid; e < NP * NP; e += kThreads) {
-      const int j = e / NP, k = e % NP;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      float gh = 0.f;
-      if (j < N && k < N && k >= j) {
-        const double zj = sZ[j];
-        const double h1 = hb(k + 1);
-        const double q1 = sqrt(fmax((h1 - zj) * (2.0 * Rp + h1 + zj), 0.0));
-        const double d = dl_of(j, k);
-        double fz = 0.0, fr = 0.0;
-        if (q1 > 0.0) {
-          gh = (float)(2.0 * (Rp + h1) / q1);
-          fz = -2.0 * (Rp + zj) / q1;
-          fr = 2.0 * (h1 - zj) / q1;
-        }
-        v = make_float4((float)d, (float)fz, (float)fr, 0.f);
-      }
-      m3[(int64_t)j * NP + k] = v;
-      mt[(int64_t)k * NP + j] = make_float2(v.x, gh);
-    }
-  }
   uint8_t* dst = slab + L.off_dl;
   if (a.precision == TRX_FP64) {
     double* dlT = reinterpret_cast<double*>(dst);
@@ -643,7 +606,38 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     __syncthreads();
     // the fragments of the round's slot blocks
     const int nc = min(R, nkq - r0);
-    if (a.precision == TRX_FP32) {
+    if (L.grad && nU + nV <= kKG) {
+      // gradient layouts: P hi in FP32 as A fragments (rows = rays) and as
+      // P^T fragments (rows = slots): lane l, step i holds
+      // P[16 jb + 2 i + l/32][32 qb + l%32]; each slot block c writes the
+      // lanes of its 16 slots (the last one also zeroes its partner half)
+      float* pa = reinterpret_cast<float*>(slab + L.off_pa);
+      float* pt = reinterpret_cast<float*>(slab + L.off_pt);
+      for (int e = tid; e < nc * 64 * nrb; e += kPT) {
+        const int cr = e / (64 * nrb), rem = e - cr * 64 * nrb;
+        const int rb = rem >> 6, lane = rem & 63;
+        const int col = cr * NR32 + 32 * rb + (lane & 31);
+        float* o = pa + (((int64_t)rb * (kKG / 16) + r0 + cr) * 64 + lane) * 8;
+        for (int i = 0; i < 8; ++i) o[i] = (float)sAcc[2 * i + (lane >> 5)][col];
+      }
+      for (int e = tid; e < nc * 64 * 2 * nrb; e += kPT) {
+        const int cr = e / (128 * nrb), rem = e - cr * 128 * nrb;
+        const int jb = rem >> 6, lane = rem & 63;
+        const int c = r0 + cr, qb = c >> 1, half = c & 1;
+        const int v = (lane & 31) - 16 * half;
+        const bool mine = v >= 0 && v < 16;
+        const bool zero_partner = !mine && half == 0 && c == nkq - 1;
+        if (!mine && !zero_partner) continue;
+        float* o = pt + (((int64_t)qb * (L.NP / 16) + jb) * 64 + lane) * 8;
+        for (int i = 0; i < 8; ++i) {
+          const int j = 16 * jb + 2 * i + (lane >> 5);
+          o[i] = mine ? (float)sAcc[v][cr * NR32 + j] : 0.f;
+        }
+      }
+    }
+    if (a.precision == TRX_FP64) {
+      // the forward kernel of this mode does not read P
+    } else if (a.precision == TRX_FP32) {
       float* f = reinterpret_cast<float*>(dst);
       for (int e = tid; e < nc * 64 * nrb; e += kPT) {
         const int cr = e / (64 * nrb), rem = e - cr * 64 * nrb;
@@ -719,7 +713,7 @@ void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* 
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   hipLaunchKernelGGL(k_geom, dim3(B_grid), dim3(kThreads), 0, s, a);
-  if (a.precision != TRX_FP64) hipLaunchKernelGGL(k_pmat, dim3(B_grid), dim3(kPT), 0, s, a);
+  if (a.precision != TRX_FP64 || a.L.grad) hipLaunchKernelGGL(k_pmat, dim3(B_grid), dim3(kPT), 0, s, a);
 }
 
 }  // namespace trx

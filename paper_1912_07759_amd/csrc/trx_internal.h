@@ -92,13 +92,17 @@ struct Layout {
   int64_t off_sid;         // [16 NKQ] table row of each opacity slot (corners, then CIA nodes)
   int64_t off_aw;          // [NP] float2 (A_j/Rs^2, Rayleigh path weight of ray j)
   int64_t dl_bytes;        // mode-specific path-length storage
-  // gradient layouts only (0 otherwise):
-  int64_t off_lwd32;       // [NP][8] FP32 d(record weight)/dT at fixed P
-  int64_t off_m3;          // [NP][NP] float4 (dl_jk, -2(Rp+z_j)/Q, 2(h_{k+1}-z_j)/Q, 0), Q = q_j(h_{k+1}), row = ray j
-  int64_t off_mt;          // [NP][NP] float2 (dl_jk, d(2 q_j(h_{k+1}))/dh_{k+1}), row = layer k
+  // gradient layouts only (0 otherwise); the gradient takes models of at
+  // most kKG opacity slots:
+  int64_t off_lwd64;       // [NP][8] FP64 d(record weight)/dT at fixed P
+  int64_t off_pa;          // P (FP32) as v_mfma_f32_32x32x2_f32 A fragments, rows = rays: [NRB][kKG/16][64][8]
+  int64_t off_pt;          // P^T as A fragments, rows = slots: [kKG/32][NP/16][64][8]
   int32_t grad;
   int64_t slab;            // bytes per model (multiple of 256)
 };
+
+// Opacity slots the gradient supports per model (corners and CIA nodes).
+constexpr int kKG = 96;
 
 // Opacity slots of a model in the matrix-core modes: its distinct
 // cross-section corners (at most 4 per layer, at most the grid's n_T n_P)
@@ -153,9 +157,13 @@ inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& 
   L.off_dl = take(L.dl_bytes);
   if (grad) {
     L.grad = 1;
-    L.off_lwd32 = take(4LL * 8 * L.NP);
-    L.off_m3 = take(16LL * L.NP * L.NP);
-    L.off_mt = take(8LL * L.NP * L.NP);
+    L.off_lwd64 = take(8LL * 8 * L.NP);
+    L.off_pa = take(4LL * L.NRB * (kKG / 16) * 64 * 8);
+    L.off_pt = take(4LL * (kKG / 32) * (L.NP / 16) * 64 * 8);
+    if (L.off_sid == 0) {   // FP64 forward: the gradient still needs the slot table and ray weights
+      L.off_sid = take(4LL * 16 * L.NKQ);
+      L.off_aw = take(8LL * L.NP);
+    }
   }
   L.slab = o;
   return L;
@@ -258,7 +266,7 @@ struct BinArgs {
 // Per-model FP64 accumulators of the adjoint (offsets in doubles).
 struct GradAcc {
   int32_t NP;
-  int32_t o_A, o_z, o_h, o_T, o_Rp, o_chi, o_cw, n;
+  int32_t o_A, o_z, o_h, o_T, o_Rp, o_chi, o_cw, o_PR, o_P, n;
 };
 __host__ __device__ inline GradAcc make_grad_acc(int NP) {
   GradAcc g{};
@@ -271,6 +279,9 @@ __host__ __device__ inline GradAcc make_grad_acc(int NP) {
   g.o_Rp = o; o += 1;          // dchi2/dRp (explicit terms)
   g.o_chi = o; o += kMaxSpecies;  // dchi2/dchi_s through the opacity
   g.o_cw = o; o += TRX_MAX_CIA;   // dchi2/d(chi_a chi_b) per CIA pair
+  g.o_PR = o; o += NP;         // dchi2/dPR_j, Rayleigh path weight of ray j
+  o = (o + 31) / 32 * 32;
+  g.o_P = o; o += NP * kKG;    // dchi2/dP[j][q], row j of kKG slots
   g.n = (o + 31) / 32 * 32;
   return g;
 }
@@ -295,17 +306,22 @@ struct AdjArgs {
   double* chi2;           // [B]
   float* dbar;            // [B][n_wn] dchi2/dD_i inside the window
   double* acc;            // [B][G.n]
-  float* part;            // [B][n_spans][G.n] per-item partial sums (same offsets)
+  float* part;            // [B][n_items][G.n] per-item partial sums (same offsets)
   int32_t n_spans;        // 64-column spans of the grid
+  int32_t span_group;     // spans per backward work item
+  int32_t n_items;        // work items per model = ceil(n_spans / span_group)
   double* dT;             // [layer_off[B]]
   double* dvmr;           // [B][n_abs]
   double* dRp;            // [B]
   int32_t* model_status;  // [B]
 };
+// spans per backward work item
+constexpr int kAdjSpanGroup = 32;
 size_t adj_item_lds_bytes(const Layout& L);
 void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s);
 hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s);
 void launch_adj_reduce(const AdjArgs& a, int B_grid, hipStream_t s);
+void launch_adj_pmat(const AdjArgs& a, int B_grid, hipStream_t s);
 void launch_adj_geom(const AdjArgs& a, int B_grid, hipStream_t s);
 
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s);
