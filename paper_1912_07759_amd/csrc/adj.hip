@@ -193,7 +193,12 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
   }
 }
 
-__global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
+// PT: Pbar tiles per wave (2 covers 128 rays x 96 slots, 3 covers 224
+// rays); with two, the kernel fits 128 registers, so two workgroups share a
+// CU (the LDS of a 128-ray layout allows it)
+template <int PT>
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 4 : 1)))
+void k_adj_item(AdjArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int b = __builtin_amdgcn_readfirstlane(blockIdx.x);
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
 
   // Pbar tiles (32 rays x 32 slots) of this wave, t = wave + 8 u, kept in
   // registers over the item's spans
-  constexpr int kPT = 3;
+  constexpr int kPT = PT;
   f32x16 pb[kPT];
 #pragma unroll
   for (int u = 0; u < kPT; ++u) pb[u] = f32x16{};
@@ -306,7 +311,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
       for (int w = 0; w < kWaves; ++w) Rc += s.rpart[w * kCols + c];
       const int cg = col0 + c;
       const float Db = (cg >= lo && cg < hi) ? a.dbar[(int64_t)b * W + cg] : 0.f;
-      float ab[16], pr[16];
       float rs = 0.f;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
@@ -315,23 +319,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_item(AdjArgs a) {
         const float x = fmaf(w.y, Rc, tau[q]);
         const float tv = Db * w.x * __expf(-x);
         s.tbar[j * kLd + c] = tv;
-        ab[q] = -Db * expm1f(-x);
-        pr[q] = tv * Rc;
         rs = fmaf(w.y, tv, rs);
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        ab[q] = half_sum(ab[q]);
-        pr[q] = half_sum(pr[q]);
-      }
-      if (lc == 0) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
-          if (j < N) {
-            atomicAdd(acc + G.o_A + j, ab[q]);
-            atomicAdd(acc + G.o_PR + j, pr[q]);
-          }
+        // column sums of the annulus and Rayleigh-path cotangents of ray j
+        const float ab = half_sum(-Db * expm1f(-x));
+        const float pr = half_sum(tv * Rc);
+        if (lc == 0 && j < N) {
+          atomicAdd(acc + G.o_A + j, ab);
+          atomicAdd(acc + G.o_PR + j, pr);
         }
       }
       rs += __shfl_xor(rs, 32, 64);
@@ -713,9 +707,14 @@ void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
 hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return hipSuccess;
   const size_t lds = adj_item_lds_bytes(a.L);
-  hipError_t e = hipFuncSetAttribute((const void*)k_adj_item, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const bool small = a.L.NRB * (kKG / 32) <= 2 * kWaves;
+  const void* fn = small ? (const void*)k_adj_item<2> : (const void*)k_adj_item<3>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_item, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
+  if (small)
+    hipLaunchKernelGGL(k_adj_item<2>, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_item<3>, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
   return hipGetLastError();
 }
 
