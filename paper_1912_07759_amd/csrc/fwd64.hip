@@ -16,6 +16,13 @@
 // ray.  Models above 256 layers take several passes over the ray blocks.
 // Depth: D = (Rp/Rs)^2 + sum_j (A_j/Rs^2)(-expm1(-tau_j)), the per-ray-block
 // partials summed in a fixed order.
+//
+// Models of at most TRX_MAX_LAYERS_MFMA layers take the slot form instead
+// (k_fwd64s): tau_j = sum_q P[j][q] M_q + PR_j R with P = dl W formed once
+// per model by the geometry in FP64, so each span stages the mixed rows M
+// of the model's opacity slots (table corners and CIA nodes) and contracts
+// over them on the same FP64 instruction, skipping the slot blocks whose P
+// is zero for a ray block; no per-layer opacity is formed.
 #include "trx_internal.h"
 
 namespace trx {
@@ -237,12 +244,221 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd64(FwdArgs a) {
   process64(a, blockIdx.x, blockIdx.y, sm);
 }
 
+
+// ---- slot form ------------------------------------------------------------
+constexpr int kKC64 = 96;    // slots per staging chunk
+constexpr int kLd64 = 66;    // LDS row stride (doubles): the four row groups of a read hit distinct banks
+constexpr int kR16 = 2;      // 16-ray blocks per wave per pass
+constexpr int kS64 = 4;      // spans per work item
+static_assert(TRX_MAX_LAYERS_MFMA % 16 == 0, "16-ray blocks");
+
+struct Smem64s {
+  double rows[kKC64][kLd64];                       // mixed slot rows of the chunk
+  double part[TRX_MAX_LAYERS_MFMA / 16][kCols];    // per-16-ray-block depth partials
+  double rpart[kWaves][kCols];                     // Rayleigh sums by wave
+  double A[TRX_MAX_LAYERS_MFMA];                   // A_j/Rs^2
+  double PR[TRX_MAX_LAYERS_MFMA];                  // Rayleigh path weights
+  int32_t sid[kKC64];
+  double chis[kMaxSpecies];
+  double ciaw[TRX_MAX_CIA];   // CIA pair weights times kCiaScale32 (the scale of P's CIA columns)
+};
+
+// s[i] += sum_t wt[t] tab_t[rows[i]][col] over the tables t < nt for the
+// slots i in [i0, i1) of a group of 8 (rows of the others clamped into it).
+__device__ inline void mix64(const double* tab, int64_t stride, int nt, const double* wt, const int32_t* rows, int i0,
+                             int i1, int W, int col, double (&s)[8]) {
+  int64_t off[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = i < i0 ? i0 : (i >= i1 ? i1 - 1 : i);
+    off[i] = (int64_t)__builtin_amdgcn_readfirstlane(rows[k]) * W + col;
+  }
+  for (int t0 = 0; t0 < nt; t0 += 2) {
+    double v[2][8];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+      if (t0 + tt < nt) {
+        const double* p = tab + (int64_t)(t0 + tt) * stride;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[tt][i] = p[off[i]];
+      }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+      if (t0 + tt < nt) {
+        const double c = wt[t0 + tt];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i >= i0 && i < i1) s[i] = fma(c, v[tt][i], s[i]);
+      }
+  }
+}
+
+__device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, Smem64s& sm) {
+  const int b = __builtin_amdgcn_readfirstlane(b_in);
+  const Layout& L = a.L;
+  const uint8_t* slab = a.ws + (int64_t)b * L.slab;
+  const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
+  const int N = hd->n;
+  if (N == 0) return;
+  const int lo = hd->lo, hi = hd->hi;
+  const int sp0 = __builtin_amdgcn_readfirstlane(max(s_first, lo / kCols));
+  const int sp1 = __builtin_amdgcn_readfirstlane(min(s_end, (hi + kCols - 1) / kCols));
+  if (sp0 >= sp1) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const DevTables& tb = a.tab;
+  const int W = tb.n_wn;
+  const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
+  const int nU = ml->nU, nV = tb.n_cia > 0 ? ml->nV : 0;
+  const int K = nU + nV;
+  const int nrb = hd->nrb, n16 = 2 * nrb;
+  const int NKQ = L.NKQ;
+  const int32_t* sid = reinterpret_cast<const int32_t*>(slab + L.off_sid);
+  const double* P = reinterpret_cast<const double*>(slab + L.off_dl);
+  const double* A64 = reinterpret_cast<const double*>(slab + L.off_A64);
+  const double* PR64 = reinterpret_cast<const double*>(slab + L.off_pr64);
+  const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
+  const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
+  const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
+
+  if (tid < 32 * nrb) {
+    sm.A[tid] = tid < N ? A64[tid] : 0.0;
+    sm.PR[tid] = tid < N ? PR64[tid] : 0.0;
+  }
+  if (K <= kKC64 && tid < K) sm.sid[tid] = sid[tid];
+  if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s[tid];
+  if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w[tid] * kCiaScale32;
+  __syncthreads();
+
+  for (int span = sp0; span < sp1; ++span) {
+    const int col0 = span * kCols;
+    const int col = col0 + lane;
+    const bool valid = col >= lo && col < hi;
+    const int cc = valid ? col : lo;
+    {
+      double rp = 0.0;
+      for (int k = wave; k < ns; k += kWaves) rp = fma(sm.chis[k], tb.ray64[(int64_t)k * W + cc], rp);
+      sm.rpart[wave][lane] = rp;
+    }
+    // stage the slot chunk c0 .. (8-slot groups g = wave, wave + 4, ...)
+    auto stage_chunk = [&](int c0) {
+      const int kc = min(kKC64, K - c0);
+      if (K > kKC64) {
+        __syncthreads();
+        if (tid < kc) sm.sid[tid] = sid[c0 + tid];
+        __syncthreads();
+      }
+      const int ng = 2 * ((kc + 15) / 16);
+      for (int g = wave; g < ng; g += kWaves) {
+        const int s0 = c0 + 8 * g;
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.0;
+        const int nc = min(max(nU - s0, 0), 8);
+        if (nc > 0) mix64(tb.xsec64, abs_stride, tb.n_abs, hd->chi_s, sm.sid + 8 * g, 0, nc, W, cc, v);
+        const int vb = min(max(K - s0, 0), 8);
+        if (vb > nc) mix64(tb.cia64, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, cc, v);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sm.rows[8 * g + i][lane] = v[i];
+      }
+      __syncthreads();
+    };
+    if (K <= kKC64) stage_chunk(0);
+
+    // passes over the 16-ray blocks: wave w takes blocks p0 + w + 4 r
+    for (int p0 = 0; p0 < n16; p0 += kWaves * kR16) {
+      f64x4 acc[kR16][4];
+#pragma unroll
+      for (int r = 0; r < kR16; ++r)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[r][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+      uint64_t msk[kR16];
+#pragma unroll
+      for (int r = 0; r < kR16; ++r) {
+        const int r16 = p0 + wave + kWaves * r;
+        msk[r] = r16 < n16 ? hd->kq_mask[r16 >> 1] : 0ull;
+      }
+      for (int c0 = 0; c0 < K; c0 += kKC64) {
+        if (K > kKC64) stage_chunk(c0);
+        const int nq = (min(kKC64, K - c0) + 15) >> 4;
+        for (int kq = 0; kq < nq; ++kq) {
+          const int kqa = (c0 >> 4) + kq;
+          if (!(((msk[0] | msk[1]) >> kqa) & 1)) continue;
+          double bv[4][4];
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+              bv[st][cb] = sm.rows[16 * kq + 4 * st + (lane >> 4)][16 * cb + (lane & 15)];
+#pragma unroll
+          for (int r = 0; r < kR16; ++r) {
+            if ((msk[r] >> kqa) & 1) {
+              const int r16 = p0 + wave + kWaves * r;
+              const double4 av = *reinterpret_cast<const double4*>(P + (((int64_t)r16 * NKQ + kqa) * 64 + lane) * 4);
+              const double avs[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+              for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                  acc[r][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(avs[st], bv[st][cb], acc[r][cb], 0, 0, 0);
+            }
+          }
+        }
+      }
+      // depth partials: element q of lane l is ray 16 r16 + l/16 + 4 q
+#pragma unroll
+      for (int r = 0; r < kR16; ++r) {
+        const int r16 = p0 + wave + kWaves * r;
+        if (r16 < n16) {
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            const int c = 16 * cb + (lane & 15);
+            double Rc = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) Rc += sm.rpart[w][c];
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int j = 16 * r16 + (lane >> 4) + 4 * q;
+              s = fma(sm.A[j], -expm1(-fma(sm.PR[j], Rc, acc[r][cb][q])), s);
+            }
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            if (lane < 16) sm.part[r16][c] = s;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < kCols && valid) {
+      double atm = 0.0;
+      for (int r16 = 0; r16 < n16; ++r16) atm += sm.part[r16][tid];
+      const int64_t o = (int64_t)b * W + col;
+      reinterpret_cast<double*>(a.aws)[o] = atm;
+      if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + atm;
+      if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
+    }
+    __syncthreads();   // rows, partials and Rayleigh sums are rewritten by the next span
+  }
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_fwd64s(FwdArgs a) {
+  __shared__ Smem64s sm;
+  const int B = a.B_dev ? *a.B_dev : a.B;
+  if ((int)blockIdx.x >= B) return;
+  process64s(a, blockIdx.x, blockIdx.y * kS64, blockIdx.y * kS64 + kS64, sm);
+}
+
 }  // namespace
 
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   const int spans = (a.tab.n_wn + kCols - 1) / kCols;
-  hipLaunchKernelGGL(k_fwd64, dim3(B_grid, spans), dim3(64 * kWaves), 0, s, a);
+  if (a.L.slot64)
+    hipLaunchKernelGGL(k_fwd64s, dim3(B_grid, (spans + kS64 - 1) / kS64), dim3(64 * kWaves), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_fwd64, dim3(B_grid, spans), dim3(64 * kWaves), 0, s, a);
 }
 
 }  // namespace trx

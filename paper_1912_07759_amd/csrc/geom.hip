@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   // (the FP64 kernel stages them when a model's lists overflow)
   KBlk* kblk = reinterpret_cast<KBlk*>(slab + L.off_kblk);
   const int nkb = (N + 15) / 16;
-  for (int kb = tid; kb < (a.precision == TRX_FP64 ? L.NKB : 0); kb += kThreads) {
+  for (int kb = tid; kb < (a.precision == TRX_FP64 && !L.slot64 ? L.NKB : 0); kb += kThreads) {
     KBlk d;
     d.nU = 0;
     d.nV = 0;
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     return 2.0 * (hk1 - hk) * (2.0 * Rp + hk + hk1) / (q1 + q0);
   };
   uint8_t* dst = slab + L.off_dl;
-  if (a.precision == TRX_FP64) {
+  if (a.precision == TRX_FP64 && !L.slot64) {
     double* dlT = reinterpret_cast<double*>(dst);
     for (int e = tid; e < NP * NP; e += kThreads) {
       const int k = e / NP, j = e % NP;
@@ -564,7 +564,11 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   };
 
   // annulus weights (zero past N); the Rayleigh task adds its path weights
-  if (tid < L.NP) aw[tid] = make_float2(tid < N ? (float)A64[tid] : 0.f, 0.f);
+  double* pr64 = L.off_pr64 ? reinterpret_cast<double*>(slab + L.off_pr64) : nullptr;
+  if (tid < L.NP) {
+    aw[tid] = make_float2(tid < N ? (float)A64[tid] : 0.f, 0.f);
+    if (pr64) pr64[tid] = 0.0;
+  }
   __syncthreads();   // ordered before the Rayleigh task's writes
 
   uint8_t* dst = slab + L.off_dl;
@@ -591,6 +595,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
       double pr = 0.0, q0 = 0.0;
       for (int l = j; l < N; ++l) pr += chord(l, q0) * sW[l][6];
       aw[j] = make_float2((float)A64[j], (float)pr);
+      if (pr64) pr64[j] = pr;
     }
     {
       // ray blocks with a nonzero product in this slot block (each thread
@@ -636,7 +641,18 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
       }
     }
     if (a.precision == TRX_FP64) {
-      // the forward kernel of this mode does not read P
+      if (L.slot64) {
+        // v_mfma_f64_16x16x4f64 A operand: lane l, step s holds
+        // P[16 r16 + l%16][16 kq + 4 s + l/16]
+        double* f = reinterpret_cast<double*>(dst);
+        for (int e = tid; e < nc * 128 * nrb; e += kPT) {
+          const int cr = e / (128 * nrb), rem = e - cr * 128 * nrb;
+          const int r16 = rem >> 6, lane = rem & 63;
+          const int col = cr * NR32 + 16 * r16 + (lane & 15);
+          double* o = f + (((int64_t)r16 * L.NKQ + r0 + cr) * 64 + lane) * 4;
+          for (int st = 0; st < 4; ++st) o[st] = sAcc[4 * st + (lane >> 4)][col];
+        }
+      }
     } else if (a.precision == TRX_FP32) {
       float* f = reinterpret_cast<float*>(dst);
       for (int e = tid; e < nc * 64 * nrb; e += kPT) {
@@ -713,7 +729,7 @@ void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* 
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   hipLaunchKernelGGL(k_geom, dim3(B_grid), dim3(kThreads), 0, s, a);
-  if (a.precision != TRX_FP64 || a.L.grad) hipLaunchKernelGGL(k_pmat, dim3(B_grid), dim3(kPT), 0, s, a);
+  if (a.precision != TRX_FP64 || a.L.grad || a.L.slot64) hipLaunchKernelGGL(k_pmat, dim3(B_grid), dim3(kPT), 0, s, a);
 }
 
 }  // namespace trx

@@ -91,6 +91,8 @@ struct Layout {
   int64_t off_z, off_A64, off_A32, off_lw64, off_lw32, off_lid, off_kblk, off_mlist, off_dl;
   int64_t off_sid;         // [16 NKQ] table row of each opacity slot (corners, then CIA nodes)
   int64_t off_aw;          // [NP] float2 (A_j/Rs^2, Rayleigh path weight of ray j)
+  int64_t off_pr64;        // FP64 slot form: [NP] FP64 Rayleigh path weight of ray j
+  int32_t slot64;          // FP64 mode in the slot form (models of at most TRX_MAX_LAYERS_MFMA layers)
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise); the gradient takes models of at
   // most kKG opacity slots:
@@ -146,8 +148,15 @@ inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& 
   L.off_lid = take(4LL * 8 * L.NP);
   L.off_kblk = take((int64_t)sizeof(KBlk) * L.NKB);
   L.off_mlist = take((int64_t)sizeof(MList));
-  if (precision == TRX_FP64) {
+  if (precision == TRX_FP64 && L.NP > TRX_MAX_LAYERS_MFMA) {
     L.dl_bytes = 8LL * L.NP * L.NP;  // dense transposed dlT[k][j]
+  } else if (precision == TRX_FP64) {
+    // P in FP64 as v_mfma_f64_16x16x4f64 A fragments [16-ray block][kq][lane][4]
+    L.slot64 = 1;
+    L.off_sid = take(4LL * 16 * L.NKQ);
+    L.off_aw = take(8LL * L.NP);
+    L.off_pr64 = take(8LL * L.NP);
+    L.dl_bytes = (int64_t)(L.NP / 16) * L.NKQ * 64 * 4 * 8;
   } else {
     // P[j][q] = sum_l dl[j][l] W[l][q] in A-operand fragments [rb][kq][piece]
     L.off_sid = take(4LL * 16 * L.NKQ);
