@@ -195,6 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     if (a.mlay) a.mlay[b] = N;
     if (a.mspan) a.mspan[b] = make_int2(lo / kSpanCols, (hi + kSpanCols - 1) / kSpanCols);
     h->Rp2_Rs2 = (Rp / Rs) * (Rp / Rs);
+    for (int r = 0; r < TRX_MAX_LAYERS_MFMA / 32; ++r) h->kq_mask[r] = 0ull;   // set by the path-matrix kernel
     h->inv_Rs2 = 1.0 / (Rs * Rs);
     h->Rp = Rp;
     h->mu_kg = mu;
@@ -248,6 +249,9 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         lw32[8 * l + q] = (float)(q >= 5 ? w[q] / kCiaScale32 : w[q]);
       }
       lw32[8 * l + 7] = (float)A;   // FP32 records carry the ray's annulus weight
+      // ray weights of the slot form; the path-matrix kernel adds PR_j
+      if (L.off_aw) reinterpret_cast<float2*>(slab + L.off_aw)[l] = make_float2((float)A, 0.f);
+      if (L.off_pr64) reinterpret_cast<double*>(slab + L.off_pr64)[l] = 0.0;
       if (L.grad) {
         // d(weight)/dT at fixed P: the bracket slope in T (zero where T is
         // clamped: one-sided at nodes, Opacities section rules) and the
@@ -281,6 +285,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       zs[l] = 0.0;
       A64[l] = 0.0;
       A32[l] = 0.0f;
+      if (L.off_aw) reinterpret_cast<float2*>(slab + L.off_aw)[l] = make_float2(0.f, 0.f);
+      if (L.off_pr64) reinterpret_cast<double*>(slab + L.off_pr64)[l] = 0.0;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
       if (L.grad)
         for (int q = 0; q < 8; ++q) reinterpret_cast<double*>(slab + L.off_lwd64)[8 * l + q] = 0.0;
@@ -483,8 +489,13 @@ constexpr int kPT = 256;
 constexpr int kMaxKQ = (4 * TRX_MAX_LAYERS_MFMA + TRX_MAX_TGRID + 15) / 16;
 static_assert(TRX_MAX_LAYERS_MFMA <= kPT, "one thread per ray");
 
+// Workgroups per model: a model's tasks (slot blocks and the Rayleigh
+// weights) are dealt to kPG workgroups, so that a lone model is not one
+// workgroup's serial work.
+constexpr int kPG = 4;
 __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   const int b = blockIdx.x;
+  const int grp = blockIdx.y;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if (b >= B) return;
   const Layout& L = a.L;
@@ -512,7 +523,6 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   __shared__ int4 sS[TRX_MAX_LAYERS_MFMA];        // slots: corners 0,1 | 2,3 | CIA 0,1 (16 bits each)
   __shared__ int sLo[kMaxKQ], sHi[kMaxKQ];
   __shared__ double sAcc[16][kPT];
-  __shared__ unsigned long long sMask[kPT / 32];
 
   for (int l = tid; l < N; l += kPT) {
     sZ[l] = zs[l];
@@ -528,7 +538,6 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     sLo[c] = N;
     sHi[c] = -1;
   }
-  if (tid < kPT / 32) sMask[tid] = 0ull;
   __syncthreads();
   for (int m = tid; m <= N; m += kPT) sH[m] = m == 0 ? 0.0 : (m == N ? sZ[N - 1] : 0.5 * (sZ[m - 1] + sZ[m]));
   // the run of layers of each slot block
@@ -563,18 +572,16 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     return d;
   };
 
-  // annulus weights (zero past N); the Rayleigh task adds its path weights
+  // the Rayleigh task completes the ray weights the geometry initialised
   double* pr64 = L.off_pr64 ? reinterpret_cast<double*>(slab + L.off_pr64) : nullptr;
-  if (tid < L.NP) {
-    aw[tid] = make_float2(tid < N ? (float)A64[tid] : 0.f, 0.f);
-    if (pr64) pr64[tid] = 0.0;
-  }
-  __syncthreads();   // ordered before the Rayleigh task's writes
 
   uint8_t* dst = slab + L.off_dl;
   const int np = a.precision == TRX_BF16_SPLIT3 ? 3 : 2;
-  for (int r0 = 0; r0 <= nkq; r0 += R) {
-    const int c = r0 + rep;
+  // tasks of this workgroup: grp, grp + kPG, ... <= nkq; round r0 holds the
+  // tasks of replicas 0 .. R-1
+  const int ntask = grp <= nkq ? (nkq - grp) / kPG + 1 : 0;
+  for (int r0 = 0; r0 < ntask; r0 += R) {
+    const int c = (r0 + rep) < ntask ? grp + kPG * (r0 + rep) : nkq + 1;
     for (int v = 0; v < 16; ++v) sAcc[v][tid] = 0.0;
     if (act && c < nkq) {
       const int la = sLo[c], lb = sHi[c];
@@ -605,12 +612,14 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
       const unsigned long long bal = __ballot(nz);
       if ((tid & 31) == 0 && rep < R && c < nkq) {
         const unsigned long long half = (tid & 32) ? bal >> 32 : bal & 0xffffffffull;
-        if (half) atomicOr(&sMask[j >> 5], 1ull << c);
+        if (half) atomicOr(reinterpret_cast<unsigned long long*>(&hw->kq_mask[j >> 5]), 1ull << c);
       }
     }
     __syncthreads();
-    // the fragments of the round's slot blocks
-    const int nc = min(R, nkq - r0);
+    // the fragments of the round's slot blocks: replica cr holds task
+    // grp + kPG (r0 + cr)
+    const int nc = min(R, ntask - r0);
+    auto task_of = [&](int cr) { return grp + kPG * (r0 + cr); };
     if (L.grad && nU + nV <= kKG) {
       // gradient layouts: P hi in FP32 as A fragments (rows = rays) and as
       // P^T fragments (rows = slots): lane l, step i holds
@@ -621,14 +630,16 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
       for (int e = tid; e < nc * 64 * nrb; e += kPT) {
         const int cr = e / (64 * nrb), rem = e - cr * 64 * nrb;
         const int rb = rem >> 6, lane = rem & 63;
+        if (task_of(cr) >= nkq) continue;
         const int col = cr * NR32 + 32 * rb + (lane & 31);
-        float* o = pa + (((int64_t)rb * (kKG / 16) + r0 + cr) * 64 + lane) * 8;
+        float* o = pa + (((int64_t)rb * (kKG / 16) + task_of(cr)) * 64 + lane) * 8;
         for (int i = 0; i < 8; ++i) o[i] = (float)sAcc[2 * i + (lane >> 5)][col];
       }
       for (int e = tid; e < nc * 64 * 2 * nrb; e += kPT) {
         const int cr = e / (128 * nrb), rem = e - cr * 128 * nrb;
         const int jb = rem >> 6, lane = rem & 63;
-        const int c = r0 + cr, qb = c >> 1, half = c & 1;
+        const int c = task_of(cr), qb = c >> 1, half = c & 1;
+        if (c >= nkq) continue;
         const int v = (lane & 31) - 16 * half;
         const bool mine = v >= 0 && v < 16;
         const bool zero_partner = !mine && half == 0 && c == nkq - 1;
@@ -648,8 +659,9 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
         for (int e = tid; e < nc * 128 * nrb; e += kPT) {
           const int cr = e / (128 * nrb), rem = e - cr * 128 * nrb;
           const int r16 = rem >> 6, lane = rem & 63;
+          if (task_of(cr) >= nkq) continue;
           const int col = cr * NR32 + 16 * r16 + (lane & 15);
-          double* o = f + (((int64_t)r16 * L.NKQ + r0 + cr) * 64 + lane) * 4;
+          double* o = f + (((int64_t)r16 * L.NKQ + task_of(cr)) * 64 + lane) * 4;
           for (int st = 0; st < 4; ++st) o[st] = sAcc[4 * st + (lane >> 4)][col];
         }
       }
@@ -658,8 +670,9 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
       for (int e = tid; e < nc * 64 * nrb; e += kPT) {
         const int cr = e / (64 * nrb), rem = e - cr * 64 * nrb;
         const int rb = rem >> 6, lane = rem & 63;
+        if (task_of(cr) >= nkq) continue;
         const int col = cr * NR32 + 32 * rb + (lane & 31);
-        float* o = f + (((int64_t)rb * L.NKQ + r0 + cr) * 2 * 64 + lane) * 8;
+        float* o = f + (((int64_t)rb * L.NKQ + task_of(cr)) * 2 * 64 + lane) * 8;
         for (int i = 0; i < 8; ++i) {
           const double x = sAcc[2 * i + (lane >> 5)][col];
           const float hi32 = (float)x;
@@ -672,8 +685,9 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
       for (int e = tid; e < nc * 64 * nrb; e += kPT) {
         const int cr = e / (64 * nrb), rem = e - cr * 64 * nrb;
         const int rb = rem >> 6, lane = rem & 63;
+        if (task_of(cr) >= nkq) continue;
         const int col = cr * NR32 + 32 * rb + (lane & 31);
-        uint16_t* o = f + (((int64_t)rb * L.NKQ + r0 + cr) * np * 64 + lane) * 8;
+        uint16_t* o = f + (((int64_t)rb * L.NKQ + task_of(cr)) * np * 64 + lane) * 8;
         for (int v = 0; v < 8; ++v) {
           const double x = sAcc[8 * (lane >> 5) + v][col];
           const uint16_t p0 = bf16_bits((float)x);
@@ -687,7 +701,6 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     }
     __syncthreads();
   }
-  if (tid < TRX_MAX_LAYERS_MFMA / 32) hw->kq_mask[tid] = tid < nrb ? sMask[tid] : 0ull;
 }
 
 // Work order of the persistent launch: model indices sorted by layer count,
@@ -729,7 +742,8 @@ void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* 
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   hipLaunchKernelGGL(k_geom, dim3(B_grid), dim3(kThreads), 0, s, a);
-  if (a.precision != TRX_FP64 || a.L.grad || a.L.slot64) hipLaunchKernelGGL(k_pmat, dim3(B_grid), dim3(kPT), 0, s, a);
+  if (a.precision != TRX_FP64 || a.L.grad || a.L.slot64)
+    hipLaunchKernelGGL(k_pmat, dim3(B_grid, kPG), dim3(kPT), 0, s, a);
 }
 
 }  // namespace trx
