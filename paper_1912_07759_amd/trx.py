@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libtrx.so")
 FP64, FP32, BF16_SPLIT2, BF16_SPLIT3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16_SPLIT2, "bf16x3": BF16_SPLIT3}
 
-MODEL_OK, BAD_CHEMISTRY, BAD_PROFILE, BAD_WINDOW, NONFINITE = 0, 1, 2, 4, 8
+MODEL_OK, BAD_CHEMISTRY, BAD_PROFILE, BAD_WINDOW, NONFINITE, GRAD_UNSUPPORTED = 0, 1, 2, 4, 8, 16
 PLAN_GRAPH, PLAN_PERSISTENT, PLAN_GRAD = 1, 2, 4
 
 STATUS_NAMES = {0: "TRX_OK", 1: "TRX_E_INVALID_ARG", 2: "TRX_E_OUT_OF_MEMORY",

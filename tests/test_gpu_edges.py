@@ -131,3 +131,24 @@ def test_no_opacity_gives_bare_disc(gpu_ctx, tables, mode):
         lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
         want = (Rp[b] / R_SUN) ** 2
         assert np.all(nat[b, lo:hi] == want), (mode, b)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_many_opacity_slots(gpu_ctx, tables, mode):
+    """A three-level zig-zag temperature profile touches ~180 distinct table
+    corners and CIA nodes, more than one staging chunk in every mode (128
+    slots in the matrix-core modes, 96 in FP64), next to an ordinary model
+    with a ragged window."""
+    t = tables
+    N = 200
+    i = np.arange(N)
+    zig = np.where(i % 2 == 0, 250.0, 3300.0) + np.linspace(0.0, 900.0, N)
+    zig = np.where(i % 4 == 1, 1700.0 + np.linspace(0.0, 900.0, N), zig)
+    Ts = [zig, _profile(120)]
+    vmr = np.tile(np.array([-4.0, -5.0, -6.0, -3.5, -7.0]), (2, 1))
+    batch = batch_from_models(Ts, 1e6, 1e-4, vmr, R_JUP, R_SUN, GM_JUP, [0, 37], [t.n_wn, 650])
+    ch = _channels(t)
+    nat, binned, st = _run(gpu_ctx, t, batch, ch, mode, N)
+    worst = _check(t, batch, ch, mode, nat, binned, st)
+    print(f"{mode}: many opacity slots worst rel err {worst:.2e}")
+    assert worst <= TOL[mode]

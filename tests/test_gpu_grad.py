@@ -161,3 +161,47 @@ def test_gradient_plan_graph(gpu_ctx, problem):
     plan.close()
     bins.close()
     Tt.close()
+
+
+def test_gradient_long_models_and_slot_limit(gpu_ctx):
+    """Models of 40, 150 and 224 layers in one batch (224 takes the kernel
+    variant for more than 160 rays) against the oracle's reference gradient,
+    next to a model whose zig-zag temperature profile touches more than 96
+    distinct table corners and CIA nodes: that one is flagged
+    TRX_MODEL_GRAD_UNSUPPORTED with NaN outputs, its neighbours unaffected."""
+    from paper_1912_07759_amd import trx
+    from synth.atmosphere import guillot_T, log_midpoint_pressures, log_uniform_channels
+    from synth.constants import GM_JUP, R_JUP, R_SUN
+    from synth.workloads import Channels, batch_from_models, make_tables
+    tables = make_tables(4, n_wn=700, n_lines=80)
+    lo, hi = log_uniform_channels(tables.wn, 24)
+    ch = Channels(lo, hi)
+    g0 = GM_JUP / R_JUP ** 2
+    Ts = [guillot_T(log_midpoint_pressures(1e6, 1e-4, N), g0, Ti)
+          for N, Ti in ((40, 900.0), (150, 1500.0), (224, 2100.0))]
+    zig = np.where(np.arange(90) % 2 == 0, 250.0, 3300.0) + np.linspace(0.0, 600.0, 90)
+    Ts.append(zig)
+    rng = np.random.default_rng(7)
+    vmr = rng.uniform(-7.0, -3.0, (len(Ts), tables.n_abs))
+    batch = batch_from_models(Ts, 1e6, 1e-4, vmr, R_JUP, R_SUN, GM_JUP, 0, tables.n_wn)
+    refs = [oracle.forward_model(batch.model(b), tables, ch)["binned"] for b in range(3)]
+    noise, sigma = observation_noise(4, 1, len(ch.lo))
+    obs = np.stack([r * (1.0 + 2e-4 * np.sin(np.arange(len(ch.lo)) + b)) for b, r in enumerate(refs)]
+                   + [refs[0]])
+    Tt = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, Tt, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=224)
+    out = trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, np.full(len(ch.lo), 50e-6), "fp64")
+    g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    bins.close()
+    Tt.close()
+    off = batch.layer_off
+    assert np.all(g["status"][:3] == 0), g["status"]
+    assert g["status"][3] & trx.GRAD_UNSUPPORTED
+    assert np.all(np.isnan(g["dT"][off[3]:off[4]])) and np.isnan(g["dRp"][3])
+    for b in range(3):
+        ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], np.full(len(ch.lo), 50e-6))
+        mine = {"dT": g["dT"][off[b]:off[b + 1]], "dlog10_vmr": g["dlog10_vmr"][b], "dRp": g["dRp"][b]}
+        norm, comp = _grad_err(mine, ref)
+        print(f"N={len(Ts[b])}: grad norm err {norm:.2e} comp err {comp:.2e}")
+        assert norm <= GRAD_TOL and comp <= GRAD_TOL, (b, norm, comp)
