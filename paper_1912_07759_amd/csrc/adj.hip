@@ -292,18 +292,31 @@ void k_adj_item(AdjArgs a) {
     // over the nonzero 16-slot blocks; then taubar, Abar, PRbar and Rbar
     for (int t = wave; t < 2 * nrb; t += kWaves) {
       const int rb = t >> 1, tcb = t & 1;
-      const uint64_t m = hd->kq_mask[rb];
+      // nonzero slot blocks of the ray block, the next one's fragment
+      // loaded before the current products
+      uint64_t m = hd->kq_mask[rb] & ((nkq < 64 ? (1ull << nkq) : 0ull) - 1ull);
       f32x16 tau = f32x16{};
-      for (int kq = 0; kq < nkq; ++kq) {
-        if (!((m >> kq) & 1)) continue;
+      auto afrag = [&](int kq, u32x4& x0, u32x4& x1) {
         const u32x4* fp = reinterpret_cast<const u32x4*>(pa + (((int64_t)rb * (kKG / 16) + kq) * 64 + lane) * 8);
-        const u32x4 a0 = fp[0], a1 = fp[1];
+        x0 = fp[0];
+        x1 = fp[1];
+      };
+      u32x4 a0{}, a1{}, n0{}, n1{};
+      int kq = m ? __builtin_ctzll(m) : -1;
+      if (kq >= 0) afrag(kq, a0, a1);
+      while (kq >= 0) {
+        m &= m - 1;
+        const int kn = m ? __builtin_ctzll(m) : -1;
+        if (kn >= 0) afrag(kn, n0, n1);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const float av = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
           const float bv = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
           tau = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, tau, 0, 0, 0);
         }
+        a0 = n0;
+        a1 = n1;
+        kq = kn;
       }
       const int c = 32 * tcb + lc;
       float Rc = 0.f;
@@ -353,16 +366,32 @@ void k_adj_item(AdjArgs a) {
     const bool has_mb = wave < 2 * nqb;
     if (has_mb) {
       const int qb = wave >> 1, tcb = wave & 1;
-      for (int jb = 0; jb < 2 * nrb; ++jb) {
-        if (!((hd->kq_mask[jb >> 1] >> (2 * qb)) & 3)) continue;
+      // 16-ray blocks with a nonzero product, the next one's fragment loaded
+      // before the current products
+      uint32_t jm = 0;
+      for (int jb = 0; jb < 2 * nrb; ++jb)
+        if ((hd->kq_mask[jb >> 1] >> (2 * qb)) & 3) jm |= 1u << jb;
+      auto tfrag = [&](int jb, u32x4& x0, u32x4& x1) {
         const u32x4* fp = reinterpret_cast<const u32x4*>(pt + (((int64_t)qb * NJB + jb) * 64 + lane) * 8);
-        const u32x4 a0 = fp[0], a1 = fp[1];
+        x0 = fp[0];
+        x1 = fp[1];
+      };
+      u32x4 a0{}, a1{}, n0{}, n1{};
+      int jb = jm ? __builtin_ctz(jm) : -1;
+      if (jb >= 0) tfrag(jb, a0, a1);
+      while (jb >= 0) {
+        jm &= jm - 1;
+        const int jn = jm ? __builtin_ctz(jm) : -1;
+        if (jn >= 0) tfrag(jn, n0, n1);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const float av = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
           const float bv = s.tbar[(16 * jb + 2 * i + hl) * kLd + 32 * tcb + lc];
           mb = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, mb, 0, 0, 0);
         }
+        a0 = n0;
+        a1 = n1;
+        jb = jn;
       }
     }
     __syncthreads();   // M is no longer read: its rows take Mbar
@@ -416,18 +445,61 @@ void k_adj_item(AdjArgs a) {
           }
         }
       }
+      // CIA: the wave's nodes t = nU + wave + 8 k (at most kCN) of every
+      // pair, all loads issued before the sums
+      constexpr int kCN = 4;
+      for (int p0 = 0; p0 < tb.n_cia; p0 += 2) {
+        float cv[2][kCN];
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+          for (int k = 0; k < kCN; ++k) {
+            const int t = nU + wave + kWaves * k;
+            cv[pp][k] = (p0 + pp < tb.n_cia && t < K)
+                            ? tb.cia32[(int64_t)(p0 + pp) * cia_stride + (int64_t)s.sid[t] * W + cc]
+                            : 0.f;
+          }
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp) {
+          if (p0 + pp < tb.n_cia) {
+            float acc_p = 0.f;
+#pragma unroll
+            for (int k = 0; k < kCN; ++k) {
+              const int t = nU + wave + kWaves * k;
+              if (t < K) acc_p = fmaf(s.rows[t * kLd + lane], cv[pp][k], acc_p);
+            }
+            acc_p = wave_sum(acc_p);
+            if (lane == 0) atomicAdd(acc + G.o_cw + p0 + pp, acc_p);
+          }
+        }
+      }
+      // nodes past kCN per wave (more than 32 CIA nodes)
       for (int p = 0; p < tb.n_cia; ++p) {
         const float* tp = tb.cia32 + (int64_t)p * cia_stride;
         float acc_p = 0.f;
-        for (int t = nU + wave; t < K; t += kWaves)
+        for (int t = nU + wave + kWaves * kCN; t < K; t += kWaves)
           acc_p = fmaf(s.rows[t * kLd + lane], tp[(int64_t)s.sid[t] * W + cc], acc_p);
-        acc_p = wave_sum(acc_p);
-        if (lane == 0) atomicAdd(acc + G.o_cw + p, acc_p);
+        if (nU + wave + kWaves * kCN < K) {
+          acc_p = wave_sum(acc_p);
+          if (lane == 0) atomicAdd(acc + G.o_cw + p, acc_p);
+        }
       }
+      // Rayleigh: the wave's species q = wave + 8 k, loads first
       const float rl = s.rbar[lane];
-      for (int q = wave; q < ns; q += kWaves) {
-        const float t = wave_sum(rl * tb.ray32[(int64_t)q * W + cc]);
-        if (lane == 0) atomicAdd(acc + G.o_chi + q, t);
+      constexpr int kRS = (kMaxSpecies + kWaves - 1) / kWaves;
+      float rv[kRS];
+#pragma unroll
+      for (int k = 0; k < kRS; ++k) {
+        const int q = wave + kWaves * k;
+        rv[k] = q < ns ? tb.ray32[(int64_t)q * W + cc] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < kRS; ++k) {
+        const int q = wave + kWaves * k;
+        if (q < ns) {
+          const float t = wave_sum(rl * rv[k]);
+          if (lane == 0) atomicAdd(acc + G.o_chi + q, t);
+        }
       }
     }
     __syncthreads();   // rows, tbar and rbar are rewritten by the next span
