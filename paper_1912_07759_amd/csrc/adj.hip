@@ -35,13 +35,11 @@
 // fixed order in FP64.  The result is held to 1e-4 of the FP64 reference
 // gradient.
 #include "trx_internal.h"
-#include "stage.h"
 
 namespace trx {
 
 namespace {
 
-using stage::kRsrcWord3;
 constexpr int kWaves = 8;
 constexpr int kCols = 64;
 constexpr int kLd = 65;   // LDS row stride of the [row][column] tiles: transposed reads hit distinct banks

@@ -35,7 +35,6 @@
 // per-ray-block partial in LDS, and the partials are summed in ray-block
 // order (same bits every run).
 #include "trx_internal.h"
-#include "stage.h"
 
 #include <type_traits>
 
@@ -43,7 +42,6 @@ namespace trx {
 
 namespace {
 
-using stage::kRsrcWord3;
 
 constexpr int kWaves = 4;
 constexpr int kCols = 64;               // columns per workgroup

@@ -10,6 +10,10 @@
 namespace trx {
 
 constexpr int kHdrBytes = 2048;    // per-model header block in the slab
+// Word 3 of a raw 32-bit buffer resource (gfx9 family): the buffer loads of
+// the table rows take the column as the per-lane offset, the row as the
+// uniform offset.
+constexpr int kRsrcWord3 = 0x00020000;
 // CIA cross-sections (~1e-46 cm^5) are below the FP32 range and their layer
 // weights 1e-10 rho^2 (up to ~1e42 m^-6) above it, so the FP32 copy of the
 // CIA tables is stored multiplied by kCiaScale32 and the FP32 CIA weights
