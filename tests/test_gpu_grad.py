@@ -205,3 +205,40 @@ def test_gradient_long_models_and_slot_limit(gpu_ctx):
         norm, comp = _grad_err(mine, ref)
         print(f"N={len(Ts[b])}: grad norm err {norm:.2e} comp err {comp:.2e}")
         assert norm <= GRAD_TOL and comp <= GRAD_TOL, (b, norm, comp)
+
+
+def test_gradient_constant_gravity_and_window(gpu_ctx):
+    """The constant-gravity altitude recursion (g = GM/Rp^2) and a window
+    of 480 of the 700 grid points, whose channels lie inside it: both
+    against the oracle's reference gradient."""
+    from paper_1912_07759_amd import trx
+    from synth.atmosphere import guillot_T, log_midpoint_pressures, log_uniform_channels
+    from synth.constants import GM_JUP, R_JUP, R_SUN
+    from synth.workloads import Channels, batch_from_models, make_tables
+    tables = make_tables(4, n_wn=700, n_lines=80)
+    lo, hi = log_uniform_channels(tables.wn[110:590], 16)
+    ch = Channels(lo, hi)
+    g0 = GM_JUP / R_JUP ** 2
+    Ts = [guillot_T(log_midpoint_pressures(1e6, 1e-4, 80), g0, Ti) for Ti in (1100.0, 1700.0)]
+    rng = np.random.default_rng(11)
+    vmr = rng.uniform(-7.0, -3.0, (2, tables.n_abs))
+    sigma = np.full(len(ch.lo), 50e-6)
+    for gravity in (0, 1):
+        batch = batch_from_models(Ts, 1e6, 1e-4, vmr, R_JUP, R_SUN, GM_JUP, 100, 580, gravity=gravity)
+        refs = [oracle.forward_model(batch.model(b), tables, ch)["binned"] for b in range(2)]
+        obs = np.stack([r * (1.0 + 3e-4 * np.cos(np.arange(len(ch.lo)) + b)) for b, r in enumerate(refs)])
+        Tt = trx.Tables.from_synth(gpu_ctx, tables)
+        bins = trx.Bins(gpu_ctx, Tt, ch.lo, ch.hi)
+        db = trx.DeviceBatch.from_synth(batch, max_layers=80)
+        out = trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, sigma, "fp64")
+        g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+        bins.close()
+        Tt.close()
+        assert np.all(g["status"] == 0), g["status"]
+        off = batch.layer_off
+        for b in range(2):
+            ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
+            mine = {"dT": g["dT"][off[b]:off[b + 1]], "dlog10_vmr": g["dlog10_vmr"][b], "dRp": g["dRp"][b]}
+            norm, comp = _grad_err(mine, ref)
+            print(f"gravity={gravity} model {b}: grad norm err {norm:.2e} comp err {comp:.2e}")
+            assert norm <= GRAD_TOL and comp <= GRAD_TOL, (gravity, b, norm, comp)
