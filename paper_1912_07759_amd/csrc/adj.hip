@@ -49,10 +49,25 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 static_assert(kKG % 32 == 0 && kKG <= 3 * 32, "slot blocks of the gradient");
 static_assert(TRX_MAX_LAYERS_MFMA <= 32 * kWaves, "one ray block per wave");
 
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// v of another lane of the same 16-lane row (DPP lane move; CTRL is the
+// data-parallel-primitive control: quad permutations, row mirrors)
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+// sum over each 16-lane row, in every lane of the row: pairs, quads, the
+// two halves of the row, then the two mirrored halves
+__device__ inline float row_sum(float v) {
+  v += dpp_mov<0xB1>(v);    // quad permutation (1, 0, 3, 2)
+  v += dpp_mov<0x4E>(v);    // quad permutation (2, 3, 0, 1)
+  v += dpp_mov<0x141>(v);   // mirror within each half-row (lane 7 - i)
+  v += dpp_mov<0x140>(v);   // mirror within the row (lane 15 - i)
   return v;
+}
+__device__ inline float wave_sum(float v) {
+  v = row_sum(v);
+  v += __shfl_xor(v, 16, 64);
+  return v + __shfl_xor(v, 32, 64);
 }
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
@@ -61,9 +76,8 @@ __device__ inline double wave_sum_d(double v) {
 }
 // sum over the 32 lanes of a half-wave
 __device__ inline float half_sum(float v) {
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = row_sum(v);
+  return v + __shfl_xor(v, 16, 64);
 }
 
 // ---- chi^2 and the per-point cotangent Dbar_i ---------------------------
