@@ -76,7 +76,7 @@ struct Smem {
   // B operand of the staged slot chunk
   __attribute__((aligned(16))) uint32_t bfrag[Cfg<MODE, RBW>::bdw];
   float part[kWaves * RBW][kCols];  // per-ray-block depth partials
-  float2 aw[TRX_MAX_LAYERS_MFMA];   // per ray: A_j/Rs^2, PR_j
+  float2 aw[TRX_MAX_LAYERS_MFMA];   // per ray: A_j/Rs^2, -PR_j / ln 2
   float rpart[kWaves][kCols];       // Rayleigh sums by wave
   int32_t sid[kKC];                 // table rows of the chunk's slots
   float chi[TRX_MAX_ABSORBERS];
@@ -95,6 +95,8 @@ __device__ inline uint32_t bf16_pair(float a, float b) {
 }
 __device__ inline float bf16_lo_f(uint32_t p) { return __uint_as_float(p << 16); }
 __device__ inline float bf16_hi_f(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
+constexpr float kNegLog2e32 = -1.4426950408889634f;   // -1 / ln 2
 
 // Ray block r (0..RBW-1) of a wave: w, then 7 - w.
 template <int RBW>
@@ -217,12 +219,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
   const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
 
-  // per-item records: ray weights (zero past N), slot rows, mixing ratios
+  // per-item records: ray weights (zero past N; the Rayleigh path weight
+  // scaled like the fragments), slot rows, mixing ratios
   {
     const int nr = 32 * nrb;
     const float2 w = tid < nr ? awg[tid] : float2{};
     const int32_t r = K <= kKC && tid < K ? sid[tid] : 0;
-    if (tid < nr) sm.aw[tid] = w;
+    if (tid < nr) sm.aw[tid] = float2{w.x, kNegLog2e32 * w.y};
     if (K <= kKC && tid < K) sm.sid[tid] = r;
     if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
     if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s32[tid];
@@ -254,6 +257,22 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       }
     }
   };
+
+  // sum of A_j over each of the wave's ray blocks, in the order in which the
+  // depth epilogue sums A_j e^{-tau_j}: where every e^{-tau_j} is 1 the two
+  // agree to the bit and the block adds exactly zero
+  const int hl = lane >> 5, lc = lane & 31;
+  float awsum[RBW];
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = own_rb<RBW>(wave, r);
+    float t = 0.f;
+    if (rb < nrb) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) t = fmaf(sm.aw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)].x, 1.f, t);
+    }
+    awsum[r] = t + __shfl_xor(t, 32, 64);
+  }
 
   const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
   for (int span = sp0; span < sp1; ++span) {
@@ -464,9 +483,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     for (int c0 = kKC; c0 < K; c0 += kKC) run_chunk(c0, std::false_type{});
 
     // depth: accumulator register q holds ray 8 (q/4) + 4 (lane/32) + q%4
-    // of column 32 (column block) + lane%32
-    const float nl2e = -1.4426950408889634f;
-    const int hl = lane >> 5, lc = lane & 31;
+    // of column 32 (column block) + lane%32, as -tau_j / ln 2 less the
+    // Rayleigh term; sum_j A_j (1 - e^{-tau_j}) is taken as the ray block's
+    // sum of A_j less sum_j A_j e^{-tau_j}
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
       const int rb = own_rb<RBW>(wave, r);
@@ -479,11 +498,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
             const float2 w = sm.aw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)];
-            const float tau = fmaf(w.y, Rc, acc[r][tcb][q]);
-            s = fmaf(w.x, 1.f - __builtin_amdgcn_exp2f(nl2e * tau), s);
+            s = fmaf(w.x, __builtin_amdgcn_exp2f(fmaf(w.y, Rc, acc[r][tcb][q])), s);
           }
           s += __shfl_xor(s, 32, 64);
-          if (hl == 0) sm.part[rb][cl] = s;
+          if (hl == 0) sm.part[rb][cl] = awsum[r] - s;
         }
       }
     }

@@ -484,8 +484,11 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
 // of the matrix instruction: FP32 mode hi + lo pieces in the
 // v_mfma_f32_32x32x2_f32 layout (lane l, step i: P[32 rb + l%32][16 kq + 2 i + l/32]),
 // bf16 modes 2 or 3 bf16 pieces in the v_mfma_f32_32x32x16_bf16 layout
-// (lane l: P[32 rb + l%32][16 kq + 8 (l/32) + v], v = 0..7).
+// (lane l: P[32 rb + l%32][16 kq + 8 (l/32) + v], v = 0..7).  These two
+// store -P / ln 2, so that the forward kernel's accumulator is the base-2
+// exponent of e^{-tau} (the FP64 and gradient fragments hold P itself).
 constexpr int kPT = 256;
+constexpr double kNegLog2e = -1.4426950408889634074;   // -1 / ln 2
 constexpr int kMaxKQ = (4 * TRX_MAX_LAYERS_MFMA + TRX_MAX_TGRID + 15) / 16;
 static_assert(TRX_MAX_LAYERS_MFMA <= kPT, "one thread per ray");
 
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
         const int col = cr * NR32 + 32 * rb + (lane & 31);
         float* o = f + (((int64_t)rb * L.NKQ + task_of(cr)) * 2 * 64 + lane) * 8;
         for (int i = 0; i < 8; ++i) {
-          const double x = sAcc[2 * i + (lane >> 5)][col];
+          const double x = kNegLog2e * sAcc[2 * i + (lane >> 5)][col];
           const float hi32 = (float)x;
           o[i] = hi32;
           o[64 * 8 + i] = (float)(x - (double)hi32);
@@ -690,7 +693,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
         const int col = cr * NR32 + 32 * rb + (lane & 31);
         uint16_t* o = f + (((int64_t)rb * L.NKQ + task_of(cr)) * np * 64 + lane) * 8;
         for (int v = 0; v < 8; ++v) {
-          const double x = sAcc[8 * (lane >> 5) + v][col];
+          const double x = kNegLog2e * sAcc[8 * (lane >> 5) + v][col];
           const uint16_t p0 = bf16_bits((float)x);
           const double r1 = x - bf16_to_double(p0);
           const uint16_t p1 = bf16_bits((float)r1);
