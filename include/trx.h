@@ -85,7 +85,7 @@ enum {
   TRX_MODEL_NONFINITE = 8,     /* a non-finite value appeared in the outputs */
   TRX_MODEL_GRAD_UNSUPPORTED = 16 /* trx_chi2_grad: the model has more distinct
                                      table corners and CIA nodes than the
-                                     gradient kernel stages (96); its gradient
+                                     gradient kernel stages (128); its gradient
                                      outputs are NaN */
 };
 

@@ -46,8 +46,9 @@ constexpr int kLd = 65;   // LDS row stride of the [row][column] tiles: transpos
 constexpr int kAS = 4;    // tables per load batch in the staging
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-static_assert(kKG % 32 == 0 && kKG <= 3 * 32, "slot blocks of the gradient");
+static_assert(kKG % 32 == 0 && kKG <= 4 * 32, "slot blocks of the gradient: one Mbar tile per wave");
 static_assert(TRX_MAX_LAYERS_MFMA <= 32 * kWaves, "one ray block per wave");
+static_assert((TRX_MAX_LAYERS_MFMA / 32) * (kKG / 32) <= 4 * kWaves, "four Pbar tiles per wave cover every layout");
 
 // v of another lane of the same 16-lane row (DPP lane move; CTRL is the
 // data-parallel-primitive control: quad permutations, row mirrors)
@@ -205,7 +206,7 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
   }
 }
 
-// PT: Pbar tiles per wave (2 covers 128 rays x 96 slots, 3 covers 224
+// PT: Pbar tiles per wave (2 covers 128 rays x 128 slots, 4 covers 224
 // rays); with two, the kernel fits 128 registers, so two workgroups share a
 // CU (the LDS of a 128-ray layout allows it)
 template <int PT>
@@ -792,13 +793,13 @@ hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return hipSuccess;
   const size_t lds = adj_item_lds_bytes(a.L);
   const bool small = a.L.NRB * (kKG / 32) <= 2 * kWaves;
-  const void* fn = small ? (const void*)k_adj_item<2> : (const void*)k_adj_item<3>;
+  const void* fn = small ? (const void*)k_adj_item<2> : (const void*)k_adj_item<4>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (small)
     hipLaunchKernelGGL(k_adj_item<2>, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
   else
-    hipLaunchKernelGGL(k_adj_item<3>, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
+    hipLaunchKernelGGL(k_adj_item<4>, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
   return hipGetLastError();
 }
 

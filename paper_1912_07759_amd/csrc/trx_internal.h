@@ -108,7 +108,7 @@ struct Layout {
 };
 
 // Opacity slots the gradient supports per model (corners and CIA nodes).
-constexpr int kKG = 96;
+constexpr int kKG = 128;
 
 // Opacity slots of a model in the matrix-core modes: its distinct
 // cross-section corners (at most 4 per layer, at most the grid's n_T n_P)

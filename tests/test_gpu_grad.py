@@ -166,8 +166,8 @@ def test_gradient_plan_graph(gpu_ctx, problem):
 def test_gradient_long_models_and_slot_limit(gpu_ctx):
     """Models of 40, 150 and 224 layers in one batch (224 takes the kernel
     variant for more than 160 rays) against the oracle's reference gradient,
-    next to a model whose zig-zag temperature profile touches more than 96
-    distinct table corners and CIA nodes: that one is flagged
+    next to a model whose zig-zag temperature profile touches more than 128
+    distinct table corners and CIA nodes (about 150): that one is flagged
     TRX_MODEL_GRAD_UNSUPPORTED with NaN outputs, its neighbours unaffected."""
     from paper_1912_07759_amd import trx
     from synth.atmosphere import guillot_T, log_midpoint_pressures, log_uniform_channels
@@ -179,7 +179,9 @@ def test_gradient_long_models_and_slot_limit(gpu_ctx):
     g0 = GM_JUP / R_JUP ** 2
     Ts = [guillot_T(log_midpoint_pressures(1e6, 1e-4, N), g0, Ti)
           for N, Ti in ((40, 900.0), (150, 1500.0), (224, 2100.0))]
-    zig = np.where(np.arange(90) % 2 == 0, 250.0, 3300.0) + np.linspace(0.0, 600.0, 90)
+    # alternate layers on two branches, 250 -> 1450 K and 3300 -> 2100 K
+    ramp = np.linspace(0.0, 1200.0, 120)
+    zig = np.where(np.arange(120) % 2 == 0, 250.0 + ramp, 3300.0 - ramp)
     Ts.append(zig)
     rng = np.random.default_rng(7)
     vmr = rng.uniform(-7.0, -3.0, (len(Ts), tables.n_abs))
@@ -242,3 +244,47 @@ def test_gradient_constant_gravity_and_window(gpu_ctx):
             norm, comp = _grad_err(mine, ref)
             print(f"gravity={gravity} model {b}: grad norm err {norm:.2e} comp err {comp:.2e}")
             assert norm <= GRAD_TOL and comp <= GRAD_TOL, (gravity, b, norm, comp)
+
+
+def test_large_workload_forward_and_gradient(gpu_ctx):
+    """The large batched workload's shapes with fewer wavenumbers and models:
+    40 T x 30 P tables of 10 absorbers with CIA and Rayleigh, five models of
+    100-196 layers, three of them with 104-111 opacity slots (four 32-slot
+    blocks in the gradient).  The split-bf16 forward against the oracle's
+    depth, then chi^2 and its gradient (recompute mode, FP64 forward) against
+    the oracle's reference gradient."""
+    from paper_1912_07759_amd import trx
+    from parity_util import TOL, binned_rel_err, native_rel_err
+    tables, full, ch = make_config(5, n_wn=1200, n_lines=80, B=24)
+    batch = full.subset([2, 3, 5, 12, 15])
+    refs = [oracle.forward_model(batch.model(b), tables, ch) for b in range(batch.B)]
+    Tt = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, Tt, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=200)
+    nat, binned, st = trx.forward(gpu_ctx, Tt, db, bins, "bf16x2")
+    gpu_ctx.synchronize()
+    nat, binned, st = nat.cpu().numpy(), binned.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0), st
+    worst = 0.0
+    for b, r in enumerate(refs):
+        worst = max(worst, native_rel_err(nat[b], r["depth"], 0, tables.n_wn),
+                    binned_rel_err(binned[b], r["binned"]))
+    print(f"large workload bf16x2 forward: worst rel err {worst:.2e}")
+    assert worst <= TOL["bf16x2"]
+
+    sigma = np.full(len(ch.lo), 50e-6)
+    obs = np.stack([r["binned"] * (1.0 + 2e-4 * np.sin(np.arange(len(ch.lo)) + b))
+                    for b, r in enumerate(refs)])
+    out = trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, sigma, "fp64")
+    g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    bins.close()
+    Tt.close()
+    assert np.all(g["status"] == 0), g["status"]
+    off = batch.layer_off
+    for b in range(batch.B):
+        ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
+        assert abs(g["chi2"][b] - ref["chi2"]) <= 1e-5 * ref["chi2"]
+        mine = {"dT": g["dT"][off[b]:off[b + 1]], "dlog10_vmr": g["dlog10_vmr"][b], "dRp": g["dRp"][b]}
+        norm, comp = _grad_err(mine, ref)
+        print(f"large workload model {b} (N={int(batch.n_layers[b])}): grad norm err {norm:.2e} comp err {comp:.2e}")
+        assert norm <= GRAD_TOL and comp <= GRAD_TOL, (b, norm, comp)
