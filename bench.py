@@ -49,6 +49,10 @@ def parse():
                    help="skip the gradient leg (chi^2 gradients of the 256-point workload)")
     p.add_argument("--grad-precision", default="fp64", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
                    help="forward pass of the gradient leg (the residual needs its accuracy)")
+    p.add_argument("--large", action="store_true",
+                   help="also run the large workload (1024 models of 100-200 layers, 10 "
+                        "absorbers, 40 x 30 x 100000 tables): split-bf16 forward and FP64-forward "
+                        "gradients, with the device memory in use")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="also run one plain device copy of this many MiB (reference "
                         "for the HBM byte counters of a profiler run)")
@@ -83,11 +87,52 @@ def traffic_of(kernel, precision):
         return None
 
 
+def observation(args, ctx, trx, T, bins, tables, batch, ch, cfg, n_layers):
+    """The synthetic observation of a gradient workload: the binned spectrum of
+    point 0 plus seeded 50 ppm noise.  With the oracle leg on, that spectrum
+    is the oracle's (it is then also an input of the oracle's check); with
+    --no-cpu it comes from the library's FP64 path and nothing is checked."""
+    from synth.workloads import observation_noise
+    if not args.no_cpu:
+        import oracle
+        truth = oracle.forward_model(batch.model(0), tables, ch)["binned"]
+    else:
+        one = trx.DeviceBatch.from_synth(batch.subset([0]), max_layers=n_layers)
+        _, tb, _ = trx.forward(ctx, T, one, bins, "fp64", native=False)
+        truth = tb[0].cpu().numpy()
+    noise, sigma = observation_noise(cfg, 1, bins.n)
+    return np.tile(truth + noise[0], (batch.B, 1)), sigma
+
+
+def oracle_grad_check(args, batch, tables, ch, obs, sigma, g, picks):
+    """Largest gradient error of the library against the oracle's reference
+    gradient over the points `picks` (stopping after --cpu-seconds) and the
+    oracle's single-core rate."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    off = batch.layer_off
+    errs, done, t_cpu = [], 0, 0.0
+    with threadpool_limits(limits=1):
+        for b in picks:
+            if done and t_cpu > args.cpu_seconds:
+                break
+            t1 = time.perf_counter()
+            ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
+            t_cpu += time.perf_counter() - t1
+            done += 1
+            v = np.concatenate([g["dT"][off[b]:off[b + 1]], g["dlog10_vmr"][b], [g["dRp"][b]]])
+            r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
+            big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
+            errs.append(max(np.linalg.norm(v - r) / np.linalg.norm(r),
+                            float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big])))))
+    return max(errs), done, t_cpu
+
+
 def gradient_leg(args, ctx, trx, torch):
     """chi^2 gradients of 256 parameter points (100-layer perturbed Guillot
     profiles, 7 absorbers, 50000-point tables, 100 channels, 50 ppm noise on
     the truth's binned spectrum) from one graph-captured gradient plan."""
-    from synth.workloads import make_config, observation_noise
+    from synth.workloads import make_config
     t0 = time.time()
     tables, batch, ch = make_config(4)
     log(f"gradient inputs generated in {time.time() - t0:.1f} s: B={batch.B}, W={tables.n_wn}")
@@ -95,12 +140,7 @@ def gradient_leg(args, ctx, trx, torch):
     bins = trx.Bins(ctx, T, ch.lo, ch.hi)
     db = trx.DeviceBatch.from_synth(batch, max_layers=100)
     B = batch.B
-    # the observation: the truth (point 0) binned by the FP64 path, plus noise
-    _, truth, _ = trx.forward(ctx, T, trx.DeviceBatch.from_synth(batch.subset([0]), max_layers=100),
-                              bins, "fp64", native=False)
-    noise, sigma = observation_noise(4, 1, bins.n)
-    obs_row = truth[0].cpu().numpy() + noise[0]
-    obs = np.tile(obs_row, (B, 1))
+    obs, sigma = observation(args, ctx, trx, T, bins, tables, batch, ch, 4, 100)
     plan = trx.Plan(ctx, T, bins, B_max=B, N_max=100, precision=args.grad_precision, graph=True,
                     grad=True)
     plan.autotune(db)
@@ -125,31 +165,80 @@ def gradient_leg(args, ctx, trx, torch):
                       "channels": bins.n, "noise_ppm": 50, "variant": plan.describe()}}
     log(f"gradient: {ms:.3f} ms/step ({B / (ms * 1e-3):.1f} evals/s)")
     if not args.no_cpu:
-        import oracle
-        from threadpoolctl import threadpool_limits
         g = {k: v.cpu().numpy() for k, v in out.items()}
-        off = batch.layer_off
-        errs, done, t_cpu = [], 0, 0.0
-        with threadpool_limits(limits=1):
-            for b in range(B):
-                if done and t_cpu > args.cpu_seconds:
-                    break
-                t1 = time.perf_counter()
-                ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
-                t_cpu += time.perf_counter() - t1
-                done += 1
-                v = np.concatenate([g["dT"][off[b]:off[b + 1]], g["dlog10_vmr"][b], [g["dRp"][b]]])
-                r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
-                big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
-                errs.append(max(np.linalg.norm(v - r) / np.linalg.norm(r),
-                                float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big])))))
-        res["error"] = {"max_rel_err_gradient": max(errs), "models_checked": done}
+        worst, done, t_cpu = oracle_grad_check(args, batch, tables, ch, obs, sigma, g, range(B))
+        res["error"] = {"max_rel_err_gradient": worst, "models_checked": done}
         res["cpu_baseline"] = {"value": round(done / t_cpu, 4), "unit": "gradient evals/s",
                                "cores": 1, "kind": "oracle",
                                "sample": f"first {done} of {B} points, {t_cpu:.1f} s "
                                          f"single-threaded numpy FP64 reverse mode"}
-        log(f"gradient oracle: {done} points in {t_cpu:.1f} s; max err {max(errs):.2e}")
+        log(f"gradient oracle: {done} points in {t_cpu:.1f} s; max err {worst:.2e}")
     plan.close()
+    bins.close()
+    T.close()
+    return res
+
+
+def large_leg(args, ctx, trx, torch):
+    """The large workload: 1024 models of 100-200 layers, 10 absorbers with
+    CIA and Rayleigh on 40 T x 30 P x 100000-point tables, 100 channels.  The
+    split-bf16 forward and the chi^2 gradients (recompute mode, FP64 forward)
+    of one graph-captured plan each, the device memory in use at the end
+    (tables, model workspaces, partial sums and outputs of both plans), and
+    the gradient error of sampled points against the oracle."""
+    from synth.workloads import make_config
+    t0 = time.time()
+    tables, batch, ch = make_config(5)
+    B = batch.B
+    log(f"large inputs generated in {time.time() - t0:.1f} s: B={B}, W={tables.n_wn}")
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    T = trx.Tables.from_synth(ctx, tables)
+    bins = trx.Bins(ctx, T, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=200)
+    pf = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision="bf16x2", graph=True)
+    pf.autotune(db)
+    ms_f = time_steps(lambda: pf.launch(db), args.steps, args.warmup)
+    _, _, st = pf.launch(db)
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    log(f"large forward bf16x2: {ms_f:.3f} ms/step")
+    obs, sigma = observation(args, ctx, trx, T, bins, tables, batch, ch, 5, 200)
+    pg = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision="fp64", graph=True, grad=True)
+    ms_g = time_steps(lambda: pg.launch_grad(db, obs, sigma), max(2, args.steps // 3), 1)
+    out = pg.launch_grad(db, obs, sigma)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    n_bad = int((out["status"] != 0).sum())
+    ctx.profile(True)
+    pg.launch_grad(db, obs, sigma)
+    kms = {}
+    for k, name in ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_FORWARD, "forward"),
+                    (trx.KERNEL_ADJOINT, "adjoint_item"), (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")):
+        tot, n = ctx.profile_read(k)
+        kms[name] = round(tot / max(n, 1), 3)
+    ctx.profile(False)
+    log(f"large gradient: {ms_g:.3f} ms/step, {n_bad} points flagged")
+    res = {"forward_ms_per_step": round(ms_f, 3), "forward_spectra_per_s": round(B / (ms_f * 1e-3), 1),
+           "forward_precision": "bf16x2", "forward_variant": pf.describe(),
+           "gradient_ms_per_step": round(ms_g, 3),
+           "gradient_evals_per_s": round(B / (ms_g * 1e-3), 1), "gradient_forward_precision": "fp64",
+           "gradient_points_unsupported": n_bad, "gradient_kernel_ms": kms,
+           "device_memory_gb": round((free0 - free1) / 1e9, 2),
+           "config": {"workload": "batched-grad-1024-100to200L-10abs-100000wn", "models": B,
+                      "layers": "100-200", "absorbers": tables.n_abs, "wavenumbers": tables.n_wn,
+                      "table_grid": [len(tables.T_grid), len(tables.log10P_grid)],
+                      "channels": bins.n}}
+    if not args.no_cpu:
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        order = np.argsort(batch.n_layers)
+        picks = [int(order[-1]), int(order[0])] + list(range(B))
+        worst, done, t_cpu = oracle_grad_check(args, batch, tables, ch, obs, sigma, g, picks)
+        res["error"] = {"max_rel_err_gradient": worst, "models_checked": done,
+                        "oracle_seconds": round(t_cpu, 1)}
+        log(f"large gradient oracle: {done} points in {t_cpu:.1f} s; max err {worst:.2e}")
+    pg.close()
+    pf.close()
     bins.close()
     T.close()
     return res
@@ -280,6 +369,7 @@ def main():
     grad = None
     if not args.no_grad:
         grad = gradient_leg(args, ctx, trx, torch)
+    large = large_leg(args, ctx, trx, torch) if args.large else None
 
     # oracle leg: CPU baseline rate and the error stamp of sampled models
     cpu = None
@@ -326,6 +416,8 @@ def main():
                       "launch": "hip graph of one plan", "variant": variant},
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
            "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad}
+    if large is not None:
+        out["large"] = large
     print(json.dumps(out), flush=True)
 
 
