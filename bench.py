@@ -182,10 +182,11 @@ def gradient_leg(args, ctx, trx, torch):
 def large_leg(args, ctx, trx, torch):
     """The large workload: 1024 models of 100-200 layers, 10 absorbers with
     CIA and Rayleigh on 40 T x 30 P x 100000-point tables, 100 channels.  The
-    split-bf16 forward and the chi^2 gradients (recompute mode, FP64 forward)
-    of one graph-captured plan each, the device memory in use at the end
-    (tables, model workspaces, partial sums and outputs of both plans), and
-    the gradient error of sampled points against the oracle."""
+    split-bf16 forward, and the chi^2 gradients (recompute mode) with the FP64
+    and with the split-bf16 forward, one graph-captured plan each; the device
+    memory in use with each gradient plan (tables, model workspaces, partial
+    sums and outputs), and the gradient error of sampled points against the
+    oracle."""
     from synth.workloads import make_config
     t0 = time.time()
     tables, batch, ch = make_config(5)
@@ -204,40 +205,45 @@ def large_leg(args, ctx, trx, torch):
     assert int((st != 0).sum()) == 0
     log(f"large forward bf16x2: {ms_f:.3f} ms/step")
     obs, sigma = observation(args, ctx, trx, T, bins, tables, batch, ch, 5, 200)
-    pg = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision="fp64", graph=True, grad=True)
-    ms_g = time_steps(lambda: pg.launch_grad(db, obs, sigma), max(2, args.steps // 3), 1)
-    out = pg.launch_grad(db, obs, sigma)
-    torch.cuda.synchronize()
-    free1, _ = torch.cuda.mem_get_info()
-    n_bad = int((out["status"] != 0).sum())
-    ctx.profile(True)
-    pg.launch_grad(db, obs, sigma)
-    kms = {}
-    for k, name in ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_FORWARD, "forward"),
-                    (trx.KERNEL_ADJOINT, "adjoint_item"), (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")):
-        tot, n = ctx.profile_read(k)
-        kms[name] = round(tot / max(n, 1), 3)
-    ctx.profile(False)
-    log(f"large gradient: {ms_g:.3f} ms/step, {n_bad} points flagged")
     res = {"forward_ms_per_step": round(ms_f, 3), "forward_spectra_per_s": round(B / (ms_f * 1e-3), 1),
            "forward_precision": "bf16x2", "forward_variant": pf.describe(),
-           "gradient_ms_per_step": round(ms_g, 3),
-           "gradient_evals_per_s": round(B / (ms_g * 1e-3), 1), "gradient_forward_precision": "fp64",
-           "gradient_points_unsupported": n_bad, "gradient_kernel_ms": kms,
-           "device_memory_gb": round((free0 - free1) / 1e9, 2),
            "config": {"workload": "batched-grad-1024-100to200L-10abs-100000wn", "models": B,
                       "layers": "100-200", "absorbers": tables.n_abs, "wavenumbers": tables.n_wn,
                       "table_grid": [len(tables.T_grid), len(tables.log10P_grid)],
                       "channels": bins.n}}
-    if not args.no_cpu:
-        g = {k: v.cpu().numpy() for k, v in out.items()}
-        order = np.argsort(batch.n_layers)
-        picks = [int(order[-1]), int(order[0])] + list(range(B))
-        worst, done, t_cpu = oracle_grad_check(args, batch, tables, ch, obs, sigma, g, picks)
-        res["error"] = {"max_rel_err_gradient": worst, "models_checked": done,
-                        "oracle_seconds": round(t_cpu, 1)}
-        log(f"large gradient oracle: {done} points in {t_cpu:.1f} s; max err {worst:.2e}")
-    pg.close()
+    # gradients with the FP64 forward (the residual at its full accuracy) and
+    # with the split-bf16 forward; one plan at a time
+    for prec in ("fp64", "bf16x2"):
+        pg = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision=prec, graph=True, grad=True)
+        ms_g = time_steps(lambda: pg.launch_grad(db, obs, sigma), max(2, args.steps // 3), 1)
+        out = pg.launch_grad(db, obs, sigma)
+        torch.cuda.synchronize()
+        free1, _ = torch.cuda.mem_get_info()
+        n_bad = int((out["status"] != 0).sum())
+        ctx.profile(True)
+        pg.launch_grad(db, obs, sigma)
+        kms = {}
+        for k, name in ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_FORWARD, "forward"),
+                        (trx.KERNEL_ADJOINT, "adjoint_item"),
+                        (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")):
+            tot, n = ctx.profile_read(k)
+            kms[name] = round(tot / max(n, 1), 3)
+        ctx.profile(False)
+        log(f"large gradient ({prec} forward): {ms_g:.3f} ms/step, {n_bad} points flagged")
+        gr = {"ms_per_step": round(ms_g, 3), "evals_per_s": round(B / (ms_g * 1e-3), 1),
+              "forward_precision": prec, "points_unsupported": n_bad, "kernel_ms": kms,
+              "device_memory_gb": round((free0 - free1) / 1e9, 2)}
+        if not args.no_cpu:
+            g = {k: v.cpu().numpy() for k, v in out.items()}
+            order = np.argsort(batch.n_layers)
+            # point 0 (whose residual is the noise), the longest and the shortest
+            picks = list(dict.fromkeys([0, int(order[-1]), int(order[0])] + list(range(B))))
+            worst, done, t_cpu = oracle_grad_check(args, batch, tables, ch, obs, sigma, g, picks)
+            gr["error"] = {"max_rel_err_gradient": worst, "models_checked": done,
+                           "oracle_seconds": round(t_cpu, 1)}
+            log(f"large gradient oracle: {done} points in {t_cpu:.1f} s; max err {worst:.2e}")
+        res["gradient_" + prec] = gr
+        pg.close()
     pf.close()
     bins.close()
     T.close()

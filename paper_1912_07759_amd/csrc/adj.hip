@@ -48,7 +48,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 static_assert(kKG % 32 == 0 && kKG <= 4 * 32, "slot blocks of the gradient: one Mbar tile per wave");
 static_assert(TRX_MAX_LAYERS_MFMA <= 32 * kWaves, "one ray block per wave");
-static_assert((TRX_MAX_LAYERS_MFMA / 32) * (kKG / 32) <= 4 * kWaves, "four Pbar tiles per wave cover every layout");
+static_assert((TRX_MAX_LAYERS_MFMA / 32) * (kKG / 32) <= 2 * 2 * kWaves, "two Pbar tiles per wave of 16 cover every layout");
 
 // v of another lane of the same 16-lane row (DPP lane move; CTRL is the
 // data-parallel-primitive control: quad permutations, row mirrors)
@@ -140,7 +140,7 @@ struct ItemLds {
   float* rows;   // [kKG][kLd] mixed slot rows M of the span, later their adjoints
   float* tbar;   // [NP][kLd] taubar of the span
   float2* aw;    // [NP] (A_j/Rs^2, PR_j)
-  float* rpart;  // [kWaves][64] Rayleigh sums by wave
+  float* rpart;  // [waves][64] Rayleigh sums by wave
   float* rbar;   // [64] Rbar of the span
   int32_t* sid;  // [kKG] table row of each slot
   float* chi;    // [TRX_MAX_ABSORBERS]
@@ -149,7 +149,8 @@ struct ItemLds {
   float* pacc;   // [G.o_P] this item's partial sums below the Pbar block
 };
 
-__host__ __device__ inline size_t carve(const Layout& L, const GradAcc& G, unsigned char* base, ItemLds* out) {
+__host__ __device__ inline size_t carve(const Layout& L, const GradAcc& G, int nw, unsigned char* base,
+                                        ItemLds* out) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
     unsigned char* p = base ? base + o : nullptr;
@@ -160,7 +161,7 @@ __host__ __device__ inline size_t carve(const Layout& L, const GradAcc& G, unsig
   s.rows = (float*)take((size_t)kKG * kLd * 4);
   s.tbar = (float*)take((size_t)L.NP * kLd * 4);
   s.aw = (float2*)take((size_t)L.NP * 8);
-  s.rpart = (float*)take((size_t)kWaves * kCols * 4);
+  s.rpart = (float*)take((size_t)nw * kCols * 4);
   s.rbar = (float*)take((size_t)kCols * 4);
   s.sid = (int32_t*)take(kKG * 4);
   s.chi = (float*)take(TRX_MAX_ABSORBERS * 4);
@@ -206,11 +207,12 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
   }
 }
 
-// PT: Pbar tiles per wave (2 covers 128 rays x 128 slots, 4 covers 224
-// rays); with two, the kernel fits 128 registers, so two workgroups share a
-// CU (the LDS of a 128-ray layout allows it)
-template <int PT>
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 4 : 1)))
+// PT Pbar tiles per wave, NW waves per workgroup: 8 waves cover 128 rays x
+// 128 slots, 16 waves 224 rays.  With two tiles the kernel fits 128
+// registers, four waves per SIMD: two 8-wave workgroups share a CU (the LDS
+// of a 128-ray layout allows it), or one 16-wave workgroup.
+template <int PT, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 4 : 1)))
 void k_adj_item(AdjArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   const int B = a.B_dev ? *a.B_dev : a.B;
@@ -249,7 +251,7 @@ void k_adj_item(AdjArgs a) {
   const float* pa = reinterpret_cast<const float*>(slab + L.off_pa);
   const float* pt = reinterpret_cast<const float*>(slab + L.off_pt);
   ItemLds s;
-  carve(L, G, dyn, &s);
+  carve(L, G, NW, dyn, &s);
 
   // records: ray weights (zero past N), slot rows, mixing ratios
   {
@@ -260,7 +262,7 @@ void k_adj_item(AdjArgs a) {
     if (tid < TRX_MAX_ABSORBERS) s.chi[tid] = hd->chi_abs32[tid];
     if (tid < TRX_MAX_CIA) s.ciaw[tid] = hd->cia_w32[tid];
     if (tid < kMaxSpecies) s.chis[tid] = hd->chi_s32[tid];
-    for (int e = tid; e < G.o_P; e += 64 * kWaves) s.pacc[e] = 0.f;
+    for (int e = tid; e < G.o_P; e += 64 * NW) s.pacc[e] = 0.f;
   }
   __syncthreads();
   float* acc = s.pacc;
@@ -283,10 +285,10 @@ void k_adj_item(AdjArgs a) {
     // staging: M of the span's slots (zero past K) and the Rayleigh sums
     {
       float rp = 0.f;
-      for (int k = wave; k < ns; k += kWaves) rp = fmaf(s.chis[k], tb.ray32[(int64_t)k * W + cc], rp);
+      for (int k = wave; k < ns; k += NW) rp = fmaf(s.chis[k], tb.ray32[(int64_t)k * W + cc], rp);
       s.rpart[wave * kCols + lane] = rp;
     }
-    for (int g = wave; g < KP / 8; g += kWaves) {
+    for (int g = wave; g < KP / 8; g += NW) {
       const int s0 = 8 * g;
       float v[8];
 #pragma unroll
@@ -303,7 +305,7 @@ void k_adj_item(AdjArgs a) {
 
     // tau tiles (32 rays x 32 columns), t = wave, wave + 8: tau = P M + PR R
     // over the nonzero 16-slot blocks; then taubar, Abar, PRbar and Rbar
-    for (int t = wave; t < 2 * nrb; t += kWaves) {
+    for (int t = wave; t < 2 * nrb; t += NW) {
       const int rb = t >> 1, tcb = t & 1;
       // nonzero slot blocks of the ray block, the next one's fragment
       // loaded before the current products
@@ -334,7 +336,7 @@ void k_adj_item(AdjArgs a) {
       const int c = 32 * tcb + lc;
       float Rc = 0.f;
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) Rc += s.rpart[w * kCols + c];
+      for (int w = 0; w < NW; ++w) Rc += s.rpart[w * kCols + c];
       const int cg = col0 + c;
       const float Db = (cg >= lo && cg < hi) ? a.dbar[(int64_t)b * W + cg] : 0.f;
       float rs = 0.f;
@@ -362,7 +364,7 @@ void k_adj_item(AdjArgs a) {
     // Pbar += taubar M^T over the span's 64 columns (tiles of nonzero P)
 #pragma unroll
     for (int u = 0; u < kPT; ++u) {
-      const int t = wave + kWaves * u;
+      const int t = wave + NW * u;
       if (t < nrb * nqb) {
         const int rb = t / nqb, qb = t - rb * nqb;
         if ((hd->kq_mask[rb] >> (2 * qb)) & 3) {
@@ -423,11 +425,11 @@ void k_adj_item(AdjArgs a) {
       constexpr int DG = 8, DA = 4;   // corners x absorbers in flight
       for (int i0 = 0; i0 < tb.n_abs; i0 += DA) {
         float acc_i[DA] = {0.f, 0.f, 0.f, 0.f};
-        for (int u0 = wave; u0 < nU; u0 += kWaves * DG) {
+        for (int u0 = wave; u0 < nU; u0 += NW * DG) {
           int soff[DG];
 #pragma unroll
           for (int g = 0; g < DG; ++g) {
-            const int u = u0 + kWaves * g < nU ? u0 + kWaves * g : u0;
+            const int u = u0 + NW * g < nU ? u0 + NW * g : u0;
             soff[g] = __builtin_amdgcn_readfirstlane(s.sid[u]) * W * 4;
           }
           float v[DA][DG];
@@ -446,7 +448,7 @@ void k_adj_item(AdjArgs a) {
             if (i0 + ii < tb.n_abs) {
 #pragma unroll
               for (int g = 0; g < DG; ++g)
-                if (u0 + kWaves * g < nU) acc_i[ii] = fmaf(s.rows[(u0 + kWaves * g) * kLd + lane], v[ii][g], acc_i[ii]);
+                if (u0 + NW * g < nU) acc_i[ii] = fmaf(s.rows[(u0 + NW * g) * kLd + lane], v[ii][g], acc_i[ii]);
             }
           }
         }
@@ -467,7 +469,7 @@ void k_adj_item(AdjArgs a) {
         for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
           for (int k = 0; k < kCN; ++k) {
-            const int t = nU + wave + kWaves * k;
+            const int t = nU + wave + NW * k;
             cv[pp][k] = (p0 + pp < tb.n_cia && t < K)
                             ? tb.cia32[(int64_t)(p0 + pp) * cia_stride + (int64_t)s.sid[t] * W + cc]
                             : 0.f;
@@ -478,7 +480,7 @@ void k_adj_item(AdjArgs a) {
             float acc_p = 0.f;
 #pragma unroll
             for (int k = 0; k < kCN; ++k) {
-              const int t = nU + wave + kWaves * k;
+              const int t = nU + wave + NW * k;
               if (t < K) acc_p = fmaf(s.rows[t * kLd + lane], cv[pp][k], acc_p);
             }
             acc_p = wave_sum(acc_p);
@@ -490,25 +492,25 @@ void k_adj_item(AdjArgs a) {
       for (int p = 0; p < tb.n_cia; ++p) {
         const float* tp = tb.cia32 + (int64_t)p * cia_stride;
         float acc_p = 0.f;
-        for (int t = nU + wave + kWaves * kCN; t < K; t += kWaves)
+        for (int t = nU + wave + NW * kCN; t < K; t += NW)
           acc_p = fmaf(s.rows[t * kLd + lane], tp[(int64_t)s.sid[t] * W + cc], acc_p);
-        if (nU + wave + kWaves * kCN < K) {
+        if (nU + wave + NW * kCN < K) {
           acc_p = wave_sum(acc_p);
           if (lane == 0) atomicAdd(acc + G.o_cw + p, acc_p);
         }
       }
       // Rayleigh: the wave's species q = wave + 8 k, loads first
       const float rl = s.rbar[lane];
-      constexpr int kRS = (kMaxSpecies + kWaves - 1) / kWaves;
+      constexpr int kRS = (kMaxSpecies + NW - 1) / NW;
       float rv[kRS];
 #pragma unroll
       for (int k = 0; k < kRS; ++k) {
-        const int q = wave + kWaves * k;
+        const int q = wave + NW * k;
         rv[k] = q < ns ? tb.ray32[(int64_t)q * W + cc] : 0.f;
       }
 #pragma unroll
       for (int k = 0; k < kRS; ++k) {
-        const int q = wave + kWaves * k;
+        const int q = wave + NW * k;
         if (q < ns) {
           const float t = wave_sum(rl * rv[k]);
           if (lane == 0) atomicAdd(acc + G.o_chi + q, t);
@@ -520,10 +522,10 @@ void k_adj_item(AdjArgs a) {
 
   // this item's partial sums, reduced per model in a fixed order later
   float* dst = a.part + ((int64_t)b * a.n_items + item) * G.n;
-  for (int e = tid; e < G.o_P; e += 64 * kWaves) dst[e] = s.pacc[e];
+  for (int e = tid; e < G.o_P; e += 64 * NW) dst[e] = s.pacc[e];
 #pragma unroll
   for (int u = 0; u < kPT; ++u) {
-    const int t = wave + kWaves * u;
+    const int t = wave + NW * u;
     if (t < nrb * nqb) {
       const int rb = t / nqb, qb = t - rb * nqb;
 #pragma unroll
@@ -782,7 +784,12 @@ __global__ __launch_bounds__(64) void k_adj_geom(AdjArgs a) {
 
 }  // namespace
 
-size_t adj_item_lds_bytes(const Layout& L) { return carve(L, make_grad_acc(L.NP), nullptr, nullptr); }
+// the 8-wave variant takes layouts of at most 128 rays (its two Pbar tiles
+// per wave cover 4 x 4 ray x slot blocks), the 16-wave one the others
+static bool adj_small(const Layout& L) { return L.NRB * (kKG / 32) <= 2 * kWaves; }
+size_t adj_item_lds_bytes(const Layout& L) {
+  return carve(L, make_grad_acc(L.NP), adj_small(L) ? kWaves : 2 * kWaves, nullptr, nullptr);
+}
 
 void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
@@ -792,14 +799,14 @@ void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
 hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return hipSuccess;
   const size_t lds = adj_item_lds_bytes(a.L);
-  const bool small = a.L.NRB * (kKG / 32) <= 2 * kWaves;
-  const void* fn = small ? (const void*)k_adj_item<2> : (const void*)k_adj_item<4>;
+  const bool small = adj_small(a.L);
+  const void* fn = small ? (const void*)k_adj_item<2, kWaves> : (const void*)k_adj_item<2, 2 * kWaves>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (small)
-    hipLaunchKernelGGL(k_adj_item<2>, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
+    hipLaunchKernelGGL((k_adj_item<2, kWaves>), dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
   else
-    hipLaunchKernelGGL(k_adj_item<4>, dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
+    hipLaunchKernelGGL((k_adj_item<2, 2 * kWaves>), dim3(B_grid, a.n_items), dim3(128 * kWaves), lds, s, a);
   return hipGetLastError();
 }
 
