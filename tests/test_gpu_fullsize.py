@@ -1,0 +1,147 @@
+"""GPU parity at the full sizes of the benchmark's workloads, in the launch
+configuration bench.py times (graph-captured plans, autotuned variant):
+sampled models against the oracle one by one, and properties that every
+model of the batch must hold whatever its size."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth.workloads import make_config, observation_noise
+from parity_util import TOL, binned_rel_err, native_rel_err
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-4
+
+
+def _picks(batch, k, seed):
+    """The models of largest and smallest work (layers x window), then k
+    random ones."""
+    work = batch.n_layers.astype(np.float64) * (batch.wn_hi - batch.wn_lo)
+    order = np.argsort(work)
+    rnd = np.random.default_rng(seed).permutation(batch.B)[:k]
+    return list(dict.fromkeys([int(order[-1]), int(order[0])] + [int(i) for i in rnd]))
+
+
+def _bare_disc(batch):
+    return (np.asarray(batch.Rp, dtype=np.float64) / np.asarray(batch.Rs, dtype=np.float64)) ** 2 \
+        * np.ones(batch.B)
+
+
+def _grad_err(g, off, b, ref):
+    v = np.concatenate([g["dT"][off[b]:off[b + 1]], g["dlog10_vmr"][b], [g["dRp"][b]]])
+    r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
+    big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
+    return max(np.linalg.norm(v - r) / np.linalg.norm(r),
+               float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big]))))
+
+
+def _forward_full(ctx, cfg, precision, n_layers, n_check, seed):
+    """Forward of workload `cfg` at full size through an autotuned graph plan:
+    the binned output as timed, then the native grid from the same plan."""
+    from paper_1912_07759_amd import trx
+    tables, batch, ch = make_config(cfg)
+    T = trx.Tables.from_synth(ctx, tables)
+    bins = trx.Bins(ctx, T, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=n_layers)
+    plan = trx.Plan(ctx, T, bins, B_max=batch.B, N_max=n_layers, precision=precision, graph=True)
+    variant = plan.autotune(db)
+    _, binned, st = plan.launch(db)
+    binned, st = binned.cpu().numpy().copy(), st.cpu().numpy().copy()
+    nat, binned2, _ = plan.launch(db, native=True)
+    nat, binned2 = nat.cpu().numpy(), binned2.cpu().numpy()
+    plan.close()
+    bins.close()
+    T.close()
+    print(f"workload {cfg}: B={batch.B}, W={tables.n_wn}, variant {variant}")
+
+    # every model: valid, the binned output identical with and without the
+    # native grid, finite depths no smaller than the bare disc inside the
+    # window (each 1 - e^{-tau} >= 0) and nothing written outside it; the
+    # binned channels outside the window are NaN (their pattern is checked
+    # against the oracle on the sampled models), every model has some inside
+    assert np.all(st == 0), np.flatnonzero(st)
+    assert np.array_equal(binned, binned2, equal_nan=True)
+    disc = _bare_disc(batch)
+    ok = ~np.isnan(binned)
+    assert np.all(ok.any(axis=1))
+    assert np.all(np.isfinite(binned[ok]))
+    assert np.all(binned[ok] >= np.broadcast_to(disc[:, None], binned.shape)[ok] * (1.0 - 1e-12))
+    for b in range(batch.B):
+        lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+        inside = nat[b, lo:hi]
+        assert np.all(np.isfinite(inside)) and np.all(inside >= disc[b] * (1.0 - 1e-12)), b
+        assert np.all(np.isnan(nat[b, :lo])) and np.all(np.isnan(nat[b, hi:])), b
+
+    # sampled models against the oracle, element by element
+    worst = 0.0
+    for b in _picks(batch, n_check, seed):
+        ref = oracle.forward_model(batch.model(b), tables, ch)
+        lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+        e1 = native_rel_err(nat[b], ref["depth"], lo, hi)
+        e2 = binned_rel_err(binned[b], ref["binned"])
+        print(f"  model {b} (N={int(batch.n_layers[b])}, window {hi - lo}): native {e1:.2e} binned {e2:.2e}")
+        worst = max(worst, e1, e2)
+    assert worst <= TOL[precision]
+    return tables, batch, ch
+
+
+def test_batched_4096_full_size(gpu_ctx):
+    """The benchmark's batch: 4096 models of 50-200 layers, windows of
+    5000-40000 of 40000 points, 5 absorbers with CIA and Rayleigh, 50
+    channels, split-bf16."""
+    _forward_full(gpu_ctx, 3, "bf16x2", 200, 4, 0)
+
+
+def _gradient_full(ctx, cfg, tables, batch, ch, n_layers, n_check, seed):
+    """chi^2 gradients of workload `cfg` at full size through an autotuned
+    graph-captured gradient plan (FP64 forward), against the oracle's
+    reference gradient on point 0 (its residual is the noise) and sampled
+    points; every point valid with finite outputs."""
+    from paper_1912_07759_amd import trx
+    T = trx.Tables.from_synth(ctx, tables)
+    bins = trx.Bins(ctx, T, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=n_layers)
+    truth = oracle.forward_model(batch.model(0), tables, ch)["binned"]
+    noise, sigma = observation_noise(cfg, 1, len(ch.lo))
+    obs = np.tile(truth + noise[0], (batch.B, 1))
+    plan = trx.Plan(ctx, T, bins, B_max=batch.B, N_max=n_layers, precision="fp64", graph=True,
+                    grad=True)
+    plan.autotune(db)
+    out = plan.launch_grad(db, obs, sigma)
+    g = {k: v.cpu().numpy().copy() for k, v in out.items()}
+    plan.close()
+    bins.close()
+    T.close()
+    assert np.all(g["status"] == 0), np.flatnonzero(g["status"])
+    for k in ("chi2", "dT", "dlog10_vmr", "dRp"):
+        assert np.all(np.isfinite(g[k])), k
+    assert np.all(g["chi2"] >= 0.0)
+    off = batch.layer_off
+    picks = list(dict.fromkeys([0] + [int(i) for i in
+                                      np.random.default_rng(seed).permutation(batch.B)[:n_check]]))
+    for b in picks:
+        ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
+        err = _grad_err(g, off, b, ref)
+        print(f"  point {b} (N={int(batch.n_layers[b])}): chi2 {g['chi2'][b]:.6e} "
+              f"(oracle {ref['chi2']:.6e}), grad err {err:.2e}")
+        assert abs(g["chi2"][b] - ref["chi2"]) <= 1e-5 * ref["chi2"]
+        assert err <= GRAD_TOL, (b, err)
+
+
+def test_gradient_256_full_size(gpu_ctx):
+    """The benchmark's gradient workload: 256 points of a 100-layer free
+    temperature profile, 7 absorbers, 50000 points, 100 channels, 50 ppm
+    noise on the truth's binned spectrum."""
+    tables, batch, ch = make_config(4)
+    _gradient_full(gpu_ctx, 4, tables, batch, ch, 100, 3, 1)
+
+
+def test_large_workload_full_size(gpu_ctx):
+    """The large workload: 1024 models of 100-200 layers, 10 absorbers on 40
+    x 30 x 100000-point tables, 100 channels; split-bf16 forward of every
+    model (sampled ones against the oracle), then gradients with the FP64
+    forward on sampled points."""
+    tables, batch, ch = _forward_full(gpu_ctx, 5, "bf16x2", 200, 1, 2)
+    _gradient_full(gpu_ctx, 5, tables, batch, ch, 200, 1, 3)
