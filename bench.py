@@ -49,6 +49,8 @@ def parse():
                    help="skip the gradient leg (chi^2 gradients of the 256-point workload)")
     p.add_argument("--grad-precision", default="fp64", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
                    help="forward pass of the gradient leg (the residual needs its accuracy)")
+    p.add_argument("--no-single", action="store_true",
+                   help="skip the single-model leg (one model per graph replay)")
     p.add_argument("--large", action="store_true",
                    help="also run the large workload (1024 models of 100-200 layers, 10 "
                         "absorbers, 40 x 30 x 100000 tables): split-bf16 forward and FP64-forward "
@@ -250,6 +252,66 @@ def large_leg(args, ctx, trx, torch):
     return res
 
 
+def single_leg(args, ctx, trx, torch):
+    """One model per launch, each launch one replay of the plan's graph, back
+    to back: the plain model (100 isothermal layers, one absorber, 2000
+    points, native depth) in FP64, and the 5-absorber Guillot model on 40000
+    points binned to 50 channels in FP32 (P in hi + lo), split-bf16 and
+    FP64.  These are single-model latencies: one model does not fill the
+    GPU."""
+    from synth.workloads import make_config, CONFIG_NAMES
+    res = {}
+    for cfg, precs in ((1, ("fp64",)), (2, ("fp32", "bf16x2", "fp64"))):
+        tables, batch, ch = make_config(cfg)
+        T = trx.Tables.from_synth(ctx, tables)
+        bins = trx.Bins(ctx, T, ch.lo, ch.hi) if ch is not None else None
+        db = trx.DeviceBatch.from_synth(batch, max_layers=100)
+        ref = None
+        if not args.no_cpu:
+            import oracle
+            ref = oracle.forward_model(batch.model(0), tables, ch)
+        for prec in precs:
+            plan = trx.Plan(ctx, T, bins, B_max=1, N_max=100, precision=prec, graph=True)
+            plan.autotune(db)
+            native = bins is None
+            fn = lambda: plan.launch(db, native=native, binned=not native)
+            us = time_steps(fn, 200, 20) * 1e3
+            nat, binned, st = fn()
+            torch.cuda.synchronize()
+            assert int(st[0]) == 0
+            entry = {"us_per_model": round(us, 2), "spectra_per_s": round(1e6 / us, 1),
+                     "variant": plan.describe()}
+            if ref is not None:
+                if native:
+                    g = nat[0].cpu().numpy()
+                    entry["max_rel_err_native"] = float(np.max(np.abs(g - ref["depth"]) / ref["depth"]))
+                else:
+                    g = binned[0].cpu().numpy()
+                    entry["max_rel_err_binned"] = float(np.max(np.abs(g - ref["binned"]) / ref["binned"]))
+            res[f"{CONFIG_NAMES[cfg]}:{prec}"] = entry
+            log(f"single {CONFIG_NAMES[cfg]} {prec}: {us:.1f} us/model")
+            plan.close()
+        if bins is not None:
+            bins.close()
+        T.close()
+    return res
+
+
+def step_stats(fn, steps):
+    """Median and quartiles (ms) of `steps` launches, each between its own
+    pair of events on the current stream."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for s, e in ev:
+        s.record()
+        fn()
+        e.record()
+    torch.cuda.synchronize()
+    t = np.array([s.elapsed_time(e) for s, e in ev])
+    return float(np.median(t)), float(np.percentile(t, 25)), float(np.percentile(t, 75))
+
+
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -303,6 +365,7 @@ def main():
     _, binned, status = plan.launch(db)
     torch.cuda.synchronize()
     assert int((status != 0).sum()) == 0
+    med, q1, q3 = step_stats(step, args.steps)
 
     # dominant kernel, timed live with HIP events around each launch on the
     # library's stream (the plan launches its kernels one by one meanwhile)
@@ -375,6 +438,7 @@ def main():
     grad = None
     if not args.no_grad:
         grad = gradient_leg(args, ctx, trx, torch)
+    single = None if args.no_single else single_leg(args, ctx, trx, torch)
     large = large_leg(args, ctx, trx, torch) if args.large else None
 
     # oracle leg: CPU baseline rate and the error stamp of sampled models
@@ -421,7 +485,9 @@ def main():
                       "channels": bins.n, "precision": args.precision,
                       "launch": "hip graph of one plan", "variant": variant},
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
-           "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad}
+           "ms_per_step_median": round(med, 3), "ms_per_step_iqr": [round(q1, 3), round(q3, 3)],
+           "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad,
+           "single_model": single}
     if large is not None:
         out["large"] = large
     print(json.dumps(out), flush=True)
