@@ -46,6 +46,9 @@ constexpr int kLd = 65;   // LDS row stride of the [row][column] tiles: transpos
 constexpr int kAS = 4;    // tables per load batch in the staging
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 static_assert(kKG % 32 == 0 && kKG <= 4 * 32, "slot blocks of the gradient: one Mbar tile per wave");
 static_assert(TRX_MAX_LAYERS_MFMA <= 32 * kWaves, "one ray block per wave");
 static_assert((TRX_MAX_LAYERS_MFMA / 32) * (kKG / 32) <= 2 * 2 * kWaves, "two Pbar tiles per wave of 16 cover every layout");
@@ -79,6 +82,59 @@ __device__ inline double wave_sum_d(double v) {
 __device__ inline float half_sum(float v) {
   v = row_sum(v);
   return v + __shfl_xor(v, 16, 64);
+}
+
+// Products on v_mfma_f32_32x32x16_bf16 at FP32 accuracy: each operand is
+// split into three bf16 pieces (x = hi + mid + lo to about 2^-24 of x) and
+// the six piece products with index sum below three are accumulated (the
+// dropped ones are below 2^-24 of the product).  Lane l supplies the same 8
+// operand values as for eight v_mfma_f32_32x32x2f32 steps, k = 2 v + l/32
+// for step v: the bf16 instruction reads them as k = 8 (l/32) + v, the same
+// permutation of k on both operands, which leaves the sum unchanged.
+__device__ inline void split3(const float (&x)[8], u32x4 (&p)[3]) {
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = x[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      // (r[2i], r[2i+1]) rounded to bf16 (nearest even), r[2i] in the low half
+      const uint32_t q = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{r[2 * i], r[2 * i + 1]}, bf16x2));
+      p[c][i] = q;
+      if (c < 2) {
+        r[2 * i] -= __uint_as_float(q << 16);
+        r[2 * i + 1] -= __uint_as_float(q & 0xffff0000u);
+      }
+    }
+  }
+}
+__device__ inline f32x16 mfma3(const u32x4 (&a)[3], const u32x4 (&b)[3], f32x16 c) {
+  auto m = [](u32x4 x, u32x4 y, f32x16 z) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), z,
+                                                   0, 0, 0);
+  };
+  c = m(a[2], b[0], c);
+  c = m(a[1], b[1], c);
+  c = m(a[0], b[2], c);
+  c = m(a[1], b[0], c);
+  c = m(a[0], b[1], c);
+  return m(a[0], b[0], c);
+}
+// acc += A B over one 16-deep block, from each lane's 8 values of A and B:
+// three-piece bf16 products (SPLIT) or eight v_mfma_f32_32x32x2f32 steps
+template <bool SPLIT>
+__device__ inline f32x16 mfma_block(const float (&av)[8], const float (&bv)[8], f32x16 acc) {
+  if constexpr (SPLIT) {
+    u32x4 ap[3], bp[3];
+    split3(av, ap);
+    split3(bv, bp);
+    return mfma3(ap, bp, acc);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[v], bv[v], acc, 0, 0, 0);
+    return acc;
+  }
 }
 
 // ---- chi^2 and the per-point cotangent Dbar_i ---------------------------
@@ -270,6 +326,10 @@ void k_adj_item(AdjArgs a) {
   // Pbar tiles (32 rays x 32 slots) of this wave, t = wave + 8 u, kept in
   // registers over the item's spans
   constexpr int kPT = PT;
+  // the 8-wave kernel takes the three-piece bf16 products (2.7x fewer matrix
+  // cycles, 13.8 -> 12.8 ms on 100-layer models); the 16-wave one keeps the
+  // FP32 instructions: its piece registers spill (257 -> 268 ms, 224 rays)
+  constexpr bool kSplit = NW == 8;
   f32x16 pb[kPT];
 #pragma unroll
   for (int u = 0; u < kPT; ++u) pb[u] = f32x16{};
@@ -323,12 +383,13 @@ void k_adj_item(AdjArgs a) {
         m &= m - 1;
         const int kn = m ? __builtin_ctzll(m) : -1;
         if (kn >= 0) afrag(kn, n0, n1);
+        float av[8], bv[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const float av = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
-          const float bv = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
-          tau = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, tau, 0, 0, 0);
+          av[i] = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
+          bv[i] = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
         }
+        tau = mfma_block<kSplit>(av, bv, tau);
         a0 = n0;
         a1 = n1;
         kq = kn;
@@ -370,9 +431,16 @@ void k_adj_item(AdjArgs a) {
         if ((hd->kq_mask[rb] >> (2 * qb)) & 3) {
           const float* ar = s.tbar + (32 * rb + lc) * kLd + hl;
           const float* br = s.rows + (32 * qb + lc) * kLd + hl;
-#pragma unroll 8
-          for (int st = 0; st < 32; ++st)
-            pb[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[2 * st], br[2 * st], pb[u], 0, 0, 0);
+#pragma unroll 1
+          for (int k16 = 0; k16 < 4; ++k16) {
+            float av[8], bv[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              av[v] = ar[2 * (8 * k16 + v)];
+              bv[v] = br[2 * (8 * k16 + v)];
+            }
+            pb[u] = mfma_block<kSplit>(av, bv, pb[u]);
+          }
         }
       }
     }
@@ -398,12 +466,13 @@ void k_adj_item(AdjArgs a) {
         jm &= jm - 1;
         const int jn = jm ? __builtin_ctz(jm) : -1;
         if (jn >= 0) tfrag(jn, n0, n1);
+        float av[8], bv[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const float av = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
-          const float bv = s.tbar[(16 * jb + 2 * i + hl) * kLd + 32 * tcb + lc];
-          mb = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, mb, 0, 0, 0);
+          av[i] = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
+          bv[i] = s.tbar[(16 * jb + 2 * i + hl) * kLd + 32 * tcb + lc];
         }
+        mb = mfma_block<kSplit>(av, bv, mb);
         a0 = n0;
         a1 = n1;
         jb = jn;
