@@ -51,7 +51,8 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 static_assert(kKG % 32 == 0 && kKG <= 4 * 32, "slot blocks of the gradient: one Mbar tile per wave");
 static_assert(TRX_MAX_LAYERS_MFMA <= 32 * kWaves, "one ray block per wave");
-static_assert((TRX_MAX_LAYERS_MFMA / 32) * (kKG / 32) <= 2 * 2 * kWaves, "two Pbar tiles per wave of 16 cover every layout");
+constexpr int kWavesL = 12;   // waves of the workgroups of layouts above 128 rays
+static_assert((TRX_MAX_LAYERS_MFMA / 32) * (kKG / 32) <= 3 * kWavesL, "three Pbar tiles per wave of 12 cover every layout");
 
 // v of another lane of the same 16-lane row (DPP lane move; CTRL is the
 // data-parallel-primitive control: quad permutations, row mirrors)
@@ -121,20 +122,12 @@ __device__ inline f32x16 mfma3(const u32x4 (&a)[3], const u32x4 (&b)[3], f32x16 
   c = m(a[0], b[1], c);
   return m(a[0], b[0], c);
 }
-// acc += A B over one 16-deep block, from each lane's 8 values of A and B:
-// three-piece bf16 products (SPLIT) or eight v_mfma_f32_32x32x2f32 steps
-template <bool SPLIT>
+// acc += A B over one 16-deep block, from each lane's 8 values of A and B
 __device__ inline f32x16 mfma_block(const float (&av)[8], const float (&bv)[8], f32x16 acc) {
-  if constexpr (SPLIT) {
-    u32x4 ap[3], bp[3];
-    split3(av, ap);
-    split3(bv, bp);
-    return mfma3(ap, bp, acc);
-  } else {
-#pragma unroll
-    for (int v = 0; v < 8; ++v) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[v], bv[v], acc, 0, 0, 0);
-    return acc;
-  }
+  u32x4 ap[3], bp[3];
+  split3(av, ap);
+  split3(bv, bp);
+  return mfma3(ap, bp, acc);
 }
 
 // ---- chi^2 and the per-point cotangent Dbar_i ---------------------------
@@ -263,12 +256,13 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
   }
 }
 
-// PT Pbar tiles per wave, NW waves per workgroup: 8 waves cover 128 rays x
-// 128 slots, 16 waves 224 rays.  With two tiles the kernel fits 128
-// registers, four waves per SIMD: two 8-wave workgroups share a CU (the LDS
-// of a 128-ray layout allows it), or one 16-wave workgroup.
+// PT Pbar tiles per wave, NW waves per workgroup: 8 waves of two tiles cover
+// 128 rays x 128 slots in 128 registers, so that two workgroups share a CU
+// (the LDS of a 128-ray layout allows it, four waves per SIMD); 12 waves of
+// three tiles cover 224 rays in 168 registers, one workgroup per CU (its LDS
+// takes about 100 KB), three waves per SIMD.
 template <int PT, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 4 : 1)))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 4 : 3)))
 void k_adj_item(AdjArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   const int B = a.B_dev ? *a.B_dev : a.B;
@@ -326,10 +320,6 @@ void k_adj_item(AdjArgs a) {
   // Pbar tiles (32 rays x 32 slots) of this wave, t = wave + 8 u, kept in
   // registers over the item's spans
   constexpr int kPT = PT;
-  // the 8-wave kernel takes the three-piece bf16 products (2.7x fewer matrix
-  // cycles, 13.8 -> 12.8 ms on 100-layer models); the 16-wave one keeps the
-  // FP32 instructions: its piece registers spill (257 -> 268 ms, 224 rays)
-  constexpr bool kSplit = NW == 8;
   f32x16 pb[kPT];
 #pragma unroll
   for (int u = 0; u < kPT; ++u) pb[u] = f32x16{};
@@ -389,7 +379,7 @@ void k_adj_item(AdjArgs a) {
           av[i] = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
           bv[i] = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
         }
-        tau = mfma_block<kSplit>(av, bv, tau);
+        tau = mfma_block(av, bv, tau);
         a0 = n0;
         a1 = n1;
         kq = kn;
@@ -439,7 +429,7 @@ void k_adj_item(AdjArgs a) {
               av[v] = ar[2 * (8 * k16 + v)];
               bv[v] = br[2 * (8 * k16 + v)];
             }
-            pb[u] = mfma_block<kSplit>(av, bv, pb[u]);
+            pb[u] = mfma_block(av, bv, pb[u]);
           }
         }
       }
@@ -472,7 +462,7 @@ void k_adj_item(AdjArgs a) {
           av[i] = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
           bv[i] = s.tbar[(16 * jb + 2 * i + hl) * kLd + 32 * tcb + lc];
         }
-        mb = mfma_block<kSplit>(av, bv, mb);
+        mb = mfma_block(av, bv, mb);
         a0 = n0;
         a1 = n1;
         jb = jn;
@@ -854,10 +844,10 @@ __global__ __launch_bounds__(64) void k_adj_geom(AdjArgs a) {
 }  // namespace
 
 // the 8-wave variant takes layouts of at most 128 rays (its two Pbar tiles
-// per wave cover 4 x 4 ray x slot blocks), the 16-wave one the others
+// per wave cover 4 x 4 ray x slot blocks), the 12-wave one the others
 static bool adj_small(const Layout& L) { return L.NRB * (kKG / 32) <= 2 * kWaves; }
 size_t adj_item_lds_bytes(const Layout& L) {
-  return carve(L, make_grad_acc(L.NP), adj_small(L) ? kWaves : 2 * kWaves, nullptr, nullptr);
+  return carve(L, make_grad_acc(L.NP), adj_small(L) ? kWaves : kWavesL, nullptr, nullptr);
 }
 
 void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {
@@ -869,13 +859,13 @@ hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return hipSuccess;
   const size_t lds = adj_item_lds_bytes(a.L);
   const bool small = adj_small(a.L);
-  const void* fn = small ? (const void*)k_adj_item<2, kWaves> : (const void*)k_adj_item<2, 2 * kWaves>;
+  const void* fn = small ? (const void*)k_adj_item<2, kWaves> : (const void*)k_adj_item<3, kWavesL>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (small)
     hipLaunchKernelGGL((k_adj_item<2, kWaves>), dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
   else
-    hipLaunchKernelGGL((k_adj_item<2, 2 * kWaves>), dim3(B_grid, a.n_items), dim3(128 * kWaves), lds, s, a);
+    hipLaunchKernelGGL((k_adj_item<3, kWavesL>), dim3(B_grid, a.n_items), dim3(64 * kWavesL), lds, s, a);
   return hipGetLastError();
 }
 
