@@ -29,8 +29,9 @@
 // constraint; log10 parameters) in reverse, in FP64.
 //
 // The work item is one model over a group of consecutive 64-column spans;
-// its products run on v_mfma_f32_32x32x2_f32 (FP32 operands, P rounded from
-// FP64), Pbar is accumulated in registers over the item's spans and each
+// its products take FP32 operands (P rounded from FP64) split into three
+// bf16 pieces on v_mfma_f32_32x32x16_bf16 (FP32 accuracy), Pbar is
+// accumulated in registers over the item's spans and each
 // item writes its partial sums once; a per-model kernel adds them in a
 // fixed order in FP64.  The result is held to 1e-4 of the FP64 reference
 // gradient.

@@ -101,7 +101,7 @@ struct Layout {
   // gradient layouts only (0 otherwise); the gradient takes models of at
   // most kKG opacity slots:
   int64_t off_lwd64;       // [NP][8] FP64 d(record weight)/dT at fixed P
-  int64_t off_pa;          // P (FP32) as v_mfma_f32_32x32x2_f32 A fragments, rows = rays: [NRB][kKG/16][64][8]
+  int64_t off_pa;          // P (FP32), rows = rays: [NRB][kKG/16][64][8], lane l, step i: k = 2 i + l/32
   int64_t off_pt;          // P^T as A fragments, rows = slots: [kKG/32][NP/16][64][8]
   int32_t grad;
   int64_t slab;            // bytes per model (multiple of 256)
