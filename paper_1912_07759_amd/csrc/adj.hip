@@ -358,8 +358,9 @@ void k_adj_item(AdjArgs a) {
     // over the nonzero 16-slot blocks; then taubar, Abar, PRbar and Rbar
     for (int t = wave; t < 2 * nrb; t += NW) {
       const int rb = t >> 1, tcb = t & 1;
-      // nonzero slot blocks of the ray block, the next one's fragment
-      // loaded before the current products
+      // nonzero slot blocks of the ray block (each block's fragment loaded
+      // at its turn: prefetching the next one costs more in spilled
+      // registers than it hides)
       uint64_t m = hd->kq_mask[rb] & ((nkq < 64 ? (1ull << nkq) : 0ull) - 1ull);
       f32x16 tau = f32x16{};
       auto afrag = [&](int kq, u32x4& x0, u32x4& x1) {
@@ -367,13 +368,12 @@ void k_adj_item(AdjArgs a) {
         x0 = fp[0];
         x1 = fp[1];
       };
-      u32x4 a0{}, a1{}, n0{}, n1{};
+      u32x4 a0{}, a1{};
       int kq = m ? __builtin_ctzll(m) : -1;
-      if (kq >= 0) afrag(kq, a0, a1);
       while (kq >= 0) {
         m &= m - 1;
         const int kn = m ? __builtin_ctzll(m) : -1;
-        if (kn >= 0) afrag(kn, n0, n1);
+        afrag(kq, a0, a1);
         float av[8], bv[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -381,8 +381,6 @@ void k_adj_item(AdjArgs a) {
           bv[i] = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
         }
         tau = mfma_block(av, bv, tau);
-        a0 = n0;
-        a1 = n1;
         kq = kn;
       }
       const int c = 32 * tcb + lc;
@@ -440,8 +438,7 @@ void k_adj_item(AdjArgs a) {
     const bool has_mb = wave < 2 * nqb;
     if (has_mb) {
       const int qb = wave >> 1, tcb = wave & 1;
-      // 16-ray blocks with a nonzero product, the next one's fragment loaded
-      // before the current products
+      // 16-ray blocks with a nonzero product
       uint32_t jm = 0;
       for (int jb = 0; jb < 2 * nrb; ++jb)
         if ((hd->kq_mask[jb >> 1] >> (2 * qb)) & 3) jm |= 1u << jb;
@@ -450,13 +447,12 @@ void k_adj_item(AdjArgs a) {
         x0 = fp[0];
         x1 = fp[1];
       };
-      u32x4 a0{}, a1{}, n0{}, n1{};
+      u32x4 a0{}, a1{};
       int jb = jm ? __builtin_ctz(jm) : -1;
-      if (jb >= 0) tfrag(jb, a0, a1);
       while (jb >= 0) {
         jm &= jm - 1;
         const int jn = jm ? __builtin_ctz(jm) : -1;
-        if (jn >= 0) tfrag(jn, n0, n1);
+        tfrag(jb, a0, a1);
         float av[8], bv[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -464,8 +460,6 @@ void k_adj_item(AdjArgs a) {
           bv[i] = s.tbar[(16 * jb + 2 * i + hl) * kLd + 32 * tcb + lc];
         }
         mb = mfma_block(av, bv, mb);
-        a0 = n0;
-        a1 = n1;
         jb = jn;
       }
     }
