@@ -59,13 +59,17 @@ typedef enum {
   TRX_E_UNSUPPORTED = 4    /* valid request outside what is built */
 } trx_status;
 
-/* Arithmetic of the opacity and optical-depth steps.  Geometry, altitude and
- * the final depth assembly are FP64 in every mode.
- *  TRX_FP64         FP64 tables, FP64 opacity, FP64 contraction (reference).
- *  TRX_FP32         FP32 tables and opacity, FP32 matrix-core contraction with
- *                   the path lengths split into FP32 hi + lo parts.
- *  TRX_BF16_SPLIT2  FP32 opacity; path lengths and opacity each split into
- *                   two bf16 parts, three bf16 matrix-core products
+/* Arithmetic of the opacity, optical-depth and depth steps.  Pressure grid,
+ * chemistry, altitudes and path lengths are FP64 in every mode, and so are
+ * the per-model products P = dl x (interpolation weights) that the matrix
+ * cores contract with the mixed cross-sections.
+ *  TRX_FP64         FP64 tables, opacity, contraction and depth (reference).
+ *  TRX_FP32         FP32 tables and mixing, FP32 matrix-core contraction with
+ *                   P split into FP32 hi + lo parts; the annulus terms
+ *                   A_j (1 - e^-tau_j) summed in FP32, added to (Rp/Rs)^2 in
+ *                   FP64 (so for the two modes below).
+ *  TRX_BF16_SPLIT2  FP32 mixing; P and the mixed cross-sections each split
+ *                   into two bf16 parts, three bf16 matrix-core products
  *                   (hi*hi + hi*lo + lo*hi) with FP32 accumulation.
  *  TRX_BF16_SPLIT3  three bf16 parts each, six products (~FP32 accuracy). */
 typedef enum {
@@ -201,6 +205,14 @@ trx_status trx_forward(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch
  *  depth_binned DEVICE [B][n_ch] or NULL
  *  recompute  1: the opacity and optical depth are recomputed in the
  *             backward pass instead of stored (the only mode built).
+ * `precision` is the arithmetic of the forward pass, i.e. of the residual
+ * D - obs (TRX_FP64 holds the gradient to 1e-4 of the FP64 reference near
+ * the optimum, where the residual is at the noise level); the backward
+ * contractions take FP32 operands split into bf16 pieces (FP32 accuracy)
+ * and the layer-level adjoints are FP64.  A model with more than 128
+ * opacity slots (distinct table corners it interpolates from, plus CIA
+ * temperature nodes) is flagged TRX_MODEL_GRAD_UNSUPPORTED with NaN
+ * gradient outputs.
  * Derivatives at table nodes and under clamps are one-sided (the lower
  * bracket's slope; zero under a clamp).  The binned spectrum must cover
  * every channel in each model's window, else that model's chi2 is NaN. */
@@ -283,7 +295,7 @@ trx_status trx_profile_read(trx_ctx* ctx, int32_t kernel, double* total_ms, int3
  * JSON object of strings).  Synchronises the context's stream. */
 trx_status trx_autotune(trx_plan* p, const trx_batch* batch, const char* cache_json);
 /* Set the variant directly from a string as returned by trx_plan_describe
- * ("persistent=1 group=32"; unknown keys are an error). */
+ * ("persistent=1 group=0 spans=8"; unknown keys are an error). */
 trx_status trx_plan_set_variant(trx_plan* p, const char* variant);
 /* Current variant of a plan as a short printable string (owned by the
  * plan, valid until the next call on it). */
