@@ -183,3 +183,53 @@ def test_plan_errors(gpu_ctx, ragged):
     plan.close()
     bins.close()
     T.close()
+
+
+class _DeviceArray:
+    """A device buffer owned by the library, seen by torch without a copy."""
+
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2}
+
+
+class _OwnBatch:
+    def __init__(self, c, B):
+        self.c, self.B = c, B
+
+    def cstruct(self):
+        return self.c
+
+
+def test_plan_owned_input_buffers(gpu_ctx, ragged):
+    """trx_plan_batch: the plan's own device input buffers (B_max models of
+    N_max layers, default constants), filled by the caller with a batch of
+    fewer models, give the same result as the caller's own buffers."""
+    import ctypes
+    from paper_1912_07759_amd import trx
+    tables, batch, ch = ragged
+    T, bins, db = _setup(gpu_ctx, tables, batch, ch)
+    plan = trx.Plan(gpu_ctx, T, bins, B_max=16, N_max=200, precision="bf16x2", graph=True)
+    own = trx.BatchC()
+    gpu_ctx.check(trx.lib().trx_plan_batch(plan.h, ctypes.byref(own)))
+    assert own.B == 16 and own.max_layers == 200 and own.gravity == 0
+    assert own.he_h2_ratio == 0.17 and own.k_B == 1.380649e-23 and own.amu_kg == 1.66053906660e-27
+    for name, src, ts in (("n_layers", db.n_layers, "<i4"), ("layer_off", db.layer_off, "<i8"),
+                          ("T_K", db.T, "<f8"), ("p_bot_Pa", db.p_bot, "<f8"),
+                          ("p_top_Pa", db.p_top, "<f8"), ("log10_vmr", db.log10_vmr, "<f8"),
+                          ("Rp_m", db.Rp, "<f8"), ("Rs_m", db.Rs, "<f8"), ("GM_m3s2", db.GM, "<f8"),
+                          ("wn_lo", db.wn_lo, "<i4"), ("wn_hi", db.wn_hi, "<i4")):
+        dst = torch.as_tensor(_DeviceArray(getattr(own, name), src.numel(), ts), device="cuda")
+        dst.copy_(src.reshape(-1))
+    own.B, own.max_layers = db.B, db.max_layers
+    own.he_h2_ratio, own.k_B, own.amu_kg, own.gravity = db.he_h2, db.k_B, db.amu, db.gravity
+    nat, binned, st = plan.launch(_OwnBatch(own, db.B), native=True)
+    nat, binned, st = nat.cpu().numpy(), binned.cpu().numpy(), st.cpu().numpy()
+    ref_nat, ref_binned, ref_st = trx.forward(gpu_ctx, T, db, bins, "bf16x2")
+    gpu_ctx.synchronize()
+    plan.close()
+    bins.close()
+    T.close()
+    assert np.array_equal(st, ref_st.cpu().numpy()) and np.all(st == 0)
+    assert np.array_equal(nat, ref_nat.cpu().numpy(), equal_nan=True)
+    assert np.array_equal(binned, ref_binned.cpu().numpy(), equal_nan=True)
