@@ -330,7 +330,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched "
-              "path shards by model across GPUs with no exchange, which this build does "
+              "path shards by model across GPUs with no exchange, which this benchmark does "
               "not launch.", file=sys.stderr)
         sys.exit(2)
     import torch

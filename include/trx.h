@@ -93,7 +93,7 @@ enum {
                                      outputs are NaN */
 };
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define TRX_MAX_LAYERS_FP64 1024 /* TRX_FP64 */
 #define TRX_MAX_LAYERS_MFMA 224  /* the matrix-core modes */
 #define TRX_MAX_ABSORBERS 32
