@@ -190,10 +190,17 @@ typedef struct {
  *                inside each model's window are written.
  *  depth_binned  DEVICE [B][n_ch] or NULL (requires bins).
  *  model_status  DEVICE [B], required.
+ *  tau           DEVICE [B][max_layers][n_wn] or NULL: the optical depth
+ *                tau[b][j][i] of the chord at impact altitude z_j (ray j,
+ *                j < n_layers[b]) at native point i, total of all
+ *                contributions (equation tot_opt_dpth), written for the
+ *                points of each model's window only; FP64 in TRX_FP64, the
+ *                FP32 accumulator of the matrix product in the other modes.
  * Returns TRX_E_UNSUPPORTED if max_layers exceeds the mode's limit. */
 trx_status trx_forward(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch,
                        const trx_bins* bins, trx_precision precision,
-                       double* depth_native, double* depth_binned, int32_t* model_status);
+                       double* depth_native, double* depth_binned, int32_t* model_status,
+                       double* tau);
 
 /* chi^2 = sum_c ((D_c - obs_c)/sigma_c)^2 and its gradient, per model.
  *  obs        DEVICE [B][n_ch]; sigma DEVICE [n_ch] (> 0).

@@ -357,7 +357,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
                                 const int32_t* B_dev, int max_layers, const trx_bins* bins,
                                 int precision, const RunConfig& rc, uint8_t* ws, void* aws,
                                 const SchedBufs& sb, double* depth_native, double* depth_binned,
-                                int32_t* status, bool grad_layout) {
+                                int32_t* status, bool grad_layout, double* tau) {
   const Layout L = make_layout(max_layers, precision, grad_layout, t->dev);
   GeomArgs g;
   g.bt = db;
@@ -395,6 +395,8 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   f.depth_native = depth_native;
   f.aws = aws;
   f.model_status = status;
+  f.tau = tau;
+  f.tau_ld = (int64_t)max_layers * t->dev.n_wn;
   f.order = sb.order;
   f.mspan = sb.mspan;
   f.qcount = sb.qcount;
@@ -512,7 +514,7 @@ RunConfig trx::default_config(int precision, int max_layers) {
 
 extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_batch* bt,
                                   const trx_bins* bins, trx_precision precision, double* depth_native,
-                                  double* depth_binned, int32_t* model_status) {
+                                  double* depth_binned, int32_t* model_status, double* tau) {
   if (!c) return TRX_E_INVALID_ARG;
   c->err.clear();
   trx_status s = check_batch(c, t, bt, precision);
@@ -529,7 +531,7 @@ extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_bat
   RunConfig rc = default_config(precision, bt->max_layers);
   return enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision, rc,
                          (uint8_t*)c->ws.ptr, c->aws.ptr, SchedBufs::carve(c->sched.ptr, bt->B),
-                         depth_native, depth_binned, model_status);
+                         depth_native, depth_binned, model_status, false, tau);
 }
 
 // --------------------------------------------------------------------------

@@ -79,6 +79,9 @@ __device__ inline void stage64(const double* tab, int64_t abs_stride, int W, int
   }
 }
 
+// TAU: also write the optical depth of every ray and column to a.tau (a
+// separate instantiation: the stores cost the kernel registers)
+template <bool TAU>
 __device__ void process64(const FwdArgs& a, int b_in, int span_in, Smem64& sm) {
   const int b = __builtin_amdgcn_readfirstlane(b_in);
   const int span = __builtin_amdgcn_readfirstlane(span_in);
@@ -208,6 +211,10 @@ __device__ void process64(const FwdArgs& a, int b_in, int span_in, Smem64& sm) {
           for (int q = 0; q < 4; ++q) {
             const int j = 16 * rb + (lane >> 4) + 4 * q;
             s = fma(A[j], -expm1(-acc[r][cb][q]), s);
+            if constexpr (TAU) {
+              const int cg = col0 + 16 * cb + (lane & 15);
+              if (j < N && cg >= lo && cg < hi) a.tau[(int64_t)b * a.tau_ld + (int64_t)j * W + cg] = acc[r][cb][q];
+            }
           }
           s += __shfl_xor(s, 16, 64);
           s += __shfl_xor(s, 32, 64);
@@ -237,11 +244,12 @@ __device__ void process64(const FwdArgs& a, int b_in, int span_in, Smem64& sm) {
   __syncthreads();
 }
 
+template <bool TAU>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd64(FwdArgs a) {
   __shared__ Smem64 sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
-  process64(a, blockIdx.x, blockIdx.y, sm);
+  process64<TAU>(a, blockIdx.x, blockIdx.y, sm);
 }
 
 
@@ -293,6 +301,7 @@ __device__ inline void mix64(const double* tab, int64_t stride, int nt, const do
   }
 }
 
+template <bool TAU>
 __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, Smem64s& sm) {
   const int b = __builtin_amdgcn_readfirstlane(b_in);
   const Layout& L = a.L;
@@ -425,8 +434,13 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int j = 16 * r16 + (lane >> 4) + 4 * q;
-              s = fma(sm.A[j], exp(-fma(sm.PR[j], Rc, acc[r][cb][q])), s);
+              const double tau = fma(sm.PR[j], Rc, acc[r][cb][q]);
+              s = fma(sm.A[j], exp(-tau), s);
               sa = fma(sm.A[j], 1.0, sa);
+              if constexpr (TAU) {
+                const int cg = col0 + c;
+                if (j < N && cg >= lo && cg < hi) a.tau[(int64_t)b * a.tau_ld + (int64_t)j * W + cg] = tau;
+              }
             }
             s += __shfl_xor(s, 16, 64);
             s += __shfl_xor(s, 32, 64);
@@ -450,11 +464,12 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
   }
 }
 
+template <bool TAU>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd64s(FwdArgs a) {
   __shared__ Smem64s sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
-  process64s(a, blockIdx.x, blockIdx.y * kS64, blockIdx.y * kS64 + kS64, sm);
+  process64s<TAU>(a, blockIdx.x, blockIdx.y * kS64, blockIdx.y * kS64 + kS64, sm);
 }
 
 }  // namespace
@@ -462,10 +477,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd64s(FwdArgs a) {
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   const int spans = (a.tab.n_wn + kCols - 1) / kCols;
-  if (a.L.slot64)
-    hipLaunchKernelGGL(k_fwd64s, dim3(B_grid, (spans + kS64 - 1) / kS64), dim3(64 * kWaves), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_fwd64, dim3(B_grid, spans), dim3(64 * kWaves), 0, s, a);
+  if (a.L.slot64) {
+    const dim3 grid(B_grid, (spans + kS64 - 1) / kS64);
+    if (a.tau)
+      hipLaunchKernelGGL(k_fwd64s<true>, grid, dim3(64 * kWaves), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_fwd64s<false>, grid, dim3(64 * kWaves), 0, s, a);
+  } else if (a.tau) {
+    hipLaunchKernelGGL(k_fwd64<true>, dim3(B_grid, spans), dim3(64 * kWaves), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_fwd64<false>, dim3(B_grid, spans), dim3(64 * kWaves), 0, s, a);
+  }
 }
 
 }  // namespace trx

@@ -177,7 +177,9 @@ __device__ inline void mix_corners(const float* wt, int nt, int t0, const float 
 
 // One work item: model b, columns [64 s_first, 64 s_end) cut to its window.
 // Called by all threads of the workgroup (every early return is uniform).
-template <int MODE, int RBW>
+// TAU: also write the optical depth of every ray and column to a.tau (a
+// separate instantiation: the stores cost the hot kernel registers)
+template <int MODE, int RBW, bool TAU>
 __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end, Smem<MODE, RBW>& sm) {
   using C = Cfg<MODE, RBW>;
   constexpr int npc = C::npc, kAW = C::kAW, KB = C::KB;
@@ -498,7 +500,14 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
             const float2 w = sm.aw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)];
-            s = fmaf(w.x, __builtin_amdgcn_exp2f(fmaf(w.y, Rc, acc[r][tcb][q])), s);
+            const float x = fmaf(w.y, Rc, acc[r][tcb][q]);   // -tau / ln 2
+            s = fmaf(w.x, __builtin_amdgcn_exp2f(x), s);
+            if constexpr (TAU) {
+              const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
+              const int cg = span * kCols + cl;
+              if (j < N && cg >= lo && cg < hi)
+                a.tau[(int64_t)b * a.tau_ld + (int64_t)j * W + cg] = -0.69314718055994531 * (double)x;
+            }
           }
           s += __shfl_xor(s, 32, 64);
           if (hl == 0) sm.part[rb][cl] = awsum[r] - s;
@@ -522,13 +531,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 }
 
 // One workgroup per (model, span).
-template <int MODE, int RBW>
+template <int MODE, int RBW, bool TAU>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
   __shared__ Smem<MODE, RBW> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
   const int S = a.span_group;
-  process<MODE, RBW>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
+  process<MODE, RBW, TAU>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
 }
 
 // Persistent: a fixed grid pops chunks of (span, model) items from kQueues
@@ -579,7 +588,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
+        if (bm >= 0) process<MODE, RBW, false>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
       }
       __syncthreads();
     }
@@ -599,14 +608,18 @@ int occupancy() {
   return blocks;
 }
 
+// The optical-depth output always takes the one-workgroup-per-item kernel.
 template <int MODE, int RBW>
 void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
-  if (a.persistent) {
+  if (a.persistent && !a.tau) {
     const int grid = n_cu * occupancy<MODE, RBW>();
     hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW>), dim3(grid), dim3(64 * kWaves), 0, s, a);
   } else {
     dim3 grid(B_grid, ((a.tab.n_wn + kCols - 1) / kCols + a.span_group - 1) / a.span_group);
-    hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW>), grid, dim3(64 * kWaves), 0, s, a);
+    if (a.tau)
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true>), grid, dim3(64 * kWaves), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false>), grid, dim3(64 * kWaves), 0, s, a);
   }
 }
 

@@ -101,7 +101,8 @@ RunConfig default_config(int precision, int max_layers);
 trx_status enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B, const int32_t* B_dev,
                            int max_layers, const trx_bins* bins, int precision, const RunConfig& rc,
                            uint8_t* ws, void* aws, const SchedBufs& sb, double* depth_native,
-                           double* depth_binned, int32_t* status, bool grad_layout = false);
+                           double* depth_binned, int32_t* status, bool grad_layout = false,
+                           double* tau = nullptr);
 
 size_t grad_scratch_bytes(int B, int n_wn, int n_ch, int NP);
 // Forward pass on the gradient layout, chi^2, and the adjoint kernels.

@@ -245,6 +245,8 @@ struct FwdArgs {
   double* depth_native;   // [B][n_wn] or null
   void* aws;              // [B][n_wn] atmospheric part a/Rs^2 (double for FP64, else float)
   int32_t* model_status;  // [B]
+  double* tau;            // [B][tau_ld] optical depth tau[b][j][column] (rows j < N, window columns), or null
+  int64_t tau_ld;         // max_layers * n_wn
   // persistent scheduling: queue q holds the items (model, span) of the
   // spans s = q (mod kQueues); the models in order[] (layer count
   // descending) are taken in groups of `group`, each group over the queue's

@@ -258,9 +258,11 @@ def _prec(p):
 
 
 def forward(ctx, tables, batch, bins=None, precision=FP64, native=True, binned=True,
-            out_native=None, out_binned=None, out_status=None):
+            out_native=None, out_binned=None, out_status=None, out_tau=None):
     """trx_forward.  Returns (depth_native [B, n_wn] or None,
-    depth_binned [B, n_ch] or None, model_status [B])."""
+    depth_binned [B, n_ch] or None, model_status [B]).  With out_tau (a
+    float64 device tensor [B, max_layers, n_wn]) the optical depth of every
+    ray j < N inside each model's window is written there as well."""
     dev = batch.T.device
     B = batch.B
     if native and out_native is None:
@@ -277,7 +279,8 @@ def forward(ctx, tables, batch, bins=None, precision=FP64, native=True, binned=T
     bc = batch.cstruct()
     ctx.check(lib().trx_forward(ctx.h, tables.h, ctypes.byref(bc),
                                 bins.h if bins is not None else None, _prec(precision),
-                                _ptr(out_native), _ptr(out_binned), _ptr(out_status)))
+                                _ptr(out_native), _ptr(out_binned), _ptr(out_status),
+                                _ptr(out_tau)))
     return out_native, out_binned, out_status
 
 

@@ -32,6 +32,8 @@ def oracle_batch(tables, batch, channels, precision, models=None):
 
 def native_rel_err(gpu_native_row, ref, lo, hi):
     g = np.asarray(gpu_native_row)[lo:hi]
+    # a NaN would drop out of the callers' max(): reject it here
+    assert np.all(np.isfinite(g)), "non-finite native depth inside the window"
     return float(np.max(np.abs(g - ref) / np.abs(ref)))
 
 

@@ -12,6 +12,7 @@ import pytest
 from synth.atmosphere import guillot_T, log_midpoint_pressures, log_uniform_channels
 from synth.constants import GM_JUP, R_JUP, R_SUN
 from synth.workloads import Channels, batch_from_models, make_tables
+import oracle
 from parity_util import TOL, binned_rel_err, native_rel_err, oracle_batch
 
 pytestmark = pytest.mark.gpu
@@ -152,3 +153,28 @@ def test_many_opacity_slots(gpu_ctx, tables, mode):
     worst = _check(t, batch, ch, mode, nat, binned, st)
     print(f"{mode}: many opacity slots worst rel err {worst:.2e}")
     assert worst <= TOL[mode]
+
+
+def test_optical_depth_output_long_fp64(gpu_ctx, tables):
+    """The optical-depth output of the FP64 layer kernel (models beyond
+    TRX_MAX_LAYERS_MFMA layers): 300 layers against the oracle's tau."""
+    import torch
+    from paper_1912_07759_amd import trx
+    t = tables
+    batch = batch_from_models([_profile(300)], 1e6, 1e-4, np.array([[-4.0, -5.0, -6.0, -3.5, -7.0]]),
+                              R_JUP, R_SUN, GM_JUP, [40], [t.n_wn - 7])
+    T = trx.Tables.from_synth(gpu_ctx, t)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=300)
+    tau = torch.full((1, 300, t.n_wn), float("nan"), dtype=torch.float64, device="cuda")
+    _, _, st = trx.forward(gpu_ctx, T, db, None, "fp64", out_tau=tau)
+    gpu_ctx.synchronize()
+    T.close()
+    assert int(st[0]) == 0
+    g = tau[0].cpu().numpy()
+    ref = oracle.forward_model(batch.model(0), t, None, keep=True)["tau"]
+    got = g[:, 40:t.n_wn - 7]
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    assert np.all(np.isfinite(got)) and not np.any(np.isnan(err))
+    assert np.all(np.isnan(g[:, :40])) and np.all(np.isnan(g[:, t.n_wn - 7:]))
+    print(f"fp64 300 layers: optical depth worst rel err {err.max():.2e}")
+    assert err.max() <= 1e-12

@@ -117,3 +117,48 @@ def test_tables_beyond_32bit_row_offsets_rejected(gpu_ctx):
     rc = trx.lib().trx_tables_create(gpu_ctx.h, ctypes.byref(d), ctypes.byref(h))
     assert rc == 4, trx.lib().trx_last_error(gpu_ctx.h)
     assert not h.value
+
+
+# observed: 1.2e-14, 3.9e-7, 2.3e-5, 5.4e-7
+TAU_TOL = {"fp64": 1e-12, "fp32": 2e-6, "bf16x2": 1e-4, "bf16x3": 2e-6}
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_optical_depth_output(gpu_ctx, mode):
+    """trx_forward's optical-depth output on a ragged batch: tau[j, i] of
+    every ray against the oracle's (equation tot_opt_dpth), element by
+    element inside each model's window; nothing written past N or outside
+    the window; the depth outputs are the same bits as without it."""
+    import torch
+    import oracle
+    from paper_1912_07759_amd import trx
+    tables, batch, ch = make_config(3, n_wn=1200, n_lines=100, B=4)
+    T = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, T, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=200)
+    tau = torch.full((batch.B, 200, tables.n_wn), float("nan"), dtype=torch.float64, device="cuda")
+    nat, binned, st = trx.forward(gpu_ctx, T, db, bins, mode, out_tau=tau)
+    nat0, binned0, _ = trx.forward(gpu_ctx, T, db, bins, mode)
+    gpu_ctx.synchronize()
+    tau = tau.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    assert np.array_equal(nat.cpu().numpy(), nat0.cpu().numpy(), equal_nan=True)
+    assert np.array_equal(binned.cpu().numpy(), binned0.cpu().numpy(), equal_nan=True)
+    worst = 0.0
+    for b in range(batch.B):
+        N = int(batch.n_layers[b])
+        lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+        ref = oracle.forward_model(batch.model(b), tables, ch, keep=True)["tau"]
+        g = tau[b, :N, lo:hi]
+        assert np.all(np.isfinite(g))
+        # the top ray's chord is zero (its impact altitude is the top
+        # boundary): tau = 0 there on both sides
+        err = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-300)
+        assert not np.any(np.isnan(err))
+        worst = max(worst, float(np.max(err)))
+        assert np.all(np.isnan(tau[b, N:])) and np.all(np.isnan(tau[b, :N, :lo]))
+        assert np.all(np.isnan(tau[b, :N, hi:]))
+    print(f"{mode}: optical depth worst rel err {worst:.2e}")
+    bins.close()
+    T.close()
+    assert worst <= TAU_TOL[mode]

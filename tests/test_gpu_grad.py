@@ -43,6 +43,7 @@ def _gpu(ctx, tables, batch, ch, obs, sigma, precision, T=None):
 
 def _grad_err(g, ref):
     v = np.concatenate([g["dT"], g["dlog10_vmr"], [g["dRp"]]])
+    assert np.all(np.isfinite(v)), "non-finite gradient"
     r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
     norm = np.linalg.norm(v - r) / np.linalg.norm(r)
     big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
