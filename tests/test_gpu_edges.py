@@ -178,3 +178,56 @@ def test_optical_depth_output_long_fp64(gpu_ctx, tables):
     assert np.all(np.isnan(g[:, :40])) and np.all(np.isnan(g[:, t.n_wn - 7:]))
     print(f"fp64 300 layers: optical depth worst rel err {err.max():.2e}")
     assert err.max() <= 1e-12
+
+
+def _no_absorber_tables(t):
+    """The same grid with no absorbers: CIA and the H2 and He Rayleigh rows only."""
+    return dataclasses.replace(t, xsec=np.zeros((0,) + t.xsec.shape[1:]), abs_mass=np.zeros(0),
+                               cia_pair=t.cia_pair - t.n_abs, rayleigh=t.rayleigh[t.n_abs:], names=[])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_no_absorbers(gpu_ctx, tables, mode):
+    """Tables without absorbers (n_abs = 0; the fill gases' CIA and Rayleigh
+    only): forward against the oracle, a full and a partial window."""
+    t = _no_absorber_tables(tables)
+    Ts = [_profile(60), _profile(150, 1700.0)]
+    batch = batch_from_models(Ts, 1e6, 1e-4, np.zeros((2, 0)), R_JUP, R_SUN, GM_JUP, [0, 90], [t.n_wn, 600])
+    ch = _channels(t)
+    nat, binned, st = _run(gpu_ctx, t, batch, ch, mode, 200)
+    worst = _check(t, batch, ch, mode, nat, binned, st)
+    print(f"{mode}: no absorbers worst rel err {worst:.2e}")
+    assert worst <= TOL[mode]
+
+
+def test_no_absorbers_gradient(gpu_ctx, tables):
+    """chi^2 gradient (FP64 forward) with tables without absorbers: d/dT and
+    d/dRp against the oracle's reference gradient; no mixing-ratio outputs."""
+    from paper_1912_07759_amd import trx
+    t = _no_absorber_tables(tables)
+    Ts = [_profile(60), _profile(100, 1500.0)]
+    batch = batch_from_models(Ts, 1e6, 1e-4, np.zeros((2, 0)), R_JUP, R_SUN, GM_JUP, 0, t.n_wn)
+    ch = _channels(t)
+    refs = [oracle.forward_model(batch.model(b), t, ch)["binned"] for b in range(2)]
+    sigma = np.full(len(ch.lo), 50e-6)
+    obs = np.stack([r * (1.0 + 2e-4 * np.sin(np.arange(len(ch.lo)) + b)) for b, r in enumerate(refs)])
+    Tt = trx.Tables.from_synth(gpu_ctx, t)
+    bins = trx.Bins(gpu_ctx, Tt, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=100)
+    out = trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, sigma, "fp64")
+    g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    bins.close()
+    Tt.close()
+    assert np.all(g["status"] == 0), g["status"]
+    off = batch.layer_off
+    for b in range(2):
+        ref = oracle.chi2_and_grad(batch.model(b), t, ch, obs[b], sigma)
+        assert abs(g["chi2"][b] - ref["chi2"]) <= 1e-5 * ref["chi2"]
+        v = np.concatenate([g["dT"][off[b]:off[b + 1]], [g["dRp"][b]]])
+        r = np.concatenate([ref["dT"], [ref["dRp"]]])
+        assert np.all(np.isfinite(v))
+        norm = np.linalg.norm(v - r) / np.linalg.norm(r)
+        big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
+        comp = float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big])))
+        print(f"no absorbers model {b}: grad norm err {norm:.2e} comp err {comp:.2e}")
+        assert norm <= 1e-4 and comp <= 1e-4
