@@ -302,9 +302,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     f32x16 acc[RBW][2];
     auto run_chunk = [&](const int c0, auto first_t) {
       constexpr bool first = decltype(first_t)::value;
-      // tables per load batch (two batches in flight): 6 when the
-      // accumulators are not live, else 2
-      constexpr int SA = first ? 6 : 2;
+      // tables per load batch (two batches in flight): 5 when the
+      // accumulators are not live (6 spills registers), else 2
+      constexpr int SA = first ? 5 : 2;
       const int nq = (min(kKC, K - c0) + 15) >> 4;
       const int kqa = c0 >> 4;
       if (K > kKC) {
