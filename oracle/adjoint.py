@@ -11,9 +11,9 @@ absorbers (the log10 parameter space of the Optimization section; the fill
 gases respond through the sum constraint) and the planet radius.
 
 It walks the forward steps in reverse: binning, depth, exp and annulus sum,
-the chord contraction, the opacity (bracket slopes in T, number density,
-mixing ratios), the chord geometry, the altitude recursion and the
-chemistry.  Derivatives at table nodes and under clamps are one-sided: the
+the chord contraction, the cloud deck's contribution, the opacity (bracket
+slopes in T, number density, mixing ratios), the chord geometry, the
+altitude recursion and the chemistry.  Derivatives at table nodes and under clamps are one-sided: the
 lower-closed bracket's slope, zero under a clamp (reading A16).
 
 Pinned by complex-step differentiation of ``oracle.forward`` (agreement to
@@ -89,10 +89,22 @@ def chi2_and_grad(m, tables, channels, obs, sigma):
     dl_bar = np.triu(tau_bar @ kappa.T)
     kappa_bar = dl.T @ tau_bar
 
+    # cloud deck: tau += tau_c[:, None], tau_c = dl @ kappa_c, kappa_c =
+    # sigma rho on the deck (d rho/dT = -rho/T; the deck's layers are fixed
+    # by the pressure grid, so its bounds have no derivative).  An opaque
+    # deck has none either: its rays have e^-tau = 0 and the others no path
+    # through it.
+    kappa_c = f["kappa_c"]
+    cT_bar = np.zeros(N)
+    if kappa_c is not None and np.isfinite(m["cloud_sigma"]):
+        tc_bar = np.sum(tau_bar, axis=1)                     # [N]
+        dl_bar += np.triu(np.outer(tc_bar, kappa_c))
+        cT_bar = (dl.T @ tc_bar) * (-kappa_c / T)
+
     # opacity
     n = number_density(P, T, kB)
     lp = np.log10(P)
-    T_bar = np.zeros(N)
+    T_bar = cT_bar.copy()
     chi_bar = np.zeros(n_abs + 2)
     for l in range(N):
         kb = kappa_bar[l]

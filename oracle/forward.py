@@ -44,6 +44,11 @@ design notes):
   A14 chi^2 = sum_c ((D_c - O_c)/sigma_c)^2.
   A18 Rayleigh applies to every species (absorbers, H2, He); CIA pairs are
       given by species ids (absorbers 0..n_abs-1, then H2, then He).
+  A19 the flat-opacity cloud deck (equation clouds) is sigma rho on the
+      layers whose centre pressure lies between the two deck pressures
+      (bounds included, either order); sigma = +inf is the fully opaque
+      deck, whose optical depth is +inf on every ray with a nonzero path
+      through it.
 
 Pins (tests/test_oracle_pins.py): zero opacity gives (Rp/Rs)^2 exactly; the
 opaque limit equals the closed-form trapezoid sum; the constant-g isothermal
@@ -253,6 +258,35 @@ def opacity(T, P, chi_abs, chi_h2, chi_he, tables, k_B, lo, hi,
     return kappa
 
 
+def cloud_opacity(P, T, k_B, sigma, p_top, p_bottom):
+    """Equation clouds: a flat (wavenumber-independent) cross-section sigma
+    (m^2) on the layers inside the deck and zero outside, entering the path
+    integral with the number density like absorption (w = 1), so the deck
+    adds kappa_c[l] = sigma rho_l (m^-1).  Reading A19: the deck is
+    discretised on the layer-centre pressures and takes the layers with
+    min(p_top, p_bottom) <= P_l <= max(p_top, p_bottom) (the equation and
+    the text name the two bounds in opposite orders).  sigma = +inf is the
+    fully opaque deck of the Retrievals section.
+    """
+    lo_p, hi_p = min(p_top, p_bottom), max(p_top, p_bottom)
+    deck = (np.real(P) >= lo_p) & (np.real(P) <= hi_p)
+    if np.isinf(sigma):
+        return np.where(deck, np.inf, 0.0), deck
+    n = number_density(P, T, k_B)
+    return np.where(deck, sigma * n, 0.0 * n), deck
+
+
+def cloud_optical_depth(dl, kappa_c, deck, sigma):
+    """The deck's own line-of-sight integral per ray, tau_c[j] =
+    sum_{k >= j} dl[j, k] kappa_c[k] (equation tot_opt_dpth sums the
+    contributions' integrals).  For sigma = +inf this is the limit: +inf
+    for a ray with a nonzero path through the deck, zero otherwise."""
+    if np.isinf(sigma):
+        col = np.real(dl) @ deck.astype(np.float64)
+        return np.where(col > 0.0, np.inf, 0.0)
+    return dl @ kappa_c
+
+
 def optical_depth(dl, kappa):
     """tau[j, w] = sum_{k >= j} dl[j, k] kappa[k, w]: the line-of-sight
     integral of equation opt_dpth for the ray at altitude z_j, with each
@@ -307,7 +341,9 @@ def bin_spectrum(D, w):
 def forward_model(m, tables, channels=None, p_interp="log", zero_rule="both",
                   keep=False):
     """One model: dict ``m`` with T (per layer, bottom first), p_bot, p_top,
-    log10_vmr, Rp, Rs, GM, wn_lo, wn_hi, he_h2, k_B, amu, gravity.
+    log10_vmr, Rp, Rs, GM, wn_lo, wn_hi, he_h2, k_B, amu, gravity, and
+    optionally a cloud deck: cloud_sigma (m^2, +inf for opaque; absent or 0
+    for none), cloud_p_top, cloud_p_bottom (Pa).
 
     Returns a dict with the native depth over the window (``depth``), the
     binned depth (``binned``, if channels are given) and ``valid``.  With
@@ -326,6 +362,14 @@ def forward_model(m, tables, channels=None, p_interp="log", zero_rule="both",
     kappa = opacity(T, P, chi, chi_h2, chi_he, tables, m["k_B"], lo, hi,
                     p_interp, zero_rule)
     tau = optical_depth(dl, kappa)
+    sigma_c = m.get("cloud_sigma", 0.0)
+    if sigma_c != 0.0:
+        kappa_c, deck = cloud_opacity(P, T, m["k_B"], sigma_c, m["cloud_p_top"],
+                                      m["cloud_p_bottom"])
+        tau_c = cloud_optical_depth(dl, kappa_c, deck, sigma_c)
+        tau = tau + tau_c[:, None]
+    else:
+        kappa_c = tau_c = None
     D = transit_depth(tau, A, m["Rp"], m["Rs"])
     out = {"depth": D, "valid": valid}
     if channels is not None:
@@ -333,7 +377,8 @@ def forward_model(m, tables, channels=None, p_interp="log", zero_rule="both",
         out["binned"] = bin_spectrum(D, w)
     if keep:
         out.update(z=z, dl=dl, A=A, kappa=kappa, tau=tau, P=P, mu=mu,
-                   chi=chi, chi_h2=chi_h2, chi_he=chi_he)
+                   chi=chi, chi_h2=chi_h2, chi_he=chi_he, kappa_c=kappa_c,
+                   tau_c=tau_c)
     return out
 
 

@@ -89,6 +89,12 @@ class Batch:
     k_B: float = K_BOLTZMANN
     amu: float = AMU_KG
     gravity: int = 0               # 0: g = GM/(Rp+z)^2, 1: g = GM/Rp^2
+    # optional flat-opacity cloud deck per model ([B] each, or None for no
+    # decks): cross-section in m^2 (0: none, +inf: opaque) and the deck's
+    # bounding pressures in Pa
+    cloud_sigma: np.ndarray = None
+    cloud_p_top: np.ndarray = None
+    cloud_p_bottom: np.ndarray = None
 
     @property
     def B(self):
@@ -99,12 +105,17 @@ class Batch:
 
     def model(self, b):
         """Per-model view as a dict (the oracle's input form)."""
-        return dict(T=self.T_of(b).copy(), p_bot=float(self.p_bot[b]),
+        d = dict(T=self.T_of(b).copy(), p_bot=float(self.p_bot[b]),
                     p_top=float(self.p_top[b]), log10_vmr=self.log10_vmr[b].copy(),
                     Rp=float(self.Rp[b]), Rs=float(self.Rs[b]), GM=float(self.GM[b]),
                     wn_lo=int(self.wn_lo[b]), wn_hi=int(self.wn_hi[b]),
                     he_h2=self.he_h2, k_B=self.k_B, amu=self.amu,
                     gravity=self.gravity)
+        if self.cloud_sigma is not None:
+            d.update(cloud_sigma=float(self.cloud_sigma[b]),
+                     cloud_p_top=float(self.cloud_p_top[b]),
+                     cloud_p_bottom=float(self.cloud_p_bottom[b]))
+        return d
 
     def subset(self, idx):
         idx = np.asarray(idx)
@@ -117,7 +128,39 @@ class Batch:
                      self.log10_vmr[idx].copy(), self.Rp[idx].copy(),
                      self.Rs[idx].copy(), self.GM[idx].copy(),
                      self.wn_lo[idx].copy(), self.wn_hi[idx].copy(),
-                     self.he_h2, self.k_B, self.amu, self.gravity)
+                     self.he_h2, self.k_B, self.amu, self.gravity,
+                     *(None if c is None else c[idx].copy()
+                       for c in (self.cloud_sigma, self.cloud_p_top, self.cloud_p_bottom)))
+
+
+def with_cloud_decks(batch, seed, kinds=("none", "flat", "opaque")):
+    """A copy of ``batch`` with a cloud deck per model, model b of kind
+    kinds[b % len(kinds)]: "none" (sigma 0), "flat" (a deck of 2-20 % of the
+    atmosphere's log-pressure span at a random height, log10 sigma uniform in
+    [-32, -27] m^2, so that its optical depth along a chord spans ~0.01-1e4),
+    "opaque" (sigma +inf from a cloud-top pressure log-uniform over the
+    upper 80 % of the span down to the bottom boundary: the fully opaque deck
+    whose top pressure the paper's transit retrieval fits)."""
+    rng = np.random.default_rng(seed)
+    B = batch.B
+    sig = np.zeros(B)
+    pt = np.ones(B)
+    pb = np.ones(B)
+    for b in range(B):
+        kind = kinds[b % len(kinds)]
+        xb, xt = np.log10(batch.p_bot[b]), np.log10(batch.p_top[b])
+        if kind == "flat":
+            width = rng.uniform(0.02, 0.2) * (xb - xt)
+            x1 = rng.uniform(xt, xb - width)
+            pt[b], pb[b] = 10.0 ** x1, 10.0 ** (x1 + width)
+            sig[b] = 10.0 ** rng.uniform(-32.0, -27.0)
+        elif kind == "opaque":
+            pt[b] = 10.0 ** rng.uniform(xt, xt + 0.8 * (xb - xt))
+            pb[b] = batch.p_bot[b]
+            sig[b] = np.inf
+    out = batch.subset(np.arange(B))
+    out.cloud_sigma, out.cloud_p_top, out.cloud_p_bottom = sig, pt, pb
+    return out
 
 
 @dataclass
