@@ -183,6 +183,20 @@ typedef struct {
   double k_B;                   /* Boltzmann constant, J/K */
   double amu_kg;                /* atomic mass unit, kg */
   int32_t gravity;              /* 0: g = GM/(Rp+z)^2, 1: g = GM/Rp^2 */
+  /* Optional flat-opacity cloud deck per model (equation clouds, Forward
+   * Models section): the cross-section sigma (m^2 per molecule) times the
+   * number density is added to the opacity of every layer whose centre
+   * pressure lies between the two deck pressures (bounds included, in
+   * either order), at every wavenumber.  All three NULL: no decks; else all
+   * three set.  sigma = 0: no deck for that model; sigma = +INFINITY: a
+   * fully opaque deck (every ray with a nonzero path through it is
+   * blocked).  sigma < 0 or NaN, or (sigma > 0 and) a deck pressure that is
+   * not finite and positive flags the model TRX_MODEL_BAD_PROFILE.  The
+   * gradient treats the deck's layers as fixed: the deck pressures are not
+   * differentiated (the deck is a step in P). */
+  const double* cloud_sigma_m2;   /* [B] */
+  const double* cloud_p_top_Pa;   /* [B] */
+  const double* cloud_p_bottom_Pa;/* [B] */
 } trx_batch;
 
 /* Forward model for every model of the batch.
@@ -251,8 +265,8 @@ trx_status trx_plan_create(trx_ctx* ctx, const trx_tables* t, const trx_bins* bi
 trx_status trx_plan_destroy(trx_plan* p);
 /* Fill `out` with device input buffers owned by the plan (B = B_max,
  * max_layers = N_max, layer_off sized for B_max * N_max layers; default
- * constants He/H2 0.17, CODATA k_B and atomic mass unit, gravity 0).  Their
- * use is optional: any batch with B <= B_max and max_layers <= N_max can be
+ * constants He/H2 0.17, CODATA k_B and atomic mass unit, gravity 0; cloud
+ * deck arrays zeroed at creation, i.e. no decks).  Their use is optional: any batch with B <= B_max and max_layers <= N_max can be
  * launched. */
 trx_status trx_plan_batch(trx_plan* p, trx_batch* out);
 /* Run the plan on `batch` (batch->B models).  Outputs as in trx_forward and

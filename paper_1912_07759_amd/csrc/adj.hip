@@ -182,6 +182,7 @@ __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
     a.chi2[b] = t2;
     // D_i = (Rp/Rs)^2 + ...: sum_i Dbar_i = sum_c Dbar_c
     acc[a.G.o_Rp] = ts * 2.0 * hd->Rp * hd->inv_Rs2;
+    acc[a.G.o_S] = ts;
   }
 }
 
@@ -625,7 +626,12 @@ __global__ __launch_bounds__(256) void k_adj_reduce(AdjArgs a) {
 // PRbar_j w_R,l gives the chord adjoints: with dl[j][l] = 2 (Q_{j,l+1} -
 // Q_{j,l}) (Q_{j,j} = 0), dQ/dh_m = (Rp + h_m)/Q, dQ/dz_j = -(Rp + z_j)/Q,
 // dQ/dRp = (h_m - z_j)/Q (a zero Q, the top ray at the top boundary, has no
-// derivative).
+// derivative).  A cloud deck (optical depth tc_j along ray j, folded into
+// the ray's weight A'_j = A_j e^{-tc_j} and the constant sum_j A_j (1 -
+// e^{-tc_j})) unfolds here: with S = sum_i Dbar_i, Abar_j = Abar'_j
+// e^{-tc_j} + S (1 - e^{-tc_j}) and tcbar_j = A'_j (S - Abar'_j), and
+// tc_j = sum_l dl[j][l] c_l with the layer weight c_l = sigma rho_l joins
+// the chord and temperature sums like the Rayleigh weight.
 constexpr int kPM = 256;
 __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
   const int b = blockIdx.x;
@@ -652,20 +658,31 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
 
   __shared__ double sZ[TRX_MAX_LAYERS_MFMA];
   __shared__ double sH[TRX_MAX_LAYERS_MFMA + 1];
-  __shared__ double sW[TRX_MAX_LAYERS_MFMA][7];   // 4 corners, 2 CIA nodes, Rayleigh
-  __shared__ double sD[TRX_MAX_LAYERS_MFMA][7];   // their d/dT at fixed P
+  __shared__ double sW[TRX_MAX_LAYERS_MFMA][8];   // 4 corners, 2 CIA nodes, Rayleigh, cloud
+  __shared__ double sD[TRX_MAX_LAYERS_MFMA][8];   // their d/dT at fixed P
   __shared__ int sS[TRX_MAX_LAYERS_MFMA][6];      // their slots
   __shared__ double sHb[TRX_MAX_LAYERS_MFMA + 1];
   __shared__ double sRp[kPM / 64];
+  __shared__ double sTcb[TRX_MAX_LAYERS_MFMA];    // tcbar_j (zero without a deck)
   const int nq = nV > 0 ? 6 : 4;
   for (int l = tid; l < N; l += kPM) {
     sZ[l] = zs[l];
-    const int perm[7] = {0, 1, 2, 3, 5, 6, 4};
-    for (int q = 0; q < 7; ++q) {
+    const int perm[8] = {0, 1, 2, 3, 5, 6, 4, 7};
+    for (int q = 0; q < 8; ++q) {
       const double w = lw64[8 * l + perm[q]];
       sW[l][q] = (q == 4 || q == 5) ? w / kCiaScale32 : w;
       sD[l][q] = lwd[8 * l + perm[q]];
     }
+    double tcb = 0.0;
+    if (hd->cloud) {
+      const double tc = reinterpret_cast<const double*>(slab + L.off_pc64)[l];
+      const double Ap = reinterpret_cast<const double*>(slab + L.off_A64)[l];
+      const double S = acc[G.o_S], Abp = acc[G.o_A + l];
+      // an opaque ray (tc = inf) has A' = 0 and no tcbar
+      tcb = isinf(tc) ? 0.0 : Ap * (S - Abp);
+      acc[G.o_A + l] = Abp * exp(-tc) - S * expm1(-tc);
+    }
+    sTcb[l] = tcb;
     const uint32_t c01 = (uint32_t)lid[8 * l + 6], c23 = (uint32_t)lid[8 * l + 7];
     const uint32_t cw = (uint32_t)lid[8 * l + 3];
     sS[l][0] = c01 & 0xffff;
@@ -690,16 +707,18 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
 
   // temperatures through the weights: thread per layer
   for (int l = tid; l < N; l += kPM) {
-    double wb[7] = {0, 0, 0, 0, 0, 0, 0};
+    double wb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int j = 0; j <= l; ++j) {
       const double d = chord(j, l);
       const double* pr = Pb + (int64_t)j * kKG;
       for (int q = 0; q < nq; ++q) wb[q] += d * pr[sS[l][q]];
       wb[6] += d * PRb[j];
+      wb[7] += d * sTcb[j];
     }
     double t = 0.0;
     for (int q = 0; q < nq; ++q) t += wb[q] * sD[l][q];
     t += wb[6] * sD[l][6];
+    t += wb[7] * sD[l][7];
     acc[G.o_T + l] += t;
   }
   // chords: thread per ray
@@ -710,7 +729,7 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
     double zb = 0.0;
     double q0 = 0.0;
     for (int l = j; l < N; ++l) {
-      double dlb = PRb[j] * sW[l][6];
+      double dlb = PRb[j] * sW[l][6] + sTcb[j] * sW[l][7];
       for (int q = 0; q < nq; ++q) dlb += pr[sS[l][q]] * sW[l][q];
       const double g = 2.0 * dlb;
       const double h1 = sH[l + 1];

@@ -340,6 +340,9 @@ trx_status trx::check_batch(trx_ctx* c, const trx_tables* t, const trx_batch* bt
   if (!(bt->he_h2_ratio >= 0) || !(bt->k_B > 0) || !(bt->amu_kg > 0))
     return set_err(c, TRX_E_INVALID_ARG, "he_h2_ratio must be >= 0 and k_B, amu_kg > 0");
   if (bt->gravity != 0 && bt->gravity != 1) return set_err(c, TRX_E_INVALID_ARG, "gravity must be 0 or 1");
+  const int nc = !!bt->cloud_sigma_m2 + !!bt->cloud_p_top_Pa + !!bt->cloud_p_bottom_Pa;
+  if (nc != 0 && nc != 3)
+    return set_err(c, TRX_E_INVALID_ARG, "cloud deck arrays: all three or none");
   return TRX_OK;
 }
 
@@ -350,6 +353,7 @@ DevBatch trx::dev_batch(const trx_batch* bt) {
   d.Rp = bt->Rp_m; d.Rs = bt->Rs_m; d.GM = bt->GM_m3s2;
   d.wn_lo = bt->wn_lo; d.wn_hi = bt->wn_hi;
   d.he_h2 = bt->he_h2_ratio; d.kB = bt->k_B; d.amu = bt->amu_kg; d.gravity = bt->gravity;
+  d.cloud_sigma = bt->cloud_sigma_m2; d.cloud_p1 = bt->cloud_p_top_Pa; d.cloud_p2 = bt->cloud_p_bottom_Pa;
   return d;
 }
 
@@ -411,6 +415,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
       launch_fwd_mfma(f, precision, rc.nrb_max, B, c->n_cu, c->stream);
     }
   }
+  if (tau && db.cloud_sigma) launch_tau_cloud(ws, L, B_dev, B, max_layers, t->dev.n_wn, tau, c->stream);
   if (depth_binned) {
     BinArgs ba;
     ba.ws = ws; ba.L = L; ba.B_dev = B_dev; ba.B = B;

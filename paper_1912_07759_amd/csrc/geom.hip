@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
 
   __shared__ double sP[TRX_MAX_LAYERS_FP64];
   __shared__ double sZ[TRX_MAX_LAYERS_FP64];
-  __shared__ double sC[TRX_MAX_LAYERS_FP64];   // kB T_l * ln(P_{l+1}/P_l)
+  __shared__ double sC[TRX_MAX_LAYERS_FP64];   // kB T_l * ln(P_{l+1}/P_l), later the deck's terms
   __shared__ int s_status;
   __shared__ double s_mu;
 
@@ -107,6 +107,11 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       S += pow(10.0, x);
     }
     if (!fin || !(S < 1.0)) st |= TRX_MODEL_BAD_CHEMISTRY;
+    if (a.bt.cloud_sigma) {
+      const double sg = a.bt.cloud_sigma[b];
+      if (!(sg >= 0.0)) st |= TRX_MODEL_BAD_PROFILE;
+      if (sg > 0.0 && !(finite_pos(a.bt.cloud_p1[b]) && finite_pos(a.bt.cloud_p2[b]))) st |= TRX_MODEL_BAD_PROFILE;
+    }
     s_status = st;
   }
   __syncthreads();
@@ -122,6 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     if (tid == 0) {
       h->n = 0; h->status = status; h->lo = lo; h->hi = hi;
       h->nrb = 0; h->nkb = 0; h->span_lo = 0; h->span_hi = 0;
+      h->cloud = 0;
       if (a.mlay) a.mlay[b] = 0;
       if (a.mspan) a.mspan[b] = make_int2(0, 0);
     }
@@ -203,6 +209,33 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   __syncthreads();
   const double inv_Rs2 = 1.0 / (Rs * Rs);
 
+  // a3: chord length of ray j through layer k
+  auto dl_of = [&](int j, int k) -> double {
+    if (j >= N || k >= N || k < j) return 0.0;
+    const double zj = sZ[j];
+    const double hk = (k == 0) ? 0.0 : 0.5 * (sZ[k - 1] + sZ[k]);
+    const double hk1 = (k == N - 1) ? sZ[N - 1] : 0.5 * (sZ[k] + sZ[k + 1]);
+    const double q1 = sqrt(fmax((hk1 - zj) * (2.0 * Rp + hk1 + zj), 0.0));
+    if (k == j) return 2.0 * q1;
+    const double q0 = sqrt((hk - zj) * (2.0 * Rp + hk + zj));
+    return 2.0 * (hk1 - hk) * (2.0 * Rp + hk + hk1) / (q1 + q0);
+  };
+  // cloud deck (equation clouds): sigma rho on the layers whose centre
+  // pressure lies in [min(p1, p2), max(p1, p2)], at every wavenumber.  Its
+  // optical depth along ray j, tc_j = sum_k dl[j][k] sigma rho_k, does not
+  // depend on the wavenumber, so A_j (1 - e^{-tau_j - tc_j}) = A_j (1 -
+  // e^{-tc_j}) + A_j e^{-tc_j} (1 - e^{-tau_j}): the first term joins the
+  // model's constant (Rp/Rs)^2 and the ray carries A_j e^{-tc_j} as its
+  // annulus weight, so that every forward kernel runs unchanged.  An opaque
+  // deck (sigma = +inf) has tc_j = +inf on the rays with a nonzero path
+  // through it, 0 on the others.
+  const double csig = a.bt.cloud_sigma ? a.bt.cloud_sigma[b] : 0.0;
+  const double cp_lo = csig > 0.0 ? fmin(a.bt.cloud_p1[b], a.bt.cloud_p2[b]) : 0.0;
+  const double cp_hi = csig > 0.0 ? fmax(a.bt.cloud_p1[b], a.bt.cloud_p2[b]) : -1.0;
+  const bool copaque = isinf(csig);
+  auto in_deck = [&](int k) { return sP[k] >= cp_lo && sP[k] <= cp_hi; };
+  double* pc64 = reinterpret_cast<double*>(slab + L.off_pc64);
+
   // a3: annulus weights; a4: layer records
   const int NP = L.NP;
   for (int l = tid; l < NP; l += kThreads) {
@@ -210,7 +243,20 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       const double z = sZ[l];
       const double hl = (l == 0) ? 0.0 : 0.5 * (sZ[l - 1] + z);
       const double hu = (l == N - 1) ? z : 0.5 * (z + sZ[l + 1]);
-      const double A = 2.0 * (Rp + z) * (hu - hl) * inv_Rs2;
+      const double A0 = 2.0 * (Rp + z) * (hu - hl) * inv_Rs2;
+      double tc = 0.0;
+      for (int k = l; k < N && csig > 0.0; ++k) {
+        if (!in_deck(k)) continue;
+        const double d = dl_of(l, k);
+        if (copaque) {
+          if (d > 0.0) tc = __builtin_inf();
+        } else {
+          tc += d * (csig * sP[k] / (a.bt.kB * a.bt.T[off + k]));
+        }
+      }
+      const double A = A0 * exp(-tc);
+      sC[l] = -A0 * expm1(-tc);   // this ray's share of the deck's constant term
+      pc64[l] = tc;
       zs[l] = z;
       A64[l] = A;
       A32[l] = (float)A;
@@ -243,7 +289,10 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         iC = 0;
         w[5] = w[6] = 0.0;
       }
-      w[7] = 0.0;
+      // the deck's weight sigma rho of this layer (the gradient's chord and
+      // temperature terms; zero outside the deck and for an opaque deck)
+      const bool cl = csig > 0.0 && !copaque && in_deck(l);
+      w[7] = cl ? csig * n : 0.0;
       for (int q = 0; q < 8; ++q) {
         lw64[8 * l + q] = w[q];
         lw32[8 * l + q] = (float)(q >= 5 ? w[q] / kCiaScale32 : w[q]);
@@ -276,8 +325,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         } else {
           d[5] = d[6] = 0.0;
         }
-        d[7] = 0.0;
-        for (int q = 0; q < 8; ++q) lwd[q] = q >= 5 ? d[q] / kCiaScale32 : d[q];
+        d[7] = -w[7] / T;
+        for (int q = 0; q < 8; ++q) lwd[q] = q >= 5 && q < 7 ? d[q] / kCiaScale32 : d[q];
       }
       lid[8 * l] = iT * tb.n_P + iP;
       lid[8 * l + 1] = iC;
@@ -285,6 +334,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       zs[l] = 0.0;
       A64[l] = 0.0;
       A32[l] = 0.0f;
+      pc64[l] = 0.0;
       if (L.off_aw) reinterpret_cast<float2*>(slab + L.off_aw)[l] = make_float2(0.f, 0.f);
       if (L.off_pr64) reinterpret_cast<double*>(slab + L.off_pr64)[l] = 0.0;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
@@ -294,6 +344,13 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     }
   }
   __syncthreads();
+  if (tid == 0) {
+    // the deck's constant term, summed in layer order
+    double s = 0.0;
+    for (int l = 0; l < N && csig > 0.0; ++l) s += sC[l];
+    h->Rp2_Rs2 = (Rp / Rs) * (Rp / Rs) + s;
+    h->cloud = csig > 0.0 ? 1 : 0;
+  }
 
   // distinct corners of the whole model (bitmaps over the keys
   // iP n_T + iT, slots = rank of the key among the set bits, so that the
@@ -447,17 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     kblk[kb] = d;
   }
 
-  // a3: chord lengths
-  auto dl_of = [&](int j, int k) -> double {
-    if (j >= N || k >= N || k < j) return 0.0;
-    const double zj = sZ[j];
-    const double hk = (k == 0) ? 0.0 : 0.5 * (sZ[k - 1] + sZ[k]);
-    const double hk1 = (k == N - 1) ? sZ[N - 1] : 0.5 * (sZ[k] + sZ[k + 1]);
-    const double q1 = sqrt(fmax((hk1 - zj) * (2.0 * Rp + hk1 + zj), 0.0));
-    if (k == j) return 2.0 * q1;
-    const double q0 = sqrt((hk - zj) * (2.0 * Rp + hk + zj));
-    return 2.0 * (hk1 - hk) * (2.0 * Rp + hk + hk1) / (q1 + q0);
-  };
+  // a3: chord lengths (dl_of above)
   uint8_t* dst = slab + L.off_dl;
   if (a.precision == TRX_FP64 && !L.slot64) {
     double* dlT = reinterpret_cast<double*>(dst);
@@ -743,11 +790,35 @@ void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* 
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(1024), 0, s, mlay, B_dev, B, order, qcount);
 }
 
+// The cloud deck's optical depth tc_j is folded into the annulus weights,
+// not into tau; the optical-depth output adds it back, per ray, over the
+// model's window.
+static __global__ __launch_bounds__(256) void k_tau_cloud(const uint8_t* ws, Layout L, const int32_t* B_dev, int B,
+                                                  int64_t ld, int W, double* tau) {
+  const int b = blockIdx.x;
+  if (b >= (B_dev ? *B_dev : B)) return;
+  const uint8_t* slab = ws + (int64_t)b * L.slab;
+  const ModelHdr* h = reinterpret_cast<const ModelHdr*>(slab);
+  const int j = blockIdx.y;
+  if (h->n == 0 || h->cloud == 0 || j >= h->n) return;
+  const double tc = reinterpret_cast<const double*>(slab + L.off_pc64)[j];
+  if (tc == 0.0) return;
+  double* row = tau + (int64_t)b * ld + (int64_t)j * W;
+  for (int i = h->lo + (int)threadIdx.x; i < h->hi; i += 256) row[i] += tc;
+}
+
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   hipLaunchKernelGGL(k_geom, dim3(B_grid), dim3(kThreads), 0, s, a);
   if (a.precision != TRX_FP64 || a.L.grad || a.L.slot64)
     hipLaunchKernelGGL(k_pmat, dim3(B_grid, kPG), dim3(kPT), 0, s, a);
+}
+
+void launch_tau_cloud(const uint8_t* ws, const Layout& L, const int32_t* B_dev, int B, int max_layers, int W,
+                      double* tau, hipStream_t s) {
+  if (B <= 0 || max_layers <= 0) return;
+  hipLaunchKernelGGL(k_tau_cloud, dim3(B, max_layers), dim3(256), 0, s, ws, L, B_dev, B,
+                     (int64_t)max_layers * W, W, tau);
 }
 
 }  // namespace trx

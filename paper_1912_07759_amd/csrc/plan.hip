@@ -81,7 +81,8 @@ bool same_batch(const trx_batch& a, const trx_batch& b) {
          a.T_K == b.T_K && a.p_bot_Pa == b.p_bot_Pa && a.p_top_Pa == b.p_top_Pa &&
          a.log10_vmr == b.log10_vmr && a.Rp_m == b.Rp_m && a.Rs_m == b.Rs_m && a.GM_m3s2 == b.GM_m3s2 &&
          a.wn_lo == b.wn_lo && a.wn_hi == b.wn_hi && a.he_h2_ratio == b.he_h2_ratio && a.k_B == b.k_B &&
-         a.amu_kg == b.amu_kg && a.gravity == b.gravity;
+         a.amu_kg == b.amu_kg && a.gravity == b.gravity && a.cloud_sigma_m2 == b.cloud_sigma_m2 &&
+         a.cloud_p_top_Pa == b.cloud_p_top_Pa && a.cloud_p_bottom_Pa == b.cloud_p_bottom_Pa;
 }
 
 // The launch sequence of one plan run on the context's current stream.
@@ -253,7 +254,14 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   b.k_B = 1.380649e-23;
   b.amu_kg = 1.66053906660e-27;
   b.gravity = 0;
+  // cloud decks: zero cross-sections (no decks) until the caller writes them
+  b.cloud_sigma_m2 = (double*)take(8 * (size_t)B_max);
+  b.cloud_p_top_Pa = (double*)take(8 * (size_t)B_max);
+  b.cloud_p_bottom_Pa = (double*)take(8 * (size_t)B_max);
   p->B_dev = (int32_t*)take(4);
+  if (e == hipSuccess) e = hipMemset((void*)b.cloud_sigma_m2, 0, 8 * (size_t)B_max);
+  if (e == hipSuccess) e = hipMemset((void*)b.cloud_p_top_Pa, 0, 8 * (size_t)B_max);
+  if (e == hipSuccess) e = hipMemset((void*)b.cloud_p_bottom_Pa, 0, 8 * (size_t)B_max);
   if (e != hipSuccess) return fail(hip_err(c, e, "trx_plan_create"));
   if (flags & TRX_PLAN_GRAPH) {
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);

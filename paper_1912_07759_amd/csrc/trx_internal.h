@@ -66,6 +66,9 @@ struct ModelHdr {
   // ray block rb has a nonzero path x weight product (rays above every layer
   // of a slot block see none of it)
   uint64_t kq_mask[TRX_MAX_LAYERS_MFMA / 32];
+  // 1 when a cloud deck adds optical depth to some ray; its per-ray depth
+  // is then folded into the annulus weights (see the geometry kernel)
+  int32_t cloud;
 };
 static_assert(sizeof(ModelHdr) <= kHdrBytes, "header too large");
 
@@ -96,6 +99,7 @@ struct Layout {
   int64_t off_sid;         // [16 NKQ] table row of each opacity slot (corners, then CIA nodes)
   int64_t off_aw;          // [NP] float2 (A_j/Rs^2, Rayleigh path weight of ray j)
   int64_t off_pr64;        // FP64 slot form: [NP] FP64 Rayleigh path weight of ray j
+  int64_t off_pc64;        // [NP] FP64 optical depth of the cloud deck along ray j (+inf: opaque)
   int32_t slot64;          // FP64 mode in the slot form (models of at most TRX_MAX_LAYERS_MFMA layers)
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise); the gradient takes models of at
@@ -145,6 +149,7 @@ inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& 
   L.off_z = take(8LL * L.NP);
   L.off_A64 = take(8LL * L.NP);
   L.off_A32 = take(4LL * L.NP);
+  L.off_pc64 = take(8LL * L.NP);
   L.off_lw64 = take(8LL * 8 * L.NP);
   L.off_lw32 = take(4LL * 8 * L.NP);
   // per layer: abs corner, CIA node, model-list slots (abs, CIA), block-list
@@ -201,6 +206,9 @@ struct DevBatch {
   const int32_t* wn_hi;
   double he_h2, kB, amu;
   int32_t gravity;
+  const double* cloud_sigma;   // [B] or null (then the next two are null too)
+  const double* cloud_p1;
+  const double* cloud_p2;
 };
 
 struct GeomArgs {
@@ -228,6 +236,8 @@ __host__ __device__ inline ModelHdr* hdr_of(uint8_t* ws, const Layout& L, int b)
 }
 
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s);
+void launch_tau_cloud(const uint8_t* ws, const Layout& L, const int32_t* B_dev, int B, int max_layers, int W,
+                      double* tau, hipStream_t s);
 
 }  // namespace trx
 
@@ -281,7 +291,7 @@ struct BinArgs {
 // Per-model FP64 accumulators of the adjoint (offsets in doubles).
 struct GradAcc {
   int32_t NP;
-  int32_t o_A, o_z, o_h, o_T, o_Rp, o_chi, o_cw, o_PR, o_P, n;
+  int32_t o_A, o_z, o_h, o_T, o_Rp, o_S, o_chi, o_cw, o_PR, o_P, n;
 };
 __host__ __device__ inline GradAcc make_grad_acc(int NP) {
   GradAcc g{};
@@ -292,6 +302,7 @@ __host__ __device__ inline GradAcc make_grad_acc(int NP) {
   g.o_h = o; o += NP + 1;      // dchi2/dh_k, shell boundaries 0..N
   g.o_T = o; o += NP;          // dchi2/dT_l through the opacity
   g.o_Rp = o; o += 1;          // dchi2/dRp (explicit terms)
+  g.o_S = o; o += 1;           // sum_i dchi2/dD_i (every point of the window)
   g.o_chi = o; o += kMaxSpecies;  // dchi2/dchi_s through the opacity
   g.o_cw = o; o += TRX_MAX_CIA;   // dchi2/d(chi_a chi_b) per CIA pair
   g.o_PR = o; o += NP;         // dchi2/dPR_j, Rayleigh path weight of ray j

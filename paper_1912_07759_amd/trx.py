@@ -59,7 +59,8 @@ class BatchC(ctypes.Structure):
                 ("T_K", _P), ("p_bot_Pa", _P), ("p_top_Pa", _P), ("log10_vmr", _P),
                 ("Rp_m", _P), ("Rs_m", _P), ("GM_m3s2", _P), ("wn_lo", _P),
                 ("wn_hi", _P), ("he_h2_ratio", _D), ("k_B", _D), ("amu_kg", _D),
-                ("gravity", _I)]
+                ("gravity", _I), ("cloud_sigma_m2", _P), ("cloud_p_top_Pa", _P),
+                ("cloud_p_bottom_Pa", _P)]
 
 
 _lib = None
@@ -198,7 +199,8 @@ class DeviceBatch:
 
     def __init__(self, n_layers, T, p_bot, p_top, log10_vmr, Rp, Rs, GM, wn_lo, wn_hi,
                  he_h2=0.17, k_B=1.380649e-23, amu=1.66053906660e-27, gravity=0,
-                 device="cuda", max_layers=None):
+                 device="cuda", max_layers=None, cloud_sigma=None, cloud_p_top=None,
+                 cloud_p_bottom=None):
         dev = torch.device(device)
         t = lambda a, dt: torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a,
                                           dtype=dt).to(dev).contiguous()
@@ -214,12 +216,19 @@ class DeviceBatch:
         self.wn_lo, self.wn_hi = t(wn_lo, torch.int32), t(wn_hi, torch.int32)
         self.he_h2, self.k_B, self.amu, self.gravity = he_h2, k_B, amu, gravity
         self.B = int(self.n_layers.numel())
+        # optional cloud decks: all three per-model arrays, or none
+        if (cloud_sigma is None) != (cloud_p_top is None) or (cloud_sigma is None) != (cloud_p_bottom is None):
+            raise ValueError("cloud deck arrays: all three or none")
+        self.cloud = None if cloud_sigma is None else tuple(
+            t(v, torch.float64) for v in (cloud_sigma, cloud_p_top, cloud_p_bottom))
         self.max_layers = int(max_layers if max_layers is not None else max(2, int(nl.max())))
 
     @classmethod
     def from_synth(cls, b, device="cuda", max_layers=None):
         return cls(b.n_layers, b.T, b.p_bot, b.p_top, b.log10_vmr, b.Rp, b.Rs, b.GM,
-                   b.wn_lo, b.wn_hi, b.he_h2, b.k_B, b.amu, b.gravity, device, max_layers)
+                   b.wn_lo, b.wn_hi, b.he_h2, b.k_B, b.amu, b.gravity, device, max_layers,
+                   getattr(b, "cloud_sigma", None), getattr(b, "cloud_p_top", None),
+                   getattr(b, "cloud_p_bottom", None))
 
     @property
     def n_abs(self):
@@ -234,7 +243,8 @@ class DeviceBatch:
                       _ptr(self.layer_off), _ptr(self.T), _ptr(self.p_bot), _ptr(self.p_top),
                       _ptr(self.log10_vmr), _ptr(self.Rp), _ptr(self.Rs), _ptr(self.GM),
                       _ptr(self.wn_lo), _ptr(self.wn_hi), float(self.he_h2), float(self.k_B),
-                      float(self.amu), int(self.gravity))
+                      float(self.amu), int(self.gravity),
+                      *((None, None, None) if self.cloud is None else (_ptr(c) for c in self.cloud)))
 
 
 class _ModelView:
@@ -250,7 +260,8 @@ class _ModelView:
         return BatchC(1, d.max_layers, at(d.n_layers, b), at(d.layer_off, b), _ptr(d.T),
                       at(d.p_bot, b), at(d.p_top, b), at(d.log10_vmr, b * d.n_abs),
                       at(d.Rp, b), at(d.Rs, b), at(d.GM, b), at(d.wn_lo, b), at(d.wn_hi, b),
-                      float(d.he_h2), float(d.k_B), float(d.amu), int(d.gravity))
+                      float(d.he_h2), float(d.k_B), float(d.amu), int(d.gravity),
+                      *((None, None, None) if d.cloud is None else (at(c, b) for c in d.cloud)))
 
 
 def _prec(p):
