@@ -49,6 +49,8 @@ def parse():
                    help="skip the gradient leg (chi^2 gradients of the 256-point workload)")
     p.add_argument("--grad-precision", default="fp64", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
                    help="forward pass of the gradient leg (the residual needs its accuracy)")
+    p.add_argument("--no-clouds", action="store_true",
+                   help="skip the leg with cloud decks on the main batch")
     p.add_argument("--no-single", action="store_true",
                    help="skip the single-model leg (one model per graph replay)")
     p.add_argument("--large", action="store_true",
@@ -297,6 +299,31 @@ def single_leg(args, ctx, trx, torch):
     return res
 
 
+def clouds_leg(args, plan, tables, batch, ch, trx, torch):
+    """The main batch with a flat-opacity cloud deck on two thirds of the
+    models (a third finite decks, a third opaque), through the same plan;
+    sampled models (one of each kind) against the oracle."""
+    import oracle
+    from synth.workloads import with_cloud_decks
+    cb = with_cloud_decks(batch, 5)
+    dbc = trx.DeviceBatch.from_synth(cb, max_layers=200)
+    ms = time_steps(lambda: plan.launch(dbc), args.steps, args.warmup)
+    _, binned, status = plan.launch(dbc)
+    torch.cuda.synchronize()
+    assert int((status != 0).sum()) == 0
+    gb = binned.cpu().numpy()
+    errs = []
+    for b in (0, 1, 2, 3, 4, 5):
+        ref = oracle.forward_model(cb.model(b), tables, ch)["binned"]
+        ok = ~np.isnan(ref)
+        errs.append(float(np.max(np.abs(gb[b][ok] - ref[ok]) / ref[ok])))
+    log(f"clouds: {ms:.3f} ms/step; max rel err {max(errs):.2e}")
+    return {"ms_per_step": round(ms, 3), "spectra_per_s": round(batch.B / (ms * 1e-3), 1),
+            "decks": "one third none, one third finite (log10 sigma in [-32, -27] m^2), "
+                     "one third opaque",
+            "max_rel_err_binned": max(errs), "models_checked": len(errs)}
+
+
 def step_stats(fn, steps):
     """Median and quartiles (ms) of `steps` launches, each between its own
     pair of events on the current stream."""
@@ -473,6 +500,8 @@ def main():
         err = {"max_rel_err_binned": max(errs), "models_checked": len(done)}
         log(f"oracle: {len(done)} models in {t_cpu:.1f} s; max rel err {max(errs):.2e}")
 
+    clouds = None if args.no_clouds else clouds_leg(args, plan, tables, batch, ch, trx, torch)
+
     out = {"metric": "forward spectra/s and gradient evals/s at \u22641e-6 rel err, batched vs "
                      "plain FP64",
            "value": round(B / (ms * 1e-3), 1), "unit": "spectra/s", "n_gpus": 1,
@@ -487,7 +516,7 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
            "ms_per_step_median": round(med, 3), "ms_per_step_iqr": [round(q1, 3), round(q3, 3)],
            "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad,
-           "single_model": single}
+           "single_model": single, "clouds": clouds}
     if large is not None:
         out["large"] = large
     print(json.dumps(out), flush=True)
