@@ -44,7 +44,7 @@ design notes):
   A14 chi^2 = sum_c ((D_c - O_c)/sigma_c)^2.
   A18 Rayleigh applies to every species (absorbers, H2, He); CIA pairs are
       given by species ids (absorbers 0..n_abs-1, then H2, then He).
-  A19 the flat-opacity cloud deck (equation clouds) is sigma rho on the
+  A24 the flat-opacity cloud deck (equation clouds) is sigma rho on the
       layers whose centre pressure lies between the two deck pressures
       (bounds included, either order); sigma = +inf is the fully opaque
       deck, whose optical depth is +inf on every ray with a nonzero path
@@ -262,7 +262,7 @@ def cloud_opacity(P, T, k_B, sigma, p_top, p_bottom):
     """Equation clouds: a flat (wavenumber-independent) cross-section sigma
     (m^2) on the layers inside the deck and zero outside, entering the path
     integral with the number density like absorption (w = 1), so the deck
-    adds kappa_c[l] = sigma rho_l (m^-1).  Reading A19: the deck is
+    adds kappa_c[l] = sigma rho_l (m^-1).  Reading A24: the deck is
     discretised on the layer-centre pressures and takes the layers with
     min(p_top, p_bottom) <= P_l <= max(p_top, p_bottom) (the equation and
     the text name the two bounds in opposite orders).  sigma = +inf is the
