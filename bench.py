@@ -51,6 +51,8 @@ def parse():
                    help="forward pass of the gradient leg (the residual needs its accuracy)")
     p.add_argument("--no-clouds", action="store_true",
                    help="skip the leg with cloud decks on the main batch")
+    p.add_argument("--no-retrieval", action="store_true",
+                   help="skip the synthetic nested-sampling retrieval")
     p.add_argument("--no-single", action="store_true",
                    help="skip the single-model leg (one model per graph replay)")
     p.add_argument("--large", action="store_true",
@@ -324,6 +326,49 @@ def clouds_leg(args, plan, tables, batch, ch, trx, torch):
             "max_rel_err_binned": max(errs), "models_checked": len(errs)}
 
 
+def retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch):
+    """The paper's transit retrieval on synthetic data: 5 log abundances, an
+    isothermal T, Rp and the top of an opaque cloud deck, uniform priors; the
+    observation is the oracle's binned spectrum of the truth (100 layers, the
+    whole 40000-point grid) plus seeded 50 ppm noise; single-ellipsoid
+    nested sampling with candidates evaluated 2048 per plan launch."""
+    import oracle
+    from paper_1912_07759_amd.retrieval import TransitRetrieval, nested_sample, posterior
+    from synth.constants import GM_JUP, R_SUN
+    from synth.workloads import observation_noise
+    N = 100
+    truth = np.array([-3.5, -6.0, -5.0, -7.0, -8.0, 1200.0, 1.35, 3.0])
+    na = tables.n_abs
+    m = dict(T=np.full(N, truth[na]), p_bot=1e6, p_top=1e-4, log10_vmr=truth[:na],
+             Rp=truth[na + 1] * TransitRetrieval.R_JUP, Rs=R_SUN, GM=GM_JUP, wn_lo=0,
+             wn_hi=tables.n_wn, he_h2=0.17, k_B=1.380649e-23, amu=1.66053906660e-27, gravity=0,
+             cloud_sigma=np.inf, cloud_p_top=10.0 ** truth[na + 2], cloud_p_bottom=1e6)
+    noise, sigma = observation_noise(3, 1, len(ch.lo))
+    obs = oracle.forward_model(m, tables, ch)["binned"] + noise[0]
+    ret = TransitRetrieval(ctx, T, bins, obs, sigma, tables.names, R_SUN, GM_JUP, n_layers=N,
+                           B_max=2048, precision=args.precision)
+    ret(np.full((4, len(ret.priors)), 0.5))      # graph capture outside the timing
+    torch.cuda.synchronize()
+    ret.n_eval = ret.n_launch = 0
+    ret.gpu_seconds = 0.0
+    r = nested_sample(ret, len(ret.priors), n_live=200, batch=2048, dlogz=0.5, seed=1)
+    _, mean, std = posterior(r, ret.priors)
+    ret.close()
+    names = [p.name for p in ret.priors]
+    log(f"retrieval: {r['n_eval']} likelihoods in {r['seconds']:.1f} s "
+        f"({ret.gpu_seconds:.1f} s in {ret.n_launch} launches), logz {r['logz']:.2f}")
+    return {"seconds": round(r["seconds"], 2), "likelihood_evals": int(r["n_eval"]),
+            "launches": int(ret.n_launch), "seconds_in_launches": round(ret.gpu_seconds, 2),
+            "likelihoods_per_s": round(r["n_eval"] / r["seconds"], 1),
+            "iterations": int(r["n_iter"]), "n_live": 200,
+            "logz": round(r["logz"], 3), "logz_err": round(r["logz_err"], 3),
+            "truth": dict(zip(names, truth.tolist())),
+            "posterior_mean": dict(zip(names, np.round(mean, 4).tolist())),
+            "posterior_std": dict(zip(names, np.round(std, 4).tolist())),
+            "config": "5 log abundances, isothermal T, Rp, opaque cloud-deck top; 100 layers, "
+                      "40000 points, 50 channels, 50 ppm noise"}
+
+
 def step_stats(fn, steps):
     """Median and quartiles (ms) of `steps` launches, each between its own
     pair of events on the current stream."""
@@ -501,6 +546,7 @@ def main():
         log(f"oracle: {len(done)} models in {t_cpu:.1f} s; max rel err {max(errs):.2e}")
 
     clouds = None if args.no_clouds else clouds_leg(args, plan, tables, batch, ch, trx, torch)
+    retrieval = None if args.no_retrieval else retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch)
 
     out = {"metric": "forward spectra/s and gradient evals/s at \u22641e-6 rel err, batched vs "
                      "plain FP64",
@@ -516,7 +562,7 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
            "ms_per_step_median": round(med, 3), "ms_per_step_iqr": [round(q1, 3), round(q3, 3)],
            "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad,
-           "single_model": single, "clouds": clouds}
+           "single_model": single, "clouds": clouds, "retrieval": retrieval}
     if large is not None:
         out["large"] = large
     print(json.dumps(out), flush=True)

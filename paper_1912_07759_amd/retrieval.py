@@ -1,0 +1,259 @@
+"""A synthetic transmission retrieval driven by the batched forward plan.
+
+The paper's transmission retrieval (Retrievals section, prior table) fits
+five absorber abundances in log10 space, an isothermal temperature, the
+planet radius and the pressure of a fully opaque cloud deck, all with
+uniform priors whose bounds are given in linear space (Optimization
+section); a model the forward model rejects gets the lowest possible
+log-likelihood (Model Rejection subsection).  Its samplers are nested
+samplers (MultiNest, Nestle, PolyChord, ...), which are not part of this
+library; `nested_sample` is a plain single-ellipsoid nested sampler
+(Skilling's algorithm with the bounding-ellipsoid proposal of the Nestle /
+MultiNest family) written for batched likelihoods: candidates are drawn
+from the current ellipsoid a batch at a time, evaluated in one launch of
+the plan, and consumed in order by the usual rejection step.
+
+Every forward model runs on the GPU through `trx.Plan`; the Gaussian
+log-likelihood of the binned spectra is summed on the host over the
+channels (B x n_ch values).
+"""
+
+import time
+
+import numpy as np
+
+
+class UniformPrior:
+    """Uniform prior of one parameter; bounds in linear space, the
+    parameter sampled uniformly in linear or log10 space."""
+
+    def __init__(self, name, lo, hi, mode="linear"):
+        assert mode in ("linear", "log") and hi > lo
+        self.name, self.lo, self.hi, self.mode = name, float(lo), float(hi), mode
+        if mode == "log":
+            assert lo > 0
+            self.a, self.b = np.log10(lo), np.log10(hi)
+        else:
+            self.a, self.b = self.lo, self.hi
+
+    def __call__(self, u):
+        """Unit-cube coordinate -> the sampled value (log10 of the parameter
+        in log mode)."""
+        return self.a + (self.b - self.a) * np.asarray(u)
+
+
+def paper_transit_priors(absorbers):
+    """The paper's transmission priors: abundances 1e-12..1e-1 (log),
+    T 400..2000 K, radius 1.2..1.5 R_J, cloud-top pressure 1e-8..1 bar
+    (log; in Pa here)."""
+    pri = [UniformPrior(f"log10_{a}", 1e-12, 1e-1, "log") for a in absorbers]
+    pri += [UniformPrior("T_K", 400.0, 2000.0), UniformPrior("Rp_RJ", 1.2, 1.5),
+            UniformPrior("log10_Pcloud_Pa", 1e-3, 1e5, "log")]
+    return pri
+
+
+def _logsubexp(a, b):
+    return a + np.log1p(-np.exp(b - a))
+
+
+def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25, seed=0,
+                  max_iter=200000, max_evals=10 ** 7):
+    """Nested sampling of the unit cube [0, 1]^ndim (the priors are applied
+    by `loglike`, which maps an [K, ndim] array of unit-cube points to K
+    log-likelihoods, -inf for a rejected model).
+
+    Each iteration removes the live point of lowest likelihood L_min, books
+    it with the prior volume shrinking by e^{-1/n_live} per iteration, and
+    replaces it by a point with L > L_min drawn uniformly from the live
+    points' bounding ellipsoid (scaled to contain them all, volume enlarged
+    by `enlarge`) intersected with the cube.  Proposals come from a pool
+    filled `batch` at a time (one `loglike` call each).  Stops when the live
+    points can add less than `dlogz` to log Z.
+
+    Returns dict(logz, logz_err, information, samples [M, ndim] unit-cube,
+    logl [M], logwt [M], n_iter, n_eval, n_calls, seconds)."""
+    rng = np.random.default_rng(seed)
+    t0 = time.perf_counter()
+    u = rng.random((n_live, ndim))
+    logl = np.asarray(loglike(u), dtype=np.float64)
+    n_eval, n_calls = n_live, 1
+    dead_u, dead_l, dead_v = [], [], []
+    logvol = 0.0
+    logz, h = -np.inf, 0.0
+    pool_u = np.zeros((0, ndim))
+    pool_l = np.zeros(0)
+    it = 0
+    step = -1.0 / n_live
+    while it < max_iter:
+        # remaining evidence bound: the live points' best L over the volume left
+        lmax = np.max(logl)
+        if np.isfinite(logz) and np.logaddexp(logz, lmax + logvol) - logz < dlogz:
+            break
+        w = int(np.argmin(logl))
+        lmin = logl[w]
+        # the shell between e^{logvol} and e^{logvol - 1/n_live}
+        logwt = _logsubexp(logvol, logvol + step) + lmin
+        if np.isfinite(logwt):
+            lz_new = np.logaddexp(logz, logwt)
+            h = (np.exp(logwt - lz_new) * lmin
+                 + (np.exp(logz - lz_new) * (h + logz) if np.isfinite(logz) else 0.0) - lz_new)
+            logz = lz_new
+        dead_u.append(u[w].copy())
+        dead_l.append(lmin)
+        dead_v.append(logwt)
+        logvol += step
+        # replacement: the first pool candidate with L > L_min; refill the pool
+        # from the current ellipsoid when it runs dry
+        while True:
+            ok = np.flatnonzero(pool_l > lmin)
+            if ok.size:
+                k = int(ok[0])
+                u[w], logl[w] = pool_u[k], pool_l[k]
+                pool_u, pool_l = pool_u[k + 1:], pool_l[k + 1:]
+                break
+            if n_eval >= max_evals:
+                raise RuntimeError("nested_sample: likelihood budget exhausted")
+            pool_u = _ellipsoid_draws(u, batch, enlarge, rng)
+            pool_l = np.asarray(loglike(pool_u), dtype=np.float64)
+            n_eval += len(pool_u)
+            n_calls += 1
+        it += 1
+    # the live points share the remaining volume equally
+    live_wt = logvol - np.log(n_live) + logl
+    for k in np.argsort(logl):
+        lz_new = np.logaddexp(logz, live_wt[k])
+        if np.isfinite(live_wt[k]):
+            h = (np.exp(live_wt[k] - lz_new) * logl[k]
+                 + np.exp(logz - lz_new) * (h + logz) - lz_new)
+        logz = lz_new
+    samples = np.vstack([np.array(dead_u).reshape(-1, ndim), u])
+    lw = np.concatenate([np.array(dead_v), live_wt])
+    ll = np.concatenate([np.array(dead_l), logl])
+    return {"logz": float(logz), "logz_err": float(np.sqrt(max(h, 0.0) / n_live)),
+            "information": float(h), "samples": samples, "logl": ll, "logwt": lw,
+            "n_iter": it, "n_eval": n_eval, "n_calls": n_calls,
+            "seconds": time.perf_counter() - t0}
+
+
+def _ellipsoid_draws(u, n, enlarge, rng):
+    """n points uniform in the intersection of the unit cube with the
+    bounding ellipsoid of the rows of u (scaled to contain them all, volume
+    times `enlarge`): draws outside the cube are dropped and replaced, so
+    that a likelihood launch carries a full batch."""
+    d = u.shape[1]
+    mu = u.mean(axis=0)
+    cov = np.cov(u, rowvar=False) + 1e-12 * np.eye(d)
+    inv = np.linalg.inv(cov)
+    x = u - mu
+    r2 = np.max(np.einsum("ij,jk,ik->i", x, inv, x))
+    scale = np.sqrt(r2) * enlarge ** (1.0 / d)
+    L = np.linalg.cholesky(cov)
+    out, have = [], 0
+    for _ in range(64):
+        g = rng.standard_normal((2 * n, d))
+        g /= np.linalg.norm(g, axis=1)[:, None]
+        rad = rng.random(2 * n) ** (1.0 / d)
+        pts = mu + scale * (g * rad[:, None]) @ L.T
+        pts = pts[np.all((pts > 0.0) & (pts < 1.0), axis=1)]
+        out.append(pts)
+        have += len(pts)
+        if have >= n:
+            break
+    return np.vstack(out)[:n]
+
+
+def posterior(result, priors=None):
+    """Normalised posterior weights, weighted mean and standard deviation of
+    the samples (in the priors' sampled coordinates when given)."""
+    w = np.exp(result["logwt"] - result["logz"])
+    w = w / w.sum()
+    x = result["samples"]
+    if priors is not None:
+        x = np.column_stack([p(x[:, i]) for i, p in enumerate(priors)])
+    mean = w @ x
+    std = np.sqrt(np.maximum(w @ (x - mean) ** 2, 0.0))
+    return w, mean, std
+
+
+class TransitRetrieval:
+    """Log-likelihood of the paper's transmission retrieval on one forward
+    plan: isothermal atmospheres of `n_layers` layers between p_bot and p_top
+    (Pa), constant abundances of the tables' absorbers, radius in Jupiter
+    radii, a fully opaque cloud deck from the cloud-top pressure down, on the
+    whole wavenumber grid, binned to `bins`; Gaussian likelihood of `obs`
+    with per-channel `sigma`.  Candidates are evaluated up to `B_max` per
+    launch of a graph-captured plan whose device inputs are rewritten in
+    place."""
+
+    R_JUP = 6.9911e7
+
+    def __init__(self, ctx, tables, bins, obs, sigma, absorbers, Rs, GM, n_layers=100,
+                 p_bot=1e6, p_top=1e-4, B_max=2048, precision="bf16x2"):
+        import torch
+        from . import trx
+        self.trx, self.torch = trx, torch
+        self.priors = paper_transit_priors(absorbers)
+        self.n_abs = len(absorbers)
+        self.obs = np.asarray(obs, dtype=np.float64)
+        self.sigma = np.asarray(sigma, dtype=np.float64)
+        self.N, self.B_max = int(n_layers), int(B_max)
+        self.p_bot = float(p_bot)
+        B, N = self.B_max, self.N
+        W = tables.n_wn
+        self.db = trx.DeviceBatch(np.full(B, N), np.full(B * N, 1000.0), np.full(B, p_bot),
+                                  np.full(B, p_top), np.full((B, self.n_abs), -6.0),
+                                  np.full(B, 1.3 * self.R_JUP), np.full(B, Rs), np.full(B, GM),
+                                  np.zeros(B), np.full(B, W), max_layers=N,
+                                  cloud_sigma=np.full(B, np.inf), cloud_p_top=np.full(B, 1e3),
+                                  cloud_p_bottom=np.full(B, p_bot))
+        self.plan = trx.Plan(ctx, tables, bins, B_max=B, N_max=N, precision=precision, graph=True)
+        self.n_eval = 0
+        self.n_launch = 0
+        self.gpu_seconds = 0.0
+
+    def physical(self, u):
+        """Unit-cube points -> sampled coordinates (log10 abundances, T,
+        Rp/R_J, log10 cloud-top pressure in Pa)."""
+        return np.column_stack([p(u[:, i]) for i, p in enumerate(self.priors)])
+
+    def __call__(self, u):
+        u = np.atleast_2d(u)
+        out = np.empty(len(u))
+        for s in range(0, len(u), self.B_max):
+            out[s:s + self.B_max] = self._chunk(self.physical(u[s:s + self.B_max]))
+        return out
+
+    def _chunk(self, x):
+        torch = self.torch
+        K, N, na = len(x), self.N, self.n_abs
+        db = self.db
+        t0 = time.perf_counter()
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        db.T[:K * N].copy_(dev(np.repeat(x[:, na], N)))
+        db.log10_vmr[:K].copy_(dev(x[:, :na]))
+        db.Rp[:K].copy_(dev(x[:, na + 1] * self.R_JUP))
+        db.cloud[1][:K].copy_(dev(10.0 ** x[:, na + 2]))
+        _, binned, status = self.plan.launch(_Prefix(db, K))
+        binned = binned[:K].cpu().numpy()
+        status = status[:K].cpu().numpy()
+        self.gpu_seconds += time.perf_counter() - t0
+        self.n_eval += K
+        self.n_launch += 1
+        r = (binned - self.obs[None, :]) / self.sigma[None, :]
+        ll = -0.5 * np.sum(r * r, axis=1) - np.sum(np.log(np.sqrt(2.0 * np.pi) * self.sigma))
+        # rejected models (Model Rejection subsection): lowest log-likelihood
+        ll[(status != 0) | ~np.isfinite(ll)] = -np.inf
+        return ll
+
+    def close(self):
+        self.plan.close()
+
+
+class _Prefix:
+    """The first K models of a DeviceBatch (same device arrays)."""
+
+    def __init__(self, db, K):
+        self.db, self.B = db, int(K)
+
+    def cstruct(self):
+        return self.db.cstruct(self.B)
