@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth.workloads import make_config, observation_noise
+from synth.workloads import make_config, observation_noise, with_cloud_decks
 from parity_util import TOL, binned_rel_err, native_rel_err
 
 pytestmark = pytest.mark.gpu
@@ -37,11 +37,14 @@ def _grad_err(g, off, b, ref):
                float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big]))))
 
 
-def _forward_full(ctx, cfg, precision, n_layers, n_check, seed):
+def _forward_full(ctx, cfg, precision, n_layers, n_check, seed, decks=False):
     """Forward of workload `cfg` at full size through an autotuned graph plan:
-    the binned output as timed, then the native grid from the same plan."""
+    the binned output as timed, then the native grid from the same plan
+    (with decks: the benchmark's cloud decks on two thirds of the models)."""
     from paper_1912_07759_amd import trx
     tables, batch, ch = make_config(cfg)
+    if decks:
+        batch = with_cloud_decks(batch, 5)
     T = trx.Tables.from_synth(ctx, tables)
     bins = trx.Bins(ctx, T, ch.lo, ch.hi)
     db = trx.DeviceBatch.from_synth(batch, max_layers=n_layers)
@@ -76,7 +79,7 @@ def _forward_full(ctx, cfg, precision, n_layers, n_check, seed):
 
     # sampled models against the oracle, element by element
     worst = 0.0
-    for b in _picks(batch, n_check, seed):
+    for b in dict.fromkeys(_picks(batch, n_check, seed) + ([0, 1, 2] if decks else [])):
         ref = oracle.forward_model(batch.model(b), tables, ch)
         lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
         e1 = native_rel_err(nat[b], ref["depth"], lo, hi)
@@ -92,6 +95,12 @@ def test_batched_4096_full_size(gpu_ctx):
     5000-40000 of 40000 points, 5 absorbers with CIA and Rayleigh, 50
     channels, split-bf16."""
     _forward_full(gpu_ctx, 3, "bf16x2", 200, 4, 0)
+
+
+def test_batched_4096_with_cloud_decks_full_size(gpu_ctx):
+    """The benchmark's batch with its cloud decks (a third none, a third
+    finite, a third opaque); sampled models of each kind among the checked."""
+    _forward_full(gpu_ctx, 3, "bf16x2", 200, 4, 6, decks=True)
 
 
 def _gradient_full(ctx, cfg, tables, batch, ch, n_layers, n_check, seed):
