@@ -57,16 +57,21 @@ def _logsubexp(a, b):
 
 
 def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25, seed=0,
-                  max_iter=200000, max_evals=10 ** 7):
+                  max_iter=200000, max_evals=10 ** 7, method="multi"):
     """Nested sampling of the unit cube [0, 1]^ndim (the priors are applied
     by `loglike`, which maps an [K, ndim] array of unit-cube points to K
     log-likelihoods, -inf for a rejected model).
 
     Each iteration removes the live point of lowest likelihood L_min, books
     it with the prior volume shrinking by e^{-1/n_live} per iteration, and
-    replaces it by a point with L > L_min drawn uniformly from the live
-    points' bounding ellipsoid (scaled to contain them all, volume enlarged
-    by `enlarge`) intersected with the cube.  Proposals come from a pool
+    replaces it by a point with L > L_min drawn uniformly from a bound of the
+    live points intersected with the cube: their bounding ellipsoid (scaled
+    to contain them all, volume enlarged by `enlarge`; method "single"), or
+    a union of such ellipsoids from recursive 2-means splits kept while they
+    halve the volume (method "multi", the MultiNest construction; a point
+    covered by q ellipsoids is kept with probability 1/q, and no ellipsoid is
+    smaller than its share n_k/n_live of the expected prior volume left).
+    Proposals come from a pool
     filled `batch` at a time (one `loglike` call each).  Stops when the live
     points can add less than `dlogz` to log Z.
 
@@ -113,7 +118,9 @@ def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25
                 break
             if n_eval >= max_evals:
                 raise RuntimeError("nested_sample: likelihood budget exhausted")
-            pool_u = _ellipsoid_draws(u, batch, enlarge, rng)
+            ells = ([_bounding_ellipsoid(u, enlarge)] if method == "single"
+                    else _split_ellipsoids(u, enlarge, np.exp(logvol), n_live))
+            pool_u = _union_draws(ells, batch, rng)
             pool_l = np.asarray(loglike(pool_u), dtype=np.float64)
             n_eval += len(pool_u)
             n_calls += 1
@@ -135,25 +142,109 @@ def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25
             "seconds": time.perf_counter() - t0}
 
 
-def _ellipsoid_draws(u, n, enlarge, rng):
-    """n points uniform in the intersection of the unit cube with the
-    bounding ellipsoid of the rows of u (scaled to contain them all, volume
-    times `enlarge`): draws outside the cube are dropped and replaced, so
-    that a likelihood launch carries a full batch."""
-    d = u.shape[1]
-    mu = u.mean(axis=0)
-    cov = np.cov(u, rowvar=False) + 1e-12 * np.eye(d)
-    inv = np.linalg.inv(cov)
-    x = u - mu
-    r2 = np.max(np.einsum("ij,jk,ik->i", x, inv, x))
-    scale = np.sqrt(r2) * enlarge ** (1.0 / d)
-    L = np.linalg.cholesky(cov)
-    out, have = [], 0
-    for _ in range(64):
-        g = rng.standard_normal((2 * n, d))
+class _Ellipsoid:
+    """{x : (x - mu)^T A^{-1} (x - mu) <= 1} with A = scale^2 cov."""
+
+    def __init__(self, mu, cov, scale2):
+        self.mu, self.d = mu, len(mu)
+        self.A = cov * scale2
+        self.L = np.linalg.cholesky(self.A)
+        self.Ainv = np.linalg.inv(self.A)
+        self.logvol = float(np.sum(np.log(np.diag(self.L))))   # up to the unit ball's volume
+
+    def grow_to(self, logvol):
+        if logvol > self.logvol:
+            f = np.exp(2.0 * (logvol - self.logvol) / self.d)
+            self.__init__(self.mu, self.A, f)
+
+    def contains(self, x):
+        y = x - self.mu
+        return np.einsum("ij,jk,ik->i", y, self.Ainv, y) <= 1.0
+
+    def draw(self, n, rng):
+        g = rng.standard_normal((n, self.d))
         g /= np.linalg.norm(g, axis=1)[:, None]
-        rad = rng.random(2 * n) ** (1.0 / d)
-        pts = mu + scale * (g * rad[:, None]) @ L.T
+        rad = rng.random(n) ** (1.0 / self.d)
+        return self.mu + (g * rad[:, None]) @ self.L.T
+
+
+def _bounding_ellipsoid(x, enlarge):
+    """The ellipsoid of the points' covariance shape scaled to contain them
+    all, its volume times `enlarge`."""
+    d = x.shape[1]
+    mu = x.mean(axis=0)
+    cov = np.cov(x, rowvar=False) + 1e-12 * np.eye(d)
+    y = x - mu
+    r2 = np.max(np.einsum("ij,jk,ik->i", y, np.linalg.inv(cov), y))
+    return _Ellipsoid(mu, cov, r2 * enlarge ** (2.0 / d))
+
+
+def _two_means(x, iters=10):
+    """Lloyd's 2-means from the two points farthest apart along the first
+    principal axis."""
+    y = x - x.mean(axis=0)
+    ax = np.linalg.svd(y, full_matrices=False)[2][0]
+    p = y @ ax
+    c = np.stack([x[np.argmin(p)], x[np.argmax(p)]])
+    lab = np.zeros(len(x), dtype=int)
+    for _ in range(iters):
+        lab = np.argmin(((x[:, None, :] - c[None]) ** 2).sum(-1), axis=1)
+        if lab.min() == lab.max():
+            break
+        c = np.stack([x[lab == k].mean(axis=0) for k in (0, 1)])
+    return lab
+
+
+def _split_ellipsoids(x, enlarge, x_vol, n_live, min_pts=None):
+    """Recursive 2-means splits of the points, kept while the two children's
+    bounding ellipsoids fill less than half their parent's volume; each
+    ellipsoid then grown, if needed, to its share of the prior volume left
+    (the cube has volume 1; volumes in units of the d-ball's)."""
+    d = x.shape[1]
+    min_pts = 2 * (d + 1) if min_pts is None else min_pts
+    from math import lgamma, log, pi
+    log_ball = 0.5 * d * log(pi) - lgamma(0.5 * d + 1.0)
+
+    def rec(pts):
+        e = _bounding_ellipsoid(pts, enlarge)
+        if len(pts) < 2 * min_pts:
+            return [(e, len(pts))]
+        lab = _two_means(pts)
+        a, b = pts[lab == 0], pts[lab == 1]
+        if len(a) < min_pts or len(b) < min_pts:
+            return [(e, len(pts))]
+        ea, eb = _bounding_ellipsoid(a, enlarge), _bounding_ellipsoid(b, enlarge)
+        if np.logaddexp(ea.logvol, eb.logvol) < e.logvol + np.log(0.5):
+            return rec(a) + rec(b)
+        return [(e, len(pts))]
+
+    out = []
+    for e, n in rec(x):
+        e.grow_to(np.log(n / n_live * x_vol) - log_ball)
+        out.append(e)
+    return out
+
+
+def _union_draws(ells, n, rng):
+    """n points uniform in the union of the ellipsoids intersected with the
+    unit cube: an ellipsoid picked with probability proportional to its
+    volume, a uniform point in it, kept with probability 1/q (q = the number
+    of ellipsoids holding it) and only inside the cube; refilled until n
+    points are kept, so that a likelihood launch carries a full batch."""
+    lv = np.array([e.logvol for e in ells])
+    p = np.exp(lv - lv.max())
+    p /= p.sum()
+    out, have = [], 0
+    for _ in range(256):
+        k = rng.choice(len(ells), size=2 * n, p=p)
+        pts = np.empty((2 * n, ells[0].d))
+        for j, e in enumerate(ells):
+            m = k == j
+            if m.any():
+                pts[m] = e.draw(int(m.sum()), rng)
+        if len(ells) > 1:
+            q = np.sum([e.contains(pts) for e in ells], axis=0)
+            pts = pts[rng.random(len(pts)) * q < 1.0]
         pts = pts[np.all((pts > 0.0) & (pts < 1.0), axis=1)]
         out.append(pts)
         have += len(pts)

@@ -39,6 +39,30 @@ def test_gaussian_evidence_and_moments():
     assert abs(r["information"] - h_exact) < 0.3
 
 
+@pytest.mark.parametrize("method", ["single", "multi"])
+def test_gaussian_evidence_both_bounds(method):
+    r = nested_sample(_gauss, D, n_live=300, batch=256, seed=4, method=method)
+    assert abs(r["logz"] - D * np.log(_cube_mass(0.0, 1.0))) <= 4.0 * r["logz_err"] + 0.02
+
+
+def test_bimodal_evidence_and_mode_weights():
+    """Two equal, well separated Gaussians (each of weight 1/2, normalised):
+    Z = 1 and half the posterior mass in each mode; the multi-ellipsoid
+    bound keeps both modes."""
+    c1, c2, s = np.array([0.25] * D), np.array([0.75] * D), 0.03
+
+    def ll(u):
+        u = np.atleast_2d(u)
+        a = -0.5 * np.sum(((u - c1) / s) ** 2, axis=1)
+        b = -0.5 * np.sum(((u - c2) / s) ** 2, axis=1)
+        return np.logaddexp(a, b) + np.log(0.5) - D * np.log(np.sqrt(2.0 * np.pi) * s)
+    r = nested_sample(ll, D, n_live=400, batch=512, seed=3, method="multi")
+    assert abs(r["logz"]) <= 4.0 * r["logz_err"] + 0.02, (r["logz"], r["logz_err"])
+    w, _, _ = posterior(r)
+    left = np.sum(w[r["samples"][:, 0] < 0.5])
+    assert abs(left - 0.5) < 0.1
+
+
 def test_rejected_region_removes_its_evidence():
     def ll(u):
         v = _gauss(u)
