@@ -144,24 +144,30 @@ def test_gradient_plan_graph(gpu_ctx, problem):
                     grad=True)
 
     def check(out, n):
+        # the per-span FP32 partials are summed by atomics in no fixed order:
+        # with ~200 items per model each component may move by up to
+        # 200 x 2^-24 of the largest partial sum, which shows on components
+        # that cancel to near zero (hence the floor of 2e-5 of the largest)
         for k in ("chi2", "dT", "dlog10_vmr", "dRp"):
             got = out[k].cpu().numpy()
             want = ref[k][:n] if k != "dT" else ref[k][:int(batch.layer_off[n])]
-            assert np.allclose(got, want, rtol=1e-5, atol=1e-9 * np.max(np.abs(want))), k
-    for r in range(3):
-        x = torch.randn(1 << 18, device="cuda").sum()
+            assert np.allclose(got, want, rtol=1e-5, atol=2e-5 * np.max(np.abs(want))), k
+    try:
+        for r in range(3):
+            x = torch.randn(1 << 18, device="cuda").sum()
+            torch.cuda.synchronize()
+            out = plan.launch_grad(db, obs, sigma)
+            torch.cuda.synchronize()
+            assert float(x) == float(x)
+            check(out, batch.B)
+        sub = db.view(0)
+        out = plan.launch_grad(sub, obs[:1], sigma)
         torch.cuda.synchronize()
-        out = plan.launch_grad(db, obs, sigma)
-        torch.cuda.synchronize()
-        assert float(x) == float(x)
-        check(out, batch.B)
-    sub = db.view(0)
-    out = plan.launch_grad(sub, obs[:1], sigma)
-    torch.cuda.synchronize()
-    check(out, 1)
-    plan.close()
-    bins.close()
-    Tt.close()
+        check(out, 1)
+    finally:
+        plan.close()
+        bins.close()
+        Tt.close()
 
 
 def test_gradient_long_models_and_slot_limit(gpu_ctx):
