@@ -121,10 +121,13 @@ def test_autograd_function(gpu_ctx, problem):
     (c2 * w).sum().backward()
     ref = trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, sigma, "fp32")
     counts = torch.as_tensor(np.diff(batch.layer_off), device=c2.device)
-    assert torch.allclose(c2, ref["chi2"])
-    assert torch.allclose(T.grad, ref["dT"] * torch.repeat_interleave(w, counts))
-    assert torch.allclose(v.grad, ref["dlog10_vmr"] * w[:, None])
-    assert torch.allclose(R.grad, ref["dRp"] * w)
+    # a second run of the FP32 adjoint: its atomics sum the span partials in
+    # another order (floor 2e-5 of the largest component, as for the plans)
+    close = lambda a, b: torch.allclose(a, b, rtol=1e-5, atol=2e-5 * float(b.abs().max()))
+    assert close(c2, ref["chi2"])
+    assert close(T.grad, ref["dT"] * torch.repeat_interleave(w, counts))
+    assert close(v.grad, ref["dlog10_vmr"] * w[:, None])
+    assert close(R.grad, ref["dRp"] * w)
     bins.close()
     Tt.close()
 
