@@ -72,8 +72,11 @@ def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25
     covered by q ellipsoids is kept with probability 1/q, and no ellipsoid is
     smaller than its share n_k/n_live of the expected prior volume left).
     Proposals come from a pool
-    filled `batch` at a time (one `loglike` call each).  Stops when the live
-    points can add less than `dlogz` to log Z.
+    filled `batch` at a time (one `loglike` call each); a `loglike` with
+    submit(u) / collect() methods gets the next batch, drawn from the bound
+    of the moment, submitted as soon as a pool is taken, so that it is
+    evaluated while the pool is consumed.  Stops when the live points can
+    add less than `dlogz` to log Z.
 
     Returns dict(logz, logz_err, information, samples [M, ndim] unit-cube,
     logl [M], logwt [M], n_iter, n_eval, n_calls, seconds)."""
@@ -87,6 +90,8 @@ def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25
     logz, h = -np.inf, 0.0
     pool_u = np.zeros((0, ndim))
     pool_l = np.zeros(0)
+    overlap = hasattr(loglike, "submit") and hasattr(loglike, "collect")
+    pending = None
     it = 0
     step = -1.0 / n_live
     while it < max_iter:
@@ -120,11 +125,20 @@ def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25
                 raise RuntimeError("nested_sample: likelihood budget exhausted")
             ells = ([_bounding_ellipsoid(u, enlarge)] if method == "single"
                     else _split_ellipsoids(u, enlarge, np.exp(logvol), n_live))
-            pool_u = _union_draws(ells, batch, rng)
-            pool_l = np.asarray(loglike(pool_u), dtype=np.float64)
+            if pending is not None:
+                pool_u, pool_l = pending, np.asarray(loglike.collect(), dtype=np.float64)
+                pending = None
+            else:
+                pool_u = _union_draws(ells, batch, rng)
+                pool_l = np.asarray(loglike(pool_u), dtype=np.float64)
             n_eval += len(pool_u)
             n_calls += 1
+            if overlap:
+                pending = _union_draws(ells, batch, rng)
+                loglike.submit(pending)
         it += 1
+    if pending is not None:
+        loglike.collect()          # the batch in flight at the end is not used
     # the live points share the remaining volume equally
     live_wt = logvol - np.log(n_live) + logl
     for k in np.argsort(logl):
@@ -267,14 +281,16 @@ def posterior(result, priors=None):
 
 
 class TransitRetrieval:
-    """Log-likelihood of the paper's transmission retrieval on one forward
-    plan: isothermal atmospheres of `n_layers` layers between p_bot and p_top
-    (Pa), constant abundances of the tables' absorbers, radius in Jupiter
-    radii, a fully opaque cloud deck from the cloud-top pressure down, on the
-    whole wavenumber grid, binned to `bins`; Gaussian likelihood of `obs`
-    with per-channel `sigma`.  Candidates are evaluated up to `B_max` per
-    launch of a graph-captured plan whose device inputs are rewritten in
-    place."""
+    """Log-likelihood of the paper's transmission retrieval on forward plans:
+    isothermal atmospheres of `n_layers` layers between p_bot and p_top (Pa),
+    constant abundances of the tables' absorbers, radius in Jupiter radii, a
+    fully opaque cloud deck from the cloud-top pressure down, on the whole
+    wavenumber grid, binned to `bins`; Gaussian likelihood of `obs` with
+    per-channel `sigma`.  Candidates are evaluated up to `B_max` per launch
+    of a graph-captured plan whose device inputs are rewritten in place.  Two
+    plans, each with its own inputs and pinned staging buffers, alternate
+    under submit() / collect(), so that one batch runs on the GPU while the
+    caller works on the previous one."""
 
     R_JUP = 6.9911e7
 
@@ -288,19 +304,25 @@ class TransitRetrieval:
         self.obs = np.asarray(obs, dtype=np.float64)
         self.sigma = np.asarray(sigma, dtype=np.float64)
         self.N, self.B_max = int(n_layers), int(B_max)
-        self.p_bot = float(p_bot)
-        B, N = self.B_max, self.N
+        B, N, na = self.B_max, self.N, self.n_abs
         W = tables.n_wn
-        self.db = trx.DeviceBatch(np.full(B, N), np.full(B * N, 1000.0), np.full(B, p_bot),
-                                  np.full(B, p_top), np.full((B, self.n_abs), -6.0),
-                                  np.full(B, 1.3 * self.R_JUP), np.full(B, Rs), np.full(B, GM),
-                                  np.zeros(B), np.full(B, W), max_layers=N,
-                                  cloud_sigma=np.full(B, np.inf), cloud_p_top=np.full(B, 1e3),
-                                  cloud_p_bottom=np.full(B, p_bot))
-        self.plan = trx.Plan(ctx, tables, bins, B_max=B, N_max=N, precision=precision, graph=True)
+        self.slots = []
+        for _ in range(2):
+            db = trx.DeviceBatch(np.full(B, N), np.full(B * N, 1000.0), np.full(B, p_bot),
+                                 np.full(B, p_top), np.full((B, na), -6.0),
+                                 np.full(B, 1.3 * self.R_JUP), np.full(B, Rs), np.full(B, GM),
+                                 np.zeros(B), np.full(B, W), max_layers=N,
+                                 cloud_sigma=np.full(B, np.inf), cloud_p_top=np.full(B, 1e3),
+                                 cloud_p_bottom=np.full(B, p_bot))
+            plan = trx.Plan(ctx, tables, bins, B_max=B, N_max=N, precision=precision, graph=True)
+            pin = lambda *shape: torch.empty(shape, dtype=torch.float64, pin_memory=True)
+            self.slots.append({"db": db, "plan": plan, "T": pin(B * N), "vmr": pin(B, na),
+                               "Rp": pin(B), "pc": pin(B)})
+        self.turn = 0
+        self.inflight = None
         self.n_eval = 0
         self.n_launch = 0
-        self.gpu_seconds = 0.0
+        self.wait_seconds = 0.0   # host time blocked in collect()
 
     def physical(self, u):
         """Unit-cube points -> sampled coordinates (log10 abundances, T,
@@ -311,23 +333,42 @@ class TransitRetrieval:
         u = np.atleast_2d(u)
         out = np.empty(len(u))
         for s in range(0, len(u), self.B_max):
-            out[s:s + self.B_max] = self._chunk(self.physical(u[s:s + self.B_max]))
+            self.submit(u[s:s + self.B_max])
+            out[s:s + self.B_max] = self.collect()
         return out
 
-    def _chunk(self, x):
-        torch = self.torch
+    def submit(self, u):
+        """Queue the likelihoods of at most B_max unit-cube points (one plan
+        launch); the results come from the next collect()."""
+        assert self.inflight is None, "collect() the batch in flight first"
+        u = np.atleast_2d(u)
+        assert len(u) <= self.B_max
+        x = self.physical(u)
         K, N, na = len(x), self.N, self.n_abs
-        db = self.db
+        sl = self.slots[self.turn]
+        self.turn ^= 1
+        db = sl["db"]
+        # the staging buffers of this slot were last read by its previous
+        # launch, which its collect() has waited for
+        sl["T"][:K * N].numpy()[:] = np.repeat(x[:, na], N)
+        sl["vmr"][:K].numpy()[:] = x[:, :na]
+        sl["Rp"][:K].numpy()[:] = x[:, na + 1] * self.R_JUP
+        sl["pc"][:K].numpy()[:] = 10.0 ** x[:, na + 2]
+        db.T[:K * N].copy_(sl["T"][:K * N], non_blocking=True)
+        db.log10_vmr[:K].copy_(sl["vmr"][:K], non_blocking=True)
+        db.Rp[:K].copy_(sl["Rp"][:K], non_blocking=True)
+        db.cloud[1][:K].copy_(sl["pc"][:K], non_blocking=True)
+        _, binned, status = sl["plan"].launch(_Prefix(db, K))
+        self.inflight = (binned, status, K)
+
+    def collect(self):
+        """Log-likelihoods of the batch in flight (waits for it)."""
+        binned, status, K = self.inflight
+        self.inflight = None
         t0 = time.perf_counter()
-        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
-        db.T[:K * N].copy_(dev(np.repeat(x[:, na], N)))
-        db.log10_vmr[:K].copy_(dev(x[:, :na]))
-        db.Rp[:K].copy_(dev(x[:, na + 1] * self.R_JUP))
-        db.cloud[1][:K].copy_(dev(10.0 ** x[:, na + 2]))
-        _, binned, status = self.plan.launch(_Prefix(db, K))
         binned = binned[:K].cpu().numpy()
         status = status[:K].cpu().numpy()
-        self.gpu_seconds += time.perf_counter() - t0
+        self.wait_seconds += time.perf_counter() - t0
         self.n_eval += K
         self.n_launch += 1
         r = (binned - self.obs[None, :]) / self.sigma[None, :]
@@ -337,7 +378,10 @@ class TransitRetrieval:
         return ll
 
     def close(self):
-        self.plan.close()
+        if self.inflight is not None:
+            self.collect()
+        for sl in self.slots:
+            sl["plan"].close()
 
 
 class _Prefix:
