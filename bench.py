@@ -546,7 +546,13 @@ def main():
         log(f"oracle: {len(done)} models in {t_cpu:.1f} s; max rel err {max(errs):.2e}")
 
     clouds = None if args.no_clouds else clouds_leg(args, plan, tables, batch, ch, trx, torch)
-    retrieval = None if args.no_retrieval else retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch)
+    retrieval = None
+    if not args.no_retrieval:
+        try:
+            retrieval = retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch)
+        except RuntimeError as e:      # the sampler's likelihood budget: report, keep the line
+            retrieval = {"error": str(e)}
+            log(f"retrieval failed: {e}")
 
     out = {"metric": "forward spectra/s and gradient evals/s at \u22641e-6 rel err, batched vs "
                      "plain FP64",
