@@ -249,7 +249,10 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         if (!in_deck(k)) continue;
         const double d = dl_of(l, k);
         if (copaque) {
-          if (d > 0.0) tc = __builtin_inf();
+          if (d > 0.0) {   // one path through an opaque deck blocks the ray
+            tc = __builtin_inf();
+            break;
+          }
         } else {
           tc += d * (csig * sP[k] / (a.bt.kB * a.bt.T[off + k]));
         }
