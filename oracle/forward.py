@@ -52,8 +52,11 @@ design notes):
 
 Pins (tests/test_oracle_pins.py): zero opacity gives (Rp/Rs)^2 exactly; the
 opaque limit equals the closed-form trapezoid sum; the constant-g isothermal
-altitude equals H ln(P_0/P_l); the isothermal constant-cross-section model
-converges to the exact continuous transit depth (Bessel K1 chord integral);
+altitude equals H ln(P_0/P_l); with T linear in ln P the altitude's error
+is exactly that of a left Riemann sum (the lower layer's H); the isothermal
+constant-cross-section model converges to the exact continuous transit depth
+(Bessel K1 chord integral), and so does a constant-CIA model (rho^2 halves
+the scale height; H2-H2, H2-He and absorber-H2 pairs);
 chords match a 50-digit mpmath evaluation and a fine-step quadrature of
 int kappa ds along the ray; the chord sum equals the full chord; bilinear
 interpolation is exact on T-logP-bilinear tables and at nodes; each clamp

@@ -114,6 +114,28 @@ def test_altitude_variable_gravity_first_order_convergence():
     assert all(0.9 < o < 1.1 for o in orders), orders
 
 
+def test_altitude_non_isothermal_uses_lower_layer_scale_height():
+    """Constant g and mu, T linear in x = ln(P_0/P): the exact hydrostatic
+    altitude is (k_B/(mu g)) int_0^x T dx'.  A step that takes the scale
+    height of the lower layer (the altitude equation's H_{l-1}) is the left
+    Riemann sum of that integral, whose error for a linear integrand is
+    exactly -(k_B/(mu g)) alpha x_l dx / 2: the upper layer's H gives the
+    opposite sign and a centred H gives none."""
+    N, mu = 120, 2.3 * AMU_KG
+    _, P = F.pressure_grid(1e6, 1e-4, N)
+    x = np.log(P[0] / P)
+    dx = x[1] - x[0]
+    for T0, alpha in ((800.0, 60.0), (2600.0, -55.0)):
+        T = T0 + alpha * x
+        z = F.altitude(T, P, mu, R_JUP, GM_JUP, K_BOLTZMANN, gravity=1)
+        c = K_BOLTZMANN * R_JUP ** 2 / (mu * GM_JUP)
+        exact = c * (T0 * x + 0.5 * alpha * x ** 2)
+        err = z - exact
+        want = -0.5 * c * alpha * x * dx
+        assert np.allclose(err[1:], want[1:], rtol=1e-7, atol=0), (T0, alpha)
+        assert np.all(np.sign(err[1:]) == -np.sign(alpha))
+
+
 # --------------------------------------------------------------------------
 # a3: geometry
 # --------------------------------------------------------------------------
@@ -327,6 +349,65 @@ def test_isothermal_constant_sigma_converges_to_continuous_model():
     # refinement; at 100 layers the atmospheric part is within ~1.5e-3
     orders = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
     assert errs[0] < 3e-3
+    assert all(1.3 < o < 2.0 for o in orders), (errs, orders)
+    assert max(orders) - min(orders) < 0.1, orders
+
+
+def _cia_tables(sigma_cm5, pair, n_wn=3, nT=3):
+    """One absorber with zero cross-section and one CIA pair (species ids
+    ``pair``) whose cross-section sigma_cm5 is the same at every T and
+    wavenumber."""
+    wn = np.linspace(1000.0, 3000.0, n_wn)
+    T = np.linspace(100.0, 4000.0, nT)
+    lp = np.linspace(-6.0, 8.0, 3)
+    return Tables(wn, T, lp, np.zeros((1, nT, 3, n_wn)), np.array([MASSES_AMU["H2O"]]),
+                  MASSES_AMU["H2"], MASSES_AMU["He"], T.copy(),
+                  np.full((1, nT, n_wn), sigma_cm5), np.array([pair], np.int32), None, ["X"])
+
+
+def _continuous_cia_depth(N, kappa0, T, mu_kg):
+    """Continuous isothermal constant-g atmosphere whose opacity is
+    kappa0 e^{-2z/H}, i.e. rho^2 with rho = rho_0 e^{-z/H} (equation
+    cia_opt_dpth): the chord integral is the absorption one with H/2,
+    tau(b) = 2 kappa0 b K1(2b/H) e^{2Rp/H}."""
+    _, P = F.pressure_grid(1e6, 1e-4, N)
+    H = K_BOLTZMANN * T * R_JUP ** 2 / (mu_kg * GM_JUP)
+    ztop = H * np.log(P[0] / P[-1])
+    Hc = 0.5 * H
+
+    def tau(z):
+        b = R_JUP + z
+        return 2.0 * kappa0 * b * special.k1e(b / Hc) * np.exp(-z / Hc)
+
+    f = lambda z: 2.0 * (R_JUP + z) * (-np.expm1(-tau(z)))
+    a, _ = integrate.quad(f, 0.0, ztop, epsabs=0, epsrel=1e-13, limit=500)
+    return (R_JUP ** 2 + a) / R_SUN ** 2, (R_JUP ** 2) / R_SUN ** 2
+
+
+@pytest.mark.parametrize("pair,vmr", [((1, 1), -30.0), ((1, 2), -30.0), ((0, 1), -1.0)])
+def test_isothermal_constant_cia_converges_to_continuous_model(pair, vmr):
+    """Equation cia_opt_dpth with one pair of constant cross-section
+    sigma_c (cm^5): kappa = 1e-10 sigma_c chi_a chi_b rho^2 (m^-1).  With the
+    pair weight of the species ids H2-H2, H2-He or absorber-H2 (a 10 %
+    absorber) the discrete model converges to the continuous one, whose
+    rho^2 profile has half the scale height.  A wrong unit factor, power of
+    rho or pair index moves the depth by percents, far outside the bound."""
+    T, sigma_c = 1500.0, 1e-43
+    t = _cia_tables(sigma_c, pair)
+    chi, h2, he, mu, _ = F.chemistry(np.array([vmr]), HE_H2_RATIO, t.abs_mass, t.h2_mass,
+                                     t.he_mass, AMU_KG)
+    species = [chi[0], h2, he]
+    w = species[pair[0]] * species[pair[1]]
+    errs = []
+    for N in (100, 200, 400, 800):
+        n0 = F.pressure_grid(1e6, 1e-4, N)[1][0] / (K_BOLTZMANN * T)   # rho at z = 0
+        kappa0 = 1e-10 * sigma_c * w * n0 ** 2
+        m = _model(N=N, T=T, vmr=vmr, gravity=1)
+        D = F.forward_model(m, t)["depth"][0]
+        Dc, D0 = _continuous_cia_depth(N, kappa0, T, mu)
+        errs.append(abs(D - Dc) / (Dc - D0))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert errs[0] < 3.5e-3, errs
     assert all(1.3 < o < 2.0 for o in orders), (errs, orders)
     assert max(orders) - min(orders) < 0.1, orders
 
