@@ -216,6 +216,26 @@ trx_status trx_forward(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch
                        double* depth_native, double* depth_binned, int32_t* model_status,
                        double* tau);
 
+/* Bytes of the fixed device array that trx_forward_noalloc works in. */
+#define TRX_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* trx_forward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, outputs and errors as in trx_forward (without the optical-depth
+ * output).  The call allocates and frees nothing: its workspace (per-model
+ * slabs, the atmospheric depth per native point, the work order) is carved
+ * from one fixed array of TRX_NOALLOC_SCRATCH_BYTES that each device holds
+ * from its first trx_create until the process ends.  A batch needing more
+ * (about 0.5 MB per 100-layer model on a 40000-point grid in the matrix-core
+ * modes) returns TRX_E_UNSUPPORTED with the byte count in trx_last_error and
+ * enqueues nothing: split it.  Every call on a device shares that device's
+ * array and leaves the last call's contents in it; calls on one stream are
+ * ordered, but calls whose work overlaps on one device (other streams, other
+ * contexts, other threads) race and must not be issued. */
+trx_status trx_forward_noalloc(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch,
+                               const trx_bins* bins, trx_precision precision,
+                               double* depth_native, double* depth_binned, int32_t* model_status);
+
 /* chi^2 = sum_c ((D_c - obs_c)/sigma_c)^2 and its gradient, per model.
  *  obs        DEVICE [B][n_ch]; sigma DEVICE [n_ch] (> 0).
  *  chi2       DEVICE [B]

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,36 @@ __global__ void k_copy_status(const uint8_t* ws, int64_t slab, const int32_t* B_
   if (b < nb) out[b] = reinterpret_cast<const ModelHdr*>(ws + (int64_t)b * slab)->status;
 }
 
+// Workspace of trx_forward_noalloc: one fixed array that each device holds
+// from the first use of this code object until the process ends.  In host
+// code the name is a stand-in for the symbol, not a device address: its
+// address on a device is taken once, with that device current, by
+// scratch_address(), and only that address is handed to kernels.
+__device__ __align__(256) uint8_t scratch[TRX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxScratchDevices];
+hipError_t g_scratch_err[kMaxScratchDevices];
+void* g_scratch_ptr[kMaxScratchDevices];
+
+// Device address of `scratch` on `device`, which must be the current
+// device; looked up on the first call per device and kept.
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[device] = true;
+  }
+  *out = g_scratch_ptr[device];
+  return g_scratch_err[device];
+}
+
 }  // namespace
 
 trx_status trx::upload(trx_ctx* c, const double* host, int64_t n, double** d64, float** d32,
@@ -118,6 +149,10 @@ extern "C" trx_status trx_create(int device, trx_ctx** out) {
     c->n_cu = prop.multiProcessorCount;
     snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
   }
+  // the no-allocation workspace of this device (a failure is reported by
+  // trx_forward_noalloc, the only user)
+  void* sp = nullptr;
+  (void)scratch_address(device, &sp);
   *out = c;
   return TRX_OK;
 }
@@ -539,6 +574,48 @@ extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_bat
                          depth_native, depth_binned, model_status, false, tau);
 }
 
+extern "C" trx_status trx_forward_noalloc(trx_ctx* c, const trx_tables* t, const trx_batch* bt,
+                                          const trx_bins* bins, trx_precision precision,
+                                          double* depth_native, double* depth_binned,
+                                          int32_t* model_status) {
+  if (!c) return TRX_E_INVALID_ARG;
+  c->err.clear();
+  trx_status s = check_batch(c, t, bt, precision);
+  if (s != TRX_OK) return s;
+  if (!model_status) return set_err(c, TRX_E_INVALID_ARG, "model_status is required");
+  if (depth_binned && !bins) return set_err(c, TRX_E_INVALID_ARG, "depth_binned requires bins");
+  if (bins && bins->tables != t) return set_err(c, TRX_E_INVALID_ARG, "bins were made for other tables");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_err(c, e, "trx_forward_noalloc");
+  void* base = nullptr;
+  e = scratch_address(c->device, &base);
+  if (e != hipSuccess || !base)
+    return set_err(c, TRX_E_DEVICE, "trx_forward_noalloc: no scratch array on device %d (%s)", c->device,
+                   hipGetErrorString(e));
+  // carve the workspace of trx_forward (slabs, atmospheric depth, work
+  // order) from the array, each part 256-byte aligned
+  const Layout L = make_layout(bt->max_layers, precision, false, t->dev);
+  const size_t esz = precision == TRX_FP64 ? 8 : 4;
+  size_t used = 0;
+  auto take = [&](size_t bytes) { const size_t o = used; used += (bytes + 255) / 256 * 256; return o; };
+  const size_t o_ws = take((size_t)bt->B * (size_t)L.slab);
+  const size_t o_aws = take((size_t)bt->B * (size_t)t->dev.n_wn * esz);
+  const size_t o_sched = take(SchedBufs::bytes(bt->B));
+  if (used > (size_t)TRX_NOALLOC_SCRATCH_BYTES)
+    return set_err(c, TRX_E_UNSUPPORTED,
+                   "trx_forward_noalloc: %d models of up to %d layers on %d wavenumbers need %zu bytes of "
+                   "workspace, more than the %zu bytes of the fixed scratch array; split the batch",
+                   bt->B, bt->max_layers, t->dev.n_wn, used, (size_t)TRX_NOALLOC_SCRATCH_BYTES);
+  uint8_t* p = (uint8_t*)base;
+  // no profiling events either: creating them may allocate
+  c->no_events = true;
+  s = enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision,
+                      default_config(precision, bt->max_layers), p + o_ws, p + o_aws,
+                      SchedBufs::carve(p + o_sched, bt->B), depth_native, depth_binned, model_status);
+  c->no_events = false;
+  return s;
+}
+
 // --------------------------------------------------------------------------
 // measurement
 // --------------------------------------------------------------------------
@@ -554,7 +631,7 @@ static hipEvent_t take_event(trx_ctx* c) {
 }
 
 trx::ProfScope::ProfScope(trx_ctx* ctx, int k) : c(ctx), kind(k) {
-  if (!c->profile || c->capturing) return;
+  if (!c->profile || c->capturing || c->no_events) return;
   a = take_event(c);
   b = take_event(c);
   hipEventRecord(a, c->stream);

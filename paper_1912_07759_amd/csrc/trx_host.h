@@ -30,6 +30,7 @@ struct trx_ctx {
   double total_ms[TRX_KERNEL_CLASSES] = {0};
   int launches[TRX_KERNEL_CLASSES] = {0};
   bool capturing = false;
+  bool no_events = false;   // trx_forward_noalloc: record no profiling events
 };
 
 struct trx_tables {

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "TRX_OK", 1: "TRX_E_INVALID_ARG", 2: "TRX_E_OUT_OF_MEMORY",
 
 EXPORTS = ["trx_create", "trx_destroy", "trx_last_error", "trx_set_stream",
            "trx_synchronize", "trx_tables_create", "trx_tables_destroy",
-           "trx_bins_create", "trx_bins_destroy", "trx_forward", "trx_chi2_grad",
+           "trx_bins_create", "trx_bins_destroy", "trx_forward", "trx_forward_noalloc",
+           "trx_chi2_grad",
            "trx_plan_create", "trx_plan_destroy", "trx_plan_batch", "trx_plan_launch",
            "trx_autotune", "trx_plan_set_variant", "trx_plan_describe", "trx_profile",
            "trx_profile_read"]
@@ -292,6 +293,19 @@ def forward(ctx, tables, batch, bins=None, precision=FP64, native=True, binned=T
                                 bins.h if bins is not None else None, _prec(precision),
                                 _ptr(out_native), _ptr(out_binned), _ptr(out_status),
                                 _ptr(out_tau)))
+    return out_native, out_binned, out_status
+
+
+def forward_noalloc(ctx, tables, batch, bins, precision, out_native, out_binned, out_status):
+    """trx_forward_noalloc: the forward model in the library's fixed device
+    array (no device memory is allocated by the library).  The outputs are
+    caller tensors as for trx_forward (out_native / out_binned may be None);
+    returns them."""
+    ctx.bind_stream()
+    bc = batch.cstruct()
+    ctx.check(lib().trx_forward_noalloc(ctx.h, tables.h, ctypes.byref(bc),
+                                        bins.h if bins is not None else None, _prec(precision),
+                                        _ptr(out_native), _ptr(out_binned), _ptr(out_status)))
     return out_native, out_binned, out_status
 
 
