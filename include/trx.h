@@ -247,10 +247,14 @@ trx_status trx_forward_noalloc(trx_ctx* ctx, const trx_tables* t, const trx_batc
  *  recompute  1: the opacity and optical depth are recomputed in the
  *             backward pass instead of stored (the only mode built).
  * `precision` is the arithmetic of the forward pass, i.e. of the residual
- * D - obs (TRX_FP64 holds the gradient to 1e-4 of the FP64 reference near
- * the optimum, where the residual is at the noise level); the backward
- * contractions take FP32 operands split into bf16 pieces (FP32 accuracy)
- * and the layer-level adjoints are FP64.  A model with more than 128
+ * D - obs, which near the optimum is at the noise level: there the matrix-
+ * core modes take an accurate depth epilogue (each 1 - e^-tau_j to a few
+ * FP32 units, the annulus sum in FP64), so that TRX_FP32 holds the gradient
+ * to 1e-4 of the FP64 reference like TRX_FP64 (TRX_BF16_SPLIT2 keeps the
+ * 16-bit rounding of the path x weight products: about 4e-5).  The
+ * backward contractions take FP32 operands split into bf16 pieces (FP32
+ * accuracy) and the layer-level adjoints are FP64.  Every sum runs in a
+ * fixed order: the same call gives the same bits.  A model with more than 128
  * opacity slots (distinct table corners it interpolates from, plus CIA
  * temperature nodes) is flagged TRX_MODEL_GRAD_UNSUPPORTED with NaN
  * gradient outputs.

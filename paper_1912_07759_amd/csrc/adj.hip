@@ -132,6 +132,9 @@ __device__ inline f32x16 mfma_block(const float (&av)[8], const float (&bv)[8], 
 }
 
 // ---- chi^2 and the per-point cotangent Dbar_i ---------------------------
+// Dbar_c = 2 (D_c - O_c)/sigma_c^2 per channel; Dbar_i = sum_c Dbar_c w_ci /
+// sum_i' w_ci' per native point, summed over the point's channels in
+// ascending order (no atomics: the same bits every run).
 __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
   constexpr int kW = 4;   // waves of this kernel
   const int b = blockIdx.x;
@@ -148,9 +151,7 @@ __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
     return;
   }
   const int lo = hd->lo, hi = hd->hi, W = a.tab.n_wn;
-  float* dbar = a.dbar + (int64_t)b * W;
-  for (int i = lo + tid; i < hi; i += 256) dbar[i] = 0.f;
-  __syncthreads();
+  double* coef = a.coef + (int64_t)b * a.n_ch;
   __shared__ double s_part[2][kW];
   double c2 = 0.0, sd = 0.0;
   for (int c = wave; c < a.n_ch; c += kW) {
@@ -165,14 +166,19 @@ __global__ __launch_bounds__(256) void k_chi2_dbar(AdjArgs a) {
     const double db = 2.0 * r / sg;
     c2 += r * r;
     sd += db;
-    const double coef = db / ws;
-    for (int i = i0 + lane; i < i1; i += 64) atomicAdd(&dbar[i], (float)(coef * w[i]));
+    if (lane == 0) coef[c] = ws > 0.0 ? db / ws : 0.0;
   }
   if (lane == 0) {
     s_part[0][wave] = c2;
     s_part[1][wave] = sd;
   }
-  __syncthreads();
+  __syncthreads();   // coef of every channel written (workgroup-scope fence)
+  float* dbar = a.dbar + (int64_t)b * W;
+  for (int i = lo + tid; i < hi; i += 256) {
+    double t = 0.0;
+    for (int64_t k = a.pt_off[i]; k < a.pt_off[i + 1]; ++k) t = fma(coef[a.pt_ch[k]], a.pt_w[k], t);
+    dbar[i] = (float)t;
+  }
   if (tid == 0) {
     double t2 = 0.0, ts = 0.0;
     for (int w = 0; w < kW; ++w) {
@@ -192,12 +198,19 @@ struct ItemLds {
   float* tbar;   // [NP][kLd] taubar of the span
   float2* aw;    // [NP] (A_j/Rs^2, PR_j)
   float* rpart;  // [waves][64] Rayleigh sums by wave
-  float* rbar;   // [64] Rbar of the span
+  float* rbp;    // [NRB][64] Rbar of the span by ray block
   int32_t* sid;  // [kKG] table row of each slot
   float* chi;    // [TRX_MAX_ABSORBERS]
   float* ciaw;   // [TRX_MAX_CIA]
   float* chis;   // [kMaxSpecies]
-  float* pacc;   // [G.o_P] this item's partial sums below the Pbar block
+  // this item's partial sums, each element written by one lane only (the
+  // same bits every run): Abar_j and PRbar_j by column block [2][NP],
+  // chibar and the CIA-weight adjoints by wave [waves][kMaxSpecies],
+  // [waves][TRX_MAX_CIA]
+  float* abp;
+  float* prp;
+  float* chp;
+  float* cwp;
 };
 
 __host__ __device__ inline size_t carve(const Layout& L, const GradAcc& G, int nw, unsigned char* base,
@@ -213,12 +226,15 @@ __host__ __device__ inline size_t carve(const Layout& L, const GradAcc& G, int n
   s.tbar = (float*)take((size_t)L.NP * kLd * 4);
   s.aw = (float2*)take((size_t)L.NP * 8);
   s.rpart = (float*)take((size_t)nw * kCols * 4);
-  s.rbar = (float*)take((size_t)kCols * 4);
+  s.rbp = (float*)take((size_t)L.NRB * kCols * 4);
   s.sid = (int32_t*)take(kKG * 4);
   s.chi = (float*)take(TRX_MAX_ABSORBERS * 4);
   s.ciaw = (float*)take(TRX_MAX_CIA * 4);
   s.chis = (float*)take(kMaxSpecies * 4);
-  s.pacc = (float*)take((size_t)G.o_P * 4);
+  s.abp = (float*)take((size_t)2 * L.NP * 4);
+  s.prp = (float*)take((size_t)2 * L.NP * 4);
+  s.chp = (float*)take((size_t)nw * kMaxSpecies * 4);
+  s.cwp = (float*)take((size_t)nw * TRX_MAX_CIA * 4);
   if (out) *out = s;
   return o;
 }
@@ -314,10 +330,16 @@ void k_adj_item(AdjArgs a) {
     if (tid < TRX_MAX_ABSORBERS) s.chi[tid] = hd->chi_abs32[tid];
     if (tid < TRX_MAX_CIA) s.ciaw[tid] = hd->cia_w32[tid];
     if (tid < kMaxSpecies) s.chis[tid] = hd->chi_s32[tid];
-    for (int e = tid; e < G.o_P; e += 64 * NW) s.pacc[e] = 0.f;
+    for (int e = tid; e < 2 * L.NP; e += 64 * NW) {
+      s.abp[e] = 0.f;
+      s.prp[e] = 0.f;
+    }
+    for (int e = tid; e < NW * kMaxSpecies; e += 64 * NW) s.chp[e] = 0.f;
+    for (int e = tid; e < NW * TRX_MAX_CIA; e += 64 * NW) s.cwp[e] = 0.f;
   }
   __syncthreads();
-  float* acc = s.pacc;
+  float* chp = s.chp + wave * kMaxSpecies;   // this wave's chibar partials
+  float* cwp = s.cwp + wave * TRX_MAX_CIA;
 
   // Pbar tiles (32 rays x 32 slots) of this wave, t = wave + 8 u, kept in
   // registers over the item's spans
@@ -352,7 +374,6 @@ void k_adj_item(AdjArgs a) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) s.rows[(s0 + i) * kLd + lane] = v[i];
     }
-    if (tid < kCols) s.rbar[tid] = 0.f;
     __syncthreads();
 
     // tau tiles (32 rays x 32 columns), t = wave, wave + 8: tau = P M + PR R
@@ -403,12 +424,12 @@ void k_adj_item(AdjArgs a) {
         const float ab = half_sum(-Db * expm1f(-x));
         const float pr = half_sum(tv * Rc);
         if (lc == 0 && j < N) {
-          atomicAdd(acc + G.o_A + j, ab);
-          atomicAdd(acc + G.o_PR + j, pr);
+          s.abp[tcb * L.NP + j] += ab;
+          s.prp[tcb * L.NP + j] += pr;
         }
       }
       rs += __shfl_xor(rs, 32, 64);
-      if (hl == 0) atomicAdd(&s.rbar[c], rs);
+      if (hl == 0) s.rbp[rb * kCols + c] = rs;
     }
     __syncthreads();
 
@@ -513,7 +534,7 @@ void k_adj_item(AdjArgs a) {
         for (int ii = 0; ii < DA; ++ii) {
           if (i0 + ii < tb.n_abs) {
             const float t = wave_sum(acc_i[ii]);
-            if (lane == 0) atomicAdd(acc + G.o_chi + i0 + ii, t);
+            if (lane == 0) chp[i0 + ii] += t;
           }
         }
       }
@@ -541,7 +562,7 @@ void k_adj_item(AdjArgs a) {
               if (t < K) acc_p = fmaf(s.rows[t * kLd + lane], cv[pp][k], acc_p);
             }
             acc_p = wave_sum(acc_p);
-            if (lane == 0) atomicAdd(acc + G.o_cw + p0 + pp, acc_p);
+            if (lane == 0) cwp[p0 + pp] += acc_p;
           }
         }
       }
@@ -553,11 +574,12 @@ void k_adj_item(AdjArgs a) {
           acc_p = fmaf(s.rows[t * kLd + lane], tp[(int64_t)s.sid[t] * W + cc], acc_p);
         if (nU + wave + NW * kCN < K) {
           acc_p = wave_sum(acc_p);
-          if (lane == 0) atomicAdd(acc + G.o_cw + p, acc_p);
+          if (lane == 0) cwp[p] += acc_p;
         }
       }
       // Rayleigh: the wave's species q = wave + 8 k, loads first
-      const float rl = s.rbar[lane];
+      float rl = 0.f;
+      for (int rb = 0; rb < nrb; ++rb) rl += s.rbp[rb * kCols + lane];
       constexpr int kRS = (kMaxSpecies + NW - 1) / NW;
       float rv[kRS];
 #pragma unroll
@@ -570,7 +592,7 @@ void k_adj_item(AdjArgs a) {
         const int q = wave + NW * k;
         if (q < ns) {
           const float t = wave_sum(rl * rv[k]);
-          if (lane == 0) atomicAdd(acc + G.o_chi + q, t);
+          if (lane == 0) chp[q] += t;
         }
       }
     }
@@ -579,7 +601,19 @@ void k_adj_item(AdjArgs a) {
 
   // this item's partial sums, reduced per model in a fixed order later
   float* dst = a.part + ((int64_t)b * a.n_items + item) * G.n;
-  for (int e = tid; e < G.o_P; e += 64 * NW) dst[e] = s.pacc[e];
+  for (int e = tid; e < G.o_P; e += 64 * NW) {
+    float v = 0.f;
+    if (e >= G.o_A && e < G.o_A + L.NP) {
+      v = s.abp[e - G.o_A] + s.abp[L.NP + e - G.o_A];
+    } else if (e >= G.o_PR && e < G.o_PR + L.NP) {
+      v = s.prp[e - G.o_PR] + s.prp[L.NP + e - G.o_PR];
+    } else if (e >= G.o_chi && e < G.o_chi + kMaxSpecies) {
+      for (int w = 0; w < NW; ++w) v += s.chp[w * kMaxSpecies + e - G.o_chi];
+    } else if (e >= G.o_cw && e < G.o_cw + TRX_MAX_CIA) {
+      for (int w = 0; w < NW; ++w) v += s.cwp[w * TRX_MAX_CIA + e - G.o_cw];
+    }
+    dst[e] = v;
+  }
 #pragma unroll
   for (int u = 0; u < kPT; ++u) {
     const int t = wave + NW * u;
@@ -705,6 +739,15 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
     return 2.0 * (h1 - h0) * (2.0 * Rp + h0 + h1) / (q1 + qv(h0, zj));
   };
 
+  // dchi2/d dl[j][l]: the path x weight products, the Rayleigh path and the
+  // deck's optical depth of ray j, each through layer l's weight
+  auto dlbar = [&](int j, int l) -> double {
+    const double* pr = Pb + (int64_t)j * kKG;
+    double d = PRb[j] * sW[l][6] + sTcb[j] * sW[l][7];
+    for (int q = 0; q < nq; ++q) d += pr[sS[l][q]] * sW[l][q];
+    return d;
+  };
+
   // temperatures through the weights: thread per layer
   for (int l = tid; l < N; l += kPM) {
     double wb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -725,29 +768,40 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
   double rpb = 0.0;
   for (int j = tid; j < N; j += kPM) {
     const double zj = sZ[j];
-    const double* pr = Pb + (int64_t)j * kKG;
     double zb = 0.0;
     double q0 = 0.0;
     for (int l = j; l < N; ++l) {
-      double dlb = PRb[j] * sW[l][6] + sTcb[j] * sW[l][7];
-      for (int q = 0; q < nq; ++q) dlb += pr[sS[l][q]] * sW[l][q];
-      const double g = 2.0 * dlb;
+      const double g = 2.0 * dlbar(j, l);
       const double h1 = sH[l + 1];
       const double q1 = qv(h1, zj);
       if (q1 > 0.0) {
         zb -= g * (Rp + zj) / q1;
         rpb += g * (h1 - zj) / q1;
-        atomicAdd(&sHb[l + 1], g * (Rp + h1) / q1);
       }
       if (l > j && q0 > 0.0) {
         const double h0 = sH[l];
         zb += g * (Rp + zj) / q0;
         rpb -= g * (h0 - zj) / q0;
-        atomicAdd(&sHb[l], -g * (Rp + h0) / q0);
       }
       q0 = q1;
     }
     acc[G.o_z + j] += zb;
+  }
+  // shell boundaries: thread per boundary m >= 1 (h_0 = 0 is fixed), over
+  // the rays below it; boundary m is the outer edge of shell m - 1 and the
+  // inner edge of shell m (for the rays below layer m)
+  for (int m = tid + 1; m <= N; m += kPM) {
+    const double hm = sH[m];
+    double t = 0.0;
+    for (int j = 0; j < m; ++j) {
+      const double q = qv(hm, sZ[j]);
+      if (q > 0.0) {
+        double g = dlbar(j, m - 1);
+        if (m < N) g -= dlbar(j, m);
+        t += 2.0 * g / q;
+      }
+    }
+    sHb[m] = t * (Rp + hm);
   }
   rpb = wave_sum_d(rpb);
   if ((tid & 63) == 0) sRp[tid >> 6] = rpb;

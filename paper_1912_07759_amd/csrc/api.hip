@@ -321,6 +321,21 @@ extern "C" trx_status trx_bins_create(trx_ctx* c, const trx_tables* t, int32_t n
       w.push_back(std::max(ov, 0.0) / (ehi[i] - elo[i]));
     }
   }
+  // the same weights by native point, channels ascending
+  std::vector<int64_t> poff(W + 1, 0);
+  for (int k = 0; k < n_ch; ++k)
+    for (int i = i0[k]; i < i1[k]; ++i) ++poff[i + 1];
+  for (int i = 0; i < W; ++i) poff[i + 1] += poff[i];
+  std::vector<int32_t> pch(std::max<int64_t>(poff[W], 1));
+  std::vector<double> pw(std::max<int64_t>(poff[W], 1));
+  {
+    std::vector<int64_t> fill(poff.begin(), poff.end() - 1);
+    for (int k = 0; k < n_ch; ++k)
+      for (int i = i0[k]; i < i1[k]; ++i) {
+        pch[fill[i]] = k;
+        pw[fill[i]++] = w[off[k] + (i - i0[k])];
+      }
+  }
   if (w.empty()) w.push_back(0.0);
   hipSetDevice(c->device);
   trx_bins* bn = new trx_bins();
@@ -337,6 +352,9 @@ extern "C" trx_status trx_bins_create(trx_ctx* c, const trx_tables* t, int32_t n
   put((void**)&bn->i1, i1.data(), n_ch * sizeof(int32_t));
   put((void**)&bn->off, off.data(), n_ch * sizeof(int64_t));
   put((void**)&bn->w, w.data(), w.size() * sizeof(double));
+  put((void**)&bn->poff, poff.data(), poff.size() * sizeof(int64_t));
+  put((void**)&bn->pch, pch.data(), pch.size() * sizeof(int32_t));
+  put((void**)&bn->pw, pw.data(), pw.size() * sizeof(double));
   if (e != hipSuccess) {
     for (void* p : bn->owned) hipFree(p);
     delete bn;
@@ -442,6 +460,9 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   f.persistent = persistent ? 1 : 0;
   f.group = rc.group;
   f.span_group = rc.span_group > 0 ? rc.span_group : 1;
+  // the residual D - obs of a chi^2 gradient near the optimum is at the
+  // noise level: its forward pass takes the accurate depth epilogue
+  f.accurate = grad_layout ? 1 : 0;
   {
     ProfScope ps(c, TRX_KERNEL_FORWARD);
     if (precision == TRX_FP64) {
@@ -465,12 +486,29 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   return TRX_OK;
 }
 
-size_t trx::grad_scratch_bytes(int B, int n_wn, int n_ch, int NP) {
+GradScratch trx::carve_grad_scratch(void* base, int B, int n_wn, int n_ch, int NP) {
   const GradAcc G = make_grad_acc(NP);
   const size_t spans = (size_t)(n_wn + kSpanCols - 1) / kSpanCols;
   const size_t items = (spans + kAdjSpanGroup - 1) / kAdjSpanGroup;
-  return (size_t)B * G.n * 8 + (size_t)B * n_ch * 8 + (size_t)B * n_wn * 4 + 256 +
-         (size_t)B * items * G.n * 4 + 1024;
+  uint8_t* p = (uint8_t*)base;
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* r = p ? p + o : nullptr;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  GradScratch g;
+  g.acc = (double*)take((size_t)B * G.n * 8);
+  g.binned = (double*)take((size_t)B * n_ch * 8);
+  g.coef = (double*)take((size_t)B * n_ch * 8);
+  g.dbar = (float*)take((size_t)B * n_wn * 4);
+  g.part = (float*)take((size_t)B * items * G.n * 4);
+  g.bytes = o;
+  return g;
+}
+
+size_t trx::grad_scratch_bytes(int B, int n_wn, int n_ch, int NP) {
+  return carve_grad_scratch(nullptr, B, n_wn, n_ch, NP).bytes;
 }
 
 trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B,
@@ -491,12 +529,8 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
     if ((s = ensure_buffer(c, grad, grad_scratch_bytes(B, W, bins->n_ch, L.NP), "workspace")) != TRX_OK)
       return s;
   }
-  uint8_t* gp = (uint8_t*)grad.ptr;
-  double* acc = (double*)gp;
-  double* binned_tmp = (double*)(gp + (size_t)B * G.n * 8);
-  float* dbar = (float*)(gp + (size_t)B * G.n * 8 + (size_t)B * bins->n_ch * 8);
-  float* part = (float*)(gp + ((size_t)B * G.n * 8 + (size_t)B * bins->n_ch * 8 + (size_t)B * W * 4 + 255) / 256 * 256);
-  double* binned = depth_binned ? depth_binned : binned_tmp;
+  const GradScratch gs = carve_grad_scratch(grad.ptr, B, W, bins->n_ch, L.NP);
+  double* binned = depth_binned ? depth_binned : gs.binned;
   trx_status s = enqueue_forward(c, t, db, B, B_dev, max_layers, bins, precision, rc, (uint8_t*)ws.ptr,
                                  aws.ptr, SchedBufs::carve(sched.ptr, B), nullptr, binned, status, true);
   if (s != TRX_OK) return s;
@@ -511,13 +545,15 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   a.B = B;
   a.n_ch = bins->n_ch;
   a.ch_i0 = bins->i0; a.ch_i1 = bins->i1; a.ch_off = bins->off; a.ch_w = bins->w;
+  a.pt_off = bins->poff; a.pt_ch = bins->pch; a.pt_w = bins->pw;
+  a.coef = gs.coef;
   a.binned = binned;
   a.obs = obs;
   a.sigma = sigma;
   a.chi2 = chi2;
-  a.dbar = dbar;
-  a.acc = acc;
-  a.part = part;
+  a.dbar = gs.dbar;
+  a.acc = gs.acc;
+  a.part = gs.part;
   a.n_spans = (W + kSpanCols - 1) / kSpanCols;
   a.span_group = kAdjSpanGroup;
   a.n_items = (a.n_spans + kAdjSpanGroup - 1) / kAdjSpanGroup;

@@ -33,7 +33,16 @@
 // adds the Rayleigh term, then (A_j/Rs^2)(1 - exp(-tau)) over the 32 rays of
 // a block per column (two lanes per column, one cross-lane exchange) into a
 // per-ray-block partial in LDS, and the partials are summed in ray-block
-// order (same bits every run).
+// order (same bits every run).  The fast epilogue takes the sum as the ray
+// block's sum of A_j less sum_j A_j e^{-tau_j}; its FP32 rounding is about
+// 1e-7 of the block's sum of A_j whatever tau, which is far inside the
+// depth's tolerance but, being the same for every column, shows in chi^2
+// gradients near the optimum (so does the FP32 sum over rays that are
+// opaque at every column: its rounding is one constant per model).  The
+// accurate epilogue (the forward pass of the gradient) forms each
+// 1 - e^{-tau_j} to a relative error of a few FP32 units (a range-reduced
+// expm1) and sums A_j/Rs^2 (1 - e^{-tau_j}) in FP64 with A_j in FP64, so
+// that no rounding is shared by every column.
 #include "trx_internal.h"
 
 #include <type_traits>
@@ -71,12 +80,15 @@ struct Cfg {
   static constexpr int bdw = MODE == TRX_FP32 ? kKC * 64 : kKC * npc * 32;
 };
 
-template <int MODE, int RBW>
+template <int MODE, int RBW, bool ACC>
 struct Smem {
   // B operand of the staged slot chunk
   __attribute__((aligned(16))) uint32_t bfrag[Cfg<MODE, RBW>::bdw];
   float part[kWaves * RBW][kCols];  // per-ray-block depth partials
   float2 aw[TRX_MAX_LAYERS_MFMA];   // per ray: A_j/Rs^2, -PR_j / ln 2
+  // accurate epilogue: per ray A_j/Rs^2 in FP64, per-ray-block FP64 partials
+  double a64[ACC ? TRX_MAX_LAYERS_MFMA : 1];
+  double partd[ACC ? kWaves * RBW : 1][ACC ? kCols : 1];
   float rpart[kWaves][kCols];       // Rayleigh sums by wave
   int32_t sid[kKC];                 // table rows of the chunk's slots
   float chi[TRX_MAX_ABSORBERS];
@@ -97,6 +109,31 @@ __device__ inline float bf16_lo_f(uint32_t p) { return __uint_as_float(p << 16);
 __device__ inline float bf16_hi_f(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
 
 constexpr float kNegLog2e32 = -1.4426950408889634f;   // -1 / ln 2
+
+// 1 - 2^x for x = -tau / ln 2 to a relative error of a few FP32 units, with
+// rounding errors that do not share a sign: 2^x = 2^-k e^y with k the
+// integer nearest -x and y = (x + k) ln 2, |y| <= ln 2 / 2 (x + k is exact);
+// e^y - 1 by its Taylor series to y^9 (truncation below 1e-11 relative);
+// then 1 - 2^x = -(2^-k (e^y - 1) + (2^-k - 1)), one rounding, and for
+// k = 0 the series itself (no cancellation for small tau).  tau is capped
+// at 100, where 1 - e^{-tau} rounds to 1.
+__device__ inline float one_minus_exp2(float x) {
+  const float xc = fmaxf(x, -144.26950408889634f);
+  const float kf = __builtin_rintf(-xc);
+  const float y = (xc + kf) * 0.69314718055994531f;
+  float p = 1.f / 362880.f;
+  p = fmaf(y, p, 1.f / 40320.f);
+  p = fmaf(y, p, 1.f / 5040.f);
+  p = fmaf(y, p, 1.f / 720.f);
+  p = fmaf(y, p, 1.f / 120.f);
+  p = fmaf(y, p, 1.f / 24.f);
+  p = fmaf(y, p, 1.f / 6.f);
+  p = fmaf(y, p, 0.5f);
+  p = fmaf(y, p, 1.f);
+  const float em1 = y * p;                                      // e^y - 1
+  const float sc = __builtin_amdgcn_ldexpf(1.f, -(int)kf);      // 2^-k
+  return -fmaf(sc, em1, sc - 1.f);
+}
 
 // Ray block r (0..RBW-1) of a wave: w, then 7 - w.
 template <int RBW>
@@ -178,9 +215,10 @@ __device__ inline void mix_corners(const float* wt, int nt, int t0, const float 
 // One work item: model b, columns [64 s_first, 64 s_end) cut to its window.
 // Called by all threads of the workgroup (every early return is uniform).
 // TAU: also write the optical depth of every ray and column to a.tau (a
-// separate instantiation: the stores cost the hot kernel registers)
-template <int MODE, int RBW, bool TAU>
-__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end, Smem<MODE, RBW>& sm) {
+// separate instantiation: the stores cost the hot kernel registers).
+// ACC: the accurate depth epilogue.
+template <int MODE, int RBW, bool TAU, bool ACC>
+__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end, Smem<MODE, RBW, ACC>& sm) {
   using C = Cfg<MODE, RBW>;
   constexpr int npc = C::npc, kAW = C::kAW, KB = C::KB;
   constexpr bool PF = C::PF;
@@ -228,6 +266,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     const float2 w = tid < nr ? awg[tid] : float2{};
     const int32_t r = K <= kKC && tid < K ? sid[tid] : 0;
     if (tid < nr) sm.aw[tid] = float2{w.x, kNegLog2e32 * w.y};
+    if constexpr (ACC) {
+      const double* A64 = reinterpret_cast<const double*>(slab + L.off_A64);
+      if (tid < nr) sm.a64[tid] = A64[tid];
+    }
     if (K <= kKC && tid < K) sm.sid[tid] = r;
     if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
     if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s32[tid];
@@ -497,11 +539,15 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
           const int cl = 32 * tcb + lc;
           const float Rc = sm.rpart[0][cl] + sm.rpart[1][cl] + sm.rpart[2][cl] + sm.rpart[3][cl];
           float s = 0.f;
+          double sd = 0.0;
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
             const float2 w = sm.aw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)];
             const float x = fmaf(w.y, Rc, acc[r][tcb][q]);   // -tau / ln 2
-            s = fmaf(w.x, __builtin_amdgcn_exp2f(x), s);
+            if constexpr (ACC)
+              sd = fma(sm.a64[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)], (double)one_minus_exp2(x), sd);
+            else
+              s = fmaf(w.x, __builtin_amdgcn_exp2f(x), s);
             if constexpr (TAU) {
               const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
               const int cg = span * kCols + cl;
@@ -509,8 +555,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
                 a.tau[(int64_t)b * a.tau_ld + (int64_t)j * W + cg] = -0.69314718055994531 * (double)x;
             }
           }
-          s += __shfl_xor(s, 32, 64);
-          if (hl == 0) sm.part[rb][cl] = awsum[r] - s;
+          if constexpr (ACC) {
+            sd += __shfl_xor(sd, 32, 64);
+            if (hl == 0) sm.partd[rb][cl] = sd;
+          } else {
+            s += __shfl_xor(s, 32, 64);
+            if (hl == 0) sm.part[rb][cl] = awsum[r] - s;
+          }
         }
       }
     }
@@ -520,24 +571,32 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     // are rewritten only after the next span's staging barrier)
     __syncthreads();
     if (wave == 0 && valid) {
-      float atm = 0.f;
-      for (int rb = 0; rb < nrb; ++rb) atm += sm.part[rb][lane];
       const int64_t o = (int64_t)b * W + col;
-      reinterpret_cast<float*>(a.aws)[o] = atm;
-      if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + (double)atm;
-      if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
+      if constexpr (ACC) {
+        double atm = 0.0;
+        for (int rb = 0; rb < nrb; ++rb) atm += sm.partd[rb][lane];
+        reinterpret_cast<float*>(a.aws)[o] = (float)atm;
+        if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + atm;
+        if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
+      } else {
+        float atm = 0.f;
+        for (int rb = 0; rb < nrb; ++rb) atm += sm.part[rb][lane];
+        reinterpret_cast<float*>(a.aws)[o] = atm;
+        if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + (double)atm;
+        if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
+      }
     }
   }
 }
 
 // One workgroup per (model, span).
-template <int MODE, int RBW, bool TAU>
+template <int MODE, int RBW, bool TAU, bool ACC>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
-  __shared__ Smem<MODE, RBW> sm;
+  __shared__ Smem<MODE, RBW, ACC> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
   const int S = a.span_group;
-  process<MODE, RBW, TAU>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
+  process<MODE, RBW, TAU, ACC>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
 }
 
 // Persistent: a fixed grid pops chunks of (span, model) items from kQueues
@@ -547,9 +606,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
 // one XCD share the table rows of few spans in its L2, and moves on to the
 // other queues when its own is drained.  Every workgroup leaves once all
 // queues are drained.
-template <int MODE, int RBW>
+template <int MODE, int RBW, bool ACC>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_mfma_persist(FwdArgs a) {
-  __shared__ Smem<MODE, RBW> sm;
+  __shared__ Smem<MODE, RBW, ACC> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int S = a.span_group;
   const int ngroups = ((a.tab.n_wn + kCols - 1) / kCols + S - 1) / S;
@@ -588,19 +647,19 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW, false>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
+        if (bm >= 0) process<MODE, RBW, false, ACC>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
       }
       __syncthreads();
     }
   }
 }
 
-template <int MODE, int RBW>
+template <int MODE, int RBW, bool ACC>
 int occupancy() {
   static int blocks = 0;
   if (!blocks) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW>, 64 * kWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, ACC>, 64 * kWaves, 0) !=
             hipSuccess || nb < 1)
       nb = 1;
     blocks = nb;
@@ -609,18 +668,26 @@ int occupancy() {
 }
 
 // The optical-depth output always takes the one-workgroup-per-item kernel.
-template <int MODE, int RBW>
-void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
+template <int MODE, int RBW, bool ACC>
+void launch_rbw_acc(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
   if (a.persistent && !a.tau) {
-    const int grid = n_cu * occupancy<MODE, RBW>();
-    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW>), dim3(grid), dim3(64 * kWaves), 0, s, a);
+    const int grid = n_cu * occupancy<MODE, RBW, ACC>();
+    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, ACC>), dim3(grid), dim3(64 * kWaves), 0, s, a);
   } else {
     dim3 grid(B_grid, ((a.tab.n_wn + kCols - 1) / kCols + a.span_group - 1) / a.span_group);
     if (a.tau)
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true, false>), grid, dim3(64 * kWaves), 0, s, a);
     else
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false, ACC>), grid, dim3(64 * kWaves), 0, s, a);
   }
+}
+
+// The optical-depth output never takes the accurate epilogue (it writes tau,
+// not the depth's rounding).
+template <int MODE, int RBW>
+void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
+  if (a.accurate && !a.tau) launch_rbw_acc<MODE, RBW, true>(a, B_grid, n_cu, s);
+  else launch_rbw_acc<MODE, RBW, false>(a, B_grid, n_cu, s);
 }
 
 template <int MODE>

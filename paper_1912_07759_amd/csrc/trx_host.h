@@ -48,6 +48,11 @@ struct trx_bins {
   int32_t* i1 = nullptr;
   int64_t* off = nullptr;
   double* w = nullptr;
+  // the same weights by native point: point i lies in the channels
+  // pch[poff[i] .. poff[i+1]) (ascending) with weights pw
+  int64_t* poff = nullptr;
+  int32_t* pch = nullptr;
+  double* pw = nullptr;
   std::vector<void*> owned;
 };
 
@@ -105,6 +110,16 @@ trx_status enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, 
                            double* depth_binned, int32_t* status, bool grad_layout = false,
                            double* tau = nullptr);
 
+// Gradient workspace carved from one buffer (base null: sizes only).
+struct GradScratch {
+  double* acc;        // [B][G.n] per-model FP64 accumulators
+  double* binned;     // [B][n_ch] binned depth when the caller asks for none
+  double* coef;       // [B][n_ch] dchi2/dD_c over the channel's weight sum
+  float* dbar;        // [B][n_wn] dchi2/dD_i
+  float* part;        // [B][n_items][G.n] per-item partial sums
+  size_t bytes;
+};
+GradScratch carve_grad_scratch(void* base, int B, int n_wn, int n_ch, int NP);
 size_t grad_scratch_bytes(int B, int n_wn, int n_ch, int NP);
 // Forward pass on the gradient layout, chi^2, and the adjoint kernels.
 // alloc: grow the buffers as needed (false: they are already large enough).

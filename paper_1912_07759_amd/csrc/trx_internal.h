@@ -267,6 +267,7 @@ struct FwdArgs {
   int32_t persistent;     // 1: persistent grid, 0: one workgroup per (model, span)
   int32_t group;          // models per item group of the persistent order (0: all)
   int32_t span_group;     // consecutive spans per work item (matrix-core kernel)
+  int32_t accurate;       // matrix-core modes: depth epilogue accurate per element (gradient's forward)
 };
 
 void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* order, int32_t* qcount,
@@ -326,6 +327,10 @@ struct AdjArgs {
   const int32_t* ch_i1;
   const int64_t* ch_off;
   const double* ch_w;
+  const int64_t* pt_off;  // [n_wn + 1] channels of native point i: pt_ch[pt_off[i] ..]
+  const int32_t* pt_ch;
+  const double* pt_w;     // their weights w_ci
+  double* coef;           // [B][n_ch] dchi2/dD_c / sum_i w_ci
   const double* binned;   // [B][n_ch] forward result
   const double* obs;      // [B][n_ch]
   const double* sigma;    // [n_ch]

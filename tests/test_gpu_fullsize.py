@@ -103,11 +103,12 @@ def test_batched_4096_with_cloud_decks_full_size(gpu_ctx):
     _forward_full(gpu_ctx, 3, "bf16x2", 200, 4, 6, decks=True)
 
 
-def _gradient_full(ctx, cfg, tables, batch, ch, n_layers, n_check, seed):
+def _gradient_full(ctx, cfg, tables, batch, ch, n_layers, n_check, seed, precision="fp64"):
     """chi^2 gradients of workload `cfg` at full size through an autotuned
-    graph-captured gradient plan (FP64 forward), against the oracle's
-    reference gradient on point 0 (its residual is the noise) and sampled
-    points; every point valid with finite outputs."""
+    graph-captured gradient plan (forward pass in `precision`), against the
+    oracle's reference gradient on point 0 (its residual is the noise) and
+    sampled points; every point valid with finite outputs.  Returns the
+    gradient outputs and the observation."""
     from paper_1912_07759_amd import trx
     T = trx.Tables.from_synth(ctx, tables)
     bins = trx.Bins(ctx, T, ch.lo, ch.hi)
@@ -115,7 +116,7 @@ def _gradient_full(ctx, cfg, tables, batch, ch, n_layers, n_check, seed):
     truth = oracle.forward_model(batch.model(0), tables, ch)["binned"]
     noise, sigma = observation_noise(cfg, 1, len(ch.lo))
     obs = np.tile(truth + noise[0], (batch.B, 1))
-    plan = trx.Plan(ctx, T, bins, B_max=batch.B, N_max=n_layers, precision="fp64", graph=True,
+    plan = trx.Plan(ctx, T, bins, B_max=batch.B, N_max=n_layers, precision=precision, graph=True,
                     grad=True)
     plan.autotune(db)
     out = plan.launch_grad(db, obs, sigma)
@@ -130,21 +131,96 @@ def _gradient_full(ctx, cfg, tables, batch, ch, n_layers, n_check, seed):
     off = batch.layer_off
     picks = list(dict.fromkeys([0] + [int(i) for i in
                                       np.random.default_rng(seed).permutation(batch.B)[:n_check]]))
+    worst = 0.0
     for b in picks:
         ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
         err = _grad_err(g, off, b, ref)
-        print(f"  point {b} (N={int(batch.n_layers[b])}): chi2 {g['chi2'][b]:.6e} "
+        print(f"  {precision} point {b} (N={int(batch.n_layers[b])}): chi2 {g['chi2'][b]:.6e} "
               f"(oracle {ref['chi2']:.6e}), grad err {err:.2e}")
         assert abs(g["chi2"][b] - ref["chi2"]) <= 1e-5 * ref["chi2"]
-        assert err <= GRAD_TOL, (b, err)
+        worst = max(worst, err)
+    print(f"  {precision}: worst gradient error {worst:.2e} over {len(picks)} points")
+    assert worst <= GRAD_TOL, worst
+    return g, obs, sigma
 
 
-def test_gradient_256_full_size(gpu_ctx):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x2", "fp64"])
+def test_gradient_256_full_size(gpu_ctx, precision):
     """The benchmark's gradient workload: 256 points of a 100-layer free
     temperature profile, 7 absorbers, 50000 points, 100 channels, 50 ppm
-    noise on the truth's binned spectrum."""
+    noise on the truth's binned spectrum; the forward pass in FP32 (the
+    workload's own precision), split-bf16 and FP64; point 0 and 8 random
+    points against the oracle's reference gradient."""
     tables, batch, ch = make_config(4)
-    _gradient_full(gpu_ctx, 4, tables, batch, ch, 100, 3, 1)
+    _gradient_full(gpu_ctx, 4, tables, batch, ch, 100, 8, 1, precision)
+
+
+def test_gradient_256_central_differences(gpu_ctx):
+    """Central differences of chi^2, every component of 8 points of the
+    gradient workload (108 parameters each: 100 temperatures, 7 log10 mixing
+    ratios, Rp), from the library's FP64 forward model, against the
+    gradients with the FP32 and split-bf16 forwards.  Steps: 1e-4 K (the
+    temperatures stay 1e-3 K from the table nodes), 1e-6 dex, 1e-7 Rp; all
+    perturbed models run as one batch."""
+    from paper_1912_07759_amd import trx
+    tables, batch, ch = make_config(4)
+    truth = oracle.forward_model(batch.model(0), tables, ch)["binned"]
+    noise, sigma = observation_noise(4, 1, len(ch.lo))
+    obs = truth + noise[0]
+    pts = [0] + [int(i) for i in np.random.default_rng(17).permutation(np.arange(1, batch.B))[:7]]
+    sub = batch.subset(pts)
+    N, na = 100, tables.n_abs
+    # perturbed copies: point p, parameter k, sign s
+    Ts, vmr, Rp, steps = [], [], [], []
+    for p in range(len(pts)):
+        for k in range(N + na + 1):
+            for sgn in (1.0, -1.0):
+                T = sub.T_of(p).copy()
+                v = sub.log10_vmr[p].copy()
+                R = float(sub.Rp[p])
+                if k < N:
+                    h = 1e-4
+                    T[k] += sgn * h
+                elif k < N + na:
+                    h = 1e-6
+                    v[k - N] += sgn * h
+                else:
+                    h = 1e-7 * R
+                    R += sgn * h
+                Ts.append(T)
+                vmr.append(v)
+                Rp.append(R)
+                steps.append(h)
+    from synth.workloads import batch_from_models
+    fd_batch = batch_from_models(Ts, 1e6, 1e-4, np.array(vmr), np.array(Rp), sub.Rs[0], sub.GM[0], 0,
+                                 tables.n_wn)
+    Tt = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, Tt, ch.lo, ch.hi)
+    try:
+        db = trx.DeviceBatch.from_synth(fd_batch, max_layers=N)
+        _, binned, st = trx.forward(gpu_ctx, Tt, db, bins, "fp64", native=False)
+        binned, st = binned.cpu().numpy(), st.cpu().numpy()
+        assert np.all(st == 0)
+        c2 = np.sum(((binned - obs[None, :]) / sigma[None, :]) ** 2, axis=1)
+        fd = ((c2[0::2] - c2[1::2]) / (2.0 * np.array(steps[0::2]))).reshape(len(pts), N + na + 1)
+        dsub = trx.DeviceBatch.from_synth(sub, max_layers=N)
+        for mode in ("fp32", "bf16x2"):
+            g = trx.chi2_grad(gpu_ctx, Tt, dsub, bins, np.tile(obs, (len(pts), 1)), sigma, mode)
+            g = {k: v.cpu().numpy() for k, v in g.items() if v is not None}
+            assert np.all(g["status"] == 0)
+            worst = 0.0
+            for p in range(len(pts)):
+                v = np.concatenate([g["dT"][p * N:(p + 1) * N], g["dlog10_vmr"][p], [g["dRp"][p]]])
+                r = fd[p]
+                big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
+                err = max(np.linalg.norm(v - r) / np.linalg.norm(r),
+                          float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big]))))
+                print(f"  {mode} point {pts[p]}: gradient vs central differences {err:.2e}")
+                worst = max(worst, err)
+            assert worst <= GRAD_TOL, (mode, worst)
+    finally:
+        bins.close()
+        Tt.close()
 
 
 def test_large_workload_full_size(gpu_ctx):

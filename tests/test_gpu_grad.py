@@ -69,6 +69,18 @@ def test_gradient_matches_oracle(gpu_ctx, problem, mode):
     assert worst <= GRAD_TOL
 
 
+@pytest.mark.parametrize("mode", ["fp32", "bf16x2", "fp64"])
+def test_gradient_deterministic(gpu_ctx, problem, mode):
+    """Two runs of the same gradient call give the same bits: every sum of
+    the adjoint (span partials, channel cotangents, shell boundaries) runs
+    in a fixed order."""
+    tables, batch, ch, obs, sigma = problem
+    a = _gpu(gpu_ctx, tables, batch, ch, obs, sigma, mode)
+    b = _gpu(gpu_ctx, tables, batch, ch, obs, sigma, mode)
+    for k in ("chi2", "dT", "dlog10_vmr", "dRp", "status"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_gradient_central_differences(gpu_ctx, problem):
     """Central differences of chi^2 from the library's FP64 forward path
     (step 1e-4 K, 1e-6 dex, 1e-7 Rp) against the FP32 gradient."""
@@ -121,21 +133,20 @@ def test_autograd_function(gpu_ctx, problem):
     (c2 * w).sum().backward()
     ref = trx.chi2_grad(gpu_ctx, Tt, db, bins, obs, sigma, "fp32")
     counts = torch.as_tensor(np.diff(batch.layer_off), device=c2.device)
-    # a second run of the FP32 adjoint: its atomics sum the span partials in
-    # another order (floor 2e-5 of the largest component, as for the plans)
-    close = lambda a, b: torch.allclose(a, b, rtol=1e-5, atol=2e-5 * float(b.abs().max()))
-    assert close(c2, ref["chi2"])
-    assert close(T.grad, ref["dT"] * torch.repeat_interleave(w, counts))
-    assert close(v.grad, ref["dlog10_vmr"] * w[:, None])
-    assert close(R.grad, ref["dRp"] * w)
+    # a second run of the same call: the gradient is summed in a fixed order,
+    # so the Function's outputs equal it bit for bit (times the weights)
+    assert torch.equal(c2, ref["chi2"])
+    assert torch.equal(T.grad, ref["dT"] * torch.repeat_interleave(w, counts))
+    assert torch.equal(v.grad, ref["dlog10_vmr"] * w[:, None])
+    assert torch.equal(R.grad, ref["dRp"] * w)
     bins.close()
     Tt.close()
 
 
 def test_gradient_plan_graph(gpu_ctx, problem):
-    """A graph-captured gradient plan reproduces trx_chi2_grad (up to the
-    summation order of the per-model atomics), over replays with unrelated
-    eager work in between and for a smaller B on the same graph."""
+    """A graph-captured gradient plan reproduces trx_chi2_grad bit for bit,
+    over replays with unrelated eager work in between and for a smaller B on
+    the same graph."""
     from paper_1912_07759_amd import trx
     tables, batch, ch, obs, sigma = problem
     Tt = trx.Tables.from_synth(gpu_ctx, tables)
@@ -147,14 +158,10 @@ def test_gradient_plan_graph(gpu_ctx, problem):
                     grad=True)
 
     def check(out, n):
-        # the per-span FP32 partials are summed by atomics in no fixed order:
-        # with ~200 items per model each component may move by up to
-        # 200 x 2^-24 of the largest partial sum, which shows on components
-        # that cancel to near zero (hence the floor of 2e-5 of the largest)
         for k in ("chi2", "dT", "dlog10_vmr", "dRp"):
             got = out[k].cpu().numpy()
             want = ref[k][:n] if k != "dT" else ref[k][:int(batch.layer_off[n])]
-            assert np.allclose(got, want, rtol=1e-5, atol=2e-5 * np.max(np.abs(want))), k
+            assert np.array_equal(got, want), k
     try:
         for r in range(3):
             x = torch.randn(1 << 18, device="cuda").sum()
