@@ -22,3 +22,5 @@ from .forward import (  # noqa: F401
     bin_spectrum, forward_model, forward_batch, chi2,
 )
 from .adjoint import chi2_and_grad, chi2_grad_batch  # noqa: F401
+from .emission import (emission_model, emergent_intensity, gauss_legendre_mu,  # noqa: F401
+                       planck, vertical_optical_depth)
