@@ -20,7 +20,9 @@
  *   a8  chi^2 against an observation and its gradient with respect to the
  *       per-layer temperatures, log10 mixing ratios and Rp;
  *   a9  a batched form over a ragged live-point set run as one persistent,
- *       graph-captured launch (the plan API).
+ *       graph-captured launch (the plan API);
+ *   and the emission (eclipse) spectrum of the same atmospheres (Forward
+ *   Models section, emission intensity and its Gauss-Legendre flux).
  *
  * Conventions
  *  - Units are SI (Forward Models section) except: wavenumbers in cm^-1,
@@ -100,6 +102,7 @@ enum {
 #define TRX_MAX_CIA 8
 #define TRX_MAX_TGRID 128
 #define TRX_MAX_PGRID 128
+#define TRX_MAX_MU 16           /* Gauss-Legendre angles of the emission flux */
 
 /* ---- context ---------------------------------------------------------- */
 
@@ -216,6 +219,33 @@ trx_status trx_forward(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch
                        double* depth_native, double* depth_binned, int32_t* model_status,
                        double* tau);
 
+/* Emission forward model (Forward Models section: the emission intensity,
+ * its N-point Gauss-Legendre flux and F_p/F_s = I/I_s (Rp/Rs)^2) of every
+ * model of the batch: the same atmosphere and opacity as trx_forward (steps
+ * a1-a4, cloud decks included), seen as a plane-parallel slab.
+ *  - tau_l is the vertical optical depth from the top down to the bottom of
+ *    shell l (the transmission shells: h_0 = 0, midpoints, h_N = z_{N-1});
+ *    each shell emits the Planck intensity of its layer's temperature, the
+ *    surface that of the bottom layer (the temperature at maximum pressure):
+ *      I(mu) = B(T_0) e^{-tau_0/mu} + sum_l B(T_l) (e^{-tau_{l+1}/mu} - e^{-tau_l/mu});
+ *  - flux ratio 2 sum_i w_i mu_i I(mu_i) / B(T_star) (Rp/Rs)^2 with the
+ *    n_mu-point Gauss-Legendre nodes mu_i and weights w_i on [0, 1], so that
+ *    an isothermal planet at T_star gives (Rp/Rs)^2; B is Planck's law per
+ *    unit wavenumber (h, c exact SI; the batch's k_B).
+ *  n_mu        1..TRX_MAX_MU angles.
+ *  T_star_K    DEVICE [B] blackbody temperature of each model's star (a
+ *              non-positive or non-finite one flags TRX_MODEL_BAD_PROFILE).
+ *  fpfs_native DEVICE [B][n_wn] or NULL: F_p/F_s on the model's window.
+ *  fpfs_binned DEVICE [B][n_ch] or NULL (requires bins), binned as depths.
+ *  model_status DEVICE [B], required.
+ * Returns TRX_E_UNSUPPORTED for TRX_FP64 batches of more than
+ * TRX_MAX_LAYERS_MFMA layers.  No gradient of this model is built.  In the
+ * FP32 and split-bf16 modes a planet whose flux is below ~1e-38 of the
+ * star's at some wavenumber underflows to zero there. */
+trx_status trx_emission(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch, const trx_bins* bins,
+                        trx_precision precision, int32_t n_mu, const double* T_star_K,
+                        double* fpfs_native, double* fpfs_binned, int32_t* model_status);
+
 /* Bytes of the fixed device array that trx_forward_noalloc works in. */
 #define TRX_NOALLOC_SCRATCH_BYTES (64u << 20)
 
@@ -273,7 +303,9 @@ trx_status trx_chi2_grad(trx_ctx* ctx, const trx_tables* t, const trx_batch* bat
 enum {
   TRX_PLAN_GRAPH = 1,       /* replay the launch sequence from a HIP graph */
   TRX_PLAN_PERSISTENT = 2,  /* allow the persistent work-queue kernel */
-  TRX_PLAN_GRAD = 4         /* plan computes chi^2 and its gradient */
+  TRX_PLAN_GRAD = 4,        /* plan computes chi^2 and its gradient */
+  TRX_PLAN_EMISSION = 8     /* plan computes the emission spectrum (trx_emission);
+                               the native and binned outputs hold F_p/F_s */
 };
 
 /* A plan owns the workspace for up to B_max models of at most N_max layers
@@ -287,6 +319,10 @@ trx_status trx_plan_create(trx_ctx* ctx, const trx_tables* t, const trx_bins* bi
                            int32_t B_max, int32_t N_max, trx_precision precision,
                            int32_t flags, trx_plan** out);
 trx_status trx_plan_destroy(trx_plan* p);
+/* The star of a TRX_PLAN_EMISSION plan: DEVICE [B_max] temperatures
+ * (borrowed by every later launch) and the number of Gauss-Legendre angles,
+ * as in trx_emission.  Required before the first launch of such a plan. */
+trx_status trx_plan_set_star(trx_plan* p, const double* T_star_K, int32_t n_mu);
 /* Fill `out` with device input buffers owned by the plan (B = B_max,
  * max_layers = N_max, layer_off sized for B_max * N_max layers; default
  * constants He/H2 0.17, CODATA k_B and atomic mass unit, gravity 0; cloud

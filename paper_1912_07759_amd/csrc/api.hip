@@ -399,6 +399,42 @@ trx_status trx::check_batch(trx_ctx* c, const trx_tables* t, const trx_batch* bt
   return TRX_OK;
 }
 
+trx_status trx::check_emission(trx_ctx* c, int precision, int max_layers, const double* T_star, int n_mu) {
+  if (n_mu < 1 || n_mu > TRX_MAX_MU)
+    return set_err(c, TRX_E_INVALID_ARG, "n_mu must be in 1..%d", TRX_MAX_MU);
+  if (!T_star) return set_err(c, TRX_E_INVALID_ARG, "the stellar temperatures are required");
+  if (precision == TRX_FP64 && max_layers > TRX_MAX_LAYERS_MFMA)
+    return set_err(c, TRX_E_UNSUPPORTED, "emission takes at most %d layers", TRX_MAX_LAYERS_MFMA);
+  return TRX_OK;
+}
+
+// Gauss-Legendre rule on [-1, 1]: the roots x_i of the Legendre polynomial
+// P_n by Newton's method from x = cos(pi (i + 3/4)/(n + 1/2)), with P_n and
+// P_n' from the three-term recurrence (k P_k = (2k-1) x P_{k-1} - (k-1)
+// P_{k-2}) and P_n' = n (x P_n - P_{n-1})/(x^2 - 1); weights 2/((1 - x^2)
+// P_n'(x)^2).  Mapped to mu = (1 + x)/2 with weights w/2.
+void trx::gauss_legendre01(int n, double* mu, double* w) {
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double x = cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    mu[i] = 0.5 * (1.0 + x);
+    w[i] = 1.0 / ((1.0 - x * x) * dp * dp);   // half of 2 / ((1 - x^2) P_n'^2)
+  }
+}
+
 DevBatch trx::dev_batch(const trx_batch* bt) {
   DevBatch d;
   d.n_layers = bt->n_layers; d.layer_off = bt->layer_off; d.T = bt->T_K;
@@ -414,8 +450,8 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
                                 const int32_t* B_dev, int max_layers, const trx_bins* bins,
                                 int precision, const RunConfig& rc, uint8_t* ws, void* aws,
                                 const SchedBufs& sb, double* depth_native, double* depth_binned,
-                                int32_t* status, bool grad_layout, double* tau) {
-  const Layout L = make_layout(max_layers, precision, grad_layout, t->dev);
+                                int32_t* status, bool grad_layout, double* tau, const EmissionIn* em) {
+  const Layout L = make_layout(max_layers, precision, grad_layout, t->dev, em != nullptr);
   GeomArgs g;
   g.bt = db;
   g.tab = t->dev;
@@ -429,6 +465,9 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   g.depth_native = depth_native;
   g.mlay = sb.mlay;
   g.mspan = sb.mspan;
+  g.T_star = em ? em->T_star : nullptr;
+  // h c / k_B in K cm (h and c exact SI, k_B as passed)
+  g.c2 = 100.0 * 6.62607015e-34 * 299792458.0 / db.kB;
   {
     ProfScope ps(c, TRX_KERNEL_GEOMETRY);
     launch_geom(g, B, c->stream);
@@ -463,6 +502,17 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
   // the residual D - obs of a chi^2 gradient near the optimum is at the
   // noise level: its forward pass takes the accurate depth epilogue
   f.accurate = grad_layout ? 1 : 0;
+  if (em) {
+    double mu[TRX_MAX_MU], w[TRX_MAX_MU];
+    gauss_legendre01(em->n_mu, mu, w);
+    f.n_mu = em->n_mu;
+    for (int i = 0; i < em->n_mu; ++i) {
+      f.em_k64[i] = 1.0 / mu[i];
+      f.em_c64[i] = 2.0 * w[i] * mu[i];
+      f.em_k32[i] = (float)f.em_k64[i];
+      f.em_c32[i] = (float)f.em_c64[i];
+    }
+  }
   {
     ProfScope ps(c, TRX_KERNEL_FORWARD);
     if (precision == TRX_FP64) {
@@ -650,6 +700,30 @@ extern "C" trx_status trx_forward_noalloc(trx_ctx* c, const trx_tables* t, const
                       SchedBufs::carve(p + o_sched, bt->B), depth_native, depth_binned, model_status);
   c->no_events = false;
   return s;
+}
+
+extern "C" trx_status trx_emission(trx_ctx* c, const trx_tables* t, const trx_batch* bt, const trx_bins* bins,
+                                   trx_precision precision, int32_t n_mu, const double* T_star_K,
+                                   double* fpfs_native, double* fpfs_binned, int32_t* model_status) {
+  if (!c) return TRX_E_INVALID_ARG;
+  c->err.clear();
+  trx_status s = check_batch(c, t, bt, precision);
+  if (s != TRX_OK) return s;
+  if ((s = check_emission(c, precision, bt->max_layers, T_star_K, n_mu)) != TRX_OK) return s;
+  if (!model_status) return set_err(c, TRX_E_INVALID_ARG, "model_status is required");
+  if (fpfs_binned && !bins) return set_err(c, TRX_E_INVALID_ARG, "fpfs_binned requires bins");
+  if (bins && bins->tables != t) return set_err(c, TRX_E_INVALID_ARG, "bins were made for other tables");
+  hipSetDevice(c->device);
+  const Layout L = make_layout(bt->max_layers, precision, false, t->dev, true);
+  if ((s = ensure_buffer(c, c->ws, (size_t)bt->B * L.slab, "workspace")) != TRX_OK) return s;
+  const size_t esz = precision == TRX_FP64 ? 8 : 4;
+  if ((s = ensure_buffer(c, c->aws, (size_t)bt->B * t->dev.n_wn * esz, "workspace")) != TRX_OK) return s;
+  if ((s = ensure_buffer(c, c->sched, SchedBufs::bytes(bt->B), "workspace")) != TRX_OK) return s;
+  RunConfig rc = default_config(precision, bt->max_layers);
+  const EmissionIn em{T_star_K, n_mu};
+  return enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision, rc,
+                         (uint8_t*)c->ws.ptr, c->aws.ptr, SchedBufs::carve(c->sched.ptr, bt->B), fpfs_native,
+                         fpfs_binned, model_status, false, nullptr, &em);
 }
 
 // --------------------------------------------------------------------------

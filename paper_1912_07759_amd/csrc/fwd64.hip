@@ -260,6 +260,7 @@ constexpr int kR16 = 2;      // 16-ray blocks per wave per pass
 constexpr int kS64 = 4;      // spans per work item
 static_assert(TRX_MAX_LAYERS_MFMA % 16 == 0, "16-ray blocks");
 
+template <bool EM>
 struct Smem64s {
   double rows[kKC64][kLd64];                       // mixed slot rows of the chunk
   double part[TRX_MAX_LAYERS_MFMA / 16][kCols];    // per-16-ray-block depth partials
@@ -269,7 +270,27 @@ struct Smem64s {
   int32_t sid[kKC64];
   double chis[kMaxSpecies];
   double ciaw[TRX_MAX_CIA];   // CIA pair weights times kCiaScale32 (the scale of P's CIA columns)
+  double4 em[EM ? TRX_MAX_LAYERS_MFMA : 1];        // emission: the layer records
 };
+
+// One row's term of the emission flux ratio in FP64 (before (Rp/Rs)^2):
+// (B_{l-1} - B_l)/B_* G(tau_l), G(tau) = sum_i 2 w_i mu_i e^{-tau/mu_i},
+// from the records e (layer l: c2/T_l, c2 (T_{l-1} - T_l)/(T_l T_{l-1}),
+// c2 (1/T_l - 1/T_*), the deck's vertical optical depth) and em (layer
+// l - 1), the gas optical depth tau, the wavenumber nu and 1 - e^{-x_*}.
+// B/B_* = e^{x_* - x} (1 - e^{-x_*})/(1 - e^{-x}); neighbouring layers'
+// difference without cancellation as in the matrix-core kernel.
+__device__ inline double emission_term64(double4 e, double4 em, double tau, double nu, double wst,
+                                         const FwdArgs& a) {
+  const double tt = tau + e.w;
+  double G = 0.0;
+  for (int i = 0; i < a.n_mu; ++i) G = fma(a.em_c64[i], exp(-tt * a.em_k64[i]), G);
+  const double wl = -expm1(-nu * e.x), wm = -expm1(-nu * em.x);
+  const double rl = exp(-nu * e.z);
+  const double dx = nu * e.y;
+  const double dB = fabs(dx) <= 1.0 ? rl * expm1(dx) * wst / (wm * wl) : wst * (exp(-nu * em.z) / wm - rl / wl);
+  return dB * G;
+}
 
 // s[i] += sum_t wt[t] tab_t[rows[i]][col] over the tables t < nt for the
 // slots i in [i0, i1) of a group of 8 (rows of the others clamped into it).
@@ -301,8 +322,8 @@ __device__ inline void mix64(const double* tab, int64_t stride, int nt, const do
   }
 }
 
-template <bool TAU>
-__device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, Smem64s& sm) {
+template <bool TAU, bool EM>
+__device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, Smem64s<EM>& sm) {
   const int b = __builtin_amdgcn_readfirstlane(b_in);
   const Layout& L = a.L;
   const uint8_t* slab = a.ws + (int64_t)b * L.slab;
@@ -334,6 +355,7 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
   if (tid < 32 * nrb) {
     sm.A[tid] = tid < N ? A64[tid] : 0.0;
     sm.PR[tid] = tid < N ? PR64[tid] : 0.0;
+    if constexpr (EM) sm.em[tid] = reinterpret_cast<const double4*>(slab + L.off_em64)[tid];
   }
   if (K <= kKC64 && tid < K) sm.sid[tid] = sid[tid];
   if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s[tid];
@@ -426,6 +448,23 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
             double Rc = 0.0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) Rc += sm.rpart[w][c];
+            if constexpr (EM) {
+              // emission: the rows' terms of the flux ratio
+              const int cg = col0 + c;
+              const double nu = tb.wn[cg < W ? cg : W - 1];
+              const double wst = -expm1(-nu * hd->em_star);
+              double s = 0.0;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int j = 16 * r16 + (lane >> 4) + 4 * q;
+                if (j >= 1 && j < N)
+                  s += emission_term64(sm.em[j], sm.em[j - 1], fma(sm.PR[j], Rc, acc[r][cb][q]), nu, wst, a);
+              }
+              s += __shfl_xor(s, 16, 64);
+              s += __shfl_xor(s, 32, 64);
+              if (lane < 16) sm.part[r16][c] = s;
+              continue;
+            }
             // sum_j A_j (1 - e^{-tau_j}) as the block's sum of A_j less
             // sum_j A_j e^{-tau_j}, the first summed in the same order (a
             // block with tau = 0 adds exactly zero); the difference loses
@@ -455,6 +494,12 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
     if (tid < kCols && valid) {
       double atm = 0.0;
       for (int r16 = 0; r16 < n16; ++r16) atm += sm.part[r16][tid];
+      if constexpr (EM) {
+        // the top layer's B_{N-1}/B_*, then (Rp/Rs)^2
+        const double nu = tb.wn[col];
+        const double4 e = sm.em[N - 1];
+        atm = hd->em_scale * (atm + exp(-nu * e.z) * (-expm1(-nu * hd->em_star)) / (-expm1(-nu * e.x)));
+      }
       const int64_t o = (int64_t)b * W + col;
       reinterpret_cast<double*>(a.aws)[o] = atm;
       if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + atm;
@@ -464,12 +509,12 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
   }
 }
 
-template <bool TAU>
+template <bool TAU, bool EM>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd64s(FwdArgs a) {
-  __shared__ Smem64s sm;
+  __shared__ Smem64s<EM> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
-  process64s<TAU>(a, blockIdx.x, blockIdx.y * kS64, blockIdx.y * kS64 + kS64, sm);
+  process64s<TAU, EM>(a, blockIdx.x, blockIdx.y * kS64, blockIdx.y * kS64 + kS64, sm);
 }
 
 }  // namespace
@@ -479,10 +524,12 @@ void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s) {
   const int spans = (a.tab.n_wn + kCols - 1) / kCols;
   if (a.L.slot64) {
     const dim3 grid(B_grid, (spans + kS64 - 1) / kS64);
-    if (a.tau)
-      hipLaunchKernelGGL(k_fwd64s<true>, grid, dim3(64 * kWaves), 0, s, a);
+    if (a.L.em)
+      hipLaunchKernelGGL((k_fwd64s<false, true>), grid, dim3(64 * kWaves), 0, s, a);
+    else if (a.tau)
+      hipLaunchKernelGGL((k_fwd64s<true, false>), grid, dim3(64 * kWaves), 0, s, a);
     else
-      hipLaunchKernelGGL(k_fwd64s<false>, grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd64s<false, false>), grid, dim3(64 * kWaves), 0, s, a);
   } else if (a.tau) {
     hipLaunchKernelGGL(k_fwd64<true>, dim3(B_grid, spans), dim3(64 * kWaves), 0, s, a);
   } else {

@@ -43,6 +43,24 @@
 // 1 - e^{-tau_j} to a relative error of a few FP32 units (a range-reduced
 // expm1) and sums A_j/Rs^2 (1 - e^{-tau_j}) in FP64 with A_j in FP64, so
 // that no rounding is shared by every column.
+//
+// Emission (Forward Models section, the emission intensity and its
+// Gauss-Legendre flux).  The path matrix of an emission layout holds the
+// vertical shell thicknesses, so that the accumulator of row l is the
+// optical depth tau_l from the top down to the bottom of shell l (plus the
+// deck's, from the records).  The layer sum of the formal solution,
+// I(mu) = B_s e^{-tau_0/mu} + sum_l B_l (e^{-tau_{l+1}/mu} - e^{-tau_l/mu})
+// with B_s = B_0, telescopes to I = B_{N-1} + sum_{l >= 1} (B_{l-1} - B_l)
+// e^{-tau_l/mu}, so the flux ratio is a sum over rows of one term each:
+//   F/F_s = (Rp/Rs)^2 [B_{N-1} + sum_{l>=1} (B_{l-1} - B_l) G(tau_l)] / B_*,
+//   G(tau) = sum_i 2 w_i mu_i e^{-tau/mu_i}.
+// Relative to the star, B_l/B_* = e^{x_* - x_l} w_* / w_l with x = h c nu /
+// k_B T and w = 1 - e^{-x} (accurate expm1), and the difference of two
+// neighbouring layers is formed without cancellation,
+// B_{l-1}/B_* - B_l/B_* = e^{x_* - x_l} (e^{x_l - x_{l-1}} - 1) w_* /
+// (w_{l-1} w_l), where x_l - x_{l-1} comes from (T_{l-1} - T_l)/(T_l T_{l-1})
+// (the direct difference when |x_l - x_{l-1}| > 1).  Rows are summed in
+// FP64.
 #include "trx_internal.h"
 
 #include <type_traits>
@@ -80,15 +98,21 @@ struct Cfg {
   static constexpr int bdw = MODE == TRX_FP32 ? kKC * 64 : kKC * npc * 32;
 };
 
-template <int MODE, int RBW, bool ACC>
+// Depth epilogues: fast transit, accurate transit, emission.
+enum { kEpiFast = 0, kEpiAcc = 1, kEpiEm = 2 };
+
+template <int MODE, int RBW, int EPI>
 struct Smem {
   // B operand of the staged slot chunk
   __attribute__((aligned(16))) uint32_t bfrag[Cfg<MODE, RBW>::bdw];
   float part[kWaves * RBW][kCols];  // per-ray-block depth partials
   float2 aw[TRX_MAX_LAYERS_MFMA];   // per ray: A_j/Rs^2, -PR_j / ln 2
-  // accurate epilogue: per ray A_j/Rs^2 in FP64, per-ray-block FP64 partials
-  double a64[ACC ? TRX_MAX_LAYERS_MFMA : 1];
-  double partd[ACC ? kWaves * RBW : 1][ACC ? kCols : 1];
+  // accurate and emission epilogues: per ray A_j/Rs^2 in FP64 (accurate),
+  // per-ray-block FP64 partials; emission: the layer records
+  double a64[EPI == kEpiAcc ? TRX_MAX_LAYERS_MFMA : 1];
+  double partd[EPI != kEpiFast ? kWaves * RBW : 1][EPI != kEpiFast ? kCols : 1];
+  float4 em[EPI == kEpiEm ? TRX_MAX_LAYERS_MFMA : 1];
+  double emz[EPI == kEpiEm ? TRX_MAX_LAYERS_MFMA : 1];   // c2 (1/T_l - 1/T_*) in FP64
   float rpart[kWaves][kCols];       // Rayleigh sums by wave
   int32_t sid[kKC];                 // table rows of the chunk's slots
   float chi[TRX_MAX_ABSORBERS];
@@ -133,6 +157,41 @@ __device__ inline float one_minus_exp2(float x) {
   const float em1 = y * p;                                      // e^y - 1
   const float sc = __builtin_amdgcn_ldexpf(1.f, -(int)kf);      // 2^-k
   return -fmaf(sc, em1, sc - 1.f);
+}
+
+// e^{-y} to a few FP32 units for an argument y known in FP64 (up to
+// ~100: an FP32 argument would lose 1e-6 of the result there): 2^-y log2 e
+// split into an integer power of two and 2^f, |f| <= 1/2, in FP64.
+__device__ inline float exp_neg_d(double y) {
+  const double t = -1.4426950408889634074 * y;
+  const double n = __builtin_rint(t);
+  return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
+}
+
+// One row's term of the emission flux ratio (before (Rp/Rs)^2):
+// (B_{l-1} - B_l)/B_* G(tau_l), from the records e (layer l) and em (layer
+// l - 1) with their x_* - x terms zl, zm in FP64, the accumulator x =
+// -tau_gas/ln 2, the wavenumber nu and the star's 1 - e^{-x_*}.
+__device__ inline float emission_term(float4 e, float4 em, double zl, double zm, float x, float nu, double nud,
+                                      float wst, const FwdArgs& a) {
+  constexpr float kL2e = 1.4426950408889634f;
+  // G: the angles' weights times e^{-tau/mu_i}, tau with the deck's part
+  const float xt = x - kL2e * e.w;
+  float G = 0.f;
+  for (int i = 0; i < a.n_mu; ++i) G = fmaf(a.em_c32[i], __builtin_amdgcn_exp2f(xt * a.em_k32[i]), G);
+  const float wl = one_minus_exp2(-kL2e * nu * e.x);
+  const float wm = one_minus_exp2(-kL2e * nu * em.x);
+  const float rl = exp_neg_d(nud * zl);                          // e^{x_* - x_l}
+  const float dx = nu * e.y;                                     // x_l - x_{l-1}
+  float dB;
+  if (fabsf(dx) <= 1.f) {
+    const float ed = -one_minus_exp2(kL2e * dx);                 // e^{dx} - 1
+    dB = rl * ed * wst / (wm * wl);
+  } else {
+    const float rm = exp_neg_d(nud * zm);
+    dB = wst * (rm / wm - rl / wl);
+  }
+  return dB * G;
 }
 
 // Ray block r (0..RBW-1) of a wave: w, then 7 - w.
@@ -216,9 +275,9 @@ __device__ inline void mix_corners(const float* wt, int nt, int t0, const float 
 // Called by all threads of the workgroup (every early return is uniform).
 // TAU: also write the optical depth of every ray and column to a.tau (a
 // separate instantiation: the stores cost the hot kernel registers).
-// ACC: the accurate depth epilogue.
-template <int MODE, int RBW, bool TAU, bool ACC>
-__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end, Smem<MODE, RBW, ACC>& sm) {
+// EPI: the depth epilogue (kEpiFast, kEpiAcc, kEpiEm).
+template <int MODE, int RBW, bool TAU, int EPI>
+__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end, Smem<MODE, RBW, EPI>& sm) {
   using C = Cfg<MODE, RBW>;
   constexpr int npc = C::npc, kAW = C::kAW, KB = C::KB;
   constexpr bool PF = C::PF;
@@ -266,9 +325,17 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     const float2 w = tid < nr ? awg[tid] : float2{};
     const int32_t r = K <= kKC && tid < K ? sid[tid] : 0;
     if (tid < nr) sm.aw[tid] = float2{w.x, kNegLog2e32 * w.y};
-    if constexpr (ACC) {
+    if constexpr (EPI == kEpiAcc) {
       const double* A64 = reinterpret_cast<const double*>(slab + L.off_A64);
       if (tid < nr) sm.a64[tid] = A64[tid];
+    }
+    if constexpr (EPI == kEpiEm) {
+      const float4* e32 = reinterpret_cast<const float4*>(slab + L.off_em32);
+      const double4* e64 = reinterpret_cast<const double4*>(slab + L.off_em64);
+      if (tid < nr) {
+        sm.em[tid] = e32[tid];
+        sm.emz[tid] = e64[tid].z;
+      }
     }
     if (K <= kKC && tid < K) sm.sid[tid] = r;
     if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
@@ -540,14 +607,28 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
           const float Rc = sm.rpart[0][cl] + sm.rpart[1][cl] + sm.rpart[2][cl] + sm.rpart[3][cl];
           float s = 0.f;
           double sd = 0.0;
+          // emission: the column's wavenumber and the star's 1 - e^{-x_*}
+          float nu = 0.f, wst = 0.f;
+          double nud = 0.0;
+          if constexpr (EPI == kEpiEm) {
+            const int cg = span * kCols + cl;
+            nud = tb.wn[cg < W ? cg : W - 1];
+            nu = (float)nud;
+            wst = one_minus_exp2(-1.4426950408889634f * nu * (float)hd->em_star);
+          }
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
             const float2 w = sm.aw[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)];
             const float x = fmaf(w.y, Rc, acc[r][tcb][q]);   // -tau / ln 2
-            if constexpr (ACC)
+            if constexpr (EPI == kEpiAcc) {
               sd = fma(sm.a64[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)], (double)one_minus_exp2(x), sd);
-            else
+            } else if constexpr (EPI == kEpiEm) {
+              const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
+              if (j >= 1 && j < N)
+                sd += (double)emission_term(sm.em[j], sm.em[j - 1], sm.emz[j], sm.emz[j - 1], x, nu, nud, wst, a);
+            } else {
               s = fmaf(w.x, __builtin_amdgcn_exp2f(x), s);
+            }
             if constexpr (TAU) {
               const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
               const int cg = span * kCols + cl;
@@ -555,7 +636,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
                 a.tau[(int64_t)b * a.tau_ld + (int64_t)j * W + cg] = -0.69314718055994531 * (double)x;
             }
           }
-          if constexpr (ACC) {
+          if constexpr (EPI != kEpiFast) {
             sd += __shfl_xor(sd, 32, 64);
             if (hl == 0) sm.partd[rb][cl] = sd;
           } else {
@@ -572,9 +653,19 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     __syncthreads();
     if (wave == 0 && valid) {
       const int64_t o = (int64_t)b * W + col;
-      if constexpr (ACC) {
+      if constexpr (EPI != kEpiFast) {
         double atm = 0.0;
         for (int rb = 0; rb < nrb; ++rb) atm += sm.partd[rb][lane];
+        if constexpr (EPI == kEpiEm) {
+          // the top layer's B_{N-1}/B_*, then (Rp/Rs)^2
+          const double nud = tb.wn[col];
+          const float nu = (float)nud;
+          const float4 e = sm.em[N - 1];
+          const float wst = one_minus_exp2(-1.4426950408889634f * nu * (float)hd->em_star);
+          const float wl = one_minus_exp2(-1.4426950408889634f * nu * e.x);
+          const float rl = exp_neg_d(nud * sm.emz[N - 1]);
+          atm = hd->em_scale * (atm + (double)(rl * wst / wl));
+        }
         reinterpret_cast<float*>(a.aws)[o] = (float)atm;
         if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + atm;
         if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
@@ -590,13 +681,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 }
 
 // One workgroup per (model, span).
-template <int MODE, int RBW, bool TAU, bool ACC>
+template <int MODE, int RBW, bool TAU, int EPI>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
-  __shared__ Smem<MODE, RBW, ACC> sm;
+  __shared__ Smem<MODE, RBW, EPI> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
   const int S = a.span_group;
-  process<MODE, RBW, TAU, ACC>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
+  process<MODE, RBW, TAU, EPI>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
 }
 
 // Persistent: a fixed grid pops chunks of (span, model) items from kQueues
@@ -606,9 +697,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
 // one XCD share the table rows of few spans in its L2, and moves on to the
 // other queues when its own is drained.  Every workgroup leaves once all
 // queues are drained.
-template <int MODE, int RBW, bool ACC>
+template <int MODE, int RBW, int EPI>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_mfma_persist(FwdArgs a) {
-  __shared__ Smem<MODE, RBW, ACC> sm;
+  __shared__ Smem<MODE, RBW, EPI> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int S = a.span_group;
   const int ngroups = ((a.tab.n_wn + kCols - 1) / kCols + S - 1) / S;
@@ -647,19 +738,19 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW, false, ACC>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
+        if (bm >= 0) process<MODE, RBW, false, EPI>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
       }
       __syncthreads();
     }
   }
 }
 
-template <int MODE, int RBW, bool ACC>
+template <int MODE, int RBW, int EPI>
 int occupancy() {
   static int blocks = 0;
   if (!blocks) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, ACC>, 64 * kWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, EPI>, 64 * kWaves, 0) !=
             hipSuccess || nb < 1)
       nb = 1;
     blocks = nb;
@@ -668,26 +759,27 @@ int occupancy() {
 }
 
 // The optical-depth output always takes the one-workgroup-per-item kernel.
-template <int MODE, int RBW, bool ACC>
-void launch_rbw_acc(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
+template <int MODE, int RBW, int EPI>
+void launch_rbw_epi(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
   if (a.persistent && !a.tau) {
-    const int grid = n_cu * occupancy<MODE, RBW, ACC>();
-    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, ACC>), dim3(grid), dim3(64 * kWaves), 0, s, a);
+    const int grid = n_cu * occupancy<MODE, RBW, EPI>();
+    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, EPI>), dim3(grid), dim3(64 * kWaves), 0, s, a);
   } else {
     dim3 grid(B_grid, ((a.tab.n_wn + kCols - 1) / kCols + a.span_group - 1) / a.span_group);
     if (a.tau)
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true, false>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true, kEpiFast>), grid, dim3(64 * kWaves), 0, s, a);
     else
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false, ACC>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false, EPI>), grid, dim3(64 * kWaves), 0, s, a);
   }
 }
 
-// The optical-depth output never takes the accurate epilogue (it writes tau,
-// not the depth's rounding).
+// The optical-depth output (transmission only) takes the fast epilogue: it
+// writes tau, not the depth's rounding.
 template <int MODE, int RBW>
 void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
-  if (a.accurate && !a.tau) launch_rbw_acc<MODE, RBW, true>(a, B_grid, n_cu, s);
-  else launch_rbw_acc<MODE, RBW, false>(a, B_grid, n_cu, s);
+  if (a.L.em) launch_rbw_epi<MODE, RBW, kEpiEm>(a, B_grid, n_cu, s);
+  else if (a.accurate && !a.tau) launch_rbw_epi<MODE, RBW, kEpiAcc>(a, B_grid, n_cu, s);
+  else launch_rbw_epi<MODE, RBW, kEpiFast>(a, B_grid, n_cu, s);
 }
 
 template <int MODE>

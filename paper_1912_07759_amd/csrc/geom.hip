@@ -112,6 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       if (!(sg >= 0.0)) st |= TRX_MODEL_BAD_PROFILE;
       if (sg > 0.0 && !(finite_pos(a.bt.cloud_p1[b]) && finite_pos(a.bt.cloud_p2[b]))) st |= TRX_MODEL_BAD_PROFILE;
     }
+    if (L.em && !finite_pos(a.T_star[b])) st |= TRX_MODEL_BAD_PROFILE;
     s_status = st;
   }
   __syncthreads();
@@ -235,6 +236,13 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   const bool copaque = isinf(csig);
   auto in_deck = [&](int k) { return sP[k] >= cp_lo && sP[k] <= cp_hi; };
   double* pc64 = reinterpret_cast<double*>(slab + L.off_pc64);
+  // emission: shell thickness and the per-layer records of the Planck terms
+  auto shell_dz = [&](int k) -> double {
+    const double h0 = (k == 0) ? 0.0 : 0.5 * (sZ[k - 1] + sZ[k]);
+    const double h1 = (k == N - 1) ? sZ[N - 1] : 0.5 * (sZ[k] + sZ[k + 1]);
+    return h1 - h0;
+  };
+  const double Tstar = L.em ? a.T_star[b] : 1.0;
 
   // a3: annulus weights; a4: layer records
   const int NP = L.NP;
@@ -244,10 +252,12 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       const double hl = (l == 0) ? 0.0 : 0.5 * (sZ[l - 1] + z);
       const double hu = (l == N - 1) ? z : 0.5 * (z + sZ[l + 1]);
       const double A0 = 2.0 * (Rp + z) * (hu - hl) * inv_Rs2;
+      // the deck's optical depth along ray j = l (emission: vertically,
+      // from the top down to the bottom of shell l)
       double tc = 0.0;
       for (int k = l; k < N && csig > 0.0; ++k) {
         if (!in_deck(k)) continue;
-        const double d = dl_of(l, k);
+        const double d = L.em ? shell_dz(k) : dl_of(l, k);
         if (copaque) {
           if (d > 0.0) {   // one path through an opaque deck blocks the ray
             tc = __builtin_inf();
@@ -257,9 +267,20 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
           tc += d * (csig * sP[k] / (a.bt.kB * a.bt.T[off + k]));
         }
       }
-      const double A = A0 * exp(-tc);
-      sC[l] = -A0 * expm1(-tc);   // this ray's share of the deck's constant term
+      // transmission folds the deck into the annulus weights and the
+      // constant term; emission keeps it per layer in its records
+      const double A = L.em ? A0 : A0 * exp(-tc);
+      sC[l] = L.em ? 0.0 : -A0 * expm1(-tc);   // this ray's share of the deck's constant term
       pc64[l] = tc;
+      if (L.em) {
+        const double Tl = a.bt.T[off + l];
+        const double Tm = l > 0 ? a.bt.T[off + l - 1] : Tl;
+        const double e0 = a.c2 / Tl;
+        const double e1 = l > 0 ? a.c2 * ((Tm - Tl) / (Tl * Tm)) : 0.0;
+        const double e2 = a.c2 * ((Tstar - Tl) / (Tl * Tstar));
+        reinterpret_cast<double4*>(slab + L.off_em64)[l] = make_double4(e0, e1, e2, tc);
+        reinterpret_cast<float4*>(slab + L.off_em32)[l] = make_float4((float)e0, (float)e1, (float)e2, (float)tc);
+      }
       zs[l] = z;
       A64[l] = A;
       A32[l] = (float)A;
@@ -338,6 +359,10 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       A64[l] = 0.0;
       A32[l] = 0.0f;
       pc64[l] = 0.0;
+      if (L.em) {
+        reinterpret_cast<double4*>(slab + L.off_em64)[l] = make_double4(0.0, 0.0, 0.0, 0.0);
+        reinterpret_cast<float4*>(slab + L.off_em32)[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
       if (L.off_aw) reinterpret_cast<float2*>(slab + L.off_aw)[l] = make_float2(0.f, 0.f);
       if (L.off_pr64) reinterpret_cast<double*>(slab + L.off_pr64)[l] = 0.0;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
@@ -353,6 +378,14 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     for (int l = 0; l < N && csig > 0.0; ++l) s += sC[l];
     h->Rp2_Rs2 = (Rp / Rs) * (Rp / Rs) + s;
     h->cloud = csig > 0.0 ? 1 : 0;
+    h->em_scale = (Rp / Rs) * (Rp / Rs);
+    h->em_star = a.c2 / Tstar;
+    if (L.em) {
+      // the emission output has no additive constant (its records carry
+      // the deck)
+      h->Rp2_Rs2 = 0.0;
+      h->cloud = 0;
+    }
   }
 
   // distinct corners of the whole model (bitmaps over the keys
@@ -619,7 +652,11 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   // difference loses about log10(q/dl) <= 3 digits, far below what P is
   // rounded to, and spares a division per step.
   auto qj = [&](double h) { return sqrt(fmax((h - zj) * (2.0 * Rp + h + zj), 0.0)); };
+  // emission layouts: the vertical path from the bottom of shell j up
+  // through shell l >= j is the shell's thickness
+  const bool em = L.em != 0;
   auto chord = [&](int l, double& q0) -> double {
+    if (em) return sH[l + 1] - sH[l];
     const double q1 = qj(sH[l + 1]);
     const double d = 2.0 * (q1 - q0);   // q0 = 0 at l = j
     q0 = q1;

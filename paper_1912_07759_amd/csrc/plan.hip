@@ -43,6 +43,9 @@ struct trx_plan {
   double* cap_binned = nullptr;
   int32_t* cap_status = nullptr;
   const void* cap_grad[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // emission plans: the stellar temperatures and angles (trx_plan_set_star)
+  const double* T_star = nullptr;
+  int n_mu = 0;
 };
 
 // Outputs (and, for gradient plans, observation inputs) of one launch.
@@ -90,9 +93,10 @@ bool same_batch(const trx_batch& a, const trx_batch& b) {
 // sized for B_max); otherwise from B.
 trx_status enqueue(trx_plan* p, const trx_batch* bt, int B, const int32_t* B_dev, const RunConfig& rc,
                    double* native, double* binned, int32_t* status) {
+  const EmissionIn em{p->T_star, p->n_mu};
   return enqueue_forward(p->ctx, p->t, dev_batch(bt), B, B_dev, p->N_max, p->bins, p->precision, rc,
                          (uint8_t*)p->ws.ptr, p->aws.ptr, SchedBufs::carve(p->sched.ptr, p->B_max), native,
-                         binned, status);
+                         binned, status, false, nullptr, (p->flags & TRX_PLAN_EMISSION) ? &em : nullptr);
 }
 
 trx_status enqueue_io(trx_plan* p, const trx_batch* bt, int B, const int32_t* B_dev, const RunConfig& rc,
@@ -113,6 +117,8 @@ trx_status check_launch(trx_plan* p, const trx_batch* bt, double* binned, const 
     return set_err(c, TRX_E_INVALID_ARG, "batch.max_layers %d exceeds the plan's N_max %d", bt->max_layers, p->N_max);
   if (need_status && !status) return set_err(c, TRX_E_INVALID_ARG, "model_status is required");
   if (binned && !p->bins) return set_err(c, TRX_E_INVALID_ARG, "depth_binned requires a plan made with bins");
+  if ((p->flags & TRX_PLAN_EMISSION) && !p->T_star)
+    return set_err(c, TRX_E_INVALID_ARG, "an emission plan needs its star (trx_plan_set_star) before a launch");
   return TRX_OK;
 }
 
@@ -203,9 +209,13 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   const int limit = precision == TRX_FP64 ? TRX_MAX_LAYERS_FP64 : TRX_MAX_LAYERS_MFMA;
   if (N_max < 2) return set_err(c, TRX_E_INVALID_ARG, "N_max must be >= 2");
   if (N_max > limit) return set_err(c, TRX_E_UNSUPPORTED, "N_max %d exceeds %d for this precision", N_max, limit);
-  if (flags & ~(TRX_PLAN_GRAPH | TRX_PLAN_PERSISTENT | TRX_PLAN_GRAD))
+  if (flags & ~(TRX_PLAN_GRAPH | TRX_PLAN_PERSISTENT | TRX_PLAN_GRAD | TRX_PLAN_EMISSION))
     return set_err(c, TRX_E_INVALID_ARG, "unknown plan flags 0x%x", flags);
   const bool grad = (flags & TRX_PLAN_GRAD) != 0;
+  const bool emission = (flags & TRX_PLAN_EMISSION) != 0;
+  if (grad && emission) return set_err(c, TRX_E_UNSUPPORTED, "the gradient of the emission model is not built");
+  if (emission && precision == TRX_FP64 && N_max > TRX_MAX_LAYERS_MFMA)
+    return set_err(c, TRX_E_UNSUPPORTED, "emission takes at most %d layers", TRX_MAX_LAYERS_MFMA);
   if (grad && !bins) return set_err(c, TRX_E_INVALID_ARG, "gradient plans need channels (bins)");
   if (grad && N_max > TRX_MAX_LAYERS_MFMA)
     return set_err(c, TRX_E_UNSUPPORTED, "the gradient supports at most %d layers", TRX_MAX_LAYERS_MFMA);
@@ -217,7 +227,7 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   if (!(flags & TRX_PLAN_PERSISTENT)) p->rc.persistent = 0;
   describe(p);
   auto fail = [&](trx_status s) { trx_plan_destroy(p); return s; };
-  const Layout L = make_layout(N_max, precision, grad, t->dev);
+  const Layout L = make_layout(N_max, precision, grad, t->dev, emission);
   trx_status s;
   if ((s = ensure_buffer(c, p->ws, (size_t)B_max * L.slab, "plan workspace")) != TRX_OK) return fail(s);
   if (grad && (s = ensure_buffer(c, p->grad, grad_scratch_bytes(B_max, t->dev.n_wn, bins->n_ch, L.NP),
@@ -358,6 +368,19 @@ extern "C" trx_status trx_plan_launch(trx_plan* p, const trx_batch* bt, double* 
   return TRX_OK;
 }
 
+extern "C" trx_status trx_plan_set_star(trx_plan* p, const double* T_star_K, int32_t n_mu) {
+  if (!p) return TRX_E_INVALID_ARG;
+  trx_ctx* c = p->ctx;
+  c->err.clear();
+  if (!(p->flags & TRX_PLAN_EMISSION)) return set_err(c, TRX_E_INVALID_ARG, "not an emission plan");
+  trx_status s = check_emission(c, p->precision, p->N_max, T_star_K, n_mu);
+  if (s != TRX_OK) return s;
+  if (T_star_K != p->T_star || n_mu != p->n_mu) drop_graph(p);
+  p->T_star = T_star_K;
+  p->n_mu = n_mu;
+  return TRX_OK;
+}
+
 extern "C" trx_status trx_plan_set_variant(trx_plan* p, const char* v) {
   if (!p) return TRX_E_INVALID_ARG;
   RunConfig rc = p->rc;
@@ -379,7 +402,8 @@ extern "C" trx_status trx_autotune(trx_plan* p, const trx_batch* bt, const char*
   hipSetDevice(c->device);
   char key[256];
   snprintf(key, sizeof key, "%s/%s/B%d/N%d/W%d/abs%d/flags%d", c->arch, prec_name(p->precision), bucket(p->B_max),
-           bucket(p->N_max), p->t->dev.n_wn, p->t->dev.n_abs, p->flags & TRX_PLAN_PERSISTENT);
+           bucket(p->N_max), p->t->dev.n_wn, p->t->dev.n_abs,
+           p->flags & (TRX_PLAN_PERSISTENT | TRX_PLAN_EMISSION));
   std::map<std::string, std::string> cache;
   if (cache_json) {
     cache = read_cache(cache_json);

@@ -102,13 +102,23 @@ trx_status upload(trx_ctx* c, const double* host, int64_t n, double** d64, float
 void launch_copy_status(const uint8_t* ws, int64_t slab, const int32_t* B_dev, int B, int32_t* out,
                         hipStream_t s);
 trx_status check_batch(trx_ctx* c, const trx_tables* t, const trx_batch* bt, int precision);
+
+// Emission inputs of one launch (a null pointer: transmission).
+struct EmissionIn {
+  const double* T_star;   // [B] device, K
+  int n_mu;               // Gauss-Legendre angles, 1..TRX_MAX_MU
+};
+// Checks the emission arguments of a call (n_mu, star pointer, layer limit).
+trx_status check_emission(trx_ctx* c, int precision, int max_layers, const double* T_star, int n_mu);
+// n Gauss-Legendre abscissas and weights on [0, 1] (weights sum to 1).
+void gauss_legendre01(int n, double* mu, double* w);
 DevBatch dev_batch(const trx_batch* bt);
 RunConfig default_config(int precision, int max_layers);
 trx_status enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, int B, const int32_t* B_dev,
                            int max_layers, const trx_bins* bins, int precision, const RunConfig& rc,
                            uint8_t* ws, void* aws, const SchedBufs& sb, double* depth_native,
                            double* depth_binned, int32_t* status, bool grad_layout = false,
-                           double* tau = nullptr);
+                           double* tau = nullptr, const EmissionIn* em = nullptr);
 
 // Gradient workspace carved from one buffer (base null: sizes only).
 struct GradScratch {

@@ -69,6 +69,11 @@ struct ModelHdr {
   // 1 when a cloud deck adds optical depth to some ray; its per-ray depth
   // is then folded into the annulus weights (see the geometry kernel)
   int32_t cloud;
+  // emission layouts: F_p/F_s = em_scale x (the flux ratio), em_scale =
+  // (Rp/Rs)^2; em_star = c2 / T_star (so that h c nu / k_B T_star =
+  // em_star x wavenumber)
+  double em_scale;
+  double em_star;
 };
 static_assert(sizeof(ModelHdr) <= kHdrBytes, "header too large");
 
@@ -100,6 +105,11 @@ struct Layout {
   int64_t off_aw;          // [NP] float2 (A_j/Rs^2, Rayleigh path weight of ray j)
   int64_t off_pr64;        // FP64 slot form: [NP] FP64 Rayleigh path weight of ray j
   int64_t off_pc64;        // [NP] FP64 optical depth of the cloud deck along ray j (+inf: opaque)
+  // emission layouts: per layer l the records {c2/T_l, c2 (T_{l-1} - T_l)/(T_l T_{l-1}),
+  // c2 (1/T_l - 1/T_star), vertical cloud optical depth down to the bottom of
+  // shell l}, FP32 (float4) and FP64 (double4); c2 = 100 h c / k_B (K cm)
+  int32_t em;
+  int64_t off_em32, off_em64;
   int32_t slot64;          // FP64 mode in the slot form (models of at most TRX_MAX_LAYERS_MFMA layers)
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise); the gradient takes models of at
@@ -138,7 +148,7 @@ inline int frag_piece_bytes(int precision) {
   return precision == TRX_FP32 ? 64 * 8 * 4 : 64 * 8 * 2;
 }
 
-inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& t) {
+inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& t, bool emission = false) {
   Layout L{};
   L.NP = ((N_max + 31) / 32) * 32;
   L.NRB = L.NP / 32;
@@ -157,6 +167,11 @@ inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& 
   L.off_lid = take(4LL * 8 * L.NP);
   L.off_kblk = take((int64_t)sizeof(KBlk) * L.NKB);
   L.off_mlist = take((int64_t)sizeof(MList));
+  if (emission) {
+    L.em = 1;
+    L.off_em32 = take(16LL * L.NP);
+    L.off_em64 = take(32LL * L.NP);
+  }
   if (precision == TRX_FP64 && L.NP > TRX_MAX_LAYERS_MFMA) {
     L.dl_bytes = 8LL * L.NP * L.NP;  // dense transposed dlT[k][j]
   } else if (precision == TRX_FP64) {
@@ -224,6 +239,10 @@ struct GeomArgs {
   double* depth_native;   // [B][n_wn] or null: NaN written for invalid models
   int32_t* mlay;          // [B] layer count (0 for an invalid model)
   int2* mspan;            // [B] spans [lo, hi) of kSpanCols columns its window covers
+  // emission (L.em): the path matrix takes the vertical shell thickness
+  // instead of the chords, and the records of the Planck terms are written
+  const double* T_star;   // [B] stellar temperature, K
+  double c2;              // 100 h c / k_B, K cm
 };
 
 // Columns of one work item of the forward kernels.
@@ -268,6 +287,13 @@ struct FwdArgs {
   int32_t group;          // models per item group of the persistent order (0: all)
   int32_t span_group;     // consecutive spans per work item (matrix-core kernel)
   int32_t accurate;       // matrix-core modes: depth epilogue accurate per element (gradient's forward)
+  // emission (L.em): Gauss-Legendre angles on [0, 1], n_mu of them:
+  // em_k[i] = 1/mu_i, em_c[i] = 2 w_i mu_i (sum to 1)
+  int32_t n_mu;
+  float em_k32[TRX_MAX_MU];
+  float em_c32[TRX_MAX_MU];
+  double em_k64[TRX_MAX_MU];
+  double em_c64[TRX_MAX_MU];
 };
 
 void launch_schedule(const int32_t* mlay, const int32_t* B_dev, int B, int32_t* order, int32_t* qcount,

@@ -20,7 +20,7 @@ FP64, FP32, BF16_SPLIT2, BF16_SPLIT3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16_SPLIT2, "bf16x3": BF16_SPLIT3}
 
 MODEL_OK, BAD_CHEMISTRY, BAD_PROFILE, BAD_WINDOW, NONFINITE, GRAD_UNSUPPORTED = 0, 1, 2, 4, 8, 16
-PLAN_GRAPH, PLAN_PERSISTENT, PLAN_GRAD = 1, 2, 4
+PLAN_GRAPH, PLAN_PERSISTENT, PLAN_GRAD, PLAN_EMISSION = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "TRX_OK", 1: "TRX_E_INVALID_ARG", 2: "TRX_E_OUT_OF_MEMORY",
                 3: "TRX_E_DEVICE", 4: "TRX_E_UNSUPPORTED"}
@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "TRX_OK", 1: "TRX_E_INVALID_ARG", 2: "TRX_E_OUT_OF_MEMORY",
 EXPORTS = ["trx_create", "trx_destroy", "trx_last_error", "trx_set_stream",
            "trx_synchronize", "trx_tables_create", "trx_tables_destroy",
            "trx_bins_create", "trx_bins_destroy", "trx_forward", "trx_forward_noalloc",
-           "trx_chi2_grad",
+           "trx_emission", "trx_plan_set_star", "trx_chi2_grad",
            "trx_plan_create", "trx_plan_destroy", "trx_plan_batch", "trx_plan_launch",
            "trx_autotune", "trx_plan_set_variant", "trx_plan_describe", "trx_profile",
            "trx_profile_read"]
@@ -296,6 +296,29 @@ def forward(ctx, tables, batch, bins=None, precision=FP64, native=True, binned=T
     return out_native, out_binned, out_status
 
 
+def emission(ctx, tables, batch, bins=None, precision=FP64, n_mu=4, T_star=5800.0, native=True,
+             binned=True):
+    """trx_emission.  T_star: a scalar or [B] stellar temperatures.  Returns
+    (fpfs_native [B, n_wn] or None, fpfs_binned [B, n_ch] or None,
+    model_status [B])."""
+    dev = batch.T.device
+    B = batch.B
+    ts = torch.as_tensor(np.broadcast_to(np.asarray(T_star, dtype=np.float64), (B,)).copy()
+                         if not torch.is_tensor(T_star) else T_star, dtype=torch.float64).to(dev)
+    out_native = torch.full((B, tables.n_wn), float("nan"), dtype=torch.float64, device=dev) \
+        if native else None
+    out_binned = torch.empty((B, bins.n), dtype=torch.float64, device=dev) \
+        if (binned and bins is not None) else None
+    out_status = torch.empty(B, dtype=torch.int32, device=dev)
+    ctx.bind_stream()
+    bc = batch.cstruct()
+    ctx.check(lib().trx_emission(ctx.h, tables.h, ctypes.byref(bc),
+                                 bins.h if bins is not None else None, _prec(precision), int(n_mu),
+                                 _ptr(ts), _ptr(out_native), _ptr(out_binned), _ptr(out_status)))
+    ctx._keep_star = ts
+    return out_native, out_binned, out_status
+
+
 def forward_noalloc(ctx, tables, batch, bins, precision, out_native, out_binned, out_status):
     """trx_forward_noalloc: the forward model in the library's fixed device
     array (no device memory is allocated by the library).  The outputs are
@@ -392,11 +415,11 @@ class Plan:
     was captured with."""
 
     def __init__(self, ctx, tables, bins, B_max, N_max, precision=FP32, graph=True,
-                 persistent=True, grad=False):
+                 persistent=True, grad=False, emission=False):
         self.ctx, self.tables, self.bins = ctx, tables, bins
         self.B_max, self.N_max = int(B_max), int(N_max)
         flags = (PLAN_GRAPH if graph else 0) | (PLAN_PERSISTENT if persistent else 0) | \
-            (PLAN_GRAD if grad else 0)
+            (PLAN_GRAD if grad else 0) | (PLAN_EMISSION if emission else 0)
         h = ctypes.c_void_p()
         ctx.check(lib().trx_plan_create(ctx.h, tables.h, bins.h if bins is not None else None,
                                         self.B_max, self.N_max, _prec(precision), flags,
@@ -416,6 +439,19 @@ class Plan:
             self.out_dT = torch.empty(self.B_max * self.N_max, **f64)
             self.out_dvmr = torch.empty((self.B_max, max(tables.n_abs, 1)), **f64)
             self.out_dRp = torch.empty(self.B_max, **f64)
+
+    def set_star(self, T_star, n_mu=4):
+        """trx_plan_set_star of an emission plan: T_star (scalar or [<= B_max])
+        is copied into a plan-owned device tensor of B_max entries."""
+        dev = self.out_status.device
+        t = torch.as_tensor(T_star, dtype=torch.float64).flatten()
+        if not hasattr(self, "T_star"):
+            self.T_star = torch.full((self.B_max,), 5800.0, dtype=torch.float64, device=dev)
+        if t.numel() == 1:
+            self.T_star.fill_(float(t[0]))
+        else:
+            self.T_star[:t.numel()].copy_(t)
+        self.ctx.check(lib().trx_plan_set_star(self.h, _ptr(self.T_star), int(n_mu)))
 
     def launch_grad(self, batch, obs, sigma):
         """trx_plan_launch of a gradient plan: chi^2 against obs [B, n_ch]
