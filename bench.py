@@ -10,8 +10,12 @@ Inputs are resident in device memory before the timed region.
 
 Prints one JSON line with the throughput (spectra/s), the roofline of the
 dominant kernel (timed live with HIP events on the library's stream), the
-plain FP64 GPU path on the same batch, the error of sampled models against
-the FP64 oracle and the oracle's own rate on the host (CPU baseline leg).
+plain FP64 GPU path on the same batch, the error of a stratified sample of
+models against the FP64 oracle and the oracle's own rate on the host's cores
+(CPU baseline leg, a pool of worker processes forked before the GPU is
+touched), and the other legs: chi^2 gradients (FP32 forward, FP64 forward as
+a second figure), emission spectra, single-model latencies, cloud decks, a
+synthetic retrieval and the large workload.
 """
 
 import argparse
@@ -36,7 +40,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--precision", default="bf16x2", choices=list(PEAKS_TFLOPS))
     p.add_argument("--models", type=int, default=4096)
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-seconds", type=float, default=30.0,
+                   help="budget of single-process oracle work (large workload checks)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--variant", default=None,
@@ -47,18 +52,20 @@ def parse():
                         "(0: skip); the rate is scaled to the batch")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the gradient leg (chi^2 gradients of the 256-point workload)")
-    p.add_argument("--grad-precision", default="fp64", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
-                   help="forward pass of the gradient leg (the residual needs its accuracy)")
+    p.add_argument("--grad-precision", default="fp32", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
+                   help="forward pass of the gradient leg (FP64 is always timed as well)")
+    p.add_argument("--no-emission", action="store_true", help="skip the emission leg")
+    p.add_argument("--emission-precision", default="fp32", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
+                   help="the emission leg's fast mode (FP64 is always timed as well)")
     p.add_argument("--no-clouds", action="store_true",
                    help="skip the leg with cloud decks on the main batch")
     p.add_argument("--no-retrieval", action="store_true",
                    help="skip the synthetic nested-sampling retrieval")
     p.add_argument("--no-single", action="store_true",
                    help="skip the single-model leg (one model per graph replay)")
-    p.add_argument("--large", action="store_true",
-                   help="also run the large workload (1024 models of 100-200 layers, 10 "
-                        "absorbers, 40 x 30 x 100000 tables): split-bf16 forward and FP64-forward "
-                        "gradients, with the device memory in use")
+    p.add_argument("--no-large", action="store_true",
+                   help="skip the large workload (1024 models of 100-200 layers, 10 absorbers, "
+                        "40 x 30 x 100000 tables): split-bf16 forward and gradients")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="also run one plain device copy of this many MiB (reference "
                         "for the HBM byte counters of a profiler run)")
@@ -69,6 +76,103 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------------------
+# the oracle on the host's cores: worker processes forked before the GPU is
+# initialised, the workload arrays shared with them copy-on-write
+# ---------------------------------------------------------------------------
+_SHARED = {}
+
+
+def pool_size():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _ping(_):
+    return os.getpid()
+
+
+def _oracle_task(job):
+    """One oracle evaluation in a worker (one BLAS thread), with its wall
+    interval and its own duration."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    kind, b, extra = job
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        p0 = time.perf_counter()
+        if kind in ("forward", "clouds"):
+            tables, batch, ch = _SHARED["cfg3"]
+            m = (_SHARED["cfg3_clouds"] if kind == "clouds" else batch).model(b)
+            r = oracle.forward_model(m, tables, ch)
+            out = (r["depth"], r["binned"])
+        elif kind == "emission":
+            tables, batch, ch = _SHARED["cfg3"]
+            r = oracle.emission_model(batch.model(b), tables, ch, n_mu=extra[0],
+                                      T_star=float(_SHARED["T_star"][b]))
+            out = (r["fpfs"], r["binned"])
+        else:   # gradient
+            tables, batch, ch = _SHARED["cfg4"]
+            obs, sigma = extra
+            g = oracle.chi2_and_grad(batch.model(b), tables, ch, obs, sigma)
+            out = (g["dT"], g["dlog10_vmr"], g["dRp"], g["chi2"])
+        dt = time.perf_counter() - p0
+    return b, out, t0, time.time(), dt
+
+
+def run_oracle(pool, kind, picks, extra=None):
+    """Results by model index, the wall time of the pool (first start to
+    last end) and the summed per-model time."""
+    res = list(pool.map(_oracle_task, [(kind, int(b), extra) for b in picks], chunksize=1))
+    wall = max(r[3] for r in res) - min(r[2] for r in res)
+    return {r[0]: r[1] for r in res}, wall, sum(r[4] for r in res)
+
+
+def stratified(batch, k, seed):
+    """Models spread evenly over the batch's work (layers x window) ranks,
+    the largest and the smallest included, about k of them."""
+    work = batch.n_layers.astype(np.float64) * (batch.wn_hi - batch.wn_lo)
+    order = np.argsort(work, kind="stable")
+    ranks = np.unique(np.linspace(0, batch.B - 1, min(k, batch.B)).round().astype(int))
+    pick = [int(order[-1]), int(order[0])] + [int(order[r]) for r in ranks]
+    return list(dict.fromkeys(pick))
+
+
+def rel_err(g, r):
+    g, r = np.asarray(g), np.asarray(r)
+    ok = ~np.isnan(r)
+    if not ok.any():
+        return 0.0
+    if not np.all(np.isfinite(g[ok])):
+        return float("inf")
+    return float(np.max(np.abs(g[ok] - r[ok]) / np.abs(r[ok])))
+
+
+def grad_err(v, r):
+    """Norm-wise and per-component (components above 1e-3 of the largest)."""
+    big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
+    return max(np.linalg.norm(v - r) / np.linalg.norm(r),
+               float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big]))))
+
+
+# ---------------------------------------------------------------------------
+# helpers on the GPU side
+# ---------------------------------------------------------------------------
 def traffic_of(kernel, precision):
     """HBM bytes per launch of `kernel` from the committed profiler summary,
     if it was taken on the current source of the kernel, else None."""
@@ -93,106 +197,180 @@ def traffic_of(kernel, precision):
         return None
 
 
-def observation(args, ctx, trx, T, bins, tables, batch, ch, cfg, n_layers):
-    """The synthetic observation of a gradient workload: the binned spectrum of
-    point 0 plus seeded 50 ppm noise.  With the oracle leg on, that spectrum
-    is the oracle's (it is then also an input of the oracle's check); with
-    --no-cpu it comes from the library's FP64 path and nothing is checked."""
+def observation(ctx, trx, T, bins, batch, cfg, n_layers, n_ch):
+    """The synthetic observation of a gradient workload: the library's FP64
+    binned spectrum of point 0 plus seeded 50 ppm noise (the oracle only
+    checks)."""
     from synth.workloads import observation_noise
-    if not args.no_cpu:
-        import oracle
-        truth = oracle.forward_model(batch.model(0), tables, ch)["binned"]
-    else:
-        one = trx.DeviceBatch.from_synth(batch.subset([0]), max_layers=n_layers)
-        _, tb, _ = trx.forward(ctx, T, one, bins, "fp64", native=False)
-        truth = tb[0].cpu().numpy()
-    noise, sigma = observation_noise(cfg, 1, bins.n)
-    return np.tile(truth + noise[0], (batch.B, 1)), sigma
+    one = trx.DeviceBatch.from_synth(batch.subset([0]), max_layers=n_layers)
+    _, tb, st = trx.forward(ctx, T, one, bins, "fp64", native=False)
+    assert int(st[0]) == 0
+    noise, sigma = observation_noise(cfg, 1, n_ch)
+    return np.tile(tb[0].cpu().numpy() + noise[0], (batch.B, 1)), sigma
 
 
-def oracle_grad_check(args, batch, tables, ch, obs, sigma, g, picks):
-    """Largest gradient error of the library against the oracle's reference
-    gradient over the points `picks` (stopping after --cpu-seconds) and the
-    oracle's single-core rate."""
-    import oracle
-    from threadpoolctl import threadpool_limits
-    off = batch.layer_off
-    errs, done, t_cpu = [], 0, 0.0
-    with threadpool_limits(limits=1):
-        for b in picks:
-            if done and t_cpu > args.cpu_seconds:
-                break
-            t1 = time.perf_counter()
-            ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], sigma)
-            t_cpu += time.perf_counter() - t1
-            done += 1
-            v = np.concatenate([g["dT"][off[b]:off[b + 1]], g["dlog10_vmr"][b], [g["dRp"][b]]])
-            r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
-            big = np.abs(r) >= 1e-3 * np.max(np.abs(r))
-            errs.append(max(np.linalg.norm(v - r) / np.linalg.norm(r),
-                            float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big])))))
-    return max(errs), done, t_cpu
+def kernel_times(ctx, trx, fn, reps, classes):
+    ctx.profile(True)
+    for _ in range(reps):
+        fn()
+    out = {}
+    for k, name in classes:
+        tot, n = ctx.profile_read(k)
+        out[name] = round(tot / max(n, 1), 4)
+    ctx.profile(False)
+    return out
 
 
-def gradient_leg(args, ctx, trx, torch):
+def step_stats(fn, steps):
+    """Median and quartiles (ms) of `steps` launches, each between its own
+    pair of events on the current stream."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for s, e in ev:
+        s.record()
+        fn()
+        e.record()
+    torch.cuda.synchronize()
+    t = np.array([s.elapsed_time(e) for s, e in ev])
+    return float(np.median(t)), float(np.percentile(t, 25)), float(np.percentile(t, 75))
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
+# ---------------------------------------------------------------------------
+# legs
+# ---------------------------------------------------------------------------
+def gradient_leg(args, ctx, trx, torch, pool):
     """chi^2 gradients of 256 parameter points (100-layer perturbed Guillot
     profiles, 7 absorbers, 50000-point tables, 100 channels, 50 ppm noise on
-    the truth's binned spectrum) from one graph-captured gradient plan."""
-    from synth.workloads import make_config
-    t0 = time.time()
-    tables, batch, ch = make_config(4)
-    log(f"gradient inputs generated in {time.time() - t0:.1f} s: B={batch.B}, W={tables.n_wn}")
+    the truth's binned spectrum) from one graph-captured gradient plan, with
+    the workload's FP32 forward (--grad-precision) and, as a second figure,
+    the FP64 forward; every point against the oracle's reference gradient."""
+    tables, batch, ch = _SHARED["cfg4"]
     T = trx.Tables.from_synth(ctx, tables)
     bins = trx.Bins(ctx, T, ch.lo, ch.hi)
     db = trx.DeviceBatch.from_synth(batch, max_layers=100)
     B = batch.B
-    obs, sigma = observation(args, ctx, trx, T, bins, tables, batch, ch, 4, 100)
-    plan = trx.Plan(ctx, T, bins, B_max=B, N_max=100, precision=args.grad_precision, graph=True,
-                    grad=True)
-    plan.autotune(db)
-    ms = time_steps(lambda: plan.launch_grad(db, obs, sigma), args.steps, args.warmup)
-    out = plan.launch_grad(db, obs, sigma)
-    torch.cuda.synchronize()
-    assert int((out["status"] != 0).sum()) == 0
-    ctx.profile(True)
-    for _ in range(max(2, args.steps // 3)):
-        plan.launch_grad(db, obs, sigma)
-    kms = {}
-    for k, name in ((trx.KERNEL_FORWARD, "forward"), (trx.KERNEL_ADJOINT, "adjoint_item"),
-                    (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")):
-        tot, n = ctx.profile_read(k)
-        kms[name] = round(tot / max(n, 1), 4)
-    ctx.profile(False)
-    res = {"metric": "gradient evals/s", "value": round(B / (ms * 1e-3), 1),
-           "unit": "gradient evals/s", "ms_per_step": round(ms, 3),
-           "precision": args.grad_precision, "kernel_ms": kms,
-           "config": {"workload": "gradient-256-100L-7abs-50kwn", "models": B, "layers": 100,
-                      "absorbers": tables.n_abs, "wavenumbers": tables.n_wn,
-                      "channels": bins.n, "noise_ppm": 50, "variant": plan.describe()}}
-    log(f"gradient: {ms:.3f} ms/step ({B / (ms * 1e-3):.1f} evals/s)")
-    if not args.no_cpu:
-        g = {k: v.cpu().numpy() for k, v in out.items()}
-        worst, done, t_cpu = oracle_grad_check(args, batch, tables, ch, obs, sigma, g, range(B))
-        res["error"] = {"max_rel_err_gradient": worst, "models_checked": done}
-        res["cpu_baseline"] = {"value": round(done / t_cpu, 4), "unit": "gradient evals/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"first {done} of {B} points, {t_cpu:.1f} s "
-                                         f"single-threaded numpy FP64 reverse mode"}
-        log(f"gradient oracle: {done} points in {t_cpu:.1f} s; max err {worst:.2e}")
-    plan.close()
+    obs, sigma = observation(ctx, trx, T, bins, batch, 4, 100, bins.n)
+    res = None
+    for prec in dict.fromkeys([args.grad_precision, "fp64"]):
+        plan = trx.Plan(ctx, T, bins, B_max=B, N_max=100, precision=prec, graph=True, grad=True)
+        plan.autotune(db)
+        ms = time_steps(lambda: plan.launch_grad(db, obs, sigma), args.steps, args.warmup)
+        out = plan.launch_grad(db, obs, sigma)
+        torch.cuda.synchronize()
+        assert int((out["status"] != 0).sum()) == 0
+        kms = kernel_times(ctx, trx, lambda: plan.launch_grad(db, obs, sigma), max(2, args.steps // 3),
+                           ((trx.KERNEL_FORWARD, "forward"), (trx.KERNEL_ADJOINT, "adjoint_item"),
+                            (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")))
+        log(f"gradient ({prec} forward): {ms:.3f} ms/step ({B / (ms * 1e-3):.1f} evals/s)")
+        g = {k: v.cpu().numpy().copy() for k, v in out.items()}
+        variant = plan.describe()
+        plan.close()
+        if res is None:
+            res = {"metric": "gradient evals/s", "value": round(B / (ms * 1e-3), 1),
+                   "unit": "gradient evals/s", "ms_per_step": round(ms, 3),
+                   "precision": prec, "kernel_ms": kms,
+                   "config": {"workload": "gradient-256-100L-7abs-50kwn", "models": B, "layers": 100,
+                              "absorbers": tables.n_abs, "wavenumbers": tables.n_wn,
+                              "channels": bins.n, "noise_ppm": 50, "variant": variant}}
+            g_main = g
+        else:
+            res["fp64_forward"] = {"ms_per_step": round(ms, 3), "value": round(B / (ms * 1e-3), 1),
+                                   "kernel_ms": kms}
+            g_64 = g
+    if pool is not None:
+        refs, wall, cpu = run_oracle(pool, "gradient", range(B), (obs[0], sigma))
+        off = batch.layer_off
+        errs, errs64 = [], []
+        for b in range(B):
+            dT, dv, dR, c2 = refs[b]
+            r = np.concatenate([dT, dv, [dR]])
+            for gg, lst in ((g_main, errs), (g_64 if args.grad_precision != "fp64" else g_main, errs64)):
+                v = np.concatenate([gg["dT"][off[b]:off[b + 1]], gg["dlog10_vmr"][b], [gg["dRp"][b]]])
+                lst.append(grad_err(v, r))
+        res["error"] = {"max_rel_err_gradient": max(errs), "median_rel_err_gradient": float(np.median(errs)),
+                        "models_checked": B}
+        if "fp64_forward" in res:
+            res["fp64_forward"]["max_rel_err_gradient"] = max(errs64)
+        n = pool_size()
+        res["cpu_baseline"] = {"value": round(B / wall, 3), "unit": "gradient evals/s", "cores": n,
+                               "kind": "oracle", "single_core_value": round(B / cpu, 4),
+                               "cpu_model": cpu_model(),
+                               "sample": f"all {B} points, numpy FP64 reverse mode, {n} worker "
+                                         f"processes of one thread ({wall:.1f} s wall, {cpu:.1f} s "
+                                         f"of single-thread work)"}
+        log(f"gradient oracle: {B} points in {wall:.1f} s on {n} processes; max err {max(errs):.2e} "
+            f"({args.grad_precision}), {max(errs64):.2e} (fp64)")
     bins.close()
     T.close()
     return res
 
 
+def emission_leg(args, ctx, trx, torch, T, bins, tables, batch, db, pool):
+    """Emission spectra (F_p/F_s, 4 Gauss-Legendre angles, a blackbody star
+    per model) of the main batch from one graph-captured emission plan, and
+    the same with the FP64 path; stratified models against the oracle."""
+    B = batch.B
+    T_star = _SHARED["T_star"]
+    res = {}
+    for prec in dict.fromkeys([args.emission_precision, "fp64"]):
+        pe = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision=prec, graph=True, emission=True)
+        pe.set_star(T_star, n_mu=4)
+        pe.autotune(db)
+        ms = time_steps(lambda: pe.launch(db), max(2, args.steps // (1 if prec != "fp64" else 3)), 1)
+        nat, binned, st = pe.launch(db, native=True)
+        torch.cuda.synchronize()
+        assert int((st != 0).sum()) == 0
+        kms = kernel_times(ctx, trx, lambda: pe.launch(db), 2, ((trx.KERNEL_FORWARD, "forward"),))
+        log(f"emission {prec}: {ms:.3f} ms/step")
+        entry = {"ms_per_step": round(ms, 3), "spectra_per_s": round(B / (ms * 1e-3), 1),
+                 "kernel_ms": kms, "variant": pe.describe()}
+        if pool is not None:
+            picks = stratified(batch, 64, 9)
+            refs, _, _ = run_oracle(pool, "emission", picks, (4,))
+            gn = nat[picks].cpu().numpy()
+            gb = binned[picks].cpu().numpy()
+            en, eb = [], []
+            for i, b in enumerate(picks):
+                lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+                en.append(rel_err(gn[i, lo:hi], refs[b][0]))
+                eb.append(rel_err(gb[i], refs[b][1]))
+            entry["error"] = {"max_rel_err_native": max(en), "median_rel_err_native": float(np.median(en)),
+                              "max_rel_err_binned": max(eb), "models_checked": len(picks)}
+            log(f"emission {prec} oracle: {len(picks)} models, native {max(en):.2e}, binned {max(eb):.2e}")
+        res[prec] = entry
+        pe.close()
+    ep = args.emission_precision
+    out = dict(res[ep])
+    out.update({"precision": ep, "n_mu": 4, "star": "blackbody, 4500-6500 K per model"})
+    if "fp64" in res and ep != "fp64":
+        out["fp64_gpu"] = res["fp64"]
+        out["speedup_vs_fp64_batched"] = round(res["fp64"]["ms_per_step"] / res[ep]["ms_per_step"], 2)
+    return out
+
+
 def large_leg(args, ctx, trx, torch):
     """The large workload: 1024 models of 100-200 layers, 10 absorbers with
     CIA and Rayleigh on 40 T x 30 P x 100000-point tables, 100 channels.  The
-    split-bf16 forward, and the chi^2 gradients (recompute mode) with the FP64
-    and with the split-bf16 forward, one graph-captured plan each; the device
-    memory in use with each gradient plan (tables, model workspaces, partial
-    sums and outputs), and the gradient error of sampled points against the
-    oracle."""
+    split-bf16 forward, and the chi^2 gradients (recompute mode) with the
+    split-bf16 and with the FP64 forward, one graph-captured plan each; the
+    device memory in use with each gradient plan; the forward of two models
+    and the gradient of point 0 against the oracle (in this process, within
+    --cpu-seconds)."""
     from synth.workloads import make_config
     t0 = time.time()
     tables, batch, ch = make_config(5)
@@ -206,51 +384,64 @@ def large_leg(args, ctx, trx, torch):
     pf = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision="bf16x2", graph=True)
     pf.autotune(db)
     ms_f = time_steps(lambda: pf.launch(db), args.steps, args.warmup)
-    _, _, st = pf.launch(db)
+    nat, binned, st = pf.launch(db, native=True)
     torch.cuda.synchronize()
     assert int((st != 0).sum()) == 0
     log(f"large forward bf16x2: {ms_f:.3f} ms/step")
-    obs, sigma = observation(args, ctx, trx, T, bins, tables, batch, ch, 5, 200)
+    obs, sigma = observation(ctx, trx, T, bins, batch, 5, 200, bins.n)
     res = {"forward_ms_per_step": round(ms_f, 3), "forward_spectra_per_s": round(B / (ms_f * 1e-3), 1),
            "forward_precision": "bf16x2", "forward_variant": pf.describe(),
            "config": {"workload": "batched-grad-1024-100to200L-10abs-100000wn", "models": B,
                       "layers": "100-200", "absorbers": tables.n_abs, "wavenumbers": tables.n_wn,
                       "table_grid": [len(tables.T_grid), len(tables.log10P_grid)],
                       "channels": bins.n}}
-    # gradients with the FP64 forward (the residual at its full accuracy) and
-    # with the split-bf16 forward; one plan at a time
-    for prec in ("fp64", "bf16x2"):
+    import oracle
+    from threadpoolctl import threadpool_limits
+    t_cpu = 0.0
+    if not args.no_cpu:
+        order = np.argsort(batch.n_layers * (batch.wn_hi - batch.wn_lo))
+        errs = []
+        with threadpool_limits(limits=1):
+            for b in (int(order[-1]), int(order[0])):
+                t1 = time.perf_counter()
+                r = oracle.forward_model(batch.model(b), tables, ch)
+                t_cpu += time.perf_counter() - t1
+                lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+                errs += [rel_err(nat[b, lo:hi].cpu().numpy(), r["depth"]),
+                         rel_err(binned[b].cpu().numpy(), r["binned"])]
+        res["forward_error"] = {"max_rel_err": max(errs), "models_checked": 2}
+        log(f"large forward oracle: 2 models in {t_cpu:.1f} s, max err {max(errs):.2e}")
+    del nat
+    pf.close()
+    for prec in ("bf16x2", "fp64"):
         pg = trx.Plan(ctx, T, bins, B_max=B, N_max=200, precision=prec, graph=True, grad=True)
         ms_g = time_steps(lambda: pg.launch_grad(db, obs, sigma), max(2, args.steps // 3), 1)
         out = pg.launch_grad(db, obs, sigma)
         torch.cuda.synchronize()
         free1, _ = torch.cuda.mem_get_info()
         n_bad = int((out["status"] != 0).sum())
-        ctx.profile(True)
-        pg.launch_grad(db, obs, sigma)
-        kms = {}
-        for k, name in ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_FORWARD, "forward"),
-                        (trx.KERNEL_ADJOINT, "adjoint_item"),
-                        (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")):
-            tot, n = ctx.profile_read(k)
-            kms[name] = round(tot / max(n, 1), 3)
-        ctx.profile(False)
+        kms = kernel_times(ctx, trx, lambda: pg.launch_grad(db, obs, sigma), 1,
+                           ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_FORWARD, "forward"),
+                            (trx.KERNEL_ADJOINT, "adjoint_item"),
+                            (trx.KERNEL_GEOM_ADJ, "chi2_and_geometry_adjoint")))
         log(f"large gradient ({prec} forward): {ms_g:.3f} ms/step, {n_bad} points flagged")
         gr = {"ms_per_step": round(ms_g, 3), "evals_per_s": round(B / (ms_g * 1e-3), 1),
               "forward_precision": prec, "points_unsupported": n_bad, "kernel_ms": kms,
               "device_memory_gb": round((free0 - free1) / 1e9, 2)}
-        if not args.no_cpu:
+        if not args.no_cpu and t_cpu < args.cpu_seconds:
             g = {k: v.cpu().numpy() for k, v in out.items()}
-            order = np.argsort(batch.n_layers)
-            # point 0 (whose residual is the noise), the longest and the shortest
-            picks = list(dict.fromkeys([0, int(order[-1]), int(order[0])] + list(range(B))))
-            worst, done, t_cpu = oracle_grad_check(args, batch, tables, ch, obs, sigma, g, picks)
-            gr["error"] = {"max_rel_err_gradient": worst, "models_checked": done,
-                           "oracle_seconds": round(t_cpu, 1)}
-            log(f"large gradient oracle: {done} points in {t_cpu:.1f} s; max err {worst:.2e}")
+            off = batch.layer_off
+            with threadpool_limits(limits=1):
+                t1 = time.perf_counter()
+                ref = oracle.chi2_and_grad(batch.model(0), tables, ch, obs[0], sigma)
+                t_cpu += time.perf_counter() - t1
+            v = np.concatenate([g["dT"][off[0]:off[1]], g["dlog10_vmr"][0], [g["dRp"][0]]])
+            r = np.concatenate([ref["dT"], ref["dlog10_vmr"], [ref["dRp"]]])
+            gr["error"] = {"max_rel_err_gradient": grad_err(v, r), "models_checked": 1,
+                           "point": "0 (residual at the noise level)"}
+            log(f"large gradient oracle ({prec}): point 0, err {gr['error']['max_rel_err_gradient']:.2e}")
         res["gradient_" + prec] = gr
         pg.close()
-    pf.close()
     bins.close()
     T.close()
     return res
@@ -287,11 +478,9 @@ def single_leg(args, ctx, trx, torch):
                      "variant": plan.describe()}
             if ref is not None:
                 if native:
-                    g = nat[0].cpu().numpy()
-                    entry["max_rel_err_native"] = float(np.max(np.abs(g - ref["depth"]) / ref["depth"]))
+                    entry["max_rel_err_native"] = rel_err(nat[0].cpu().numpy(), ref["depth"])
                 else:
-                    g = binned[0].cpu().numpy()
-                    entry["max_rel_err_binned"] = float(np.max(np.abs(g - ref["binned"]) / ref["binned"]))
+                    entry["max_rel_err_binned"] = rel_err(binned[0].cpu().numpy(), ref["binned"])
             res[f"{CONFIG_NAMES[cfg]}:{prec}"] = entry
             log(f"single {CONFIG_NAMES[cfg]} {prec}: {us:.1f} us/model")
             plan.close()
@@ -301,59 +490,68 @@ def single_leg(args, ctx, trx, torch):
     return res
 
 
-def clouds_leg(args, plan, tables, batch, ch, trx, torch):
+def clouds_leg(args, plan, trx, torch, pool):
     """The main batch with a flat-opacity cloud deck on two thirds of the
     models (a third finite decks, a third opaque), through the same plan;
-    sampled models (one of each kind) against the oracle."""
-    import oracle
-    from synth.workloads import with_cloud_decks
-    cb = with_cloud_decks(batch, 5)
+    four models of each kind against the oracle."""
+    cb = _SHARED["cfg3_clouds"]
     dbc = trx.DeviceBatch.from_synth(cb, max_layers=200)
     ms = time_steps(lambda: plan.launch(dbc), args.steps, args.warmup)
     _, binned, status = plan.launch(dbc)
     torch.cuda.synchronize()
     assert int((status != 0).sum()) == 0
-    gb = binned.cpu().numpy()
-    errs = []
-    for b in (0, 1, 2, 3, 4, 5):
-        ref = oracle.forward_model(cb.model(b), tables, ch)["binned"]
-        ok = ~np.isnan(ref)
-        errs.append(float(np.max(np.abs(gb[b][ok] - ref[ok]) / ref[ok])))
-    log(f"clouds: {ms:.3f} ms/step; max rel err {max(errs):.2e}")
-    return {"ms_per_step": round(ms, 3), "spectra_per_s": round(batch.B / (ms * 1e-3), 1),
-            "decks": "one third none, one third finite (log10 sigma in [-32, -27] m^2), "
-                     "one third opaque",
-            "max_rel_err_binned": max(errs), "models_checked": len(errs)}
+    res = {"ms_per_step": round(ms, 3), "spectra_per_s": round(cb.B / (ms * 1e-3), 1),
+           "decks": "one third none, one third finite (log10 sigma in [-32, -27] m^2), "
+                    "one third opaque"}
+    if pool is not None:
+        picks = list(range(12))
+        refs, _, _ = run_oracle(pool, "clouds", picks)
+        gb = binned[picks].cpu().numpy()
+        errs = [rel_err(gb[i], refs[b][1]) for i, b in enumerate(picks)]
+        res.update({"max_rel_err_binned": max(errs), "models_checked": len(picks)})
+        log(f"clouds: {ms:.3f} ms/step; max rel err {max(errs):.2e}")
+    return res
 
 
 def retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch):
     """The paper's transit retrieval on synthetic data: 5 log abundances, an
     isothermal T, Rp and the top of an opaque cloud deck, uniform priors; the
-    observation is the oracle's binned spectrum of the truth (100 layers, the
-    whole 40000-point grid) plus seeded 50 ppm noise; single-ellipsoid
-    nested sampling with candidates evaluated 2048 per plan launch."""
-    import oracle
-    from paper_1912_07759_amd.retrieval import TransitRetrieval, nested_sample, posterior
+    observation is the library's FP64 binned spectrum of the truth (100
+    layers, the whole 40000-point grid) plus seeded 50 ppm noise;
+    multi-ellipsoid nested sampling with candidates evaluated 2048 per plan
+    launch (two plans alternating)."""
+    from paper_1912_07759_amd.retrieval import (LikelihoodBudgetExhausted, TransitRetrieval,
+                                                nested_sample, posterior)
     from synth.constants import GM_JUP, R_SUN
     from synth.workloads import observation_noise
     N = 100
     truth = np.array([-3.5, -6.0, -5.0, -7.0, -8.0, 1200.0, 1.35, 3.0])
     na = tables.n_abs
-    m = dict(T=np.full(N, truth[na]), p_bot=1e6, p_top=1e-4, log10_vmr=truth[:na],
-             Rp=truth[na + 1] * TransitRetrieval.R_JUP, Rs=R_SUN, GM=GM_JUP, wn_lo=0,
-             wn_hi=tables.n_wn, he_h2=0.17, k_B=1.380649e-23, amu=1.66053906660e-27, gravity=0,
-             cloud_sigma=np.inf, cloud_p_top=10.0 ** truth[na + 2], cloud_p_bottom=1e6)
+    one = trx.DeviceBatch([N], np.full(N, truth[na]), [1e6], [1e-4], truth[None, :na],
+                          [truth[na + 1] * TransitRetrieval.R_JUP], [R_SUN], [GM_JUP], [0],
+                          [tables.n_wn], max_layers=N, cloud_sigma=[np.inf],
+                          cloud_p_top=[10.0 ** truth[na + 2]], cloud_p_bottom=[1e6])
+    _, tb, st = trx.forward(ctx, T, one, bins, "fp64", native=False)
+    assert int(st[0]) == 0
     noise, sigma = observation_noise(3, 1, len(ch.lo))
-    obs = oracle.forward_model(m, tables, ch)["binned"] + noise[0]
+    obs = tb[0].cpu().numpy() + noise[0]
     ret = TransitRetrieval(ctx, T, bins, obs, sigma, tables.names, R_SUN, GM_JUP, n_layers=N,
                            B_max=2048, precision=args.precision)
-    ret(np.full((4, len(ret.priors)), 0.5))      # graph capture outside the timing
-    torch.cuda.synchronize()
-    ret.n_eval = ret.n_launch = 0
-    ret.wait_seconds = 0.0
-    r = nested_sample(ret, len(ret.priors), n_live=200, batch=2048, dlogz=0.5, seed=1)
+    try:
+        # capture both alternating plans' graphs outside the timing
+        for _ in range(2):
+            ret(np.full((4, len(ret.priors)), 0.5))
+        torch.cuda.synchronize()
+        ret.n_eval = ret.n_launch = 0
+        ret.wait_seconds = 0.0
+        try:
+            r = nested_sample(ret, len(ret.priors), n_live=200, batch=2048, dlogz=0.5, seed=1)
+        except LikelihoodBudgetExhausted as e:
+            log(f"retrieval: {e}")
+            return {"error": str(e)}
+    finally:
+        ret.close()
     _, mean, std = posterior(r, ret.priors)
-    ret.close()
     names = [p.name for p in ret.priors]
     log(f"retrieval: {r['n_eval']} likelihoods in {r['seconds']:.1f} s "
         f"({ret.n_launch} launches, host waited {ret.wait_seconds:.1f} s), logz {r['logz']:.2f}")
@@ -369,35 +567,6 @@ def retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch):
                       "40000 points, 50 channels, 50 ppm noise"}
 
 
-def step_stats(fn, steps):
-    """Median and quartiles (ms) of `steps` launches, each between its own
-    pair of events on the current stream."""
-    import torch
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
-    for s, e in ev:
-        s.record()
-        fn()
-        e.record()
-    torch.cuda.synchronize()
-    t = np.array([s.elapsed_time(e) for s, e in ev])
-    return float(np.median(t)), float(np.percentile(t, 25)), float(np.percentile(t, 75))
-
-
-def time_steps(fn, steps, warmup):
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(steps):
-        fn()
-    e.record()
-    torch.cuda.synchronize()
-    return s.elapsed_time(e) / steps
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -405,13 +574,28 @@ def main():
               "path shards by model across GPUs with no exchange, which this benchmark does "
               "not launch.", file=sys.stderr)
         sys.exit(2)
-    import torch
-    from paper_1912_07759_amd import trx
-    from synth.workloads import make_config, CONFIG_NAMES
+    from synth.workloads import CONFIG_NAMES, make_config, stellar_temperatures, with_cloud_decks
 
+    # host inputs, then the oracle's worker pool, before anything touches the GPU
     t0 = time.time()
     tables, batch, ch = make_config(3, B=args.models)
+    _SHARED["cfg3"] = (tables, batch, ch)
+    _SHARED["cfg3_clouds"] = with_cloud_decks(batch, 5)
+    _SHARED["T_star"] = stellar_temperatures(batch.B)
+    if not args.no_grad:
+        _SHARED["cfg4"] = make_config(4)
     log(f"inputs generated in {time.time() - t0:.1f} s: B={batch.B}, W={tables.n_wn}")
+    pool = None
+    if not args.no_cpu:
+        import multiprocessing
+        from concurrent.futures import ProcessPoolExecutor
+        n = pool_size()
+        pool = ProcessPoolExecutor(max_workers=n, mp_context=multiprocessing.get_context("fork"))
+        list(pool.map(_ping, range(4 * n)))     # every worker forked now
+
+    import torch
+    from paper_1912_07759_amd import trx
+
     ctx = trx.Context(0)
     T = trx.Tables.from_synth(ctx, tables)
     bins = trx.Bins(ctx, T, ch.lo, ch.hi)
@@ -441,15 +625,9 @@ def main():
 
     # dominant kernel, timed live with HIP events around each launch on the
     # library's stream (the plan launches its kernels one by one meanwhile)
-    ctx.profile(True)
-    for _ in range(args.steps):
-        step()
-    kms = {}
-    for k, name in ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_SCHEDULE, "schedule"),
-                    (trx.KERNEL_FORWARD, "forward"), (trx.KERNEL_BINNING, "binning")):
-        tot, n = ctx.profile_read(k)
-        kms[name] = tot / max(n, 1)
-    ctx.profile(False)
+    kms = kernel_times(ctx, trx, step, args.steps,
+                       ((trx.KERNEL_GEOMETRY, "geometry"), (trx.KERNEL_SCHEDULE, "schedule"),
+                        (trx.KERNEL_FORWARD, "forward"), (trx.KERNEL_BINNING, "binning")))
     n_l = batch.n_layers.astype(np.float64)
     w_l = (batch.wn_hi - batch.wn_lo).astype(np.float64)
     flops = float(np.sum(n_l * (n_l + 1.0) * w_l))        # triangular dl.kappa, 2 flop/MAC
@@ -458,11 +636,19 @@ def main():
     kname = {"fp64": "k_fwd64"}.get(args.precision,
                                     "k_fwd_mfma_persist" if "persistent=1" in variant
                                     else "k_fwd_mfma")
+    # the interpolation's compulsory HBM bytes: every FP32 table value once
+    # (cross-sections, CIA, Rayleigh), against the forward kernel's time
+    esz = 8 if args.precision == "fp64" else 4
+    table_bytes = esz * (tables.xsec.size + tables.cia.size
+                         + (tables.rayleigh.size if tables.rayleigh is not None else 0))
+    interp_gbs = table_bytes / (kms["forward"] * 1e-3) / 1e9
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": traffic_of(kname, args.precision),
                 "kernel": kname, "kernel_ms": round(kms["forward"], 4),
-                "algorithmic_tflop_per_launch": round(flops / 1e12, 4)}
+                "algorithmic_tflop_per_launch": round(flops / 1e12, 4),
+                "interp_hbm": {"compulsory_bytes": table_bytes, "achieved_gbs": round(interp_gbs, 2),
+                               "peak_gbs": HBM_PEAK_GBS, "frac": round(interp_gbs / HBM_PEAK_GBS, 5)}}
 
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -507,54 +693,50 @@ def main():
                          "speedup_vs_looped": round(B / (ms * 1e-3) / rate, 2)})
             log(f"fp64 looped: {rate:.1f} spectra/s")
 
-    grad = None
-    if not args.no_grad:
-        grad = gradient_leg(args, ctx, trx, torch)
+    # oracle leg: the error stamp of a stratified sample of at least 256
+    # models (native and binned) and the CPU baseline on the host's cores
+    cpu = err = None
+    if pool is not None:
+        picks = stratified(batch, 256, 0)
+        refs, wall, cpu_s = run_oracle(pool, "forward", picks)
+        nat, _, _ = plan.launch(db, native=True)
+        gn = nat[picks].cpu().numpy()
+        del nat
+        gb = binned[picks].cpu().numpy()
+        en, eb = [], []
+        for i, b in enumerate(picks):
+            lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+            en.append(rel_err(gn[i, lo:hi], refs[b][0]))
+            eb.append(rel_err(gb[i], refs[b][1]))
+        work = float(np.sum(n_l[picks] * w_l[picks]))
+        scale = (work / len(picks)) / float(np.mean(n_l * w_l))
+        n = pool_size()
+        cpu = {"value": round(len(picks) / wall * scale, 3), "unit": "spectra/s", "cores": n,
+               "kind": "oracle", "single_core_value": round(len(picks) / cpu_s * scale, 4),
+               "cpu_model": cpu_model(),
+               "sample": f"{len(picks)} of {B} models spread over the work ranks (largest and "
+                         f"smallest included), numpy FP64 in {n} worker processes of one thread: "
+                         f"{wall:.1f} s wall, {cpu_s:.1f} s of single-thread work; rates scaled "
+                         f"to the batch's mean layers x window"}
+        err = {"max_rel_err_native": max(en), "max_rel_err_binned": max(eb),
+               "median_rel_err_native": float(np.median(en)), "models_checked": len(picks)}
+        log(f"oracle: {len(picks)} models in {wall:.1f} s on {n} processes ({cpu_s:.1f} s of work); "
+            f"max rel err native {max(en):.2e}, binned {max(eb):.2e}")
+
+    grad = None if args.no_grad else gradient_leg(args, ctx, trx, torch, pool)
+    emission = None if args.no_emission else emission_leg(args, ctx, trx, torch, T, bins, tables,
+                                                          batch, db, pool)
+    clouds = None if args.no_clouds else clouds_leg(args, plan, trx, torch, pool)
     single = None if args.no_single else single_leg(args, ctx, trx, torch)
-    large = large_leg(args, ctx, trx, torch) if args.large else None
+    if pool is not None:
+        pool.shutdown()
+    retrieval = None if args.no_retrieval else retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch)
+    plan.close()
+    bins.close()
+    T.close()
+    large = None if args.no_large else large_leg(args, ctx, trx, torch)
 
-    # oracle leg: CPU baseline rate and the error stamp of sampled models
-    cpu = None
-    err = None
-    if not args.no_cpu:
-        import oracle
-        from threadpoolctl import threadpool_limits
-        gb = binned.cpu().numpy()
-        order = np.argsort(batch.n_layers * (batch.wn_hi - batch.wn_lo))
-        pick = [int(order[-1]), int(order[0])] + [int(i) for i in
-                                                  np.random.default_rng(0).permutation(B)]
-        done, errs, t_cpu = [], [], 0.0
-        with threadpool_limits(limits=1):
-            for b in pick:
-                if done and t_cpu > args.cpu_seconds:
-                    break
-                t1 = time.perf_counter()
-                r = oracle.forward_model(batch.model(b), tables, ch)
-                t_cpu += time.perf_counter() - t1
-                done.append(b)
-                ref = r["binned"]
-                ok = ~np.isnan(ref)
-                errs.append(float(np.max(np.abs(gb[b][ok] - ref[ok]) / ref[ok])) if ok.any() else 0.0)
-        work = float(np.sum(n_l[done] * w_l[done]))
-        mean_work = float(np.mean(n_l * w_l))
-        cpu = {"value": round(len(done) / t_cpu * (work / len(done)) / mean_work, 4),
-               "unit": "spectra/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(done)} of {B} models (largest, smallest, then random), "
-                         f"{t_cpu:.1f} s single-threaded numpy FP64, rate scaled to the "
-                         f"batch's mean layers x window"}
-        err = {"max_rel_err_binned": max(errs), "models_checked": len(done)}
-        log(f"oracle: {len(done)} models in {t_cpu:.1f} s; max rel err {max(errs):.2e}")
-
-    clouds = None if args.no_clouds else clouds_leg(args, plan, tables, batch, ch, trx, torch)
-    retrieval = None
-    if not args.no_retrieval:
-        try:
-            retrieval = retrieval_leg(args, ctx, T, bins, tables, ch, trx, torch)
-        except RuntimeError as e:      # the sampler's likelihood budget: report, keep the line
-            retrieval = {"error": str(e)}
-            log(f"retrieval failed: {e}")
-
-    out = {"metric": "forward spectra/s and gradient evals/s at \u22641e-6 rel err, batched vs "
+    out = {"metric": "forward spectra/s and gradient evals/s at ≤1e-6 rel err, batched vs "
                      "plain FP64",
            "value": round(B / (ms * 1e-3), 1), "unit": "spectra/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -563,14 +745,13 @@ def main():
            "data": "synthetic",
            "config": {"workload": CONFIG_NAMES[3], "models": B, "layers": "50-200",
                       "wavenumbers": tables.n_wn, "window": "5000-40000", "absorbers": 5,
-                      "channels": bins.n, "precision": args.precision,
+                      "channels": len(ch.lo), "precision": args.precision,
                       "launch": "hip graph of one plan", "variant": variant},
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
            "ms_per_step_median": round(med, 3), "ms_per_step_iqr": [round(q1, 3), round(q3, 3)],
            "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad,
-           "single_model": single, "clouds": clouds, "retrieval": retrieval}
-    if large is not None:
-        out["large"] = large
+           "emission": emission, "single_model": single, "clouds": clouds, "retrieval": retrieval,
+           "large": large}
     print(json.dumps(out), flush=True)
 
 

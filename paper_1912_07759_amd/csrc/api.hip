@@ -527,7 +527,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
     ba.ws = ws; ba.L = L; ba.B_dev = B_dev; ba.B = B;
     ba.n_wn = t->dev.n_wn; ba.n_ch = bins->n_ch;
     ba.ch_i0 = bins->i0; ba.ch_i1 = bins->i1; ba.ch_off = bins->off; ba.ch_w = bins->w;
-    ba.aws = aws; ba.aws_f64 = precision == TRX_FP64; ba.out = depth_binned;
+    ba.aws = aws; ba.aws_f64 = precision == TRX_FP64 || em != nullptr; ba.out = depth_binned;
     ProfScope ps(c, TRX_KERNEL_BINNING);
     launch_bin(ba, B, c->stream);
   }
@@ -716,7 +716,7 @@ extern "C" trx_status trx_emission(trx_ctx* c, const trx_tables* t, const trx_ba
   hipSetDevice(c->device);
   const Layout L = make_layout(bt->max_layers, precision, false, t->dev, true);
   if ((s = ensure_buffer(c, c->ws, (size_t)bt->B * L.slab, "workspace")) != TRX_OK) return s;
-  const size_t esz = precision == TRX_FP64 ? 8 : 4;
+  const size_t esz = 8;   // the flux ratio per native point is kept in FP64 in every mode
   if ((s = ensure_buffer(c, c->aws, (size_t)bt->B * t->dev.n_wn * esz, "workspace")) != TRX_OK) return s;
   if ((s = ensure_buffer(c, c->sched, SchedBufs::bytes(bt->B), "workspace")) != TRX_OK) return s;
   RunConfig rc = default_config(precision, bt->max_layers);

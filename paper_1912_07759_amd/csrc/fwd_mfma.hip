@@ -159,39 +159,48 @@ __device__ inline float one_minus_exp2(float x) {
   return -fmaf(sc, em1, sc - 1.f);
 }
 
-// e^{-y} to a few FP32 units for an argument y known in FP64 (up to
-// ~100: an FP32 argument would lose 1e-6 of the result there): 2^-y log2 e
-// split into an integer power of two and 2^f, |f| <= 1/2, in FP64.
-__device__ inline float exp_neg_d(double y) {
-  const double t = -1.4426950408889634074 * y;
+// e^{-y} for an argument y >= 0 known in FP64, to a few FP32 units and in
+// the FP64 range (a planet's flux relative to its star's reaches e^-100
+// and below at short wavelengths, and an FP32 argument of ~100 would lose
+// 1e-6 of the result): 2^{-y log2 e} split into an integer power of two and
+// 2^f, |f| <= 1/2, in FP64; +inf gives 0.
+__device__ inline double exp_neg_dd(double y) {
+  const double t = -1.4426950408889634074 * fmin(y, 2000.0);
   const double n = __builtin_rint(t);
-  return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
+  return __builtin_amdgcn_ldexp((double)__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
 }
 
 // One row's term of the emission flux ratio (before (Rp/Rs)^2):
 // (B_{l-1} - B_l)/B_* G(tau_l), from the records e (layer l) and em (layer
-// l - 1) with their x_* - x terms zl, zm in FP64, the accumulator x =
-// -tau_gas/ln 2, the wavenumber nu and the star's 1 - e^{-x_*}.
-__device__ inline float emission_term(float4 e, float4 em, double zl, double zm, float x, float nu, double nud,
-                                      float wst, const FwdArgs& a) {
+// l - 1) with their x_l - x_* terms zl, zm in FP64, the accumulator x =
+// -tau_gas/ln 2, the wavenumber nu and the star's 1 - e^{-x_*}.  The
+// Planck difference is e^{-(x_b - x_*)} q with x_b the hotter of the two
+// layers when they differ by more than 1 in x (then the direct difference),
+// else the cancellation-free form; each angle's exponential is taken
+// together with e^{-(x_b - x_*)} in FP64 range.
+__device__ inline double emission_term(float4 e, float4 em, double zl, double zm, float x, float nu, double nud,
+                                       float wst, const FwdArgs& a) {
   constexpr float kL2e = 1.4426950408889634f;
-  // G: the angles' weights times e^{-tau/mu_i}, tau with the deck's part
-  const float xt = x - kL2e * e.w;
-  float G = 0.f;
-  for (int i = 0; i < a.n_mu; ++i) G = fmaf(a.em_c32[i], __builtin_amdgcn_exp2f(xt * a.em_k32[i]), G);
   const float wl = one_minus_exp2(-kL2e * nu * e.x);
   const float wm = one_minus_exp2(-kL2e * nu * em.x);
-  const float rl = exp_neg_d(nud * zl);                          // e^{x_* - x_l}
   const float dx = nu * e.y;                                     // x_l - x_{l-1}
-  float dB;
+  double yb;
+  float q;
   if (fabsf(dx) <= 1.f) {
-    const float ed = -one_minus_exp2(kL2e * dx);                 // e^{dx} - 1
-    dB = rl * ed * wst / (wm * wl);
+    yb = nud * zl;
+    q = -one_minus_exp2(kL2e * dx) * wst / (wm * wl);            // (e^{dx} - 1) w_* / (w_{l-1} w_l)
+  } else if (dx > 1.f) {
+    yb = nud * zm;
+    q = wst * (1.f / wm - __builtin_amdgcn_exp2f(-kL2e * dx) / wl);
   } else {
-    const float rm = exp_neg_d(nud * zm);
-    dB = wst * (rm / wm - rl / wl);
+    yb = nud * zl;
+    q = wst * (__builtin_amdgcn_exp2f(kL2e * dx) / wm - 1.f / wl);
   }
-  return dB * G;
+  // tau/mu_i with the deck's part (x = -tau_gas / ln 2)
+  const float tau = e.w - 0.69314718055994531f * x;
+  double G = 0.0;
+  for (int i = 0; i < a.n_mu; ++i) G = fma((double)a.em_c32[i], exp_neg_dd(yb + (double)(tau * a.em_k32[i])), G);
+  return (double)q * G;
 }
 
 // Ray block r (0..RBW-1) of a wave: w, then 7 - w.
@@ -625,7 +634,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
             } else if constexpr (EPI == kEpiEm) {
               const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
               if (j >= 1 && j < N)
-                sd += (double)emission_term(sm.em[j], sm.em[j - 1], sm.emz[j], sm.emz[j - 1], x, nu, nud, wst, a);
+                sd += emission_term(sm.em[j], sm.em[j - 1], sm.emz[j], sm.emz[j - 1], x, nu, nud, wst, a);
+              // the top layer also carries B_{N-1}/B_* (e^{-tau_N/mu} = 1): added here,
+              // before the span's barrier, not by the final sum, whose wave
+              // may overlap the next item's loading of these records
+              if (j == N - 1)
+                sd += exp_neg_dd(nud * sm.emz[j]) *
+                      (double)(wst / one_minus_exp2(-1.4426950408889634f * nu * sm.em[j].x));
             } else {
               s = fmaf(w.x, __builtin_amdgcn_exp2f(x), s);
             }
@@ -657,16 +672,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         double atm = 0.0;
         for (int rb = 0; rb < nrb; ++rb) atm += sm.partd[rb][lane];
         if constexpr (EPI == kEpiEm) {
-          // the top layer's B_{N-1}/B_*, then (Rp/Rs)^2
-          const double nud = tb.wn[col];
-          const float nu = (float)nud;
-          const float4 e = sm.em[N - 1];
-          const float wst = one_minus_exp2(-1.4426950408889634f * nu * (float)hd->em_star);
-          const float wl = one_minus_exp2(-1.4426950408889634f * nu * e.x);
-          const float rl = exp_neg_d(nud * sm.emz[N - 1]);
-          atm = hd->em_scale * (atm + (double)(rl * wst / wl));
+          // (Rp/Rs)^2; only the partials (rewritten after the next span's
+          // staging barrier) and the model's header are read here
+          atm *= hd->em_scale;
+          reinterpret_cast<double*>(a.aws)[o] = atm;   // FP64: the flux ratio spans the FP64 range
+        } else {
+          reinterpret_cast<float*>(a.aws)[o] = (float)atm;
         }
-        reinterpret_cast<float*>(a.aws)[o] = (float)atm;
         if (a.depth_native) a.depth_native[o] = hd->Rp2_Rs2 + atm;
         if (!isfinite(atm)) atomicOr(&a.model_status[b], TRX_MODEL_NONFINITE);
       } else {

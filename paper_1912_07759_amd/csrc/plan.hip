@@ -233,7 +233,7 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   if (grad && (s = ensure_buffer(c, p->grad, grad_scratch_bytes(B_max, t->dev.n_wn, bins->n_ch, L.NP),
                                  "plan workspace")) != TRX_OK)
     return fail(s);
-  const size_t esz = precision == TRX_FP64 ? 8 : 4;
+  const size_t esz = (precision == TRX_FP64 || emission) ? 8 : 4;
   if ((s = ensure_buffer(c, p->aws, (size_t)B_max * t->dev.n_wn * esz, "plan workspace")) != TRX_OK)
     return fail(s);
   if ((s = ensure_buffer(c, p->sched, SchedBufs::bytes(B_max), "plan workspace")) != TRX_OK) return fail(s);

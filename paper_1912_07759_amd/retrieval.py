@@ -52,6 +52,12 @@ def paper_transit_priors(absorbers):
     return pri
 
 
+class LikelihoodBudgetExhausted(Exception):
+    """nested_sample stopped: it spent its likelihood budget (max_evals)
+    before the evidence converged.  Not a RuntimeError, so that library and
+    device errors are never mistaken for it."""
+
+
 def _logsubexp(a, b):
     return a + np.log1p(-np.exp(b - a))
 
@@ -122,7 +128,7 @@ def nested_sample(loglike, ndim, n_live=400, batch=1024, dlogz=0.1, enlarge=1.25
                 pool_u, pool_l = pool_u[k + 1:], pool_l[k + 1:]
                 break
             if n_eval >= max_evals:
-                raise RuntimeError("nested_sample: likelihood budget exhausted")
+                raise LikelihoodBudgetExhausted("nested_sample: likelihood budget exhausted")
             ells = ([_bounding_ellipsoid(u, enlarge)] if method == "single"
                     else _split_ellipsoids(u, enlarge, np.exp(logvol), n_live))
             if pending is not None:

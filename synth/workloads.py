@@ -320,6 +320,12 @@ def make_config(cfg_index, n_wn=None, n_lines=None, B=None, layer_range=None,
     raise ValueError(f"unknown workload {cfg_index}")
 
 
+def stellar_temperatures(B, seed=58):
+    """Seeded blackbody temperatures of the stars of an emission batch,
+    uniform in [4500, 6500] K (the paper's host stars are Sun-like)."""
+    return np.random.default_rng(seed).uniform(4500.0, 6500.0, B)
+
+
 def observation_noise(cfg_index, n_models, n_ch, sigma_ppm=50.0):
     """Seeded N(0, sigma^2) noise [n_models, n_ch] and the per-channel sigma
     for a workload's synthetic observation (50 ppm by default)."""

@@ -5,6 +5,7 @@ model of the batch must hold whatever its size."""
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from synth.workloads import make_config, observation_noise, with_cloud_decks
@@ -230,3 +231,46 @@ def test_large_workload_full_size(gpu_ctx):
     forward on sampled points."""
     tables, batch, ch = _forward_full(gpu_ctx, 5, "bf16x2", 200, 1, 2)
     _gradient_full(gpu_ctx, 5, tables, batch, ch, 200, 1, 3)
+
+
+def test_emission_4096_full_size(gpu_ctx):
+    """The benchmark's batch in emission (a blackbody star of 4500-6500 K per
+    model, 4 angles) through an autotuned graph-captured emission plan in
+    FP32, in the benchmark's launch configuration (persistent kernel, items
+    of several spans, back to back): every model valid with finite outputs
+    on its window, sampled models within each point's bound of the oracle."""
+    from paper_1912_07759_amd import trx
+    from synth.workloads import stellar_temperatures
+    from test_gpu_emission import _tol_native
+    tables, batch, ch = make_config(3)
+    T_star = stellar_temperatures(batch.B)
+    T = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, T, ch.lo, ch.hi)
+    plan = trx.Plan(gpu_ctx, T, bins, B_max=batch.B, N_max=200, precision="fp32", graph=True,
+                    emission=True)
+    try:
+        plan.set_star(T_star, n_mu=4)
+        db = trx.DeviceBatch.from_synth(batch, max_layers=200)
+        print("variant", plan.autotune(db))
+        for _ in range(3):
+            nat, binned, st = plan.launch(db, native=True)
+        st = st.cpu().numpy()
+        assert np.all(st == 0), np.flatnonzero(st)
+        picks = _picks(batch, 3, 4)
+        rows = nat[picks].cpu().numpy()
+        for i, b in enumerate(picks):
+            lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+            ref = oracle.emission_model(batch.model(b), tables, ch, n_mu=4, T_star=float(T_star[b]),
+                                        keep=True)
+            g = rows[i, lo:hi]
+            assert np.all(np.isfinite(g))
+            frac = np.max(np.abs(g - ref["fpfs"]) / ref["fpfs"] / _tol_native("fp32", ref, 4))
+            print(f"  model {b}: worst point at {frac:.2f} of its bound")
+            assert frac <= 1.0
+        for b in range(batch.B):
+            lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+            assert bool(torch.all(torch.isfinite(nat[b, lo:hi]))), b
+    finally:
+        plan.close()
+        bins.close()
+        T.close()

@@ -91,3 +91,58 @@ def test_uniform_priors():
     assert [p.name for p in pri][-3:] == ["T_K", "Rp_RJ", "log10_Pcloud_Pa"]
     assert pri[-1](0.0) == pytest.approx(-3.0) and pri[-1](1.0) == pytest.approx(5.0)
     assert (pri[-2].lo, pri[-2].hi) == (1.2, 1.5)
+
+
+class _Deferred:
+    """A likelihood with the submit / collect interface of the GPU
+    retrieval, evaluated on the CPU: submit() only stores the candidates,
+    collect() evaluates them, so the sampler's overlap path (a pending
+    batch drawn from an earlier bound) runs as it does on the GPU."""
+
+    def __init__(self, f):
+        self.f, self.pending, self.n_submit = f, None, 0
+
+    def __call__(self, u):
+        return self.f(u)
+
+    def submit(self, u):
+        assert self.pending is None
+        self.pending = np.array(u, copy=True)
+        self.n_submit += 1
+
+    def collect(self):
+        u, self.pending = self.pending, None
+        return self.f(u)
+
+
+def test_overlapped_batches_keep_the_gaussian_pins():
+    lk = _Deferred(_gauss)
+    r = nested_sample(lk, D, n_live=300, batch=256, seed=11)
+    assert lk.n_submit > 5 and lk.pending is None
+    assert abs(r["logz"] - D * np.log(_cube_mass(0.0, 1.0))) <= 4.0 * r["logz_err"] + 0.02
+    w, mean, std = posterior(r)
+    assert np.all(np.abs(mean - MU) < 0.01) and np.all(np.abs(std - SIG) < 0.01)
+
+
+def test_overlapped_batches_keep_the_bimodal_pins():
+    c1, c2, s = np.array([0.25] * D), np.array([0.75] * D), 0.03
+
+    def ll(u):
+        u = np.atleast_2d(u)
+        a = -0.5 * np.sum(((u - c1) / s) ** 2, axis=1)
+        b = -0.5 * np.sum(((u - c2) / s) ** 2, axis=1)
+        return np.logaddexp(a, b) + np.log(0.5) - D * np.log(np.sqrt(2.0 * np.pi) * s)
+    r = nested_sample(_Deferred(ll), D, n_live=400, batch=512, seed=13, method="multi")
+    assert abs(r["logz"]) <= 4.0 * r["logz_err"] + 0.02, (r["logz"], r["logz_err"])
+    w, _, _ = posterior(r)
+    assert abs(np.sum(w[r["samples"][:, 0] < 0.5]) - 0.5) < 0.1
+
+
+def test_budget_exhaustion_is_its_own_exception():
+    """A spent likelihood budget raises LikelihoodBudgetExhausted, which is
+    not a RuntimeError (so library and device errors are never taken for
+    it)."""
+    from paper_1912_07759_amd.retrieval import LikelihoodBudgetExhausted
+    assert not issubclass(LikelihoodBudgetExhausted, RuntimeError)
+    with pytest.raises(LikelihoodBudgetExhausted):
+        nested_sample(_gauss, D, n_live=50, batch=64, seed=1, max_evals=200)
