@@ -104,7 +104,8 @@ def emission_model(m, tables, channels=None, n_mu=4, T_star=5800.0, keep=False):
     chi, chi_h2, chi_he, mu_kg, valid = chemistry(m["log10_vmr"], m["he_h2"], tables.abs_mass,
                                                   tables.h2_mass, tables.he_mass, m["amu"])
     z = altitude(T, P, mu_kg, m["Rp"], m["GM"], m["k_B"], m["gravity"])
-    kappa = opacity(T, P, chi, chi_h2, chi_he, tables, m["k_B"], lo, hi)
+    kappa = opacity(T, P, chi, chi_h2, chi_he, tables, m["k_B"], lo, hi,
+                    t_interp=m.get("t_interp", "linear"))
     sigma_c = m.get("cloud_sigma", 0.0)
     if sigma_c != 0.0:
         kappa_c, _ = cloud_opacity(P, T, m["k_B"], sigma_c, m["cloud_p_top"], m["cloud_p_bottom"])

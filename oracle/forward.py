@@ -44,6 +44,13 @@ design notes):
   A14 chi^2 = sum_c ((D_c - O_c)/sigma_c)^2.
   A18 Rayleigh applies to every species (absorbers, H2, He); CIA pairs are
       given by species ids (absorbers 0..n_abs-1, then H2, then He).
+  A25 the exponential temperature scheme (Opacities section, sigma(T) =
+      a e^{-b/T} through the two bracketing grid temperatures, then linear
+      along log10 P as in A1) applies to the cross-section tables; CIA stays
+      linear in T.  Where a node value is not positive (the logarithm in b is
+      undefined) that (P node, wavenumber) falls back to the linear scheme.
+      Out-of-range T clamps to the edge node as in A3 (the scheme then
+      returns the node value).
   A24 the flat-opacity cloud deck (equation clouds) is sigma rho on the
       layers whose centre pressure lies between the two deck pressures
       (bounds included, either order); sigma = +inf is the fully opaque
@@ -187,10 +194,13 @@ def bracket(grid, x):
 
 
 def interp_xsec(table, T_grid, log10P_grid, T, log10P, p_interp="log",
-                zero_rule="both"):
+                zero_rule="both", t_interp="linear"):
     """Opacities section, linear scheme: sigma(T) = sigma(T1) + m (T - T1)
     with m = (sigma(T2) - sigma(T1)) / (T2 - T1), then the same form along P
     (reading A1: along log10 P, or along P itself with p_interp="linear").
+    t_interp="exp": the exponential scheme along T (reading A25),
+    sigma(T) = a e^{-b/T}, b = (1/T2 - 1/T1)^{-1} ln(sigma(T1)/sigma(T2)),
+    a = sigma(T1) e^{b/T1}.
 
     table: [nT, nP, W].  Out-of-range rules (reading A3): T and P clamp to
     the grid edges; T below AND P below the grid gives zero.
@@ -206,7 +216,15 @@ def interp_xsec(table, T_grid, log10P_grid, T, log10P, p_interp="log",
     def along_T(j):
         s1, s2 = table[iT, j], table[iT + 1, j]
         m = (s2 - s1) / (T2 - T1)
-        return s1 + m * (Tu - T1)
+        lin = s1 + m * (Tu - T1)
+        if t_interp == "linear":
+            return lin
+        ok = (s1 > 0) & (s2 > 0)
+        r1 = np.where(ok, s1, 1.0)
+        r2 = np.where(ok, s2, 1.0)
+        b = np.log(r1 / r2) / (1.0 / T2 - 1.0 / T1)
+        a = r1 * np.exp(b / T1)
+        return np.where(ok, a * np.exp(-b / Tu), lin)
 
     s_p1, s_p2 = along_T(iP), along_T(iP + 1)
     if p_interp == "log":
@@ -228,7 +246,7 @@ def interp_cia(table, T_grid, T):
 
 
 def opacity(T, P, chi_abs, chi_h2, chi_he, tables, k_B, lo, hi,
-            p_interp="log", zero_rule="both"):
+            p_interp="log", zero_rule="both", t_interp="linear"):
     """Absorption coefficient kappa[l, w] (m^-1) of each layer over the
     window [lo, hi): the integrands of equations opt_dpth (absorption),
     cia_opt_dpth (CIA) and contrib (Rayleigh with w = chi), summed over
@@ -248,7 +266,7 @@ def opacity(T, P, chi_abs, chi_h2, chi_he, tables, k_B, lo, hi,
         for i in range(tables.n_abs):
             acc = acc + chi_abs[i] * interp_xsec(tables.xsec[i][:, :, lo:hi],
                                                  tables.T_grid, tables.log10P_grid,
-                                                 T[l], lp[l], p_interp, zero_rule)
+                                                 T[l], lp[l], p_interp, zero_rule, t_interp)
         if tables.rayleigh is not None:
             for s in range(tables.n_abs + 2):
                 acc = acc + chi_s[s] * tables.rayleigh[s, lo:hi]
@@ -346,7 +364,8 @@ def forward_model(m, tables, channels=None, p_interp="log", zero_rule="both",
     """One model: dict ``m`` with T (per layer, bottom first), p_bot, p_top,
     log10_vmr, Rp, Rs, GM, wn_lo, wn_hi, he_h2, k_B, amu, gravity, and
     optionally a cloud deck: cloud_sigma (m^2, +inf for opaque; absent or 0
-    for none), cloud_p_top, cloud_p_bottom (Pa).
+    for none), cloud_p_top, cloud_p_bottom (Pa); optionally t_interp
+    ("linear", the default, or "exp": reading A25).
 
     Returns a dict with the native depth over the window (``depth``), the
     binned depth (``binned``, if channels are given) and ``valid``.  With
@@ -363,7 +382,7 @@ def forward_model(m, tables, channels=None, p_interp="log", zero_rule="both",
     dl = chord_lengths(z, m["Rp"])
     A = annulus_weights(z, m["Rp"])
     kappa = opacity(T, P, chi, chi_h2, chi_he, tables, m["k_B"], lo, hi,
-                    p_interp, zero_rule)
+                    p_interp, zero_rule, m.get("t_interp", "linear"))
     tau = optical_depth(dl, kappa)
     sigma_c = m.get("cloud_sigma", 0.0)
     if sigma_c != 0.0:

@@ -462,3 +462,84 @@ def test_paper_magnitude_sanity():
     tables, batch, _ = make_config(1)
     D = F.forward_model(batch.model(0), tables)["depth"]
     assert 0.0100983 < D.min() and D.max() < 0.0125
+
+
+# --------------------------------------------------------------------------
+# exponential temperature interpolation (reading A25)
+# --------------------------------------------------------------------------
+def _exp_table(nT=7, nP=5, W=6, seed=4):
+    """Tables of the form a(P, w) e^{-b(P, w)/T} at the grid temperatures."""
+    rng = np.random.default_rng(seed)
+    T = np.sort(rng.uniform(250, 3200, nT))
+    lp = np.sort(rng.uniform(-4, 6, nP))
+    a = 10.0 ** rng.uniform(-24, -20, (nP, W))
+    b = rng.uniform(200.0, 6000.0, (nP, W))
+    tab = a[None] * np.exp(-b[None] / T[:, None, None])
+    return T, lp, tab, a, b
+
+
+def test_exp_interpolation_exact_on_exponential_tables():
+    """The scheme reproduces a e^{-b/T} exactly between the nodes along T;
+    along log10 P it is linear (checked at the P nodes and by linearity)."""
+    T, lp, tab, a, b = _exp_table()
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        t = rng.uniform(T[0], T[-1])
+        j = int(rng.integers(0, len(lp)))
+        v = F.interp_xsec(tab, T, lp, t, lp[j], t_interp="exp")
+        assert np.allclose(v, a[j] * np.exp(-b[j] / t), rtol=1e-12, atol=0)
+        x = rng.uniform(lp[0], lp[-1])
+        i = int(np.searchsorted(lp, x, side="right")) - 1
+        w = (x - lp[i]) / (lp[i + 1] - lp[i])
+        want = (1 - w) * a[i] * np.exp(-b[i] / t) + w * a[i + 1] * np.exp(-b[i + 1] / t)
+        assert np.allclose(F.interp_xsec(tab, T, lp, t, x, t_interp="exp"), want, rtol=1e-12, atol=0)
+    # the linear scheme is not exact on these tables (the two differ between nodes)
+    t = 0.5 * (T[2] + T[3])
+    assert not np.allclose(F.interp_xsec(tab, T, lp, t, lp[1]), a[1] * np.exp(-b[1] / t), rtol=1e-3,
+                           atol=0)
+
+
+def test_exp_interpolation_nodes_clamps_and_fallback():
+    """Node values are returned at the nodes; out-of-range T and P follow the
+    clamp rules; where a node value is not positive the linear scheme is
+    used (and reproduces linear data there)."""
+    T, lp, tab, a, b = _exp_table()
+    for i in range(len(T)):
+        for j in range(len(lp)):
+            # a e^{-b/T} at a node cancels e^{b/T1} e^{-b/T1}: rounding
+            # grows with b/T (here up to ~100)
+            assert np.allclose(F.interp_xsec(tab, T, lp, T[i], lp[j], t_interp="exp"), tab[i, j],
+                               rtol=1e-11, atol=0)
+    xm = 0.5 * (lp[1] + lp[2])
+    assert np.allclose(F.interp_xsec(tab, T, lp, T[0] - 40, xm, t_interp="exp"),
+                       F.interp_xsec(tab, T, lp, T[0], xm, t_interp="exp"), rtol=1e-14, atol=0)
+    assert np.allclose(F.interp_xsec(tab, T, lp, T[-1] + 40, xm, t_interp="exp"),
+                       F.interp_xsec(tab, T, lp, T[-1], xm, t_interp="exp"), rtol=1e-14, atol=0)
+    assert np.all(F.interp_xsec(tab, T, lp, T[0] - 40, lp[0] - 1, t_interp="exp") == 0.0)
+    # zeros at one node of a column: that column is linear in T
+    lin_T, lin_lp, lin_tab, f = _bilinear_table(nT=len(T), nP=len(lp), W=6)
+    mixed = tab.copy()
+    mixed[:, :, 2] = lin_tab[:, :, 2]
+    mixed[3, :, 2] = 0.0
+    t = 0.3 * T[2] + 0.7 * T[3]
+    v = F.interp_xsec(mixed, T, lp, t, lp[1], t_interp="exp")
+    s1, s2 = mixed[2, 1, 2], mixed[3, 1, 2]
+    assert np.isclose(v[2], s1 + (s2 - s1) * (t - T[2]) / (T[3] - T[2]), rtol=1e-14, atol=0)
+    assert np.allclose(v[[0, 1, 3, 4, 5]], (a[1] * np.exp(-b[1] / t))[[0, 1, 3, 4, 5]], rtol=1e-12,
+                       atol=0)
+
+
+def test_exp_interpolation_model_equals_linear_at_node_temperatures():
+    """An isothermal model at a grid temperature gives the same spectrum in
+    both schemes (each layer interpolates at a node), and a model between
+    nodes does not."""
+    tables, batch, _ = make_config(2, n_wn=300, n_lines=60)
+    m = batch.model(0)
+    m["T"] = np.full(len(m["T"]), tables.T_grid[7])
+    a = F.forward_model(m, tables)["depth"]
+    bq = F.forward_model(dict(m, t_interp="exp"), tables)["depth"]
+    assert np.allclose(a, bq, rtol=1e-13, atol=0)
+    m["T"] = np.full(len(m["T"]), 0.5 * (tables.T_grid[7] + tables.T_grid[8]))
+    a = F.forward_model(m, tables)["depth"]
+    bq = F.forward_model(dict(m, t_interp="exp"), tables)["depth"]
+    assert not np.allclose(a, bq, rtol=1e-9, atol=0)
