@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--no-emission", action="store_true", help="skip the emission leg")
     p.add_argument("--emission-precision", default="fp32", choices=["fp32", "bf16x2", "bf16x3", "fp64"],
                    help="the emission leg's fast mode (FP64 is always timed as well)")
+    p.add_argument("--no-exp-t", action="store_true",
+                   help="skip the leg with the exponential temperature scheme")
     p.add_argument("--no-clouds", action="store_true",
                    help="skip the leg with cloud decks on the main batch")
     p.add_argument("--no-retrieval", action="store_true",
@@ -116,9 +118,11 @@ def _oracle_task(job):
     with threadpool_limits(limits=1):
         t0 = time.time()
         p0 = time.perf_counter()
-        if kind in ("forward", "clouds"):
+        if kind in ("forward", "clouds", "exp_t"):
             tables, batch, ch = _SHARED["cfg3"]
             m = (_SHARED["cfg3_clouds"] if kind == "clouds" else batch).model(b)
+            if kind == "exp_t":
+                m = dict(m, t_interp="exp")
             r = oracle.forward_model(m, tables, ch)
             out = (r["depth"], r["binned"])
         elif kind == "emission":
@@ -360,6 +364,52 @@ def emission_leg(args, ctx, trx, torch, T, bins, tables, batch, db, pool):
     if "fp64" in res and ep != "fp64":
         out["fp64_gpu"] = res["fp64"]
         out["speedup_vs_fp64_batched"] = round(res["fp64"]["ms_per_step"] / res[ep]["ms_per_step"], 2)
+    return out
+
+
+def exp_t_leg(args, ctx, trx, torch, tables, bins_lin, batch, db, ch, pool):
+    """The main batch over the same tables in the exponential temperature
+    scheme (sigma = a e^{-b/T} between the T nodes): one graph-captured plan
+    in the main precision and the FP64 path; stratified models against the
+    oracle in that scheme."""
+    B = batch.B
+    Tx = trx.Tables.from_synth(ctx, tables, "exp")
+    bx = trx.Bins(ctx, Tx, ch.lo, ch.hi)
+    res = {}
+    for prec in dict.fromkeys([args.precision, "fp64"]):
+        px = trx.Plan(ctx, Tx, bx, B_max=B, N_max=200, precision=prec, graph=True)
+        px.autotune(db)
+        ms = time_steps(lambda: px.launch(db), max(2, args.steps // (1 if prec != "fp64" else 3)), 1)
+        nat, binned, st = px.launch(db, native=True)
+        torch.cuda.synchronize()
+        assert int((st != 0).sum()) == 0
+        kms = kernel_times(ctx, trx, lambda: px.launch(db), 2, ((trx.KERNEL_FORWARD, "forward"),))
+        log(f"exp-T {prec}: {ms:.3f} ms/step")
+        entry = {"ms_per_step": round(ms, 3), "spectra_per_s": round(B / (ms * 1e-3), 1),
+                 "kernel_ms": kms, "variant": px.describe()}
+        if pool is not None and prec != "fp64":
+            picks = stratified(batch, 64, 11)
+            refs, _, _ = run_oracle(pool, "exp_t", picks)
+            gn = nat[picks].cpu().numpy()
+            gb = binned[picks].cpu().numpy()
+            en, eb = [], []
+            for i, b in enumerate(picks):
+                lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
+                en.append(rel_err(gn[i, lo:hi], refs[b][0]))
+                eb.append(rel_err(gb[i], refs[b][1]))
+            entry["error"] = {"max_rel_err_native": max(en), "median_rel_err_native": float(np.median(en)),
+                              "max_rel_err_binned": max(eb), "models_checked": len(picks)}
+            log(f"exp-T {prec} oracle: {len(picks)} models, native {max(en):.2e}, binned {max(eb):.2e}")
+        res[prec] = entry
+        del nat, binned
+        px.close()
+    bx.close()
+    Tx.close()
+    out = dict(res[args.precision])
+    out["precision"] = args.precision
+    if "fp64" in res and args.precision != "fp64":
+        out["fp64_gpu"] = res["fp64"]
+        out["speedup_vs_fp64_batched"] = round(res["fp64"]["ms_per_step"] / res[args.precision]["ms_per_step"], 2)
     return out
 
 
@@ -727,6 +777,7 @@ def main():
     emission = None if args.no_emission else emission_leg(args, ctx, trx, torch, T, bins, tables,
                                                           batch, db, pool)
     clouds = None if args.no_clouds else clouds_leg(args, plan, trx, torch, pool)
+    exp_t = None if args.no_exp_t else exp_t_leg(args, ctx, trx, torch, tables, bins, batch, db, ch, pool)
     single = None if args.no_single else single_leg(args, ctx, trx, torch)
     if pool is not None:
         pool.shutdown()
@@ -750,7 +801,8 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
            "ms_per_step_median": round(med, 3), "ms_per_step_iqr": [round(q1, 3), round(q3, 3)],
            "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad,
-           "emission": emission, "single_model": single, "clouds": clouds, "retrieval": retrieval,
+           "emission": emission, "exp_t": exp_t, "single_model": single, "clouds": clouds,
+           "retrieval": retrieval,
            "large": large}
     print(json.dumps(out), flush=True)
 

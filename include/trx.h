@@ -120,6 +120,24 @@ trx_status trx_synchronize(trx_ctx* ctx);
 
 /* ---- opacity tables (Opacities section) ------------------------------- */
 
+/* How the cross-sections are interpolated in temperature between the two
+ * bracketing grid temperatures T1 < T2 (Opacities section); either way the
+ * result is then interpolated linearly in log10 P, and CIA is linear in T.
+ *  TRX_T_LINEAR  sigma = sigma1 + (sigma2 - sigma1)(T - T1)/(T2 - T1).
+ *  TRX_T_EXP     sigma = a e^{-b/T} through both nodes, i.e.
+ *                sigma1 (sigma2/sigma1)^u with u = (1/T - 1/T1)/(1/T2 - 1/T1);
+ *                where sigma1 or sigma2 is not positive that point takes
+ *                the linear scheme.  Out-of-range T clamps to the edge
+ *                node as in the linear scheme.  The device keeps a second
+ *                FP32 table of (sigma, log2 of the ratio to the next
+ *                temperature node) pairs, twice the FP32 table's size.
+ *                Not differentiated: trx_chi2_grad and gradient plans
+ *                return TRX_E_UNSUPPORTED for such tables. */
+typedef enum {
+  TRX_T_LINEAR = 0,
+  TRX_T_EXP = 1
+} trx_t_interp;
+
 /* All pointers are HOST pointers, read during the call.  Every table lives
  * on one shared wavenumber grid (the paper's "native" grid, resampling
  * done by the caller).  Species ids: 0..n_abs-1 absorbers, n_abs = H2,
@@ -142,14 +160,16 @@ typedef struct {
   const double* cia_cm5;        /* [n_cia][n_Tcia][n_wn] */
   const int32_t* cia_pair;      /* [n_cia][2] species ids */
   const double* rayleigh_cm2;   /* [n_abs + 2][n_wn], or NULL for none */
+  int32_t t_interp;             /* trx_t_interp: scheme of the cross-sections in T */
 } trx_tables_desc;
 
 /* Copy the tables to the device (FP64 and FP32 copies, wavenumber
  * contiguous).  The handle owns the device memory.  Returns
- * TRX_E_INVALID_ARG for a malformed description and TRX_E_UNSUPPORTED when
- * the FP32 table of one absorber (n_T n_P n_wn values), of one CIA pair
- * (n_Tcia n_wn) or the Rayleigh table ((n_abs + 2) n_wn) reaches 2 GiB: the
- * matrix-core kernels address a table row with a 32-bit byte offset. */
+ * TRX_E_INVALID_ARG for a malformed description (t_interp included) and
+ * TRX_E_UNSUPPORTED when the FP32 table of one absorber (n_T n_P n_wn
+ * values; twice that for TRX_T_EXP), of one CIA pair (n_Tcia n_wn) or the
+ * Rayleigh table ((n_abs + 2) n_wn) reaches 2 GiB: the matrix-core kernels
+ * address a table row with a 32-bit byte offset. */
 trx_status trx_tables_create(trx_ctx* ctx, const trx_tables_desc* desc, trx_tables** out);
 trx_status trx_tables_destroy(trx_tables* t);
 
@@ -290,7 +310,8 @@ trx_status trx_forward_noalloc(trx_ctx* ctx, const trx_tables* t, const trx_batc
  * gradient outputs.
  * Derivatives at table nodes and under clamps are one-sided (the lower
  * bracket's slope; zero under a clamp).  The binned spectrum must cover
- * every channel in each model's window, else that model's chi2 is NaN. */
+ * every channel in each model's window, else that model's chi2 is NaN.
+ * Tables with t_interp = TRX_T_EXP: TRX_E_UNSUPPORTED. */
 trx_status trx_chi2_grad(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch,
                          const trx_bins* bins, trx_precision precision,
                          const double* obs, const double* sigma, int32_t recompute,
@@ -314,7 +335,8 @@ enum {
  * kernels for TRX_PLAN_GRAD).  It replaces the sampler-level parallelism
  * over live points (Parallel/MPI discussion of the Benchmarks section) by
  * one launch over the whole live-point set.  bins may be NULL (then no
- * binned output).  Creating a plan allocates; launching one does not. */
+ * binned output).  Creating a plan allocates; launching one does not.
+ * TRX_PLAN_GRAD with TRX_T_EXP tables: TRX_E_UNSUPPORTED. */
 trx_status trx_plan_create(trx_ctx* ctx, const trx_tables* t, const trx_bins* bins,
                            int32_t B_max, int32_t N_max, trx_precision precision,
                            int32_t flags, trx_plan** out);

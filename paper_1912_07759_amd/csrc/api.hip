@@ -68,6 +68,25 @@ __global__ void k_to_f32(const double* __restrict__ s, float* __restrict__ d, in
   for (; i < n; i += st) d[i] = (float)(s[i] * scale);
 }
 
+// Exponential-T pairs: for every absorber, temperature node iT, pressure
+// node and wavenumber, (sigma[iT], log2(sigma[iT+1] / sigma[iT])) in FP32 from
+// the FP64 table; NaN as the ratio where either value is not positive (that
+// point takes the linear scheme), 0 at the last temperature node (no
+// interval above it).
+__global__ void k_exp_pairs(const double* __restrict__ s, float2* __restrict__ d, int64_t n, int64_t row_T,
+                            int64_t per_abs) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double s1 = s[i];
+    const int64_t within = i % per_abs;   // index inside one absorber's [n_T][n_P][n_wn]
+    double r = 0.0;
+    if (within + row_T < per_abs) {
+      const double s2 = s[i + row_T];
+      r = (s1 > 0.0 && s2 > 0.0) ? log2(s2 / s1) : __builtin_nan("");
+    }
+    d[i] = make_float2((float)s1, (float)r);
+  }
+}
+
 __global__ void k_copy_status(const uint8_t* ws, int64_t slab, const int32_t* B_dev, int B,
                               int32_t* out) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,6 +219,8 @@ extern "C" trx_status trx_tables_create(trx_ctx* c, const trx_tables_desc* d, tr
   if (d->n_P < 2 || d->n_P > TRX_MAX_PGRID || !d->log10P_Pa || !strictly_increasing(d->log10P_Pa, d->n_P))
     return set_err(c, TRX_E_INVALID_ARG, "log10 pressure grid must have 2..%d strictly increasing points",
                    TRX_MAX_PGRID);
+  if (d->t_interp != TRX_T_LINEAR && d->t_interp != TRX_T_EXP)
+    return set_err(c, TRX_E_INVALID_ARG, "t_interp must be TRX_T_LINEAR or TRX_T_EXP");
   if (d->n_abs < 0 || d->n_abs > TRX_MAX_ABSORBERS)
     return set_err(c, TRX_E_INVALID_ARG, "n_abs must be in 0..%d", TRX_MAX_ABSORBERS);
   if (d->n_abs > 0 && (!d->xsec_cm2 || !d->abs_mass_amu))
@@ -223,7 +244,8 @@ extern "C" trx_status trx_tables_create(trx_ctx* c, const trx_tables_desc* d, tr
   {
     const double lim = 2147483648.0;   // row offsets are 32-bit byte offsets
     const double wb = 4.0 * d->n_wn;
-    if (wb * d->n_T * d->n_P >= lim || (d->n_cia > 0 && wb * d->n_Tcia >= lim) || wb * (d->n_abs + 2) >= lim)
+    const double wx = d->t_interp == TRX_T_EXP ? 2.0 * wb : wb;
+    if (wx * d->n_T * d->n_P >= lim || (d->n_cia > 0 && wb * d->n_Tcia >= lim) || wb * (d->n_abs + 2) >= lim)
       return set_err(c, TRX_E_UNSUPPORTED, "an FP32 table of one absorber, CIA pair or the Rayleigh table reaches 2 GiB");
   }
   hipSetDevice(c->device);
@@ -248,6 +270,21 @@ extern "C" trx_status trx_tables_create(trx_ctx* c, const trx_tables_desc* d, tr
   const int64_t nx = (int64_t)d->n_abs * d->n_T * d->n_P * d->n_wn;
   if ((s = upload(c, d->xsec_cm2, nx, &g, &f32, t->owned)) != TRX_OK) return fail(s);
   D.xsec64 = g; D.xsec32 = f32;
+  if (d->t_interp == TRX_T_EXP) {
+    D.t_exp = 1;
+    if (nx > 0) {
+      float2* px = nullptr;
+      hipError_t e = hipMalloc(&px, nx * sizeof(float2));
+      if (e != hipSuccess) return fail(hip_err(c, e, "trx_tables_create"));
+      t->owned.push_back(px);
+      const int64_t row_T = (int64_t)d->n_P * d->n_wn;
+      hipLaunchKernelGGL(k_exp_pairs, dim3(1024), dim3(256), 0, (hipStream_t)0, D.xsec64, px, nx, row_T,
+                         (int64_t)d->n_T * row_T);
+      e = hipGetLastError();
+      if (e != hipSuccess) return fail(hip_err(c, e, "trx_tables_create"));
+      D.xexp32 = px;
+    }
+  }
   if (d->n_cia > 0) {
     if ((s = upload(c, d->Tcia_K, d->n_Tcia, &g, &f32, t->owned)) != TRX_OK) return fail(s);
     D.Tcia = g;
@@ -804,6 +841,8 @@ extern "C" trx_status trx_chi2_grad(trx_ctx* c, const trx_tables* t, const trx_b
     return set_err(c, TRX_E_INVALID_ARG, "trx_chi2_grad: a required pointer is null");
   if (!recompute)
     return set_err(c, TRX_E_UNSUPPORTED, "only the recompute mode of the gradient is built");
+  if (t->dev.t_exp)
+    return set_err(c, TRX_E_UNSUPPORTED, "the gradient of the exponential temperature scheme is not built");
   if (bt->max_layers > TRX_MAX_LAYERS_MFMA)
     return set_err(c, TRX_E_UNSUPPORTED, "the gradient supports at most %d layers", TRX_MAX_LAYERS_MFMA);
   hipSetDevice(c->device);

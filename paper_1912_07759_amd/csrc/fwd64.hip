@@ -23,6 +23,12 @@
 // of the model's opacity slots (table corners and CIA nodes) and contracts
 // over them on the same FP64 instruction, skipping the slot blocks whose P
 // is zero for a ray block; no per-layer opacity is formed.
+//
+// Tables in the exponential temperature scheme (Opacities section) have one
+// absorber slot per layer: its row is the layer's own mixed cross-section,
+// sum_i chi_i sigma_i with sigma_i = sigma1 e^{u ln(sigma2/sigma1)} at the two
+// pressure nodes of the layer's bracket and linear in log10 P between them;
+// the dense kernel forms the same per layer.
 #include "trx_internal.h"
 
 namespace trx {
@@ -79,6 +85,28 @@ __device__ inline void stage64(const double* tab, int64_t abs_stride, int W, int
   }
 }
 
+// Exponential temperature scheme in FP64 (Opacities section):
+// sigma1 (sigma2/sigma1)^u = sigma1 e^{u ln(sigma2/sigma1)}, or the linear
+// form where either node value is not positive.
+__device__ inline double xt_sigma64(double s1, double s2, double u, double wT) {
+  return (s1 > 0.0 && s2 > 0.0) ? s1 * exp(u * log(s2 / s1)) : fma(wT, s2 - s1, s1);
+}
+// sum_t wt[t] sigma_t at the layer of record r = {u, w_P, w_T, 0} whose
+// lower corner (iT, iP) has row offset o (= (iT n_P + iP) W + column):
+// the exponential form in T at both pressure nodes, then linear in log10 P.
+__device__ inline double xt_mix64(const double* tab, int64_t stride, int nt, const double* wt, int64_t o,
+                                  double4 r, int W, int nP) {
+  double acc = 0.0;
+  const int64_t dT = (int64_t)nP * W;
+  for (int t = 0; t < nt; ++t) {
+    const double* p = tab + (int64_t)t * stride + o;
+    const double g0 = xt_sigma64(p[0], p[dT], r.x, r.z);
+    const double g1 = xt_sigma64(p[W], p[dT + W], r.x, r.z);
+    acc = fma(wt[t], fma(r.y, g1 - g0, g0), acc);
+  }
+  return acc;
+}
+
 // TAU: also write the optical depth of every ray and column to a.tau (a
 // separate instantiation: the stores cost the kernel registers)
 template <bool TAU>
@@ -128,9 +156,14 @@ __device__ void process64(const FwdArgs& a, int b_in, int span_in, Smem64& sm) {
     crows = rows + nU * kCols;
     if (has_cia) stage64(tb.cia64, cia_stride, W, cc, sm.tids, nV, hd->cia_w, tb.n_cia, crows, wave, lane);
   };
-  const bool mstage = ml->nU + ml->nV <= kRows && ml->nV <= kMListV;
+  // the exponential scheme forms each layer's cross-sections directly: only
+  // the CIA rows are staged
+  const bool xt = L.xt != 0;
+  const double4* xt64 = reinterpret_cast<const double4*>(slab + L.off_xt64);
+  const int nUs = xt ? 0 : ml->nU;
+  const bool mstage = nUs + ml->nV <= kRows && ml->nV <= kMListV;
   const int slot_off = mstage ? 2 : 4;
-  if (mstage) stage(ml->ids, ml->nU, ml->tids, ml->nV);
+  if (mstage) stage(ml->ids, nUs, ml->tids, ml->nV);
   if (tid < kCols) sm.atm[tid] = 0.0;
 
   const int nrb16 = (N + 15) / 16;
@@ -144,7 +177,7 @@ __device__ void process64(const FwdArgs& a, int b_in, int span_in, Smem64& sm) {
     for (int kb = p0; kb < nkb; ++kb) {
       if (!mstage) {
         const KBlk* kd = kblk + kb;
-        stage(kd->ids, kd->nU, kd->tids, kd->nV);
+        stage(kd->ids, xt ? 0 : kd->nU, kd->tids, kd->nV);
       }
       if (tid < 16 * 8) {
         const int l = 16 * kb + tid / 8;
@@ -163,11 +196,16 @@ __device__ void process64(const FwdArgs& a, int b_in, int span_in, Smem64& sm) {
         double kv = 0.0;
         if (l < N) {
           const double* w = sm.lw[k];
-          const uint32_t sl = __builtin_amdgcn_readfirstlane((uint32_t)sm.sl[k].x);
-          kv = w[0] * rows[(sl & 0xff) * kCols + lane];
-          kv = fma(w[1], rows[((sl >> 8) & 0xff) * kCols + lane], kv);
-          kv = fma(w[2], rows[((sl >> 16) & 0xff) * kCols + lane], kv);
-          kv = fma(w[3], rows[(sl >> 24) * kCols + lane], kv);
+          if (xt) {
+            const int64_t o = (int64_t)lid[8 * l] * W + cc;
+            kv = w[0] * xt_mix64(tb.xsec64, abs_stride, tb.n_abs, hd->chi_s, o, xt64[N - 1 - l], W, tb.n_P);
+          } else {
+            const uint32_t sl = __builtin_amdgcn_readfirstlane((uint32_t)sm.sl[k].x);
+            kv = w[0] * rows[(sl & 0xff) * kCols + lane];
+            kv = fma(w[1], rows[((sl >> 8) & 0xff) * kCols + lane], kv);
+            kv = fma(w[2], rows[((sl >> 16) & 0xff) * kCols + lane], kv);
+            kv = fma(w[3], rows[(sl >> 24) * kCols + lane], kv);
+          }
           kv = fma(w[4], R, kv);
           if (has_cia) {
             const uint32_t cl = __builtin_amdgcn_readfirstlane((uint32_t)sm.sl[k].y);
@@ -387,7 +425,17 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = 0.0;
         const int nc = min(max(nU - s0, 0), 8);
-        if (nc > 0) mix64(tb.xsec64, abs_stride, tb.n_abs, hd->chi_s, sm.sid + 8 * g, 0, nc, W, cc, v);
+        if (nc > 0 && L.xt) {
+          // exponential scheme: slot s0 + i is layer N - 1 - s0 - i (records by slot)
+          const double4* xr = reinterpret_cast<const double4*>(slab + L.off_xt64) + s0;
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i < nc)
+              v[i] = xt_mix64(tb.xsec64, abs_stride, tb.n_abs, hd->chi_s,
+                              (int64_t)__builtin_amdgcn_readfirstlane(sm.sid[8 * g + i]) * W + cc, xr[i], W, tb.n_P);
+        } else if (nc > 0) {
+          mix64(tb.xsec64, abs_stride, tb.n_abs, hd->chi_s, sm.sid + 8 * g, 0, nc, W, cc, v);
+        }
         const int vb = min(max(K - s0, 0), 8);
         if (vb > nc) mix64(tb.cia64, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, cc, v);
 #pragma unroll

@@ -29,6 +29,17 @@
 //     pieces: x0 y0 + x0 y1 + x1 y0) or < 3 (three pieces, six products) are
 //     accumulated in FP32.
 //
+// Exponential temperature scheme (Opacities section: sigma = a e^{-b/T}
+// through the two bracketing temperature nodes).  It is not linear in the
+// table values, so corners cannot be mixed once per model: each layer is
+// its own slot (P[j][l] = dl[j][l] 1e-4 rho_l; the top layer first, so that
+// the FP32 accumulator of a ray takes its smallest terms first, as with
+// the corner slots, which follow rising pressure) and its row is staged per
+// column as sum_i chi_i [(1 - w_P) g_i(iP) + w_P g_i(iP + 1)] with
+// g = sigma1 2^{u log2(sigma2/sigma1)}, u = w_T T2/T, from a table of
+// (sigma1, log2 ratio) pairs (one 8-byte load and one accurate 2^x - 1 per
+// absorber and pressure node); CIA slots stay linear.
+//
 // Depth.  Each accumulator element is a (ray, column) optical depth; a wave
 // adds the Rayleigh term, then (A_j/Rs^2)(1 - exp(-tau)) over the 32 rays of
 // a block per column (two lanes per column, one cross-lane exchange) into a
@@ -81,6 +92,7 @@ static_assert(kKC <= 64 * kWaves, "a thread copies one slot id");
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 template <int MODE, int RBW>
 struct Cfg {
@@ -101,7 +113,7 @@ struct Cfg {
 // Depth epilogues: fast transit, accurate transit, emission.
 enum { kEpiFast = 0, kEpiAcc = 1, kEpiEm = 2 };
 
-template <int MODE, int RBW, int EPI>
+template <int MODE, int RBW, int EPI, bool XT>
 struct Smem {
   // B operand of the staged slot chunk
   __attribute__((aligned(16))) uint32_t bfrag[Cfg<MODE, RBW>::bdw];
@@ -115,6 +127,7 @@ struct Smem {
   double emz[EPI == kEpiEm ? TRX_MAX_LAYERS_MFMA : 1];   // c2 (1/T_l - 1/T_*) in FP64
   float rpart[kWaves][kCols];       // Rayleigh sums by wave
   int32_t sid[kKC];                 // table rows of the chunk's slots
+  float4 xr[XT ? kKC : 1];          // exponential scheme: records of the chunk's layer slots
   float chi[TRX_MAX_ABSORBERS];
   float chis[kMaxSpecies];          // all species (Rayleigh)
   float ciaw[TRX_MAX_CIA];
@@ -248,6 +261,78 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
   }
 }
 
+// Exponential temperature scheme: s[i] += sum_t wt[t] sigma_t(layer of slot
+// i) for the slots i < i1 of a group of 8 (the others clamped into range,
+// their values unused), with
+//   sigma = (1 - w_P) g(iP) + w_P g(iP + 1),  g = sigma1 2^{u log2(sigma2/sigma1)}
+// at the two pressure nodes (Opacities section), from the pair table
+// (sigma1, log2 ratio) of the slot's row; a NaN ratio (a value that is not
+// positive) takes the linear form sigma1 + w_T (sigma2 - sigma1) from the
+// FP32 table.  rec[i] = {u, w_P, w_T, 0}.  Loads: 8 slots x 2 pressure
+// nodes x SA tables per batch, 8-byte buffer loads.
+template <int SA>
+__device__ inline void mix_group_xt(const float2* pairs, const float* tab, int64_t stride, int nt, const float* wt,
+                                    const int32_t* rows, const float4* rec, int i1, int W, int nP, int col,
+                                    float* s) {
+  const int rec8 = (int)(stride * 8 < 0x7fffffff ? stride * 8 : 0x7fffffff);
+  const int rec4 = (int)(stride * 4 < 0x7fffffff ? stride * 4 : 0x7fffffff);
+  int soff[8];
+  float u[8], wp[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = i >= i1 ? i1 - 1 : i;
+    soff[i] = __builtin_amdgcn_readfirstlane(rows[k]) * W * 8;
+    u[i] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(rec[k].x)));
+    wp[i] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(rec[k].y)));
+  }
+  const int rowP = W * 8;   // next pressure node
+  for (int t0 = 0; t0 < nt; t0 += SA) {
+    u32x2 v[SA][8][2];
+#pragma unroll
+    for (int tt = 0; tt < SA; ++tt) {
+      if (t0 + tt < nt) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(pairs + (int64_t)(t0 + tt) * stride), (short)0, rec8, kRsrcWord3);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          v[tt][i][0] = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * col, soff[i], 0);
+          v[tt][i][1] = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * col, soff[i] + rowP, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < SA; ++tt) {
+      if (t0 + tt < nt) {
+        const float c = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(wt[t0 + tt])));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          if (i < i1) {
+            float g[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+              const float s1 = __uint_as_float(v[tt][i][p].x);
+              const float d = __uint_as_float(v[tt][i][p].y);
+              if (d == d) {
+                // s1 + s1 (2^{u d} - 1): the accurate 2^x - 1 keeps the
+                // result to about one rounding of s1 where u d is small
+                g[p] = fmaf(-s1, one_minus_exp2(u[i] * d), s1);
+              } else {
+                const __amdgpu_buffer_rsrc_t r4 = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(tab + (int64_t)(t0 + tt) * stride), (short)0, rec4, kRsrcWord3);
+                const int row4 = soff[i] / 2 + p * W * 4 + nP * W * 4;   // (iT + 1, iP + p)
+                const float s2 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r4, 4 * col, row4, 0));
+                const float wT = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(rec[i].z)));
+                g[p] = fmaf(wT, s2 - s1, s1);
+              }
+            }
+            s[i] = fmaf(c, fmaf(wp[i], g[1] - g[0], g[0]), s[i]);
+          }
+        }
+      }
+    }
+  }
+}
+
 // Full corner groups (8 slots, all corners) in batches of SA absorber
 // tables: issue_corners loads tables t0 .. t0 + SA - 1 of the 8 slot rows,
 // mix_corners adds chi_t times them; a wave keeps two batches in flight.
@@ -285,8 +370,10 @@ __device__ inline void mix_corners(const float* wt, int nt, int t0, const float 
 // TAU: also write the optical depth of every ray and column to a.tau (a
 // separate instantiation: the stores cost the hot kernel registers).
 // EPI: the depth epilogue (kEpiFast, kEpiAcc, kEpiEm).
-template <int MODE, int RBW, bool TAU, int EPI>
-__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end, Smem<MODE, RBW, EPI>& sm) {
+// XT: the exponential temperature scheme (the absorber slots are layers).
+template <int MODE, int RBW, bool TAU, int EPI, bool XT>
+__device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end,
+                                        Smem<MODE, RBW, EPI, XT>& sm) {
   using C = Cfg<MODE, RBW>;
   constexpr int npc = C::npc, kAW = C::kAW, KB = C::KB;
   constexpr bool PF = C::PF;
@@ -347,6 +434,8 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       }
     }
     if (K <= kKC && tid < K) sm.sid[tid] = r;
+    if constexpr (XT)
+      if (K <= kKC && tid < nU) sm.xr[tid] = reinterpret_cast<const float4*>(slab + L.off_xt32)[tid];
     if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
     if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s32[tid];
     if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w32[tid];
@@ -428,6 +517,8 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       if (K > kKC) {
         __syncthreads();   // the previous chunk's products are done with bfrag
         if (tid < kKC && c0 + tid < K) sm.sid[tid] = sid[c0 + tid];
+        if constexpr (XT)
+          if (tid < kKC && c0 + tid < nU) sm.xr[tid] = reinterpret_cast<const float4*>(slab + L.off_xt32)[c0 + tid];
         __syncthreads();
       }
       u32x4 A[RBW][KB][kAW];
@@ -465,8 +556,8 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.f;
       };
-      // full corner groups: g < gf
-      const int gf = min(ng, max(nU - c0, 0) / 8);
+      // full corner groups: g < gf (none in the exponential scheme)
+      const int gf = XT ? 0 : min(ng, max(nU - c0, 0) / 8);
       const int na = tb.n_abs;
       const int nta = na > 0 ? na : 1;
       {
@@ -500,7 +591,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.f;
         const int nc = min(max(nU - s0, 0), 8);
-        if (nc > 0) mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g, 0, nc, W, voff, s);
+        if (nc > 0) {
+          if constexpr (XT)
+            mix_group_xt<first ? 2 : 1>(tb.xexp32, tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g,
+                                         sm.xr + 8 * g, nc, W, tb.n_P, cc, s);
+          else
+            mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g, 0, nc, W, voff, s);
+        }
         const int vb = min(max(K - s0, 0), 8);
         if (vb > nc) mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, voff, s);
         write_group(g, s);
@@ -693,13 +790,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 }
 
 // One workgroup per (model, span).
-template <int MODE, int RBW, bool TAU, int EPI>
+template <int MODE, int RBW, bool TAU, int EPI, bool XT>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
-  __shared__ Smem<MODE, RBW, EPI> sm;
+  __shared__ Smem<MODE, RBW, EPI, XT> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
   const int S = a.span_group;
-  process<MODE, RBW, TAU, EPI>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
+  process<MODE, RBW, TAU, EPI, XT>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
 }
 
 // Persistent: a fixed grid pops chunks of (span, model) items from kQueues
@@ -709,9 +806,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
 // one XCD share the table rows of few spans in its L2, and moves on to the
 // other queues when its own is drained.  Every workgroup leaves once all
 // queues are drained.
-template <int MODE, int RBW, int EPI>
+template <int MODE, int RBW, int EPI, bool XT>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_mfma_persist(FwdArgs a) {
-  __shared__ Smem<MODE, RBW, EPI> sm;
+  __shared__ Smem<MODE, RBW, EPI, XT> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int S = a.span_group;
   const int ngroups = ((a.tab.n_wn + kCols - 1) / kCols + S - 1) / S;
@@ -750,19 +847,19 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW, false, EPI>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
+        if (bm >= 0) process<MODE, RBW, false, EPI, XT>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
       }
       __syncthreads();
     }
   }
 }
 
-template <int MODE, int RBW, int EPI>
+template <int MODE, int RBW, int EPI, bool XT>
 int occupancy() {
   static int blocks = 0;
   if (!blocks) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, EPI>, 64 * kWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, EPI, XT>, 64 * kWaves, 0) !=
             hipSuccess || nb < 1)
       nb = 1;
     blocks = nb;
@@ -771,17 +868,17 @@ int occupancy() {
 }
 
 // The optical-depth output always takes the one-workgroup-per-item kernel.
-template <int MODE, int RBW, int EPI>
+template <int MODE, int RBW, int EPI, bool XT>
 void launch_rbw_epi(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
   if (a.persistent && !a.tau) {
-    const int grid = n_cu * occupancy<MODE, RBW, EPI>();
-    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, EPI>), dim3(grid), dim3(64 * kWaves), 0, s, a);
+    const int grid = n_cu * occupancy<MODE, RBW, EPI, XT>();
+    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, EPI, XT>), dim3(grid), dim3(64 * kWaves), 0, s, a);
   } else {
     dim3 grid(B_grid, ((a.tab.n_wn + kCols - 1) / kCols + a.span_group - 1) / a.span_group);
     if (a.tau)
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true, kEpiFast>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true, kEpiFast, XT>), grid, dim3(64 * kWaves), 0, s, a);
     else
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false, EPI>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false, EPI, XT>), grid, dim3(64 * kWaves), 0, s, a);
   }
 }
 
@@ -789,9 +886,17 @@ void launch_rbw_epi(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
 // writes tau, not the depth's rounding.
 template <int MODE, int RBW>
 void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
-  if (a.L.em) launch_rbw_epi<MODE, RBW, kEpiEm>(a, B_grid, n_cu, s);
-  else if (a.accurate && !a.tau) launch_rbw_epi<MODE, RBW, kEpiAcc>(a, B_grid, n_cu, s);
-  else launch_rbw_epi<MODE, RBW, kEpiFast>(a, B_grid, n_cu, s);
+  // the exponential scheme has no gradient, so no accurate epilogue
+  if (a.L.xt) {
+    if (a.L.em) launch_rbw_epi<MODE, RBW, kEpiEm, true>(a, B_grid, n_cu, s);
+    else launch_rbw_epi<MODE, RBW, kEpiFast, true>(a, B_grid, n_cu, s);
+  } else if (a.L.em) {
+    launch_rbw_epi<MODE, RBW, kEpiEm, false>(a, B_grid, n_cu, s);
+  } else if (a.accurate && !a.tau) {
+    launch_rbw_epi<MODE, RBW, kEpiAcc, false>(a, B_grid, n_cu, s);
+  } else {
+    launch_rbw_epi<MODE, RBW, kEpiFast, false>(a, B_grid, n_cu, s);
+  }
 }
 
 template <int MODE>

@@ -23,6 +23,10 @@
 //      below the grid give zero cross-section (Opacities section).
 //      The model's opacity slots: its distinct corners (ordered by pressure
 //      node, then temperature node) and its distinct CIA temperature nodes.
+//      Exponential temperature scheme: the layers are the absorber slots
+//      (top layer first), each with weight 1e-4 rho, and each slot keeps
+//      its layer's {u, w_P, w_T} with u = (1/T - 1/T1)/(1/T2 - 1/T1) =
+//      w_T T2/T.
 //
 // The matrix-core modes then take, per model, the products of the chord
 // lengths and the opacity weights (k_pmat below).
@@ -297,11 +301,22 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       double w[8];
       if (Tb && Pb) {
         w[0] = w[1] = w[2] = w[3] = 0.0;
+      } else if (L.xt) {
+        // exponential scheme: the layer is its own slot with weight 1e-4 rho
+        w[0] = f1;
+        w[1] = w[2] = w[3] = 0.0;
       } else {
         w[0] = f1 * (1.0 - wT) * (1.0 - wP);
         w[1] = f1 * wT * (1.0 - wP);
         w[2] = f1 * (1.0 - wT) * wP;
         w[3] = f1 * wT * wP;
+      }
+      if (L.xt) {
+        // sigma1 (sigma2/sigma1)^u, u = (1/T - 1/T1)/(1/T2 - 1/T1) = w_T T2/T
+        // (0 and 1 under the clamps, where T is taken at the edge node)
+        const double u = c0 ? wT : wT * (tb.T[iT + 1] / T);
+        reinterpret_cast<double4*>(slab + L.off_xt64)[N - 1 - l] = make_double4(u, wP, wT, 0.0);
+        reinterpret_cast<float4*>(slab + L.off_xt32)[N - 1 - l] = make_float4((float)u, (float)wP, (float)wT, 0.f);
       }
       w[4] = tb.has_rayleigh ? f1 : 0.0;
       if (tb.n_cia > 0) {
@@ -363,6 +378,10 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         reinterpret_cast<double4*>(slab + L.off_em64)[l] = make_double4(0.0, 0.0, 0.0, 0.0);
         reinterpret_cast<float4*>(slab + L.off_em32)[l] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
+      if (L.xt) {
+        reinterpret_cast<double4*>(slab + L.off_xt64)[l] = make_double4(0.0, 0.0, 0.0, 0.0);
+        reinterpret_cast<float4*>(slab + L.off_xt32)[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
       if (L.off_aw) reinterpret_cast<float2*>(slab + L.off_aw)[l] = make_float2(0.f, 0.f);
       if (L.off_pr64) reinterpret_cast<double*>(slab + L.off_pr64)[l] = 0.0;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
@@ -391,8 +410,13 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   // distinct corners of the whole model (bitmaps over the keys
   // iP n_T + iT, slots = rank of the key among the set bits, so that the
   // slots follow the pressure nodes and a run of slots is used by a run of
-  // layers) and each layer's slots in them
+  // layers) and each layer's slots in them; in the exponential scheme the
+  // absorber slots are the layers, top first (slot q: layer N-1-q, its row
+  // id the corner (iT, iP) it interpolates from), so that a ray's optical
+  // depth is accumulated from its smallest terms up, as the corner slots
+  // are (rising pressure nodes)
   {
+    const bool xt = L.xt != 0;
     __shared__ int s_nu;
     __shared__ uint32_t s_bm[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
     __shared__ uint32_t s_pre[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
@@ -415,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     for (int l = tid; l < N; l += kThreads) {
       int cs[4];
       corner_keys(lid[8 * l], cs);
-      for (int q = 0; q < 4; ++q) atomicOr(&s_bm[cs[q] >> 5], 1u << (cs[q] & 31));
+      for (int q = 0; q < 4 && !xt; ++q) atomicOr(&s_bm[cs[q] >> 5], 1u << (cs[q] & 31));
       if (tb.n_cia > 0) {
         const int t0 = lid[8 * l + 1];
         atomicOr(&s_cbm[t0 >> 5], 1u << (t0 & 31));
@@ -429,9 +453,9 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       uint32_t cacc = 0;
       for (int w = 0; w < ncwords; ++w) { s_cpre[w] = cacc; cacc += __popc(s_cbm[w]); }
       MList* ml = reinterpret_cast<MList*>(slab + L.off_mlist);
-      ml->nU = (int)acc;
+      ml->nU = xt ? N : (int)acc;
       ml->nV = tb.n_cia > 0 ? (int)cacc : 0;
-      s_nu = (int)acc;
+      s_nu = xt ? N : (int)acc;
     }
     __syncthreads();
     MList* ml = reinterpret_cast<MList*>(slab + L.off_mlist);
@@ -440,7 +464,11 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     // matrix-core modes
     int32_t* sid = L.off_sid ? reinterpret_cast<int32_t*>(slab + L.off_sid) : nullptr;
     const int nu = s_nu;
-    for (int w = tid; w < nwords; w += kThreads) {
+    for (int q = tid; q < (xt ? N : 0); q += kThreads) {
+      if (q < kMListU) ml->ids[q] = lid[8 * (N - 1 - q)];
+      if (sid) sid[q] = lid[8 * (N - 1 - q)];
+    }
+    for (int w = tid; w < (xt ? 0 : nwords); w += kThreads) {
       uint32_t bits = s_bm[w];
       int slot = (int)s_pre[w];
       while (bits) {
@@ -477,11 +505,18 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       int cs[4];
       corner_keys(lid[8 * l], cs);
       uint32_t slots = 0;
-      for (int q = 0; q < 4; ++q) slots |= rank(s_bm, s_pre, cs[q]) << (8 * q);
+      for (int q = 0; q < 4 && !xt; ++q) slots |= rank(s_bm, s_pre, cs[q]) << (8 * q);
       lid[8 * l + 2] = (int32_t)slots;
-      // unclamped 16-bit slots of the four corners
-      lid[8 * l + 6] = (int32_t)(rank_full(s_bm, s_pre, cs[0]) | (rank_full(s_bm, s_pre, cs[1]) << 16));
-      lid[8 * l + 7] = (int32_t)(rank_full(s_bm, s_pre, cs[2]) | (rank_full(s_bm, s_pre, cs[3]) << 16));
+      // unclamped 16-bit slots of the four corners (the exponential scheme:
+      // the layer's own slot, the other three weights being zero)
+      if (xt) {
+        const int q = N - 1 - l;
+        lid[8 * l + 6] = (int32_t)(q | (q << 16));
+        lid[8 * l + 7] = (int32_t)(q | (q << 16));
+      } else {
+        lid[8 * l + 6] = (int32_t)(rank_full(s_bm, s_pre, cs[0]) | (rank_full(s_bm, s_pre, cs[1]) << 16));
+        lid[8 * l + 7] = (int32_t)(rank_full(s_bm, s_pre, cs[2]) | (rank_full(s_bm, s_pre, cs[3]) << 16));
+      }
       uint32_t cslots = 0;
       if (tb.n_cia > 0) {
         const int t0 = lid[8 * l + 1];

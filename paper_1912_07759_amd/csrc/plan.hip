@@ -216,6 +216,8 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   if (grad && emission) return set_err(c, TRX_E_UNSUPPORTED, "the gradient of the emission model is not built");
   if (emission && precision == TRX_FP64 && N_max > TRX_MAX_LAYERS_MFMA)
     return set_err(c, TRX_E_UNSUPPORTED, "emission takes at most %d layers", TRX_MAX_LAYERS_MFMA);
+  if (grad && t->dev.t_exp)
+    return set_err(c, TRX_E_UNSUPPORTED, "the gradient of the exponential temperature scheme is not built");
   if (grad && !bins) return set_err(c, TRX_E_INVALID_ARG, "gradient plans need channels (bins)");
   if (grad && N_max > TRX_MAX_LAYERS_MFMA)
     return set_err(c, TRX_E_UNSUPPORTED, "the gradient supports at most %d layers", TRX_MAX_LAYERS_MFMA);

@@ -91,6 +91,11 @@ struct DevTables {
   const float* cia32;      // same layout in FP32, times kCiaScale32
   const double* ray64;     // [n_abs+2][n_wn] (zeros when absent)
   const float* ray32;
+  // exponential temperature scheme (t_exp = 1): per absorber [n_T][n_P][n_wn]
+  // pairs (sigma, log2(sigma at the next T node / sigma)) in FP32, the ratio
+  // NaN where the scheme falls back to linear
+  int32_t t_exp;
+  const float2* xexp32;
   double mass[kMaxSpecies];          // amu: absorbers, H2, He
   int32_t cia_pair[TRX_MAX_CIA][2];
 };
@@ -110,6 +115,14 @@ struct Layout {
   // shell l}, FP32 (float4) and FP64 (double4); c2 = 100 h c / k_B (K cm)
   int32_t em;
   int64_t off_em32, off_em64;
+  // exponential temperature scheme (tables with t_exp): the absorber slots
+  // are the layers themselves, top first (slot q = layer N-1-q, its mixed
+  // cross-sections formed per column by the forward kernels), and per slot
+  // its layer's record {u, w_P, w_T, 0}: the exponent of the ratio of the
+  // two T nodes (u = w_T T2 / T), the log10 P weight and the linear T
+  // weight of the fallback, FP32 (float4) and FP64 (double4)
+  int32_t xt;
+  int64_t off_xt32, off_xt64;
   int32_t slot64;          // FP64 mode in the slot form (models of at most TRX_MAX_LAYERS_MFMA layers)
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise); the gradient takes models of at
@@ -125,10 +138,11 @@ struct Layout {
 constexpr int kKG = 128;
 
 // Opacity slots of a model in the matrix-core modes: its distinct
-// cross-section corners (at most 4 per layer, at most the grid's n_T n_P)
-// and its distinct CIA temperature nodes (at most 2 per layer).
+// cross-section corners (at most 4 per layer, at most the grid's n_T n_P;
+// one per layer in the exponential scheme) and its distinct CIA temperature
+// nodes (at most 2 per layer).
 inline int slot_capacity(const DevTables& t, int NP) {
-  const int corners = std::min(4 * NP, t.n_T * t.n_P);
+  const int corners = t.t_exp ? NP : std::min(4 * NP, t.n_T * t.n_P);
   const int nodes = t.n_cia > 0 ? std::min(2 * NP, t.n_Tcia) : 0;
   return corners + nodes;
 }
@@ -171,6 +185,11 @@ inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& 
     L.em = 1;
     L.off_em32 = take(16LL * L.NP);
     L.off_em64 = take(32LL * L.NP);
+  }
+  if (t.t_exp) {
+    L.xt = 1;
+    L.off_xt32 = take(16LL * L.NP);
+    L.off_xt64 = take(32LL * L.NP);
   }
   if (precision == TRX_FP64 && L.NP > TRX_MAX_LAYERS_MFMA) {
     L.dl_bytes = 8LL * L.NP * L.NP;  // dense transposed dlT[k][j]

@@ -52,7 +52,7 @@ class TablesDesc(ctypes.Structure):
                 ("n_P", _I), ("log10P_Pa", _P), ("n_abs", _I), ("xsec_cm2", _P),
                 ("abs_mass_amu", _P), ("h2_mass_amu", _D), ("he_mass_amu", _D),
                 ("n_cia", _I), ("n_Tcia", _I), ("Tcia_K", _P), ("cia_cm5", _P),
-                ("cia_pair", _P), ("rayleigh_cm2", _P)]
+                ("cia_pair", _P), ("rayleigh_cm2", _P), ("t_interp", _I)]
 
 
 class BatchC(ctypes.Structure):
@@ -138,11 +138,15 @@ class Context:
             pass
 
 
+T_INTERP = {"linear": 0, "exp": 1}
+
+
 class Tables:
-    """Device copy of opacity tables (host float64 arrays in)."""
+    """Device copy of opacity tables (host float64 arrays in).  t_interp:
+    "linear" or "exp", the cross-sections' scheme in temperature."""
 
     def __init__(self, ctx, wn, T_grid, log10P_grid, xsec, abs_mass, h2_mass, he_mass,
-                 Tcia_grid=None, cia=None, cia_pair=None, rayleigh=None):
+                 Tcia_grid=None, cia=None, cia_pair=None, rayleigh=None, t_interp="linear"):
         self.ctx = ctx
         c = lambda a, dt=np.float64: None if a is None else np.ascontiguousarray(a, dtype=dt)
         self._keep = [c(wn), c(T_grid), c(log10P_grid), c(xsec), c(abs_mass),
@@ -154,20 +158,21 @@ class Tables:
                        float(h2_mass), float(he_mass), n_cia,
                        0 if Tcia_grid is None else len(Tcia_grid), _hptr(Tcia_grid),
                        _hptr(cia) if n_cia else None, _hptr(cia_pair) if n_cia else None,
-                       _hptr(rayleigh))
+                       _hptr(rayleigh), T_INTERP[t_interp])
         h = ctypes.c_void_p()
         ctx.check(lib().trx_tables_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
         self.h = h
         self.n_wn = len(wn)
         self.n_abs = int(xsec.shape[0])
+        self.t_interp = t_interp
         self._keep = None
 
     @classmethod
-    def from_synth(cls, ctx, t):
+    def from_synth(cls, ctx, t, t_interp="linear"):
         return cls(ctx, t.wn, t.T_grid, t.log10P_grid, t.xsec, t.abs_mass, t.h2_mass,
                    t.he_mass, t.Tcia_grid if t.cia.shape[0] else None,
                    t.cia if t.cia.shape[0] else None,
-                   t.cia_pair if t.cia.shape[0] else None, t.rayleigh)
+                   t.cia_pair if t.cia.shape[0] else None, t.rayleigh, t_interp)
 
     def close(self):
         if self.h:

@@ -59,9 +59,9 @@ def _rel(g, r):
     return float(np.max(np.abs(g - r) / np.abs(r)))
 
 
-def _check(ctx, tables, batch, ch, mode, n_mu, T_star, max_layers=None):
+def _check(ctx, tables, batch, ch, mode, n_mu, T_star, max_layers=None, t_interp="linear"):
     from paper_1912_07759_amd import trx
-    Tt = trx.Tables.from_synth(ctx, tables)
+    Tt = trx.Tables.from_synth(ctx, tables, t_interp)
     bins = trx.Bins(ctx, Tt, ch.lo, ch.hi)
     try:
         db = trx.DeviceBatch.from_synth(batch, max_layers=max_layers)
@@ -75,8 +75,8 @@ def _check(ctx, tables, batch, ch, mode, n_mu, T_star, max_layers=None):
     Ts = np.broadcast_to(np.asarray(T_star, dtype=np.float64), (batch.B,))
     worst = 0.0
     for b in range(batch.B):
-        ref = oracle.emission_model(batch.model(b), tables, ch, n_mu=n_mu, T_star=float(Ts[b]),
-                                    keep=True)
+        ref = oracle.emission_model(dict(batch.model(b), t_interp=t_interp), tables, ch, n_mu=n_mu,
+                                    T_star=float(Ts[b]), keep=True)
         lo, hi = int(batch.wn_lo[b]), int(batch.wn_hi[b])
         g = nat[b, lo:hi]
         assert np.all(np.isfinite(g)), "non-finite emission output"
