@@ -37,8 +37,8 @@
 // the corner slots, which follow rising pressure) and its row is staged per
 // column as sum_i chi_i [(1 - w_P) g_i(iP) + w_P g_i(iP + 1)] with
 // g = sigma1 2^{u log2(sigma2/sigma1)}, u = w_T T2/T, from a table of
-// (sigma1, log2 ratio) pairs (one 8-byte load and one accurate 2^x - 1 per
-// absorber and pressure node); CIA slots stay linear.
+// (sigma1, log2 ratio) pairs (one 8-byte load and one exp2 per absorber and
+// pressure node); CIA slots stay linear.
 //
 // Depth.  Each accumulator element is a (ray, column) optical depth; a wave
 // adds the Rayleigh term, then (A_j/Rs^2)(1 - exp(-tau)) over the 32 rays of
@@ -268,14 +268,17 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
 // at the two pressure nodes (Opacities section), from the pair table
 // (sigma1, log2 ratio) of the slot's row; a NaN ratio (a value that is not
 // positive) takes the linear form sigma1 + w_T (sigma2 - sigma1) from the
-// FP32 table.  rec[i] = {u, w_P, w_T, 0}.  Loads: 8 slots x 2 pressure
-// nodes x SA tables per batch, 8-byte buffer loads.
+// FP32 table.  rec[i] = {u, w_P, w_T, 0}.  Loads: 8-byte buffer loads of
+// the two pressure nodes of each slot for SA tables per batch; consecutive
+// slots (layers) often share their row, or step one pressure node down, and
+// then reuse the previous slot's pairs (uniform branches on the row offsets).
 template <int SA>
 __device__ inline void mix_group_xt(const float2* pairs, const float* tab, int64_t stride, int nt, const float* wt,
                                     const int32_t* rows, const float4* rec, int i1, int W, int nP, int col,
                                     float* s) {
   const int rec8 = (int)(stride * 8 < 0x7fffffff ? stride * 8 : 0x7fffffff);
   const int rec4 = (int)(stride * 4 < 0x7fffffff ? stride * 4 : 0x7fffffff);
+  const int rowP = W * 8;   // next pressure node
   int soff[8];
   float u[8], wp[8];
 #pragma unroll
@@ -285,7 +288,6 @@ __device__ inline void mix_group_xt(const float2* pairs, const float* tab, int64
     u[i] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(rec[k].x)));
     wp[i] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(rec[k].y)));
   }
-  const int rowP = W * 8;   // next pressure node
   for (int t0 = 0; t0 < nt; t0 += SA) {
     u32x2 v[SA][8][2];
 #pragma unroll
@@ -295,8 +297,17 @@ __device__ inline void mix_group_xt(const float2* pairs, const float* tab, int64
             (void*)(pairs + (int64_t)(t0 + tt) * stride), (short)0, rec8, kRsrcWord3);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          v[tt][i][0] = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * col, soff[i], 0);
-          v[tt][i][1] = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * col, soff[i] + rowP, 0);
+          const int dr = i > 0 ? soff[i] - soff[i - 1] : -1;
+          if (dr == 0) {
+            v[tt][i][0] = v[tt][i - 1][0];
+            v[tt][i][1] = v[tt][i - 1][1];
+          } else if (dr == rowP) {
+            v[tt][i][0] = v[tt][i - 1][1];
+            v[tt][i][1] = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * col, soff[i] + rowP, 0);
+          } else {
+            v[tt][i][0] = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * col, soff[i], 0);
+            v[tt][i][1] = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * col, soff[i] + rowP, 0);
+          }
         }
       }
     }
@@ -313,9 +324,7 @@ __device__ inline void mix_group_xt(const float2* pairs, const float* tab, int64
               const float s1 = __uint_as_float(v[tt][i][p].x);
               const float d = __uint_as_float(v[tt][i][p].y);
               if (d == d) {
-                // s1 + s1 (2^{u d} - 1): the accurate 2^x - 1 keeps the
-                // result to about one rounding of s1 where u d is small
-                g[p] = fmaf(-s1, one_minus_exp2(u[i] * d), s1);
+                g[p] = s1 * __builtin_amdgcn_exp2f(u[i] * d);
               } else {
                 const __amdgpu_buffer_rsrc_t r4 = __builtin_amdgcn_make_buffer_rsrc(
                     (void*)(tab + (int64_t)(t0 + tt) * stride), (short)0, rec4, kRsrcWord3);
