@@ -19,7 +19,8 @@ from .forward import (  # noqa: F401
     pressure_grid, chemistry, altitude, shell_boundaries, chord_lengths,
     annulus_weights, bracket, interp_xsec, interp_cia, number_density,
     opacity, optical_depth, transit_depth, native_bin_edges, bin_weights,
-    bin_spectrum, forward_model, forward_batch, chi2,
+    bin_spectrum, forward_model, forward_batch, chi2, two_layer_vmr, chemistry_profile,
+    model_chemistry,
 )
 from .adjoint import chi2_and_grad, chi2_grad_batch  # noqa: F401
 from .emission import (emission_model, emergent_intensity, gauss_legendre_mu,  # noqa: F401

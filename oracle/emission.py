@@ -46,7 +46,7 @@ optical depth converges to the hydrostatic column chi sigma Delta P /(mu g).
 
 import numpy as np
 
-from .forward import (bin_spectrum, bin_weights, chemistry, altitude, cloud_opacity,
+from .forward import (bin_spectrum, bin_weights, altitude, cloud_opacity, model_chemistry,
                       opacity, pressure_grid, shell_boundaries)
 
 H_PLANCK = 6.62607015e-34   # J s (exact SI)
@@ -101,8 +101,7 @@ def emission_model(m, tables, channels=None, n_mu=4, T_star=5800.0, keep=False):
     N = len(T)
     lo, hi = m["wn_lo"], m["wn_hi"]
     _, P = pressure_grid(m["p_bot"], m["p_top"], N)
-    chi, chi_h2, chi_he, mu_kg, valid = chemistry(m["log10_vmr"], m["he_h2"], tables.abs_mass,
-                                                  tables.h2_mass, tables.he_mass, m["amu"])
+    chi, chi_h2, chi_he, mu_kg, valid = model_chemistry(m, tables, P)
     z = altitude(T, P, mu_kg, m["Rp"], m["GM"], m["k_B"], m["gravity"])
     kappa = opacity(T, P, chi, chi_h2, chi_he, tables, m["k_B"], lo, hi,
                     t_interp=m.get("t_interp", "linear"))

@@ -51,6 +51,12 @@ design notes):
       undefined) that (P node, wavenumber) falls back to the linear scheme.
       Out-of-range T clamps to the edge node as in A3 (the scheme then
       returns the node value).
+  A26 the two-layer mixing profile (Chemistry subsection, its surface and
+      top mixing ratios): absorber i has its surface value at the layers
+      whose centre pressure is at or above a switch pressure p_i and its top
+      value above (lower pressure), a step with no smoothing; the fill gases
+      and the mean molecular weight follow per layer, and the altitude step
+      uses the lower layer's mu as A5 uses its T.
   A24 the flat-opacity cloud deck (equation clouds) is sigma rho on the
       layers whose centre pressure lies between the two deck pressures
       (bounds included, either order); sigma = +inf is the fully opaque
@@ -105,22 +111,57 @@ def chemistry(log10_vmr, he_h2, abs_mass, h2_mass, he_mass, amu):
     return chi, chi_h2, chi_he, mu_amu * amu, valid
 
 
+def two_layer_vmr(log10_surface, log10_top, p_switch, P):
+    """Reading A26: chi[l, i] = 10**log10_surface[i] at the layers with
+    P_l >= p_switch[i], 10**log10_top[i] above."""
+    deep = np.asarray(P)[:, None] >= np.asarray(p_switch, dtype=np.float64)[None, :]
+    return np.where(deep, 10.0 ** np.asarray(log10_surface)[None, :],
+                    10.0 ** np.asarray(log10_top)[None, :])
+
+
+def chemistry_profile(chi, he_h2, abs_mass, h2_mass, he_mass, amu):
+    """The chemistry of ``chemistry`` layer by layer for absorber profiles
+    chi[l, i]: per-layer fill gases and mean molecular weight.  Returns
+    (chi, chi_h2[N], chi_he[N], mu_kg[N], valid), valid when every layer's
+    absorbers sum below 1."""
+    S = np.sum(chi, axis=1)
+    chi_h2 = (1.0 - S) / (1.0 + he_h2)
+    chi_he = he_h2 * chi_h2
+    mu_amu = chi @ np.asarray(abs_mass, dtype=np.float64) + chi_h2 * h2_mass + chi_he * he_mass
+    valid = bool(np.all(np.real(S) < 1.0))
+    return chi, chi_h2, chi_he, mu_amu * amu, valid
+
+
+def model_chemistry(m, tables, P):
+    """The chemistry of model dict m at layer centres P: constant profiles
+    (log10_vmr) or, when m has log10_vmr_top and vmr_switch (Pa), the
+    two-layer profiles of reading A26."""
+    if m.get("log10_vmr_top") is not None:
+        chi = two_layer_vmr(m["log10_vmr"], m["log10_vmr_top"], m["vmr_switch"], P)
+        return chemistry_profile(chi, m["he_h2"], tables.abs_mass, tables.h2_mass, tables.he_mass,
+                                 m["amu"])
+    return chemistry(m["log10_vmr"], m["he_h2"], tables.abs_mass, tables.h2_mass, tables.he_mass,
+                     m["amu"])
+
+
 def altitude(T, P, mu_kg, Rp, GM, k_B, gravity=0):
     """Forward Models section, altitude equation.
 
     z_0 = 0 (bottom of the atmosphere, where Rp is defined); for l >= 1,
     z_l = z_{l-1} - H_{l-1} ln(P_l / P_{l-1}) with H = k_B T / (mu g).
     Reading A4: g_{l-1} = GM / (Rp + z_{l-1})^2 (gravity=0) or GM/Rp^2.
-    Reading A5: the lower layer's H is used for each step.
+    Reading A5: the lower layer's H is used for each step (mu_kg a scalar
+    or per layer, reading A26).
     """
     N = len(T)
     z = np.zeros(N, dtype=np.result_type(T, Rp, mu_kg, 0.0))
+    mu = np.broadcast_to(np.asarray(mu_kg), (N,))
     for l in range(1, N):
         if gravity == 0:
             g = GM / (Rp + z[l - 1]) ** 2
         else:
             g = GM / Rp ** 2
-        H = k_B * T[l - 1] / (mu_kg * g)
+        H = k_B * T[l - 1] / (mu[l - 1] * g)
         z[l] = z[l - 1] - H * np.log(P[l] / P[l - 1])
     return z
 
@@ -254,14 +295,23 @@ def opacity(T, P, chi_abs, chi_h2, chi_he, tables, k_B, lo, hi,
 
         kappa = 1e-4 rho [sum_i chi_i sigma_i(T,P) + sum_s chi_s sigma_R,s]
               + 1e-10 rho^2 sum_pairs chi_a chi_b sigma_ab(T).
+
+    chi_abs is [n_abs] (constant profiles) or [N, n_abs] with chi_h2 and
+    chi_he per layer (reading A26).
     """
     N = len(T)
     n = number_density(P, T, k_B)
-    chi_s = list(chi_abs) + [chi_h2, chi_he]
+    per_layer = np.ndim(chi_abs) == 2
     W = hi - lo
     kappa = np.zeros((N, W), dtype=np.result_type(T, chi_abs, 0.0))
     lp = np.log10(P)
+    chi_all = chi_abs
     for l in range(N):
+        if per_layer:
+            chi_abs = chi_all[l]
+            chi_s = list(chi_abs) + [chi_h2[l], chi_he[l]]
+        else:
+            chi_s = list(chi_abs) + [chi_h2, chi_he]
         acc = np.zeros(W, dtype=kappa.dtype)
         for i in range(tables.n_abs):
             acc = acc + chi_abs[i] * interp_xsec(tables.xsec[i][:, :, lo:hi],
@@ -365,7 +415,8 @@ def forward_model(m, tables, channels=None, p_interp="log", zero_rule="both",
     log10_vmr, Rp, Rs, GM, wn_lo, wn_hi, he_h2, k_B, amu, gravity, and
     optionally a cloud deck: cloud_sigma (m^2, +inf for opaque; absent or 0
     for none), cloud_p_top, cloud_p_bottom (Pa); optionally t_interp
-    ("linear", the default, or "exp": reading A25).
+    ("linear", the default, or "exp": reading A25); optionally two-layer
+    profiles: log10_vmr_top and vmr_switch (Pa) per absorber (reading A26).
 
     Returns a dict with the native depth over the window (``depth``), the
     binned depth (``binned``, if channels are given) and ``valid``.  With
@@ -375,9 +426,7 @@ def forward_model(m, tables, channels=None, p_interp="log", zero_rule="both",
     N = len(T)
     lo, hi = m["wn_lo"], m["wn_hi"]
     _, P = pressure_grid(m["p_bot"], m["p_top"], N)
-    chi, chi_h2, chi_he, mu, valid = chemistry(m["log10_vmr"], m["he_h2"],
-                                               tables.abs_mass, tables.h2_mass,
-                                               tables.he_mass, m["amu"])
+    chi, chi_h2, chi_he, mu, valid = model_chemistry(m, tables, P)
     z = altitude(T, P, mu, m["Rp"], m["GM"], m["k_B"], m["gravity"])
     dl = chord_lengths(z, m["Rp"])
     A = annulus_weights(z, m["Rp"])
