@@ -89,10 +89,14 @@ enum {
                                   p_bot <= p_top, non-finite input */
   TRX_MODEL_BAD_WINDOW = 4,    /* window empty or outside the grid */
   TRX_MODEL_NONFINITE = 8,     /* a non-finite value appeared in the outputs */
-  TRX_MODEL_GRAD_UNSUPPORTED = 16 /* trx_chi2_grad: the model has more distinct
+  TRX_MODEL_GRAD_UNSUPPORTED = 16, /* trx_chi2_grad: the model has more distinct
                                      table corners and CIA nodes than the
                                      gradient kernel stages (128); its gradient
                                      outputs are NaN */
+  TRX_MODEL_UNSUPPORTED = 32   /* two-layer profiles that cut the model's layers
+                                  into more than TRX_MAX_REGIMES runs of one
+                                  chemistry, or more than 1024 opacity slots
+                                  in all; its outputs are NaN */
 };
 
 /* Limits of the library. */
@@ -103,6 +107,7 @@ enum {
 #define TRX_MAX_TGRID 128
 #define TRX_MAX_PGRID 128
 #define TRX_MAX_MU 16           /* Gauss-Legendre angles of the emission flux */
+#define TRX_MAX_REGIMES 4       /* runs of one chemistry per model (two-layer profiles) */
 
 /* ---- context ---------------------------------------------------------- */
 
@@ -220,6 +225,22 @@ typedef struct {
   const double* cloud_sigma_m2;   /* [B] */
   const double* cloud_p_top_Pa;   /* [B] */
   const double* cloud_p_bottom_Pa;/* [B] */
+  /* Optional two-layer mixing profiles (Chemistry subsection: the two-layer
+   * profile with a surface and a top mixing ratio).  Absorber i of model b
+   * has log10_vmr[b][i] at the layers whose centre pressure is at or above
+   * vmr_switch_Pa[b][i] and log10_vmr_top[b][i] at the layers above (lower
+   * pressure): a step, no smoothing.  The fill gases and the mean molecular
+   * weight follow layer by layer (each altitude step takes the lower
+   * layer's).  A constant gas has equal values (or a switch pressure
+   * outside the model).  Both NULL: constant profiles; else both set.  A
+   * switch pressure that is not finite and positive, a top value that is
+   * not finite, or a layer whose absorbers sum to 1 or more flags
+   * TRX_MODEL_BAD_CHEMISTRY; switches that cut a model's layers into more
+   * than TRX_MAX_REGIMES runs flag TRX_MODEL_UNSUPPORTED.  Not
+   * differentiated: trx_chi2_grad returns TRX_E_UNSUPPORTED; TRX_FP64 takes
+   * at most TRX_MAX_LAYERS_MFMA layers with them. */
+  const double* log10_vmr_top;    /* [B][n_abs] */
+  const double* vmr_switch_Pa;    /* [B][n_abs] */
 } trx_batch;
 
 /* Forward model for every model of the batch.
@@ -311,7 +332,8 @@ trx_status trx_forward_noalloc(trx_ctx* ctx, const trx_tables* t, const trx_batc
  * Derivatives at table nodes and under clamps are one-sided (the lower
  * bracket's slope; zero under a clamp).  The binned spectrum must cover
  * every channel in each model's window, else that model's chi2 is NaN.
- * Tables with t_interp = TRX_T_EXP: TRX_E_UNSUPPORTED. */
+ * Tables with t_interp = TRX_T_EXP, or a batch with two-layer profiles:
+ * TRX_E_UNSUPPORTED. */
 trx_status trx_chi2_grad(trx_ctx* ctx, const trx_tables* t, const trx_batch* batch,
                          const trx_bins* bins, trx_precision precision,
                          const double* obs, const double* sigma, int32_t recompute,
@@ -325,8 +347,11 @@ enum {
   TRX_PLAN_GRAPH = 1,       /* replay the launch sequence from a HIP graph */
   TRX_PLAN_PERSISTENT = 2,  /* allow the persistent work-queue kernel */
   TRX_PLAN_GRAD = 4,        /* plan computes chi^2 and its gradient */
-  TRX_PLAN_EMISSION = 8     /* plan computes the emission spectrum (trx_emission);
+  TRX_PLAN_EMISSION = 8,    /* plan computes the emission spectrum (trx_emission);
                                the native and binned outputs hold F_p/F_s */
+  TRX_PLAN_TWO_LAYER = 16   /* plan accepts batches with two-layer profiles (its
+                               workspace holds the per-run chemistry); without
+                               it such a batch is refused at launch */
 };
 
 /* A plan owns the workspace for up to B_max models of at most N_max layers
@@ -336,7 +361,8 @@ enum {
  * over live points (Parallel/MPI discussion of the Benchmarks section) by
  * one launch over the whole live-point set.  bins may be NULL (then no
  * binned output).  Creating a plan allocates; launching one does not.
- * TRX_PLAN_GRAD with TRX_T_EXP tables: TRX_E_UNSUPPORTED. */
+ * TRX_PLAN_GRAD with TRX_T_EXP tables or with TRX_PLAN_TWO_LAYER:
+ * TRX_E_UNSUPPORTED. */
 trx_status trx_plan_create(trx_ctx* ctx, const trx_tables* t, const trx_bins* bins,
                            int32_t B_max, int32_t N_max, trx_precision precision,
                            int32_t flags, trx_plan** out);
@@ -348,7 +374,10 @@ trx_status trx_plan_set_star(trx_plan* p, const double* T_star_K, int32_t n_mu);
 /* Fill `out` with device input buffers owned by the plan (B = B_max,
  * max_layers = N_max, layer_off sized for B_max * N_max layers; default
  * constants He/H2 0.17, CODATA k_B and atomic mass unit, gravity 0; cloud
- * deck arrays zeroed at creation, i.e. no decks).  Their use is optional: any batch with B <= B_max and max_layers <= N_max can be
+ * deck arrays zeroed at creation, i.e. no decks; for TRX_PLAN_TWO_LAYER
+ * plans the two-layer arrays, their switch pressures at 1e-300 Pa at
+ * creation, i.e. surface values everywhere, otherwise NULL).  Their use is
+ * optional: any batch with B <= B_max and max_layers <= N_max can be
  * launched. */
 trx_status trx_plan_batch(trx_plan* p, trx_batch* out);
 /* Run the plan on `batch` (batch->B models).  Outputs as in trx_forward and

@@ -433,6 +433,11 @@ trx_status trx::check_batch(trx_ctx* c, const trx_tables* t, const trx_batch* bt
   const int nc = !!bt->cloud_sigma_m2 + !!bt->cloud_p_top_Pa + !!bt->cloud_p_bottom_Pa;
   if (nc != 0 && nc != 3)
     return set_err(c, TRX_E_INVALID_ARG, "cloud deck arrays: all three or none");
+  if (!bt->log10_vmr_top != !bt->vmr_switch_Pa)
+    return set_err(c, TRX_E_INVALID_ARG, "two-layer arrays: log10_vmr_top and vmr_switch_Pa both or neither");
+  if (bt->log10_vmr_top && precision == TRX_FP64 && bt->max_layers > TRX_MAX_LAYERS_MFMA)
+    return set_err(c, TRX_E_UNSUPPORTED, "two-layer profiles take at most %d layers in TRX_FP64",
+                   TRX_MAX_LAYERS_MFMA);
   return TRX_OK;
 }
 
@@ -480,6 +485,7 @@ DevBatch trx::dev_batch(const trx_batch* bt) {
   d.wn_lo = bt->wn_lo; d.wn_hi = bt->wn_hi;
   d.he_h2 = bt->he_h2_ratio; d.kB = bt->k_B; d.amu = bt->amu_kg; d.gravity = bt->gravity;
   d.cloud_sigma = bt->cloud_sigma_m2; d.cloud_p1 = bt->cloud_p_top_Pa; d.cloud_p2 = bt->cloud_p_bottom_Pa;
+  d.vmr_top = bt->log10_vmr_top; d.vmr_sw = bt->vmr_switch_Pa;
   return d;
 }
 
@@ -487,8 +493,9 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
                                 const int32_t* B_dev, int max_layers, const trx_bins* bins,
                                 int precision, const RunConfig& rc, uint8_t* ws, void* aws,
                                 const SchedBufs& sb, double* depth_native, double* depth_binned,
-                                int32_t* status, bool grad_layout, double* tau, const EmissionIn* em) {
-  const Layout L = make_layout(max_layers, precision, grad_layout, t->dev, em != nullptr);
+                                int32_t* status, bool grad_layout, double* tau, const EmissionIn* em,
+                                bool regimes) {
+  const Layout L = make_layout(max_layers, precision, grad_layout, t->dev, em != nullptr, regimes);
   GeomArgs g;
   g.bt = db;
   g.tab = t->dev;
@@ -686,7 +693,8 @@ extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_bat
   if (depth_binned && !bins) return set_err(c, TRX_E_INVALID_ARG, "depth_binned requires bins");
   if (bins && bins->tables != t) return set_err(c, TRX_E_INVALID_ARG, "bins were made for other tables");
   hipSetDevice(c->device);
-  const Layout L = make_layout(bt->max_layers, precision, false, t->dev);
+  const bool rg = bt->log10_vmr_top != nullptr;
+  const Layout L = make_layout(bt->max_layers, precision, false, t->dev, false, rg);
   if ((s = ensure_buffer(c, c->ws, (size_t)bt->B * L.slab, "workspace")) != TRX_OK) return s;
   const size_t esz = precision == TRX_FP64 ? 8 : 4;
   if ((s = ensure_buffer(c, c->aws, (size_t)bt->B * t->dev.n_wn * esz, "workspace")) != TRX_OK) return s;
@@ -694,7 +702,7 @@ extern "C" trx_status trx_forward(trx_ctx* c, const trx_tables* t, const trx_bat
   RunConfig rc = default_config(precision, bt->max_layers);
   return enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision, rc,
                          (uint8_t*)c->ws.ptr, c->aws.ptr, SchedBufs::carve(c->sched.ptr, bt->B),
-                         depth_native, depth_binned, model_status, false, tau);
+                         depth_native, depth_binned, model_status, false, tau, nullptr, rg);
 }
 
 extern "C" trx_status trx_forward_noalloc(trx_ctx* c, const trx_tables* t, const trx_batch* bt,
@@ -717,7 +725,8 @@ extern "C" trx_status trx_forward_noalloc(trx_ctx* c, const trx_tables* t, const
                    hipGetErrorString(e));
   // carve the workspace of trx_forward (slabs, atmospheric depth, work
   // order) from the array, each part 256-byte aligned
-  const Layout L = make_layout(bt->max_layers, precision, false, t->dev);
+  const bool rg = bt->log10_vmr_top != nullptr;
+  const Layout L = make_layout(bt->max_layers, precision, false, t->dev, false, rg);
   const size_t esz = precision == TRX_FP64 ? 8 : 4;
   size_t used = 0;
   auto take = [&](size_t bytes) { const size_t o = used; used += (bytes + 255) / 256 * 256; return o; };
@@ -734,7 +743,8 @@ extern "C" trx_status trx_forward_noalloc(trx_ctx* c, const trx_tables* t, const
   c->no_events = true;
   s = enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision,
                       default_config(precision, bt->max_layers), p + o_ws, p + o_aws,
-                      SchedBufs::carve(p + o_sched, bt->B), depth_native, depth_binned, model_status);
+                      SchedBufs::carve(p + o_sched, bt->B), depth_native, depth_binned, model_status, false,
+                      nullptr, nullptr, rg);
   c->no_events = false;
   return s;
 }
@@ -751,7 +761,8 @@ extern "C" trx_status trx_emission(trx_ctx* c, const trx_tables* t, const trx_ba
   if (fpfs_binned && !bins) return set_err(c, TRX_E_INVALID_ARG, "fpfs_binned requires bins");
   if (bins && bins->tables != t) return set_err(c, TRX_E_INVALID_ARG, "bins were made for other tables");
   hipSetDevice(c->device);
-  const Layout L = make_layout(bt->max_layers, precision, false, t->dev, true);
+  const bool rg = bt->log10_vmr_top != nullptr;
+  const Layout L = make_layout(bt->max_layers, precision, false, t->dev, true, rg);
   if ((s = ensure_buffer(c, c->ws, (size_t)bt->B * L.slab, "workspace")) != TRX_OK) return s;
   const size_t esz = 8;   // the flux ratio per native point is kept in FP64 in every mode
   if ((s = ensure_buffer(c, c->aws, (size_t)bt->B * t->dev.n_wn * esz, "workspace")) != TRX_OK) return s;
@@ -760,7 +771,7 @@ extern "C" trx_status trx_emission(trx_ctx* c, const trx_tables* t, const trx_ba
   const EmissionIn em{T_star_K, n_mu};
   return enqueue_forward(c, t, dev_batch(bt), bt->B, nullptr, bt->max_layers, bins, precision, rc,
                          (uint8_t*)c->ws.ptr, c->aws.ptr, SchedBufs::carve(c->sched.ptr, bt->B), fpfs_native,
-                         fpfs_binned, model_status, false, nullptr, &em);
+                         fpfs_binned, model_status, false, nullptr, &em, rg);
 }
 
 // --------------------------------------------------------------------------
@@ -843,6 +854,8 @@ extern "C" trx_status trx_chi2_grad(trx_ctx* c, const trx_tables* t, const trx_b
     return set_err(c, TRX_E_UNSUPPORTED, "only the recompute mode of the gradient is built");
   if (t->dev.t_exp)
     return set_err(c, TRX_E_UNSUPPORTED, "the gradient of the exponential temperature scheme is not built");
+  if (bt->log10_vmr_top)
+    return set_err(c, TRX_E_UNSUPPORTED, "the gradient of two-layer profiles is not built");
   if (bt->max_layers > TRX_MAX_LAYERS_MFMA)
     return set_err(c, TRX_E_UNSUPPORTED, "the gradient supports at most %d layers", TRX_MAX_LAYERS_MFMA);
   hipSetDevice(c->device);

@@ -306,8 +306,8 @@ struct Smem64s {
   double A[TRX_MAX_LAYERS_MFMA];                   // A_j/Rs^2
   double PR[TRX_MAX_LAYERS_MFMA];                  // Rayleigh path weights
   int32_t sid[kKC64];
-  double chis[kMaxSpecies];
-  double ciaw[TRX_MAX_CIA];   // CIA pair weights times kCiaScale32 (the scale of P's CIA columns)
+  double chis[kMaxRegimes][kMaxSpecies];   // mixing ratios per run (two-layer profiles; else run 0)
+  double ciaw[kMaxRegimes][TRX_MAX_CIA];   // CIA pair weights times kCiaScale32 (the scale of P's CIA columns)
   double4 em[EM ? TRX_MAX_LAYERS_MFMA : 1];        // emission: the layer records
 };
 
@@ -338,7 +338,7 @@ __device__ inline void mix64(const double* tab, int64_t stride, int nt, const do
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int k = i < i0 ? i0 : (i >= i1 ? i1 - 1 : i);
-    off[i] = (int64_t)__builtin_amdgcn_readfirstlane(rows[k]) * W + col;
+    off[i] = (int64_t)(__builtin_amdgcn_readfirstlane(rows[k]) & 0xffffff) * W + col;
   }
   for (int t0 = 0; t0 < nt; t0 += 2) {
     double v[2][8];
@@ -379,7 +379,8 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
   const int W = tb.n_wn;
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const int nU = ml->nU, nV = tb.n_cia > 0 ? ml->nV : 0;
-  const int K = nU + nV;
+  const int nR = L.rg ? ml->pad[0] : 0;   // Rayleigh slots, one per run (two-layer layouts)
+  const int K = nU + nV + nR;
   const int nrb = hd->nrb, n16 = 2 * nrb;
   const int NKQ = L.NKQ;
   const int32_t* sid = reinterpret_cast<const int32_t*>(slab + L.off_sid);
@@ -388,7 +389,7 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
   const double* PR64 = reinterpret_cast<const double*>(slab + L.off_pr64);
   const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
   const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
-  const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
+  const int ns = tb.has_rayleigh && !L.rg ? tb.n_abs + 2 : 0;
 
   if (tid < 32 * nrb) {
     sm.A[tid] = tid < N ? A64[tid] : 0.0;
@@ -396,8 +397,16 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
     if constexpr (EM) sm.em[tid] = reinterpret_cast<const double4*>(slab + L.off_em64)[tid];
   }
   if (K <= kKC64 && tid < K) sm.sid[tid] = sid[tid];
-  if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s[tid];
-  if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w[tid] * kCiaScale32;
+  if (tid < kMaxSpecies) sm.chis[0][tid] = hd->chi_s[tid];
+  if (tid < TRX_MAX_CIA) sm.ciaw[0][tid] = hd->cia_w[tid] * kCiaScale32;
+  if (L.rg && tid < kMaxSpecies) {
+    // the other runs' mixing ratios (two-layer profiles)
+    const RegChem* rc = reinterpret_cast<const RegChem*>(slab + L.off_rg);
+    for (int r = 1; r < kMaxRegimes; ++r) {
+      sm.chis[r][tid] = rc[r].chi_s[tid];
+      if (tid < TRX_MAX_CIA) sm.ciaw[r][tid] = rc[r].cia_w[tid] * kCiaScale32;
+    }
+  }
   __syncthreads();
 
   for (int span = sp0; span < sp1; ++span) {
@@ -407,7 +416,7 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
     const int cc = valid ? col : lo;
     {
       double rp = 0.0;
-      for (int k = wave; k < ns; k += kWaves) rp = fma(sm.chis[k], tb.ray64[(int64_t)k * W + cc], rp);
+      for (int k = wave; k < ns; k += kWaves) rp = fma(sm.chis[0][k], tb.ray64[(int64_t)k * W + cc], rp);
       sm.rpart[wave][lane] = rp;
     }
     // stage the slot chunk c0 .. (8-slot groups g = wave, wave + 4, ...)
@@ -421,23 +430,39 @@ __device__ void process64s(const FwdArgs& a, int b_in, int s_first, int s_end, S
       const int ng = 2 * ((kc + 15) / 16);
       for (int g = wave; g < ng; g += kWaves) {
         const int s0 = c0 + 8 * g;
+        // the run of the group (its first slot's; two-layer layouts pad
+        // each run's slots of one kind to whole groups)
+        const int rg = s0 < K ? min((int)((uint32_t)__builtin_amdgcn_readfirstlane(sm.sid[8 * g]) >> 24),
+                                    kMaxRegimes - 1) : 0;
         double v[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = 0.0;
         const int nc = min(max(nU - s0, 0), 8);
         if (nc > 0 && L.xt) {
-          // exponential scheme: slot s0 + i is layer N - 1 - s0 - i (records by slot)
+          // exponential scheme: layer slots (records by slot)
           const double4* xr = reinterpret_cast<const double4*>(slab + L.off_xt64) + s0;
 #pragma unroll
           for (int i = 0; i < 8; ++i)
             if (i < nc)
-              v[i] = xt_mix64(tb.xsec64, abs_stride, tb.n_abs, hd->chi_s,
-                              (int64_t)__builtin_amdgcn_readfirstlane(sm.sid[8 * g + i]) * W + cc, xr[i], W, tb.n_P);
+              v[i] = xt_mix64(tb.xsec64, abs_stride, tb.n_abs, sm.chis[rg],
+                              (int64_t)(__builtin_amdgcn_readfirstlane(sm.sid[8 * g + i]) & 0xffffff) * W + cc,
+                              xr[i], W, tb.n_P);
         } else if (nc > 0) {
-          mix64(tb.xsec64, abs_stride, tb.n_abs, hd->chi_s, sm.sid + 8 * g, 0, nc, W, cc, v);
+          mix64(tb.xsec64, abs_stride, tb.n_abs, sm.chis[rg], sm.sid + 8 * g, 0, nc, W, cc, v);
         }
-        const int vb = min(max(K - s0, 0), 8);
-        if (vb > nc) mix64(tb.cia64, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, cc, v);
+        const int vb = min(max(nU + nV - s0, 0), 8);
+        if (vb > nc) mix64(tb.cia64, cia_stride, tb.n_cia, sm.ciaw[rg], sm.sid + 8 * g, nc, vb, W, cc, v);
+        // Rayleigh slots (two-layer layouts): each its own run's mix
+        const int vr = min(max(K - s0, 0), 8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          if (i >= vb && i < vr) {
+            const int r = min((int)((uint32_t)__builtin_amdgcn_readfirstlane(sm.sid[8 * g + i]) >> 24), kMaxRegimes - 1);
+            double acc = 0.0;
+            for (int k = 0; k < tb.n_abs + 2; ++k) acc = fma(sm.chis[r][k], tb.ray64[(int64_t)k * W + cc], acc);
+            v[i] = acc;
+          }
+        }
 #pragma unroll
         for (int i = 0; i < 8; ++i) sm.rows[8 * g + i][lane] = v[i];
       }

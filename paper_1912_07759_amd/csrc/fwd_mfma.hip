@@ -126,11 +126,10 @@ struct Smem {
   float4 em[EPI == kEpiEm ? TRX_MAX_LAYERS_MFMA : 1];
   double emz[EPI == kEpiEm ? TRX_MAX_LAYERS_MFMA : 1];   // c2 (1/T_l - 1/T_*) in FP64
   float rpart[kWaves][kCols];       // Rayleigh sums by wave
-  int32_t sid[kKC];                 // table rows of the chunk's slots
+  int32_t sid[kKC];                 // table rows of the chunk's slots (| run << 24)
   float4 xr[XT ? kKC : 1];          // exponential scheme: records of the chunk's layer slots
-  float chi[TRX_MAX_ABSORBERS];
-  float chis[kMaxSpecies];          // all species (Rayleigh)
-  float ciaw[TRX_MAX_CIA];
+  float chis[kMaxRegimes][kMaxSpecies];   // mixing ratios per run: absorbers, H2, He
+  float ciaw[kMaxRegimes][TRX_MAX_CIA];   // CIA pair weights per run
   int32_t items[kChunk];
   int32_t spans[kChunk];
   int32_t base;
@@ -236,7 +235,7 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int k = i < i0 ? i0 : (i >= i1 ? i1 - 1 : i);
-    soff[i] = __builtin_amdgcn_readfirstlane(rows[k]) * W * 4;
+    soff[i] = (__builtin_amdgcn_readfirstlane(rows[k]) & 0xffffff) * W * 4;
   }
   for (int t0 = 0; t0 < nt; t0 += SA) {
     float v[SA][8];
@@ -258,6 +257,26 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
           if (i >= i0 && i < i1) s[i] = fmaf(c, v[tt][i], s[i]);
       }
     }
+  }
+}
+
+// Rayleigh slots of two-layer layouts: s[i] += sum_k chis[run of slot i][k]
+// ray_k[col] over the ns species for the slots i in [i0, i1) of a group
+// (the run in bits 24.. of the slot entry); each species' row is loaded once
+// for all the group's slots.
+__device__ inline void mix_rayleigh(const float* ray, int ns, int W, const float (*chis)[kMaxSpecies],
+                                    const int32_t* rows, int i0, int i1, int voff, float* s) {
+  const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc((void*)ray, (short)0, ns * W * 4, kRsrcWord3);
+  int run[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    run[i] = min((int)((uint32_t)__builtin_amdgcn_readfirstlane(rows[i < i1 ? i : i1 - 1]) >> 24), kMaxRegimes - 1);
+  for (int k = 0; k < ns; ++k) {
+    const float v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rr, voff, k * W * 4, 0));
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i >= i0 && i < i1)
+        s[i] = fmaf(__uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(chis[run[i]][k]))), v, s[i]);
   }
 }
 
@@ -284,7 +303,7 @@ __device__ inline void mix_group_xt(const float2* pairs, const float* tab, int64
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int k = i >= i1 ? i1 - 1 : i;
-    soff[i] = __builtin_amdgcn_readfirstlane(rows[k]) * W * 8;
+    soff[i] = (__builtin_amdgcn_readfirstlane(rows[k]) & 0xffffff) * W * 8;
     u[i] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(rec[k].x)));
     wp[i] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(rec[k].y)));
   }
@@ -351,7 +370,7 @@ __device__ inline void issue_corners(const float* tab, int64_t stride, int nt, c
   const int rec = (int)(stride * 4 < 0x7fffffff ? stride * 4 : 0x7fffffff);
   int soff[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) soff[i] = __builtin_amdgcn_readfirstlane(rows[i]) * W * 4;
+  for (int i = 0; i < 8; ++i) soff[i] = (__builtin_amdgcn_readfirstlane(rows[i]) & 0xffffff) * W * 4;
 #pragma unroll
   for (int tt = 0; tt < SA; ++tt) {
     if (t0 + tt < nt) {
@@ -405,7 +424,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   const int W = tb.n_wn;
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const int nU = ml->nU, nV = tb.n_cia > 0 ? ml->nV : 0;
-  const int K = nU + nV;
+  // two-layer layouts: one Rayleigh slot per run after the node slots
+  const int nR = L.rg ? ml->pad[0] : 0;
+  const int K = nU + nV + nR;
   const int nrb = hd->nrb;
   const int NKQ = L.NKQ;
   // slot blocks with a nonzero product, per ray block of this wave
@@ -445,9 +466,16 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     if (K <= kKC && tid < K) sm.sid[tid] = r;
     if constexpr (XT)
       if (K <= kKC && tid < nU) sm.xr[tid] = reinterpret_cast<const float4*>(slab + L.off_xt32)[tid];
-    if (tid < TRX_MAX_ABSORBERS) sm.chi[tid] = hd->chi_abs32[tid];
-    if (tid < kMaxSpecies) sm.chis[tid] = hd->chi_s32[tid];
-    if (tid < TRX_MAX_CIA) sm.ciaw[tid] = hd->cia_w32[tid];
+    if (tid < kMaxSpecies) sm.chis[0][tid] = hd->chi_s32[tid];
+    if (tid < TRX_MAX_CIA) sm.ciaw[0][tid] = hd->cia_w32[tid];
+    if (L.rg && tid < kMaxSpecies) {
+      // the other runs' mixing ratios (two-layer profiles)
+      const RegChem* rc = reinterpret_cast<const RegChem*>(slab + L.off_rg);
+      for (int r = 1; r < kMaxRegimes; ++r) {
+        sm.chis[r][tid] = rc[r].chi_s32[tid];
+        if (tid < TRX_MAX_CIA) sm.ciaw[r][tid] = rc[r].cia_w32[tid];
+      }
+    }
   }
   __syncthreads();
 
@@ -492,7 +520,8 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     awsum[r] = t + __shfl_xor(t, 32, 64);
   }
 
-  const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
+  // Rayleigh by ray weights (two-layer layouts: by slots)
+  const int ns = tb.has_rayleigh && !L.rg ? tb.n_abs + 2 : 0;
   for (int span = sp0; span < sp1; ++span) {
     const int col = span * kCols + lane;
     const bool valid = col >= lo && col < hi;
@@ -511,6 +540,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         rv[u] = k < ns ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rr, voff, k * W * 4, 0)) : 0.f;
       }
     }
+
+    // the run whose mixing ratios a staged group of 8 slots takes (its
+    // first slot's; two-layer layouts pad each run's slots of one kind to
+    // whole groups)
+    auto run_of_group = [&](int g) -> int {
+      return min((int)((uint32_t)__builtin_amdgcn_readfirstlane(sm.sid[8 * g]) >> 24), kMaxRegimes - 1);
+    };
 
     // one staging chunk (slots c0 ..): stage, then contract; the first
     // chunk zeroes the accumulators after its staging (they are not live
@@ -582,7 +618,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
             tn = 0;
           }
           if (gn < gf) issue_corners<SA>(tb.xsec32, abs_stride, na, sm.sid + 8 * gn, tn, W, voff, nxt);
-          mix_corners<SA>(sm.chi, na, t0, cur, s);
+          mix_corners<SA>(sm.chis[run_of_group(g)], na, t0, cur, s);
           if (tn == 0) write_group(g, s);
           g = gn;
           t0 = tn;
@@ -596,19 +632,23 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       // the other groups
       for (int g = gf + ((wave - gf) % kWaves + kWaves) % kWaves; g < ng; g += kWaves) {
         const int s0 = c0 + 8 * g;
+        const int rg = run_of_group(g);
         float s[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.f;
         const int nc = min(max(nU - s0, 0), 8);
         if (nc > 0) {
           if constexpr (XT)
-            mix_group_xt<first ? 2 : 1>(tb.xexp32, tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g,
+            mix_group_xt<first ? 2 : 1>(tb.xexp32, tb.xsec32, abs_stride, tb.n_abs, sm.chis[rg], sm.sid + 8 * g,
                                          sm.xr + 8 * g, nc, W, tb.n_P, cc, s);
           else
-            mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chi, sm.sid + 8 * g, 0, nc, W, voff, s);
+            mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chis[rg], sm.sid + 8 * g, 0, nc, W, voff, s);
         }
-        const int vb = min(max(K - s0, 0), 8);
-        if (vb > nc) mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw, sm.sid + 8 * g, nc, vb, W, voff, s);
+        const int vb = min(max(nU + nV - s0, 0), 8);
+        if (vb > nc)
+          mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw[rg], sm.sid + 8 * g, nc, vb, W, voff, s);
+        const int vr = min(max(K - s0, 0), 8);
+        if (vr > vb) mix_rayleigh(tb.ray32, tb.n_abs + 2, W, sm.chis, sm.sid + 8 * g, vb, vr, voff, s);
         write_group(g, s);
       }
       if (c0 == 0) {
@@ -616,9 +656,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = wave + kWaves * u;
-          if (k < ns) rp = fmaf(sm.chis[k], rv[u], rp);
+          if (k < ns) rp = fmaf(sm.chis[0][k], rv[u], rp);
         }
-        for (int k = wave + 4 * kWaves; k < ns; k += kWaves) rp = fmaf(sm.chis[k], tb.ray32[(int64_t)k * W + cc], rp);
+        for (int k = wave + 4 * kWaves; k < ns; k += kWaves) rp = fmaf(sm.chis[0][k], tb.ray32[(int64_t)k * W + cc], rp);
         sm.rpart[wave][lane] = rp;
       }
       __syncthreads();   // staged slots visible

@@ -87,7 +87,10 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   __shared__ double sZ[TRX_MAX_LAYERS_FP64];
   __shared__ double sC[TRX_MAX_LAYERS_FP64];   // kB T_l * ln(P_{l+1}/P_l), later the deck's terms
   __shared__ int s_status;
-  __shared__ double s_mu;
+  __shared__ double s_mu[kMaxRegimes];
+  __shared__ int s_cut[kMaxRegimes + 1];   // first layer of each run
+  __shared__ int s_lsw[TRX_MAX_ABSORBERS];  // first layer where each absorber takes its top value
+  __shared__ int s_nreg;
 
   const int tid = threadIdx.x;
   const int N = a.bt.n_layers[b];
@@ -109,8 +112,13 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       double x = a.bt.log10_vmr[(int64_t)b * nabs + i];
       fin = fin && isfinite(x);
       S += pow(10.0, x);
+      if (a.bt.vmr_top) {
+        fin = fin && isfinite(a.bt.vmr_top[(int64_t)b * nabs + i]);
+        fin = fin && finite_pos(a.bt.vmr_sw[(int64_t)b * nabs + i]);
+      }
     }
-    if (!fin || !(S < 1.0)) st |= TRX_MODEL_BAD_CHEMISTRY;
+    // two-layer models: each run's sum is checked once the runs are known
+    if (!fin || (!a.bt.vmr_top && !(S < 1.0))) st |= TRX_MODEL_BAD_CHEMISTRY;
     if (a.bt.cloud_sigma) {
       const double sg = a.bt.cloud_sigma[b];
       if (!(sg >= 0.0)) st |= TRX_MODEL_BAD_PROFILE;
@@ -127,12 +135,13 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     }
   }
   __syncthreads();
-  const int status = s_status;
-  if (status) {
+  // an invalid model: status, no layers, NaN in its window
+  auto reject = [&](int status) {
     if (tid == 0) {
       h->n = 0; h->status = status; h->lo = lo; h->hi = hi;
       h->nrb = 0; h->nkb = 0; h->span_lo = 0; h->span_hi = 0;
       h->cloud = 0;
+      h->nreg = 0;
       if (a.mlay) a.mlay[b] = 0;
       if (a.mspan) a.mspan[b] = make_int2(0, 0);
     }
@@ -140,6 +149,9 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
       for (int i = lo + tid; i < hi; i += kThreads)
         a.depth_native[(int64_t)b * tb.n_wn + i] = __builtin_nan("");
     }
+  };
+  if (s_status) {
+    reject(s_status);
     return;
   }
 
@@ -150,36 +162,108 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     double p1 = pow(10.0, xb + (xt - xb) * (double)(l + 1) / (double)N);
     sP[l] = p0 * sqrt(p1 / p0);
   }
-  // a1: chemistry
-  if (tid == 0) {
-    double S = 0.0, mu = 0.0;
-    for (int i = 0; i < TRX_MAX_ABSORBERS; ++i) h->chi_abs32[i] = 0.0f;
-    for (int i = 0; i < nabs; ++i) {
-      double c = pow(10.0, a.bt.log10_vmr[(int64_t)b * nabs + i]);
-      h->chi_s[i] = c;
-      h->chi_s32[i] = (float)c;
-      h->chi_abs32[i] = (float)c;
-      S += c;
-      mu += c * tb.mass[i];
+  __syncthreads();
+  // a1: chemistry.  Constant profiles: one run.  Two-layer profiles
+  // (Chemistry subsection): absorber i takes its top value from the first
+  // layer whose centre pressure is below its switch pressure, l_i; the
+  // distinct l_i inside the model cut its layers into runs of one
+  // chemistry (run r: layers from the r-th cut on), each with its own fill
+  // gases and mean molecular weight.
+  RegChem* rgc = L.rg ? reinterpret_cast<RegChem*>(slab + L.off_rg) : nullptr;
+  // the switch layer of each absorber (N: surface value everywhere)
+  for (int i = tid; i < nabs; i += kThreads) {
+    int l = N;
+    if (a.bt.vmr_top) {
+      const double sw = a.bt.vmr_sw[(int64_t)b * nabs + i];
+      l = 0;
+      while (l < N && sP[l] >= sw) ++l;
     }
-    const double r = a.bt.he_h2;
-    const double ch2 = (1.0 - S) / (1.0 + r), che = r * ch2;
-    h->chi_s[nabs] = ch2;
-    h->chi_s[nabs + 1] = che;
-    h->chi_s32[nabs] = (float)ch2;
-    h->chi_s32[nabs + 1] = (float)che;
-    mu += ch2 * tb.mass[nabs] + che * tb.mass[nabs + 1];
-    s_mu = mu * a.bt.amu;
-    for (int p = 0; p < TRX_MAX_CIA; ++p) {
-      double w = p < tb.n_cia ? h->chi_s[tb.cia_pair[p][0]] * h->chi_s[tb.cia_pair[p][1]] : 0.0;
-      h->cia_w[p] = w;
-      h->cia_w32[p] = (float)w;
-    }
+    s_lsw[i] = l;
   }
   __syncthreads();
-  const double mu = s_mu;
+  if (tid == 0) {
+    int R = 1;
+    s_cut[0] = 0;
+    for (int i = 0; i < nabs; ++i) {
+      const int l = s_lsw[i];
+      if (l <= 0 || l >= N) continue;
+      bool seen = false;
+      for (int r = 1; r < R; ++r) seen = seen || s_cut[r] == l;
+      if (seen) continue;
+      if (R == kMaxRegimes) {
+        R = kMaxRegimes + 1;   // too many runs
+        break;
+      }
+      // insertion keeps the cuts ascending
+      int r = R++;
+      while (r > 1 && s_cut[r - 1] > l) { s_cut[r] = s_cut[r - 1]; --r; }
+      s_cut[r] = l;
+    }
+    int st = 0;
+    if (R > kMaxRegimes) st |= TRX_MODEL_UNSUPPORTED;
+    for (int r = 0; r < R && !st; ++r) {
+      const int lr = s_cut[r];   // first layer of run r
+      double chi[kMaxSpecies];
+      double S = 0.0, mu = 0.0;
+      for (int i = 0; i < nabs; ++i) {
+        const bool top = lr >= s_lsw[i];
+        const double x = top ? a.bt.vmr_top[(int64_t)b * nabs + i] : a.bt.log10_vmr[(int64_t)b * nabs + i];
+        chi[i] = pow(10.0, x);
+        S += chi[i];
+        mu += chi[i] * tb.mass[i];
+      }
+      if (!(S < 1.0)) {
+        st |= TRX_MODEL_BAD_CHEMISTRY;
+        break;
+      }
+      const double rr = a.bt.he_h2;
+      chi[nabs] = (1.0 - S) / (1.0 + rr);
+      chi[nabs + 1] = rr * chi[nabs];
+      mu += chi[nabs] * tb.mass[nabs] + chi[nabs + 1] * tb.mass[nabs + 1];
+      s_mu[r] = mu * a.bt.amu;
+      double cw[TRX_MAX_CIA];
+      for (int p = 0; p < TRX_MAX_CIA; ++p)
+        cw[p] = p < tb.n_cia ? chi[tb.cia_pair[p][0]] * chi[tb.cia_pair[p][1]] : 0.0;
+      if (rgc) {
+        for (int k = 0; k < kMaxSpecies; ++k) {
+          const double v = k < nabs + 2 ? chi[k] : 0.0;
+          rgc[r].chi_s[k] = v;
+          rgc[r].chi_s32[k] = (float)v;
+        }
+        for (int p = 0; p < TRX_MAX_CIA; ++p) {
+          rgc[r].cia_w[p] = cw[p];
+          rgc[r].cia_w32[p] = (float)cw[p];
+        }
+      }
+      if (r == 0) {
+        for (int i = 0; i < TRX_MAX_ABSORBERS; ++i) h->chi_abs32[i] = i < nabs ? (float)chi[i] : 0.0f;
+        for (int k = 0; k < nabs + 2; ++k) {
+          h->chi_s[k] = chi[k];
+          h->chi_s32[k] = (float)chi[k];
+        }
+        for (int p = 0; p < TRX_MAX_CIA; ++p) {
+          h->cia_w[p] = cw[p];
+          h->cia_w32[p] = (float)cw[p];
+        }
+      }
+    }
+    s_nreg = R;
+    s_status = st;
+  }
+  __syncthreads();
+  if (s_status) {
+    reject(s_status);
+    return;
+  }
+  const int R = s_nreg;
+  // run of layer l
+  auto run_of = [&](int l) {
+    int r = 0;
+    for (int k = 1; k < R; ++k) r += l >= s_cut[k];
+    return r;
+  };
   for (int l = tid; l < N - 1; l += kThreads)
-    sC[l] = a.bt.kB * a.bt.T[off + l] * log(sP[l + 1] / sP[l]) / mu;
+    sC[l] = a.bt.kB * a.bt.T[off + l] * log(sP[l + 1] / sP[l]) / s_mu[run_of(l)];
   __syncthreads();
   // a2: altitude recurrence, one lane
   if (tid == 0) {
@@ -209,7 +293,8 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     for (int r = 0; r < TRX_MAX_LAYERS_MFMA / 32; ++r) h->kq_mask[r] = 0ull;   // set by the path-matrix kernel
     h->inv_Rs2 = 1.0 / (Rs * Rs);
     h->Rp = Rp;
-    h->mu_kg = mu;
+    h->mu_kg = s_mu[0];
+    h->nreg = R;
   }
   __syncthreads();
   const double inv_Rs2 = 1.0 / (Rs * Rs);
@@ -247,6 +332,33 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
     return h1 - h0;
   };
   const double Tstar = L.em ? a.T_star[b] : 1.0;
+
+  // exponential scheme: each layer is an absorber slot, the top run's
+  // layers first, each run top layer first and padded to a multiple of 8
+  // slots in two-layer layouts (constant profiles: slot N-1-l); the
+  // records are kept by slot, zero for the padding slots
+  __shared__ int s_xb[kMaxRegimes];
+  if (L.xt) {
+    if (tid == 0) {
+      int base = 0;
+      for (int r = R - 1; r >= 0; --r) {
+        s_xb[r] = base;
+        const int n = (r == R - 1 ? N : s_cut[r + 1]) - s_cut[r];
+        base += L.rg ? (n + 7) / 8 * 8 : n;
+      }
+    }
+    const int nslot = L.rg ? 16 * L.NKQ : L.NP;
+    for (int q = tid; q < nslot; q += kThreads) {
+      reinterpret_cast<double4*>(slab + L.off_xt64)[q] = make_double4(0.0, 0.0, 0.0, 0.0);
+      reinterpret_cast<float4*>(slab + L.off_xt32)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+  }
+  auto xt_slot = [&](int l) {
+    const int r = run_of(l);
+    const int last = (r == R - 1 ? N : s_cut[r + 1]) - 1;
+    return s_xb[r] + (last - l);
+  };
 
   // a3: annulus weights; a4: layer records
   const int NP = L.NP;
@@ -315,8 +427,9 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         // sigma1 (sigma2/sigma1)^u, u = (1/T - 1/T1)/(1/T2 - 1/T1) = w_T T2/T
         // (0 and 1 under the clamps, where T is taken at the edge node)
         const double u = c0 ? wT : wT * (tb.T[iT + 1] / T);
-        reinterpret_cast<double4*>(slab + L.off_xt64)[N - 1 - l] = make_double4(u, wP, wT, 0.0);
-        reinterpret_cast<float4*>(slab + L.off_xt32)[N - 1 - l] = make_float4((float)u, (float)wP, (float)wT, 0.f);
+        const int q = xt_slot(l);
+        reinterpret_cast<double4*>(slab + L.off_xt64)[q] = make_double4(u, wP, wT, 0.0);
+        reinterpret_cast<float4*>(slab + L.off_xt32)[q] = make_float4((float)u, (float)wP, (float)wT, 0.f);
       }
       w[4] = tb.has_rayleigh ? f1 : 0.0;
       if (tb.n_cia > 0) {
@@ -378,10 +491,6 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         reinterpret_cast<double4*>(slab + L.off_em64)[l] = make_double4(0.0, 0.0, 0.0, 0.0);
         reinterpret_cast<float4*>(slab + L.off_em32)[l] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      if (L.xt) {
-        reinterpret_cast<double4*>(slab + L.off_xt64)[l] = make_double4(0.0, 0.0, 0.0, 0.0);
-        reinterpret_cast<float4*>(slab + L.off_xt32)[l] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
       if (L.off_aw) reinterpret_cast<float2*>(slab + L.off_aw)[l] = make_float2(0.f, 0.f);
       if (L.off_pr64) reinterpret_cast<double*>(slab + L.off_pr64)[l] = 0.0;
       for (int q = 0; q < 8; ++q) { lw64[8 * l + q] = 0.0; lw32[8 * l + q] = 0.0f; }
@@ -415,13 +524,13 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
   // id the corner (iT, iP) it interpolates from), so that a ray's optical
   // depth is accumulated from its smallest terms up, as the corner slots
   // are (rising pressure nodes)
-  {
+  __shared__ int s_nu;
+  __shared__ uint32_t s_bm[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
+  __shared__ uint32_t s_pre[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
+  __shared__ uint32_t s_cbm[TRX_MAX_TGRID / 32];
+  __shared__ uint32_t s_cpre[TRX_MAX_TGRID / 32];
+  if (!L.rg) {
     const bool xt = L.xt != 0;
-    __shared__ int s_nu;
-    __shared__ uint32_t s_bm[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
-    __shared__ uint32_t s_pre[TRX_MAX_TGRID * TRX_MAX_PGRID / 32];
-    __shared__ uint32_t s_cbm[TRX_MAX_TGRID / 32];
-    __shared__ uint32_t s_cpre[TRX_MAX_TGRID / 32];
     const int nwords = (tb.n_T * tb.n_P + 31) / 32;
     const int ncwords = (tb.n_Tcia + 31) / 32;
     for (int w = tid; w < nwords; w += kThreads) s_bm[w] = 0u;
@@ -523,6 +632,142 @@ __global__ __launch_bounds__(kThreads) void k_geom(GeomArgs a) {
         cslots = rank(s_cbm, s_cpre, t0) | (rank(s_cbm, s_cpre, t0 + 1) << 8);
       }
       lid[8 * l + 3] = (int32_t)cslots;
+    }
+  } else {
+    // two-layer layouts: the same per run, top run first, each run's
+    // corner slots and node slots padded to a multiple of 8 (padding slots
+    // point at row 0 and have no weight); then one Rayleigh slot per run.
+    // The slot table holds row | run << 24; per layer, lid[2] = its run,
+    // lid[3] = its two node slots (16 bits each, counted from the first
+    // node slot), lid[6], lid[7] = its four corner slots.
+    const bool xt = L.xt != 0;
+    const int nT = tb.n_T, nP = tb.n_P;
+    const int nwords = (nT * nP + 31) / 32;
+    const int ncwords = (tb.n_Tcia + 31) / 32;
+    const int cap = 16 * L.NKQ;
+    int32_t* sid = reinterpret_cast<int32_t*>(slab + L.off_sid);
+    __shared__ int s_cu[kMaxRegimes], s_cv[kMaxRegimes], s_ub[kMaxRegimes], s_vb[kMaxRegimes];
+    __shared__ int s_tot[3];   // corner, node and Rayleigh slots (padded)
+    auto corner_keys = [&](int base, int* ks) {
+      const int k0 = (base % nP) * nT + base / nP;
+      ks[0] = k0;
+      ks[1] = k0 + 1;
+      ks[2] = k0 + nT;
+      ks[3] = k0 + nT + 1;
+    };
+    // the bitmaps of run r: its layers' corners and CIA nodes
+    auto mark_run = [&](int r) {
+      for (int w = tid; w < nwords; w += kThreads) s_bm[w] = 0u;
+      for (int w = tid; w < ncwords; w += kThreads) s_cbm[w] = 0u;
+      __syncthreads();
+      const int la = s_cut[r], lb = r == R - 1 ? N : s_cut[r + 1];
+      for (int l = la + tid; l < lb; l += kThreads) {
+        int cs[4];
+        corner_keys(lid[8 * l], cs);
+        for (int q = 0; q < 4 && !xt; ++q) atomicOr(&s_bm[cs[q] >> 5], 1u << (cs[q] & 31));
+        if (tb.n_cia > 0) {
+          const int t0 = lid[8 * l + 1];
+          atomicOr(&s_cbm[t0 >> 5], 1u << (t0 & 31));
+          atomicOr(&s_cbm[(t0 + 1) >> 5], 1u << ((t0 + 1) & 31));
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < nwords; ++w) { s_pre[w] = acc; acc += __popc(s_bm[w]); }
+        uint32_t cacc = 0;
+        for (int w = 0; w < ncwords; ++w) { s_cpre[w] = cacc; cacc += __popc(s_cbm[w]); }
+        s_cu[r] = xt ? lb - la : (int)acc;
+        s_cv[r] = tb.n_cia > 0 ? (int)cacc : 0;
+      }
+      __syncthreads();
+    };
+    // pass 1: the slot counts of every run, then the bases
+    for (int r = R - 1; r >= 0; --r) mark_run(r);
+    if (tid == 0) {
+      int u = 0, v = 0;
+      for (int r = R - 1; r >= 0; --r) {
+        s_ub[r] = u;
+        s_vb[r] = v;
+        u += (s_cu[r] + 7) / 8 * 8;
+        v += (s_cv[r] + 7) / 8 * 8;
+      }
+      s_tot[0] = u;
+      s_tot[1] = v;
+      s_tot[2] = tb.has_rayleigh ? (R + 7) / 8 * 8 : 0;
+      if (u + v + s_tot[2] > cap) s_status = TRX_MODEL_UNSUPPORTED;
+      MList* ml = reinterpret_cast<MList*>(slab + L.off_mlist);
+      ml->nU = u;
+      ml->nV = v;
+      ml->pad[0] = s_tot[2];
+      ml->pad[1] = R;
+    }
+    __syncthreads();
+    if (s_status) {
+      reject(s_status);
+      return;
+    }
+    const int nU = s_tot[0], nV = s_tot[1];
+    auto rank_of = [&](const uint32_t* bm, const uint32_t* pre, int c) -> int {
+      return (int)(pre[c >> 5] + __popc(bm[c >> 5] & ((1u << (c & 31)) - 1u)));
+    };
+    // pass 2: each run's slots
+    for (int r = R - 1; r >= 0; --r) {
+      mark_run(r);
+      const int la = s_cut[r], lb = r == R - 1 ? N : s_cut[r + 1];
+      const int ub = s_ub[r], vb = s_vb[r];
+      const uint32_t tag = (uint32_t)r << 24;
+      if (xt) {
+        for (int l = la + tid; l < lb; l += kThreads) sid[ub + (lb - 1 - l)] = (int32_t)(lid[8 * l] | tag);
+      } else {
+        for (int w = tid; w < nwords; w += kThreads) {
+          uint32_t bits = s_bm[w];
+          int slot = ub + (int)s_pre[w];
+          while (bits) {
+            const int key = 32 * w + __ffs(bits) - 1;
+            sid[slot++] = (int32_t)(((key % nT) * nP + key / nT) | tag);
+            bits &= bits - 1;
+          }
+        }
+      }
+      for (int q = ub + s_cu[r] + tid; q < ub + (s_cu[r] + 7) / 8 * 8; q += kThreads) sid[q] = (int32_t)tag;
+      if (tb.n_cia > 0) {
+        for (int w = tid; w < ncwords; w += kThreads) {
+          uint32_t bits = s_cbm[w];
+          int slot = nU + vb + (int)s_cpre[w];
+          while (bits) {
+            sid[slot++] = (int32_t)((32 * w + __ffs(bits) - 1) | tag);
+            bits &= bits - 1;
+          }
+        }
+        for (int q = nU + vb + s_cv[r] + tid; q < nU + vb + (s_cv[r] + 7) / 8 * 8; q += kThreads)
+          sid[q] = (int32_t)tag;
+      }
+      for (int l = la + tid; l < lb; l += kThreads) {
+        lid[8 * l + 2] = r;
+        if (xt) {
+          const int q = ub + (lb - 1 - l);
+          lid[8 * l + 6] = (int32_t)(q | (q << 16));
+          lid[8 * l + 7] = (int32_t)(q | (q << 16));
+        } else {
+          int cs[4];
+          corner_keys(lid[8 * l], cs);
+          lid[8 * l + 6] = (int32_t)((ub + rank_of(s_bm, s_pre, cs[0])) | ((ub + rank_of(s_bm, s_pre, cs[1])) << 16));
+          lid[8 * l + 7] = (int32_t)((ub + rank_of(s_bm, s_pre, cs[2])) | ((ub + rank_of(s_bm, s_pre, cs[3])) << 16));
+        }
+        uint32_t cslots = 0;
+        if (tb.n_cia > 0) {
+          const int t0 = lid[8 * l + 1];
+          cslots = (uint32_t)(vb + rank_of(s_cbm, s_cpre, t0)) | ((uint32_t)(vb + rank_of(s_cbm, s_cpre, t0 + 1)) << 16);
+        }
+        lid[8 * l + 3] = (int32_t)cslots;
+      }
+      __syncthreads();
+    }
+    // Rayleigh slots: run r at nU + nV + (R - 1 - r), the padding after them
+    for (int q = tid; q < s_tot[2]; q += kThreads) {
+      const int r = q < R ? R - 1 - q : 0;
+      sid[nU + nV + q] = (int32_t)((uint32_t)r << 24);
     }
   }
   __syncthreads();
@@ -627,7 +872,10 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   ModelHdr* hw = reinterpret_cast<ModelHdr*>(slab);
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const int nU = ml->nU, nV = ml->nV;
-  const int nkq = (nU + nV + 15) / 16;
+  // two-layer layouts: one Rayleigh slot per run after the node slots
+  const bool rg = L.rg != 0;
+  const int nRay = rg ? ml->pad[0] : 0, nRun = rg ? ml->pad[1] : 1;
+  const int nkq = (nU + nV + nRay + 15) / 16;
   static_assert(kMaxKQ <= 64, "slot-block masks are 64 bits");
   const double* zs = reinterpret_cast<const double*>(slab + L.off_z);
   const double* A64 = reinterpret_cast<const double*>(slab + L.off_A64);
@@ -641,7 +889,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   __shared__ double sZ[TRX_MAX_LAYERS_MFMA];
   __shared__ double sH[TRX_MAX_LAYERS_MFMA + 1];
   __shared__ double sW[TRX_MAX_LAYERS_MFMA][7];   // 4 corners, 2 CIA nodes, Rayleigh
-  __shared__ int4 sS[TRX_MAX_LAYERS_MFMA];        // slots: corners 0,1 | 2,3 | CIA 0,1 (16 bits each)
+  __shared__ int4 sS[TRX_MAX_LAYERS_MFMA];        // slots: corners 0,1 | 2,3 | CIA 0,1 (16 bits each) | Rayleigh
   __shared__ int sLo[kMaxKQ], sHi[kMaxKQ];
   __shared__ double sAcc[16][kPT];
 
@@ -652,8 +900,13 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     sW[l][5] = lw64[8 * l + 6] / kCiaScale32;
     sW[l][6] = lw64[8 * l + 4];
     const uint32_t cw = (uint32_t)lid[8 * l + 3];
-    const int cs = nV > 0 ? (int)((nU + (cw & 0xff)) | ((nU + ((cw >> 8) & 0xff)) << 16)) : -1;
-    sS[l] = make_int4(lid[8 * l + 6], lid[8 * l + 7], cs, 0);
+    int cs = -1;
+    if (nV > 0)
+      cs = rg ? (int)((nU + (cw & 0xffff)) | ((nU + (cw >> 16)) << 16))
+              : (int)((nU + (cw & 0xff)) | ((nU + ((cw >> 8) & 0xff)) << 16));
+    // the Rayleigh slot of the layer's run (two-layer layouts)
+    const int rs = rg && nRay > 0 ? nU + nV + (nRun - 1 - lid[8 * l + 2]) : 0;
+    sS[l] = make_int4(lid[8 * l + 6], lid[8 * l + 7], cs, rs);
   }
   for (int c = tid; c < nkq; c += kPT) {
     sLo[c] = N;
@@ -664,9 +917,11 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   // the run of layers of each slot block
   for (int l = tid; l < N; l += kPT) {
     const int4 ss = sS[l];
-    const uint32_t sl[6] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
-                            (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16};
-    for (int q = 0; q < (nV > 0 ? 6 : 4); ++q) {
+    const uint32_t sl[7] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
+                            (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16,
+                            (uint32_t)ss.w};
+    for (int q = 0; q < 7; ++q) {
+      if ((q >= 4 && q < 6 && nV == 0) || (q == 6 && nRay == 0)) continue;
       atomicMin(&sLo[sl[q] >> 4], l);
       atomicMax(&sHi[sl[q] >> 4], l);
     }
@@ -717,14 +972,16 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
         for (int l = l0; l <= lb; ++l) {
           const double d = chord(l, q0);
           const int4 ss = sS[l];
-          const uint32_t sl[6] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
-                                  (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16};
+          const uint32_t sl[7] = {(uint32_t)ss.x & 0xffffu, (uint32_t)ss.x >> 16, (uint32_t)ss.y & 0xffffu,
+                                  (uint32_t)ss.y >> 16, (uint32_t)ss.z & 0xffffu, (uint32_t)ss.z >> 16,
+                                  (uint32_t)ss.w};
 #pragma unroll
-          for (int q = 0; q < 6; ++q)
-            if ((int)(sl[q] >> 4) == c && (q < 4 || nV > 0)) sAcc[sl[q] & 15][tid] += d * sW[l][q];
+          for (int q = 0; q < 7; ++q)
+            if ((int)(sl[q] >> 4) == c && (q < 4 || (q < 6 && nV > 0) || (q == 6 && nRay > 0)))
+              sAcc[sl[q] & 15][tid] += d * sW[l][q];
         }
       }
-    } else if (act && c == nkq && a.tab.has_rayleigh) {
+    } else if (act && c == nkq && a.tab.has_rayleigh && !rg) {
       double pr = 0.0, q0 = 0.0;
       for (int l = j; l < N; ++l) pr += chord(l, q0) * sW[l][6];
       aw[j] = make_float2((float)A64[j], (float)pr);

@@ -85,7 +85,8 @@ bool same_batch(const trx_batch& a, const trx_batch& b) {
          a.log10_vmr == b.log10_vmr && a.Rp_m == b.Rp_m && a.Rs_m == b.Rs_m && a.GM_m3s2 == b.GM_m3s2 &&
          a.wn_lo == b.wn_lo && a.wn_hi == b.wn_hi && a.he_h2_ratio == b.he_h2_ratio && a.k_B == b.k_B &&
          a.amu_kg == b.amu_kg && a.gravity == b.gravity && a.cloud_sigma_m2 == b.cloud_sigma_m2 &&
-         a.cloud_p_top_Pa == b.cloud_p_top_Pa && a.cloud_p_bottom_Pa == b.cloud_p_bottom_Pa;
+         a.cloud_p_top_Pa == b.cloud_p_top_Pa && a.cloud_p_bottom_Pa == b.cloud_p_bottom_Pa &&
+         a.log10_vmr_top == b.log10_vmr_top && a.vmr_switch_Pa == b.vmr_switch_Pa;
 }
 
 // The launch sequence of one plan run on the context's current stream.
@@ -96,7 +97,8 @@ trx_status enqueue(trx_plan* p, const trx_batch* bt, int B, const int32_t* B_dev
   const EmissionIn em{p->T_star, p->n_mu};
   return enqueue_forward(p->ctx, p->t, dev_batch(bt), B, B_dev, p->N_max, p->bins, p->precision, rc,
                          (uint8_t*)p->ws.ptr, p->aws.ptr, SchedBufs::carve(p->sched.ptr, p->B_max), native,
-                         binned, status, false, nullptr, (p->flags & TRX_PLAN_EMISSION) ? &em : nullptr);
+                         binned, status, false, nullptr, (p->flags & TRX_PLAN_EMISSION) ? &em : nullptr,
+                         (p->flags & TRX_PLAN_TWO_LAYER) != 0);
 }
 
 trx_status enqueue_io(trx_plan* p, const trx_batch* bt, int B, const int32_t* B_dev, const RunConfig& rc,
@@ -119,6 +121,8 @@ trx_status check_launch(trx_plan* p, const trx_batch* bt, double* binned, const 
   if (binned && !p->bins) return set_err(c, TRX_E_INVALID_ARG, "depth_binned requires a plan made with bins");
   if ((p->flags & TRX_PLAN_EMISSION) && !p->T_star)
     return set_err(c, TRX_E_INVALID_ARG, "an emission plan needs its star (trx_plan_set_star) before a launch");
+  if (bt->log10_vmr_top && !(p->flags & TRX_PLAN_TWO_LAYER))
+    return set_err(c, TRX_E_INVALID_ARG, "a batch with two-layer profiles needs a TRX_PLAN_TWO_LAYER plan");
   return TRX_OK;
 }
 
@@ -209,10 +213,15 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   const int limit = precision == TRX_FP64 ? TRX_MAX_LAYERS_FP64 : TRX_MAX_LAYERS_MFMA;
   if (N_max < 2) return set_err(c, TRX_E_INVALID_ARG, "N_max must be >= 2");
   if (N_max > limit) return set_err(c, TRX_E_UNSUPPORTED, "N_max %d exceeds %d for this precision", N_max, limit);
-  if (flags & ~(TRX_PLAN_GRAPH | TRX_PLAN_PERSISTENT | TRX_PLAN_GRAD | TRX_PLAN_EMISSION))
+  if (flags & ~(TRX_PLAN_GRAPH | TRX_PLAN_PERSISTENT | TRX_PLAN_GRAD | TRX_PLAN_EMISSION | TRX_PLAN_TWO_LAYER))
     return set_err(c, TRX_E_INVALID_ARG, "unknown plan flags 0x%x", flags);
   const bool grad = (flags & TRX_PLAN_GRAD) != 0;
   const bool emission = (flags & TRX_PLAN_EMISSION) != 0;
+  const bool two_layer = (flags & TRX_PLAN_TWO_LAYER) != 0;
+  if (grad && two_layer) return set_err(c, TRX_E_UNSUPPORTED, "the gradient of two-layer profiles is not built");
+  if (two_layer && precision == TRX_FP64 && N_max > TRX_MAX_LAYERS_MFMA)
+    return set_err(c, TRX_E_UNSUPPORTED, "two-layer profiles take at most %d layers in TRX_FP64",
+                   TRX_MAX_LAYERS_MFMA);
   if (grad && emission) return set_err(c, TRX_E_UNSUPPORTED, "the gradient of the emission model is not built");
   if (emission && precision == TRX_FP64 && N_max > TRX_MAX_LAYERS_MFMA)
     return set_err(c, TRX_E_UNSUPPORTED, "emission takes at most %d layers", TRX_MAX_LAYERS_MFMA);
@@ -229,7 +238,7 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   if (!(flags & TRX_PLAN_PERSISTENT)) p->rc.persistent = 0;
   describe(p);
   auto fail = [&](trx_status s) { trx_plan_destroy(p); return s; };
-  const Layout L = make_layout(N_max, precision, grad, t->dev, emission);
+  const Layout L = make_layout(N_max, precision, grad, t->dev, emission, two_layer);
   trx_status s;
   if ((s = ensure_buffer(c, p->ws, (size_t)B_max * L.slab, "plan workspace")) != TRX_OK) return fail(s);
   if (grad && (s = ensure_buffer(c, p->grad, grad_scratch_bytes(B_max, t->dev.n_wn, bins->n_ch, L.NP),
@@ -270,6 +279,20 @@ extern "C" trx_status trx_plan_create(trx_ctx* c, const trx_tables* t, const trx
   b.cloud_sigma_m2 = (double*)take(8 * (size_t)B_max);
   b.cloud_p_top_Pa = (double*)take(8 * (size_t)B_max);
   b.cloud_p_bottom_Pa = (double*)take(8 * (size_t)B_max);
+  // two-layer plans: top values and switch pressures; until the caller
+  // writes them, a switch far below every layer (surface values everywhere)
+  b.log10_vmr_top = nullptr;
+  b.vmr_switch_Pa = nullptr;
+  if (two_layer) {
+    const size_t n = (size_t)B_max * std::max(t->dev.n_abs, 1);
+    b.log10_vmr_top = (double*)take(8 * n);
+    b.vmr_switch_Pa = (double*)take(8 * n);
+    if (e == hipSuccess) e = hipMemset((void*)b.log10_vmr_top, 0, 8 * n);
+    if (e == hipSuccess) {
+      std::vector<double> low(n, 1e-300);
+      e = hipMemcpy((void*)b.vmr_switch_Pa, low.data(), 8 * n, hipMemcpyHostToDevice);
+    }
+  }
   p->B_dev = (int32_t*)take(4);
   if (e == hipSuccess) e = hipMemset((void*)b.cloud_sigma_m2, 0, 8 * (size_t)B_max);
   if (e == hipSuccess) e = hipMemset((void*)b.cloud_p_top_Pa, 0, 8 * (size_t)B_max);
@@ -405,7 +428,7 @@ extern "C" trx_status trx_autotune(trx_plan* p, const trx_batch* bt, const char*
   char key[256];
   snprintf(key, sizeof key, "%s/%s/B%d/N%d/W%d/abs%d/flags%d", c->arch, prec_name(p->precision), bucket(p->B_max),
            bucket(p->N_max), p->t->dev.n_wn, p->t->dev.n_abs,
-           p->flags & (TRX_PLAN_PERSISTENT | TRX_PLAN_EMISSION));
+           p->flags & (TRX_PLAN_PERSISTENT | TRX_PLAN_EMISSION | TRX_PLAN_TWO_LAYER));
   std::map<std::string, std::string> cache;
   if (cache_json) {
     cache = read_cache(cache_json);

@@ -118,7 +118,7 @@ trx_status enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch& db, 
                            int max_layers, const trx_bins* bins, int precision, const RunConfig& rc,
                            uint8_t* ws, void* aws, const SchedBufs& sb, double* depth_native,
                            double* depth_binned, int32_t* status, bool grad_layout = false,
-                           double* tau = nullptr, const EmissionIn* em = nullptr);
+                           double* tau = nullptr, const EmissionIn* em = nullptr, bool regimes = false);
 
 // Gradient workspace carved from one buffer (base null: sizes only).
 struct GradScratch {

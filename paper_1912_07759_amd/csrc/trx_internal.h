@@ -44,6 +44,19 @@ struct alignas(16) KBlk {
   int32_t pad[2];
 };
 constexpr int kMaxSpecies = TRX_MAX_ABSORBERS + 2;
+constexpr int kMaxRegimes = TRX_MAX_REGIMES;
+// Slots of the matrix-core modes are tracked per 16-slot block in 64-bit
+// masks: at most 1024 slots per model.
+constexpr int kMaxSlots = 1024;
+
+// Chemistry of one run of layers (two-layer profiles): mixing ratios of the
+// absorbers, H2 and He, and the CIA pair weights chi_a chi_b.
+struct alignas(16) RegChem {
+  double chi_s[kMaxSpecies];
+  double cia_w[TRX_MAX_CIA];
+  float chi_s32[kMaxSpecies];
+  float cia_w32[TRX_MAX_CIA];
+};
 
 // Per-model values written by the geometry kernel and read by every later
 // kernel.  Lives at the start of each model's workspace slab.
@@ -74,6 +87,10 @@ struct ModelHdr {
   // em_star x wavenumber)
   double em_scale;
   double em_star;
+  // runs of one chemistry (two-layer layouts; 1 otherwise): their
+  // chemistry is in the slab's RegChem records, run 0 (the deepest) also
+  // in chi_s, cia_w and their FP32 copies above
+  int32_t nreg;
 };
 static_assert(sizeof(ModelHdr) <= kHdrBytes, "header too large");
 
@@ -123,6 +140,15 @@ struct Layout {
   // weight of the fallback, FP32 (float4) and FP64 (double4)
   int32_t xt;
   int64_t off_xt32, off_xt64;
+  // two-layer profiles (rg): the layers fall into runs of one chemistry
+  // (at most kMaxRegimes, deepest first); the opacity slots are (run,
+  // corner) and (run, CIA node) pairs and one Rayleigh slot per run, each
+  // run's slots of one kind padded to a multiple of 8 (a staging group
+  // mixes with one run's mixing ratios), ordered top run first; the slot
+  // table entry of a slot is its row | run << 24.  RegChem records at
+  // off_rg.
+  int32_t rg;
+  int64_t off_rg;
   int32_t slot64;          // FP64 mode in the slot form (models of at most TRX_MAX_LAYERS_MFMA layers)
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise); the gradient takes models of at
@@ -141,7 +167,14 @@ constexpr int kKG = 128;
 // cross-section corners (at most 4 per layer, at most the grid's n_T n_P;
 // one per layer in the exponential scheme) and its distinct CIA temperature
 // nodes (at most 2 per layer).
-inline int slot_capacity(const DevTables& t, int NP) {
+inline int slot_capacity(const DevTables& t, int NP, bool rg = false) {
+  if (rg) {
+    const int R = kMaxRegimes, pad = 7 * kMaxRegimes;
+    const int corners = (t.t_exp ? NP : std::min(4 * NP, R * t.n_T * t.n_P)) + pad;
+    const int nodes = t.n_cia > 0 ? std::min(2 * NP, R * t.n_Tcia) + pad : 0;
+    const int ray = t.has_rayleigh ? 8 : 0;
+    return std::min(corners + nodes + ray, kMaxSlots);
+  }
   const int corners = t.t_exp ? NP : std::min(4 * NP, t.n_T * t.n_P);
   const int nodes = t.n_cia > 0 ? std::min(2 * NP, t.n_Tcia) : 0;
   return corners + nodes;
@@ -162,12 +195,13 @@ inline int frag_piece_bytes(int precision) {
   return precision == TRX_FP32 ? 64 * 8 * 4 : 64 * 8 * 2;
 }
 
-inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& t, bool emission = false) {
+inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& t, bool emission = false,
+                          bool regimes = false) {
   Layout L{};
   L.NP = ((N_max + 31) / 32) * 32;
   L.NRB = L.NP / 32;
   L.NKB = L.NP / 16;
-  L.NKQ = (slot_capacity(t, L.NP) + 15) / 16;
+  L.NKQ = (slot_capacity(t, L.NP, regimes) + 15) / 16;
   int64_t o = kHdrBytes;
   auto take = [&](int64_t bytes) { int64_t r = o; o += (bytes + 255) / 256 * 256; return r; };
   L.off_z = take(8LL * L.NP);
@@ -188,8 +222,14 @@ inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& 
   }
   if (t.t_exp) {
     L.xt = 1;
-    L.off_xt32 = take(16LL * L.NP);
-    L.off_xt64 = take(32LL * L.NP);
+    // records by slot (two-layer layouts pad each run's layer slots)
+    const int nslot = regimes ? 16 * L.NKQ : L.NP;
+    L.off_xt32 = take(16LL * nslot);
+    L.off_xt64 = take(32LL * nslot);
+  }
+  if (regimes) {
+    L.rg = 1;
+    L.off_rg = take((int64_t)sizeof(RegChem) * kMaxRegimes);
   }
   if (precision == TRX_FP64 && L.NP > TRX_MAX_LAYERS_MFMA) {
     L.dl_bytes = 8LL * L.NP * L.NP;  // dense transposed dlT[k][j]
@@ -243,6 +283,8 @@ struct DevBatch {
   const double* cloud_sigma;   // [B] or null (then the next two are null too)
   const double* cloud_p1;
   const double* cloud_p2;
+  const double* vmr_top;       // [B][n_abs] two-layer top values, or null (then vmr_sw too)
+  const double* vmr_sw;        // [B][n_abs] switch pressures
 };
 
 struct GeomArgs {

@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(HERE, "libtrx.so")
 FP64, FP32, BF16_SPLIT2, BF16_SPLIT3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16_SPLIT2, "bf16x3": BF16_SPLIT3}
 
-MODEL_OK, BAD_CHEMISTRY, BAD_PROFILE, BAD_WINDOW, NONFINITE, GRAD_UNSUPPORTED = 0, 1, 2, 4, 8, 16
-PLAN_GRAPH, PLAN_PERSISTENT, PLAN_GRAD, PLAN_EMISSION = 1, 2, 4, 8
+MODEL_OK, BAD_CHEMISTRY, BAD_PROFILE, BAD_WINDOW, NONFINITE, GRAD_UNSUPPORTED, UNSUPPORTED = \
+    0, 1, 2, 4, 8, 16, 32
+PLAN_GRAPH, PLAN_PERSISTENT, PLAN_GRAD, PLAN_EMISSION, PLAN_TWO_LAYER = 1, 2, 4, 8, 16
 
 STATUS_NAMES = {0: "TRX_OK", 1: "TRX_E_INVALID_ARG", 2: "TRX_E_OUT_OF_MEMORY",
                 3: "TRX_E_DEVICE", 4: "TRX_E_UNSUPPORTED"}
@@ -61,7 +62,7 @@ class BatchC(ctypes.Structure):
                 ("Rp_m", _P), ("Rs_m", _P), ("GM_m3s2", _P), ("wn_lo", _P),
                 ("wn_hi", _P), ("he_h2_ratio", _D), ("k_B", _D), ("amu_kg", _D),
                 ("gravity", _I), ("cloud_sigma_m2", _P), ("cloud_p_top_Pa", _P),
-                ("cloud_p_bottom_Pa", _P)]
+                ("cloud_p_bottom_Pa", _P), ("log10_vmr_top", _P), ("vmr_switch_Pa", _P)]
 
 
 _lib = None
@@ -206,7 +207,7 @@ class DeviceBatch:
     def __init__(self, n_layers, T, p_bot, p_top, log10_vmr, Rp, Rs, GM, wn_lo, wn_hi,
                  he_h2=0.17, k_B=1.380649e-23, amu=1.66053906660e-27, gravity=0,
                  device="cuda", max_layers=None, cloud_sigma=None, cloud_p_top=None,
-                 cloud_p_bottom=None):
+                 cloud_p_bottom=None, log10_vmr_top=None, vmr_switch=None):
         dev = torch.device(device)
         t = lambda a, dt: torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a,
                                           dtype=dt).to(dev).contiguous()
@@ -227,6 +228,11 @@ class DeviceBatch:
             raise ValueError("cloud deck arrays: all three or none")
         self.cloud = None if cloud_sigma is None else tuple(
             t(v, torch.float64) for v in (cloud_sigma, cloud_p_top, cloud_p_bottom))
+        # optional two-layer profiles: top values and switch pressures, or none
+        if (log10_vmr_top is None) != (vmr_switch is None):
+            raise ValueError("two-layer arrays: both or neither")
+        self.two_layer = None if log10_vmr_top is None else (
+            t(log10_vmr_top, torch.float64), t(vmr_switch, torch.float64))
         self.max_layers = int(max_layers if max_layers is not None else max(2, int(nl.max())))
 
     @classmethod
@@ -234,7 +240,8 @@ class DeviceBatch:
         return cls(b.n_layers, b.T, b.p_bot, b.p_top, b.log10_vmr, b.Rp, b.Rs, b.GM,
                    b.wn_lo, b.wn_hi, b.he_h2, b.k_B, b.amu, b.gravity, device, max_layers,
                    getattr(b, "cloud_sigma", None), getattr(b, "cloud_p_top", None),
-                   getattr(b, "cloud_p_bottom", None))
+                   getattr(b, "cloud_p_bottom", None), getattr(b, "log10_vmr_top", None),
+                   getattr(b, "vmr_switch", None))
 
     @property
     def n_abs(self):
@@ -250,7 +257,8 @@ class DeviceBatch:
                       _ptr(self.log10_vmr), _ptr(self.Rp), _ptr(self.Rs), _ptr(self.GM),
                       _ptr(self.wn_lo), _ptr(self.wn_hi), float(self.he_h2), float(self.k_B),
                       float(self.amu), int(self.gravity),
-                      *((None, None, None) if self.cloud is None else (_ptr(c) for c in self.cloud)))
+                      *((None, None, None) if self.cloud is None else (_ptr(c) for c in self.cloud)),
+                      *((None, None) if self.two_layer is None else (_ptr(c) for c in self.two_layer)))
 
 
 class _ModelView:
@@ -267,7 +275,8 @@ class _ModelView:
                       at(d.p_bot, b), at(d.p_top, b), at(d.log10_vmr, b * d.n_abs),
                       at(d.Rp, b), at(d.Rs, b), at(d.GM, b), at(d.wn_lo, b), at(d.wn_hi, b),
                       float(d.he_h2), float(d.k_B), float(d.amu), int(d.gravity),
-                      *((None, None, None) if d.cloud is None else (at(c, b) for c in d.cloud)))
+                      *((None, None, None) if d.cloud is None else (at(c, b) for c in d.cloud)),
+                      *((None, None) if d.two_layer is None else (at(c, b * d.n_abs) for c in d.two_layer)))
 
 
 def _prec(p):
@@ -420,11 +429,12 @@ class Plan:
     was captured with."""
 
     def __init__(self, ctx, tables, bins, B_max, N_max, precision=FP32, graph=True,
-                 persistent=True, grad=False, emission=False):
+                 persistent=True, grad=False, emission=False, two_layer=False):
         self.ctx, self.tables, self.bins = ctx, tables, bins
         self.B_max, self.N_max = int(B_max), int(N_max)
         flags = (PLAN_GRAPH if graph else 0) | (PLAN_PERSISTENT if persistent else 0) | \
-            (PLAN_GRAD if grad else 0) | (PLAN_EMISSION if emission else 0)
+            (PLAN_GRAD if grad else 0) | (PLAN_EMISSION if emission else 0) | \
+            (PLAN_TWO_LAYER if two_layer else 0)
         h = ctypes.c_void_p()
         ctx.check(lib().trx_plan_create(ctx.h, tables.h, bins.h if bins is not None else None,
                                         self.B_max, self.N_max, _prec(precision), flags,

@@ -16,7 +16,7 @@ models, ...) so tests can build the same recipe at sizes a CPU finishes in
 seconds.
 """
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from functools import lru_cache
 
 import numpy as np
@@ -95,6 +95,10 @@ class Batch:
     cloud_sigma: np.ndarray = None
     cloud_p_top: np.ndarray = None
     cloud_p_bottom: np.ndarray = None
+    # optional two-layer profiles ([B, n_abs] each, or None): top values
+    # (log10) and switch pressures (Pa); log10_vmr holds the surface values
+    log10_vmr_top: np.ndarray = None
+    vmr_switch: np.ndarray = None
 
     @property
     def B(self):
@@ -115,6 +119,8 @@ class Batch:
             d.update(cloud_sigma=float(self.cloud_sigma[b]),
                      cloud_p_top=float(self.cloud_p_top[b]),
                      cloud_p_bottom=float(self.cloud_p_bottom[b]))
+        if self.log10_vmr_top is not None:
+            d.update(log10_vmr_top=self.log10_vmr_top[b].copy(), vmr_switch=self.vmr_switch[b].copy())
         return d
 
     def subset(self, idx):
@@ -130,7 +136,8 @@ class Batch:
                      self.wn_lo[idx].copy(), self.wn_hi[idx].copy(),
                      self.he_h2, self.k_B, self.amu, self.gravity,
                      *(None if c is None else c[idx].copy()
-                       for c in (self.cloud_sigma, self.cloud_p_top, self.cloud_p_bottom)))
+                       for c in (self.cloud_sigma, self.cloud_p_top, self.cloud_p_bottom,
+                                 self.log10_vmr_top, self.vmr_switch)))
 
 
 def with_cloud_decks(batch, seed, kinds=("none", "flat", "opaque")):
@@ -171,6 +178,24 @@ class Channels:
     @property
     def n(self):
         return int(self.lo.shape[0])
+
+
+def with_two_layer_profiles(batch, seed, n_switch=2, drop=(0.5, 4.0)):
+    """A copy of ``batch`` whose absorbers have two-layer profiles: per
+    model, n_switch switch pressures log-uniform in [1e-2, 1e5] Pa, each
+    absorber on one of them or constant (equal top and surface values), its
+    top value lower than its surface value by a drop in log10 uniform in
+    ``drop``.  The layers then fall into at most n_switch + 1 runs."""
+    rng = np.random.default_rng(seed)
+    B, na = batch.log10_vmr.shape
+    sw = 10.0 ** rng.uniform(-2.0, 5.0, (B, n_switch))
+    pick = rng.integers(0, n_switch + 1, (B, na))       # n_switch: constant
+    top = batch.log10_vmr - rng.uniform(drop[0], drop[1], (B, na))
+    top = np.where(pick == n_switch, batch.log10_vmr, top)
+    p_sw = np.take_along_axis(np.concatenate([sw, np.ones((B, 1))], axis=1), pick, axis=1)
+    out = replace(batch)
+    out.log10_vmr_top, out.vmr_switch = top, p_sw
+    return out
 
 
 def batch_from_models(T_list, p_bot, p_top, log10_vmr, Rp, Rs, GM, wn_lo, wn_hi,
