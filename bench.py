@@ -59,6 +59,8 @@ def parse():
                    help="the emission leg's fast mode (FP64 is always timed as well)")
     p.add_argument("--no-exp-t", action="store_true",
                    help="skip the leg with the exponential temperature scheme")
+    p.add_argument("--no-two-layer", action="store_true",
+                   help="skip the leg with two-layer mixing profiles")
     p.add_argument("--no-clouds", action="store_true",
                    help="skip the leg with cloud decks on the main batch")
     p.add_argument("--no-retrieval", action="store_true",
@@ -118,9 +120,10 @@ def _oracle_task(job):
     with threadpool_limits(limits=1):
         t0 = time.time()
         p0 = time.perf_counter()
-        if kind in ("forward", "clouds", "exp_t"):
+        if kind in ("forward", "clouds", "exp_t", "two_layer"):
             tables, batch, ch = _SHARED["cfg3"]
-            m = (_SHARED["cfg3_clouds"] if kind == "clouds" else batch).model(b)
+            src = {"clouds": "cfg3_clouds", "two_layer": "cfg3_two_layer"}.get(kind)
+            m = (_SHARED[src] if src else batch).model(b)
             if kind == "exp_t":
                 m = dict(m, t_interp="exp")
             r = oracle.forward_model(m, tables, ch)
@@ -413,6 +416,43 @@ def exp_t_leg(args, ctx, trx, torch, tables, bins_lin, batch, db, ch, pool):
     return out
 
 
+def two_layer_leg(args, ctx, trx, torch, T, bins, pool):
+    """The main batch with two-layer mixing profiles (two switch pressures
+    per model, each absorber on one of them or constant: up to three runs of
+    one chemistry) through a graph-captured TRX_PLAN_TWO_LAYER plan in the
+    main precision; stratified models against the oracle."""
+    tb = _SHARED["cfg3_two_layer"]
+    db = trx.DeviceBatch.from_synth(tb, max_layers=200)
+    p2 = trx.Plan(ctx, T, bins, B_max=tb.B, N_max=200, precision=args.precision, graph=True, two_layer=True)
+    p2.autotune(db)
+    ms = time_steps(lambda: p2.launch(db), args.steps, args.warmup)
+    nat, binned, st = p2.launch(db, native=True)
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    kms = kernel_times(ctx, trx, lambda: p2.launch(db), 2, ((trx.KERNEL_FORWARD, "forward"),))
+    res = {"ms_per_step": round(ms, 3), "spectra_per_s": round(tb.B / (ms * 1e-3), 1), "kernel_ms": kms,
+           "variant": p2.describe(), "precision": args.precision,
+           "profiles": "two switch pressures per model, log-uniform in [1e-2, 1e5] Pa; each absorber on "
+                       "one of them (top value 0.5-4 dex lower) or constant"}
+    log(f"two-layer {args.precision}: {ms:.3f} ms/step")
+    if pool is not None:
+        picks = stratified(tb, 64, 13)
+        refs, _, _ = run_oracle(pool, "two_layer", picks)
+        gn = nat[picks].cpu().numpy()
+        gb = binned[picks].cpu().numpy()
+        en, eb = [], []
+        for i, b in enumerate(picks):
+            lo, hi = int(tb.wn_lo[b]), int(tb.wn_hi[b])
+            en.append(rel_err(gn[i, lo:hi], refs[b][0]))
+            eb.append(rel_err(gb[i], refs[b][1]))
+        res["error"] = {"max_rel_err_native": max(en), "median_rel_err_native": float(np.median(en)),
+                        "max_rel_err_binned": max(eb), "models_checked": len(picks)}
+        log(f"two-layer oracle: {len(picks)} models, native {max(en):.2e}, binned {max(eb):.2e}")
+    del nat, binned
+    p2.close()
+    return res
+
+
 def large_leg(args, ctx, trx, torch):
     """The large workload: 1024 models of 100-200 layers, 10 absorbers with
     CIA and Rayleigh on 40 T x 30 P x 100000-point tables, 100 channels.  The
@@ -624,13 +664,15 @@ def main():
               "path shards by model across GPUs with no exchange, which this benchmark does "
               "not launch.", file=sys.stderr)
         sys.exit(2)
-    from synth.workloads import CONFIG_NAMES, make_config, stellar_temperatures, with_cloud_decks
+    from synth.workloads import (CONFIG_NAMES, make_config, stellar_temperatures, with_cloud_decks,
+                                 with_two_layer_profiles)
 
     # host inputs, then the oracle's worker pool, before anything touches the GPU
     t0 = time.time()
     tables, batch, ch = make_config(3, B=args.models)
     _SHARED["cfg3"] = (tables, batch, ch)
     _SHARED["cfg3_clouds"] = with_cloud_decks(batch, 5)
+    _SHARED["cfg3_two_layer"] = with_two_layer_profiles(batch, 6)
     _SHARED["T_star"] = stellar_temperatures(batch.B)
     if not args.no_grad:
         _SHARED["cfg4"] = make_config(4)
@@ -778,6 +820,7 @@ def main():
                                                           batch, db, pool)
     clouds = None if args.no_clouds else clouds_leg(args, plan, trx, torch, pool)
     exp_t = None if args.no_exp_t else exp_t_leg(args, ctx, trx, torch, tables, bins, batch, db, ch, pool)
+    two_layer = None if args.no_two_layer else two_layer_leg(args, ctx, trx, torch, T, bins, pool)
     single = None if args.no_single else single_leg(args, ctx, trx, torch)
     if pool is not None:
         pool.shutdown()
@@ -801,7 +844,8 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "error": err,
            "ms_per_step_median": round(med, 3), "ms_per_step_iqr": [round(q1, 3), round(q3, 3)],
            "kernel_ms": {k: round(v, 4) for k, v in kms.items()}, "gradient": grad,
-           "emission": emission, "exp_t": exp_t, "single_model": single, "clouds": clouds,
+           "emission": emission, "exp_t": exp_t, "two_layer": two_layer, "single_model": single,
+           "clouds": clouds,
            "retrieval": retrieval,
            "large": large}
     print(json.dumps(out), flush=True)
