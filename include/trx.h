@@ -91,7 +91,7 @@ enum {
   TRX_MODEL_NONFINITE = 8,     /* a non-finite value appeared in the outputs */
   TRX_MODEL_GRAD_UNSUPPORTED = 16, /* trx_chi2_grad: the model has more distinct
                                      table corners and CIA nodes than the
-                                     gradient kernel stages (128); its gradient
+                                     gradient supports (256); its gradient
                                      outputs are NaN */
   TRX_MODEL_UNSUPPORTED = 32   /* two-layer profiles that cut the model's layers
                                   into more than TRX_MAX_REGIMES runs of one
@@ -325,10 +325,11 @@ trx_status trx_forward_noalloc(trx_ctx* ctx, const trx_tables* t, const trx_batc
  * 16-bit rounding of the path x weight products: about 4e-5).  The
  * backward contractions take FP32 operands split into bf16 pieces (FP32
  * accuracy) and the layer-level adjoints are FP64.  Every sum runs in a
- * fixed order: the same call gives the same bits.  A model with more than 128
+ * fixed order: the same call gives the same bits.  A model with more than 256
  * opacity slots (distinct table corners it interpolates from, plus CIA
  * temperature nodes) is flagged TRX_MODEL_GRAD_UNSUPPORTED with NaN
- * gradient outputs.
+ * gradient outputs; above 128 its work items run the recompute of the
+ * optical depth once per 128-slot chunk.
  * Derivatives at table nodes and under clamps are one-sided (the lower
  * bracket's slope; zero under a clamp).  The binned spectrum must cover
  * every channel in each model's window, else that model's chi2 is NaN.

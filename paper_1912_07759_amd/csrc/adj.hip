@@ -286,24 +286,34 @@ void k_adj_item(AdjArgs a) {
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int b = __builtin_amdgcn_readfirstlane(blockIdx.x);
   if (b >= B) return;
+  // work item: span group g, slot chunk c (the item's P adjoints and its
+  // rows' mixing-ratio adjoints cover the chunk's slots; the optical depth
+  // is recomputed over every chunk)
   const int item = __builtin_amdgcn_readfirstlane(blockIdx.y);
+  const int grp = item / kGChunks, c = item - grp * kGChunks;
   const Layout& L = a.L;
-  const GradAcc& G = a.G;
+  const GradAcc& G = a.Gp;
   const uint8_t* slab = a.ws + (int64_t)b * L.slab;
   const ModelHdr* hd = reinterpret_cast<const ModelHdr*>(slab);
   const int N = hd->n;
   if (N == 0) return;
   const int lo = hd->lo, hi = hd->hi;
   const int S = a.span_group;
-  const int sp0 = max(item * S, lo / kCols), sp1 = min(item * S + S, (hi + kCols - 1) / kCols);
+  const int sp0 = max(grp * S, lo / kCols), sp1 = min(grp * S + S, (hi + kCols - 1) / kCols);
   if (sp0 >= sp1) return;
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
-  const int nU = ml->nU, nV = ml->nV, K = nU + nV;
-  if (K > kKG) {
+  const int nUm = ml->nU, Km = nUm + ml->nV;
+  if (Km > kKGM) {
     // more opacity slots than the gradient's capacity: not built here
     if (threadIdx.x == 0) atomicOr(&a.model_status[b], TRX_MODEL_GRAD_UNSUPPORTED);
     return;
   }
+  const int nch = (Km + kKG - 1) / kKG;
+  if (c >= nch) return;
+  // the slots of chunk k: [kKG k, kKG k + K_k), corners first
+  auto chunk_K = [&](int k) { return min(Km - kKG * k, kKG); };
+  auto chunk_nU = [&](int k) { return min(max(nUm - kKG * k, 0), kKG); };
+  const int K = chunk_K(c), nU = chunk_nU(c);
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -311,8 +321,7 @@ void k_adj_item(AdjArgs a) {
   const DevTables& tb = a.tab;
   const int W = tb.n_wn;
   const int nrb = hd->nrb, NR = 32 * nrb;
-  const int nqb = (K + 31) / 32, KP = 32 * nqb;   // 32-slot blocks
-  const int nkq = (K + 15) / 16;                  // 16-slot blocks
+  const int nqb = (K + 31) / 32;                  // 32-slot blocks of the own chunk
   const int NJB = L.NP / 16;
   const int64_t abs_stride = (int64_t)tb.n_T * tb.n_P * W;
   const int64_t cia_stride = (int64_t)tb.n_Tcia * W;
@@ -326,7 +335,6 @@ void k_adj_item(AdjArgs a) {
     const float2* awg = reinterpret_cast<const float2*>(slab + L.off_aw);
     const int32_t* sid = reinterpret_cast<const int32_t*>(slab + L.off_sid);
     if (tid < NR) s.aw[tid] = awg[tid];
-    if (tid < K) s.sid[tid] = sid[tid];
     if (tid < TRX_MAX_ABSORBERS) s.chi[tid] = hd->chi_abs32[tid];
     if (tid < TRX_MAX_CIA) s.ciaw[tid] = hd->cia_w32[tid];
     if (tid < kMaxSpecies) s.chis[tid] = hd->chi_s32[tid];
@@ -348,6 +356,10 @@ void k_adj_item(AdjArgs a) {
 #pragma unroll
   for (int u = 0; u < kPT; ++u) pb[u] = f32x16{};
   const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
+  const int32_t* sidg = reinterpret_cast<const int32_t*>(slab + L.off_sid);
+  // the per-ray and Rayleigh adjoints are the first chunk's items' (they do
+  // not depend on the slots)
+  const bool first_chunk = c == 0;
 
   for (int span = sp0; span < sp1; ++span) {
     const int col0 = span * kCols;
@@ -356,80 +368,106 @@ void k_adj_item(AdjArgs a) {
     const int cc = valid ? col : lo;
     const int voff = cc * 4;
 
-    // staging: M of the span's slots (zero past K) and the Rayleigh sums
+    // the Rayleigh sums
     {
       float rp = 0.f;
       for (int k = wave; k < ns; k += NW) rp = fmaf(s.chis[k], tb.ray32[(int64_t)k * W + cc], rp);
       s.rpart[wave * kCols + lane] = rp;
     }
-    for (int g = wave; g < KP / 8; g += NW) {
-      const int s0 = 8 * g;
-      float v[8];
+    // tau = P M + PR R over the chunks, the own chunk last so that its rows
+    // stay staged: M of chunk k's slots (zero past its end), then this
+    // wave's tiles (32 rays x 32 columns) over the chunk's nonzero 16-slot
+    // blocks; the sums over the other chunks wait in the taubar tile of
+    // LDS (each tile is one wave's), the last chunk's go on to taubar, and
+    // for the first chunk's items to Abar, PRbar and Rbar
+    for (int kk = 0; kk < nch; ++kk) {
+      const int k = (c + 1 + kk) % nch;
+      const int Kk = chunk_K(k), nUk = chunk_nU(k);
+      const bool last = kk == nch - 1;
+      if (kk > 0) __syncthreads();   // the previous chunk's rows are consumed
+      if (tid < Kk) s.sid[tid] = sidg[kKG * k + tid];
+      __syncthreads();
+      for (int g = wave; g < 4 * ((Kk + 31) / 32); g += NW) {
+        const int s0 = 8 * g;
+        float v[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = 0.f;
-      const int nc = min(max(nU - s0, 0), 8);
-      if (nc > 0) mix_group(tb.xsec32, abs_stride, tb.n_abs, s.chi, s.sid + s0, 0, nc, W, voff, v);
-      const int vb = min(max(K - s0, 0), 8);
-      if (vb > nc) mix_group(tb.cia32, cia_stride, tb.n_cia, s.ciaw, s.sid + s0, nc, vb, W, voff, v);
+        for (int i = 0; i < 8; ++i) v[i] = 0.f;
+        const int nc = min(max(nUk - s0, 0), 8);
+        if (nc > 0) mix_group(tb.xsec32, abs_stride, tb.n_abs, s.chi, s.sid + s0, 0, nc, W, voff, v);
+        const int vb = min(max(Kk - s0, 0), 8);
+        if (vb > nc) mix_group(tb.cia32, cia_stride, tb.n_cia, s.ciaw, s.sid + s0, nc, vb, W, voff, v);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) s.rows[(s0 + i) * kLd + lane] = v[i];
-    }
-    __syncthreads();
-
-    // tau tiles (32 rays x 32 columns), t = wave, wave + 8: tau = P M + PR R
-    // over the nonzero 16-slot blocks; then taubar, Abar, PRbar and Rbar
-    for (int t = wave; t < 2 * nrb; t += NW) {
-      const int rb = t >> 1, tcb = t & 1;
-      // nonzero slot blocks of the ray block (each block's fragment loaded
-      // at its turn: prefetching the next one costs more in spilled
-      // registers than it hides)
-      uint64_t m = hd->kq_mask[rb] & ((nkq < 64 ? (1ull << nkq) : 0ull) - 1ull);
-      f32x16 tau = f32x16{};
-      auto afrag = [&](int kq, u32x4& x0, u32x4& x1) {
-        const u32x4* fp = reinterpret_cast<const u32x4*>(pa + (((int64_t)rb * (kKG / 16) + kq) * 64 + lane) * 8);
-        x0 = fp[0];
-        x1 = fp[1];
-      };
-      u32x4 a0{}, a1{};
-      int kq = m ? __builtin_ctzll(m) : -1;
-      while (kq >= 0) {
-        m &= m - 1;
-        const int kn = m ? __builtin_ctzll(m) : -1;
-        afrag(kq, a0, a1);
-        float av[8], bv[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          av[i] = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
-          bv[i] = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
-        }
-        tau = mfma_block(av, bv, tau);
-        kq = kn;
+        for (int i = 0; i < 8; ++i) s.rows[(s0 + i) * kLd + lane] = v[i];
       }
-      const int c = 32 * tcb + lc;
-      float Rc = 0.f;
+      __syncthreads();
+      const int nkq = (Kk + 15) / 16;
+      for (int t = wave; t < 2 * nrb; t += NW) {
+        const int rb = t >> 1, tcb = t & 1;
+        const int c2 = 32 * tcb + lc;
+        // nonzero slot blocks of the ray block within the chunk (each
+        // block's fragment loaded at its turn: prefetching the next one
+        // costs more in spilled registers than it hides)
+        uint64_t m = (hd->kq_mask[rb] >> ((kKG / 16) * k)) & ((1ull << nkq) - 1ull);
+        f32x16 tau = f32x16{};
+        if (kk > 0) {
 #pragma unroll
-      for (int w = 0; w < NW; ++w) Rc += s.rpart[w * kCols + c];
-      const int cg = col0 + c;
-      const float Db = (cg >= lo && cg < hi) ? a.dbar[(int64_t)b * W + cg] : 0.f;
-      float rs = 0.f;
+          for (int q = 0; q < 16; ++q) tau[q] = s.tbar[(32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)) * kLd + c2];
+        }
+        auto afrag = [&](int kq, u32x4& x0, u32x4& x1) {
+          const u32x4* fp = reinterpret_cast<const u32x4*>(
+              pa + (((int64_t)rb * (kKGM / 16) + (kKG / 16) * k + kq) * 64 + lane) * 8);
+          x0 = fp[0];
+          x1 = fp[1];
+        };
+        u32x4 a0{}, a1{};
+        int kq = m ? __builtin_ctzll(m) : -1;
+        while (kq >= 0) {
+          m &= m - 1;
+          const int kn = m ? __builtin_ctzll(m) : -1;
+          afrag(kq, a0, a1);
+          float av[8], bv[8];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
-        const float2 w = s.aw[j];
-        const float x = fmaf(w.y, Rc, tau[q]);
-        const float tv = Db * w.x * __expf(-x);
-        s.tbar[j * kLd + c] = tv;
-        rs = fmaf(w.y, tv, rs);
-        // column sums of the annulus and Rayleigh-path cotangents of ray j
-        const float ab = half_sum(-Db * expm1f(-x));
-        const float pr = half_sum(tv * Rc);
-        if (lc == 0 && j < N) {
-          s.abp[tcb * L.NP + j] += ab;
-          s.prp[tcb * L.NP + j] += pr;
+          for (int i = 0; i < 8; ++i) {
+            av[i] = __uint_as_float(i < 4 ? a0[i] : a1[i - 4]);
+            bv[i] = s.rows[(16 * kq + 2 * i + hl) * kLd + 32 * tcb + lc];
+          }
+          tau = mfma_block(av, bv, tau);
+          kq = kn;
+        }
+        if (!last) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) s.tbar[(32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)) * kLd + c2] = tau[q];
+          continue;
+        }
+        float Rc = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) Rc += s.rpart[w * kCols + c2];
+        const int cg = col0 + c2;
+        const float Db = (cg >= lo && cg < hi) ? a.dbar[(int64_t)b * W + cg] : 0.f;
+        float rs = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
+          const float2 w = s.aw[j];
+          const float x = fmaf(w.y, Rc, tau[q]);
+          const float tv = Db * w.x * __expf(-x);
+          s.tbar[j * kLd + c2] = tv;
+          if (first_chunk) {
+            rs = fmaf(w.y, tv, rs);
+            // column sums of the annulus and Rayleigh-path cotangents of ray j
+            const float ab = half_sum(-Db * expm1f(-x));
+            const float pr = half_sum(tv * Rc);
+            if (lc == 0 && j < N) {
+              s.abp[tcb * L.NP + j] += ab;
+              s.prp[tcb * L.NP + j] += pr;
+            }
+          }
+        }
+        if (first_chunk) {
+          rs += __shfl_xor(rs, 32, 64);
+          if (hl == 0) s.rbp[rb * kCols + c2] = rs;
         }
       }
-      rs += __shfl_xor(rs, 32, 64);
-      if (hl == 0) s.rbp[rb * kCols + c] = rs;
     }
     __syncthreads();
 
@@ -439,7 +477,7 @@ void k_adj_item(AdjArgs a) {
       const int t = wave + NW * u;
       if (t < nrb * nqb) {
         const int rb = t / nqb, qb = t - rb * nqb;
-        if ((hd->kq_mask[rb] >> (2 * qb)) & 3) {
+        if ((hd->kq_mask[rb] >> ((kKG / 16) * c + 2 * qb)) & 3) {
           const float* ar = s.tbar + (32 * rb + lc) * kLd + hl;
           const float* br = s.rows + (32 * qb + lc) * kLd + hl;
 #pragma unroll 1
@@ -463,9 +501,10 @@ void k_adj_item(AdjArgs a) {
       // 16-ray blocks with a nonzero product
       uint32_t jm = 0;
       for (int jb = 0; jb < 2 * nrb; ++jb)
-        if ((hd->kq_mask[jb >> 1] >> (2 * qb)) & 3) jm |= 1u << jb;
+        if ((hd->kq_mask[jb >> 1] >> ((kKG / 16) * c + 2 * qb)) & 3) jm |= 1u << jb;
       auto tfrag = [&](int jb, u32x4& x0, u32x4& x1) {
-        const u32x4* fp = reinterpret_cast<const u32x4*>(pt + (((int64_t)qb * NJB + jb) * 64 + lane) * 8);
+        const u32x4* fp = reinterpret_cast<const u32x4*>(
+            pt + (((int64_t)((kKG / 32) * c + qb) * NJB + jb) * 64 + lane) * 8);
         x0 = fp[0];
         x1 = fp[1];
       };
@@ -577,20 +616,22 @@ void k_adj_item(AdjArgs a) {
           if (lane == 0) cwp[p] += acc_p;
         }
       }
-      // Rayleigh: the wave's species q = wave + 8 k, loads first
+      // Rayleigh: the wave's species q = wave + 8 k, loads first (first
+      // chunk's items only)
       float rl = 0.f;
+      const int nsr = first_chunk ? ns : 0;
       for (int rb = 0; rb < nrb; ++rb) rl += s.rbp[rb * kCols + lane];
       constexpr int kRS = (kMaxSpecies + NW - 1) / NW;
       float rv[kRS];
 #pragma unroll
       for (int k = 0; k < kRS; ++k) {
         const int q = wave + NW * k;
-        rv[k] = q < ns ? tb.ray32[(int64_t)q * W + cc] : 0.f;
+        rv[k] = q < nsr ? tb.ray32[(int64_t)q * W + cc] : 0.f;
       }
 #pragma unroll
       for (int k = 0; k < kRS; ++k) {
         const int q = wave + NW * k;
-        if (q < ns) {
+        if (q < nsr) {
           const float t = wave_sum(rl * rv[k]);
           if (lane == 0) chp[q] += t;
         }
@@ -622,7 +663,7 @@ void k_adj_item(AdjArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
-        dst[G.o_P + j * kKG + 32 * qb + lc] = pb[u][q];
+        dst[G.o_P + j * G.kp + 32 * qb + lc] = pb[u][q];
       }
     }
   }
@@ -638,19 +679,29 @@ __global__ __launch_bounds__(256) void k_adj_reduce(AdjArgs a) {
   if (hd->n == 0) return;
   const MList* ml = reinterpret_cast<const MList*>(slab + a.L.off_mlist);
   const int K = ml->nU + ml->nV;
-  if (K > kKG) return;   // flagged by the item kernel
+  if (K > kKGM) return;   // flagged by the item kernel
   const GradAcc& G = a.G;
+  const GradAcc& Gp = a.Gp;
   const int S = a.span_group;
-  const int g0 = hd->span_lo / S, g1 = (hd->span_hi - 1) / S;   // items that meet the window
-  const float* src = a.part + (int64_t)b * a.n_items * G.n;
+  const int g0 = hd->span_lo / S, g1 = (hd->span_hi - 1) / S;   // span groups that meet the window
+  const int nch = (K + kKG - 1) / kKG;
+  const float* src = a.part + (int64_t)b * a.n_items * Gp.n;
   double* acc = a.acc + (int64_t)b * G.n;
-  const int NR = 32 * hd->nrb, KP = 32 * ((K + 31) / 32);
-  const int n = G.o_P + NR * kKG;
-  for (int e = threadIdx.x; e < n; e += 256) {
-    if (e >= G.o_P && (e - G.o_P) % kKG >= KP) continue;
+  const int NR = 32 * hd->nrb;
+  // the slot-independent sums over every item of the model (chunks past the
+  // first add their chunk's mixing-ratio adjoints and zeros elsewhere) ...
+  for (int e = threadIdx.x; e < Gp.o_P; e += 256) {
     double t = 0.0;
-    for (int g = g0; g <= g1; ++g) t += src[(int64_t)g * G.n + e];
+    for (int g = g0; g <= g1; ++g)
+      for (int c = 0; c < nch; ++c) t += src[(int64_t)(g * kGChunks + c) * Gp.n + e];
     acc[e] += t;
+  }
+  // ... and the P adjoints of chunk c's slots from chunk c's items
+  for (int e = threadIdx.x; e < NR * K; e += 256) {
+    const int j = e / K, q = e - j * K, c = q / kKG, qc = q - c * kKG;
+    double t = 0.0;
+    for (int g = g0; g <= g1; ++g) t += src[(int64_t)(g * kGChunks + c) * Gp.n + Gp.o_P + j * Gp.kp + qc];
+    acc[G.o_P + j * G.kp + q] += t;
   }
 }
 
@@ -679,7 +730,7 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
   if (N == 0) return;
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const int nU = ml->nU, nV = ml->nV;
-  if (nU + nV > kKG) return;
+  if (nU + nV > kKGM) return;
   const double* zs = reinterpret_cast<const double*>(slab + L.off_z);
   const double* lw64 = reinterpret_cast<const double*>(slab + L.off_lw64);
   const double* lwd = reinterpret_cast<const double*>(slab + L.off_lwd64);
@@ -742,7 +793,7 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
   // dchi2/d dl[j][l]: the path x weight products, the Rayleigh path and the
   // deck's optical depth of ray j, each through layer l's weight
   auto dlbar = [&](int j, int l) -> double {
-    const double* pr = Pb + (int64_t)j * kKG;
+    const double* pr = Pb + (int64_t)j * G.kp;
     double d = PRb[j] * sW[l][6] + sTcb[j] * sW[l][7];
     for (int q = 0; q < nq; ++q) d += pr[sS[l][q]] * sW[l][q];
     return d;
@@ -753,7 +804,7 @@ __global__ __launch_bounds__(kPM) void k_adj_pmat(AdjArgs a) {
     double wb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int j = 0; j <= l; ++j) {
       const double d = chord(j, l);
-      const double* pr = Pb + (int64_t)j * kKG;
+      const double* pr = Pb + (int64_t)j * G.kp;
       for (int q = 0; q < nq; ++q) wb[q] += d * pr[sS[l][q]];
       wb[6] += d * PRb[j];
       wb[7] += d * sTcb[j];
@@ -917,7 +968,7 @@ __global__ __launch_bounds__(64) void k_adj_geom(AdjArgs a) {
 // per wave cover 4 x 4 ray x slot blocks), the 12-wave one the others
 static bool adj_small(const Layout& L) { return L.NRB * (kKG / 32) <= 2 * kWaves; }
 size_t adj_item_lds_bytes(const Layout& L) {
-  return carve(L, make_grad_acc(L.NP), adj_small(L) ? kWaves : kWavesL, nullptr, nullptr);
+  return carve(L, make_grad_acc(L.NP, kKG), adj_small(L) ? kWaves : kWavesL, nullptr, nullptr);
 }
 
 void launch_chi2_dbar(const AdjArgs& a, int B_grid, hipStream_t s) {

@@ -582,8 +582,9 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
 
 GradScratch trx::carve_grad_scratch(void* base, int B, int n_wn, int n_ch, int NP) {
   const GradAcc G = make_grad_acc(NP);
+  const GradAcc Gp = make_grad_acc(NP, kKG);
   const size_t spans = (size_t)(n_wn + kSpanCols - 1) / kSpanCols;
-  const size_t items = (spans + kAdjSpanGroup - 1) / kAdjSpanGroup;
+  const size_t items = (spans + kAdjSpanGroup - 1) / kAdjSpanGroup * kGChunks;
   uint8_t* p = (uint8_t*)base;
   size_t o = 0;
   auto take = [&](size_t bytes) -> void* {
@@ -596,7 +597,7 @@ GradScratch trx::carve_grad_scratch(void* base, int B, int n_wn, int n_ch, int N
   g.binned = (double*)take((size_t)B * n_ch * 8);
   g.coef = (double*)take((size_t)B * n_ch * 8);
   g.dbar = (float*)take((size_t)B * n_wn * 4);
-  g.part = (float*)take((size_t)B * items * G.n * 4);
+  g.part = (float*)take((size_t)B * items * Gp.n * 4);
   g.bytes = o;
   return g;
 }
@@ -633,6 +634,7 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   a.tab = t->dev;
   a.L = L;
   a.G = G;
+  a.Gp = make_grad_acc(L.NP, kKG);
   a.ws = (uint8_t*)ws.ptr;
   a.bt = db;
   a.B_dev = B_dev;
@@ -650,7 +652,7 @@ trx_status trx::enqueue_chi2_grad(trx_ctx* c, const trx_tables* t, const DevBatc
   a.part = gs.part;
   a.n_spans = (W + kSpanCols - 1) / kSpanCols;
   a.span_group = kAdjSpanGroup;
-  a.n_items = (a.n_spans + kAdjSpanGroup - 1) / kAdjSpanGroup;
+  a.n_items = (a.n_spans + kAdjSpanGroup - 1) / kAdjSpanGroup * kGChunks;
   a.dT = dT;
   a.dvmr = dvmr;
   a.dRp = dRp;

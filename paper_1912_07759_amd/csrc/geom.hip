@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
     // grp + kPG (r0 + cr)
     const int nc = min(R, ntask - r0);
     auto task_of = [&](int cr) { return grp + kPG * (r0 + cr); };
-    if (L.grad && nU + nV <= kKG) {
+    if (L.grad && nU + nV <= kKGM) {
       // gradient layouts: P hi in FP32 as A fragments (rows = rays) and as
       // P^T fragments (rows = slots): lane l, step i holds
       // P[16 jb + 2 i + l/32][32 qb + l%32]; each slot block c writes the
@@ -1015,7 +1015,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
         const int rb = rem >> 6, lane = rem & 63;
         if (task_of(cr) >= nkq) continue;
         const int col = cr * NR32 + 32 * rb + (lane & 31);
-        float* o = pa + (((int64_t)rb * (kKG / 16) + task_of(cr)) * 64 + lane) * 8;
+        float* o = pa + (((int64_t)rb * (kKGM / 16) + task_of(cr)) * 64 + lane) * 8;
         for (int i = 0; i < 8; ++i) o[i] = (float)sAcc[2 * i + (lane >> 5)][col];
       }
       for (int e = tid; e < nc * 64 * 2 * nrb; e += kPT) {

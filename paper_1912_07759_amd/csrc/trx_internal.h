@@ -152,16 +152,20 @@ struct Layout {
   int32_t slot64;          // FP64 mode in the slot form (models of at most TRX_MAX_LAYERS_MFMA layers)
   int64_t dl_bytes;        // mode-specific path-length storage
   // gradient layouts only (0 otherwise); the gradient takes models of at
-  // most kKG opacity slots:
+  // most kKGM opacity slots:
   int64_t off_lwd64;       // [NP][8] FP64 d(record weight)/dT at fixed P
-  int64_t off_pa;          // P (FP32), rows = rays: [NRB][kKG/16][64][8], lane l, step i: k = 2 i + l/32
-  int64_t off_pt;          // P^T as A fragments, rows = slots: [kKG/32][NP/16][64][8]
+  int64_t off_pa;          // P (FP32), rows = rays: [NRB][kKGM/16][64][8], lane l, step i: k = 2 i + l/32
+  int64_t off_pt;          // P^T as A fragments, rows = slots: [kKGM/32][NP/16][64][8]
   int32_t grad;
   int64_t slab;            // bytes per model (multiple of 256)
 };
 
-// Opacity slots the gradient supports per model (corners and CIA nodes).
+// Opacity slots the gradient supports per model (corners and CIA nodes),
+// in chunks of kKG: a work item of the adjoint holds one chunk's rows and
+// partial sums.
 constexpr int kKG = 128;
+constexpr int kKGM = 256;
+constexpr int kGChunks = kKGM / kKG;
 
 // Opacity slots of a model in the matrix-core modes: its distinct
 // cross-section corners (at most 4 per layer, at most the grid's n_T n_P;
@@ -250,8 +254,8 @@ inline Layout make_layout(int N_max, int precision, bool grad, const DevTables& 
   if (grad) {
     L.grad = 1;
     L.off_lwd64 = take(8LL * 8 * L.NP);
-    L.off_pa = take(4LL * L.NRB * (kKG / 16) * 64 * 8);
-    L.off_pt = take(4LL * (kKG / 32) * (L.NP / 16) * 64 * 8);
+    L.off_pa = take(4LL * L.NRB * (kKGM / 16) * 64 * 8);
+    L.off_pt = take(4LL * (kKGM / 32) * (L.NP / 16) * 64 * 8);
     if (L.off_sid == 0) {   // FP64 forward: the gradient still needs the slot table and ray weights
       L.off_sid = take(4LL * 16 * L.NKQ);
       L.off_aw = take(8LL * L.NP);
@@ -376,14 +380,17 @@ struct BinArgs {
   double* out;            // [B][n_ch]
 };
 
-// Per-model FP64 accumulators of the adjoint (offsets in doubles).
+// Per-model FP64 accumulators of the adjoint (offsets in doubles; the same
+// offsets in floats for the work items' partial sums, whose slot adjoints
+// cover one chunk: kp = kKG, against kp = kKGM for the model's sums).
 struct GradAcc {
-  int32_t NP;
+  int32_t NP, kp;
   int32_t o_A, o_z, o_h, o_T, o_Rp, o_S, o_chi, o_cw, o_PR, o_P, n;
 };
-__host__ __device__ inline GradAcc make_grad_acc(int NP) {
+__host__ __device__ inline GradAcc make_grad_acc(int NP, int kp = kKGM) {
   GradAcc g{};
   g.NP = NP;
+  g.kp = kp;
   int o = 0;
   g.o_A = o; o += NP;          // dchi2/dA_j (A_j including 1/Rs^2)
   g.o_z = o; o += NP;          // dchi2/dz_j
@@ -395,7 +402,7 @@ __host__ __device__ inline GradAcc make_grad_acc(int NP) {
   g.o_cw = o; o += TRX_MAX_CIA;   // dchi2/d(chi_a chi_b) per CIA pair
   g.o_PR = o; o += NP;         // dchi2/dPR_j, Rayleigh path weight of ray j
   o = (o + 31) / 32 * 32;
-  g.o_P = o; o += NP * kKG;    // dchi2/dP[j][q], row j of kKG slots
+  g.o_P = o; o += NP * kp;     // dchi2/dP[j][q], row j of kp slots
   g.n = (o + 31) / 32 * 32;
   return g;
 }
@@ -404,7 +411,8 @@ __host__ __device__ inline GradAcc make_grad_acc(int NP) {
 struct AdjArgs {
   DevTables tab;
   Layout L;
-  GradAcc G;
+  GradAcc G;              // the model's sums (acc)
+  GradAcc Gp;             // a work item's partial sums (part): one slot chunk
   uint8_t* ws;
   DevBatch bt;
   const int32_t* B_dev;
@@ -424,10 +432,10 @@ struct AdjArgs {
   double* chi2;           // [B]
   float* dbar;            // [B][n_wn] dchi2/dD_i inside the window
   double* acc;            // [B][G.n]
-  float* part;            // [B][n_items][G.n] per-item partial sums (same offsets)
+  float* part;            // [B][n_items][Gp.n] per-item partial sums
   int32_t n_spans;        // 64-column spans of the grid
   int32_t span_group;     // spans per backward work item
-  int32_t n_items;        // work items per model = ceil(n_spans / span_group)
+  int32_t n_items;        // work items per model: ceil(n_spans / span_group) span groups x kGChunks slot chunks
   double* dT;             // [layer_off[B]]
   double* dvmr;           // [B][n_abs]
   double* dRp;            // [B]

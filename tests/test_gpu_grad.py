@@ -182,10 +182,12 @@ def test_gradient_plan_graph(gpu_ctx, problem):
 
 def test_gradient_long_models_and_slot_limit(gpu_ctx):
     """Models of 40, 150 and 224 layers in one batch (224 takes the kernel
-    variant for more than 160 rays) against the oracle's reference gradient,
-    next to a model whose zig-zag temperature profile touches more than 128
-    distinct table corners and CIA nodes (about 150): that one is flagged
-    TRX_MODEL_GRAD_UNSUPPORTED with NaN outputs, its neighbours unaffected."""
+    variant for more than 160 rays) and a model whose zig-zag temperature
+    profile touches more than 128 distinct table corners and CIA nodes
+    (about 150: two slot chunks) against the oracle's reference gradient,
+    next to a model whose scrambled profile touches more than 256 (about
+    530): that one is flagged TRX_MODEL_GRAD_UNSUPPORTED with NaN outputs,
+    its neighbours unaffected."""
     from paper_1912_07759_amd import trx
     from synth.atmosphere import guillot_T, log_midpoint_pressures, log_uniform_channels
     from synth.constants import GM_JUP, R_JUP, R_SUN
@@ -200,11 +202,12 @@ def test_gradient_long_models_and_slot_limit(gpu_ctx):
     ramp = np.linspace(0.0, 1200.0, 120)
     zig = np.where(np.arange(120) % 2 == 0, 250.0 + ramp, 3300.0 - ramp)
     Ts.append(zig)
+    # every layer on a different T bracket: 220 K + (7 l mod 29)/28 x 3250 K
+    Ts.append(220.0 + (np.arange(200) * 7 % 29) / 28.0 * 3250.0)
     rng = np.random.default_rng(7)
     vmr = rng.uniform(-7.0, -3.0, (len(Ts), tables.n_abs))
     batch = batch_from_models(Ts, 1e6, 1e-4, vmr, R_JUP, R_SUN, GM_JUP, 0, tables.n_wn)
-    refs = [oracle.forward_model(batch.model(b), tables, ch)["binned"] for b in range(3)]
-    noise, sigma = observation_noise(4, 1, len(ch.lo))
+    refs = [oracle.forward_model(batch.model(b), tables, ch)["binned"] for b in range(4)]
     obs = np.stack([r * (1.0 + 2e-4 * np.sin(np.arange(len(ch.lo)) + b)) for b, r in enumerate(refs)]
                    + [refs[0]])
     Tt = trx.Tables.from_synth(gpu_ctx, tables)
@@ -215,10 +218,10 @@ def test_gradient_long_models_and_slot_limit(gpu_ctx):
     bins.close()
     Tt.close()
     off = batch.layer_off
-    assert np.all(g["status"][:3] == 0), g["status"]
-    assert g["status"][3] & trx.GRAD_UNSUPPORTED
-    assert np.all(np.isnan(g["dT"][off[3]:off[4]])) and np.isnan(g["dRp"][3])
-    for b in range(3):
+    assert np.all(g["status"][:4] == 0), g["status"]
+    assert g["status"][4] & trx.GRAD_UNSUPPORTED
+    assert np.all(np.isnan(g["dT"][off[4]:off[5]])) and np.isnan(g["dRp"][4])
+    for b in range(4):
         ref = oracle.chi2_and_grad(batch.model(b), tables, ch, obs[b], np.full(len(ch.lo), 50e-6))
         mine = {"dT": g["dT"][off[b]:off[b + 1]], "dlog10_vmr": g["dlog10_vmr"][b], "dRp": g["dRp"][b]}
         norm, comp = _grad_err(mine, ref)
