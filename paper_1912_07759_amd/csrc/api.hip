@@ -562,7 +562,7 @@ trx_status trx::enqueue_forward(trx_ctx* c, const trx_tables* t, const DevBatch&
     if (precision == TRX_FP64) {
       launch_fwd64(f, B, c->stream);
     } else {
-      launch_fwd_mfma(f, precision, rc.nrb_max, B, c->n_cu, c->stream);
+      launch_fwd_mfma(f, precision, rc.nrb_max, rc.rbw, rc.occ, B, c->n_cu, c->stream);
     }
   }
   if (tau && db.cloud_sigma) launch_tau_cloud(ws, L, B_dev, B, max_layers, t->dev.n_wn, tau, c->stream);

@@ -295,7 +295,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd64(FwdArgs a) {
 constexpr int kKC64 = 96;    // slots per staging chunk
 constexpr int kLd64 = 66;    // LDS row stride (doubles): the four row groups of a read hit distinct banks
 constexpr int kR16 = 2;      // 16-ray blocks per wave per pass
-constexpr int kS64 = 4;      // spans per work item
 static_assert(TRX_MAX_LAYERS_MFMA % 16 == 0, "16-ray blocks");
 
 template <bool EM>
@@ -587,7 +586,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd64s(FwdArgs a) {
   __shared__ Smem64s<EM> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
-  process64s<TAU, EM>(a, blockIdx.x, blockIdx.y * kS64, blockIdx.y * kS64 + kS64, sm);
+  const int S = a.span_group;
+  process64s<TAU, EM>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
 }
 
 }  // namespace
@@ -596,7 +596,8 @@ void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   const int spans = (a.tab.n_wn + kCols - 1) / kCols;
   if (a.L.slot64) {
-    const dim3 grid(B_grid, (spans + kS64 - 1) / kS64);
+    const int S = a.span_group > 0 ? a.span_group : 1;
+    const dim3 grid(B_grid, (spans + S - 1) / S);
     if (a.L.em)
       hipLaunchKernelGGL((k_fwd64s<false, true>), grid, dim3(64 * kWaves), 0, s, a);
     else if (a.tau)

@@ -399,7 +399,9 @@ __device__ inline void mix_corners(const float* wt, int nt, int t0, const float 
 // separate instantiation: the stores cost the hot kernel registers).
 // EPI: the depth epilogue (kEpiFast, kEpiAcc, kEpiEm).
 // XT: the exponential temperature scheme (the absorber slots are layers).
-template <int MODE, int RBW, bool TAU, int EPI, bool XT>
+// OCC: workgroups per CU the kernel is built for (4: smaller load batches
+// in the staging).
+template <int MODE, int RBW, bool TAU, int EPI, bool XT, int OCC = 3>
 __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end,
                                         Smem<MODE, RBW, EPI, XT>& sm) {
   using C = Cfg<MODE, RBW>;
@@ -555,8 +557,9 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     auto run_chunk = [&](const int c0, auto first_t) {
       constexpr bool first = decltype(first_t)::value;
       // tables per load batch (two batches in flight): 5 when the
-      // accumulators are not live (6 spills registers), else 2
-      constexpr int SA = first ? 5 : 2;
+      // accumulators are not live (6 spills registers), else 2; built for
+      // four workgroups per CU, 2 and 1
+      constexpr int SA = OCC == 4 ? (first ? 2 : 1) : (first ? 5 : 2);
       const int nq = (min(kKC, K - c0) + 15) >> 4;
       const int kqa = c0 >> 4;
       if (K > kKC) {
@@ -855,8 +858,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
 // one XCD share the table rows of few spans in its L2, and moves on to the
 // other queues when its own is drained.  Every workgroup leaves once all
 // queues are drained.
-template <int MODE, int RBW, int EPI, bool XT>
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_fwd_mfma_persist(FwdArgs a) {
+template <int MODE, int RBW, int EPI, bool XT, int OCC = 3>
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(OCC))) void k_fwd_mfma_persist(FwdArgs a) {
   __shared__ Smem<MODE, RBW, EPI, XT> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   const int S = a.span_group;
@@ -896,19 +899,19 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW, false, EPI, XT>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
+        if (bm >= 0) process<MODE, RBW, false, EPI, XT, OCC>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
       }
       __syncthreads();
     }
   }
 }
 
-template <int MODE, int RBW, int EPI, bool XT>
+template <int MODE, int RBW, int EPI, bool XT, int OCC>
 int occupancy() {
   static int blocks = 0;
   if (!blocks) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, EPI, XT>, 64 * kWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, EPI, XT, OCC>, 64 * kWaves, 0) !=
             hipSuccess || nb < 1)
       nb = 1;
     blocks = nb;
@@ -917,11 +920,11 @@ int occupancy() {
 }
 
 // The optical-depth output always takes the one-workgroup-per-item kernel.
-template <int MODE, int RBW, int EPI, bool XT>
+template <int MODE, int RBW, int EPI, bool XT, int OCC = 3>
 void launch_rbw_epi(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
   if (a.persistent && !a.tau) {
-    const int grid = n_cu * occupancy<MODE, RBW, EPI, XT>();
-    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, EPI, XT>), dim3(grid), dim3(64 * kWaves), 0, s, a);
+    const int grid = n_cu * occupancy<MODE, RBW, EPI, XT, OCC>();
+    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, EPI, XT, OCC>), dim3(grid), dim3(64 * kWaves), 0, s, a);
   } else {
     dim3 grid(B_grid, ((a.tab.n_wn + kCols - 1) / kCols + a.span_group - 1) / a.span_group);
     if (a.tau)
@@ -934,7 +937,14 @@ void launch_rbw_epi(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
 // The optical-depth output (transmission only) takes the fast epilogue: it
 // writes tau, not the depth's rounding.
 template <int MODE, int RBW>
-void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
+void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, int occ, hipStream_t s) {
+  // the four-workgroup build: one ray block per wave, fast transit epilogue
+  if constexpr (RBW == 1) {
+    if (occ == 4 && !a.L.xt && !a.L.em && !a.accurate) {
+      launch_rbw_epi<MODE, 1, kEpiFast, false, 4>(a, B_grid, n_cu, s);
+      return;
+    }
+  }
   // the exponential scheme has no gradient, so no accurate epilogue
   if (a.L.xt) {
     if (a.L.em) launch_rbw_epi<MODE, RBW, kEpiEm, true>(a, B_grid, n_cu, s);
@@ -948,20 +958,23 @@ void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
   }
 }
 
+// Ray blocks per wave: one (the waves own ray blocks 0-3) for models of at
+// most 128 rays unless rbw asks for two, else two (0-3 and 7-4).
 template <int MODE>
-void launch_mode(const FwdArgs& a, int nrb, int B_grid, int n_cu, hipStream_t s) {
-  if (nrb <= 4) launch_rbw<MODE, 1>(a, B_grid, n_cu, s);
-  else launch_rbw<MODE, 2>(a, B_grid, n_cu, s);
+void launch_mode(const FwdArgs& a, int nrb, int rbw, int occ, int B_grid, int n_cu, hipStream_t s) {
+  if (nrb <= 4 && rbw != 2) launch_rbw<MODE, 1>(a, B_grid, n_cu, occ, s);
+  else launch_rbw<MODE, 2>(a, B_grid, n_cu, occ, s);
 }
 
 }  // namespace
 
-void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int n_cu, hipStream_t s) {
+void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int rbw, int occ, int B_grid, int n_cu,
+                     hipStream_t s) {
   if (B_grid <= 0) return;
   switch (precision) {
-    case TRX_FP32: launch_mode<TRX_FP32>(a, nrb_max, B_grid, n_cu, s); break;
-    case TRX_BF16_SPLIT2: launch_mode<TRX_BF16_SPLIT2>(a, nrb_max, B_grid, n_cu, s); break;
-    default: launch_mode<TRX_BF16_SPLIT3>(a, nrb_max, B_grid, n_cu, s); break;
+    case TRX_FP32: launch_mode<TRX_FP32>(a, nrb_max, rbw, occ, B_grid, n_cu, s); break;
+    case TRX_BF16_SPLIT2: launch_mode<TRX_BF16_SPLIT2>(a, nrb_max, rbw, occ, B_grid, n_cu, s); break;
+    default: launch_mode<TRX_BF16_SPLIT3>(a, nrb_max, rbw, occ, B_grid, n_cu, s); break;
   }
 }
 

@@ -67,8 +67,8 @@ __global__ void k_set_count(int32_t* dst, int32_t v) { *dst = v; }
 
 void describe(trx_plan* p) {
   char buf[160];
-  snprintf(buf, sizeof buf, "persistent=%d group=%d spans=%d", p->rc.persistent, p->rc.group,
-           p->rc.span_group);
+  snprintf(buf, sizeof buf, "persistent=%d group=%d spans=%d rbw=%d occ=%d", p->rc.persistent, p->rc.group,
+           p->rc.span_group, p->rc.rbw, p->rc.occ);
   p->desc = buf;
 }
 
@@ -177,6 +177,16 @@ const char* prec_name(int p) {
   }
 }
 
+// Why a parsed variant does not fit the plan, or null.
+const char* variant_unfit(const trx_plan* p, const RunConfig& rc) {
+  const int nrb = (p->N_max + 31) / 32;
+  if (rc.rbw == 1 && nrb > 4) return "one ray block per wave takes at most 128 layers";
+  if (rc.occ == 4 && (p->precision == TRX_FP64 || nrb > 4 || rc.rbw == 2 || !rc.persistent ||
+                      (p->flags & (TRX_PLAN_EMISSION | TRX_PLAN_GRAD)) || p->t->dev.t_exp))
+    return "the four-workgroup build is the persistent transmission kernel with one ray block per wave";
+  return nullptr;
+}
+
 bool parse_variant(const char* v, RunConfig& rc) {
   RunConfig r = rc;
   std::istringstream ss(v ? v : "");
@@ -191,6 +201,8 @@ bool parse_variant(const char* v, RunConfig& rc) {
     if (k == "persistent" && (x == 0 || x == 1)) r.persistent = (int)x;
     else if (k == "group" && x >= 0 && x <= (1 << 24)) r.group = (int)x;
     else if (k == "spans" && x >= 1 && x <= 64) r.span_group = (int)x;
+    else if (k == "rbw" && x >= 0 && x <= 2) r.rbw = (int)x;
+    else if (k == "occ" && (x == 3 || x == 4)) r.occ = (int)x;
     else return false;
   }
   rc = r;
@@ -412,6 +424,7 @@ extern "C" trx_status trx_plan_set_variant(trx_plan* p, const char* v) {
   if (!parse_variant(v, rc)) return set_err(p->ctx, TRX_E_INVALID_ARG, "bad variant string '%s'", v ? v : "");
   if (rc.persistent && !(p->flags & TRX_PLAN_PERSISTENT))
     return set_err(p->ctx, TRX_E_INVALID_ARG, "plan was made without TRX_PLAN_PERSISTENT");
+  if (const char* why = variant_unfit(p, rc)) return set_err(p->ctx, TRX_E_INVALID_ARG, "variant '%s': %s", v, why);
   p->rc = rc;
   drop_graph(p);
   describe(p);
@@ -435,7 +448,8 @@ extern "C" trx_status trx_autotune(trx_plan* p, const trx_batch* bt, const char*
     auto it = cache.find(key);
     if (it != cache.end()) {
       RunConfig rc = p->rc;
-      if (parse_variant(it->second.c_str(), rc) && (!rc.persistent || (p->flags & TRX_PLAN_PERSISTENT))) {
+      if (parse_variant(it->second.c_str(), rc) && (!rc.persistent || (p->flags & TRX_PLAN_PERSISTENT)) &&
+          !variant_unfit(p, rc)) {
         p->rc = rc;
         drop_graph(p);
         describe(p);
@@ -443,11 +457,19 @@ extern "C" trx_status trx_autotune(trx_plan* p, const trx_batch* bt, const char*
       }
     }
   }
+  // the search: span groups x (one workgroup per item, or the persistent
+  // queues in span-major order or model groups of 16 and 64); then, around
+  // the best of those, the tile layouts: one or two ray blocks per wave and
+  // the four-workgroup build (models of at most 128 layers)
   std::vector<RunConfig> cand;
   RunConfig base = default_config(p->precision, p->N_max);
   if (p->precision == TRX_FP64) {
     base.persistent = 0;
-    cand.push_back(base);
+    for (int sg : {1, 2, 4, 8}) {
+      RunConfig r = base;
+      r.span_group = sg;
+      cand.push_back(r);
+    }
   } else {
     for (int sg : {1, 2, 4, 8}) {
       RunConfig r = base;
@@ -473,17 +495,33 @@ extern "C" trx_status trx_autotune(trx_plan* p, const trx_batch* bt, const char*
   hipEventCreate(&e1);
   double best = 1e300;
   RunConfig pick = cand[0];
-  for (const RunConfig& rc : cand) {
-    if ((s = enqueue(p, bt, bt->B, nullptr, rc, nullptr, binned, status)) != TRX_OK) break;
-    hipEventRecord(e0, c->stream);
-    for (int r = 0; r < 3 && s == TRX_OK; ++r) s = enqueue(p, bt, bt->B, nullptr, rc, nullptr, binned, status);
-    hipEventRecord(e1, c->stream);
-    if (s != TRX_OK) break;
-    hipError_t e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) { s = hip_err(c, e, "autotune"); break; }
-    if (ms < best) { best = ms; pick = rc; }
+  auto time_all = [&](const std::vector<RunConfig>& cs) {
+    for (const RunConfig& rc : cs) {
+      if ((s = enqueue(p, bt, bt->B, nullptr, rc, nullptr, binned, status)) != TRX_OK) return;
+      hipEventRecord(e0, c->stream);
+      for (int r = 0; r < 3 && s == TRX_OK; ++r) s = enqueue(p, bt, bt->B, nullptr, rc, nullptr, binned, status);
+      hipEventRecord(e1, c->stream);
+      if (s != TRX_OK) return;
+      hipError_t e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) { s = hip_err(c, e, "autotune"); return; }
+      if (ms < best) { best = ms; pick = rc; }
+    }
+  };
+  time_all(cand);
+  if (s == TRX_OK && p->precision != TRX_FP64) {
+    std::vector<RunConfig> tiles;
+    for (int rbw : {1, 2})
+      for (int occ : {3, 4}) {
+        RunConfig r = pick;
+        r.rbw = rbw;
+        r.occ = occ;
+        const bool same = (r.rbw == pick.rbw || (pick.rbw == 0 && r.rbw == ((p->N_max + 31) / 32 <= 4 ? 1 : 2))) &&
+                          r.occ == pick.occ;
+        if (!same && !variant_unfit(p, r)) tiles.push_back(r);
+      }
+    time_all(tiles);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -451,7 +451,8 @@ void launch_adj_pmat(const AdjArgs& a, int B_grid, hipStream_t s);
 void launch_adj_geom(const AdjArgs& a, int B_grid, hipStream_t s);
 
 void launch_fwd64(const FwdArgs& a, int B_grid, hipStream_t s);
-void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int B_grid, int n_cu, hipStream_t s);
+void launch_fwd_mfma(const FwdArgs& a, int precision, int nrb_max, int rbw, int occ, int B_grid, int n_cu,
+                     hipStream_t s);
 void launch_bin(const BinArgs& a, int B_grid, hipStream_t s);
 
 }  // namespace trx

@@ -153,8 +153,8 @@ def test_autotune_and_cache(gpu_ctx, ragged, tmp_path):
     assert list(data.values()) == [choice]
     _, got, _ = plan.launch(db)
     assert np.array_equal(_np(got), ref, equal_nan=True)
-    for v in ["persistent=0 group=0 spans=1", "persistent=1 group=8 spans=4",
-              "persistent=1 group=0 spans=2"]:
+    for v in ["persistent=0 group=0 spans=1 rbw=0 occ=3", "persistent=1 group=8 spans=4 rbw=2 occ=3",
+              "persistent=1 group=0 spans=2 rbw=0 occ=3"]:
         plan.set_variant(v)
         assert plan.describe() == v
         _, got, _ = plan.launch(db)
@@ -165,6 +165,53 @@ def test_autotune_and_cache(gpu_ctx, ragged, tmp_path):
     plan.close()
     bins.close()
     T.close()
+
+
+@pytest.mark.parametrize("mode", ["bf16x2", "fp32", "fp64"])
+def test_tile_variants_keep_bits(gpu_ctx, mode):
+    """Models of at most 128 layers: one or two ray blocks per wave, the
+    four-workgroup build of the persistent kernel and (FP64) span groups of
+    1 to 8 give the same bits; the autotuner searches them and variants
+    that do not fit the plan are refused."""
+    from paper_1912_07759_amd import trx
+    tables, batch, ch = make_config(3, n_wn=3000, n_lines=300, B=10, layer_range=(50, 128))
+    T, bins, db = _setup(gpu_ctx, tables, batch, ch)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=128)
+    plan = trx.Plan(gpu_ctx, T, bins, B_max=10, N_max=128, precision=mode, graph=True)
+    try:
+        _, ref, _ = plan.launch(db)
+        ref = _np(ref)
+        if mode == "fp64":
+            variants = [f"persistent=0 group=0 spans={k} rbw=0 occ=3" for k in (1, 2, 8)]
+        else:
+            variants = ["persistent=1 group=0 spans=8 rbw=1 occ=3", "persistent=1 group=0 spans=8 rbw=2 occ=3",
+                        "persistent=1 group=0 spans=4 rbw=1 occ=4", "persistent=0 group=0 spans=2 rbw=2 occ=3"]
+        for v in variants:
+            plan.set_variant(v)
+            assert plan.describe() == v
+            for _ in range(2):
+                _, got, st = plan.launch(db)
+                assert not _np(st).any()
+                assert np.array_equal(_np(got), ref, equal_nan=True), v
+        choice = plan.autotune(db)
+        print(f"{mode} autotune choice: {choice}")
+        _, got, _ = plan.launch(db)
+        assert np.array_equal(_np(got), ref, equal_nan=True)
+        _, r0 = oracle_batch(tables, batch, ch, mode, models=[0])
+        assert binned_rel_err(ref[0], r0[0]["binned"]) <= TOL[mode]
+    finally:
+        plan.close()
+    big = trx.Plan(gpu_ctx, T, bins, B_max=4, N_max=200, precision=mode)
+    try:
+        for v in ("persistent=1 group=0 spans=8 rbw=1 occ=3", "persistent=1 group=0 spans=8 rbw=2 occ=4"):
+            if mode == "fp64" and "persistent=1" in v:
+                v = v.replace("persistent=1", "persistent=0")
+            with pytest.raises(trx.TrxError):
+                big.set_variant(v)
+    finally:
+        big.close()
+        bins.close()
+        T.close()
 
 
 def test_plan_errors(gpu_ctx, ragged):
