@@ -329,12 +329,14 @@ void k_adj_item(AdjArgs a) {
   const float* pt = reinterpret_cast<const float*>(slab + L.off_pt);
   ItemLds s;
   carve(L, G, NW, dyn, &s);
+  const int32_t* sidg = reinterpret_cast<const int32_t*>(slab + L.off_sid);
 
   // records: ray weights (zero past N), slot rows, mixing ratios
   {
     const float2* awg = reinterpret_cast<const float2*>(slab + L.off_aw);
-    const int32_t* sid = reinterpret_cast<const int32_t*>(slab + L.off_sid);
     if (tid < NR) s.aw[tid] = awg[tid];
+    // one chunk: its slot rows for every span of the item
+    if (nch == 1 && tid < K) s.sid[tid] = sidg[tid];
     if (tid < TRX_MAX_ABSORBERS) s.chi[tid] = hd->chi_abs32[tid];
     if (tid < TRX_MAX_CIA) s.ciaw[tid] = hd->cia_w32[tid];
     if (tid < kMaxSpecies) s.chis[tid] = hd->chi_s32[tid];
@@ -356,7 +358,6 @@ void k_adj_item(AdjArgs a) {
 #pragma unroll
   for (int u = 0; u < kPT; ++u) pb[u] = f32x16{};
   const int ns = tb.has_rayleigh ? tb.n_abs + 2 : 0;
-  const int32_t* sidg = reinterpret_cast<const int32_t*>(slab + L.off_sid);
   // the per-ray and Rayleigh adjoints are the first chunk's items' (they do
   // not depend on the slots)
   const bool first_chunk = c == 0;
@@ -384,9 +385,11 @@ void k_adj_item(AdjArgs a) {
       const int k = (c + 1 + kk) % nch;
       const int Kk = chunk_K(k), nUk = chunk_nU(k);
       const bool last = kk == nch - 1;
-      if (kk > 0) __syncthreads();   // the previous chunk's rows are consumed
-      if (tid < Kk) s.sid[tid] = sidg[kKG * k + tid];
-      __syncthreads();
+      if (nch > 1) {
+        if (kk > 0) __syncthreads();   // the previous chunk's rows are consumed
+        if (tid < Kk) s.sid[tid] = sidg[kKG * k + tid];
+        __syncthreads();
+      }
       for (int g = wave; g < 4 * ((Kk + 31) / 32); g += NW) {
         const int s0 = 8 * g;
         float v[8];
