@@ -400,11 +400,15 @@ __device__ inline void mix_corners(const float* wt, int nt, int t0, const float 
 // EPI: the depth epilogue (kEpiFast, kEpiAcc, kEpiEm).
 // XT: the exponential temperature scheme (the absorber slots are layers).
 // OCC: workgroups per CU the kernel is built for (4: smaller load batches
-// in the staging).
+// in the staging, 128 registers; with two ray blocks per wave, the blocks
+// are taken in two passes over the span with one set of accumulators, the
+// staged slots serving both).
 template <int MODE, int RBW, bool TAU, int EPI, bool XT, int OCC = 3>
 __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end,
                                         Smem<MODE, RBW, EPI, XT>& sm) {
-  using C = Cfg<MODE, RBW>;
+  constexpr bool PASS = OCC == 4 && RBW == 2;
+  constexpr int RR = PASS ? 1 : RBW;   // ray blocks held in registers at a time
+  using C = Cfg<MODE, RR>;
   constexpr int npc = C::npc, kAW = C::kAW, KB = C::KB;
   constexpr bool PF = C::PF;
   // the item is the same for the whole workgroup: keep it, and every address
@@ -431,15 +435,23 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   const int K = nU + nV + nR;
   const int nrb = hd->nrb;
   const int NKQ = L.NKQ;
+  // the ray blocks of this wave in registers (pass: which of the two in
+  // the two-pass build)
+  int pass = 0;
+  auto orb = [&](int r) -> int { return PASS ? own_rb<2>(wave, pass) : own_rb<RBW>(wave, r); };
   // slot blocks with a nonzero product, per ray block of this wave
-  uint64_t msk[RBW];
+  uint64_t msk[RR];
   uint64_t any_msk = 0;
+  auto set_masks = [&]() {
+    any_msk = 0;
 #pragma unroll
-  for (int r = 0; r < RBW; ++r) {
-    const int rb = own_rb<RBW>(wave, r);
-    msk[r] = rb < nrb ? hd->kq_mask[rb] : 0ull;
-    any_msk |= msk[r];
-  }
+    for (int r = 0; r < RR; ++r) {
+      const int rb = orb(r);
+      msk[r] = rb < nrb ? hd->kq_mask[rb] : 0ull;
+      any_msk |= msk[r];
+    }
+  };
+  set_masks();
   const int32_t* sid = reinterpret_cast<const int32_t*>(slab + L.off_sid);
   const float2* awg = reinterpret_cast<const float2*>(slab + L.off_aw);
   const u32x4* frag = reinterpret_cast<const u32x4*>(slab + L.off_dl);
@@ -483,10 +495,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 
   // A fragments of slot blocks kq0 .. kq0 + KB - 1 (block-local < nq) of this
   // wave's ray blocks
-  auto load_A = [&](u32x4 (&A)[RBW][KB][kAW], int kq0, int kqa, int nq) {
+  auto load_A = [&](u32x4 (&A)[RR][KB][kAW], int kq0, int kqa, int nq) {
 #pragma unroll
-    for (int r = 0; r < RBW; ++r) {
-      const int rb = own_rb<RBW>(wave, r);
+    for (int r = 0; r < RR; ++r) {
+      const int rb = orb(r);
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
         if (kq0 + kk < nq && ((msk[r] >> (kqa + kq0 + kk)) & 1)) {
@@ -510,10 +522,11 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   // depth epilogue sums A_j e^{-tau_j}: where every e^{-tau_j} is 1 the two
   // agree to the bit and the block adds exactly zero
   const int hl = lane >> 5, lc = lane & 31;
-  float awsum[RBW];
+  float awsum[RR];
+  auto set_awsum = [&]() {
 #pragma unroll
-  for (int r = 0; r < RBW; ++r) {
-    const int rb = own_rb<RBW>(wave, r);
+  for (int r = 0; r < RR; ++r) {
+    const int rb = orb(r);
     float t = 0.f;
     if (rb < nrb) {
 #pragma unroll
@@ -521,6 +534,8 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     }
     awsum[r] = t + __shfl_xor(t, 32, 64);
   }
+  };
+  set_awsum();
 
   // Rayleigh by ray weights (two-layer layouts: by slots)
   const int ns = tb.has_rayleigh && !L.rg ? tb.n_abs + 2 : 0;
@@ -553,8 +568,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     // one staging chunk (slots c0 ..): stage, then contract; the first
     // chunk zeroes the accumulators after its staging (they are not live
     // during it)
-    f32x16 acc[RBW][2];
-    auto run_chunk = [&](const int c0, auto first_t) {
+    f32x16 acc[RR][2];
+    // stage: stage the chunk (false: the second pass over a chunk that is
+    // still staged)
+    auto run_chunk = [&](const int c0, auto first_t, const bool stage) {
       constexpr bool first = decltype(first_t)::value;
       // tables per load batch (two batches in flight): 5 when the
       // accumulators are not live (6 spills registers), else 2; built for
@@ -562,15 +579,16 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       constexpr int SA = OCC == 4 ? (first ? 2 : 1) : (first ? 5 : 2);
       const int nq = (min(kKC, K - c0) + 15) >> 4;
       const int kqa = c0 >> 4;
-      if (K > kKC) {
+      if (stage && K > kKC) {
         __syncthreads();   // the previous chunk's products are done with bfrag
         if (tid < kKC && c0 + tid < K) sm.sid[tid] = sid[c0 + tid];
         if constexpr (XT)
           if (tid < kKC && c0 + tid < nU) sm.xr[tid] = reinterpret_cast<const float4*>(slab + L.off_xt32)[c0 + tid];
         __syncthreads();
       }
-      u32x4 A[RBW][KB][kAW];
+      u32x4 A[RR][KB][kAW];
       load_A(A, 0, kqa, nq);   // in flight during the staging
+      if (stage) {
 
       // staging: 8-slot groups g = wave, wave + 4, ... of the chunk's nq
       // blocks; corner slots are mixed over the absorbers, node slots over
@@ -654,7 +672,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         if (vr > vb) mix_rayleigh(tb.ray32, tb.n_abs + 2, W, sm.chis, sm.sid + 8 * g, vb, vr, voff, s);
         write_group(g, s);
       }
-      if (c0 == 0) {
+      if (c0 == 0 && pass == 0) {
         float rp = 0.f;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -665,9 +683,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         sm.rpart[wave][lane] = rp;
       }
       __syncthreads();   // staged slots visible
+      }
       if (first) {
 #pragma unroll
-        for (int r = 0; r < RBW; ++r) {
+        for (int r = 0; r < RR; ++r) {
           acc[r][0] = f32x16{};
           acc[r][1] = f32x16{};
         }
@@ -676,7 +695,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       // products: batches of KB slot blocks, the next batch's A fragments
       // loaded before the current batch's products (PF) or after them
       for (int kb0 = 0; kb0 < nq; kb0 += KB) {
-        u32x4 An[RBW][KB][kAW];
+        u32x4 An[RR][KB][kAW];
         if constexpr (PF)
           if (kb0 + KB < nq) load_A(An, kb0 + KB, kqa, nq);
 #pragma unroll
@@ -694,7 +713,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
                 bk[tcb][4] = x1.x; bk[tcb][5] = x1.y; bk[tcb][6] = x1.z; bk[tcb][7] = x1.w;
               }
 #pragma unroll
-              for (int r = 0; r < RBW; ++r) {
+              for (int r = 0; r < RR; ++r) {
                 if ((msk[r] >> (kqa + kq)) & 1) {
 #pragma unroll
                   for (int tcb = 0; tcb < 2; ++tcb) {
@@ -716,7 +735,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
                 for (int p = 0; p < npc; ++p)
                   Bp[tcb][p] = *reinterpret_cast<const u32x4*>(sm.bfrag + (((kq * npc + p) * 2 + tcb) * 64 + lane) * 4);
 #pragma unroll
-              for (int r = 0; r < RBW; ++r) {
+              for (int r = 0; r < RR; ++r) {
                 if ((msk[r] >> (kqa + kq)) & 1) {
 #pragma unroll
                   for (int tcb = 0; tcb < 2; ++tcb) {
@@ -737,7 +756,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         if (kb0 + KB < nq) {
           if constexpr (PF) {
 #pragma unroll
-            for (int r = 0; r < RBW; ++r)
+            for (int r = 0; r < RR; ++r)
 #pragma unroll
               for (int kk = 0; kk < KB; ++kk)
 #pragma unroll
@@ -748,16 +767,22 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         }
       }
     };
-    run_chunk(0, std::true_type{});
-    for (int c0 = kKC; c0 < K; c0 += kKC) run_chunk(c0, std::false_type{});
+    for (pass = 0; pass < (PASS ? 2 : 1); ++pass) {
+    if constexpr (PASS) {
+      // this pass's ray block (the previous span ended on the other one)
+      set_masks();
+      set_awsum();
+    }
+    run_chunk(0, std::true_type{}, pass == 0 || K > kKC);
+    for (int c0 = kKC; c0 < K; c0 += kKC) run_chunk(c0, std::false_type{}, true);
 
     // depth: accumulator register q holds ray 8 (q/4) + 4 (lane/32) + q%4
     // of column 32 (column block) + lane%32, as -tau_j / ln 2 less the
     // Rayleigh term; sum_j A_j (1 - e^{-tau_j}) is taken as the ray block's
     // sum of A_j less sum_j A_j e^{-tau_j}
 #pragma unroll
-    for (int r = 0; r < RBW; ++r) {
-      const int rb = own_rb<RBW>(wave, r);
+    for (int r = 0; r < RR; ++r) {
+      const int rb = orb(r);
       if (rb < nrb) {
 #pragma unroll
         for (int tcb = 0; tcb < 2; ++tcb) {
@@ -810,6 +835,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
         }
       }
     }
+    }   // passes
     // one barrier ends the span: past it every wave is done with the slot
     // buffer, the ray weights and the Rayleigh sums of this span, so the
     // next span's staging may start while wave 0 sums the partials (they
@@ -938,12 +964,11 @@ void launch_rbw_epi(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
 // writes tau, not the depth's rounding.
 template <int MODE, int RBW>
 void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, int occ, hipStream_t s) {
-  // the four-workgroup build: one ray block per wave, fast transit epilogue
-  if constexpr (RBW == 1) {
-    if (occ == 4 && !a.L.xt && !a.L.em && !a.accurate) {
-      launch_rbw_epi<MODE, 1, kEpiFast, false, 4>(a, B_grid, n_cu, s);
-      return;
-    }
+  // the four-workgroup build (fast transit epilogue): one ray block per
+  // wave, or two in two passes
+  if (occ == 4 && !a.L.xt && !a.L.em && !a.accurate) {
+    launch_rbw_epi<MODE, RBW, kEpiFast, false, 4>(a, B_grid, n_cu, s);
+    return;
   }
   // the exponential scheme has no gradient, so no accurate epilogue
   if (a.L.xt) {

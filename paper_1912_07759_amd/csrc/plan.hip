@@ -181,9 +181,9 @@ const char* prec_name(int p) {
 const char* variant_unfit(const trx_plan* p, const RunConfig& rc) {
   const int nrb = (p->N_max + 31) / 32;
   if (rc.rbw == 1 && nrb > 4) return "one ray block per wave takes at most 128 layers";
-  if (rc.occ == 4 && (p->precision == TRX_FP64 || nrb > 4 || rc.rbw == 2 || !rc.persistent ||
+  if (rc.occ == 4 && (p->precision == TRX_FP64 || !rc.persistent ||
                       (p->flags & (TRX_PLAN_EMISSION | TRX_PLAN_GRAD)) || p->t->dev.t_exp))
-    return "the four-workgroup build is the persistent transmission kernel with one ray block per wave";
+    return "the four-workgroup build is the persistent transmission kernel";
   return nullptr;
 }
 

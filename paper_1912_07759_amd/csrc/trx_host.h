@@ -66,8 +66,8 @@ struct RunConfig {
   int group = 0;              // models per item group of the persistent order (0: all)
   int span_group = 4;         // consecutive 64-column spans per work item
   int rbw = 0;                // matrix-core kernel: 32-ray blocks per wave (1 or 2; 0: 1 up to 128 rays)
-  int occ = 3;                // workgroups per CU the persistent kernel is built for (4: one ray block
-                              // per wave in 128 registers, smaller staging batches)
+  int occ = 3;                // workgroups per CU the persistent kernel is built for (4: 128
+                              // registers, smaller staging batches, two ray blocks in two passes)
 };
 
 // Scheduling buffers of one launch (device memory).

@@ -185,7 +185,8 @@ def test_tile_variants_keep_bits(gpu_ctx, mode):
             variants = [f"persistent=0 group=0 spans={k} rbw=0 occ=3" for k in (1, 2, 8)]
         else:
             variants = ["persistent=1 group=0 spans=8 rbw=1 occ=3", "persistent=1 group=0 spans=8 rbw=2 occ=3",
-                        "persistent=1 group=0 spans=4 rbw=1 occ=4", "persistent=0 group=0 spans=2 rbw=2 occ=3"]
+                        "persistent=1 group=0 spans=4 rbw=1 occ=4", "persistent=0 group=0 spans=2 rbw=2 occ=3",
+                        "persistent=1 group=0 spans=8 rbw=2 occ=4"]
         for v in variants:
             plan.set_variant(v)
             assert plan.describe() == v
@@ -203,13 +204,61 @@ def test_tile_variants_keep_bits(gpu_ctx, mode):
         plan.close()
     big = trx.Plan(gpu_ctx, T, bins, B_max=4, N_max=200, precision=mode)
     try:
-        for v in ("persistent=1 group=0 spans=8 rbw=1 occ=3", "persistent=1 group=0 spans=8 rbw=2 occ=4"):
+        for v in ("persistent=1 group=0 spans=8 rbw=1 occ=3", "persistent=0 group=0 spans=8 rbw=2 occ=4"):
             if mode == "fp64" and "persistent=1" in v:
                 v = v.replace("persistent=1", "persistent=0")
             with pytest.raises(trx.TrxError):
                 big.set_variant(v)
     finally:
         big.close()
+        bins.close()
+        T.close()
+
+
+@pytest.mark.parametrize("mode", ["bf16x2", "fp32", "bf16x3"])
+def test_two_pass_build_keeps_bits(gpu_ctx, mode):
+    """Models of up to 200 layers (seven ray blocks): the four-workgroup
+    build, which takes a wave's two ray blocks in two passes over each span
+    with one set of accumulators, gives the bits of the default kernel, in
+    single-chunk models and in a model of more than 128 slots (restaged
+    per pass) alike."""
+    from paper_1912_07759_amd import trx
+    from synth.constants import GM_JUP, R_JUP, R_SUN
+    from synth.workloads import batch_from_models
+    tables, batch, ch = make_config(3, n_wn=3000, n_lines=300, B=10, layer_range=(150, 200))
+    # a three-level zig-zag temperature profile of 200 layers: some 180
+    # table corners and CIA nodes, two staging chunks (restaged per pass)
+    i = np.arange(200)
+    zig = np.where(i % 2 == 0, 250.0, 3300.0) + np.linspace(0.0, 900.0, 200)
+    zig = np.where(i % 4 == 1, 1700.0 + np.linspace(0.0, 900.0, 200), zig)
+    zb = batch_from_models([zig], 1e6, 1e-4, np.array([[-4.0, -5.0, -6.0, -3.5, -7.0]]), R_JUP, R_SUN, GM_JUP,
+                           [0], [tables.n_wn])
+    T, bins, _ = _setup(gpu_ctx, tables, batch, ch)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=200)
+    dz = trx.DeviceBatch.from_synth(zb, max_layers=200)
+    plan = trx.Plan(gpu_ctx, T, bins, B_max=10, N_max=200, precision=mode, graph=True)
+    try:
+        plan.set_variant("persistent=1 group=0 spans=8 rbw=0 occ=3")
+        _, zref, _ = plan.launch(dz)
+        zref = _np(zref)
+        _, ref, _ = plan.launch(db)
+        ref = _np(ref)
+        v = "persistent=1 group=0 spans=8 rbw=2 occ=4"
+        plan.set_variant(v)
+        assert plan.describe() == v
+        for _ in range(2):
+            _, got, st = plan.launch(db)
+            assert not _np(st).any()
+            assert np.array_equal(_np(got), ref, equal_nan=True)
+            _, got, st = plan.launch(dz)
+            assert not _np(st).any()
+            assert np.array_equal(_np(got), zref, equal_nan=True)
+        _, r0 = oracle_batch(tables, batch, ch, mode, models=[0])
+        assert binned_rel_err(ref[0], r0[0]["binned"]) <= TOL[mode]
+        _, rz = oracle_batch(tables, zb, ch, mode, models=[0])
+        assert binned_rel_err(zref[0], rz[0]["binned"]) <= TOL[mode]
+    finally:
+        plan.close()
         bins.close()
         T.close()
 
