@@ -460,7 +460,7 @@ extern "C" trx_status trx_autotune(trx_plan* p, const trx_batch* bt, const char*
   // the search: span groups x (one workgroup per item, or the persistent
   // queues in span-major order or model groups of 16 and 64); then, around
   // the best of those, the tile layouts: one or two ray blocks per wave and
-  // the four-workgroup build (models of at most 128 layers)
+  // the four-workgroup build (two ray blocks per wave in two passes)
   std::vector<RunConfig> cand;
   RunConfig base = default_config(p->precision, p->N_max);
   if (p->precision == TRX_FP64) {
