@@ -183,34 +183,36 @@ __device__ inline double exp_neg_dd(double y) {
 }
 
 // One row's term of the emission flux ratio (before (Rp/Rs)^2):
-// (B_{l-1} - B_l)/B_* G(tau_l), from the records e (layer l) and em (layer
-// l - 1) with their x_l - x_* terms zl, zm in FP64, the accumulator x =
-// -tau_gas/ln 2, the wavenumber nu and the star's 1 - e^{-x_*}.  The
-// Planck difference is e^{-(x_b - x_*)} q with x_b the hotter of the two
-// layers when they differ by more than 1 in x (then the direct difference),
-// else the cancellation-free form; each angle's exponential is taken
-// together with e^{-(x_b - x_*)} in FP64 range.
-__device__ inline double emission_term(float4 e, float4 em, double zl, double zm, float x, float nu, double nud,
-                                       float wst, const FwdArgs& a) {
+// (B_{l-1} - B_l)/B_* G(tau_l), from the records e (layer l) with its
+// x_l - x_* term zl and that of layer l - 1, zm, in FP64, w = 1 - e^{-x} of
+// both layers (wl, wm), the accumulator x = -tau_gas/ln 2, the wavenumber
+// nu and the star's 1 - e^{-x_*}.  The Planck difference is
+// e^{-(x_b - x_*)} q with x_b the hotter of the two layers when they
+// differ by more than 1 in x (then the direct difference), else the
+// cancellation-free form; each angle's exponential is taken together with
+// e^{-(x_b - x_*)} in FP64 range.  The quotients take the hardware
+// reciprocal (1 ulp; w lies in (0, 1], away from zero at these
+// wavenumbers and temperatures).
+__device__ inline double emission_term(float4 e, double zl, double zm, float x, float nu, double nud, float wst,
+                                       float wl, float wm, const FwdArgs& a) {
   constexpr float kL2e = 1.4426950408889634f;
-  const float wl = one_minus_exp2(-kL2e * nu * e.x);
-  const float wm = one_minus_exp2(-kL2e * nu * em.x);
   const float dx = nu * e.y;                                     // x_l - x_{l-1}
   double yb;
   float q;
   if (fabsf(dx) <= 1.f) {
     yb = nud * zl;
-    q = -one_minus_exp2(kL2e * dx) * wst / (wm * wl);            // (e^{dx} - 1) w_* / (w_{l-1} w_l)
+    q = -one_minus_exp2(kL2e * dx) * wst * __builtin_amdgcn_rcpf(wm * wl);   // (e^{dx} - 1) w_* / (w_{l-1} w_l)
   } else if (dx > 1.f) {
     yb = nud * zm;
-    q = wst * (1.f / wm - __builtin_amdgcn_exp2f(-kL2e * dx) / wl);
+    q = wst * (__builtin_amdgcn_rcpf(wm) - __builtin_amdgcn_exp2f(-kL2e * dx) * __builtin_amdgcn_rcpf(wl));
   } else {
     yb = nud * zl;
-    q = wst * (__builtin_amdgcn_exp2f(kL2e * dx) / wm - 1.f / wl);
+    q = wst * (__builtin_amdgcn_exp2f(kL2e * dx) * __builtin_amdgcn_rcpf(wm) - __builtin_amdgcn_rcpf(wl));
   }
   // tau/mu_i with the deck's part (x = -tau_gas / ln 2)
   const float tau = e.w - 0.69314718055994531f * x;
   double G = 0.0;
+#pragma unroll 4
   for (int i = 0; i < a.n_mu; ++i) G = fma((double)a.em_c32[i], exp_neg_dd(yb + (double)(tau * a.em_k32[i])), G);
   return (double)q * G;
 }
@@ -790,8 +792,10 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
           const float Rc = sm.rpart[0][cl] + sm.rpart[1][cl] + sm.rpart[2][cl] + sm.rpart[3][cl];
           float s = 0.f;
           double sd = 0.0;
-          // emission: the column's wavenumber and the star's 1 - e^{-x_*}
-          float nu = 0.f, wst = 0.f;
+          // emission: the column's wavenumber and the star's 1 - e^{-x_*};
+          // wp: 1 - e^{-x} of the lane's previous row (rows 4k .. 4k + 3 of
+          // a lane are consecutive layers)
+          float nu = 0.f, wst = 0.f, wp = 0.f;
           double nud = 0.0;
           if constexpr (EPI == kEpiEm) {
             const int cg = span * kCols + cl;
@@ -807,14 +811,16 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
               sd = fma(sm.a64[32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3)], (double)one_minus_exp2(x), sd);
             } else if constexpr (EPI == kEpiEm) {
               const int j = 32 * rb + 8 * (q >> 2) + 4 * hl + (q & 3);
-              if (j >= 1 && j < N)
-                sd += emission_term(sm.em[j], sm.em[j - 1], sm.emz[j], sm.emz[j - 1], x, nu, nud, wst, a);
+              constexpr float kL2e = 1.4426950408889634f;
+              const float4 e = sm.em[j];
+              const float wl = one_minus_exp2(-kL2e * nu * e.x);
+              const float wm = (q & 3) ? wp : (j >= 1 ? one_minus_exp2(-kL2e * nu * sm.em[j - 1].x) : 1.f);
+              wp = wl;
+              if (j >= 1 && j < N) sd += emission_term(e, sm.emz[j], sm.emz[j - 1], x, nu, nud, wst, wl, wm, a);
               // the top layer also carries B_{N-1}/B_* (e^{-tau_N/mu} = 1): added here,
               // before the span's barrier, not by the final sum, whose wave
               // may overlap the next item's loading of these records
-              if (j == N - 1)
-                sd += exp_neg_dd(nud * sm.emz[j]) *
-                      (double)(wst / one_minus_exp2(-1.4426950408889634f * nu * sm.em[j].x));
+              if (j == N - 1) sd += exp_neg_dd(nud * sm.emz[j]) * (double)(wst * __builtin_amdgcn_rcpf(wl));
             } else {
               s = fmaf(w.x, __builtin_amdgcn_exp2f(x), s);
             }
