@@ -405,7 +405,9 @@ __device__ inline void mix_corners(const float* wt, int nt, int t0, const float 
 // in the staging, 128 registers; with two ray blocks per wave, the blocks
 // are taken in two passes over the span with one set of accumulators, the
 // staged slots serving both).
-template <int MODE, int RBW, bool TAU, int EPI, bool XT, int OCC = 3>
+// RG: built for two-layer layouts (runs of one chemistry per model); the
+// other builds leave their code out.
+template <int MODE, int RBW, bool TAU, int EPI, bool XT, int OCC = 3, bool RG = false>
 __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first, int s_end,
                                         Smem<MODE, RBW, EPI, XT>& sm) {
   constexpr bool PASS = OCC == 4 && RBW == 2;
@@ -433,7 +435,8 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const int nU = ml->nU, nV = tb.n_cia > 0 ? ml->nV : 0;
   // two-layer layouts: one Rayleigh slot per run after the node slots
-  const int nR = L.rg ? ml->pad[0] : 0;
+  const bool rg = RG && L.rg;
+  const int nR = rg ? ml->pad[0] : 0;
   const int K = nU + nV + nR;
   const int nrb = hd->nrb;
   const int NKQ = L.NKQ;
@@ -484,7 +487,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       if (K <= kKC && tid < nU) sm.xr[tid] = reinterpret_cast<const float4*>(slab + L.off_xt32)[tid];
     if (tid < kMaxSpecies) sm.chis[0][tid] = hd->chi_s32[tid];
     if (tid < TRX_MAX_CIA) sm.ciaw[0][tid] = hd->cia_w32[tid];
-    if (L.rg && tid < kMaxSpecies) {
+    if (rg && tid < kMaxSpecies) {
       // the other runs' mixing ratios (two-layer profiles)
       const RegChem* rc = reinterpret_cast<const RegChem*>(slab + L.off_rg);
       for (int r = 1; r < kMaxRegimes; ++r) {
@@ -540,7 +543,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
   set_awsum();
 
   // Rayleigh by ray weights (two-layer layouts: by slots)
-  const int ns = tb.has_rayleigh && !L.rg ? tb.n_abs + 2 : 0;
+  const int ns = tb.has_rayleigh && !rg ? tb.n_abs + 2 : 0;
   for (int span = sp0; span < sp1; ++span) {
     const int col = span * kCols + lane;
     const bool valid = col >= lo && col < hi;
@@ -564,7 +567,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     // first slot's; two-layer layouts pad each run's slots of one kind to
     // whole groups)
     auto run_of_group = [&](int g) -> int {
-      return min((int)((uint32_t)__builtin_amdgcn_readfirstlane(sm.sid[8 * g]) >> 24), kMaxRegimes - 1);
+      return rg ? min((int)((uint32_t)__builtin_amdgcn_readfirstlane(sm.sid[8 * g]) >> 24), kMaxRegimes - 1) : 0;
     };
 
     // one staging chunk (slots c0 ..): stage, then contract; the first
@@ -655,23 +658,23 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       // the other groups
       for (int g = gf + ((wave - gf) % kWaves + kWaves) % kWaves; g < ng; g += kWaves) {
         const int s0 = c0 + 8 * g;
-        const int rg = run_of_group(g);
+        const int run = run_of_group(g);
         float s[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.f;
         const int nc = min(max(nU - s0, 0), 8);
         if (nc > 0) {
           if constexpr (XT)
-            mix_group_xt<first ? 2 : 1>(tb.xexp32, tb.xsec32, abs_stride, tb.n_abs, sm.chis[rg], sm.sid + 8 * g,
+            mix_group_xt<first ? 2 : 1>(tb.xexp32, tb.xsec32, abs_stride, tb.n_abs, sm.chis[run], sm.sid + 8 * g,
                                          sm.xr + 8 * g, nc, W, tb.n_P, cc, s);
           else
-            mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chis[rg], sm.sid + 8 * g, 0, nc, W, voff, s);
+            mix_group<SA>(tb.xsec32, abs_stride, tb.n_abs, sm.chis[run], sm.sid + 8 * g, 0, nc, W, voff, s);
         }
         const int vb = min(max(nU + nV - s0, 0), 8);
         if (vb > nc)
-          mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw[rg], sm.sid + 8 * g, nc, vb, W, voff, s);
+          mix_group<SA>(tb.cia32, cia_stride, tb.n_cia, sm.ciaw[run], sm.sid + 8 * g, nc, vb, W, voff, s);
         const int vr = min(max(K - s0, 0), 8);
-        if (vr > vb) mix_rayleigh(tb.ray32, tb.n_abs + 2, W, sm.chis, sm.sid + 8 * g, vb, vr, voff, s);
+        if (RG && vr > vb) mix_rayleigh(tb.ray32, tb.n_abs + 2, W, sm.chis, sm.sid + 8 * g, vb, vr, voff, s);
         write_group(g, s);
       }
       if (c0 == 0 && pass == 0) {
@@ -874,13 +877,13 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
 }
 
 // One workgroup per (model, span).
-template <int MODE, int RBW, bool TAU, int EPI, bool XT>
+template <int MODE, int RBW, bool TAU, int EPI, bool XT, bool RG>
 __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
   __shared__ Smem<MODE, RBW, EPI, XT> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
   if ((int)blockIdx.x >= B) return;
   const int S = a.span_group;
-  process<MODE, RBW, TAU, EPI, XT>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
+  process<MODE, RBW, TAU, EPI, XT, 3, RG>(a, blockIdx.x, blockIdx.y * S, blockIdx.y * S + S, sm);
 }
 
 // Persistent: a fixed grid pops chunks of (span, model) items from kQueues
@@ -890,7 +893,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_fwd_mfma(FwdArgs a) {
 // one XCD share the table rows of few spans in its L2, and moves on to the
 // other queues when its own is drained.  Every workgroup leaves once all
 // queues are drained.
-template <int MODE, int RBW, int EPI, bool XT, int OCC = 3>
+template <int MODE, int RBW, int EPI, bool XT, int OCC = 3, bool RG = false>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(OCC))) void k_fwd_mfma_persist(FwdArgs a) {
   __shared__ Smem<MODE, RBW, EPI, XT> sm;
   const int B = a.B_dev ? *a.B_dev : a.B;
@@ -931,19 +934,20 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(OCC
       if (base >= total) break;
       for (int c = 0; c < kChunk; ++c) {
         const int bm = sm.items[c];
-        if (bm >= 0) process<MODE, RBW, false, EPI, XT, OCC>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
+        if (bm >= 0) process<MODE, RBW, false, EPI, XT, OCC, RG>(a, bm, sm.spans[c] * S, sm.spans[c] * S + S, sm);
       }
       __syncthreads();
     }
   }
 }
 
-template <int MODE, int RBW, int EPI, bool XT, int OCC>
+template <int MODE, int RBW, int EPI, bool XT, int OCC, bool RG>
 int occupancy() {
   static int blocks = 0;
   if (!blocks) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, EPI, XT, OCC>, 64 * kWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd_mfma_persist<MODE, RBW, EPI, XT, OCC, RG>, 64 * kWaves,
+                                                     0) !=
             hipSuccess || nb < 1)
       nb = 1;
     blocks = nb;
@@ -952,18 +956,25 @@ int occupancy() {
 }
 
 // The optical-depth output always takes the one-workgroup-per-item kernel.
-template <int MODE, int RBW, int EPI, bool XT, int OCC = 3>
+template <int MODE, int RBW, int EPI, bool XT, int OCC = 3, bool RG = false>
 void launch_rbw_epi(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
   if (a.persistent && !a.tau) {
-    const int grid = n_cu * occupancy<MODE, RBW, EPI, XT, OCC>();
-    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, EPI, XT, OCC>), dim3(grid), dim3(64 * kWaves), 0, s, a);
+    const int grid = n_cu * occupancy<MODE, RBW, EPI, XT, OCC, RG>();
+    hipLaunchKernelGGL((k_fwd_mfma_persist<MODE, RBW, EPI, XT, OCC, RG>), dim3(grid), dim3(64 * kWaves), 0, s, a);
   } else {
     dim3 grid(B_grid, ((a.tab.n_wn + kCols - 1) / kCols + a.span_group - 1) / a.span_group);
     if (a.tau)
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true, kEpiFast, XT>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, true, kEpiFast, XT, RG>), grid, dim3(64 * kWaves), 0, s, a);
     else
-      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false, EPI, XT>), grid, dim3(64 * kWaves), 0, s, a);
+      hipLaunchKernelGGL((k_fwd_mfma<MODE, RBW, false, EPI, XT, RG>), grid, dim3(64 * kWaves), 0, s, a);
   }
+}
+
+// The build for two-layer layouts or the one without their code.
+template <int MODE, int RBW, int EPI, bool XT>
+void launch_rg(const FwdArgs& a, int B_grid, int n_cu, hipStream_t s) {
+  if (a.L.rg) launch_rbw_epi<MODE, RBW, EPI, XT, 3, true>(a, B_grid, n_cu, s);
+  else launch_rbw_epi<MODE, RBW, EPI, XT, 3, false>(a, B_grid, n_cu, s);
 }
 
 // The optical-depth output (transmission only) takes the fast epilogue: it
@@ -972,20 +983,21 @@ template <int MODE, int RBW>
 void launch_rbw(const FwdArgs& a, int B_grid, int n_cu, int occ, hipStream_t s) {
   // the four-workgroup build (fast transit epilogue): one ray block per
   // wave, or two in two passes
-  if (occ == 4 && !a.L.xt && !a.L.em && !a.accurate) {
+  if (occ == 4 && !a.L.xt && !a.L.em && !a.accurate && !a.L.rg) {
     launch_rbw_epi<MODE, RBW, kEpiFast, false, 4>(a, B_grid, n_cu, s);
     return;
   }
-  // the exponential scheme has no gradient, so no accurate epilogue
+  // the exponential scheme has no gradient, so no accurate epilogue; nor
+  // have two-layer layouts
   if (a.L.xt) {
-    if (a.L.em) launch_rbw_epi<MODE, RBW, kEpiEm, true>(a, B_grid, n_cu, s);
-    else launch_rbw_epi<MODE, RBW, kEpiFast, true>(a, B_grid, n_cu, s);
+    if (a.L.em) launch_rg<MODE, RBW, kEpiEm, true>(a, B_grid, n_cu, s);
+    else launch_rg<MODE, RBW, kEpiFast, true>(a, B_grid, n_cu, s);
   } else if (a.L.em) {
-    launch_rbw_epi<MODE, RBW, kEpiEm, false>(a, B_grid, n_cu, s);
-  } else if (a.accurate && !a.tau) {
+    launch_rg<MODE, RBW, kEpiEm, false>(a, B_grid, n_cu, s);
+  } else if (a.accurate && !a.tau && !a.L.rg) {
     launch_rbw_epi<MODE, RBW, kEpiAcc, false>(a, B_grid, n_cu, s);
   } else {
-    launch_rbw_epi<MODE, RBW, kEpiFast, false>(a, B_grid, n_cu, s);
+    launch_rg<MODE, RBW, kEpiFast, false>(a, B_grid, n_cu, s);
   }
 }
 

@@ -182,8 +182,8 @@ const char* variant_unfit(const trx_plan* p, const RunConfig& rc) {
   const int nrb = (p->N_max + 31) / 32;
   if (rc.rbw == 1 && nrb > 4) return "one ray block per wave takes at most 128 layers";
   if (rc.occ == 4 && (p->precision == TRX_FP64 || !rc.persistent ||
-                      (p->flags & (TRX_PLAN_EMISSION | TRX_PLAN_GRAD)) || p->t->dev.t_exp))
-    return "the four-workgroup build is the persistent transmission kernel";
+                      (p->flags & (TRX_PLAN_EMISSION | TRX_PLAN_GRAD | TRX_PLAN_TWO_LAYER)) || p->t->dev.t_exp))
+    return "the four-workgroup build is the persistent transmission kernel of one-chemistry layouts";
   return nullptr;
 }
 
