@@ -859,6 +859,9 @@ static_assert(TRX_MAX_LAYERS_MFMA <= kPT, "one thread per ray");
 // weights) are dealt to kPG workgroups, so that a lone model is not one
 // workgroup's serial work.
 constexpr int kPG = 4;
+// EM, RG: built for emission and for two-layer layouts (the other builds
+// leave their branches out of the chord and slot loops).
+template <bool EM, bool RG>
 __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   const int b = blockIdx.x;
   const int grp = blockIdx.y;
@@ -873,7 +876,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   const MList* ml = reinterpret_cast<const MList*>(slab + L.off_mlist);
   const int nU = ml->nU, nV = ml->nV;
   // two-layer layouts: one Rayleigh slot per run after the node slots
-  const bool rg = L.rg != 0;
+  const bool rg = RG && L.rg != 0;
   const int nRay = rg ? ml->pad[0] : 0, nRun = rg ? ml->pad[1] : 1;
   const int nkq = (nU + nV + nRay + 15) / 16;
   static_assert(kMaxKQ <= 64, "slot-block masks are 64 bits");
@@ -944,7 +947,7 @@ __global__ __launch_bounds__(kPT) void k_pmat(GeomArgs a) {
   auto qj = [&](double h) { return sqrt(fmax((h - zj) * (2.0 * Rp + h + zj), 0.0)); };
   // emission layouts: the vertical path from the bottom of shell j up
   // through shell l >= j is the shell's thickness
-  const bool em = L.em != 0;
+  const bool em = EM && L.em != 0;
   auto chord = [&](int l, double& q0) -> double {
     if (em) return sH[l + 1] - sH[l];
     const double q1 = qj(sH[l + 1]);
@@ -1142,8 +1145,15 @@ static __global__ __launch_bounds__(256) void k_tau_cloud(const uint8_t* ws, Lay
 void launch_geom(const GeomArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return;
   hipLaunchKernelGGL(k_geom, dim3(B_grid), dim3(kThreads), 0, s, a);
-  if (a.precision != TRX_FP64 || a.L.grad || a.L.slot64)
-    hipLaunchKernelGGL(k_pmat, dim3(B_grid, kPG), dim3(kPT), 0, s, a);
+  if (a.precision != TRX_FP64 || a.L.grad || a.L.slot64) {
+    if (a.L.em) {
+      if (a.L.rg) hipLaunchKernelGGL((k_pmat<true, true>), dim3(B_grid, kPG), dim3(kPT), 0, s, a);
+      else hipLaunchKernelGGL((k_pmat<true, false>), dim3(B_grid, kPG), dim3(kPT), 0, s, a);
+    } else {
+      if (a.L.rg) hipLaunchKernelGGL((k_pmat<false, true>), dim3(B_grid, kPG), dim3(kPT), 0, s, a);
+      else hipLaunchKernelGGL((k_pmat<false, false>), dim3(B_grid, kPG), dim3(kPT), 0, s, a);
+    }
+  }
 }
 
 void launch_tau_cloud(const uint8_t* ws, const Layout& L, const int32_t* B_dev, int B, int max_layers, int W,
