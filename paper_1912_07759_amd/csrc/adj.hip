@@ -278,8 +278,11 @@ __device__ inline void mix_group(const float* tab, int64_t stride, int nt, const
 // 128 rays x 128 slots in 128 registers, so that two workgroups share a CU
 // (the LDS of a 128-ray layout allows it, four waves per SIMD); 12 waves of
 // three tiles cover 224 rays in 168 registers, one workgroup per CU (its LDS
-// takes about 100 KB), three waves per SIMD.
-template <int PT, int NW>
+// takes about 100 KB), three waves per SIMD.  MULTI: the build for models
+// of more than one slot chunk (one item per span group and chunk); the other
+// build takes the models of one chunk (one item per span group) without the
+// code of the chunk loop.
+template <int PT, int NW, bool MULTI>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 4 : 3)))
 void k_adj_item(AdjArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
@@ -289,8 +292,9 @@ void k_adj_item(AdjArgs a) {
   // work item: span group g, slot chunk c (the item's P adjoints and its
   // rows' mixing-ratio adjoints cover the chunk's slots; the optical depth
   // is recomputed over every chunk)
-  const int item = __builtin_amdgcn_readfirstlane(blockIdx.y);
-  const int grp = item / kGChunks, c = item - grp * kGChunks;
+  const int by = __builtin_amdgcn_readfirstlane(blockIdx.y);
+  const int grp = MULTI ? by / kGChunks : by, c = MULTI ? by - grp * kGChunks : 0;
+  const int item = grp * kGChunks + c;   // the slot of this item's partial sums
   const Layout& L = a.L;
   const GradAcc& G = a.Gp;
   const uint8_t* slab = a.ws + (int64_t)b * L.slab;
@@ -308,7 +312,8 @@ void k_adj_item(AdjArgs a) {
     if (threadIdx.x == 0) atomicOr(&a.model_status[b], TRX_MODEL_GRAD_UNSUPPORTED);
     return;
   }
-  const int nch = (Km + kKG - 1) / kKG;
+  if (MULTI != (Km > kKG)) return;   // the other build's model
+  const int nch = MULTI ? (Km + kKG - 1) / kKG : 1;
   if (c >= nch) return;
   // the slots of chunk k: [kKG k, kKG k + K_k), corners first
   auto chunk_K = [&](int k) { return min(Km - kKG * k, kKG); };
@@ -983,13 +988,21 @@ hipError_t launch_adj_item(const AdjArgs& a, int B_grid, hipStream_t s) {
   if (B_grid <= 0) return hipSuccess;
   const size_t lds = adj_item_lds_bytes(a.L);
   const bool small = adj_small(a.L);
-  const void* fn = small ? (const void*)k_adj_item<2, kWaves> : (const void*)k_adj_item<3, kWavesL>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (small)
-    hipLaunchKernelGGL((k_adj_item<2, kWaves>), dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
-  else
-    hipLaunchKernelGGL((k_adj_item<3, kWavesL>), dim3(B_grid, a.n_items), dim3(64 * kWavesL), lds, s, a);
+  for (const void* fn : {small ? (const void*)k_adj_item<2, kWaves, false> : (const void*)k_adj_item<3, kWavesL, false>,
+                         small ? (const void*)k_adj_item<2, kWaves, true> : (const void*)k_adj_item<3, kWavesL, true>}) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  // the models of one chunk, one item per span group; then those of more
+  // (their items exit at once in the first launch, the others' in the second)
+  const int ng = a.n_items / kGChunks;
+  if (small) {
+    hipLaunchKernelGGL((k_adj_item<2, kWaves, false>), dim3(B_grid, ng), dim3(64 * kWaves), lds, s, a);
+    hipLaunchKernelGGL((k_adj_item<2, kWaves, true>), dim3(B_grid, a.n_items), dim3(64 * kWaves), lds, s, a);
+  } else {
+    hipLaunchKernelGGL((k_adj_item<3, kWavesL, false>), dim3(B_grid, ng), dim3(64 * kWavesL), lds, s, a);
+    hipLaunchKernelGGL((k_adj_item<3, kWavesL, true>), dim3(B_grid, a.n_items), dim3(64 * kWavesL), lds, s, a);
+  }
   return hipGetLastError();
 }
 
