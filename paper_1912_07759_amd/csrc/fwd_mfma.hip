@@ -18,11 +18,14 @@
 //
 // Per work item the workgroup stages M of its 64 columns, split into the
 // B-operand pieces of the matrix instruction, in LDS (wave w takes the
-// 8-slot groups w, w+4, ...; each lane keeps 8 slots x 4 tables of loads in
-// flight), and wave w contracts the ray blocks w (and 7 - w) over all slot
-// blocks, the A fragments (P) streamed from the model's workspace one batch
-// of slot blocks ahead.  Models with more slots than one staging chunk
-// (kKC) take several chunks.
+// 8-slot groups w, w+4, ...; a lane loads 8 slots x 5 tables per batch, the
+// next batch issued before the current one is mixed), and wave w contracts
+// the ray blocks w (and 7 - w) over all slot blocks, the A fragments (P)
+// streamed from the model's workspace one batch of slot blocks ahead.
+// Models with more slots than one staging chunk (kKC) take several chunks.
+// Builds: three workgroups per CU (168 registers) or four (128 registers,
+// smaller load batches; two ray blocks per wave in two passes), with or
+// without the code of two-layer layouts.
 //   FP32 mode: v_mfma_f32_32x32x2_f32, M in FP32, P as two FP32 pieces.
 //   bf16 modes: v_mfma_f32_32x32x16_bf16 with both operands split into bf16
 //     pieces x = x0 + x1 (+ x2); the products with piece-index sum < 2 (two
