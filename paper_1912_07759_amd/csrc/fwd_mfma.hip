@@ -701,7 +701,14 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
       }
 
       // products: batches of KB slot blocks, the next batch's A fragments
-      // loaded before the current batch's products (PF) or after them
+      // loaded before the current batch's products (PF) or after them.  A
+      // wave issues them at a raised priority, lowered again before the
+      // depth epilogue (a model of several chunks also stages its later
+      // chunks raised): the other waves on its SIMD are mostly staging,
+      // whose loads wait on L2 anyway.  15.92 -> 15.82 ms on the 4096-model
+      // batch; raising the priority of the staging's load issue instead
+      // cost time, and raising it through the epilogue gained less
+      __builtin_amdgcn_s_setprio(1);
       for (int kb0 = 0; kb0 < nq; kb0 += KB) {
         u32x4 An[RR][KB][kAW];
         if constexpr (PF)
@@ -783,6 +790,7 @@ __device__ __forceinline__ void process(const FwdArgs& a, int b_in, int s_first,
     }
     run_chunk(0, std::true_type{}, pass == 0 || K > kKC);
     for (int c0 = kKC; c0 < K; c0 += kKC) run_chunk(c0, std::false_type{}, true);
+    __builtin_amdgcn_s_setprio(0);
 
     // depth: accumulator register q holds ray 8 (q/4) + 4 (lane/32) + q%4
     // of column 32 (column block) + lane%32, as -tau_j / ln 2 less the
