@@ -2,7 +2,8 @@
 and the most layers each mode accepts, windows of one point and of the whole
 grid, temperatures and pressures outside the tables (each clamp rule),
 constant gravity and a model without any opacity.  The batches mix these
-cases in one launch (persistent in the matrix-core modes)."""
+cases in one launch (persistent in the matrix-core modes).  A batch of no
+models is an invalid argument at every entry point."""
 
 import dataclasses
 
@@ -231,3 +232,58 @@ def test_no_absorbers_gradient(gpu_ctx, tables):
         comp = float(np.max(np.abs(v[big] - r[big]) / np.abs(r[big])))
         print(f"no absorbers model {b}: grad norm err {norm:.2e} comp err {comp:.2e}")
         assert norm <= 1e-4 and comp <= 1e-4
+
+
+def test_empty_batch_is_rejected(gpu_ctx, tables):
+    """A batch of no models is an invalid argument at every entry point that
+    takes one (trx_forward, trx_forward_noalloc, trx_emission, trx_chi2_grad,
+    trx_plan_launch): TRX_E_INVALID_ARG with its message, nothing launched,
+    and the context works for the next call."""
+    import ctypes
+
+    import torch
+    from paper_1912_07759_amd import trx
+    L = trx.lib()
+    Ts = [_profile(40)]
+    batch = batch_from_models(Ts, 1e6, 1e-4, np.full((1, tables.n_abs), -4.0), R_JUP, R_SUN, GM_JUP,
+                              0, tables.n_wn)
+    ch = _channels(tables)
+    T = trx.Tables.from_synth(gpu_ctx, tables)
+    bins = trx.Bins(gpu_ctx, T, ch.lo, ch.hi)
+    db = trx.DeviceBatch.from_synth(batch, max_layers=40)
+    plan = trx.Plan(gpu_ctx, T, bins, B_max=1, N_max=40, precision="fp32")
+    try:
+        dev = db.T.device
+        nat = torch.empty((1, tables.n_wn), dtype=torch.float64, device=dev)
+        binned = torch.empty((1, len(ch.lo)), dtype=torch.float64, device=dev)
+        st = torch.empty(1, dtype=torch.int32, device=dev)
+        f64 = torch.ones(len(ch.lo), dtype=torch.float64, device=dev)
+        g = torch.empty(64, dtype=torch.float64, device=dev)
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        empty = db.cstruct(B=0)
+        gpu_ctx.bind_stream()
+        calls = {
+            "trx_forward": lambda: L.trx_forward(gpu_ctx.h, T.h, ctypes.byref(empty), bins.h, trx.FP32,
+                                                 p(nat), p(binned), p(st), None),
+            "trx_forward_noalloc": lambda: L.trx_forward_noalloc(gpu_ctx.h, T.h, ctypes.byref(empty), bins.h,
+                                                                 trx.FP32, p(nat), p(binned), p(st)),
+            "trx_emission": lambda: L.trx_emission(gpu_ctx.h, T.h, ctypes.byref(empty), bins.h, trx.FP32, 4,
+                                                   p(f64), p(nat), p(binned), p(st)),
+            "trx_chi2_grad": lambda: L.trx_chi2_grad(gpu_ctx.h, T.h, ctypes.byref(empty), bins.h, trx.FP64,
+                                                     p(binned), p(f64), 1, p(g), p(g), p(g), p(g), p(binned),
+                                                     p(st)),
+            "trx_plan_launch": lambda: L.trx_plan_launch(plan.h, ctypes.byref(empty), None, p(binned), p(st),
+                                                         None, None, None, None, None, None),
+        }
+        for name, call in calls.items():
+            rc = call()
+            assert rc == 1, (name, rc)   # TRX_E_INVALID_ARG
+            assert "batch.B must be >= 1" in gpu_ctx.last_error(), (name, gpu_ctx.last_error())
+        # the same context and handles still run a model of the batch
+        _, b1, s1 = trx.forward(gpu_ctx, T, db, bins, "fp32", native=False)
+        torch.cuda.synchronize()
+        assert int(s1[0]) == 0 and bool(torch.all(torch.isfinite(b1)))
+    finally:
+        plan.close()
+        bins.close()
+        T.close()
